@@ -1,0 +1,288 @@
+"""Pins for the oracle's 3D operator, surrogate, basis change, coarse space,
+patches and solver (Sec. 2.1-2.8), against invariants, closed forms, exact
+integrals and dense brute force."""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse.linalg as spla
+
+from oracle import mesh as omesh
+from oracle import transfer
+from oracle.fdm1d import setup_1d
+from oracle.gll import lagrange
+from oracle.operator import Discretization, kron3, separable_cell_matrix
+from oracle.patches import Patches
+from oracle.solver import ALPHA, Solver
+from paper_2107_14758_amd import inputs
+
+
+def jittered(n, p, seed=3, amp=0.15, kappa=False):
+    w = inputs.make_problem(n, p, seed=seed, jitter=amp, lognormal=kappa)
+    return Discretization(w["vertices"], p, w["kappa"]), w
+
+
+# ---------------------------------------------------------------- operator
+def test_operator_symmetric_and_matches_assembly():
+    d, _ = jittered(3, 3, kappa=True)
+    rng = np.random.default_rng(0)
+    x, y = rng.standard_normal(d.n), rng.standard_normal(d.n)
+    Ax, Ay = d.apply(x), d.apply(y)
+    assert abs(y @ Ax - x @ Ay) < 1e-12 * np.linalg.norm(Ax) * np.linalg.norm(y)
+    A = d.assemble()
+    np.testing.assert_allclose(A @ x, Ax, rtol=0, atol=1e-12 * np.abs(Ax).max())
+    # SPD on the free DOFs
+    assert np.linalg.eigvalsh(A.toarray()).min() > 0
+
+
+def test_element_matrices_annihilate_constants():
+    d, _ = jittered(2, 4, kappa=True)
+    Ae = d.element_matrices()
+    assert np.abs(Ae.sum(axis=2)).max() < 1e-12 * np.abs(Ae).max()
+
+
+@pytest.mark.parametrize("p", [2, 3, 5])
+def test_energy_of_linear_function_is_volume(p):
+    # u = x_1 is in Q_1 on every trilinear cell, grad u = e_1, so a(u, u) = |Omega| = 1
+    d, w = jittered(3, p, amp=0.2)
+    Ae = d.element_matrices()
+    pts = omesh.physical_points(d.vertices, d.ref["nodes"])          # nodes of each cell
+    u = pts[..., 0].reshape(d.ncell, -1)
+    energy = np.einsum("na,nab,nb->", u, Ae, u)
+    assert abs(energy - 1.0) < 1e-12
+
+
+def test_cartesian_operator_is_kronecker():
+    # eq. (kron): on an axis-aligned box cell the stiffness is separable with mu_j = L_j^-2 prod L_i
+    p = 4
+    V = inputs.cube_vertices(1)
+    V = V * np.array([0.3, 0.7, 1.9])
+    d = Discretization(V, p)
+    Ae = d.element_matrices()[0]
+    mu = omesh.cartesian_mu([0.3, 0.7, 1.9])
+    np.testing.assert_allclose(d.mu[0], mu, rtol=1e-13)
+    Ak = separable_cell_matrix(mu, d.ref["A"], d.ref["B"])
+    np.testing.assert_allclose(Ae, Ak, atol=1e-12 * np.abs(Ak).max())
+
+
+def test_fdm_interior_inverse_formula():
+    # Sec. 2.3: (A^K_II)^{-1} = (S x S x S) (Lambda^K)^{-1} (S x S x S)^T
+    p = 5
+    od = setup_1d(p)
+    mu = np.array([0.7, 1.3, 2.1])
+    Ak = separable_cell_matrix(mu, od["A"], od["B"])
+    inner = np.array([k * (p + 1) ** 2 + j * (p + 1) + i for k in range(1, p) for j in range(1, p) for i in range(1, p)])
+    AII = Ak[np.ix_(inner, inner)]
+    S3 = kron3(od["S"], od["S"], od["S"])
+    lam, one = od["lam"], np.ones(p - 1)
+    Lam = mu[0] * kron3(one, one, lam) + mu[1] * kron3(one, lam, one) + mu[2] * kron3(lam, one, one)
+    np.testing.assert_allclose(S3 @ np.diag(1 / Lam) @ S3.T, np.linalg.inv(AII), rtol=1e-10, atol=1e-13)
+
+
+def test_load_vector_integrates_bubble():
+    # f = 1 and u = x(1-x) y(1-y) z(1-z) (in Q_2, zero on the boundary): b.u = (1/6)^3
+    for p in (2, 3, 4):
+        d = Discretization(inputs.cube_vertices(2), p)
+        b = d.load_vector(np.ones((d.ncell, d.q, d.q, d.q)))
+        xi = d.ref["nodes"]
+        x = np.concatenate([(1 + xi[1:]) / 4, 0.5 + (1 + xi[1:-1]) / 4])   # free lattice coordinates
+        ux = x * (1 - x)
+        u = np.einsum("k,j,i->kji", ux, ux, ux).reshape(-1)
+        assert abs(b @ u - 1.0 / 216.0) < 1e-14
+
+
+def test_manufactured_solution_converges():
+    # -Lap u = f with u = prod sin(pi x_i), f = 3 pi^2 u: nodal error ~ h^(p+1) and exponential in p
+    def nodal_error(n, p, amp=0.0):
+        w = inputs.make_problem(n, p, seed=5, jitter=amp)
+        d = Discretization(w["vertices"], p)
+        xq = omesh.physical_points(d.vertices, d.ref["xq"])
+        f = 3 * np.pi ** 2 * np.prod(np.sin(np.pi * xq), axis=-1)
+        b = d.load_vector(f)
+        uh = spla.spsolve(d.assemble().tocsc(), b)
+        xn = omesh.physical_points(d.vertices, d.ref["nodes"])
+        u_cells = np.prod(np.sin(np.pi * xn), axis=-1)
+        K, J, I = d.cell_index()
+        full = np.zeros(d.full_shape)
+        full[K, J, I] = u_cells.reshape(K.shape)
+        return np.abs(uh - d.from_full(full)).max()
+
+    e2, e4 = nodal_error(2, 3), nodal_error(4, 3)
+    assert e4 < e2 / 2 ** 3.5
+    ep = [nodal_error(2, p) for p in (2, 4, 6)]
+    assert ep[1] < ep[0] / 30 and ep[2] < ep[1] / 30
+    assert nodal_error(3, 4, amp=0.15) < 5e-4
+
+
+# ---------------------------------------------------------------- surrogate
+def test_parallelogram_spectrum():
+    # eq. (spectralboundstheta): sheared cell, sigma(mu^-1/2 G mu^-1/2) = [1-|cos t|, 1+|cos t|] (plus 1 from z)
+    for theta in (0.4, 1.0, 2.2):
+        L1, L2, L3 = 0.8, 1.7, 0.6
+        J = np.array([[L1, L2 * np.cos(theta), 0], [0, L2 * np.sin(theta), 0], [0, 0, L3]])
+        G, _ = omesh.inverse_metric(J[None])
+        mu = np.diag(G[0])
+        M = G[0] / np.sqrt(np.outer(mu, mu))
+        ev = np.sort(np.linalg.eigvalsh(M))
+        c = abs(np.cos(theta))
+        np.testing.assert_allclose(ev, np.sort([1 - c, 1 + c, 1.0]), atol=1e-14)
+
+
+def test_theorem1_bounds_on_sheared_mesh():
+    # Theorem 1: c <= a(v,v)/a~(v,v) <= C with c, C from the scaled metric spectrum
+    theta, p = 1.1, 3
+    V = inputs.cube_vertices(2)
+    shear = np.array([[1.0, np.cos(theta), 0], [0, np.sin(theta), 0], [0, 0, 1.0]])
+    V = V @ shear.T
+    d = Discretization(V, p)
+    A = d.assemble().toarray()
+    mu = d.mu
+    Gt = np.zeros_like(d.G)
+    for j in range(3):
+        Gt[..., j, j] = mu[:, j][:, None, None, None]
+    At = d.assemble(d.element_matrices(Gt * d.w3[None, :, :, :, None, None])).toarray()
+    ev = sla.eigh(A, At, eigvals_only=True)
+    c = abs(np.cos(theta))
+    assert ev.min() >= 1 - c - 1e-10 and ev.max() <= 1 + c + 1e-10
+
+
+# ---------------------------------------------------------------- basis change / coarse space
+def test_fdm_prolong_inverts_dual_functionals():
+    # FDM coefficients of u are its values at vertex positions and moments against s_k
+    # along each interior direction (Sec. 2.4); T maps them back to u.
+    p, n = 4, 2
+    d = Discretization(inputs.cube_vertices(n), p)
+    od = setup_1d(p)
+    rng = np.random.default_rng(1)
+    u = rng.standard_normal(d.n)
+    xq, wq = od["xq"], od["wq"]
+    Vq, _ = lagrange(od["nodes"], xq)
+    s_q = Vq[:, 1:p] @ od["S"]                              # s_k at the quadrature points
+    # 1D dual functionals on the lattice: vertex positions -> point value; interior -> moment
+    Lfull = p * n + 1
+    F = np.zeros((Lfull, Lfull))
+    for e in range(n):
+        for kk in range(1, p):
+            F[p * e + kk, p * e:p * e + p + 1] = (wq * s_q[:, kk - 1]) @ Vq
+    for v in range(n + 1):
+        F[p * v, p * v] = 1.0
+    Ffree = F[1:-1, 1:-1]
+    uF = kron3(Ffree, Ffree, Ffree) @ u
+    np.testing.assert_allclose(transfer.fdm_prolong(d, od["T"], uF), u, atol=1e-11)
+
+
+def test_restrict_is_transpose_of_prolong():
+    d, _ = jittered(3, 4)
+    T = setup_1d(4)["T"]
+    rng = np.random.default_rng(2)
+    x, y = rng.standard_normal(d.n), rng.standard_normal(d.n)
+    a = transfer.fdm_prolong(d, T, x) @ y
+    b = x @ transfer.fdm_restrict(d, T, y)
+    assert abs(a - b) < 1e-12 * abs(a)
+    ec = rng.standard_normal((d.nz - 1) * (d.ny - 1) * (d.nx - 1))
+    a = transfer.coarse_prolong(d, ec) @ y
+    b = ec @ transfer.coarse_restrict(d, y)
+    assert abs(a - b) < 1e-12 * abs(a)
+
+
+def test_coarse_hat_and_galerkin():
+    p, n = 3, 3
+    d = Discretization(inputs.cube_vertices(n), p)
+    nc = (n - 1) ** 3
+    P = np.stack([transfer.coarse_prolong(d, e) for e in np.eye(nc)], axis=1)
+    # column of the interior vertex (1,1,1) is the trilinear hat at the GLL nodes
+    g = np.concatenate([(1 + d.ref["nodes"][:-1]) / 2 + e for e in range(n)] + [[n]])[1:-1] / n
+    hat = np.clip(1 - np.abs(g - 1 / 3) * 3, 0, None)
+    np.testing.assert_allclose(P[:, 0], np.einsum("k,j,i->kji", hat, hat, hat).reshape(-1), atol=1e-14)
+    dj, _ = jittered(3, 3, kappa=True)
+    P = np.stack([transfer.coarse_prolong(dj, e) for e in np.eye(nc)], axis=1)
+    A = dj.assemble().toarray()
+    np.testing.assert_allclose(transfer.coarse_matrix(dj), P.T @ A @ P, atol=1e-12 * np.abs(A).max())
+
+
+# ---------------------------------------------------------------- patches
+@pytest.mark.parametrize("p", [2, 3, 4, 7])
+def test_patch_sparsity(p):
+    d = Discretization(inputs.cube_vertices(2), p)
+    pt = Patches(d, setup_1d(p))
+    A = pt.fdm_matrix((1, 1, 1))
+    n1 = 2 * p - 1
+    # nnz equals the 7-point stencil count on the (2p-1)^3 grid (Sec. 2.5)
+    assert A.nnz == n1 ** 3 + 6 * n1 ** 2 * (n1 - 1)
+    _, face = pt.layout((1, 1, 1))
+    rows = np.diff(A.indptr)
+    # an interior row has d + 1 = 4 nonzeros inside the patch
+    assert np.all(rows[~face] == 4)
+
+
+@pytest.mark.parametrize("p", [2, 3, 4])
+def test_sparse_fdm_solve_equals_dense_gll_solve(p):
+    d, _ = jittered(3, p, kappa=True)
+    od = setup_1d(p)
+    pt = Patches(d, od)
+    rng = np.random.default_rng(4)
+    r = rng.standard_normal(d.n)
+    for v in [(1, 1, 1), (0, 1, 2), (0, 0, 3), (3, 3, 3), (1, 2, 2)]:
+        idx = pt.dofs(v)
+        # basis change restricted to the patch: T_j = T restricted, since the patch space
+        # is the same in both bases
+        Tfull = np.stack([transfer.fdm_prolong(d, od["T"], e) for e in np.eye(d.n)[idx]], axis=1)[idx]
+        uF = pt.solve(v, Tfull.T @ r[idx])
+        ug = pt.solve_dense_gll(v, r[idx])
+        np.testing.assert_allclose(Tfull @ uF, ug, rtol=1e-10, atol=1e-12 * np.abs(ug).max())
+
+
+def test_relaxation_fdm_equals_definition():
+    d, _ = jittered(3, 3, kappa=True)
+    s = Solver(d, setup_1d(3), omega=1.0)
+    r = np.random.default_rng(5).standard_normal(d.n)
+    np.testing.assert_allclose(s.relax(r), s.patches.relax_gll_dense(r), rtol=1e-10, atol=1e-12)
+
+
+# ---------------------------------------------------------------- solver
+def test_single_patch_case_is_exact_solve():
+    # 2^3 Cartesian, interior patches only: the one patch holds every DOF and the surrogate
+    # equals A, so S A = I: Lanczos gives 1, omega = 1, PCG converges in one iteration
+    w = inputs.make_problem(2, 3, seed=0)
+    d = Discretization(w["vertices"], 3)
+    b = d.load_vector(w["f"])
+    s = Solver(d, setup_1d(3), interior_only=True)
+    assert abs(s.lanczos[0] - 1) < 1e-12 and abs(s.lanczos[1] - 1) < 1e-12
+    assert abs(s.omega - 1) < 1e-12
+    x, it = s.pcg(b)
+    assert it == 1
+    xd = np.linalg.solve(d.assemble().toarray(), b)
+    np.testing.assert_allclose(x, xd, rtol=0, atol=1e-12 * np.abs(xd).max())
+
+
+def test_lanczos_inside_dense_spectrum_and_pcg_matches_direct():
+    d, w = jittered(2, 3, kappa=True)
+    od = setup_1d(3)
+    s = Solver(d, od)
+    A = d.assemble().toarray()
+    Smat = np.stack([s.relax(e) for e in np.eye(d.n)], axis=1)
+    ev = np.sort(np.linalg.eigvals(Smat @ A).real)
+    lmin, lmax = s.lanczos
+    assert ev[0] - 1e-10 <= lmin and lmax <= ev[-1] + 1e-10
+    assert lmax > 0.95 * ev[-1]
+    assert abs(s.omega - 2 / ((1 + ALPHA) * lmax + (1 - ALPHA) * lmin)) < 1e-15
+    M = np.stack([s.precondition(e) for e in np.eye(d.n)], axis=1)
+    np.testing.assert_allclose(M, M.T, atol=1e-12 * np.abs(M).max())
+    assert np.linalg.eigvalsh(0.5 * (M + M.T)).min() > 0
+    b = d.load_vector(w["f"])
+    x, it = s.pcg(b)
+    xd = np.linalg.solve(A, b)
+    assert np.linalg.norm(b - A @ x) <= 1.0000001e-8 * np.linalg.norm(b)
+    assert np.linalg.norm(x - xd) / np.linalg.norm(xd) < 1e-6
+    xa, ita = Solver(d, od, cycle="additive").pcg(b)
+    assert ita > it
+
+
+def test_iterations_nearly_flat_in_p():
+    # Sec. 2.8: on Cartesian meshes the iteration count is almost independent of p
+    its = []
+    for p in (2, 3, 4, 5):
+        w = inputs.make_problem(3, p, seed=1)
+        d = Discretization(w["vertices"], p)
+        _, it = Solver(d, setup_1d(p)).pcg(d.load_vector(w["f"]))
+        its.append(it)
+    assert max(its) - min(its) <= 2, its
