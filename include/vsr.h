@@ -1,0 +1,147 @@
+/*
+ * vsr.h -- C ABI of the MI355X (gfx950) vertex-star FDM/sparse relaxation solver.
+ *
+ * Method: Brubeck & Farrell, "A scalable and robust vertex-star relaxation for
+ * high-order FEM" (SIAM J. Sci. Comput., 2022), Sec. 2.  The library solves the
+ * Poisson problem -div(kappa grad u) = f with homogeneous Dirichlet conditions
+ * (weak form of Sec. 2.1), discretized with continuous Q_p on a structured mesh
+ * of trilinear hexahedra, by PCG (Sec. 2.8) preconditioned with the hybrid
+ * two-level V(1,1) cycle of Sec. 2.5: vertex-star additive Schwarz relaxation
+ * in the FDM basis (Sec. 2.4) with exact sparse-Cholesky patch solves (Sec. 2.6)
+ * of the separable surrogate form (Sec. 2.7), and a Q1 coarse correction.
+ *
+ * Conventions shared by every call
+ *  - Every call returns a vsr_status and never throws.  On error the outputs are
+ *    unspecified and vsr_last_error() describes the failure (thread-local text,
+ *    valid until the next failing call on that thread).  A problem stays usable
+ *    after any error except VSR_EDEVICE.
+ *  - Host arrays passed to vsr_setup are copied; the caller may free them on
+ *    return.  Vector arguments are caller-owned FP64 device buffers (HIP device
+ *    memory on the current device) of length vsr_num_dofs(); inputs and outputs
+ *    must not alias.  The library owns, and vsr_destroy frees, everything else.
+ *  - Vector layout: the free DOFs are the interior nodes of the global GLL
+ *    lattice of (p*nx+1) x (p*ny+1) x (p*nz+1) nodes, in lexicographic order
+ *    with x fastest: index (i-1) + (j-1)*Lx + (k-1)*Lx*Ly, Lx = p*nx-1, ...
+ *  - Work runs on options.stream (NULL = the default stream).  Apply calls are
+ *    asynchronous; vsr_pcg_solve returns after the solve has completed.
+ */
+#ifndef VSR_H
+#define VSR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct vsr_problem vsr_problem;
+
+typedef enum {
+    VSR_OK = 0,
+    VSR_EINVAL = 1,   /* bad argument: p outside [2,15], a mesh axis with < 2 cells,
+                         a non-finite input, a NULL pointer, an unknown mode */
+    VSR_EMESH = 2,    /* a cell with det(DF) <= 0 at a quadrature point */
+    VSR_ENOTSPD = 3,  /* a non-positive pivot in a patch or coarse Cholesky factor
+                         (e.g. a coefficient kappa <= 0) */
+    VSR_ENOCONV = 4,  /* PCG stopped at max_iterations before reaching rtol, or broke down */
+    VSR_EDEVICE = 5,  /* a HIP runtime error */
+    VSR_ENOMEM = 6    /* device or host allocation failed */
+} vsr_status;
+
+/* Structured hexahedral mesh (Sec. 2.1): nx*ny*nz cells, vertex (i,j,k) at
+ * vertices[3*(i + (nx+1)*(j + (ny+1)*k)) + c], c = 0,1,2 the coordinates.
+ * Cell (ex,ey,ez) is the trilinear image of [-1,1]^3 whose reference corner
+ * (a,b,c) in {0,1}^3 maps to vertex (ex+a, ey+b, ez+c).  Host memory, copied. */
+typedef struct {
+    int32_t nx, ny, nz;
+    const double *vertices;
+} vsr_mesh;
+
+/* Coefficients.  kappa: host, one positive value per cell (cell index
+ * ex + nx*(ey + ny*ez)), NULL means kappa = 1.  mu_override: host, 3 values per
+ * cell replacing the averaged surrogate scalings mu_j of Sec. 2.7 (used by a
+ * learned surrogate); NULL means the cell averages of the paper. */
+typedef struct {
+    const double *kappa;
+    const double *mu_override;
+} vsr_coefficients;
+
+typedef struct {
+    int32_t relax_fp32;      /* 1: relaxation, coarse correction and the cycle's inner
+                                operator applies in FP32 (outer PCG stays FP64); 0: all FP64 */
+    int32_t cycle;           /* 0: hybrid multiplicative V(1,1) (Sec. 2.5, default);
+                                1: additive z = S r + P A0^{-1} P^T r */
+    int32_t quad_points;     /* GLL points per direction; 0 => ceil(3(p+1)/2) (Sec. 2.8) */
+    int32_t lanczos_steps;   /* CG-Lanczos steps for the damping estimate; 0 => 20 */
+    int32_t max_iterations;  /* PCG iteration cap; 0 => 1000 */
+    int32_t interior_patches_only; /* 1: patches only around interior vertices; 0: every vertex */
+    uint64_t seed;           /* seed of the splitmix64 Lanczos start vector */
+    double omega;            /* > 0: use this damping instead of the Lanczos estimate */
+    void *stream;            /* hipStream_t; NULL => default stream */
+} vsr_options;
+
+typedef struct {
+    int32_t iterations;        /* number of x updates */
+    int32_t converged;         /* 1 if ||r||_2 <= rtol ||b||_2 was reached */
+    double rel_residual;       /* recursive residual norm / ||b||_2 at exit */
+    double true_rel_residual;  /* ||b - A x||_2 / ||b||_2 recomputed in FP64 at exit */
+    double omega, lambda_min, lambda_max;  /* damping and its Lanczos estimates */
+    double setup_seconds, solve_seconds;
+} vsr_solve_info;
+
+/* Fill *opt with the defaults listed above (all zero except the library's defaults). */
+void vsr_default_options(vsr_options *opt);
+
+/* Build everything the solve needs (Sec. 2.2-2.7): 1D GLL/FDM data, geometry and
+ * surrogate scalings, the Cholesky factor of every vertex-star patch, the Q1
+ * coarse matrix and its inverse, the damping omega (CG-Lanczos unless given).
+ * p in [2, 15]; mesh axes >= 2 cells.  *out receives a new problem. */
+vsr_status vsr_setup(const vsr_mesh *mesh, int32_t p, const vsr_coefficients *coef,
+                     const vsr_options *opt, vsr_problem **out);
+
+/* Number of free DOFs (length of every vector argument), or -1 for NULL. */
+int64_t vsr_num_dofs(const vsr_problem *prob);
+
+/* Load vector b_i = sum_K sum_q w_q |det DF(x_q)| phi_i(x_q) f_{K,q} (Sec. 2.1).
+ * f_dev: device FP64, one sample per cell and quadrature point, cell-major, points
+ * in x-fastest tensor order (ncell * quad_points^3 values).  b_dev: device FP64 (n). */
+vsr_status vsr_load_vector(vsr_problem *prob, const double *f_dev, double *b_dev);
+
+/* y = A x, the matrix-free sum-factorized Galerkin operator (Sec. 2.1, 2.7), FP64. */
+vsr_status vsr_apply_operator(vsr_problem *prob, const double *x_dev, double *y_dev);
+
+/* z = M r with mode 0: the full preconditioner (cycle chosen at setup);
+ * mode 1: the patch relaxation alone, z = T (sum_j Rbar_j^T A_j^{-1} Rbar_j) T^T r
+ * (Sec. 2.4-2.6, undamped); mode 2: the coarse correction z = P A0^{-1} P^T r. */
+vsr_status vsr_apply_relaxation(vsr_problem *prob, const double *r_dev, double *z_dev, int32_t mode);
+
+/* PCG (Sec. 2.8) from x = 0 until ||r||_2 <= rtol ||b||_2; x_dev receives the
+ * solution.  info may be NULL.  Returns VSR_ENOCONV if max_iterations is reached. */
+vsr_status vsr_pcg_solve(vsr_problem *prob, const double *b_dev, double *x_dev, double rtol,
+                         vsr_solve_info *info);
+
+/* Damping and Lanczos estimates chosen at setup. */
+vsr_status vsr_get_damping(const vsr_problem *prob, double *omega, double *lambda_min,
+                           double *lambda_max);
+
+/* Timing of the patch-solve kernels (the dominant kernel).  enable != 0 makes
+ * every later relaxation record HIP events around its patch-solve launches on the
+ * problem's stream; vsr_kernel_stats returns the launch count, total milliseconds
+ * and the algorithmic bytes one launch moves (factor entries read twice plus the
+ * patch vectors read and written), and resets the counters. */
+vsr_status vsr_set_profiling(vsr_problem *prob, int32_t enable);
+vsr_status vsr_kernel_stats(vsr_problem *prob, int64_t *launches, double *total_ms,
+                            double *bytes_per_launch);
+
+/* Sizes of the patch factorization: number of patches and stored factor entries. */
+vsr_status vsr_factor_info(const vsr_problem *prob, int64_t *num_patches, int64_t *factor_entries);
+
+void vsr_destroy(vsr_problem *prob);
+
+/* Description of the last failure on the calling thread ("" if none). */
+const char *vsr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VSR_H */

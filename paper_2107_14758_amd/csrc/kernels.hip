@@ -1,0 +1,980 @@
+// HIP kernels for gfx950 (CDNA4, wave64).
+//
+// Method references: Brubeck & Farrell, "A scalable and robust vertex-star
+// relaxation for high-order FEM", Sec. 2.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <stdexcept>
+
+#include "kernels.h"
+#include "vsr_internal.h"
+
+namespace vsr {
+
+namespace {
+
+constexpr int QOF(int P) { return (3 * (P + 1) + 1) / 2; }
+
+__device__ __forceinline__ bool is_free(const Dims &d, int K, int J, int I) {
+    return K >= 1 && K <= d.Lz && J >= 1 && J <= d.Ly && I >= 1 && I <= d.Lx;
+}
+__device__ __forceinline__ int64_t free_index(const Dims &d, int K, int J, int I) {
+    return ((int64_t)(K - 1) * d.Ly + (J - 1)) * d.Lx + (I - 1);
+}
+
+template <typename T>
+__device__ __forceinline__ void atomic_add_global(T *p, T v) {
+    unsafeAtomicAdd(p, v);
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// ====================================================================== operator
+// Separable (Cartesian) cell operator, eq. (kron) of Sec. 2.2:
+// A^K = mu1 B x B x A + mu2 B x A x B + mu3 A x B x B, evaluated per z-slab in LDS with
+// the z contraction done per (j, i) column in registers.
+template <typename T, int P>
+__global__ void __launch_bounds__(256) k_op_kron(Dims d, const T *__restrict__ AB1d, const T *__restrict__ mu,
+                                                 const T *__restrict__ x, T *__restrict__ y) {
+    constexpr int N1 = P + 1, N2 = N1 * N1;
+    __shared__ T sA[N2], sB[N2], xs[N2], as[N2], bs[N2];
+    const int tid = threadIdx.x;
+    for (int t = tid; t < N2; t += blockDim.x) {
+        sA[t] = AB1d[t];
+        sB[t] = AB1d[N2 + t];
+    }
+    const int64_t e = blockIdx.x;
+    const int ex = (int)(e % d.nx), ey = (int)((e / d.nx) % d.ny), ez = (int)(e / ((int64_t)d.nx * d.ny));
+    const T m0 = mu[3 * e], m1 = mu[3 * e + 1], m2 = mu[3 * e + 2];
+    const bool active = tid < N2;
+    const int j = tid / N1, i = tid % N1;
+    T wv[N1], sv[N1];
+#pragma unroll
+    for (int k = 0; k < N1; ++k) {
+        __syncthreads();
+        if (active) {
+            int K = P * ez + k, J = P * ey + j, I = P * ex + i;
+            xs[tid] = is_free(d, K, J, I) ? x[free_index(d, K, J, I)] : T(0);
+        }
+        __syncthreads();
+        if (active) {
+            T a = 0, b = 0;
+#pragma unroll
+            for (int ii = 0; ii < N1; ++ii) {
+                a += sA[i * N1 + ii] * xs[j * N1 + ii];
+                b += sB[i * N1 + ii] * xs[j * N1 + ii];
+            }
+            as[tid] = a;
+            bs[tid] = b;
+        }
+        __syncthreads();
+        if (active) {
+            T c1 = 0, c2 = 0, c3 = 0;
+#pragma unroll
+            for (int jj = 0; jj < N1; ++jj) {
+                c1 += sB[j * N1 + jj] * as[jj * N1 + i];
+                c2 += sA[j * N1 + jj] * bs[jj * N1 + i];
+                c3 += sB[j * N1 + jj] * bs[jj * N1 + i];
+            }
+            wv[k] = m0 * c1 + m1 * c2;
+            sv[k] = m2 * c3;
+        }
+    }
+    if (!active) return;
+#pragma unroll
+    for (int k = 0; k < N1; ++k) {
+        T acc = 0;
+#pragma unroll
+        for (int kk = 0; kk < N1; ++kk) acc += sB[k * N1 + kk] * wv[kk] + sA[k * N1 + kk] * sv[kk];
+        int K = P * ez + k, J = P * ey + j, I = P * ex + i;
+        if (is_free(d, K, J, I)) atomic_add_global(&y[free_index(d, K, J, I)], acc);
+    }
+}
+
+// General trilinear cell: y_K = (grad phi)^T Gw (grad phi) x_K with the q^3 GLL rule
+// (Sec. 2.1, 2.7).  Thread (b, a) owns one z-column of quadrature points; the x and y
+// contractions run per z-slab through LDS, the z contraction and the metric in registers.
+template <typename T, int P>
+__global__ void __launch_bounds__(1024) k_op_general(Dims d, const T *__restrict__ IDq, const T *__restrict__ Gw,
+                                                     const T *__restrict__ x, T *__restrict__ y) {
+    constexpr int N1 = P + 1, Q = QOF(P), Q2 = Q * Q, Q3 = Q2 * Q;
+    __shared__ T sI[Q * N1], sD[Q * N1], xs[N1 * N1], X1[N1 * Q], DX1[N1 * Q], S0[Q2], S1[Q2], S2[Q2];
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int t = tid; t < Q * N1; t += nt) {
+        sI[t] = IDq[t];
+        sD[t] = IDq[Q * N1 + t];
+    }
+    const int64_t e = blockIdx.x;
+    const int ex = (int)(e % d.nx), ey = (int)((e / d.nx) % d.ny), ez = (int)(e / ((int64_t)d.nx * d.ny));
+    const bool col = tid < Q2;
+    const int b = tid / Q, a = tid % Q;
+    T AA[N1], AB[N1], BA[N1];
+#pragma unroll
+    for (int k = 0; k < N1; ++k) {
+        __syncthreads();
+        for (int t = tid; t < N1 * N1; t += nt) {
+            int jj = t / N1, ii = t % N1;
+            int K = P * ez + k, J = P * ey + jj, I = P * ex + ii;
+            xs[t] = is_free(d, K, J, I) ? x[free_index(d, K, J, I)] : T(0);
+        }
+        __syncthreads();
+        for (int t = tid; t < N1 * Q; t += nt) {
+            int jj = t / Q, aa = t % Q;
+            T s0 = 0, s1 = 0;
+#pragma unroll
+            for (int ii = 0; ii < N1; ++ii) {
+                s0 += sI[aa * N1 + ii] * xs[jj * N1 + ii];
+                s1 += sD[aa * N1 + ii] * xs[jj * N1 + ii];
+            }
+            X1[t] = s0;
+            DX1[t] = s1;
+        }
+        __syncthreads();
+        if (col) {
+            T s0 = 0, s1 = 0, s2 = 0;
+#pragma unroll
+            for (int jj = 0; jj < N1; ++jj) {
+                s0 += sI[b * N1 + jj] * X1[jj * Q + a];
+                s1 += sD[b * N1 + jj] * X1[jj * Q + a];
+                s2 += sI[b * N1 + jj] * DX1[jj * Q + a];
+            }
+            AA[k] = s0;
+            AB[k] = s1;
+            BA[k] = s2;
+        }
+    }
+    T AAo[N1], ABo[N1], BAo[N1];
+#pragma unroll
+    for (int k = 0; k < N1; ++k) AAo[k] = ABo[k] = BAo[k] = 0;
+    if (col) {
+        const T *g = Gw + e * 6 * (int64_t)Q3;
+        for (int c = 0; c < Q; ++c) {
+            T ux = 0, uy = 0, uz = 0;
+#pragma unroll
+            for (int k = 0; k < N1; ++k) {
+                ux += sI[c * N1 + k] * BA[k];
+                uy += sI[c * N1 + k] * AB[k];
+                uz += sD[c * N1 + k] * AA[k];
+            }
+            int pt = c * Q2 + tid;
+            T gxx = g[pt], gyy = g[Q3 + pt], gzz = g[2 * Q3 + pt], gxy = g[3 * Q3 + pt], gxz = g[4 * Q3 + pt],
+              gyz = g[5 * Q3 + pt];
+            T vx = gxx * ux + gxy * uy + gxz * uz;
+            T vy = gxy * ux + gyy * uy + gyz * uz;
+            T vz = gxz * ux + gyz * uy + gzz * uz;
+#pragma unroll
+            for (int k = 0; k < N1; ++k) {
+                AAo[k] += sD[c * N1 + k] * vz;
+                ABo[k] += sI[c * N1 + k] * vy;
+                BAo[k] += sI[c * N1 + k] * vx;
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < N1; ++k) {
+        __syncthreads();
+        if (col) {
+            S0[tid] = AAo[k];
+            S1[tid] = ABo[k];
+            S2[tid] = BAo[k];
+        }
+        __syncthreads();
+        for (int t = tid; t < N1 * Q; t += nt) {
+            int jj = t / Q, aa = t % Q;
+            T s0 = 0, s1 = 0;
+            for (int bb = 0; bb < Q; ++bb) {
+                s0 += sI[bb * N1 + jj] * S0[bb * Q + aa] + sD[bb * N1 + jj] * S1[bb * Q + aa];
+                s1 += sI[bb * N1 + jj] * S2[bb * Q + aa];
+            }
+            X1[t] = s0;
+            DX1[t] = s1;
+        }
+        __syncthreads();
+        for (int t = tid; t < N1 * N1; t += nt) {
+            int jj = t / N1, ii = t % N1;
+            T s = 0;
+            for (int aa = 0; aa < Q; ++aa) s += sI[aa * N1 + ii] * X1[jj * Q + aa] + sD[aa * N1 + ii] * DX1[jj * Q + aa];
+            int K = P * ez + k, J = P * ey + jj, I = P * ex + ii;
+            if (is_free(d, K, J, I)) atomic_add_global(&y[free_index(d, K, J, I)], s);
+        }
+    }
+}
+
+// Load vector (Sec. 2.1): b += sum_K R_K^T (I x I x I)^T (w |det DF| f).
+template <int P>
+__global__ void __launch_bounds__(1024) k_load_vector(Dims d, const double *__restrict__ IDq, const double *__restrict__ wdet,
+                                                      const double *__restrict__ f, double *__restrict__ bvec) {
+    constexpr int N1 = P + 1, Q = QOF(P), Q2 = Q * Q, Q3 = Q2 * Q;
+    __shared__ double sI[Q * N1], X1[N1 * Q], S0[Q2];
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int t = tid; t < Q * N1; t += nt) sI[t] = IDq[t];
+    const int64_t e = blockIdx.x;
+    const int ex = (int)(e % d.nx), ey = (int)((e / d.nx) % d.ny), ez = (int)(e / ((int64_t)d.nx * d.ny));
+    const bool col = tid < Q2;
+    double acc[N1];
+#pragma unroll
+    for (int k = 0; k < N1; ++k) acc[k] = 0;
+    __syncthreads();
+    if (col) {
+        for (int c = 0; c < Q; ++c) {
+            int64_t pt = e * Q3 + c * Q2 + tid;
+            double g = f[pt] * wdet[pt];
+#pragma unroll
+            for (int k = 0; k < N1; ++k) acc[k] += sI[c * N1 + k] * g;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < N1; ++k) {
+        __syncthreads();
+        if (col) S0[tid] = acc[k];
+        __syncthreads();
+        for (int t = tid; t < N1 * Q; t += nt) {
+            int jj = t / Q, aa = t % Q;
+            double s = 0;
+            for (int bb = 0; bb < Q; ++bb) s += sI[bb * N1 + jj] * S0[bb * Q + aa];
+            X1[t] = s;
+        }
+        __syncthreads();
+        for (int t = tid; t < N1 * N1; t += nt) {
+            int jj = t / N1, ii = t % N1;
+            double s = 0;
+            for (int aa = 0; aa < Q; ++aa) s += sI[aa * N1 + ii] * X1[jj * Q + aa];
+            int K = P * ez + k, J = P * ey + jj, I = P * ex + ii;
+            if (is_free(d, K, J, I)) atomic_add_global(&bvec[free_index(d, K, J, I)], s);
+        }
+    }
+}
+
+// ====================================================================== lattice passes
+// out = alpha * M_axis in + beta * out, with M given by a CSR table over output positions
+// along one axis (the GLL<->FDM basis change of Sec. 2.4 and the Q1 transfers of Sec. 2.5).
+template <typename Tin, typename Tout>
+__global__ void k_axis_pass(const int *__restrict__ rowptr, const int *__restrict__ col, const Tout *__restrict__ w,
+                            int axis, int ix, int iy, int iz, int ox, int oy, int oz, const Tin *__restrict__ in,
+                            Tout *__restrict__ out, Tout alpha, Tout beta) {
+    const int64_t total = (int64_t)ox * oy * oz;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        int cx = (int)(idx % ox);
+        int cy = (int)((idx / ox) % oy);
+        int cz = (int)(idx / ((int64_t)ox * oy));
+        int o = axis == 0 ? cx : (axis == 1 ? cy : cz);
+        Tout s = 0;
+        for (int t = rowptr[o]; t < rowptr[o + 1]; ++t) {
+            int c = col[t];
+            int jx = axis == 0 ? c : cx, jy = axis == 1 ? c : cy, jz = axis == 2 ? c : cz;
+            s += w[t] * (Tout)in[((int64_t)jz * iy + jy) * ix + jx];
+        }
+        out[idx] = beta == Tout(0) ? alpha * s : alpha * s + beta * out[idx];
+    }
+}
+
+// ====================================================================== patches
+// Box coordinates of a vertex star run over [0, 2m] per axis; the central plane is at m.
+// A box position pos maps to the free lattice index p (v - 1) + pos.
+
+__device__ __forceinline__ int la_(int a, int m) { return a < m ? a : a - 1; }
+__device__ __forceinline__ int inv_la_(int c, int m) { return c < m ? c : c + 1; }
+
+// interface index of the interior-class ordering (leaves, level-1 separators, top plane)
+__device__ __forceinline__ int iface_interior(int ax, int ay, int az, int m, int w, int nl, int ns) {
+    if (az == m) return nl + ns + ay * w + ax;
+    if (ax == m) return nl + la_(az, m) * w + ay;
+    if (ay == m) return la_(az, m) * 2 * m + la_(ax, m);
+    return -1;
+}
+
+template <typename T>
+struct PatchCtx {
+    Dims d;
+    int vx, vy, vz, m, p;
+    const T *mu, *lam, *afc, *rF;
+    __device__ int64_t gidx(int ax, int ay, int az) const {
+        return ((int64_t)(p * (vz - 1) + az) * d.Ly + (p * (vy - 1) + ay)) * d.Lx + (p * (vx - 1) + ax);
+    }
+    __device__ const T *cell_mu(int cx, int cy, int cz) const {
+        int ex = vx - 1 + cx, ey = vy - 1 + cy, ez = vz - 1 + cz;
+        return mu + 3 * ((int64_t)ex + d.nx * ((int64_t)ey + d.ny * (int64_t)ez));
+    }
+    // r_F at a face DOF minus the condensed interior lines of its two cells along axis dd:
+    // g = r_G - A_GI A_II^{-1} r_I (Sec. 2.6), A_II = mu . lambda, A_GI = mu_dd A_F[interior, vertex].
+    __device__ T condensed(const int pos[3], int dd) const {
+        T g = rF[gidx(pos[0], pos[1], pos[2])];
+        int c[3], l[3];
+        for (int a = 0; a < 3; ++a) {
+            c[a] = pos[a] > m;
+            l[a] = c[a] ? pos[a] - m : pos[a] + 1;
+        }
+        T acc = 0;
+        for (int cd = 0; cd < 2; ++cd) {
+            c[dd] = cd;
+            const T *mk = cell_mu(c[0], c[1], c[2]);
+            T base = 0;
+            for (int a = 0; a < 3; ++a)
+                if (a != dd) base += mk[a] * lam[l[a] - 1];
+            int q[3] = {pos[0], pos[1], pos[2]};
+            for (int t = 1; t <= m; ++t) {
+                q[dd] = cd == 0 ? t - 1 : m + t;
+                T D = base + mk[dd] * lam[t - 1];
+                acc += mk[dd] * afc[cd * m + t - 1] * rF[gidx(q[0], q[1], q[2])] / D;
+            }
+        }
+        return g - acc;
+    }
+    // u_I = A_II^{-1}(r_I - A_IG u_G) at an interior DOF; face(dd) gives the interface value
+    template <typename F>
+    __device__ T back_interior(const int pos[3], const bool full[3], F face) const {
+        int c[3], l[3];
+        for (int a = 0; a < 3; ++a) {
+            c[a] = pos[a] > m;
+            l[a] = c[a] ? pos[a] - m : pos[a] + 1;
+        }
+        const T *mk = cell_mu(c[0], c[1], c[2]);
+        T D = mk[0] * lam[l[0] - 1] + mk[1] * lam[l[1] - 1] + mk[2] * lam[l[2] - 1];
+        T u = rF[gidx(pos[0], pos[1], pos[2])];
+        for (int a = 0; a < 3; ++a)
+            if (full[a]) u -= mk[a] * afc[c[a] * m + l[a] - 1] * face(a);
+        return u / D;
+    }
+};
+
+// Dense lower-triangular solves by one wavefront (n <= MAXW <= 64).  Lane i holds row i
+// of L (column-major storage, inverse diagonal) in registers; forward substitution
+// broadcasts each solved value, the transposed solve reduces across lanes.
+template <typename T, int MAXW>
+__device__ __forceinline__ void wave_load_rows(const T *__restrict__ L, int ld, int n, int lane, T (&row)[MAXW]) {
+#pragma unroll
+    for (int k = 0; k < MAXW; ++k) row[k] = (k < n && lane < n) ? L[(int64_t)k * ld + lane] : T(0);
+}
+
+template <typename T, int MAXW>
+__device__ __forceinline__ T wave_forward(const T (&row)[MAXW], int n, int lane, T x) {
+#pragma unroll
+    for (int k = 0; k < MAXW; ++k) {
+        if (k < n) {
+            if (lane == k) x *= row[k];
+            T yk = __shfl(x, k, 64);
+            if (lane > k) x -= row[k] * yk;
+        }
+    }
+    return x;
+}
+
+template <typename T, int MAXW>
+__device__ __forceinline__ T wave_backward(const T (&row)[MAXW], int n, int lane, T x) {
+#pragma unroll
+    for (int k = MAXW - 1; k >= 0; --k) {
+        if (k < n) {
+            T part = (lane > k && lane < n) ? row[k] * x : T(0);
+            T s = wave_sum(part);
+            if (lane == k) x = (x - s) * row[k];
+        }
+    }
+    return x;
+}
+
+template <typename T>
+struct Vec4 {
+    T v[4];
+};
+template <typename T>
+__device__ __forceinline__ Vec4<T> load4(const T *p);
+template <>
+__device__ __forceinline__ Vec4<float> load4<float>(const float *p) {
+    float4 a = *reinterpret_cast<const float4 *>(p);
+    return {{a.x, a.y, a.z, a.w}};
+}
+template <>
+__device__ __forceinline__ Vec4<double> load4<double>(const double *p) {
+    double2 a = *reinterpret_cast<const double2 *>(p);
+    double2 b = *reinterpret_cast<const double2 *>(p + 2);
+    return {{a.x, a.y, b.x, b.y}};
+}
+
+// y[r] -= sum_c M[c * ld + r] x[c] for r < nrows (ld multiple of 4, M 16-byte aligned);
+// x, y in LDS.  Work split over (row quads) x (column chunks), accumulated with LDS atomics.
+template <typename T>
+__device__ void panel_fwd(const T *__restrict__ M, int ld, int nrows, int ncols, const T *x, T *y) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int nq = (nrows + 3) / 4;
+    if (nq == 0 || ncols == 0) return;
+    int nch = max(1, min(ncols, nt / nq));
+    int chunk = (ncols + nch - 1) / nch;
+    for (int task = tid; task < nq * nch; task += nt) {
+        int rq = task % nq, ch = task / nq;
+        int c0 = ch * chunk, c1 = min(ncols, c0 + chunk);
+        T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+        const T *col = M + (int64_t)c0 * ld + 4 * rq;
+        for (int c = c0; c < c1; ++c, col += ld) {
+            Vec4<T> v = load4(col);
+            T xc = x[c];
+            a0 += v.v[0] * xc;
+            a1 += v.v[1] * xc;
+            a2 += v.v[2] * xc;
+            a3 += v.v[3] * xc;
+        }
+        int r = 4 * rq;
+        if (nch == 1) {
+            if (r < nrows) y[r] -= a0;
+            if (r + 1 < nrows) y[r + 1] -= a1;
+            if (r + 2 < nrows) y[r + 2] -= a2;
+            if (r + 3 < nrows) y[r + 3] -= a3;
+        } else {
+            if (r < nrows) atomicAdd(&y[r], -a0);
+            if (r + 1 < nrows) atomicAdd(&y[r + 1], -a1);
+            if (r + 2 < nrows) atomicAdd(&y[r + 2], -a2);
+            if (r + 3 < nrows) atomicAdd(&y[r + 3], -a3);
+        }
+    }
+}
+
+// y[c] -= sum_r M[c * ld + r] x[r] for c < ncols (one wavefront per column).
+template <typename T>
+__device__ void panel_bwd(const T *__restrict__ M, int ld, int nrows, int ncols, const T *x, T *y) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int c = wv; c < ncols; c += nw) {
+        const T *col = M + (int64_t)c * ld;
+        T s = 0;
+        for (int r = 4 * lane; r < nrows; r += 256) {
+            Vec4<T> v = load4(col + r);
+            s += v.v[0] * x[r];
+            if (r + 1 < nrows) s += v.v[1] * x[r + 1];
+            if (r + 2 < nrows) s += v.v[2] * x[r + 2];
+            if (r + 3 < nrows) s += v.v[3] * x[r + 3];
+        }
+        s = wave_sum(s);
+        if (lane == 0) y[c] -= s;
+    }
+}
+
+// Interior-vertex patch solve, one workgroup per patch (Sec. 2.6): condensation of the
+// diagonal interior block, then the nested-dissection Cholesky factor of the interface
+// Schur complement (leaves, level-1 separator slices, dense top plane), forward and
+// backward, then interior back-substitution.  Output: the patch box of (2m+1)^3 values.
+template <typename T, int P>
+__global__ void __launch_bounds__(256) k_patch_interior(Dims d, PatchArgs A, const int *__restrict__ verts,
+                                                        const T *__restrict__ factor, const T *__restrict__ mu,
+                                                        const T *__restrict__ lam, const T *__restrict__ afc,
+                                                        const T *__restrict__ rF, T *__restrict__ U) {
+    constexpr int M = P - 1, W = 2 * M + 1, NL = 4 * M * M, NS = 2 * M * W, NT = W * W, NI = NL + NS + NT;
+    __shared__ T g[NI];
+    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
+    const int pid = blockIdx.x;
+    PatchCtx<T> C{d, verts[3 * pid], verts[3 * pid + 1], verts[3 * pid + 2], M, P, mu, lam, afc, rF};
+    const T *F = factor + (int64_t)pid * A.stride;
+    T *Uo = U + ((int64_t)(C.vz * (d.ny + 1) + C.vy) * (d.nx + 1) + C.vx) * (int64_t)(W * W * W);
+
+    // ---- condensation of the interior DOFs into the interface right-hand side
+    for (int idx = tid; idx < NI; idx += nt) {
+        int pos[3];
+        if (idx < NL) {
+            pos[2] = inv_la_(idx / (2 * M), M); pos[0] = inv_la_(idx % (2 * M), M); pos[1] = M;
+        } else if (idx < NL + NS) {
+            int t = idx - NL;
+            pos[2] = inv_la_(t / W, M); pos[1] = t % W; pos[0] = M;
+        } else {
+            int t = idx - NL - NS;
+            pos[1] = t / W; pos[0] = t % W; pos[2] = M;
+        }
+        int ncen = (pos[0] == M) + (pos[1] == M) + (pos[2] == M);
+        int dd = pos[0] == M ? 0 : (pos[1] == M ? 1 : 2);
+        g[idx] = ncen == 1 ? C.condensed(pos, dd) : rF[C.gidx(pos[0], pos[1], pos[2])];
+    }
+    __syncthreads();
+    // ---- forward: leaves (diagonal)
+    const T *invd = F + A.off_invd, *B1 = F + A.off_B1, *B2 = F + A.off_B2;
+    for (int i = tid; i < NL; i += nt) g[i] *= invd[i];
+    __syncthreads();
+    // leaf columns update their level-1 slice and their top-plane line
+    for (int task = tid; task < 2 * NS; task += nt) {
+        if (task < NS) {
+            int s = task / W, r = task % W;
+            T acc = 0;
+            for (int c = 0; c < 2 * M; ++c) acc += B1[(int64_t)(s * 2 * M + c) * W + r] * g[s * 2 * M + c];
+            g[NL + s * W + r] -= acc;
+        } else {
+            int t = task - NS, lx = t / W, ay = t % W;
+            T acc = 0;
+            for (int c = 0; c < 2 * M; ++c) acc += B2[(int64_t)(lx * 2 * M + c) * W + ay] * g[c * 2 * M + lx];
+            g[NL + NS + ay * W + inv_la_(lx, M)] -= acc;
+        }
+    }
+    __syncthreads();
+    // level-1 separator slices: dense lower solves, one wavefront per slice
+    {
+        T row[W];
+        for (int s = wv; s < 2 * M; s += nw) {
+            wave_load_rows<T, W>(F + A.off_Lsep + (int64_t)s * W * W, W, W, lane, row);
+            T x = lane < W ? g[NL + s * W + lane] : T(0);
+            x = wave_forward<T, W>(row, W, lane, x);
+            if (lane < W) g[NL + s * W + lane] = x;
+        }
+    }
+    __syncthreads();
+    // level-1 panels update the top plane
+    panel_fwd<T>(F + A.off_P, A.top_pad, NT, NS, g + NL, g + NL + NS);
+    __syncthreads();
+    // dense top plane, 64-column tiles
+    T *gt = g + NL + NS;
+    for (int J = 0; J < A.ntiles; ++J) {
+        const int c0 = 64 * J, nb = min(64, NT - c0);
+        const T *D = F + A.tile_off[J];
+        if (wv == 0) {
+            T row[64];
+            wave_load_rows<T, 64>(D, 64, nb, lane, row);
+            T x = lane < nb ? gt[c0 + lane] : T(0);
+            x = wave_forward<T, 64>(row, nb, lane, x);
+            if (lane < nb) gt[c0 + lane] = x;
+        }
+        __syncthreads();
+        panel_fwd<T>(D + 64 * 64, A.tile_rows_pad[J], NT - c0 - nb, nb, gt + c0, gt + c0 + nb);
+        __syncthreads();
+    }
+    // ---- backward: top plane
+    for (int J = A.ntiles - 1; J >= 0; --J) {
+        const int c0 = 64 * J, nb = min(64, NT - c0);
+        const T *D = F + A.tile_off[J];
+        panel_bwd<T>(D + 64 * 64, A.tile_rows_pad[J], NT - c0 - nb, nb, gt + c0 + nb, gt + c0);
+        __syncthreads();
+        if (wv == 0) {
+            T row[64];
+            wave_load_rows<T, 64>(D, 64, nb, lane, row);
+            T x = lane < nb ? gt[c0 + lane] : T(0);
+            x = wave_backward<T, 64>(row, nb, lane, x);
+            if (lane < nb) gt[c0 + lane] = x;
+        }
+        __syncthreads();
+    }
+    panel_bwd<T>(F + A.off_P, A.top_pad, NT, NS, gt, g + NL);
+    __syncthreads();
+    {
+        T row[W];
+        for (int s = wv; s < 2 * M; s += nw) {
+            wave_load_rows<T, W>(F + A.off_Lsep + (int64_t)s * W * W, W, W, lane, row);
+            T x = lane < W ? g[NL + s * W + lane] : T(0);
+            x = wave_backward<T, W>(row, W, lane, x);
+            if (lane < W) g[NL + s * W + lane] = x;
+        }
+    }
+    __syncthreads();
+    for (int i = tid; i < NL; i += nt) {
+        int s = i / (2 * M), c = i % (2 * M);
+        T v = g[i];
+        for (int r = 0; r < W; ++r) v -= B1[(int64_t)(s * 2 * M + c) * W + r] * g[NL + s * W + r];
+        int ax = inv_la_(c, M);
+        for (int r = 0; r < W; ++r) v -= B2[(int64_t)(c * 2 * M + s) * W + r] * gt[r * W + ax];
+        g[i] = v * invd[i];
+    }
+    __syncthreads();
+    // ---- interface values and interior back-substitution into the patch box
+    const bool full[3] = {true, true, true};
+    for (int idx = tid; idx < W * W * W; idx += nt) {
+        int ax = idx % W, ay = (idx / W) % W, az = idx / (W * W);
+        int ii = iface_interior(ax, ay, az, M, W, NL, NS);
+        if (ii >= 0) {
+            Uo[idx] = g[ii];
+        } else {
+            int pos[3] = {ax, ay, az};
+            Uo[idx] = C.back_interior(pos, full, [&](int a) {
+                int q[3] = {ax, ay, az};
+                q[a] = M;
+                return g[iface_interior(q[0], q[1], q[2], M, W, NL, NS)];
+            });
+        }
+    }
+}
+
+// Boundary-vertex patches: their stars lose cells, and the interface Schur complement
+// splits into independent dense slices (2 full axes: crosses of 4m+1 DOFs; 1 full axis:
+// single DOFs).  desc: vx, vy, vz, kind_x, kind_y, kind_z, nslices, slice size.
+template <typename T, int P>
+__global__ void __launch_bounds__(256) k_patch_boundary(Dims d, const int *__restrict__ desc, const int64_t *__restrict__ off,
+                                                        const T *__restrict__ factor, const T *__restrict__ mu,
+                                                        const T *__restrict__ lam, const T *__restrict__ afc,
+                                                        const T *__restrict__ rF, T *__restrict__ U) {
+    constexpr int M = P - 1, W = 2 * M + 1, MAXN = 4 * M + 1;
+    __shared__ T g[M * MAXN > M * M ? M * MAXN : M * M];
+    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
+    const int pid = blockIdx.x;
+    const int *ds = desc + 8 * pid;
+    PatchCtx<T> C{d, ds[0], ds[1], ds[2], M, P, mu, lam, afc, rF};
+    const int kind[3] = {ds[3], ds[4], ds[5]};
+    const int nslices = ds[6], ns = ds[7], n = nslices * ns;
+    const bool full[3] = {kind[0] == AX_FULL, kind[1] == AX_FULL, kind[2] == AX_FULL};
+    int fa = -1, fb = -1, hh = -1, hb = -1, hc = -1;
+    for (int a = 0; a < 3; ++a) {
+        if (full[a]) { if (fa < 0) fa = a; else fb = a; }
+        else { if (hb < 0) hb = a; else hc = a; }
+    }
+    const int nfull = full[0] + full[1] + full[2];
+    if (nfull == 2) hh = hb;
+    auto spos = [&](int a, int t) { return kind[a] == AX_LOW ? M + 1 + t : t; };
+    auto sidx = [&](int a, int pos) { return kind[a] == AX_LOW ? pos - M - 1 : pos; };
+    auto decode = [&](int idx, int pos[3]) {
+        if (nfull == 2) {
+            int t = idx / ns, c = idx % ns;
+            pos[hh] = spos(hh, t);
+            if (c < 2 * M) { pos[fa] = M; pos[fb] = inv_la_(c, M); }
+            else { pos[fb] = M; pos[fa] = c - 2 * M; }
+        } else {  // one full axis
+            int tb = idx % M, tc = idx / M;
+            pos[fa] = M; pos[hb] = spos(hb, tb); pos[hc] = spos(hc, tc);
+        }
+    };
+    auto encode = [&](const int pos[3]) -> int {
+        if (nfull == 2) {
+            int t = sidx(hh, pos[hh]);
+            int c = (pos[fa] == M && pos[fb] != M) ? la_(pos[fb], M) : 2 * M + pos[fa];
+            return t * ns + c;
+        }
+        return sidx(hb, pos[hb]) + M * sidx(hc, pos[hc]);
+    };
+    T *Uo = U + ((int64_t)(C.vz * (d.ny + 1) + C.vy) * (d.nx + 1) + C.vx) * (int64_t)(W * W * W);
+    for (int idx = tid; idx < n; idx += nt) {
+        int pos[3];
+        decode(idx, pos);
+        int ncen = 0, dd = 0;
+        for (int a = 0; a < 3; ++a)
+            if (full[a] && pos[a] == M) { ++ncen; dd = a; }
+        g[idx] = ncen == 1 ? C.condensed(pos, dd) : rF[C.gidx(pos[0], pos[1], pos[2])];
+    }
+    __syncthreads();
+    const T *F = factor + (n > 0 ? off[pid] : 0);
+    if (ns == 1) {
+        for (int t = tid; t < nslices; t += nt) g[t] *= F[t] * F[t];
+    } else if (ns > 1) {
+        T row[MAXN];
+        for (int t = wv; t < nslices; t += nw) {
+            wave_load_rows<T, MAXN>(F + (int64_t)t * ns * ns, ns, ns, lane, row);
+            T x = lane < ns ? g[t * ns + lane] : T(0);
+            x = wave_forward<T, MAXN>(row, ns, lane, x);
+            x = wave_backward<T, MAXN>(row, ns, lane, x);
+            if (lane < ns) g[t * ns + lane] = x;
+        }
+    }
+    __syncthreads();
+    int lo[3], cnt[3];
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = kind[a] == AX_LOW ? M + 1 : 0;
+        cnt[a] = kind[a] == AX_FULL ? W : M;
+    }
+    const int tot = cnt[0] * cnt[1] * cnt[2];
+    for (int idx = tid; idx < tot; idx += nt) {
+        int pos[3] = {lo[0] + idx % cnt[0], lo[1] + (idx / cnt[0]) % cnt[1], lo[2] + idx / (cnt[0] * cnt[1])};
+        int box = (pos[2] * W + pos[1]) * W + pos[0];
+        bool iface = (full[0] && pos[0] == M) || (full[1] && pos[1] == M) || (full[2] && pos[2] == M);
+        if (iface) {
+            Uo[box] = g[encode(pos)];
+        } else {
+            Uo[box] = C.back_interior(pos, full, [&](int a) {
+                int q[3] = {pos[0], pos[1], pos[2]};
+                q[a] = M;
+                return g[encode(q)];
+            });
+        }
+    }
+}
+
+// Additive Schwarz sum z_F = sum_j Rbar_j^T u_j (Sec. 2.5): each free lattice point sums
+// the boxes of the (up to 8) stars that contain it.
+template <typename T>
+__global__ void k_patch_assemble(Dims d, int interior_only, const T *__restrict__ U, T *__restrict__ zF) {
+    const int p = d.p, m = p - 1, w = 2 * m + 1;
+    const int64_t n = (int64_t)d.Lx * d.Ly * d.Lz, w3 = (int64_t)w * w * w;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n; idx += (int64_t)gridDim.x * blockDim.x) {
+        int P3[3] = {(int)(idx % d.Lx) + 1, (int)((idx / d.Lx) % d.Ly) + 1, (int)(idx / ((int64_t)d.Lx * d.Ly)) + 1};
+        int ncell[3] = {d.nx, d.ny, d.nz};
+        int v[3][2], a[3][2], nc[3];
+        for (int ax = 0; ax < 3; ++ax) {
+            int Pp = P3[ax];
+            nc[ax] = 0;
+            if (Pp % p == 0) {
+                v[ax][0] = Pp / p; a[ax][0] = m; nc[ax] = 1;
+            } else {
+                int e = Pp / p, al = Pp % p;
+                v[ax][0] = e; a[ax][0] = m + al;
+                v[ax][1] = e + 1; a[ax][1] = al - 1;
+                nc[ax] = 2;
+            }
+            if (interior_only) {
+                int k = 0;
+                for (int t = 0; t < nc[ax]; ++t)
+                    if (v[ax][t] >= 1 && v[ax][t] <= ncell[ax] - 1) { v[ax][k] = v[ax][t]; a[ax][k] = a[ax][t]; ++k; }
+                nc[ax] = k;
+            }
+        }
+        T s = 0;
+        for (int tz = 0; tz < nc[2]; ++tz)
+            for (int ty = 0; ty < nc[1]; ++ty)
+                for (int tx = 0; tx < nc[0]; ++tx) {
+                    int64_t vid = ((int64_t)v[2][tz] * (d.ny + 1) + v[1][ty]) * (d.nx + 1) + v[0][tx];
+                    s += U[vid * w3 + ((int64_t)a[2][tz] * w + a[1][ty]) * w + a[0][tx]];
+                }
+        zF[idx] = s;
+    }
+}
+
+// ====================================================================== dense / vector
+template <typename T>
+__global__ void k_dense_gemv(int n, const T *__restrict__ A, const T *__restrict__ x, T *__restrict__ y, T alpha, T beta) {
+    const int lane = threadIdx.x & 63;
+    const int row = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (row >= n) return;
+    const T *a = A + (int64_t)row * n;
+    T s = 0;
+    for (int c = lane; c < n; c += 64) s += a[c] * x[c];
+    s = wave_sum(s);
+    if (lane == 0) y[row] = beta == T(0) ? alpha * s : alpha * s + beta * y[row];
+}
+
+template <typename Tin, typename Tout>
+__global__ void k_cast(int64_t n, const Tin *__restrict__ x, Tout *__restrict__ y) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = (Tout)x[i];
+}
+
+template <typename T>
+__global__ void k_fill(int64_t n, T *__restrict__ x, T v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) x[i] = v;
+}
+
+constexpr int RED_BLOCKS = 1024;
+
+__device__ __forceinline__ double block_sum(double v) {
+    __shared__ double part[16];
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if (lane == 0) part[wv] = v;
+    __syncthreads();
+    double s = 0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < nw; ++i) s += part[i];
+    return s;
+}
+
+__global__ void k_dot_partial(int64_t n, const double *__restrict__ x, const double *__restrict__ y, double *partials) {
+    double s = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) s += x[i] * y[i];
+    s = block_sum(s);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+__global__ void k_finalize(int nb, const double *__restrict__ partials, double *scal, int mode) {
+    double s = 0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) s += partials[i];
+    s = block_sum(s);
+    if (threadIdx.x == 0) {
+        if (mode == 0) {
+            scal[SC_TMP] = s;
+        } else if (mode == 1) {  // p.q -> alpha
+            scal[SC_PQ] = s;
+            scal[SC_ALPHA] = scal[SC_RZ] / s;
+        } else if (mode == 2) {  // r.z (new) -> beta, shift
+            scal[SC_RZNEW] = s;
+            scal[SC_BETA] = s / scal[SC_RZ];
+            scal[SC_RZ] = s;
+        } else if (mode == 3) {  // r.z (initial)
+            scal[SC_RZ] = s;
+        } else if (mode == 4) {  // r.r
+            scal[SC_RR] = s;
+        }
+    }
+}
+
+__global__ void k_pcg_xr(int64_t n, double *__restrict__ x, double *__restrict__ r, const double *__restrict__ p,
+                         const double *__restrict__ q, const double *__restrict__ scal, double *partials) {
+    const double alpha = scal[SC_ALPHA];
+    double s = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        x[i] += alpha * p[i];
+        double ri = r[i] - alpha * q[i];
+        r[i] = ri;
+        s += ri * ri;
+    }
+    s = block_sum(s);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+__global__ void k_pcg_p(int64_t n, double *__restrict__ p, const double *__restrict__ z, const double *__restrict__ scal) {
+    const double beta = scal[SC_BETA];
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = z[i] + beta * p[i];
+}
+
+template <typename T>
+__global__ void k_residual(int64_t n, const double *__restrict__ r, const T *Az, T *out) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = (T)r[i] - Az[i];
+}
+
+template <typename T>
+__global__ void k_axpby_to_double(int64_t n, double a, const T *__restrict__ x, double b, double *__restrict__ y) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = b == 0.0 ? a * (double)x[i] : a * (double)x[i] + b * y[i];
+}
+
+inline unsigned grid_for(int64_t n, int block = 256) {
+    int64_t g = (n + block - 1) / block;
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, 8192));
+}
+
+}  // namespace
+
+// ====================================================================== launchers
+#define VSR_P_SWITCH(p, CALL)                                  \
+    switch (p) {                                               \
+        case 2: CALL(2); break;                                \
+        case 3: CALL(3); break;                                \
+        case 4: CALL(4); break;                                \
+        case 5: CALL(5); break;                                \
+        case 6: CALL(6); break;                                \
+        case 7: CALL(7); break;                                \
+        case 8: CALL(8); break;                                \
+        case 9: CALL(9); break;                                \
+        case 10: CALL(10); break;                              \
+        case 11: CALL(11); break;                              \
+        case 12: CALL(12); break;                              \
+        case 13: CALL(13); break;                              \
+        case 14: CALL(14); break;                              \
+        case 15: CALL(15); break;                              \
+        default: throw Error(VSR_EINVAL, "unsupported degree"); \
+    }
+
+static inline unsigned round64(int n) { return (unsigned)((n + 63) / 64 * 64); }
+
+template <typename T>
+void launch_op_kron(const Dims &d, const T *AB1d, const T *mu, const T *x, T *y, hipStream_t s) {
+    int64_t ncell = (int64_t)d.nx * d.ny * d.nz;
+#define CALL(P) hipLaunchKernelGGL((k_op_kron<T, P>), dim3((unsigned)ncell), dim3(round64((P + 1) * (P + 1))), 0, s, d, AB1d, mu, x, y)
+    VSR_P_SWITCH(d.p, CALL)
+#undef CALL
+}
+
+template <typename T>
+void launch_op_general(const Dims &d, const T *IDq, const T *Gw, const T *x, T *y, hipStream_t s) {
+    int64_t ncell = (int64_t)d.nx * d.ny * d.nz;
+#define CALL(P) hipLaunchKernelGGL((k_op_general<T, P>), dim3((unsigned)ncell), dim3(round64(QOF(P) * QOF(P))), 0, s, d, IDq, Gw, x, y)
+    VSR_P_SWITCH(d.p, CALL)
+#undef CALL
+}
+
+void launch_load_vector(const Dims &d, const double *IDq, const double *wdet, const double *f, double *b, hipStream_t s) {
+    int64_t ncell = (int64_t)d.nx * d.ny * d.nz;
+#define CALL(P) hipLaunchKernelGGL((k_load_vector<P>), dim3((unsigned)ncell), dim3(round64(QOF(P) * QOF(P))), 0, s, d, IDq, wdet, f, b)
+    VSR_P_SWITCH(d.p, CALL)
+#undef CALL
+}
+
+template <typename Tin, typename Tout>
+void launch_axis_pass(const int *rowptr, const int *col, const Tout *w, int axis, const int in_dims[3], const int out_dims[3],
+                      const Tin *in, Tout *out, Tout alpha, Tout beta, hipStream_t s) {
+    int64_t n = (int64_t)out_dims[0] * out_dims[1] * out_dims[2];
+    if (n == 0) return;
+    hipLaunchKernelGGL((k_axis_pass<Tin, Tout>), dim3(grid_for(n)), dim3(256), 0, s, rowptr, col, w, axis, in_dims[0],
+                       in_dims[1], in_dims[2], out_dims[0], out_dims[1], out_dims[2], in, out, alpha, beta);
+}
+
+template <typename T>
+void launch_patch_interior(const Dims &d, const PatchArgs &a, int npatch, const int *verts, const T *factor, const T *mu,
+                           const T *lam, const T *afc, const T *rF, T *U, hipStream_t s) {
+    if (npatch == 0) return;
+#define CALL(P) hipLaunchKernelGGL((k_patch_interior<T, P>), dim3(npatch), dim3(256), 0, s, d, a, verts, factor, mu, lam, afc, rF, U)
+    VSR_P_SWITCH(d.p, CALL)
+#undef CALL
+}
+
+template <typename T>
+void launch_patch_boundary(const Dims &d, int npatch, const int *desc, const int64_t *off, const T *factor, const T *mu,
+                           const T *lam, const T *afc, const T *rF, T *U, hipStream_t s) {
+    if (npatch == 0) return;
+#define CALL(P) hipLaunchKernelGGL((k_patch_boundary<T, P>), dim3(npatch), dim3(256), 0, s, d, desc, off, factor, mu, lam, afc, rF, U)
+    VSR_P_SWITCH(d.p, CALL)
+#undef CALL
+}
+
+template <typename T>
+void launch_patch_assemble(const Dims &d, int interior_only, const T *U, T *zF, hipStream_t s) {
+    int64_t n = (int64_t)d.Lx * d.Ly * d.Lz;
+    hipLaunchKernelGGL((k_patch_assemble<T>), dim3(grid_for(n)), dim3(256), 0, s, d, interior_only, U, zF);
+}
+
+template <typename T>
+void launch_dense_gemv(int n, const T *A, const T *x, T *y, T alpha, T beta, hipStream_t s) {
+    if (n == 0) return;
+    unsigned blocks = (unsigned)(((int64_t)n * 64 + 255) / 256);
+    hipLaunchKernelGGL((k_dense_gemv<T>), dim3(blocks), dim3(256), 0, s, n, A, x, y, alpha, beta);
+}
+
+template <typename Tin, typename Tout>
+void launch_cast(int64_t n, const Tin *x, Tout *y, hipStream_t s) {
+    hipLaunchKernelGGL((k_cast<Tin, Tout>), dim3(grid_for(n)), dim3(256), 0, s, n, x, y);
+}
+
+template <typename T>
+void launch_fill(int64_t n, T *x, T v, hipStream_t s) {
+    hipLaunchKernelGGL((k_fill<T>), dim3(grid_for(n)), dim3(256), 0, s, n, x, v);
+}
+
+int launch_dot_partial(int64_t n, const double *x, const double *y, double *partials, hipStream_t s) {
+    int nb = (int)std::min<int64_t>(RED_BLOCKS, std::max<int64_t>(1, (n + 255) / 256));
+    hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(256), 0, s, n, x, y, partials);
+    return nb;
+}
+
+void launch_finalize(int nb, const double *partials, double *scal, int mode, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, nb, partials, scal, mode);
+}
+
+int launch_pcg_xr(int64_t n, double *x, double *r, const double *p, const double *q, const double *scal, double *partials,
+                  hipStream_t s) {
+    int nb = (int)std::min<int64_t>(RED_BLOCKS, std::max<int64_t>(1, (n + 255) / 256));
+    hipLaunchKernelGGL(k_pcg_xr, dim3(nb), dim3(256), 0, s, n, x, r, p, q, scal, partials);
+    return nb;
+}
+
+void launch_pcg_p(int64_t n, double *p, const double *z, const double *scal, hipStream_t s) {
+    hipLaunchKernelGGL(k_pcg_p, dim3(grid_for(n)), dim3(256), 0, s, n, p, z, scal);
+}
+
+template <typename T>
+void launch_residual(int64_t n, const double *r, const T *Az, T *out, hipStream_t s) {
+    hipLaunchKernelGGL((k_residual<T>), dim3(grid_for(n)), dim3(256), 0, s, n, r, Az, out);
+}
+
+template <typename T>
+void launch_axpby_to_double(int64_t n, double a, const T *x, double b, double *y, hipStream_t s) {
+    hipLaunchKernelGGL((k_axpby_to_double<T>), dim3(grid_for(n)), dim3(256), 0, s, n, a, x, b, y);
+}
+
+// explicit instantiations
+#define INST(T)                                                                                                         \
+    template void launch_op_kron<T>(const Dims &, const T *, const T *, const T *, T *, hipStream_t);                   \
+    template void launch_op_general<T>(const Dims &, const T *, const T *, const T *, T *, hipStream_t);                \
+    template void launch_patch_interior<T>(const Dims &, const PatchArgs &, int, const int *, const T *, const T *,      \
+                                           const T *, const T *, const T *, T *, hipStream_t);                          \
+    template void launch_patch_boundary<T>(const Dims &, int, const int *, const int64_t *, const T *, const T *,         \
+                                           const T *, const T *, const T *, T *, hipStream_t);                          \
+    template void launch_patch_assemble<T>(const Dims &, int, const T *, T *, hipStream_t);                             \
+    template void launch_dense_gemv<T>(int, const T *, const T *, T *, T, T, hipStream_t);                              \
+    template void launch_fill<T>(int64_t, T *, T, hipStream_t);                                                         \
+    template void launch_residual<T>(int64_t, const double *, const T *, T *, hipStream_t);                             \
+    template void launch_axpby_to_double<T>(int64_t, double, const T *, double, double *, hipStream_t);
+INST(float)
+INST(double)
+template void launch_axis_pass<double, double>(const int *, const int *, const double *, int, const int *, const int *,
+                                               const double *, double *, double, double, hipStream_t);
+template void launch_axis_pass<float, float>(const int *, const int *, const float *, int, const int *, const int *,
+                                             const float *, float *, float, float, hipStream_t);
+template void launch_axis_pass<double, float>(const int *, const int *, const float *, int, const int *, const int *,
+                                              const double *, float *, float, float, hipStream_t);
+template void launch_cast<double, float>(int64_t, const double *, float *, hipStream_t);
+template void launch_cast<float, double>(int64_t, const float *, double *, hipStream_t);
+template void launch_cast<double, double>(int64_t, const double *, double *, hipStream_t);
+
+}  // namespace vsr

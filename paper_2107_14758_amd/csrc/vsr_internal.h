@@ -1,0 +1,101 @@
+// Internal declarations shared by the host setup, the kernels and the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/vsr.h"
+
+namespace vsr {
+
+// Error carrying a vsr_status across internal C++ code; the C ABI converts it.
+struct Error : std::runtime_error {
+    vsr_status status;
+    Error(vsr_status s, const std::string &msg) : std::runtime_error(msg), status(s) {}
+};
+
+#define VSR_HIP(call)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            throw ::vsr::Error(VSR_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// ------------------------------------------------------------------ 1D data (host, FP64)
+struct OneD {
+    int p = 0, q = 0;
+    std::vector<double> xi, xq, wq;   // GLL nodes (p+1), quadrature points/weights (q)
+    std::vector<double> Iq, Dq;       // q x (p+1) row-major: l_j(x_a), l_j'(x_a)
+    std::vector<double> A, B;         // (p+1)^2 row-major reference stiffness / mass
+    std::vector<double> lam;          // p-1 interior eigenvalues, ascending
+    std::vector<double> T;            // (p+1)^2 row-major: GLL coefficients of the FDM basis (columns)
+    std::vector<double> Af, Bf;       // (p+1)^2 FDM-basis matrices with structural zeros imposed
+};
+OneD make_1d(int p, int q);
+
+// ------------------------------------------------------------------ geometry (host, FP64)
+struct Geometry {
+    bool cartesian = false;
+    std::vector<double> mu;     // ncell * 3 surrogate scalings (or the Cartesian closed form)
+    std::vector<double> Gw;     // ncell * 6 * q^3 (xx, yy, zz, xy, xz, yz), w_q folded in; empty if cartesian
+    std::vector<double> wdet;   // ncell * q^3 : w_q |det DF|
+};
+Geometry make_geometry(int nx, int ny, int nz, const double *vertices, const double *kappa,
+                       const OneD &od, bool keep_metric);
+
+// ------------------------------------------------------------------ patches
+// Box coordinates of a patch run over [0, 2m] per axis (m = p-1); the star's
+// central plane is at m.  Axis kinds: FULL (interior vertex), LOW (vertex at 0:
+// valid positions m+1..2m), HIGH (vertex at N: valid positions 0..m-1).
+enum AxisKind : int { AX_FULL = 0, AX_LOW = 1, AX_HIGH = 2 };
+
+// Layout of the interior-vertex patch factor (all interior patches share it).
+struct InteriorLayout {
+    int m = 0, w = 0;           // w = 2m+1
+    int n_leaf = 0, n_sep = 0, n_top = 0, n_iface = 0;
+    int top_pad = 0;            // rows of every panel column, padded to a multiple of 4
+    int64_t off_invd = 0, off_B1 = 0, off_B2 = 0, off_Lsep = 0, off_P = 0, off_Ltop = 0;
+    int ntiles = 0;
+    std::vector<int64_t> tile_off;   // offset of tile J (diag block 64x64 then panel below)
+    std::vector<int> tile_rows_pad;  // padded row count of the panel below tile J
+    int64_t stride = 0;              // entries per patch (multiple of 64)
+};
+InteriorLayout interior_layout(int p);
+
+struct PatchSet {
+    // interior class
+    InteriorLayout L;
+    std::vector<int32_t> interior_vertices;   // 3 ints per patch (vx, vy, vz)
+    // boundary classes: per patch vx,vy,vz, kind(x,y,z), nslices, slice size, factor offset
+    std::vector<int32_t> boundary_desc;       // 8 ints per patch
+    std::vector<int64_t> boundary_off;        // factor offset per boundary patch
+    int64_t boundary_entries = 0;
+    // factors (FP64 on the host; converted to the device precision on upload)
+    std::vector<double> interior_factor;      // n_interior * L.stride
+    std::vector<double> boundary_factor;
+};
+PatchSet make_patches(int nx, int ny, int nz, const OneD &od, const double *mu, bool interior_only);
+
+// ------------------------------------------------------------------ coarse space
+// Dense inverse of the Q1 Galerkin matrix over interior vertices (row-major, nc x nc).
+std::vector<double> make_coarse_inverse(int nx, int ny, int nz, const OneD &od, const Geometry &g);
+
+// 1D lattice operators (CSR rows over output positions) for the axis passes.
+struct AxisTable {
+    int n_out = 0, n_in = 0;
+    std::vector<int32_t> rowptr, col;
+    std::vector<double> w;
+};
+AxisTable table_fdm_restrict(int ncell, const OneD &od);   // T^T
+AxisTable table_fdm_prolong(int ncell, const OneD &od);    // T
+AxisTable table_coarse_restrict(int ncell, const OneD &od);// P^T
+AxisTable table_coarse_prolong(int ncell, const OneD &od); // P
+
+// Symmetric tridiagonal extreme eigenvalues by Sturm bisection.
+void tridiag_extremes(const std::vector<double> &d, const std::vector<double> &e, double &lmin, double &lmax);
+
+}  // namespace vsr

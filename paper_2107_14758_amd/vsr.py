@@ -1,0 +1,182 @@
+"""ctypes binding of libvsr.so (C ABI in include/vsr.h): argument marshalling only.
+
+Vectors are torch float64 tensors on the GPU (contiguous); their device pointers
+are handed to the library, which does all of the computation.  The library is
+loaded from this package's directory; importing fails loudly if it is missing.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvsr.so")
+
+VSR_OK, VSR_EINVAL, VSR_EMESH, VSR_ENOTSPD, VSR_ENOCONV, VSR_EDEVICE, VSR_ENOMEM = range(7)
+STATUS_NAMES = {0: "VSR_OK", 1: "VSR_EINVAL", 2: "VSR_EMESH", 3: "VSR_ENOTSPD", 4: "VSR_ENOCONV",
+                5: "VSR_EDEVICE", 6: "VSR_ENOMEM"}
+
+
+class VsrError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class Mesh(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("vertices", ctypes.POINTER(ctypes.c_double))]
+
+
+class Coefficients(ctypes.Structure):
+    _fields_ = [("kappa", ctypes.POINTER(ctypes.c_double)), ("mu_override", ctypes.POINTER(ctypes.c_double))]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("relax_fp32", ctypes.c_int32), ("cycle", ctypes.c_int32), ("quad_points", ctypes.c_int32),
+                ("lanczos_steps", ctypes.c_int32), ("max_iterations", ctypes.c_int32),
+                ("interior_patches_only", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("omega", ctypes.c_double), ("stream", ctypes.c_void_p)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("rel_residual", ctypes.c_double), ("true_rel_residual", ctypes.c_double),
+                ("omega", ctypes.c_double), ("lambda_min", ctypes.c_double), ("lambda_max", ctypes.c_double),
+                ("setup_seconds", ctypes.c_double), ("solve_seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """Load libvsr.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing; build it with python -m paper_2107_14758_amd.build")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    dp = ctypes.c_void_p
+    L.vsr_default_options.argtypes = [ctypes.POINTER(Options)]
+    L.vsr_default_options.restype = None
+    L.vsr_setup.argtypes = [ctypes.POINTER(Mesh), ctypes.c_int32, ctypes.POINTER(Coefficients),
+                            ctypes.POINTER(Options), ctypes.POINTER(P)]
+    L.vsr_num_dofs.argtypes = [P]
+    L.vsr_num_dofs.restype = ctypes.c_int64
+    L.vsr_load_vector.argtypes = [P, dp, dp]
+    L.vsr_apply_operator.argtypes = [P, dp, dp]
+    L.vsr_apply_relaxation.argtypes = [P, dp, dp, ctypes.c_int32]
+    L.vsr_pcg_solve.argtypes = [P, dp, dp, ctypes.c_double, ctypes.POINTER(SolveInfo)]
+    L.vsr_get_damping.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(ctypes.c_double)]
+    L.vsr_set_profiling.argtypes = [P, ctypes.c_int32]
+    L.vsr_kernel_stats.argtypes = [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
+                                   ctypes.POINTER(ctypes.c_double)]
+    L.vsr_factor_info.argtypes = [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+    L.vsr_destroy.argtypes = [P]
+    L.vsr_destroy.restype = None
+    L.vsr_last_error.argtypes = []
+    L.vsr_last_error.restype = ctypes.c_char_p
+    for name in ("vsr_setup", "vsr_load_vector", "vsr_apply_operator", "vsr_apply_relaxation", "vsr_pcg_solve",
+                 "vsr_get_damping", "vsr_set_profiling", "vsr_kernel_stats", "vsr_factor_info"):
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(status):
+    if status != VSR_OK:
+        raise VsrError(status, lib().vsr_last_error().decode())
+
+
+def _ptr(t):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise TypeError("vectors must be contiguous float64 CUDA tensors")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Problem:
+    """One discretized Poisson problem and its preconditioner, resident on the GPU."""
+
+    def __init__(self, vertices, p, kappa=None, mu_override=None, relax_fp32=False, cycle=0, lanczos_steps=20,
+                 max_iterations=1000, interior_patches_only=False, seed=0, omega=0.0, stream=None):
+        L = lib()
+        V = np.ascontiguousarray(vertices, dtype=np.float64)
+        nz, ny, nx = V.shape[0] - 1, V.shape[1] - 1, V.shape[2] - 1
+        self._V = V
+        mesh = Mesh(nx, ny, nz, V.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        self._kappa = None if kappa is None else np.ascontiguousarray(kappa, dtype=np.float64).reshape(-1)
+        self._mu = None if mu_override is None else np.ascontiguousarray(mu_override, dtype=np.float64).reshape(-1)
+        coef = Coefficients(
+            None if self._kappa is None else self._kappa.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+            None if self._mu is None else self._mu.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        opt = Options()
+        L.vsr_default_options(ctypes.byref(opt))
+        opt.relax_fp32 = int(bool(relax_fp32))
+        opt.cycle = int(cycle)
+        opt.lanczos_steps = int(lanczos_steps)
+        opt.max_iterations = int(max_iterations)
+        opt.interior_patches_only = int(bool(interior_patches_only))
+        opt.seed = int(seed)
+        opt.omega = float(omega)
+        opt.stream = None if stream is None else ctypes.c_void_p(stream)
+        h = ctypes.c_void_p()
+        _check(L.vsr_setup(ctypes.byref(mesh), int(p), ctypes.byref(coef), ctypes.byref(opt), ctypes.byref(h)))
+        self._h = h
+        self.p = p
+        self.shape = (nx, ny, nz)
+        self.n = int(L.vsr_num_dofs(h))
+        self.q = (3 * (p + 1) + 1) // 2
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().vsr_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def load_vector(self, f, b):
+        _check(lib().vsr_load_vector(self._h, _ptr(f), _ptr(b)))
+
+    def apply_operator(self, x, y):
+        _check(lib().vsr_apply_operator(self._h, _ptr(x), _ptr(y)))
+
+    def apply_relaxation(self, r, z, mode=0):
+        _check(lib().vsr_apply_relaxation(self._h, _ptr(r), _ptr(z), int(mode)))
+
+    def pcg_solve(self, b, x, rtol=1e-8, raise_on_noconv=True):
+        info = SolveInfo()
+        st = lib().vsr_pcg_solve(self._h, _ptr(b), _ptr(x), float(rtol), ctypes.byref(info))
+        if st != VSR_OK and (raise_on_noconv or st != VSR_ENOCONV):
+            _check(st)
+        out = info.as_dict()
+        out["status"] = st
+        return out
+
+    def damping(self):
+        w, a, b = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _check(lib().vsr_get_damping(self._h, ctypes.byref(w), ctypes.byref(a), ctypes.byref(b)))
+        return w.value, a.value, b.value
+
+    def set_profiling(self, enable=True):
+        _check(lib().vsr_set_profiling(self._h, int(bool(enable))))
+
+    def kernel_stats(self):
+        n, ms, by = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+        _check(lib().vsr_kernel_stats(self._h, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)))
+        return n.value, ms.value, by.value
+
+    def factor_info(self):
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().vsr_factor_info(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value

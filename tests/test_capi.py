@@ -1,0 +1,45 @@
+"""CPU checks of the C ABI library: it loads and exports every entry point the header declares."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "vsr.h")
+LIB = os.path.join(ROOT, "paper_2107_14758_amd", "libvsr.so")
+
+
+def declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(vsr_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared()
+    for n in ("vsr_setup", "vsr_apply_operator", "vsr_apply_relaxation", "vsr_pcg_solve", "vsr_destroy",
+              "vsr_load_vector", "vsr_num_dofs", "vsr_last_error"):
+        assert n in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libvsr.so not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libvsr.so not built")
+def test_error_text_and_defaults_without_gpu_work():
+    from paper_2107_14758_amd import vsr
+    L = vsr.lib()
+    opt = vsr.Options()
+    L.vsr_default_options(ctypes.byref(opt))
+    assert opt.lanczos_steps == 20 and opt.max_iterations == 1000 and opt.relax_fp32 == 0
+    # argument validation happens before any device call
+    h = ctypes.c_void_p()
+    mesh = vsr.Mesh(2, 2, 2, None)
+    st = L.vsr_setup(ctypes.byref(mesh), 3, None, None, ctypes.byref(h))
+    assert st == vsr.VSR_EINVAL and b"NULL" in L.vsr_last_error()
+    assert L.vsr_num_dofs(None) == -1

@@ -1,0 +1,214 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle.
+
+Sizes span several cells, tiles and patch classes, with ragged (non-cubic)
+meshes.  FP64 results must match to 1e-12 (single applies) / 1e-10 (solves);
+FP32-relaxation results to the bounds stated in each test.
+"""
+import numpy as np
+import pytest
+
+from oracle import transfer
+from oracle.fdm1d import setup_1d
+from oracle.operator import Discretization
+from oracle.solver import Solver
+from paper_2107_14758_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def dev(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def mesh(shape, p, seed=0, jitter=0.0, lognormal=False):
+    nx, ny, nz = shape
+    rng = np.random.default_rng(seed)
+    V = inputs.cube_vertices(nx, ny, nz)
+    if jitter:
+        V = inputs.jitter_vertices(V, jitter, rng)
+    kappa = inputs.lognormal_kappa(nx, ny, nz, rng) if lognormal else None
+    q = inputs.quadrature_points_per_dir(p)
+    f = inputs.rhs_samples(nx * ny * nz, q ** 3, rng)
+    return V, kappa, f
+
+
+CASES = [
+    ("cart_2x2x2_p3", (2, 2, 2), 3, 0.0, False),
+    ("cart_3x2x4_p4", (3, 2, 4), 4, 0.0, False),
+    ("jit_3x3x2_p3_kappa", (3, 3, 2), 3, 0.15, True),
+    ("jit_2x3x3_p5_kappa", (2, 3, 3), 5, 0.15, True),
+    ("jit_2x2x2_p7", (2, 2, 2), 7, 0.2, False),
+]
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def vsr():
+    from paper_2107_14758_amd import vsr as v
+    v.lib()
+    return v
+
+
+@pytest.mark.parametrize("name,shape,p,jit,logn", CASES)
+def test_operator_and_load_vector(vsr, name, shape, p, jit, logn):
+    say("case", name)
+    V, kappa, f = mesh(shape, p, seed=1, jitter=jit, lognormal=logn)
+    d = Discretization(V, p, kappa)
+    prob = vsr.Problem(V, p, kappa=kappa, omega=1.0)
+    assert prob.n == d.n
+    x = np.random.default_rng(2).uniform(-1, 1, d.n)
+    y = torch.zeros(d.n, dtype=torch.float64, device="cuda")
+    prob.apply_operator(dev(x), y)
+    assert rel(host(y), d.apply(x)) < 1e-12
+    b = torch.zeros_like(y)
+    prob.load_vector(dev(f), b)
+    assert rel(host(b), d.load_vector(f)) < 1e-12
+
+
+@pytest.mark.parametrize("name,shape,p,jit,logn", CASES)
+def test_relaxation_modes(vsr, name, shape, p, jit, logn):
+    say("case", name)
+    V, kappa, f = mesh(shape, p, seed=3, jitter=jit, lognormal=logn)
+    d = Discretization(V, p, kappa)
+    od = setup_1d(p)
+    s = Solver(d, od, omega=0.37)
+    prob = vsr.Problem(V, p, kappa=kappa, omega=0.37)
+    r = np.random.default_rng(4).uniform(-1, 1, d.n)
+    z = torch.zeros(d.n, dtype=torch.float64, device="cuda")
+    prob.apply_relaxation(dev(r), z, 1)
+    assert rel(host(z), s.relax(r)) < 1e-11
+    prob.apply_relaxation(dev(r), z, 2)
+    assert rel(host(z), s.coarse(r)) < 1e-11
+    prob.apply_relaxation(dev(r), z, 0)
+    assert rel(host(z), s.precondition(r)) < 1e-11
+
+
+def test_interior_only_relaxation_and_exact_single_patch(vsr):
+    say("case interior-only")
+    V, kappa, f = mesh((3, 2, 3), 4, seed=5, jitter=0.1)
+    d = Discretization(V, 4)
+    s = Solver(d, setup_1d(4), omega=0.5, interior_only=True)
+    prob = vsr.Problem(V, 4, omega=0.5, interior_patches_only=True)
+    r = np.random.default_rng(6).uniform(-1, 1, d.n)
+    z = torch.zeros(d.n, dtype=torch.float64, device="cuda")
+    prob.apply_relaxation(dev(r), z, 1)
+    assert rel(host(z), s.relax(r)) < 1e-11
+    # one patch holding every DOF on a Cartesian 2^3 mesh: exact solve, one PCG iteration
+    V, _, f = mesh((2, 2, 2), 3, seed=0)
+    d = Discretization(V, 3)
+    prob = vsr.Problem(V, 3, interior_patches_only=True)
+    w, lmin, lmax = prob.damping()
+    assert abs(w - 1) < 1e-12 and abs(lmin - 1) < 1e-12 and abs(lmax - 1) < 1e-12
+    b = d.load_vector(f)
+    x = torch.zeros(d.n, dtype=torch.float64, device="cuda")
+    info = prob.pcg_solve(dev(b), x)
+    assert info["iterations"] == 1
+    xd = np.linalg.solve(d.assemble().toarray(), b)
+    assert rel(host(x), xd) < 1e-12
+
+
+@pytest.mark.parametrize("name,shape,p,jit,logn", CASES[:4])
+def test_damping_and_pcg_fp64(vsr, name, shape, p, jit, logn):
+    say("case", name)
+    V, kappa, f = mesh(shape, p, seed=7, jitter=jit, lognormal=logn)
+    d = Discretization(V, p, kappa)
+    s = Solver(d, setup_1d(p), seed=11)
+    prob = vsr.Problem(V, p, kappa=kappa, seed=11)
+    w, lmin, lmax = prob.damping()
+    assert abs(lmin - s.lanczos[0]) < 1e-9 * s.lanczos[1]
+    assert abs(lmax - s.lanczos[1]) < 1e-9 * s.lanczos[1]
+    assert abs(w - s.omega) < 1e-9 * s.omega
+    b = d.load_vector(f)
+    x_o, it_o = s.pcg(b)
+    x = torch.zeros(d.n, dtype=torch.float64, device="cuda")
+    info = prob.pcg_solve(dev(b), x)
+    assert info["converged"] == 1 and info["iterations"] == it_o
+    assert info["true_rel_residual"] <= 1.0001e-8
+    assert rel(host(x), x_o) < 1e-10
+
+
+@pytest.mark.parametrize("name,shape,p,jit,logn", CASES[1:])
+def test_fp32_relaxation(vsr, name, shape, p, jit, logn):
+    # FP32 relaxation, coarse correction and inner operator applies under FP64 PCG:
+    # preconditioner error vs FP64 <= 1e-5 relative; solve still reaches the FP64 true
+    # residual 1e-8 with at most 2 extra iterations and x within 1e-6 of the FP64 oracle.
+    say("case", name)
+    V, kappa, f = mesh(shape, p, seed=8, jitter=jit, lognormal=logn)
+    d = Discretization(V, p, kappa)
+    s = Solver(d, setup_1d(p), seed=3)
+    prob = vsr.Problem(V, p, kappa=kappa, seed=3, relax_fp32=True)
+    r = np.random.default_rng(9).uniform(-1, 1, d.n)
+    z = torch.zeros(d.n, dtype=torch.float64, device="cuda")
+    prob.apply_relaxation(dev(r), z, 1)
+    assert rel(host(z), s.relax(r)) < 1e-5
+    b = d.load_vector(f)
+    x_o, it_o = s.pcg(b)
+    x = torch.zeros(d.n, dtype=torch.float64, device="cuda")
+    info = prob.pcg_solve(dev(b), x)
+    assert info["converged"] == 1 and info["iterations"] <= it_o + 2
+    assert info["true_rel_residual"] <= 1.0001e-8
+    assert rel(host(x), x_o) < 1e-6
+
+
+def test_additive_cycle(vsr):
+    say("case additive")
+    V, kappa, f = mesh((3, 2, 2), 4, seed=12, jitter=0.1)
+    d = Discretization(V, 4)
+    s = Solver(d, setup_1d(4), omega=1.0, cycle="additive")
+    prob = vsr.Problem(V, 4, omega=1.0, cycle=1)
+    r = np.random.default_rng(13).uniform(-1, 1, d.n)
+    z = torch.zeros(d.n, dtype=torch.float64, device="cuda")
+    prob.apply_relaxation(dev(r), z, 0)
+    assert rel(host(z), s.precondition(r)) < 1e-11
+
+
+def test_error_paths(vsr):
+    say("case errors")
+    V, _, f = mesh((2, 2, 2), 3)
+    with pytest.raises(vsr.VsrError) as e:
+        vsr.Problem(V, 1)
+    assert e.value.status == vsr.VSR_EINVAL
+    with pytest.raises(vsr.VsrError) as e:
+        vsr.Problem(inputs.cube_vertices(1, 2, 2), 3)
+    assert e.value.status == vsr.VSR_EINVAL
+    bad = V.copy()
+    bad[1, 1, 1] = [1.5, 1.5, 1.5]          # inverts the cell beyond the centre vertex
+    with pytest.raises(vsr.VsrError) as e:
+        vsr.Problem(bad, 3)
+    assert e.value.status == vsr.VSR_EMESH
+    with pytest.raises(vsr.VsrError) as e:
+        vsr.Problem(V, 3, kappa=-np.ones(8))
+    assert e.value.status == vsr.VSR_ENOTSPD
+    nan = V.copy()
+    nan[0, 0, 0, 0] = np.nan
+    with pytest.raises(vsr.VsrError) as e:
+        vsr.Problem(nan, 3)
+    assert e.value.status == vsr.VSR_EINVAL
+    prob = vsr.Problem(V, 3, max_iterations=2)
+    d = Discretization(V, 3)
+    b = dev(d.load_vector(f))
+    x = torch.zeros_like(b)
+    info = prob.pcg_solve(b, x, rtol=1e-30, raise_on_noconv=False)
+    assert info["status"] == vsr.VSR_ENOCONV and info["iterations"] == 2
+    bn = b.clone()
+    bn[3] = float("nan")
+    with pytest.raises(vsr.VsrError) as e:
+        prob.pcg_solve(bn, x)
+    assert e.value.status == vsr.VSR_EINVAL
+    zero = torch.zeros_like(b)
+    info = prob.pcg_solve(zero, x)
+    assert info["iterations"] == 0 and float(x.abs().max()) == 0.0
