@@ -83,7 +83,8 @@ struct vsr_problem {
     double setup_seconds = 0.0;
     // profiling of the interior patch-solve launches
     bool profiling = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> events;   // reusable pool
+    size_t events_used = 0;
 
     ~vsr_problem() {
         for (auto &e : events) {
@@ -147,15 +148,20 @@ void relax_apply(vsr_problem *P, const Tin *in, T *out, T alpha, T beta) {
     launch_axis_pass<T, T>(TT[2].rowptr, TT[2].col, wt<T>(TT[2]), 2, L, L, t2, rF, T(1), T(0), P->stream);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (P->profiling) {
-        VSR_HIP(hipEventCreate(&e0));
-        VSR_HIP(hipEventCreate(&e1));
+        if (P->events_used == P->events.size()) {
+            VSR_HIP(hipEventCreate(&e0));
+            VSR_HIP(hipEventCreate(&e1));
+            P->events.push_back({e0, e1});
+        }
+        e0 = P->events[P->events_used].first;
+        e1 = P->events[P->events_used].second;
         VSR_HIP(hipEventRecord(e0, P->stream));
     }
     launch_patch_interior<T>(P->d, P->pa, P->n_int, P->verts, (const T *)P->fint, (const T *)P->mu_sur, (const T *)P->lam,
                              (const T *)P->afc, rF, U, P->stream);
     if (P->profiling) {
         VSR_HIP(hipEventRecord(e1, P->stream));
-        P->events.push_back({e0, e1});
+        ++P->events_used;
     }
     launch_patch_boundary<T>(P->d, P->n_bnd, P->bdesc, P->boff, (const T *)P->fbnd, (const T *)P->mu_sur, (const T *)P->lam,
                              (const T *)P->afc, rF, U, P->stream);
@@ -385,16 +391,11 @@ vsr_status vsr_setup(const vsr_mesh *mesh, int32_t p, const vsr_coefficients *co
         P->bdesc = P->upload(S.boundary_desc);
         P->boff = P->upload(S.boundary_off);
         const InteriorLayout &L = S.L;
-        if (L.ntiles > 32) throw Error(VSR_EINVAL, "too many factor tiles");
         PatchArgs &a = P->pa;
         a.m = L.m; a.w = L.w; a.n_leaf = L.n_leaf; a.n_sep = L.n_sep; a.n_top = L.n_top; a.n_iface = L.n_iface;
         a.top_pad = L.top_pad; a.ntiles = L.ntiles;
         a.off_invd = L.off_invd; a.off_B1 = L.off_B1; a.off_B2 = L.off_B2; a.off_Lsep = L.off_Lsep; a.off_P = L.off_P;
         a.off_Ltop = L.off_Ltop; a.stride = L.stride;
-        for (int J = 0; J < L.ntiles; ++J) {
-            a.tile_off[J] = L.tile_off[J];
-            a.tile_rows_pad[J] = L.tile_rows_pad[J];
-        }
         int m = L.m, w = L.w;
         int64_t per_patch = (int64_t)L.n_leaf + 2LL * 4 * m * m * w + 2LL * m * w * (w + 1) / 2 +
                             2LL * m * w * L.n_top + (int64_t)L.n_top * (L.n_top + 1) / 2;
@@ -572,17 +573,15 @@ vsr_status vsr_kernel_stats(vsr_problem *P, int64_t *launches, double *total_ms,
         if (!P) throw Error(VSR_EINVAL, "NULL argument");
         VSR_HIP(hipStreamSynchronize(P->stream));
         double tot = 0;
-        for (auto &e : P->events) {
+        for (size_t i = 0; i < P->events_used; ++i) {
             float ms = 0;
-            VSR_HIP(hipEventElapsedTime(&ms, e.first, e.second));
+            VSR_HIP(hipEventElapsedTime(&ms, P->events[i].first, P->events[i].second));
             tot += ms;
-            (void)hipEventDestroy(e.first);
-            (void)hipEventDestroy(e.second);
         }
-        if (launches) *launches = (int64_t)P->events.size();
+        if (launches) *launches = (int64_t)P->events_used;
         if (total_ms) *total_ms = tot;
         if (bytes_per_launch) *bytes_per_launch = P->bytes_patch_launch;
-        P->events.clear();
+        P->events_used = 0;
     });
 }
 

@@ -32,8 +32,6 @@ struct PatchArgs {
     int m, w;
     int n_leaf, n_sep, n_top, n_iface, top_pad, ntiles;
     int64_t off_invd, off_B1, off_B2, off_Lsep, off_P, off_Ltop, stride;
-    int64_t tile_off[32];
-    int tile_rows_pad[32];
 };
 
 template <typename T>

@@ -290,90 +290,137 @@ __device__ __forceinline__ int iface_interior(int ax, int ay, int az, int m, int
     return -1;
 }
 
-template <typename T>
+// Per-patch coefficients staged in LDS: the star's cell scalings mu[cz][cy][cx][3]
+// (zero for absent cells), the interior eigenvalues lambda_1..m and the couplings
+// A_F[t, vertex] of interior mode t to the vertex on the star's central plane
+// (afc[0][.] for the cell below the plane, afc[1][.] above).
+template <typename T, int M>
 struct PatchCtx {
     Dims d;
-    int vx, vy, vz, m, p;
-    const T *mu, *lam, *afc, *rF;
+    int vx, vy, vz;
+    const T *rF;
+    const T *mu, *lam, *afc;   // LDS
     __device__ int64_t gidx(int ax, int ay, int az) const {
-        return ((int64_t)(p * (vz - 1) + az) * d.Ly + (p * (vy - 1) + ay)) * d.Lx + (p * (vx - 1) + ax);
+        return ((int64_t)(P_() * (vz - 1) + az) * d.Ly + (P_() * (vy - 1) + ay)) * d.Lx + (P_() * (vx - 1) + ax);
     }
-    __device__ const T *cell_mu(int cx, int cy, int cz) const {
-        int ex = vx - 1 + cx, ey = vy - 1 + cy, ez = vz - 1 + cz;
-        return mu + 3 * ((int64_t)ex + d.nx * ((int64_t)ey + d.ny * (int64_t)ez));
-    }
+    __device__ static constexpr int P_() { return M + 1; }
+    __device__ const T *cmu(const int c[3]) const { return mu + 3 * ((c[2] * 2 + c[1]) * 2 + c[0]); }
     // r_F at a face DOF minus the condensed interior lines of its two cells along axis dd:
     // g = r_G - A_GI A_II^{-1} r_I (Sec. 2.6), A_II = mu . lambda, A_GI = mu_dd A_F[interior, vertex].
     __device__ T condensed(const int pos[3], int dd) const {
         T g = rF[gidx(pos[0], pos[1], pos[2])];
         int c[3], l[3];
         for (int a = 0; a < 3; ++a) {
-            c[a] = pos[a] > m;
-            l[a] = c[a] ? pos[a] - m : pos[a] + 1;
+            c[a] = pos[a] > M;
+            l[a] = c[a] ? pos[a] - M : pos[a] + 1;
         }
         T acc = 0;
+#pragma unroll
         for (int cd = 0; cd < 2; ++cd) {
             c[dd] = cd;
-            const T *mk = cell_mu(c[0], c[1], c[2]);
+            const T *mk = cmu(c);
             T base = 0;
             for (int a = 0; a < 3; ++a)
                 if (a != dd) base += mk[a] * lam[l[a] - 1];
+            const T mdd = mk[dd];
             int q[3] = {pos[0], pos[1], pos[2]};
-            for (int t = 1; t <= m; ++t) {
-                q[dd] = cd == 0 ? t - 1 : m + t;
-                T D = base + mk[dd] * lam[t - 1];
-                acc += mk[dd] * afc[cd * m + t - 1] * rF[gidx(q[0], q[1], q[2])] / D;
+            T rv[M];
+#pragma unroll
+            for (int t = 1; t <= M; ++t) {
+                q[dd] = cd == 0 ? t - 1 : M + t;
+                rv[t - 1] = rF[gidx(q[0], q[1], q[2])];
             }
+#pragma unroll
+            for (int t = 1; t <= M; ++t) acc += mdd * afc[cd * M + t - 1] * rv[t - 1] / (base + mdd * lam[t - 1]);
         }
         return g - acc;
     }
-    // u_I = A_II^{-1}(r_I - A_IG u_G) at an interior DOF; face(dd) gives the interface value
+    // u_I = A_II^{-1}(r_I - A_IG u_G) at an interior DOF; face(a) gives the interface value
     template <typename F>
     __device__ T back_interior(const int pos[3], const bool full[3], F face) const {
         int c[3], l[3];
         for (int a = 0; a < 3; ++a) {
-            c[a] = pos[a] > m;
-            l[a] = c[a] ? pos[a] - m : pos[a] + 1;
+            c[a] = pos[a] > M;
+            l[a] = c[a] ? pos[a] - M : pos[a] + 1;
         }
-        const T *mk = cell_mu(c[0], c[1], c[2]);
+        const T *mk = cmu(c);
         T D = mk[0] * lam[l[0] - 1] + mk[1] * lam[l[1] - 1] + mk[2] * lam[l[2] - 1];
         T u = rF[gidx(pos[0], pos[1], pos[2])];
         for (int a = 0; a < 3; ++a)
-            if (full[a]) u -= mk[a] * afc[c[a] * m + l[a] - 1] * face(a);
+            if (full[a]) u -= mk[a] * afc[c[a] * M + l[a] - 1] * face(a);
         return u / D;
     }
 };
 
-// Dense lower-triangular solves by one wavefront (n <= MAXW <= 64).  Lane i holds row i
-// of L (column-major storage, inverse diagonal) in registers; forward substitution
-// broadcasts each solved value, the transposed solve reduces across lanes.
+template <typename T, int M>
+__device__ void stage_coefficients(const Dims &d, int vx, int vy, int vz, const int kind[3], const T *__restrict__ mu,
+                                   const T *__restrict__ lam, const T *__restrict__ afc, T *smu, T *slam, T *safc) {
+    const int tid = threadIdx.x;
+    if (tid < 24) {
+        int comp = tid % 3, cell = tid / 3, cx = cell & 1, cy = (cell >> 1) & 1, cz = cell >> 2;
+        int cc[3] = {cx, cy, cz};
+        bool ok = true;
+        for (int a = 0; a < 3; ++a)
+            if (kind[a] == AX_LOW ? cc[a] == 0 : (kind[a] == AX_HIGH ? cc[a] == 1 : false)) ok = false;
+        int ex = vx - 1 + cx, ey = vy - 1 + cy, ez = vz - 1 + cz;
+        smu[tid] = ok ? mu[3 * ((int64_t)ex + d.nx * ((int64_t)ey + d.ny * (int64_t)ez)) + comp] : T(0);
+    }
+    for (int t = tid; t < M; t += blockDim.x) slam[t] = lam[t];
+    for (int t = tid; t < 2 * M; t += blockDim.x) safc[t] = afc[t];
+}
+
+// Value of lane `l` (uniform) broadcast to the wavefront through the scalar unit.
+template <typename T>
+__device__ __forceinline__ T bcast(T v, int l);
+template <>
+__device__ __forceinline__ float bcast<float>(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+template <>
+__device__ __forceinline__ double bcast<double>(double v, int l) {
+    int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+
+// Dense lower-triangular solves by one wavefront (n <= MAXW <= 64), column-major L with
+// inverse diagonal.  Forward: lane i holds row i of L; each solved value is broadcast
+// and eliminated from the rows below.  Backward (L^T u = y): lane i holds column i of L
+// and the solved u_k is eliminated from the rows above.
 template <typename T, int MAXW>
 __device__ __forceinline__ void wave_load_rows(const T *__restrict__ L, int ld, int n, int lane, T (&row)[MAXW]) {
 #pragma unroll
     for (int k = 0; k < MAXW; ++k) row[k] = (k < n && lane < n) ? L[(int64_t)k * ld + lane] : T(0);
 }
+template <typename T, int MAXW>
+__device__ __forceinline__ void wave_load_cols(const T *__restrict__ L, int ld, int n, int lane, T (&col)[MAXW]) {
+#pragma unroll
+    for (int k = 0; k < MAXW; ++k) col[k] = (k < n && lane < n) ? L[(int64_t)lane * ld + k] : T(0);
+}
 
+// Both solves rely on the stored upper triangle being zero, so the update is branch-free:
+// lane k takes the solved value, the other lanes subtract their (possibly zero) coefficient.
 template <typename T, int MAXW>
 __device__ __forceinline__ T wave_forward(const T (&row)[MAXW], int n, int lane, T x) {
 #pragma unroll
     for (int k = 0; k < MAXW; ++k) {
         if (k < n) {
-            if (lane == k) x *= row[k];
-            T yk = __shfl(x, k, 64);
-            if (lane > k) x -= row[k] * yk;
+            const T dk = bcast(row[k], k);
+            const T yk = bcast(x, k) * dk;
+            x = lane == k ? yk : x - row[k] * yk;
         }
     }
     return x;
 }
 
 template <typename T, int MAXW>
-__device__ __forceinline__ T wave_backward(const T (&row)[MAXW], int n, int lane, T x) {
+__device__ __forceinline__ T wave_backward(const T (&col)[MAXW], int n, int lane, T x) {
 #pragma unroll
     for (int k = MAXW - 1; k >= 0; --k) {
         if (k < n) {
-            T part = (lane > k && lane < n) ? row[k] * x : T(0);
-            T s = wave_sum(part);
-            if (lane == k) x = (x - s) * row[k];
+            const T dk = bcast(col[k], k);
+            const T uk = bcast(x, k) * dk;
+            x = lane == k ? uk : x - col[k] * uk;
         }
     }
     return x;
@@ -398,26 +445,35 @@ __device__ __forceinline__ Vec4<double> load4<double>(const double *p) {
 }
 
 // y[r] -= sum_c M[c * ld + r] x[c] for r < nrows (ld multiple of 4, M 16-byte aligned);
-// x, y in LDS.  Work split over (row quads) x (column chunks), accumulated with LDS atomics.
-template <typename T>
+// x, y in LDS.  Work split over (row quads) x (column chunks), accumulated with LDS atomics;
+// each thread keeps U column loads in flight.
+template <typename T, int U = 8>
 __device__ void panel_fwd(const T *__restrict__ M, int ld, int nrows, int ncols, const T *x, T *y) {
     const int tid = threadIdx.x, nt = blockDim.x;
     const int nq = (nrows + 3) / 4;
     if (nq == 0 || ncols == 0) return;
-    int nch = max(1, min(ncols, nt / nq));
+    int nch = max(1, min((ncols + U - 1) / U, nt / nq));
     int chunk = (ncols + nch - 1) / nch;
     for (int task = tid; task < nq * nch; task += nt) {
         int rq = task % nq, ch = task / nq;
         int c0 = ch * chunk, c1 = min(ncols, c0 + chunk);
         T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-        const T *col = M + (int64_t)c0 * ld + 4 * rq;
-        for (int c = c0; c < c1; ++c, col += ld) {
-            Vec4<T> v = load4(col);
-            T xc = x[c];
-            a0 += v.v[0] * xc;
-            a1 += v.v[1] * xc;
-            a2 += v.v[2] * xc;
-            a3 += v.v[3] * xc;
+        const T *base = M + 4 * rq;
+        for (int c = c0; c < c1; c += U) {
+            Vec4<T> v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (c + u < c1) v[u] = load4(base + (int64_t)(c + u) * ld);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (c + u < c1) {
+                    T xc = x[c + u];
+                    a0 += v[u].v[0] * xc;
+                    a1 += v[u].v[1] * xc;
+                    a2 += v[u].v[2] * xc;
+                    a3 += v[u].v[3] * xc;
+                }
+            }
         }
         int r = 4 * rq;
         if (nch == 1) {
@@ -434,23 +490,50 @@ __device__ void panel_fwd(const T *__restrict__ M, int ld, int nrows, int ncols,
     }
 }
 
-// y[c] -= sum_r M[c * ld + r] x[r] for c < ncols (one wavefront per column).
-template <typename T>
+// y[c] -= sum_r M[c * ld + r] x[r] for c < ncols: a thread streams one (column, row chunk)
+// with U loads in flight; chunks of one column meet in an LDS atomic.
+template <typename T, int U = 8>
 __device__ void panel_bwd(const T *__restrict__ M, int ld, int nrows, int ncols, const T *x, T *y) {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    for (int c = wv; c < ncols; c += nw) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int nq = (nrows + 3) / 4;
+    if (nq == 0 || ncols == 0) return;
+    int nrc = max(1, min((nq + U - 1) / U, nt / ncols));
+    int chunk = (nq + nrc - 1) / nrc;
+    for (int task = tid; task < ncols * nrc; task += nt) {
+        int c = task % ncols, rc = task / ncols;
+        int q0 = rc * chunk, q1 = min(nq, q0 + chunk);
         const T *col = M + (int64_t)c * ld;
         T s = 0;
-        for (int r = 4 * lane; r < nrows; r += 256) {
-            Vec4<T> v = load4(col + r);
-            s += v.v[0] * x[r];
-            if (r + 1 < nrows) s += v.v[1] * x[r + 1];
-            if (r + 2 < nrows) s += v.v[2] * x[r + 2];
-            if (r + 3 < nrows) s += v.v[3] * x[r + 3];
+        for (int q = q0; q < q1; q += U) {
+            Vec4<T> v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (q + u < q1) v[u] = load4(col + 4 * (q + u));
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (q + u < q1) {
+                    int r = 4 * (q + u);
+                    s += v[u].v[0] * x[r];
+                    if (r + 1 < nrows) s += v[u].v[1] * x[r + 1];
+                    if (r + 2 < nrows) s += v[u].v[2] * x[r + 2];
+                    if (r + 3 < nrows) s += v[u].v[3] * x[r + 3];
+                }
+            }
         }
-        s = wave_sum(s);
-        if (lane == 0) y[c] -= s;
+        if (nrc == 1) y[c] -= s;
+        else atomicAdd(&y[c], -s);
     }
+}
+
+// Offset of top-plane tile J inside one interior-patch factor (diagonal 64x64 block, then
+// the panel of rows below it padded to a multiple of 4).
+__device__ __forceinline__ int64_t tile_offset(int64_t off_Ltop, int NT, int J) {
+    int64_t o = off_Ltop;
+    for (int j = 0; j < J; ++j) {
+        int rows = NT - 64 * j - min(64, NT - 64 * j);
+        o += 64 * 64 + (int64_t)64 * ((rows + 3) / 4 * 4);
+    }
+    return o;
 }
 
 // Interior-vertex patch solve, one workgroup per patch (Sec. 2.6): condensation of the
@@ -458,17 +541,24 @@ __device__ void panel_bwd(const T *__restrict__ M, int ld, int nrows, int ncols,
 // Schur complement (leaves, level-1 separator slices, dense top plane), forward and
 // backward, then interior back-substitution.  Output: the patch box of (2m+1)^3 values.
 template <typename T, int P>
-__global__ void __launch_bounds__(256) k_patch_interior(Dims d, PatchArgs A, const int *__restrict__ verts,
+__global__ void __launch_bounds__(256, (sizeof(T) == 4 ? 4 : 3)) k_patch_interior(Dims d, PatchArgs A, const int *__restrict__ verts,
                                                         const T *__restrict__ factor, const T *__restrict__ mu,
                                                         const T *__restrict__ lam, const T *__restrict__ afc,
                                                         const T *__restrict__ rF, T *__restrict__ U) {
     constexpr int M = P - 1, W = 2 * M + 1, NL = 4 * M * M, NS = 2 * M * W, NT = W * W, NI = NL + NS + NT;
+    constexpr int NTILE = (NT + 63) / 64;
     __shared__ T g[NI];
+    __shared__ T smu[24], slam[M], safc[2 * M];
+    __shared__ T tl[64 * 65];
     const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
     const int pid = blockIdx.x;
-    PatchCtx<T> C{d, verts[3 * pid], verts[3 * pid + 1], verts[3 * pid + 2], M, P, mu, lam, afc, rF};
+    const int kfull[3] = {AX_FULL, AX_FULL, AX_FULL};
+    const int vx = verts[3 * pid], vy = verts[3 * pid + 1], vz = verts[3 * pid + 2];
+    stage_coefficients<T, M>(d, vx, vy, vz, kfull, mu, lam, afc, smu, slam, safc);
+    __syncthreads();
+    PatchCtx<T, M> C{d, vx, vy, vz, rF, smu, slam, safc};
     const T *F = factor + (int64_t)pid * A.stride;
-    T *Uo = U + ((int64_t)(C.vz * (d.ny + 1) + C.vy) * (d.nx + 1) + C.vx) * (int64_t)(W * W * W);
+    T *Uo = U + ((int64_t)(vz * (d.ny + 1) + vy) * (d.nx + 1) + vx) * (int64_t)(W * W * W);
 
     // ---- condensation of the interior DOFs into the interface right-hand side
     for (int idx = tid; idx < NI; idx += nt) {
@@ -496,79 +586,100 @@ __global__ void __launch_bounds__(256) k_patch_interior(Dims d, PatchArgs A, con
         if (task < NS) {
             int s = task / W, r = task % W;
             T acc = 0;
+#pragma unroll
             for (int c = 0; c < 2 * M; ++c) acc += B1[(int64_t)(s * 2 * M + c) * W + r] * g[s * 2 * M + c];
             g[NL + s * W + r] -= acc;
         } else {
             int t = task - NS, lx = t / W, ay = t % W;
             T acc = 0;
+#pragma unroll
             for (int c = 0; c < 2 * M; ++c) acc += B2[(int64_t)(lx * 2 * M + c) * W + ay] * g[c * 2 * M + lx];
             g[NL + NS + ay * W + inv_la_(lx, M)] -= acc;
         }
     }
     __syncthreads();
     // level-1 separator slices: dense lower solves, one wavefront per slice
-    {
+    for (int s = wv; s < 2 * M; s += nw) {
         T row[W];
-        for (int s = wv; s < 2 * M; s += nw) {
-            wave_load_rows<T, W>(F + A.off_Lsep + (int64_t)s * W * W, W, W, lane, row);
-            T x = lane < W ? g[NL + s * W + lane] : T(0);
-            x = wave_forward<T, W>(row, W, lane, x);
-            if (lane < W) g[NL + s * W + lane] = x;
-        }
+        wave_load_rows<T, W>(F + A.off_Lsep + (int64_t)s * W * W, W, W, lane, row);
+        T x = lane < W ? g[NL + s * W + lane] : T(0);
+        x = wave_forward<T, W>(row, W, lane, x);
+        if (lane < W) g[NL + s * W + lane] = x;
     }
+    // stage the first top-plane diagonal tile while the level-1 solves finish
+    T *gt = g + NL + NS;
+    auto stage_tile = [&](int J) {      // tl[i*65+k] = L(i,k); 16 independent loads per thread
+        const T *D = F + tile_offset(A.off_Ltop, NT, J);
+        T v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) v[u] = D[tid + 256 * u];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            int e = tid + 256 * u;
+            tl[(e & 63) * 65 + (e >> 6)] = v[u];
+        }
+    };
+    stage_tile(0);
     __syncthreads();
     // level-1 panels update the top plane
-    panel_fwd<T>(F + A.off_P, A.top_pad, NT, NS, g + NL, g + NL + NS);
+    panel_fwd<T>(F + A.off_P, A.top_pad, NT, NS, g + NL, gt);
     __syncthreads();
-    // dense top plane, 64-column tiles
-    T *gt = g + NL + NS;
-    for (int J = 0; J < A.ntiles; ++J) {
+    // dense top plane, 64-column tiles: wave 0 solves the diagonal block from LDS, then all
+    // waves update the rows below while the next diagonal block is staged
+    for (int J = 0; J < NTILE; ++J) {
         const int c0 = 64 * J, nb = min(64, NT - c0);
-        const T *D = F + A.tile_off[J];
         if (wv == 0) {
             T row[64];
-            wave_load_rows<T, 64>(D, 64, nb, lane, row);
+#pragma unroll
+            for (int k = 0; k < 64; ++k) row[k] = tl[lane * 65 + k];
             T x = lane < nb ? gt[c0 + lane] : T(0);
             x = wave_forward<T, 64>(row, nb, lane, x);
             if (lane < nb) gt[c0 + lane] = x;
         }
         __syncthreads();
-        panel_fwd<T>(D + 64 * 64, A.tile_rows_pad[J], NT - c0 - nb, nb, gt + c0, gt + c0 + nb);
+        const T *D = F + tile_offset(A.off_Ltop, NT, J);
+        const int rows = NT - c0 - nb;
+        panel_fwd<T>(D + 64 * 64, (rows + 3) / 4 * 4, rows, nb, gt + c0, gt + c0 + nb);
+        if (J + 1 < NTILE) stage_tile(J + 1);
         __syncthreads();
     }
-    // ---- backward: top plane
-    for (int J = A.ntiles - 1; J >= 0; --J) {
+    // ---- backward: top plane (tile NTILE-1 is staged)
+    for (int J = NTILE - 1; J >= 0; --J) {
         const int c0 = 64 * J, nb = min(64, NT - c0);
-        const T *D = F + A.tile_off[J];
-        panel_bwd<T>(D + 64 * 64, A.tile_rows_pad[J], NT - c0 - nb, nb, gt + c0 + nb, gt + c0);
-        __syncthreads();
         if (wv == 0) {
-            T row[64];
-            wave_load_rows<T, 64>(D, 64, nb, lane, row);
+            T col[64];
+#pragma unroll
+            for (int k = 0; k < 64; ++k) col[k] = tl[k * 65 + lane];
             T x = lane < nb ? gt[c0 + lane] : T(0);
-            x = wave_backward<T, 64>(row, nb, lane, x);
+            x = wave_backward<T, 64>(col, nb, lane, x);
             if (lane < nb) gt[c0 + lane] = x;
+        }
+        __syncthreads();
+        if (J > 0) {
+            const int cp = 64 * (J - 1), nbp = 64, rows = NT - cp - nbp;
+            const T *Dp = F + tile_offset(A.off_Ltop, NT, J - 1);
+            panel_bwd<T>(Dp + 64 * 64, (rows + 3) / 4 * 4, rows, nbp, gt + cp + nbp, gt + cp);
+            stage_tile(J - 1);
         }
         __syncthreads();
     }
     panel_bwd<T>(F + A.off_P, A.top_pad, NT, NS, gt, g + NL);
     __syncthreads();
-    {
-        T row[W];
-        for (int s = wv; s < 2 * M; s += nw) {
-            wave_load_rows<T, W>(F + A.off_Lsep + (int64_t)s * W * W, W, W, lane, row);
-            T x = lane < W ? g[NL + s * W + lane] : T(0);
-            x = wave_backward<T, W>(row, W, lane, x);
-            if (lane < W) g[NL + s * W + lane] = x;
-        }
+    for (int s = wv; s < 2 * M; s += nw) {
+        T col[W];
+        wave_load_cols<T, W>(F + A.off_Lsep + (int64_t)s * W * W, W, W, lane, col);
+        T x = lane < W ? g[NL + s * W + lane] : T(0);
+        x = wave_backward<T, W>(col, W, lane, x);
+        if (lane < W) g[NL + s * W + lane] = x;
     }
     __syncthreads();
     for (int i = tid; i < NL; i += nt) {
         int s = i / (2 * M), c = i % (2 * M);
         T v = g[i];
-        for (int r = 0; r < W; ++r) v -= B1[(int64_t)(s * 2 * M + c) * W + r] * g[NL + s * W + r];
         int ax = inv_la_(c, M);
-        for (int r = 0; r < W; ++r) v -= B2[(int64_t)(c * 2 * M + s) * W + r] * gt[r * W + ax];
+#pragma unroll
+        for (int r = 0; r < W; ++r)
+            v -= B1[(int64_t)(s * 2 * M + c) * W + r] * g[NL + s * W + r] + B2[(int64_t)(c * 2 * M + s) * W + r] * gt[r * W + ax];
         g[i] = v * invd[i];
     }
     __syncthreads();
@@ -600,11 +711,14 @@ __global__ void __launch_bounds__(256) k_patch_boundary(Dims d, const int *__res
                                                         const T *__restrict__ rF, T *__restrict__ U) {
     constexpr int M = P - 1, W = 2 * M + 1, MAXN = 4 * M + 1;
     __shared__ T g[M * MAXN > M * M ? M * MAXN : M * M];
+    __shared__ T smu[24], slam[M], safc[2 * M];
     const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
     const int pid = blockIdx.x;
     const int *ds = desc + 8 * pid;
-    PatchCtx<T> C{d, ds[0], ds[1], ds[2], M, P, mu, lam, afc, rF};
     const int kind[3] = {ds[3], ds[4], ds[5]};
+    stage_coefficients<T, M>(d, ds[0], ds[1], ds[2], kind, mu, lam, afc, smu, slam, safc);
+    __syncthreads();
+    PatchCtx<T, M> C{d, ds[0], ds[1], ds[2], rF, smu, slam, safc};
     const int nslices = ds[6], ns = ds[7], n = nslices * ns;
     const bool full[3] = {kind[0] == AX_FULL, kind[1] == AX_FULL, kind[2] == AX_FULL};
     int fa = -1, fb = -1, hh = -1, hb = -1, hc = -1;
@@ -635,7 +749,7 @@ __global__ void __launch_bounds__(256) k_patch_boundary(Dims d, const int *__res
         }
         return sidx(hb, pos[hb]) + M * sidx(hc, pos[hc]);
     };
-    T *Uo = U + ((int64_t)(C.vz * (d.ny + 1) + C.vy) * (d.nx + 1) + C.vx) * (int64_t)(W * W * W);
+    T *Uo = U + ((int64_t)(ds[2] * (d.ny + 1) + ds[1]) * (d.nx + 1) + ds[0]) * (int64_t)(W * W * W);
     for (int idx = tid; idx < n; idx += nt) {
         int pos[3];
         decode(idx, pos);
@@ -649,12 +763,19 @@ __global__ void __launch_bounds__(256) k_patch_boundary(Dims d, const int *__res
     if (ns == 1) {
         for (int t = tid; t < nslices; t += nt) g[t] *= F[t] * F[t];
     } else if (ns > 1) {
-        T row[MAXN];
         for (int t = wv; t < nslices; t += nw) {
-            wave_load_rows<T, MAXN>(F + (int64_t)t * ns * ns, ns, ns, lane, row);
+            const T *Ls = F + (int64_t)t * ns * ns;
             T x = lane < ns ? g[t * ns + lane] : T(0);
-            x = wave_forward<T, MAXN>(row, ns, lane, x);
-            x = wave_backward<T, MAXN>(row, ns, lane, x);
+            {
+                T row[MAXN];
+                wave_load_rows<T, MAXN>(Ls, ns, ns, lane, row);
+                x = wave_forward<T, MAXN>(row, ns, lane, x);
+            }
+            {
+                T col[MAXN];
+                wave_load_cols<T, MAXN>(Ls, ns, ns, lane, col);
+                x = wave_backward<T, MAXN>(col, ns, lane, x);
+            }
             if (lane < ns) g[t * ns + lane] = x;
         }
     }
