@@ -114,6 +114,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is described, "
@@ -121,6 +123,15 @@ def main():
         sys.exit(2)
     import torch
 
+    if args.calibrate_copy:
+        n = args.calibrate_copy // 8
+        src = torch.rand(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": n * 8, "copies": 3}), flush=True)
+        return
     from paper_2107_14758_amd import inputs, vsr
     vsr.lib()
     w = inputs.workload(WORKLOAD, seed=0)
