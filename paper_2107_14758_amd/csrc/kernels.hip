@@ -392,10 +392,19 @@ __device__ __forceinline__ void wave_load_rows(const T *__restrict__ L, int ld, 
 #pragma unroll
     for (int k = 0; k < MAXW; ++k) row[k] = (k < n && lane < n) ? L[(int64_t)k * ld + lane] : T(0);
 }
+// Packed lower triangle (column k holds rows k..n-1 at offset k n - k (k - 1) / 2): lane i
+// receives row i (forward) or column i (backward), zeros above the diagonal.
 template <typename T, int MAXW>
-__device__ __forceinline__ void wave_load_cols(const T *__restrict__ L, int ld, int n, int lane, T (&col)[MAXW]) {
+__device__ __forceinline__ void wave_load_rows_packed(const T *__restrict__ L, int n, int lane, T (&row)[MAXW]) {
 #pragma unroll
-    for (int k = 0; k < MAXW; ++k) col[k] = (k < n && lane < n) ? L[(int64_t)lane * ld + k] : T(0);
+    for (int k = 0; k < MAXW; ++k)
+        row[k] = (k < n && lane < n && lane >= k) ? L[k * n - k * (k - 1) / 2 + (lane - k)] : T(0);
+}
+template <typename T, int MAXW>
+__device__ __forceinline__ void wave_load_cols_packed(const T *__restrict__ L, int n, int lane, T (&col)[MAXW]) {
+    const int base = lane * n - lane * (lane - 1) / 2 - lane;
+#pragma unroll
+    for (int k = 0; k < MAXW; ++k) col[k] = (k < n && lane < n && k >= lane) ? L[base + k] : T(0);
 }
 
 // Both solves rely on the stored upper triangle being zero, so the update is branch-free:
@@ -525,13 +534,20 @@ __device__ void panel_bwd(const T *__restrict__ M, int ld, int nrows, int ncols,
     }
 }
 
+// Workgroup barrier that also stops the compiler from moving instructions between the
+// phases it separates (interleaving phases raises register pressure and forces spills).
+__device__ __forceinline__ void phase_sync() {
+    __syncthreads();
+    __builtin_amdgcn_sched_barrier(0);
+}
+
 // Offset of top-plane tile J inside one interior-patch factor (diagonal 64x64 block, then
 // the panel of rows below it padded to a multiple of 4).
 __device__ __forceinline__ int64_t tile_offset(int64_t off_Ltop, int NT, int J) {
     int64_t o = off_Ltop;
     for (int j = 0; j < J; ++j) {
         int rows = NT - 64 * j - min(64, NT - 64 * j);
-        o += 64 * 64 + (int64_t)64 * ((rows + 3) / 4 * 4);
+        o += 64 * 65 / 2 + (int64_t)64 * ((rows + 3) / 4 * 4);
     }
     return o;
 }
@@ -541,7 +557,7 @@ __device__ __forceinline__ int64_t tile_offset(int64_t off_Ltop, int NT, int J) 
 // Schur complement (leaves, level-1 separator slices, dense top plane), forward and
 // backward, then interior back-substitution.  Output: the patch box of (2m+1)^3 values.
 template <typename T, int P>
-__global__ void __launch_bounds__(256, (sizeof(T) == 4 ? 4 : 3)) k_patch_interior(Dims d, PatchArgs A, const int *__restrict__ verts,
+__global__ void __launch_bounds__(256) k_patch_interior(Dims d, PatchArgs A, const int *__restrict__ verts,
                                                         const T *__restrict__ factor, const T *__restrict__ mu,
                                                         const T *__restrict__ lam, const T *__restrict__ afc,
                                                         const T *__restrict__ rF, T *__restrict__ U) {
@@ -549,13 +565,13 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? 4 : 3)) k_patch_interio
     constexpr int NTILE = (NT + 63) / 64;
     __shared__ T g[NI];
     __shared__ T smu[24], slam[M], safc[2 * M];
-    __shared__ T tl[64 * 65];
+    __shared__ T tl[64 * 65 / 2];
     const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
     const int pid = blockIdx.x;
     const int kfull[3] = {AX_FULL, AX_FULL, AX_FULL};
     const int vx = verts[3 * pid], vy = verts[3 * pid + 1], vz = verts[3 * pid + 2];
     stage_coefficients<T, M>(d, vx, vy, vz, kfull, mu, lam, afc, smu, slam, safc);
-    __syncthreads();
+    phase_sync();
     PatchCtx<T, M> C{d, vx, vy, vz, rF, smu, slam, safc};
     const T *F = factor + (int64_t)pid * A.stride;
     T *Uo = U + ((int64_t)(vz * (d.ny + 1) + vy) * (d.nx + 1) + vx) * (int64_t)(W * W * W);
@@ -576,11 +592,11 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? 4 : 3)) k_patch_interio
         int dd = pos[0] == M ? 0 : (pos[1] == M ? 1 : 2);
         g[idx] = ncen == 1 ? C.condensed(pos, dd) : rF[C.gidx(pos[0], pos[1], pos[2])];
     }
-    __syncthreads();
+    phase_sync();
     // ---- forward: leaves (diagonal)
     const T *invd = F + A.off_invd, *B1 = F + A.off_B1, *B2 = F + A.off_B2;
     for (int i = tid; i < NL; i += nt) g[i] *= invd[i];
-    __syncthreads();
+    phase_sync();
     // leaf columns update their level-1 slice and their top-plane line
     for (int task = tid; task < 2 * NS; task += nt) {
         if (task < NS) {
@@ -597,82 +613,84 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? 4 : 3)) k_patch_interio
             g[NL + NS + ay * W + inv_la_(lx, M)] -= acc;
         }
     }
-    __syncthreads();
+    phase_sync();
     // level-1 separator slices: dense lower solves, one wavefront per slice
     for (int s = wv; s < 2 * M; s += nw) {
         T row[W];
-        wave_load_rows<T, W>(F + A.off_Lsep + (int64_t)s * W * W, W, W, lane, row);
+        wave_load_rows_packed<T, W>(F + A.off_Lsep + (int64_t)s * (W * (W + 1) / 2), W, lane, row);
         T x = lane < W ? g[NL + s * W + lane] : T(0);
         x = wave_forward<T, W>(row, W, lane, x);
         if (lane < W) g[NL + s * W + lane] = x;
     }
     // stage the first top-plane diagonal tile while the level-1 solves finish
     T *gt = g + NL + NS;
-    auto stage_tile = [&](int J) {      // tl[i*65+k] = L(i,k); 16 independent loads per thread
+    // stage a packed 64-column diagonal block verbatim (column k holds rows k..63 from
+    // offset k (129 - k) / 2); 9 independent loads per thread
+    auto stage_tile = [&](int J) {
         const T *D = F + tile_offset(A.off_Ltop, NT, J);
-        T v[16];
+        constexpr int NP = 64 * 65 / 2, R = (NP + 255) / 256;
+        T v[R];
 #pragma unroll
-        for (int u = 0; u < 16; ++u) v[u] = D[tid + 256 * u];
+        for (int u = 0; u < R; ++u) v[u] = tid + 256 * u < NP ? D[tid + 256 * u] : T(0);
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            int e = tid + 256 * u;
-            tl[(e & 63) * 65 + (e >> 6)] = v[u];
-        }
+        for (int u = 0; u < R; ++u)
+            if (tid + 256 * u < NP) tl[tid + 256 * u] = v[u];
     };
     stage_tile(0);
-    __syncthreads();
+    phase_sync();
     // level-1 panels update the top plane
     panel_fwd<T>(F + A.off_P, A.top_pad, NT, NS, g + NL, gt);
-    __syncthreads();
+    phase_sync();
     // dense top plane, 64-column tiles: wave 0 solves the diagonal block from LDS, then all
     // waves update the rows below while the next diagonal block is staged
     for (int J = 0; J < NTILE; ++J) {
         const int c0 = 64 * J, nb = min(64, NT - c0);
         if (wv == 0) {
-            T row[64];
+            T row[64];   // row lane of the block: L(lane, k) at k (129 - k) / 2 + lane - k
 #pragma unroll
-            for (int k = 0; k < 64; ++k) row[k] = tl[lane * 65 + k];
+            for (int k = 0; k < 64; ++k) row[k] = k <= lane ? tl[k * (129 - k) / 2 - k + lane] : T(0);
             T x = lane < nb ? gt[c0 + lane] : T(0);
             x = wave_forward<T, 64>(row, nb, lane, x);
             if (lane < nb) gt[c0 + lane] = x;
         }
-        __syncthreads();
+        phase_sync();
         const T *D = F + tile_offset(A.off_Ltop, NT, J);
         const int rows = NT - c0 - nb;
-        panel_fwd<T>(D + 64 * 64, (rows + 3) / 4 * 4, rows, nb, gt + c0, gt + c0 + nb);
+        panel_fwd<T>(D + 64 * 65 / 2, (rows + 3) / 4 * 4, rows, nb, gt + c0, gt + c0 + nb);
         if (J + 1 < NTILE) stage_tile(J + 1);
-        __syncthreads();
+        phase_sync();
     }
     // ---- backward: top plane (tile NTILE-1 is staged)
     for (int J = NTILE - 1; J >= 0; --J) {
         const int c0 = 64 * J, nb = min(64, NT - c0);
         if (wv == 0) {
-            T col[64];
+            T col[64];   // column lane of the block: L(k, lane) at lane (129 - lane) / 2 + k - lane
+            const int cb = lane * (129 - lane) / 2 - lane;
 #pragma unroll
-            for (int k = 0; k < 64; ++k) col[k] = tl[k * 65 + lane];
+            for (int k = 0; k < 64; ++k) col[k] = k >= lane ? tl[cb + k] : T(0);
             T x = lane < nb ? gt[c0 + lane] : T(0);
             x = wave_backward<T, 64>(col, nb, lane, x);
             if (lane < nb) gt[c0 + lane] = x;
         }
-        __syncthreads();
+        phase_sync();
         if (J > 0) {
             const int cp = 64 * (J - 1), nbp = 64, rows = NT - cp - nbp;
             const T *Dp = F + tile_offset(A.off_Ltop, NT, J - 1);
-            panel_bwd<T>(Dp + 64 * 64, (rows + 3) / 4 * 4, rows, nbp, gt + cp + nbp, gt + cp);
+            panel_bwd<T>(Dp + 64 * 65 / 2, (rows + 3) / 4 * 4, rows, nbp, gt + cp + nbp, gt + cp);
             stage_tile(J - 1);
         }
-        __syncthreads();
+        phase_sync();
     }
     panel_bwd<T>(F + A.off_P, A.top_pad, NT, NS, gt, g + NL);
-    __syncthreads();
+    phase_sync();
     for (int s = wv; s < 2 * M; s += nw) {
         T col[W];
-        wave_load_cols<T, W>(F + A.off_Lsep + (int64_t)s * W * W, W, W, lane, col);
+        wave_load_cols_packed<T, W>(F + A.off_Lsep + (int64_t)s * (W * (W + 1) / 2), W, lane, col);
         T x = lane < W ? g[NL + s * W + lane] : T(0);
         x = wave_backward<T, W>(col, W, lane, x);
         if (lane < W) g[NL + s * W + lane] = x;
     }
-    __syncthreads();
+    phase_sync();
     for (int i = tid; i < NL; i += nt) {
         int s = i / (2 * M), c = i % (2 * M);
         T v = g[i];
@@ -682,7 +700,7 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? 4 : 3)) k_patch_interio
             v -= B1[(int64_t)(s * 2 * M + c) * W + r] * g[NL + s * W + r] + B2[(int64_t)(c * 2 * M + s) * W + r] * gt[r * W + ax];
         g[i] = v * invd[i];
     }
-    __syncthreads();
+    phase_sync();
     // ---- interface values and interior back-substitution into the patch box
     const bool full[3] = {true, true, true};
     for (int idx = tid; idx < W * W * W; idx += nt) {
@@ -764,16 +782,16 @@ __global__ void __launch_bounds__(256) k_patch_boundary(Dims d, const int *__res
         for (int t = tid; t < nslices; t += nt) g[t] *= F[t] * F[t];
     } else if (ns > 1) {
         for (int t = wv; t < nslices; t += nw) {
-            const T *Ls = F + (int64_t)t * ns * ns;
+            const T *Ls = F + (int64_t)t * (ns * (ns + 1) / 2);
             T x = lane < ns ? g[t * ns + lane] : T(0);
             {
                 T row[MAXN];
-                wave_load_rows<T, MAXN>(Ls, ns, ns, lane, row);
+                wave_load_rows_packed<T, MAXN>(Ls, ns, lane, row);
                 x = wave_forward<T, MAXN>(row, ns, lane, x);
             }
             {
                 T col[MAXN];
-                wave_load_cols<T, MAXN>(Ls, ns, ns, lane, col);
+                wave_load_cols_packed<T, MAXN>(Ls, ns, lane, col);
                 x = wave_backward<T, MAXN>(col, ns, lane, x);
             }
             if (lane < ns) g[t * ns + lane] = x;

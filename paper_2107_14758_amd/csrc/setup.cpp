@@ -418,7 +418,7 @@ InteriorLayout interior_layout(int p) {
     L.off_B1 = o; o += (int64_t)2 * m * 2 * m * w;
     L.off_B2 = o; o += (int64_t)2 * m * 2 * m * w;
     o = round_up(o, 4);
-    L.off_Lsep = o; o += (int64_t)2 * m * w * w;
+    L.off_Lsep = o; o += (int64_t)2 * m * (w * (w + 1) / 2);
     o = round_up(o, 4);
     L.off_P = o; o += (int64_t)2 * m * w * L.top_pad;
     L.off_Ltop = o;
@@ -429,7 +429,7 @@ InteriorLayout interior_layout(int p) {
         int rp = (int)round_up(rows, 4);
         L.tile_off.push_back(o);
         L.tile_rows_pad.push_back(rp);
-        o += 64 * 64 + (int64_t)64 * rp;
+        o += 64 * 65 / 2 + (int64_t)64 * rp;
     }
     L.stride = round_up(o, 64);
     return L;
@@ -666,10 +666,9 @@ bool factor_interior(const InteriorLayout &L, std::vector<double> &S, double *ou
         for (int i = 0; i < w; ++i)
             for (int j = 0; j < w; ++j) Ls[(size_t)i * w + j] = at(sep(s, i), sep(s, j));
         if (!cholesky_lower(w, Ls.data(), w)) return false;
-        double *Lo = out + L.off_Lsep + (int64_t)s * w * w;   // column-major [k][i]
-        for (int k = 0; k < w; ++k)
-            for (int i = 0; i < w; ++i)
-                Lo[(size_t)k * w + i] = i < k ? 0.0 : (i == k ? 1.0 / Ls[(size_t)i * w + i] : Ls[(size_t)i * w + k]);
+        double *Lo = out + L.off_Lsep + (int64_t)s * (w * (w + 1) / 2);   // packed lower, column-major
+        for (int k = 0, e = 0; k < w; ++k)
+            for (int i = k; i < w; ++i, ++e) Lo[e] = i == k ? 1.0 / Ls[(size_t)i * w + i] : Ls[(size_t)i * w + k];
         for (int r = 0; r < nt; ++r) {
             double *pr = &Pall[(size_t)r * ncol + s * w];
             for (int j = 0; j < w; ++j) {
@@ -707,16 +706,16 @@ bool factor_interior(const InteriorLayout &L, std::vector<double> &S, double *ou
     if (!cholesky_lower(nt, T.data(), nt)) return false;
     for (int J = 0; J < L.ntiles; ++J) {
         int c0 = 64 * J, nb = std::min(64, nt - c0);
-        double *D = out + L.tile_off[J];
-        for (int k = 0; k < 64; ++k)
-            for (int i = 0; i < 64; ++i) {
+        double *D = out + L.tile_off[J];   // diagonal block packed as a 64-column lower triangle
+        for (int k = 0, e = 0; k < 64; ++k)
+            for (int i = k; i < 64; ++i, ++e) {
                 double v = 0.0;
-                if (k < nb && i < nb && i >= k)
+                if (k < nb && i < nb)
                     v = i == k ? 1.0 / T[(size_t)(c0 + i) * nt + c0 + k] : T[(size_t)(c0 + i) * nt + c0 + k];
-                D[k * 64 + i] = v;
+                D[e] = v;
             }
         int rp = L.tile_rows_pad[J], r0 = c0 + nb;
-        double *Pn = D + 64 * 64;
+        double *Pn = D + 64 * 65 / 2;
         for (int k = 0; k < 64; ++k)
             for (int rr = 0; rr < rp; ++rr) {
                 int r = r0 + rr;
@@ -734,10 +733,9 @@ bool factor_slices(const IfaceMap &M, std::vector<double> &S, double *out) {
         for (int i = 0; i < ns; ++i)
             for (int j = 0; j < ns; ++j) Ls[(size_t)i * ns + j] = S[(size_t)(t * ns + i) * n + t * ns + j];
         if (!cholesky_lower(ns, Ls.data(), ns)) return false;
-        double *o = out + (int64_t)t * ns * ns;
-        for (int k = 0; k < ns; ++k)
-            for (int i = 0; i < ns; ++i)
-                o[(size_t)k * ns + i] = i < k ? 0.0 : (i == k ? 1.0 / Ls[(size_t)i * ns + i] : Ls[(size_t)i * ns + k]);
+        double *o = out + (int64_t)t * (ns * (ns + 1) / 2);   // packed lower, column-major
+        for (int k = 0, e = 0; k < ns; ++k)
+            for (int i = k; i < ns; ++i, ++e) o[e] = i == k ? 1.0 / Ls[(size_t)i * ns + i] : Ls[(size_t)i * ns + k];
     }
     return true;
 }
@@ -768,7 +766,7 @@ PatchSet make_patches(int nx, int ny, int nz, const OneD &od, const double *mu, 
                 IfaceMap M = make_map(p, kk);
                 P.boundary_desc.insert(P.boundary_desc.end(), {vx, vy, vz, kind[0], kind[1], kind[2], M.nslices, M.ns});
                 P.boundary_off.push_back(P.boundary_entries);
-                P.boundary_entries += (int64_t)M.nslices * M.ns * M.ns;
+                P.boundary_entries += (int64_t)M.nslices * (M.ns * (M.ns + 1) / 2);
             }
     int64_t ni = (int64_t)P.interior_vertices.size() / 3, nb = (int64_t)P.boundary_off.size();
     P.interior_factor.assign((size_t)(ni * P.L.stride), 0.0);
