@@ -136,6 +136,60 @@ vsr_status vsr_kernel_stats(vsr_problem *prob, int64_t *launches, double *total_
 /* Sizes of the patch factorization: number of patches and stored factor entries. */
 vsr_status vsr_factor_info(const vsr_problem *prob, int64_t *num_patches, int64_t *factor_entries);
 
+/* ---------------------------------------------------------------------------
+ * Learned separable surrogate (an extension of the averaged surrogate of Sec. 2.7;
+ * the paper has no learned part).  Cells are passed by their 8 corners: host
+ * array corners[24*cell + 3*((c*2+b)*2+a) + coord], corner (a,b,c) in {0,1}^3
+ * of the reference cube [-1,1]^3, x fastest.  kappa (host, per cell) may be NULL.
+ * All host arrays are read or written synchronously; device arrays are HIP
+ * device memory.  Errors as for the solver calls.
+ * ------------------------------------------------------------------------- */
+
+/* Number of MLP parameters (74 -> 64 -> 64 -> 3, GELU): W1 (64x74 row-major), b1 (64),
+ * W2 (64x64), b2, W3 (3x64), b3, packed in that order as float32. */
+int32_t vsr_mlp_num_params(void);
+
+/* Features per cell (device float32, ncell x 74): 8 (DF / |det DF(0)|^(1/3) - I) at the
+ * 2x2x2 Gauss points (x fastest, DF row-major), then log kappa and 0.  mu_avg (host, ncell x 3, may be NULL):
+ * the cell averages of diag(G_hat) of Sec. 2.7 with kappa = 1 and the degree-p
+ * quadrature rule.  features_dev may be NULL. */
+vsr_status vsr_surrogate_features(int64_t ncell, const double *corners, const double *kappa, int32_t p,
+                                  float *features_dev, double *mu_avg);
+
+/* Theorem 1 (Sec. 2.7) spectral ratio C_K / c_K of mu^{-1/2} G_hat mu^{-1/2} over the
+ * 27 points xi in {-1,0,1}^3, for host scalings mu (ncell x 3, positive); ratio: host (ncell). */
+vsr_status vsr_surrogate_ratio(int64_t ncell, const double *corners, const double *mu, double *ratio);
+
+/* Minimax labels: delta (host, ncell x 3) with mu = mu_avg exp(delta) minimising the
+ * Theorem-1 ratio on a fixed coarse-to-fine grid over delta = (a, b, 0), shifted so the
+ * spectrum is centred at 1; ratio (host, ncell, may be NULL) is the ratio attained. */
+vsr_status vsr_surrogate_labels(int64_t ncell, const double *corners, int32_t p, double *delta, double *ratio);
+
+/* Y = MLP(X) for n samples (device float32, X: n x 74, Y: n x 3).  bf16 != 0 rounds the
+ * weights to bfloat16 for the arithmetic (FP32 accumulation). */
+vsr_status vsr_mlp_forward(const float *params_dev, int32_t bf16, const float *X_dev, int64_t n, float *Y_dev);
+
+/* Gradient (device, vsr_mlp_num_params() floats) of the mean squared error between MLP(X)
+ * and T (device, n x 3) with respect to the parameters; loss_dev (1 float) may be NULL. */
+vsr_status vsr_mlp_gradient(const float *params_dev, int32_t bf16, const float *X_dev, const float *T_dev, int64_t n,
+                            float *grad_dev, float *loss_dev);
+
+/* `steps` Adam steps (beta 0.9 / 0.999, eps 1e-8, learning rate lr) on the FP32 master
+ * parameters; minibatch s uses the rows order_dev[s*batch .. (s+1)*batch) of X and T
+ * (device int32, steps*batch entries).  step0 counts earlier steps (bias correction).
+ * adam_m_dev, adam_v_dev: device state (num_params floats each, zero initially).
+ * loss_dev (device, steps floats, may be NULL) receives each minibatch loss. */
+vsr_status vsr_mlp_train(float *params_dev, float *adam_m_dev, float *adam_v_dev, int32_t bf16, const float *X_dev,
+                         const float *T_dev, int64_t n, const int32_t *order_dev, int32_t batch, int32_t steps,
+                         int32_t step0, float lr, float *loss_dev);
+
+/* Surrogate scalings for the solver (pass as vsr_coefficients.mu_override): per cell
+ * mu = kappa mu_avg exp(MLP(features)), kept only where its Theorem-1 ratio is below that
+ * of the averaged scalings (else kappa mu_avg).  mu_out: host ncell x 3; learned (host,
+ * ncell, may be NULL): 1 where the network's scalings were kept. */
+vsr_status vsr_surrogate_scalings(int64_t ncell, const double *corners, const double *kappa, int32_t p,
+                                  const float *params_dev, int32_t bf16, double *mu_out, int32_t *learned);
+
 void vsr_destroy(vsr_problem *prob);
 
 /* Description of the last failure on the calling thread ("" if none). */

@@ -16,8 +16,10 @@
 
 using namespace vsr;
 
+namespace vsr {
+thread_local std::string g_last_error_text;
+}
 namespace {
-thread_local std::string g_last_error;
 
 template <typename F>
 vsr_status guarded(F &&f) {
@@ -25,13 +27,13 @@ vsr_status guarded(F &&f) {
         f();
         return VSR_OK;
     } catch (const Error &e) {
-        g_last_error = e.what();
+        vsr::g_last_error_text = e.what();
         return e.status;
     } catch (const std::bad_alloc &) {
-        g_last_error = "host allocation failed";
+        vsr::g_last_error_text = "host allocation failed";
         return VSR_ENOMEM;
     } catch (const std::exception &e) {
-        g_last_error = e.what();
+        vsr::g_last_error_text = e.what();
         return VSR_EINVAL;
     }
 }
@@ -595,6 +597,6 @@ vsr_status vsr_factor_info(const vsr_problem *P, int64_t *num_patches, int64_t *
 
 void vsr_destroy(vsr_problem *P) { delete P; }
 
-const char *vsr_last_error(void) { return g_last_error.c_str(); }
+const char *vsr_last_error(void) { return vsr::g_last_error_text.c_str(); }
 
 }  // extern "C"

@@ -79,3 +79,20 @@ WORKLOADS = {
 def workload(name, seed=0):
     w = WORKLOADS[name]
     return make_problem(w["n"], w["p"], seed=seed, jitter=w["jitter"], lognormal=w["lognormal"])
+
+
+def random_cells(n, amplitude, rng, h=1.0):
+    """n independent trilinear cells: the cube [0,h]^3 with each of its 8 corners moved by an
+    independent U[-amplitude h, amplitude h] offset per coordinate; (n, 2, 2, 2, 3) [cell, c, b, a, coord]."""
+    base = np.array([[[[a, b, c] for a in range(2)] for b in range(2)] for c in range(2)], dtype=np.float64) * h
+    return base[None] + rng.uniform(-1.0, 1.0, size=(n, 2, 2, 2, 3)) * amplitude * h
+
+
+def mlp_init(rng, nin=74, nh=64, nout=3):
+    """Initial MLP parameters (float32, packed W1, b1, W2, b2, W3, b3): uniform(+-1/sqrt(fan_in)), zero biases."""
+    parts = []
+    for fan_in, fan_out in ((nin, nh), (nh, nh), (nh, nout)):
+        lim = 1.0 / np.sqrt(fan_in)
+        parts.append(rng.uniform(-lim, lim, size=fan_out * fan_in))
+        parts.append(np.zeros(fan_out))
+    return np.concatenate(parts).astype(np.float32)

@@ -180,3 +180,126 @@ class Problem:
         a, b = ctypes.c_int64(), ctypes.c_int64()
         _check(lib().vsr_factor_info(self._h, ctypes.byref(a), ctypes.byref(b)))
         return a.value, b.value
+
+
+# ---------------------------------------------------------------- learned surrogate
+def _setup_surrogate_signatures():
+    L = lib()
+    if getattr(L, "_surrogate_ready", False):
+        return L
+    P = ctypes.c_void_p
+    dpp = ctypes.POINTER(ctypes.c_double)
+    L.vsr_mlp_num_params.restype = ctypes.c_int32
+    L.vsr_surrogate_features.argtypes = [ctypes.c_int64, dpp, dpp, ctypes.c_int32, P, dpp]
+    L.vsr_surrogate_ratio.argtypes = [ctypes.c_int64, dpp, dpp, dpp]
+    L.vsr_surrogate_labels.argtypes = [ctypes.c_int64, dpp, ctypes.c_int32, dpp, dpp]
+    L.vsr_mlp_forward.argtypes = [P, ctypes.c_int32, P, ctypes.c_int64, P]
+    L.vsr_mlp_gradient.argtypes = [P, ctypes.c_int32, P, P, ctypes.c_int64, P, P]
+    L.vsr_mlp_train.argtypes = [P, P, P, ctypes.c_int32, P, P, ctypes.c_int64, P, ctypes.c_int32, ctypes.c_int32,
+                                ctypes.c_int32, ctypes.c_float, P]
+    L.vsr_surrogate_scalings.argtypes = [ctypes.c_int64, dpp, dpp, ctypes.c_int32, P, ctypes.c_int32, dpp,
+                                         ctypes.POINTER(ctypes.c_int32)]
+    for name in ("vsr_surrogate_features", "vsr_surrogate_ratio", "vsr_surrogate_labels", "vsr_mlp_forward",
+                 "vsr_mlp_gradient", "vsr_mlp_train", "vsr_surrogate_scalings"):
+        getattr(L, name).restype = ctypes.c_int
+    L._surrogate_ready = True
+    return L
+
+
+def _dp(a):
+    return None if a is None else a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _tp(t, dtype):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise TypeError(f"expected a contiguous {dtype} CUDA tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def mesh_corners(vertices):
+    """Corners (ncell, 2, 2, 2, 3) [cell, c, b, a, coord] of a structured mesh's cells (indexing only)."""
+    V = np.asarray(vertices, dtype=np.float64)
+    nz, ny, nx = V.shape[0] - 1, V.shape[1] - 1, V.shape[2] - 1
+    out = np.empty((nz, ny, nx, 2, 2, 2, 3))
+    for c in range(2):
+        for b in range(2):
+            for a in range(2):
+                out[:, :, :, c, b, a, :] = V[c:c + nz, b:b + ny, a:a + nx, :]
+    return np.ascontiguousarray(out.reshape(nz * ny * nx, 2, 2, 2, 3))
+
+
+def mlp_num_params():
+    return int(_setup_surrogate_signatures().vsr_mlp_num_params())
+
+
+def surrogate_features(corners, p, kappa=None):
+    import torch
+    L = _setup_surrogate_signatures()
+    C = np.ascontiguousarray(corners, dtype=np.float64)
+    n = C.shape[0]
+    k = None if kappa is None else np.ascontiguousarray(kappa, dtype=np.float64)
+    X = torch.empty((n, 74), dtype=torch.float32, device="cuda")
+    mu = np.empty((n, 3))
+    _check(L.vsr_surrogate_features(n, _dp(C), _dp(k), int(p), _tp(X, torch.float32), _dp(mu)))
+    return X, mu
+
+
+def surrogate_ratio(corners, mu):
+    L = _setup_surrogate_signatures()
+    C = np.ascontiguousarray(corners, dtype=np.float64)
+    m = np.ascontiguousarray(mu, dtype=np.float64)
+    r = np.empty(C.shape[0])
+    _check(L.vsr_surrogate_ratio(C.shape[0], _dp(C), _dp(m), _dp(r)))
+    return r
+
+
+def surrogate_labels(corners, p):
+    L = _setup_surrogate_signatures()
+    C = np.ascontiguousarray(corners, dtype=np.float64)
+    d = np.empty((C.shape[0], 3))
+    r = np.empty(C.shape[0])
+    _check(L.vsr_surrogate_labels(C.shape[0], _dp(C), int(p), _dp(d), _dp(r)))
+    return d, r
+
+
+def mlp_forward(params, X, bf16=True):
+    import torch
+    L = _setup_surrogate_signatures()
+    Y = torch.empty((X.shape[0], 3), dtype=torch.float32, device="cuda")
+    _check(L.vsr_mlp_forward(_tp(params, torch.float32), int(bool(bf16)), _tp(X, torch.float32), X.shape[0],
+                             _tp(Y, torch.float32)))
+    return Y
+
+
+def mlp_gradient(params, X, T, bf16=True):
+    import torch
+    L = _setup_surrogate_signatures()
+    g = torch.empty_like(params)
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    _check(L.vsr_mlp_gradient(_tp(params, torch.float32), int(bool(bf16)), _tp(X, torch.float32),
+                              _tp(T, torch.float32), X.shape[0], _tp(g, torch.float32), _tp(loss, torch.float32)))
+    return g, loss
+
+
+def mlp_train(params, m, v, X, T, order, batch, steps, step0=0, lr=1e-3, bf16=True):
+    import torch
+    L = _setup_surrogate_signatures()
+    losses = torch.empty(steps, dtype=torch.float32, device="cuda")
+    _check(L.vsr_mlp_train(_tp(params, torch.float32), _tp(m, torch.float32), _tp(v, torch.float32),
+                           int(bool(bf16)), _tp(X, torch.float32), _tp(T, torch.float32), X.shape[0],
+                           _tp(order, torch.int32), int(batch), int(steps), int(step0), float(lr),
+                           _tp(losses, torch.float32)))
+    return losses
+
+
+def surrogate_scalings(corners, p, params, kappa=None, bf16=True):
+    import torch
+    L = _setup_surrogate_signatures()
+    C = np.ascontiguousarray(corners, dtype=np.float64)
+    k = None if kappa is None else np.ascontiguousarray(kappa, dtype=np.float64)
+    mu = np.empty((C.shape[0], 3))
+    used = np.empty(C.shape[0], dtype=np.int32)
+    _check(L.vsr_surrogate_scalings(C.shape[0], _dp(C), _dp(k), int(p), _tp(params, torch.float32), int(bool(bf16)),
+                                    _dp(mu), used.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+    return mu, used
