@@ -78,6 +78,18 @@ typedef struct {
     uint64_t seed;           /* seed of the splitmix64 Lanczos start vector */
     double omega;            /* > 0: use this damping instead of the Lanczos estimate */
     void *stream;            /* hipStream_t; NULL => default stream */
+    int32_t autotune;        /* 1: pick launch shapes (cells per workgroup of the operator,
+                                lattice-pass block size, patch-panel unroll) by timing the
+                                candidates on this problem at setup, once per (GPU
+                                architecture, p, precision, operator kind) per process and
+                                per cache file; 0: fixed defaults.  Shapes never change the
+                                arithmetic of any output value. */
+    int32_t batch_streams;   /* batched solves: HIP streams the members are spread over; 0 => 4 */
+    int32_t batch_eager;     /* batched solves: 1 launches every iteration from the host;
+                                0 (default) records one lockstep iteration of all members into
+                                a hipGraph once and replays it */
+    const char *tune_cache;  /* autotune: text file of tuned shapes to read and append to;
+                                NULL => in-process cache only */
 } vsr_options;
 
 typedef struct {
@@ -190,7 +202,53 @@ vsr_status vsr_mlp_train(float *params_dev, float *adam_m_dev, float *adam_v_dev
 vsr_status vsr_surrogate_scalings(int64_t ncell, const double *corners, const double *kappa, int32_t p,
                                   const float *params_dev, int32_t bf16, double *mu_out, int32_t *learned);
 
+/* Launch shapes in use: shapes[0..3] = operator cells per workgroup (FP64, FP32),
+ * lattice-pass block size, patch-panel unroll. */
+vsr_status vsr_get_tuning(const vsr_problem *prob, int32_t shapes[4]);
+
+/* Set the launch shapes (same order; operator cells per workgroup in {1, 2, 4}, used only
+ * for Cartesian meshes with p <= 7; block a multiple of 64 in [64, 1024]; unroll in
+ * {4, 8, 16}).  VSR_EINVAL for any other value. */
+vsr_status vsr_set_tuning(vsr_problem *prob, const int32_t shapes[4]);
+
 void vsr_destroy(vsr_problem *prob);
+
+/* ---------------------------------------------------------------------------
+ * Batched solves: many independent problems (any mix of sizes, degrees, meshes
+ * and coefficients) solved together.  Every member runs its own PCG (Sec. 2.8
+ * settings) with its own scalars; the members iterate in lockstep, the stopping
+ * test of each is taken on the device and a member that has stopped skips all
+ * further work (its kernels return at once).  Members are spread over
+ * options.batch_streams streams (largest first onto the least loaded stream) so
+ * small members run concurrently; one lockstep iteration of all members is
+ * recorded into a hipGraph and replayed until none is active (one 4-byte
+ * readback per replay).  Each member gives the same iterates as vsr_pcg_solve
+ * on it up to the order of floating-point atomic additions.
+ * ------------------------------------------------------------------------- */
+typedef struct vsr_batch vsr_batch;
+
+/* Set up `count` members: meshes[i], p[i], coefs[i] (coefs may be NULL: kappa = 1
+ * everywhere), all with *opt.  Setup is as vsr_setup for each member. */
+vsr_status vsr_setup_batch(int32_t count, const vsr_mesh *meshes, const int32_t *p,
+                           const vsr_coefficients *coefs, const vsr_options *opt,
+                           vsr_batch **out);
+
+int32_t vsr_batch_size(const vsr_batch *batch);
+
+/* Member i, owned by the batch (valid until vsr_destroy_batch): use it for
+ * vsr_num_dofs, vsr_load_vector, the applies and single solves. */
+vsr_problem *vsr_batch_member(vsr_batch *batch, int32_t i);
+
+/* Solve A_i x_i = b_i for every member from x_i = 0 to ||r_i||_2 <= rtol ||b_i||_2.
+ * b_dev, x_dev: host arrays of count device pointers (FP64, length vsr_num_dofs of
+ * the member).  infos (host, count entries, may be NULL) receives per-member
+ * results; solve_seconds is the wall time of the whole batch.  Returns after
+ * completion; VSR_ENOCONV if any member stopped without converging (its info says
+ * which). */
+vsr_status vsr_pcg_solve_batch(vsr_batch *batch, const double *const *b_dev, double *const *x_dev, double rtol,
+                               vsr_solve_info *infos);
+
+void vsr_destroy_batch(vsr_batch *batch);
 
 /* Description of the last failure on the calling thread ("" if none). */
 const char *vsr_last_error(void);

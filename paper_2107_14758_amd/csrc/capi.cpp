@@ -4,10 +4,16 @@
 // relaxation for high-order FEM", Sec. 2.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <map>
 #include <memory>
+#include <mutex>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -83,8 +89,15 @@ struct vsr_problem {
     double *scal = nullptr, *partials = nullptr, *host_scal = nullptr;
     double omega = 1.0, lmin = 0.0, lmax = 0.0;
     double setup_seconds = 0.0;
+    // launch context: an optional gate (set while a batched solve drives this problem)
+    // and the launch shapes chosen by the autotuner
+    const double *gate = nullptr;
+    Tuning tune{};
+    double *vx = nullptr;             // solution of a batched solve
+    Exec ex() const { return Exec{stream, gate, tune}; }
     // profiling of the interior patch-solve launches
     bool profiling = false;
+    bool capturing = false;           // launches are being recorded into a graph
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;   // reusable pool
     size_t events_used = 0;
 
@@ -122,13 +135,13 @@ namespace {
 
 template <typename T>
 void op_apply(vsr_problem *P, const T *x, T *y) {
-    launch_fill<T>(P->n, y, T(0), P->stream);
+    launch_fill<T>(P->n, y, T(0), P->ex());
     if constexpr (std::is_same<T, double>::value) {
-        if (P->cartesian) launch_op_kron<double>(P->d, P->AB64, P->mu64, x, y, P->stream);
-        else launch_op_general<double>(P->d, P->IDq64, P->Gw64, x, y, P->stream);
+        if (P->cartesian) launch_op_kron<double>(P->d, P->AB64, P->mu64, x, y, P->ex());
+        else launch_op_general<double>(P->d, P->IDq64, P->Gw64, x, y, P->ex());
     } else {
-        if (P->cartesian) launch_op_kron<float>(P->d, P->AB32, P->mu32, x, y, P->stream);
-        else launch_op_general<float>(P->d, P->IDq32, P->Gw32, x, y, P->stream);
+        if (P->cartesian) launch_op_kron<float>(P->d, P->AB32, P->mu32, x, y, P->ex());
+        else launch_op_general<float>(P->d, P->IDq32, P->Gw32, x, y, P->ex());
     }
     VSR_HIP(hipGetLastError());
 }
@@ -145,11 +158,12 @@ void relax_apply(vsr_problem *P, const Tin *in, T *out, T alpha, T beta) {
     const int L[3] = {P->d.Lx, P->d.Ly, P->d.Lz};
     T *t1 = (T *)P->t1, *t2 = (T *)P->t2, *rF = (T *)P->rF, *zF = (T *)P->zF, *U = (T *)P->U;
     const Table *TT = P->tab[0], *Tp = P->tab[1];
-    launch_axis_pass<Tin, T>(TT[0].rowptr, TT[0].col, wt<T>(TT[0]), 0, L, L, in, t1, T(1), T(0), P->stream);
-    launch_axis_pass<T, T>(TT[1].rowptr, TT[1].col, wt<T>(TT[1]), 1, L, L, t1, t2, T(1), T(0), P->stream);
-    launch_axis_pass<T, T>(TT[2].rowptr, TT[2].col, wt<T>(TT[2]), 2, L, L, t2, rF, T(1), T(0), P->stream);
+    launch_axis_pass<Tin, T>(TT[0].rowptr, TT[0].col, wt<T>(TT[0]), 0, L, L, in, t1, T(1), T(0), P->ex());
+    launch_axis_pass<T, T>(TT[1].rowptr, TT[1].col, wt<T>(TT[1]), 1, L, L, t1, t2, T(1), T(0), P->ex());
+    launch_axis_pass<T, T>(TT[2].rowptr, TT[2].col, wt<T>(TT[2]), 2, L, L, t2, rF, T(1), T(0), P->ex());
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (P->profiling) {
+    const bool prof = P->profiling && !P->capturing;
+    if (prof) {
         if (P->events_used == P->events.size()) {
             VSR_HIP(hipEventCreate(&e0));
             VSR_HIP(hipEventCreate(&e1));
@@ -160,17 +174,17 @@ void relax_apply(vsr_problem *P, const Tin *in, T *out, T alpha, T beta) {
         VSR_HIP(hipEventRecord(e0, P->stream));
     }
     launch_patch_interior<T>(P->d, P->pa, P->n_int, P->verts, (const T *)P->fint, (const T *)P->mu_sur, (const T *)P->lam,
-                             (const T *)P->afc, rF, U, P->stream);
-    if (P->profiling) {
+                             (const T *)P->afc, rF, U, P->ex());
+    if (prof) {
         VSR_HIP(hipEventRecord(e1, P->stream));
         ++P->events_used;
     }
     launch_patch_boundary<T>(P->d, P->n_bnd, P->bdesc, P->boff, (const T *)P->fbnd, (const T *)P->mu_sur, (const T *)P->lam,
-                             (const T *)P->afc, rF, U, P->stream);
-    launch_patch_assemble<T>(P->d, P->opt.interior_patches_only, U, zF, P->stream);
-    launch_axis_pass<T, T>(Tp[0].rowptr, Tp[0].col, wt<T>(Tp[0]), 0, L, L, zF, t1, T(1), T(0), P->stream);
-    launch_axis_pass<T, T>(Tp[1].rowptr, Tp[1].col, wt<T>(Tp[1]), 1, L, L, t1, t2, T(1), T(0), P->stream);
-    launch_axis_pass<T, T>(Tp[2].rowptr, Tp[2].col, wt<T>(Tp[2]), 2, L, L, t2, out, alpha, beta, P->stream);
+                             (const T *)P->afc, rF, U, P->ex());
+    launch_patch_assemble<T>(P->d, P->opt.interior_patches_only, U, zF, P->ex());
+    launch_axis_pass<T, T>(Tp[0].rowptr, Tp[0].col, wt<T>(Tp[0]), 0, L, L, zF, t1, T(1), T(0), P->ex());
+    launch_axis_pass<T, T>(Tp[1].rowptr, Tp[1].col, wt<T>(Tp[1]), 1, L, L, t1, t2, T(1), T(0), P->ex());
+    launch_axis_pass<T, T>(Tp[2].rowptr, Tp[2].col, wt<T>(Tp[2]), 2, L, L, t2, out, alpha, beta, P->ex());
     VSR_HIP(hipGetLastError());
 }
 
@@ -178,7 +192,7 @@ void relax_apply(vsr_problem *P, const Tin *in, T *out, T alpha, T beta) {
 template <typename T, typename Tin>
 void coarse_apply(vsr_problem *P, const Tin *in, T *out, T alpha, T beta) {
     if (P->nc == 0) {
-        if (beta == T(0)) launch_fill<T>(P->n, out, T(0), P->stream);
+        if (beta == T(0)) launch_fill<T>(P->n, out, T(0), P->ex());
         return;
     }
     const int L[3] = {P->d.Lx, P->d.Ly, P->d.Lz};
@@ -186,13 +200,13 @@ void coarse_apply(vsr_problem *P, const Tin *in, T *out, T alpha, T beta) {
     const int d1[3] = {c[0], L[1], L[2]}, d2[3] = {c[0], c[1], L[2]}, d3[3] = {c[0], c[1], c[2]};
     T *c1 = (T *)P->c1, *c2 = (T *)P->c2, *c3 = (T *)P->c3, *c4 = (T *)P->c4;
     const Table *R = P->tab[2], *Pr = P->tab[3];
-    launch_axis_pass<Tin, T>(R[0].rowptr, R[0].col, wt<T>(R[0]), 0, L, d1, in, c1, T(1), T(0), P->stream);
-    launch_axis_pass<T, T>(R[1].rowptr, R[1].col, wt<T>(R[1]), 1, d1, d2, c1, c2, T(1), T(0), P->stream);
-    launch_axis_pass<T, T>(R[2].rowptr, R[2].col, wt<T>(R[2]), 2, d2, d3, c2, c3, T(1), T(0), P->stream);
-    launch_dense_gemv<T>(P->nc, (const T *)P->A0inv, c3, c4, T(1), T(0), P->stream);
-    launch_axis_pass<T, T>(Pr[2].rowptr, Pr[2].col, wt<T>(Pr[2]), 2, d3, d2, c4, c2, T(1), T(0), P->stream);
-    launch_axis_pass<T, T>(Pr[1].rowptr, Pr[1].col, wt<T>(Pr[1]), 1, d2, d1, c2, c1, T(1), T(0), P->stream);
-    launch_axis_pass<T, T>(Pr[0].rowptr, Pr[0].col, wt<T>(Pr[0]), 0, d1, L, c1, out, alpha, beta, P->stream);
+    launch_axis_pass<Tin, T>(R[0].rowptr, R[0].col, wt<T>(R[0]), 0, L, d1, in, c1, T(1), T(0), P->ex());
+    launch_axis_pass<T, T>(R[1].rowptr, R[1].col, wt<T>(R[1]), 1, d1, d2, c1, c2, T(1), T(0), P->ex());
+    launch_axis_pass<T, T>(R[2].rowptr, R[2].col, wt<T>(R[2]), 2, d2, d3, c2, c3, T(1), T(0), P->ex());
+    launch_dense_gemv<T>(P->nc, (const T *)P->A0inv, c3, c4, T(1), T(0), P->ex());
+    launch_axis_pass<T, T>(Pr[2].rowptr, Pr[2].col, wt<T>(Pr[2]), 2, d3, d2, c4, c2, T(1), T(0), P->ex());
+    launch_axis_pass<T, T>(Pr[1].rowptr, Pr[1].col, wt<T>(Pr[1]), 1, d2, d1, c2, c1, T(1), T(0), P->ex());
+    launch_axis_pass<T, T>(Pr[0].rowptr, Pr[0].col, wt<T>(Pr[0]), 0, d1, L, c1, out, alpha, beta, P->ex());
     VSR_HIP(hipGetLastError());
 }
 
@@ -212,13 +226,13 @@ void precondition(vsr_problem *P, const double *r, double *z, int mode) {
         // hybrid V(1,1): z1 = w S r; z2 = z1 + C (r - A z1); z = z2 + w S (r - A z2)
         relax_apply<T, double>(P, r, z1, w, T(0));
         op_apply<T>(P, z1, az);
-        launch_residual<T>(P->n, r, az, az, P->stream);
+        launch_residual<T>(P->n, r, az, az, P->ex());
         coarse_apply<T, T>(P, az, z1, T(1), T(1));
         op_apply<T>(P, z1, az);
-        launch_residual<T>(P->n, r, az, az, P->stream);
+        launch_residual<T>(P->n, r, az, az, P->ex());
         relax_apply<T, T>(P, az, z1, w, T(1));
     }
-    launch_axpby_to_double<T>(P->n, 1.0, z1, 0.0, z, P->stream);
+    launch_axpby_to_double<T>(P->n, 1.0, z1, 0.0, z, P->ex());
     VSR_HIP(hipGetLastError());
 }
 
@@ -234,9 +248,51 @@ double read_scalar(vsr_problem *P, int slot) {
 }
 
 double dot(vsr_problem *P, const double *x, const double *y) {
-    int nb = launch_dot_partial(P->n, x, y, P->partials, P->stream);
-    launch_finalize(nb, P->partials, P->scal, 0, P->stream);
+    int nb = launch_dot_partial(P->n, x, y, P->partials, P->ex());
+    launch_finalize(nb, P->partials, P->scal, 0, P->ex());
     return read_scalar(P, SC_TMP);
+}
+
+// ---- PCG (Hestenes-Stiefel) in pieces shared by the host-driven and the batched solves.
+// x = 0, r = b, RR = b.b
+void pcg_init(vsr_problem *P, const double *b, double *x) {
+    launch_fill<double>(P->n, x, 0.0, P->ex());
+    launch_cast<double, double>(P->n, b, P->vr, P->ex());
+    int nb = launch_dot_partial(P->n, b, b, P->partials, P->ex());
+    launch_finalize(nb, P->partials, P->scal, 4, P->ex());
+}
+
+// z = M r, RZ = r.z, p = z
+void pcg_first_direction(vsr_problem *P) {
+    precond(P, P->vr, P->vz, 0);
+    int nb = launch_dot_partial(P->n, P->vr, P->vz, P->partials, P->ex());
+    launch_finalize(nb, P->partials, P->scal, 3, P->ex());
+    launch_cast<double, double>(P->n, P->vz, P->vp, P->ex());
+}
+
+// q = A p, alpha = RZ / p.q, x += alpha p, r -= alpha q, RR = r.r; rr_mode 4 leaves the
+// stopping test to the host, 5 counts the update and takes the test on the device
+void pcg_update(vsr_problem *P, double *x, int rr_mode) {
+    op_apply<double>(P, P->vp, P->vq);
+    int nb = launch_dot_partial(P->n, P->vp, P->vq, P->partials, P->ex());
+    launch_finalize(nb, P->partials, P->scal, 1, P->ex());
+    nb = launch_pcg_xr(P->n, x, P->vr, P->vp, P->vq, P->scal, P->partials, P->ex());
+    launch_finalize(nb, P->partials, P->scal, rr_mode, P->ex());
+}
+
+// z = M r, beta = r.z / RZ, RZ = r.z, p = z + beta p
+void pcg_direction(vsr_problem *P) {
+    precond(P, P->vr, P->vz, 0);
+    int nb = launch_dot_partial(P->n, P->vr, P->vz, P->partials, P->ex());
+    launch_finalize(nb, P->partials, P->scal, 2, P->ex());
+    launch_pcg_p(P->n, P->vp, P->vz, P->scal, P->ex());
+}
+
+// ||b - A x||_2 in FP64 (ungated)
+double true_residual(vsr_problem *P, const double *b, const double *x) {
+    op_apply<double>(P, x, P->vq);
+    launch_residual<double>(P->n, b, P->vq, P->vt, P->ex());
+    return std::sqrt(std::max(0.0, dot(P, P->vt, P->vt)));
 }
 
 // splitmix64 (Steele, Lea & Flood 2014): output i of the stream seeded with `seed`
@@ -254,29 +310,29 @@ void estimate_damping(vsr_problem *P) {
     std::vector<double> h(P->n);
     for (int64_t i = 0; i < P->n; ++i) h[i] = (double)(splitmix64_at(P->opt.seed, (uint64_t)i) >> 11) * 0x1.0p-53 * 2.0 - 1.0;
     VSR_HIP(hipMemcpy(P->vr, h.data(), P->n * sizeof(double), hipMemcpyHostToDevice));
-    launch_fill<double>(P->n, P->vt, 0.0, P->stream);
+    launch_fill<double>(P->n, P->vt, 0.0, P->ex());
     precond(P, P->vr, P->vz, 1);
-    int nb = launch_dot_partial(P->n, P->vr, P->vz, P->partials, P->stream);
-    launch_finalize(nb, P->partials, P->scal, 3, P->stream);
+    int nb = launch_dot_partial(P->n, P->vr, P->vz, P->partials, P->ex());
+    launch_finalize(nb, P->partials, P->scal, 3, P->ex());
     double rz0 = read_scalar(P, SC_RZ);
-    launch_cast<double, double>(P->n, P->vz, P->vp, P->stream);
+    launch_cast<double, double>(P->n, P->vz, P->vp, P->ex());
     std::vector<double> alphas, betas;
     for (int j = 0; j < steps; ++j) {
         op_apply<double>(P, P->vp, P->vq);
-        nb = launch_dot_partial(P->n, P->vp, P->vq, P->partials, P->stream);
-        launch_finalize(nb, P->partials, P->scal, 1, P->stream);
-        nb = launch_pcg_xr(P->n, P->vt, P->vr, P->vp, P->vq, P->scal, P->partials, P->stream);
+        nb = launch_dot_partial(P->n, P->vp, P->vq, P->partials, P->ex());
+        launch_finalize(nb, P->partials, P->scal, 1, P->ex());
+        nb = launch_pcg_xr(P->n, P->vt, P->vr, P->vp, P->vq, P->scal, P->partials, P->ex());
         double alpha = read_scalar(P, SC_ALPHA);
         precond(P, P->vr, P->vz, 1);
-        nb = launch_dot_partial(P->n, P->vr, P->vz, P->partials, P->stream);
-        launch_finalize(nb, P->partials, P->scal, 2, P->stream);
+        nb = launch_dot_partial(P->n, P->vr, P->vz, P->partials, P->ex());
+        launch_finalize(nb, P->partials, P->scal, 2, P->ex());
         double beta = read_scalar(P, SC_BETA);
         double rz = read_scalar(P, SC_RZNEW);
         alphas.push_back(alpha);
         betas.push_back(beta);
         if (!(alpha > 0) || !std::isfinite(alpha)) throw Error(VSR_ENOCONV, "Lanczos breakdown");
         if (rz <= 1e-28 * rz0) break;
-        launch_pcg_p(P->n, P->vp, P->vz, P->scal, P->stream);
+        launch_pcg_p(P->n, P->vp, P->vz, P->scal, P->ex());
     }
     int k = (int)alphas.size();
     std::vector<double> dg(k), of(std::max(k - 1, 0));
@@ -287,6 +343,136 @@ void estimate_damping(vsr_problem *P) {
     tridiag_extremes(dg, of, P->lmin, P->lmax);
     const double a = 0.25;
     P->omega = 2.0 / ((1 + a) * P->lmax + (1 - a) * P->lmin);
+}
+
+// ---- autotuner: launch shapes per (GPU architecture, p, cycle precision, operator kind).
+std::mutex g_tune_mutex;
+std::map<std::string, Tuning> g_tune_cache;
+
+std::string tune_key(vsr_problem *P) {
+    int dev = 0;
+    VSR_HIP(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    VSR_HIP(hipGetDeviceProperties(&prop, dev));
+    std::string arch = prop.gcnArchName;
+    arch = arch.substr(0, arch.find(':'));
+    std::ostringstream k;
+    k << arch << " p=" << P->d.p << " prec=" << (P->fp32 ? "f32" : "f64") << " op=" << (P->cartesian ? "kron" : "general");
+    return k.str();
+}
+
+bool tune_from_file(const char *path, const std::string &key, Tuning &t) {
+    if (!path) return false;
+    std::ifstream f(path);
+    std::string line;
+    bool found = false;
+    while (std::getline(f, line)) {   // the last entry for a key wins
+        if (line.compare(0, key.size(), key) != 0 || line.size() <= key.size() || line[key.size()] != ' ') continue;
+        Tuning c;
+        if (std::sscanf(line.c_str() + key.size(), " cpw64=%d cpw32=%d axis_block=%d patch_unroll=%d", &c.op_cpw64,
+                        &c.op_cpw32, &c.axis_block, &c.patch_unroll) == 4) {
+            t = c;
+            found = true;
+        }
+    }
+    return found;
+}
+
+// Mean time of `reps` back-to-back runs of fn on the problem's stream, after one warm-up run.
+template <typename F>
+double time_ms(vsr_problem *P, F &&fn, int reps = 5) {
+    hipEvent_t a, b;
+    VSR_HIP(hipEventCreate(&a));
+    VSR_HIP(hipEventCreate(&b));
+    fn();
+    VSR_HIP(hipEventRecord(a, P->stream));
+    for (int r = 0; r < reps; ++r) fn();
+    VSR_HIP(hipEventRecord(b, P->stream));
+    VSR_HIP(hipEventSynchronize(b));
+    float ms = 0;
+    VSR_HIP(hipEventElapsedTime(&ms, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return ms / reps;
+}
+
+// Coordinate search over each shape with the others fixed; every candidate produces the
+// same values, so only time decides.
+void autotune(vsr_problem *P) {
+    const std::string key = tune_key(P);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mutex);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            P->tune = it->second;
+            return;
+        }
+    }
+    Tuning t;
+    if (tune_from_file(P->opt.tune_cache, key, t)) {
+        P->tune = t;
+        std::lock_guard<std::mutex> lk(g_tune_mutex);
+        g_tune_cache[key] = t;
+        return;
+    }
+    P->tune = Tuning{};
+    launch_fill<double>(P->n, P->vp, 1.0, P->ex());
+    auto pick = [&](int &field, std::initializer_list<int> cands, auto &&fn) {
+        double best = 1e300;
+        int arg = field;
+        for (int c : cands) {
+            field = c;
+            double ms = time_ms(P, fn);
+            if (ms < best) { best = ms; arg = c; }
+        }
+        field = arg;
+    };
+    const bool small = (P->d.p + 1) * (P->d.p + 1) <= 64;
+    if (P->cartesian && small) {
+        pick(P->tune.op_cpw64, {1, 2, 4}, [&] { op_apply<double>(P, P->vp, P->vq); });
+        if (P->fp32) {
+            launch_cast<double, float>(P->n, P->vp, (float *)P->z1, P->ex());
+            pick(P->tune.op_cpw32, {1, 2, 4}, [&] { op_apply<float>(P, (const float *)P->z1, (float *)P->az); });
+        }
+    }
+    const int L[3] = {P->d.Lx, P->d.Ly, P->d.Lz};
+    auto passes = [&](auto zero) {
+        using T = decltype(zero);
+        const Table *TT = P->tab[0], *Tp = P->tab[1];
+        T *a = (T *)P->t1, *b = (T *)P->t2;
+        for (int ax = 0; ax < 3; ++ax) {
+            launch_axis_pass<T, T>(TT[ax].rowptr, TT[ax].col, wt<T>(TT[ax]), ax, L, L, a, b, T(1), T(0), P->ex());
+            launch_axis_pass<T, T>(Tp[ax].rowptr, Tp[ax].col, wt<T>(Tp[ax]), ax, L, L, b, a, T(1), T(0), P->ex());
+        }
+    };
+    auto patch = [&](auto zero) {
+        using T = decltype(zero);
+        launch_patch_interior<T>(P->d, P->pa, P->n_int, P->verts, (const T *)P->fint, (const T *)P->mu_sur,
+                                 (const T *)P->lam, (const T *)P->afc, (const T *)P->rF, (T *)P->U, P->ex());
+    };
+    if (P->fp32) {
+        launch_fill<float>(P->n, (float *)P->t1, 1.f, P->ex());
+        launch_fill<float>(P->n, (float *)P->rF, 1.f, P->ex());
+        pick(P->tune.axis_block, {64, 128, 256, 512, 1024}, [&] { passes(0.f); });
+        if (P->n_int > 0) pick(P->tune.patch_unroll, {4, 8, 16}, [&] { patch(0.f); });
+    } else {
+        launch_fill<double>(P->n, (double *)P->t1, 1.0, P->ex());
+        launch_fill<double>(P->n, (double *)P->rF, 1.0, P->ex());
+        pick(P->tune.axis_block, {64, 128, 256, 512, 1024}, [&] { passes(0.0); });
+        if (P->n_int > 0) pick(P->tune.patch_unroll, {4, 8, 16}, [&] { patch(0.0); });
+    }
+    // the patch boxes of absent stars must read as zero in the assembly
+    const int64_t w3 = (int64_t)P->pa.w * P->pa.w * P->pa.w, nv = (int64_t)(P->d.nx + 1) * (P->d.ny + 1) * (P->d.nz + 1);
+    if (P->fp32) launch_fill<float>(nv * w3, (float *)P->U, 0.f, P->ex());
+    else launch_fill<double>(nv * w3, (double *)P->U, 0.0, P->ex());
+    VSR_HIP(hipStreamSynchronize(P->stream));
+    std::lock_guard<std::mutex> lk(g_tune_mutex);
+    g_tune_cache[key] = P->tune;
+    if (P->opt.tune_cache) {
+        std::ofstream f(P->opt.tune_cache, std::ios::app);
+        f << key << " cpw64=" << P->tune.op_cpw64 << " cpw32=" << P->tune.op_cpw32 << " axis_block=" << P->tune.axis_block
+          << " patch_unroll=" << P->tune.patch_unroll << "\n";
+    }
 }
 
 Table make_table(vsr_problem *P, const AxisTable &t) {
@@ -316,6 +502,69 @@ void upload_patch_data(vsr_problem *P, const PatchSet &S, const std::vector<doub
 }
 
 }  // namespace
+
+// Batched solves: members, the streams they are spread over and the recorded iteration.
+struct vsr_batch {
+    std::vector<vsr_problem *> members;
+    std::vector<int> stream_of;            // member -> index into streams
+    std::vector<hipStream_t> streams;
+    hipStream_t origin = nullptr;          // fork/join point and graph launch stream
+    std::vector<hipEvent_t> events;        // [0] fork, [1 + j] join of stream j
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    const double **scals = nullptr;        // device array of the members' scalar blocks
+    int *active = nullptr;                 // device counter of members still iterating
+    int *host_active = nullptr;            // pinned
+    bool eager = false;
+
+    ~vsr_batch() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        for (hipEvent_t e : events) (void)hipEventDestroy(e);
+        for (hipStream_t st : streams) (void)hipStreamDestroy(st);
+        if (origin) (void)hipStreamDestroy(origin);
+        if (scals) (void)hipFree(scals);
+        if (active) (void)hipFree(active);
+        if (host_active) (void)hipHostFree(host_active);
+        for (vsr_problem *m : members) delete m;
+    }
+
+    // Run fn(member) for every member on its stream, forked from and joined back to origin.
+    template <typename F>
+    void for_members(F &&fn) {
+        VSR_HIP(hipEventRecord(events[0], origin));
+        for (hipStream_t st : streams) VSR_HIP(hipStreamWaitEvent(st, events[0], 0));
+        for (size_t i = 0; i < members.size(); ++i) {
+            vsr_problem *P = members[i];
+            hipStream_t keep = P->stream;
+            P->stream = streams[stream_of[i]];
+            try {
+                fn(P);
+            } catch (...) {
+                P->stream = keep;
+                P->gate = nullptr;
+                throw;
+            }
+            P->stream = keep;
+        }
+        for (size_t j = 0; j < streams.size(); ++j) {
+            VSR_HIP(hipEventRecord(events[1 + j], streams[j]));
+            VSR_HIP(hipStreamWaitEvent(origin, events[1 + j], 0));
+        }
+    }
+
+    // One lockstep PCG iteration of every member, each gated by its own stop flag, then the
+    // count of members still active.
+    void iteration() {
+        for_members([](vsr_problem *P) {
+            P->gate = P->scal + SC_DONE;
+            pcg_update(P, P->vx, 5);
+            pcg_direction(P);
+            P->gate = nullptr;
+        });
+        launch_count_active((int)members.size(), scals, active, Exec{origin, nullptr, Tuning{}});
+    }
+};
 
 extern "C" {
 
@@ -450,8 +699,10 @@ vsr_status vsr_setup(const vsr_mesh *mesh, int32_t p, const vsr_coefficients *co
         P->scal = P->dalloc<double>(SC_N);
         P->partials = P->dalloc<double>(1024);
         VSR_HIP(hipHostMalloc((void **)&P->host_scal, sizeof(double) * SC_N, hipHostMallocDefault));
-        if (P->fp32) launch_fill<float>(nv * w3, (float *)P->U, 0.f, P->stream);
-        else launch_fill<double>(nv * w3, (double *)P->U, 0.0, P->stream);
+        if (P->fp32) launch_fill<float>(nv * w3, (float *)P->U, 0.f, P->ex());
+        else launch_fill<double>(nv * w3, (double *)P->U, 0.0, P->ex());
+        P->vx = P->dalloc<double>(P->n);
+        if (P->opt.autotune) autotune(P.get());
         // damping (Sec. 2.5)
         if (P->opt.omega > 0) {
             P->omega = P->opt.omega;
@@ -469,8 +720,8 @@ int64_t vsr_num_dofs(const vsr_problem *prob) { return prob ? prob->n : -1; }
 vsr_status vsr_load_vector(vsr_problem *P, const double *f, double *b) {
     return guarded([&] {
         if (!P || !f || !b) throw Error(VSR_EINVAL, "NULL argument");
-        launch_fill<double>(P->n, b, 0.0, P->stream);
-        launch_load_vector(P->d, P->IDq64, P->wdet, f, b, P->stream);
+        launch_fill<double>(P->n, b, 0.0, P->ex());
+        launch_load_vector(P->d, P->IDq64, P->wdet, f, b, P->ex());
         VSR_HIP(hipGetLastError());
     });
 }
@@ -497,51 +748,34 @@ vsr_status vsr_pcg_solve(vsr_problem *P, const double *b, double *x, double rtol
         if (!(rtol > 0)) throw Error(VSR_EINVAL, "rtol must be positive");
         double t0 = now_s();
         int maxit = P->opt.max_iterations > 0 ? P->opt.max_iterations : 1000;
-        int64_t n = P->n;
-        hipStream_t s = P->stream;
-        launch_fill<double>(n, x, 0.0, s);
-        launch_cast<double, double>(n, b, P->vr, s);
-        int nb = launch_dot_partial(n, b, b, P->partials, s);
-        launch_finalize(nb, P->partials, P->scal, 4, s);
+        pcg_init(P, b, x);
         double bb = read_scalar(P, SC_RR);
         if (!std::isfinite(bb)) throw Error(VSR_EINVAL, "non-finite right-hand side");
-        double bn = std::sqrt(bb), rn = bn;
+        double rr = bb;
         int it = 0;
-        bool conv = bn == 0.0;
+        bool conv = bb == 0.0;
         if (!conv) {
-            precond(P, P->vr, P->vz, 0);
-            nb = launch_dot_partial(n, P->vr, P->vz, P->partials, s);
-            launch_finalize(nb, P->partials, P->scal, 3, s);
-            launch_cast<double, double>(n, P->vz, P->vp, s);
+            pcg_first_direction(P);
             while (it < maxit) {
-                op_apply<double>(P, P->vp, P->vq);
-                nb = launch_dot_partial(n, P->vp, P->vq, P->partials, s);
-                launch_finalize(nb, P->partials, P->scal, 1, s);
-                nb = launch_pcg_xr(n, x, P->vr, P->vp, P->vq, P->scal, P->partials, s);
-                launch_finalize(nb, P->partials, P->scal, 4, s);
+                pcg_update(P, x, 4);
                 ++it;
-                double rr = read_scalar(P, SC_RR);
-                rn = std::sqrt(rr);
-                if (!std::isfinite(rn)) break;
-                if (rn <= rtol * bn) {
+                rr = read_scalar(P, SC_RR);
+                if (!std::isfinite(rr)) break;
+                // ||r||_2 <= rtol ||b||_2, tested on squares as the batched solve does on the device
+                if (rr <= rtol * rtol * bb) {
                     conv = true;
                     break;
                 }
-                precond(P, P->vr, P->vz, 0);
-                nb = launch_dot_partial(n, P->vr, P->vz, P->partials, s);
-                launch_finalize(nb, P->partials, P->scal, 2, s);
-                launch_pcg_p(n, P->vp, P->vz, P->scal, s);
+                pcg_direction(P);
             }
         }
-        VSR_HIP(hipStreamSynchronize(s));
+        VSR_HIP(hipStreamSynchronize(P->stream));
         double t1 = now_s();
-        // true residual in FP64
-        op_apply<double>(P, x, P->vq);
-        launch_residual<double>(n, b, P->vq, P->vt, s);
-        double tr = std::sqrt(std::max(0.0, dot(P, P->vt, P->vt)));
+        double tr = true_residual(P, b, x);
+        double bn = std::sqrt(bb);
         loc.iterations = it;
         loc.converged = conv ? 1 : 0;
-        loc.rel_residual = bn > 0 ? rn / bn : 0.0;
+        loc.rel_residual = bn > 0 ? std::sqrt(rr) / bn : 0.0;
         loc.true_rel_residual = bn > 0 ? tr / bn : 0.0;
         loc.omega = P->omega;
         loc.lambda_min = P->lmin;
@@ -596,6 +830,165 @@ vsr_status vsr_factor_info(const vsr_problem *P, int64_t *num_patches, int64_t *
 }
 
 void vsr_destroy(vsr_problem *P) { delete P; }
+
+vsr_status vsr_get_tuning(const vsr_problem *P, int32_t shapes[4]) {
+    return guarded([&] {
+        if (!P || !shapes) throw Error(VSR_EINVAL, "NULL argument");
+        shapes[0] = P->tune.op_cpw64;
+        shapes[1] = P->tune.op_cpw32;
+        shapes[2] = P->tune.axis_block;
+        shapes[3] = P->tune.patch_unroll;
+    });
+}
+
+vsr_status vsr_set_tuning(vsr_problem *P, const int32_t shapes[4]) {
+    return guarded([&] {
+        if (!P || !shapes) throw Error(VSR_EINVAL, "NULL argument");
+        auto cpw_ok = [](int c) { return c == 1 || c == 2 || c == 4; };
+        if (!cpw_ok(shapes[0]) || !cpw_ok(shapes[1])) throw Error(VSR_EINVAL, "operator cells per workgroup must be 1, 2 or 4");
+        if (shapes[2] < 64 || shapes[2] > 1024 || shapes[2] % 64) throw Error(VSR_EINVAL, "block must be a multiple of 64 in [64, 1024]");
+        if (shapes[3] != 4 && shapes[3] != 8 && shapes[3] != 16) throw Error(VSR_EINVAL, "unroll must be 4, 8 or 16");
+        VSR_HIP(hipStreamSynchronize(P->stream));
+        P->tune = Tuning{shapes[0], shapes[1], shapes[2], shapes[3]};
+    });
+}
+
+vsr_status vsr_setup_batch(int32_t count, const vsr_mesh *meshes, const int32_t *p, const vsr_coefficients *coefs,
+                           const vsr_options *opt, vsr_batch **out) {
+    return guarded([&] {
+        if (!out) throw Error(VSR_EINVAL, "NULL argument");
+        *out = nullptr;
+        if (count < 1 || !meshes || !p) throw Error(VSR_EINVAL, "a batch needs count >= 1, meshes and degrees");
+        vsr_options o;
+        if (opt) o = *opt;
+        else vsr_default_options(&o);
+        if (o.batch_streams < 0 || o.batch_streams > 16) throw Error(VSR_EINVAL, "batch_streams must be in [0, 16]");
+        auto B = std::make_unique<vsr_batch>();
+        for (int32_t i = 0; i < count; ++i) {
+            vsr_problem *P = nullptr;
+            vsr_status st = vsr_setup(&meshes[i], p[i], coefs ? &coefs[i] : nullptr, &o, &P);
+            if (st != VSR_OK) throw Error(st, "member " + std::to_string(i) + ": " + vsr::g_last_error_text);
+            B->members.push_back(P);
+        }
+        const int ns = std::min<int>(o.batch_streams > 0 ? o.batch_streams : 4, count);
+        B->streams.resize(ns, nullptr);
+        for (auto &st : B->streams) VSR_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        VSR_HIP(hipStreamCreateWithFlags(&B->origin, hipStreamNonBlocking));
+        B->events.resize(1 + ns, nullptr);
+        for (auto &e : B->events) VSR_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        // largest member first onto the least loaded stream
+        std::vector<int> order(count);
+        for (int i = 0; i < count; ++i) order[i] = i;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return B->members[a]->n > B->members[b]->n; });
+        std::vector<double> load(ns, 0.0);
+        B->stream_of.assign(count, 0);
+        for (int i : order) {
+            int j = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            B->stream_of[i] = j;
+            load[j] += (double)B->members[i]->n;
+        }
+        std::vector<const double *> sc(count);
+        for (int i = 0; i < count; ++i) sc[i] = B->members[i]->scal;
+        VSR_HIP(hipMalloc((void **)&B->scals, sizeof(double *) * count));
+        VSR_HIP(hipMemcpy(B->scals, sc.data(), sizeof(double *) * count, hipMemcpyHostToDevice));
+        VSR_HIP(hipMalloc((void **)&B->active, sizeof(int)));
+        VSR_HIP(hipHostMalloc((void **)&B->host_active, sizeof(int), hipHostMallocDefault));
+        B->eager = o.batch_eager != 0;
+        *out = B.release();
+    });
+}
+
+int32_t vsr_batch_size(const vsr_batch *B) { return B ? (int32_t)B->members.size() : -1; }
+
+vsr_problem *vsr_batch_member(vsr_batch *B, int32_t i) {
+    if (!B || i < 0 || i >= (int32_t)B->members.size()) return nullptr;
+    return B->members[i];
+}
+
+vsr_status vsr_pcg_solve_batch(vsr_batch *B, const double *const *b_dev, double *const *x_dev, double rtol,
+                               vsr_solve_info *infos) {
+    return guarded([&] {
+        if (!B || !b_dev || !x_dev) throw Error(VSR_EINVAL, "NULL argument");
+        if (!(rtol > 0)) throw Error(VSR_EINVAL, "rtol must be positive");
+        const int count = (int)B->members.size();
+        for (int i = 0; i < count; ++i)
+            if (!b_dev[i] || !x_dev[i]) throw Error(VSR_EINVAL, "NULL vector of member " + std::to_string(i));
+        // inputs written on the members' own streams are complete before the batch starts
+        for (vsr_problem *P : B->members) VSR_HIP(hipStreamSynchronize(P->stream));
+        double t0 = now_s();
+        int maxit = 0;
+        std::vector<int> idx(count);
+        for (int i = 0; i < count; ++i) idx[i] = i;
+        for (vsr_problem *P : B->members) maxit = std::max(maxit, P->opt.max_iterations > 0 ? P->opt.max_iterations : 1000);
+        // start: x = 0, r = b, stopping data, z = M r, p = z (gated: a zero b stops at once)
+        {
+            int i = 0;
+            B->for_members([&](vsr_problem *P) {
+                pcg_init(P, b_dev[i], P->vx);
+                launch_pcg_start(P->scal, rtol, P->opt.max_iterations > 0 ? P->opt.max_iterations : 1000, P->ex());
+                P->gate = P->scal + SC_DONE;
+                pcg_first_direction(P);
+                P->gate = nullptr;
+                ++i;
+            });
+        }
+        if (!B->eager && !B->exec) {
+            for (vsr_problem *P : B->members) P->capturing = true;
+            VSR_HIP(hipStreamBeginCapture(B->origin, hipStreamCaptureModeThreadLocal));
+            try {
+                B->iteration();
+            } catch (...) {
+                hipGraph_t g = nullptr;
+                (void)hipStreamEndCapture(B->origin, &g);
+                if (g) (void)hipGraphDestroy(g);
+                for (vsr_problem *P : B->members) P->capturing = false;
+                throw;
+            }
+            VSR_HIP(hipStreamEndCapture(B->origin, &B->graph));
+            for (vsr_problem *P : B->members) P->capturing = false;
+            VSR_HIP(hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0));
+        }
+        int replays = 0;
+        for (;;) {
+            if (B->eager) B->iteration();
+            else VSR_HIP(hipGraphLaunch(B->exec, B->origin));
+            ++replays;
+            VSR_HIP(hipMemcpyAsync(B->host_active, B->active, sizeof(int), hipMemcpyDeviceToHost, B->origin));
+            VSR_HIP(hipStreamSynchronize(B->origin));
+            if (*B->host_active == 0 || replays > maxit) break;
+        }
+        double t1 = now_s();
+        bool all = true;
+        std::string failed;
+        for (int i = 0; i < count; ++i) {
+            vsr_problem *P = B->members[i];
+            launch_cast<double, double>(P->n, P->vx, x_dev[i], P->ex());
+            VSR_HIP(hipMemcpyAsync(P->host_scal, P->scal, sizeof(double) * SC_N, hipMemcpyDeviceToHost, P->stream));
+            VSR_HIP(hipStreamSynchronize(P->stream));
+            const double it = P->host_scal[SC_IT], status = P->host_scal[SC_STATUS];
+            const double bb = P->host_scal[SC_BB], rr = P->host_scal[SC_RR];
+            const double tr = true_residual(P, b_dev[i], x_dev[i]);
+            vsr_solve_info loc{};
+            loc.iterations = (int32_t)it;
+            loc.converged = status == 1.0 ? 1 : 0;
+            loc.rel_residual = bb > 0 ? std::sqrt(rr / bb) : 0.0;
+            loc.true_rel_residual = bb > 0 ? tr / std::sqrt(bb) : 0.0;
+            loc.omega = P->omega;
+            loc.lambda_min = P->lmin;
+            loc.lambda_max = P->lmax;
+            loc.setup_seconds = P->setup_seconds;
+            loc.solve_seconds = t1 - t0;
+            if (infos) infos[i] = loc;
+            if (status != 1.0) {
+                all = false;
+                failed += (failed.empty() ? "" : ", ") + std::to_string(i);
+            }
+        }
+        if (!all) throw Error(VSR_ENOCONV, "batched PCG: members not converged: " + failed);
+    });
+}
+
+void vsr_destroy_batch(vsr_batch *B) { delete B; }
 
 const char *vsr_last_error(void) { return vsr::g_last_error_text.c_str(); }
 

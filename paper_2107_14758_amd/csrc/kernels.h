@@ -1,5 +1,4 @@
-// Launch wrappers of the HIP kernels (gfx950).  All pointers are device pointers;
-// every launch goes to `stream`.
+// Launch wrappers of the HIP kernels (gfx950).  All pointers are device pointers.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -14,19 +13,36 @@ struct Dims {
     int Lx, Ly, Lz;       // free lattice extents (p*n - 1)
 };
 
+// Launch shapes chosen per (degree, precision) by the autotuner; none changes the
+// arithmetic of any output value.
+struct Tuning {
+    int op_cpw64 = 1;       // cells per workgroup of the Cartesian operator kernel, FP64
+    int op_cpw32 = 1;       // same, FP32 (both 1, 2 or 4; above 1 only for p <= 7)
+    int axis_block = 256;   // threads per block of the 1D lattice passes (64..1024)
+    int patch_unroll = 8;   // column loads in flight per thread in the patch panels (4, 8, 16)
+};
+
+// Where a launch goes: its stream, an optional gate (a device flag; when it is nonzero
+// at kernel start every workgroup returns at once) and the launch shapes.
+struct Exec {
+    hipStream_t s = nullptr;
+    const double *gate = nullptr;
+    Tuning t{};
+};
+
 // y += A x (y must be zeroed by the caller); Cartesian (separable) or general metric.
 template <typename T>
-void launch_op_kron(const Dims &d, const T *AB1d, const T *mu, const T *x, T *y, hipStream_t s);
+void launch_op_kron(const Dims &d, const T *AB1d, const T *mu, const T *x, T *y, const Exec &e);
 template <typename T>
-void launch_op_general(const Dims &d, const T *IDq, const T *Gw, const T *x, T *y, hipStream_t s);
+void launch_op_general(const Dims &d, const T *IDq, const T *Gw, const T *x, T *y, const Exec &e);
 // b += sum_K R_K^T (I x I x I)^T (wdet .* f)
 void launch_load_vector(const Dims &d, const double *IDq, const double *wdet, const double *f, double *b,
-                        hipStream_t s);
+                        const Exec &e);
 
 // One 1D lattice pass: out = alpha * (table along `axis`) in + beta * out.
 template <typename Tin, typename Tout>
 void launch_axis_pass(const int *rowptr, const int *col, const Tout *w, int axis, const int in_dims[3],
-                      const int out_dims[3], const Tin *in, Tout *out, Tout alpha, Tout beta, hipStream_t s);
+                      const int out_dims[3], const Tin *in, Tout *out, Tout alpha, Tout beta, const Exec &e);
 
 struct PatchArgs {
     int m, w;
@@ -36,38 +52,52 @@ struct PatchArgs {
 
 template <typename T>
 void launch_patch_interior(const Dims &d, const PatchArgs &a, int npatch, const int *verts, const T *factor,
-                           const T *mu, const T *lam, const T *afc, const T *rF, T *U, hipStream_t s);
+                           const T *mu, const T *lam, const T *afc, const T *rF, T *U, const Exec &e);
 template <typename T>
 void launch_patch_boundary(const Dims &d, int npatch, const int *desc, const int64_t *off, const T *factor,
-                           const T *mu, const T *lam, const T *afc, const T *rF, T *U, hipStream_t s);
+                           const T *mu, const T *lam, const T *afc, const T *rF, T *U, const Exec &e);
 template <typename T>
-void launch_patch_assemble(const Dims &d, int interior_only, const T *U, T *zF, hipStream_t s);
+void launch_patch_assemble(const Dims &d, int interior_only, const T *U, T *zF, const Exec &e);
 
 // y = alpha * A x + beta * y for a dense row-major n x n matrix.
 template <typename T>
-void launch_dense_gemv(int n, const T *A, const T *x, T *y, T alpha, T beta, hipStream_t s);
+void launch_dense_gemv(int n, const T *A, const T *x, T *y, T alpha, T beta, const Exec &e);
 
 // ---- vector kernels (double unless noted)
 template <typename Tin, typename Tout>
-void launch_cast(int64_t n, const Tin *x, Tout *y, hipStream_t s);
+void launch_cast(int64_t n, const Tin *x, Tout *y, const Exec &e);
 template <typename T>
-void launch_fill(int64_t n, T *x, T v, hipStream_t s);
+void launch_fill(int64_t n, T *x, T v, const Exec &e);
 // partial sums of x.y into partials[nblocks]; returns nblocks used
-int launch_dot_partial(int64_t n, const double *x, const double *y, double *partials, hipStream_t s);
-// scal[slot] = sum(partials); mode: 0 plain, 1 alpha = scal[RZ]/sum, 2 beta = sum/scal[RZ] and RZ = sum
-void launch_finalize(int nb, const double *partials, double *scal, int mode, hipStream_t s);
+int launch_dot_partial(int64_t n, const double *x, const double *y, double *partials, const Exec &e);
+// scal[slot] = sum(partials); mode: 0 plain, 1 alpha = scal[RZ]/sum, 2 beta = sum/scal[RZ] and RZ = sum,
+// 3 RZ = sum, 4 RR = sum, 5 RR = sum and the stopping test of a device-driven PCG (see SC_DONE)
+void launch_finalize(int nb, const double *partials, double *scal, int mode, const Exec &e);
+// Start of a device-driven PCG after RR = b.b: BB = RR, IT = 0, stopping data, DONE when b = 0
+// or b is not finite.  Not gated.
+void launch_pcg_start(double *scal, double rtol, int max_iterations, const Exec &e);
 // x += alpha p ; r -= alpha q ; partial r.r
 int launch_pcg_xr(int64_t n, double *x, double *r, const double *p, const double *q, const double *scal,
-                  double *partials, hipStream_t s);
+                  double *partials, const Exec &e);
 // p = z + beta p
-void launch_pcg_p(int64_t n, double *p, const double *z, const double *scal, hipStream_t s);
+void launch_pcg_p(int64_t n, double *p, const double *z, const double *scal, const Exec &e);
 // out(T) = r(double) - Az(T) ; out may alias Az
 template <typename T>
-void launch_residual(int64_t n, const double *r, const T *Az, T *out, hipStream_t s);
+void launch_residual(int64_t n, const double *r, const T *Az, T *out, const Exec &e);
 // y(double) = a * x(T) + b * y
 template <typename T>
-void launch_axpby_to_double(int64_t n, double a, const T *x, double b, double *y, hipStream_t s);
+void launch_axpby_to_double(int64_t n, double a, const T *x, double b, double *y, const Exec &e);
+// *active = number of problems whose scal[SC_DONE] is zero (scals: device array of count pointers).
+// Not gated.
+void launch_count_active(int count, const double *const *scals, int *active, const Exec &e);
 
-enum { SC_PQ = 0, SC_RZ = 1, SC_RR = 2, SC_ALPHA = 3, SC_BETA = 4, SC_RZNEW = 5, SC_TMP = 6, SC_N = 8 };
+// Device scalars of one PCG.  A device-driven PCG (batched solves) keeps its stopping state
+// here: DONE is nonzero once the member stops; STATUS 1 converged, 2 non-finite residual,
+// 3 iteration cap; IT counts x updates.
+enum {
+    SC_PQ = 0, SC_RZ = 1, SC_RR = 2, SC_ALPHA = 3, SC_BETA = 4, SC_RZNEW = 5, SC_TMP = 6,
+    SC_DONE = 8, SC_BB = 9, SC_RTOL2 = 10, SC_IT = 11, SC_MAXIT = 12, SC_STATUS = 13,
+    SC_N = 16
+};
 
 }  // namespace vsr

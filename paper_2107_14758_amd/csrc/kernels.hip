@@ -1,86 +1,70 @@
-// HIP kernels for gfx950 (CDNA4, wave64).
+// HIP kernels for gfx950 (CDNA4, wave64): operator, load vector, lattice passes, patch
+// assembly, dense coarse solve and the PCG vector kernels.  The patch solves live in
+// patch_kernels.h.
 //
-// Method references: Brubeck & Farrell, "A scalable and robust vertex-star
-// relaxation for high-order FEM", Sec. 2.
-#include <hip/hip_runtime.h>
+// Method references: Brubeck & Farrell, "A scalable and robust vertex-star relaxation for
+// high-order FEM", Sec. 2.
+#include "device_common.h"
 
-#include <algorithm>
 #include <stdexcept>
-
-#include "kernels.h"
-#include "vsr_internal.h"
 
 namespace vsr {
 
 namespace {
-
-constexpr int QOF(int P) { return (3 * (P + 1) + 1) / 2; }
-
-__device__ __forceinline__ bool is_free(const Dims &d, int K, int J, int I) {
-    return K >= 1 && K <= d.Lz && J >= 1 && J <= d.Ly && I >= 1 && I <= d.Lx;
-}
-__device__ __forceinline__ int64_t free_index(const Dims &d, int K, int J, int I) {
-    return ((int64_t)(K - 1) * d.Ly + (J - 1)) * d.Lx + (I - 1);
-}
-
-template <typename T>
-__device__ __forceinline__ void atomic_add_global(T *p, T v) {
-    unsafeAtomicAdd(p, v);
-}
-
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
+using namespace dev;
 
 // ====================================================================== operator
 // Separable (Cartesian) cell operator, eq. (kron) of Sec. 2.2:
 // A^K = mu1 B x B x A + mu2 B x A x B + mu3 A x B x B, evaluated per z-slab in LDS with
 // the z contraction done per (j, i) column in registers.
-template <typename T, int P>
-__global__ void __launch_bounds__(256) k_op_kron(Dims d, const T *__restrict__ AB1d, const T *__restrict__ mu,
-                                                 const T *__restrict__ x, T *__restrict__ y) {
+template <typename T, int P, int CPW>
+__global__ void __launch_bounds__(256) k_op_kron(const double *__restrict__ gate, Dims d, const T *__restrict__ AB1d,
+                                                 const T *__restrict__ mu, const T *__restrict__ x, T *__restrict__ y) {
+    if (gated(gate)) return;
     constexpr int N1 = P + 1, N2 = N1 * N1;
-    __shared__ T sA[N2], sB[N2], xs[N2], as[N2], bs[N2];
+    __shared__ T sA[N2], sB[N2], xs[CPW][N2], as[CPW][N2], bs[CPW][N2];
     const int tid = threadIdx.x;
     for (int t = tid; t < N2; t += blockDim.x) {
         sA[t] = AB1d[t];
         sB[t] = AB1d[N2 + t];
     }
-    const int64_t e = blockIdx.x;
-    const int ex = (int)(e % d.nx), ey = (int)((e / d.nx) % d.ny), ez = (int)(e / ((int64_t)d.nx * d.ny));
-    const T m0 = mu[3 * e], m1 = mu[3 * e + 1], m2 = mu[3 * e + 2];
-    const bool active = tid < N2;
-    const int j = tid / N1, i = tid % N1;
+    // CPW cells per workgroup, N2 threads each (thread (j, i) of its cell owns one z-column)
+    const int sub = tid / N2, lt = tid - sub * N2;
+    const int64_t ncell = (int64_t)d.nx * d.ny * d.nz;
+    const int64_t e = (int64_t)blockIdx.x * CPW + sub;
+    const bool active = sub < CPW && e < ncell;
+    const int64_t ec = active ? e : 0;
+    const int ex = (int)(ec % d.nx), ey = (int)((ec / d.nx) % d.ny), ez = (int)(ec / ((int64_t)d.nx * d.ny));
+    const T m0 = active ? mu[3 * ec] : T(0), m1 = active ? mu[3 * ec + 1] : T(0), m2 = active ? mu[3 * ec + 2] : T(0);
+    const int j = lt / N1, i = lt % N1;
+    const int sb = active ? sub : 0;
     T wv[N1], sv[N1];
 #pragma unroll
     for (int k = 0; k < N1; ++k) {
         __syncthreads();
         if (active) {
             int K = P * ez + k, J = P * ey + j, I = P * ex + i;
-            xs[tid] = is_free(d, K, J, I) ? x[free_index(d, K, J, I)] : T(0);
+            xs[sb][lt] = is_free(d, K, J, I) ? x[free_index(d, K, J, I)] : T(0);
         }
         __syncthreads();
         if (active) {
             T a = 0, b = 0;
 #pragma unroll
             for (int ii = 0; ii < N1; ++ii) {
-                a += sA[i * N1 + ii] * xs[j * N1 + ii];
-                b += sB[i * N1 + ii] * xs[j * N1 + ii];
+                a += sA[i * N1 + ii] * xs[sb][j * N1 + ii];
+                b += sB[i * N1 + ii] * xs[sb][j * N1 + ii];
             }
-            as[tid] = a;
-            bs[tid] = b;
+            as[sb][lt] = a;
+            bs[sb][lt] = b;
         }
         __syncthreads();
         if (active) {
             T c1 = 0, c2 = 0, c3 = 0;
 #pragma unroll
             for (int jj = 0; jj < N1; ++jj) {
-                c1 += sB[j * N1 + jj] * as[jj * N1 + i];
-                c2 += sA[j * N1 + jj] * bs[jj * N1 + i];
-                c3 += sB[j * N1 + jj] * bs[jj * N1 + i];
+                c1 += sB[j * N1 + jj] * as[sb][jj * N1 + i];
+                c2 += sA[j * N1 + jj] * bs[sb][jj * N1 + i];
+                c3 += sB[j * N1 + jj] * bs[sb][jj * N1 + i];
             }
             wv[k] = m0 * c1 + m1 * c2;
             sv[k] = m2 * c3;
@@ -101,8 +85,9 @@ __global__ void __launch_bounds__(256) k_op_kron(Dims d, const T *__restrict__ A
 // (Sec. 2.1, 2.7).  Thread (b, a) owns one z-column of quadrature points; the x and y
 // contractions run per z-slab through LDS, the z contraction and the metric in registers.
 template <typename T, int P>
-__global__ void __launch_bounds__(1024) k_op_general(Dims d, const T *__restrict__ IDq, const T *__restrict__ Gw,
+__global__ void __launch_bounds__(1024) k_op_general(const double *__restrict__ gate, Dims d, const T *__restrict__ IDq, const T *__restrict__ Gw,
                                                      const T *__restrict__ x, T *__restrict__ y) {
+    if (gated(gate)) return;
     constexpr int N1 = P + 1, Q = QOF(P), Q2 = Q * Q, Q3 = Q2 * Q;
     __shared__ T sI[Q * N1], sD[Q * N1], xs[N1 * N1], X1[N1 * Q], DX1[N1 * Q], S0[Q2], S1[Q2], S2[Q2];
     const int tid = threadIdx.x, nt = blockDim.x;
@@ -208,8 +193,9 @@ __global__ void __launch_bounds__(1024) k_op_general(Dims d, const T *__restrict
 
 // Load vector (Sec. 2.1): b += sum_K R_K^T (I x I x I)^T (w |det DF| f).
 template <int P>
-__global__ void __launch_bounds__(1024) k_load_vector(Dims d, const double *__restrict__ IDq, const double *__restrict__ wdet,
+__global__ void __launch_bounds__(1024) k_load_vector(const double *__restrict__ gate, Dims d, const double *__restrict__ IDq, const double *__restrict__ wdet,
                                                       const double *__restrict__ f, double *__restrict__ bvec) {
+    if (gated(gate)) return;
     constexpr int N1 = P + 1, Q = QOF(P), Q2 = Q * Q, Q3 = Q2 * Q;
     __shared__ double sI[Q * N1], X1[N1 * Q], S0[Q2];
     const int tid = threadIdx.x, nt = blockDim.x;
@@ -255,9 +241,10 @@ __global__ void __launch_bounds__(1024) k_load_vector(Dims d, const double *__re
 // out = alpha * M_axis in + beta * out, with M given by a CSR table over output positions
 // along one axis (the GLL<->FDM basis change of Sec. 2.4 and the Q1 transfers of Sec. 2.5).
 template <typename Tin, typename Tout>
-__global__ void k_axis_pass(const int *__restrict__ rowptr, const int *__restrict__ col, const Tout *__restrict__ w,
+__global__ void k_axis_pass(const double *__restrict__ gate, const int *__restrict__ rowptr, const int *__restrict__ col, const Tout *__restrict__ w,
                             int axis, int ix, int iy, int iz, int ox, int oy, int oz, const Tin *__restrict__ in,
                             Tout *__restrict__ out, Tout alpha, Tout beta) {
+    if (gated(gate)) return;
     const int64_t total = (int64_t)ox * oy * oz;
     for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
          idx += (int64_t)gridDim.x * blockDim.x) {
@@ -275,555 +262,11 @@ __global__ void k_axis_pass(const int *__restrict__ rowptr, const int *__restric
     }
 }
 
-// ====================================================================== patches
-// Box coordinates of a vertex star run over [0, 2m] per axis; the central plane is at m.
-// A box position pos maps to the free lattice index p (v - 1) + pos.
-
-__device__ __forceinline__ int la_(int a, int m) { return a < m ? a : a - 1; }
-__device__ __forceinline__ int inv_la_(int c, int m) { return c < m ? c : c + 1; }
-
-// interface index of the interior-class ordering (leaves, level-1 separators, top plane)
-__device__ __forceinline__ int iface_interior(int ax, int ay, int az, int m, int w, int nl, int ns) {
-    if (az == m) return nl + ns + ay * w + ax;
-    if (ax == m) return nl + la_(az, m) * w + ay;
-    if (ay == m) return la_(az, m) * 2 * m + la_(ax, m);
-    return -1;
-}
-
-// Per-patch coefficients staged in LDS: the star's cell scalings mu[cz][cy][cx][3]
-// (zero for absent cells), the interior eigenvalues lambda_1..m and the couplings
-// A_F[t, vertex] of interior mode t to the vertex on the star's central plane
-// (afc[0][.] for the cell below the plane, afc[1][.] above).
-template <typename T, int M>
-struct PatchCtx {
-    Dims d;
-    int vx, vy, vz;
-    const T *rF;
-    const T *mu, *lam, *afc;   // LDS
-    __device__ int64_t gidx(int ax, int ay, int az) const {
-        return ((int64_t)(P_() * (vz - 1) + az) * d.Ly + (P_() * (vy - 1) + ay)) * d.Lx + (P_() * (vx - 1) + ax);
-    }
-    __device__ static constexpr int P_() { return M + 1; }
-    __device__ const T *cmu(const int c[3]) const { return mu + 3 * ((c[2] * 2 + c[1]) * 2 + c[0]); }
-    // r_F at a face DOF minus the condensed interior lines of its two cells along axis dd:
-    // g = r_G - A_GI A_II^{-1} r_I (Sec. 2.6), A_II = mu . lambda, A_GI = mu_dd A_F[interior, vertex].
-    __device__ T condensed(const int pos[3], int dd) const {
-        T g = rF[gidx(pos[0], pos[1], pos[2])];
-        int c[3], l[3];
-        for (int a = 0; a < 3; ++a) {
-            c[a] = pos[a] > M;
-            l[a] = c[a] ? pos[a] - M : pos[a] + 1;
-        }
-        T acc = 0;
-#pragma unroll
-        for (int cd = 0; cd < 2; ++cd) {
-            c[dd] = cd;
-            const T *mk = cmu(c);
-            T base = 0;
-            for (int a = 0; a < 3; ++a)
-                if (a != dd) base += mk[a] * lam[l[a] - 1];
-            const T mdd = mk[dd];
-            int q[3] = {pos[0], pos[1], pos[2]};
-            T rv[M];
-#pragma unroll
-            for (int t = 1; t <= M; ++t) {
-                q[dd] = cd == 0 ? t - 1 : M + t;
-                rv[t - 1] = rF[gidx(q[0], q[1], q[2])];
-            }
-#pragma unroll
-            for (int t = 1; t <= M; ++t) acc += mdd * afc[cd * M + t - 1] * rv[t - 1] / (base + mdd * lam[t - 1]);
-        }
-        return g - acc;
-    }
-    // u_I = A_II^{-1}(r_I - A_IG u_G) at an interior DOF; face(a) gives the interface value
-    template <typename F>
-    __device__ T back_interior(const int pos[3], const bool full[3], F face) const {
-        int c[3], l[3];
-        for (int a = 0; a < 3; ++a) {
-            c[a] = pos[a] > M;
-            l[a] = c[a] ? pos[a] - M : pos[a] + 1;
-        }
-        const T *mk = cmu(c);
-        T D = mk[0] * lam[l[0] - 1] + mk[1] * lam[l[1] - 1] + mk[2] * lam[l[2] - 1];
-        T u = rF[gidx(pos[0], pos[1], pos[2])];
-        for (int a = 0; a < 3; ++a)
-            if (full[a]) u -= mk[a] * afc[c[a] * M + l[a] - 1] * face(a);
-        return u / D;
-    }
-};
-
-template <typename T, int M>
-__device__ void stage_coefficients(const Dims &d, int vx, int vy, int vz, const int kind[3], const T *__restrict__ mu,
-                                   const T *__restrict__ lam, const T *__restrict__ afc, T *smu, T *slam, T *safc) {
-    const int tid = threadIdx.x;
-    if (tid < 24) {
-        int comp = tid % 3, cell = tid / 3, cx = cell & 1, cy = (cell >> 1) & 1, cz = cell >> 2;
-        int cc[3] = {cx, cy, cz};
-        bool ok = true;
-        for (int a = 0; a < 3; ++a)
-            if (kind[a] == AX_LOW ? cc[a] == 0 : (kind[a] == AX_HIGH ? cc[a] == 1 : false)) ok = false;
-        int ex = vx - 1 + cx, ey = vy - 1 + cy, ez = vz - 1 + cz;
-        smu[tid] = ok ? mu[3 * ((int64_t)ex + d.nx * ((int64_t)ey + d.ny * (int64_t)ez)) + comp] : T(0);
-    }
-    for (int t = tid; t < M; t += blockDim.x) slam[t] = lam[t];
-    for (int t = tid; t < 2 * M; t += blockDim.x) safc[t] = afc[t];
-}
-
-// Value of lane `l` (uniform) broadcast to the wavefront through the scalar unit.
-template <typename T>
-__device__ __forceinline__ T bcast(T v, int l);
-template <>
-__device__ __forceinline__ float bcast<float>(float v, int l) {
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
-}
-template <>
-__device__ __forceinline__ double bcast<double>(double v, int l) {
-    int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
-    int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
-    return __hiloint2double(hi, lo);
-}
-
-// Dense lower-triangular solves by one wavefront (n <= MAXW <= 64), column-major L with
-// inverse diagonal.  Forward: lane i holds row i of L; each solved value is broadcast
-// and eliminated from the rows below.  Backward (L^T u = y): lane i holds column i of L
-// and the solved u_k is eliminated from the rows above.
-template <typename T, int MAXW>
-__device__ __forceinline__ void wave_load_rows(const T *__restrict__ L, int ld, int n, int lane, T (&row)[MAXW]) {
-#pragma unroll
-    for (int k = 0; k < MAXW; ++k) row[k] = (k < n && lane < n) ? L[(int64_t)k * ld + lane] : T(0);
-}
-// Packed lower triangle (column k holds rows k..n-1 at offset k n - k (k - 1) / 2): lane i
-// receives row i (forward) or column i (backward), zeros above the diagonal.
-template <typename T, int MAXW>
-__device__ __forceinline__ void wave_load_rows_packed(const T *__restrict__ L, int n, int lane, T (&row)[MAXW]) {
-#pragma unroll
-    for (int k = 0; k < MAXW; ++k)
-        row[k] = (k < n && lane < n && lane >= k) ? L[k * n - k * (k - 1) / 2 + (lane - k)] : T(0);
-}
-template <typename T, int MAXW>
-__device__ __forceinline__ void wave_load_cols_packed(const T *__restrict__ L, int n, int lane, T (&col)[MAXW]) {
-    const int base = lane * n - lane * (lane - 1) / 2 - lane;
-#pragma unroll
-    for (int k = 0; k < MAXW; ++k) col[k] = (k < n && lane < n && k >= lane) ? L[base + k] : T(0);
-}
-
-// Both solves rely on the stored upper triangle being zero, so the update is branch-free:
-// lane k takes the solved value, the other lanes subtract their (possibly zero) coefficient.
-template <typename T, int MAXW>
-__device__ __forceinline__ T wave_forward(const T (&row)[MAXW], int n, int lane, T x) {
-#pragma unroll
-    for (int k = 0; k < MAXW; ++k) {
-        if (k < n) {
-            const T dk = bcast(row[k], k);
-            const T yk = bcast(x, k) * dk;
-            x = lane == k ? yk : x - row[k] * yk;
-        }
-    }
-    return x;
-}
-
-template <typename T, int MAXW>
-__device__ __forceinline__ T wave_backward(const T (&col)[MAXW], int n, int lane, T x) {
-#pragma unroll
-    for (int k = MAXW - 1; k >= 0; --k) {
-        if (k < n) {
-            const T dk = bcast(col[k], k);
-            const T uk = bcast(x, k) * dk;
-            x = lane == k ? uk : x - col[k] * uk;
-        }
-    }
-    return x;
-}
-
-template <typename T>
-struct Vec4 {
-    T v[4];
-};
-template <typename T>
-__device__ __forceinline__ Vec4<T> load4(const T *p);
-template <>
-__device__ __forceinline__ Vec4<float> load4<float>(const float *p) {
-    float4 a = *reinterpret_cast<const float4 *>(p);
-    return {{a.x, a.y, a.z, a.w}};
-}
-template <>
-__device__ __forceinline__ Vec4<double> load4<double>(const double *p) {
-    double2 a = *reinterpret_cast<const double2 *>(p);
-    double2 b = *reinterpret_cast<const double2 *>(p + 2);
-    return {{a.x, a.y, b.x, b.y}};
-}
-
-// y[r] -= sum_c M[c * ld + r] x[c] for r < nrows (ld multiple of 4, M 16-byte aligned);
-// x, y in LDS.  Work split over (row quads) x (column chunks), accumulated with LDS atomics;
-// each thread keeps U column loads in flight.
-template <typename T, int U = 8>
-__device__ void panel_fwd(const T *__restrict__ M, int ld, int nrows, int ncols, const T *x, T *y) {
-    const int tid = threadIdx.x, nt = blockDim.x;
-    const int nq = (nrows + 3) / 4;
-    if (nq == 0 || ncols == 0) return;
-    int nch = max(1, min((ncols + U - 1) / U, nt / nq));
-    int chunk = (ncols + nch - 1) / nch;
-    for (int task = tid; task < nq * nch; task += nt) {
-        int rq = task % nq, ch = task / nq;
-        int c0 = ch * chunk, c1 = min(ncols, c0 + chunk);
-        T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-        const T *base = M + 4 * rq;
-        for (int c = c0; c < c1; c += U) {
-            Vec4<T> v[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-                if (c + u < c1) v[u] = load4(base + (int64_t)(c + u) * ld);
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                if (c + u < c1) {
-                    T xc = x[c + u];
-                    a0 += v[u].v[0] * xc;
-                    a1 += v[u].v[1] * xc;
-                    a2 += v[u].v[2] * xc;
-                    a3 += v[u].v[3] * xc;
-                }
-            }
-        }
-        int r = 4 * rq;
-        if (nch == 1) {
-            if (r < nrows) y[r] -= a0;
-            if (r + 1 < nrows) y[r + 1] -= a1;
-            if (r + 2 < nrows) y[r + 2] -= a2;
-            if (r + 3 < nrows) y[r + 3] -= a3;
-        } else {
-            if (r < nrows) atomicAdd(&y[r], -a0);
-            if (r + 1 < nrows) atomicAdd(&y[r + 1], -a1);
-            if (r + 2 < nrows) atomicAdd(&y[r + 2], -a2);
-            if (r + 3 < nrows) atomicAdd(&y[r + 3], -a3);
-        }
-    }
-}
-
-// y[c] -= sum_r M[c * ld + r] x[r] for c < ncols: a thread streams one (column, row chunk)
-// with U loads in flight; chunks of one column meet in an LDS atomic.
-template <typename T, int U = 8>
-__device__ void panel_bwd(const T *__restrict__ M, int ld, int nrows, int ncols, const T *x, T *y) {
-    const int tid = threadIdx.x, nt = blockDim.x;
-    const int nq = (nrows + 3) / 4;
-    if (nq == 0 || ncols == 0) return;
-    int nrc = max(1, min((nq + U - 1) / U, nt / ncols));
-    int chunk = (nq + nrc - 1) / nrc;
-    for (int task = tid; task < ncols * nrc; task += nt) {
-        int c = task % ncols, rc = task / ncols;
-        int q0 = rc * chunk, q1 = min(nq, q0 + chunk);
-        const T *col = M + (int64_t)c * ld;
-        T s = 0;
-        for (int q = q0; q < q1; q += U) {
-            Vec4<T> v[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-                if (q + u < q1) v[u] = load4(col + 4 * (q + u));
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                if (q + u < q1) {
-                    int r = 4 * (q + u);
-                    s += v[u].v[0] * x[r];
-                    if (r + 1 < nrows) s += v[u].v[1] * x[r + 1];
-                    if (r + 2 < nrows) s += v[u].v[2] * x[r + 2];
-                    if (r + 3 < nrows) s += v[u].v[3] * x[r + 3];
-                }
-            }
-        }
-        if (nrc == 1) y[c] -= s;
-        else atomicAdd(&y[c], -s);
-    }
-}
-
-// Workgroup barrier that also stops the compiler from moving instructions between the
-// phases it separates (interleaving phases raises register pressure and forces spills).
-__device__ __forceinline__ void phase_sync() {
-    __syncthreads();
-    __builtin_amdgcn_sched_barrier(0);
-}
-
-// Offset of top-plane tile J inside one interior-patch factor (diagonal 64x64 block, then
-// the panel of rows below it padded to a multiple of 4).
-__device__ __forceinline__ int64_t tile_offset(int64_t off_Ltop, int NT, int J) {
-    int64_t o = off_Ltop;
-    for (int j = 0; j < J; ++j) {
-        int rows = NT - 64 * j - min(64, NT - 64 * j);
-        o += 64 * 65 / 2 + (int64_t)64 * ((rows + 3) / 4 * 4);
-    }
-    return o;
-}
-
-// Interior-vertex patch solve, one workgroup per patch (Sec. 2.6): condensation of the
-// diagonal interior block, then the nested-dissection Cholesky factor of the interface
-// Schur complement (leaves, level-1 separator slices, dense top plane), forward and
-// backward, then interior back-substitution.  Output: the patch box of (2m+1)^3 values.
-template <typename T, int P>
-__global__ void __launch_bounds__(256) k_patch_interior(Dims d, PatchArgs A, const int *__restrict__ verts,
-                                                        const T *__restrict__ factor, const T *__restrict__ mu,
-                                                        const T *__restrict__ lam, const T *__restrict__ afc,
-                                                        const T *__restrict__ rF, T *__restrict__ U) {
-    constexpr int M = P - 1, W = 2 * M + 1, NL = 4 * M * M, NS = 2 * M * W, NT = W * W, NI = NL + NS + NT;
-    constexpr int NTILE = (NT + 63) / 64;
-    __shared__ T g[NI];
-    __shared__ T smu[24], slam[M], safc[2 * M];
-    __shared__ T tl[64 * 65 / 2];
-    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
-    const int pid = blockIdx.x;
-    const int kfull[3] = {AX_FULL, AX_FULL, AX_FULL};
-    const int vx = verts[3 * pid], vy = verts[3 * pid + 1], vz = verts[3 * pid + 2];
-    stage_coefficients<T, M>(d, vx, vy, vz, kfull, mu, lam, afc, smu, slam, safc);
-    phase_sync();
-    PatchCtx<T, M> C{d, vx, vy, vz, rF, smu, slam, safc};
-    const T *F = factor + (int64_t)pid * A.stride;
-    T *Uo = U + ((int64_t)(vz * (d.ny + 1) + vy) * (d.nx + 1) + vx) * (int64_t)(W * W * W);
-
-    // ---- condensation of the interior DOFs into the interface right-hand side
-    for (int idx = tid; idx < NI; idx += nt) {
-        int pos[3];
-        if (idx < NL) {
-            pos[2] = inv_la_(idx / (2 * M), M); pos[0] = inv_la_(idx % (2 * M), M); pos[1] = M;
-        } else if (idx < NL + NS) {
-            int t = idx - NL;
-            pos[2] = inv_la_(t / W, M); pos[1] = t % W; pos[0] = M;
-        } else {
-            int t = idx - NL - NS;
-            pos[1] = t / W; pos[0] = t % W; pos[2] = M;
-        }
-        int ncen = (pos[0] == M) + (pos[1] == M) + (pos[2] == M);
-        int dd = pos[0] == M ? 0 : (pos[1] == M ? 1 : 2);
-        g[idx] = ncen == 1 ? C.condensed(pos, dd) : rF[C.gidx(pos[0], pos[1], pos[2])];
-    }
-    phase_sync();
-    // ---- forward: leaves (diagonal)
-    const T *invd = F + A.off_invd, *B1 = F + A.off_B1, *B2 = F + A.off_B2;
-    for (int i = tid; i < NL; i += nt) g[i] *= invd[i];
-    phase_sync();
-    // leaf columns update their level-1 slice and their top-plane line
-    for (int task = tid; task < 2 * NS; task += nt) {
-        if (task < NS) {
-            int s = task / W, r = task % W;
-            T acc = 0;
-#pragma unroll
-            for (int c = 0; c < 2 * M; ++c) acc += B1[(int64_t)(s * 2 * M + c) * W + r] * g[s * 2 * M + c];
-            g[NL + s * W + r] -= acc;
-        } else {
-            int t = task - NS, lx = t / W, ay = t % W;
-            T acc = 0;
-#pragma unroll
-            for (int c = 0; c < 2 * M; ++c) acc += B2[(int64_t)(lx * 2 * M + c) * W + ay] * g[c * 2 * M + lx];
-            g[NL + NS + ay * W + inv_la_(lx, M)] -= acc;
-        }
-    }
-    phase_sync();
-    // level-1 separator slices: dense lower solves, one wavefront per slice
-    for (int s = wv; s < 2 * M; s += nw) {
-        T row[W];
-        wave_load_rows_packed<T, W>(F + A.off_Lsep + (int64_t)s * (W * (W + 1) / 2), W, lane, row);
-        T x = lane < W ? g[NL + s * W + lane] : T(0);
-        x = wave_forward<T, W>(row, W, lane, x);
-        if (lane < W) g[NL + s * W + lane] = x;
-    }
-    // stage the first top-plane diagonal tile while the level-1 solves finish
-    T *gt = g + NL + NS;
-    // stage a packed 64-column diagonal block verbatim (column k holds rows k..63 from
-    // offset k (129 - k) / 2); 9 independent loads per thread
-    auto stage_tile = [&](int J) {
-        const T *D = F + tile_offset(A.off_Ltop, NT, J);
-        constexpr int NP = 64 * 65 / 2, R = (NP + 255) / 256;
-        T v[R];
-#pragma unroll
-        for (int u = 0; u < R; ++u) v[u] = tid + 256 * u < NP ? D[tid + 256 * u] : T(0);
-#pragma unroll
-        for (int u = 0; u < R; ++u)
-            if (tid + 256 * u < NP) tl[tid + 256 * u] = v[u];
-    };
-    stage_tile(0);
-    phase_sync();
-    // level-1 panels update the top plane
-    panel_fwd<T>(F + A.off_P, A.top_pad, NT, NS, g + NL, gt);
-    phase_sync();
-    // dense top plane, 64-column tiles: wave 0 solves the diagonal block from LDS, then all
-    // waves update the rows below while the next diagonal block is staged
-    for (int J = 0; J < NTILE; ++J) {
-        const int c0 = 64 * J, nb = min(64, NT - c0);
-        if (wv == 0) {
-            T row[64];   // row lane of the block: L(lane, k) at k (129 - k) / 2 + lane - k
-#pragma unroll
-            for (int k = 0; k < 64; ++k) row[k] = k <= lane ? tl[k * (129 - k) / 2 - k + lane] : T(0);
-            T x = lane < nb ? gt[c0 + lane] : T(0);
-            x = wave_forward<T, 64>(row, nb, lane, x);
-            if (lane < nb) gt[c0 + lane] = x;
-        }
-        phase_sync();
-        const T *D = F + tile_offset(A.off_Ltop, NT, J);
-        const int rows = NT - c0 - nb;
-        panel_fwd<T>(D + 64 * 65 / 2, (rows + 3) / 4 * 4, rows, nb, gt + c0, gt + c0 + nb);
-        if (J + 1 < NTILE) stage_tile(J + 1);
-        phase_sync();
-    }
-    // ---- backward: top plane (tile NTILE-1 is staged)
-    for (int J = NTILE - 1; J >= 0; --J) {
-        const int c0 = 64 * J, nb = min(64, NT - c0);
-        if (wv == 0) {
-            T col[64];   // column lane of the block: L(k, lane) at lane (129 - lane) / 2 + k - lane
-            const int cb = lane * (129 - lane) / 2 - lane;
-#pragma unroll
-            for (int k = 0; k < 64; ++k) col[k] = k >= lane ? tl[cb + k] : T(0);
-            T x = lane < nb ? gt[c0 + lane] : T(0);
-            x = wave_backward<T, 64>(col, nb, lane, x);
-            if (lane < nb) gt[c0 + lane] = x;
-        }
-        phase_sync();
-        if (J > 0) {
-            const int cp = 64 * (J - 1), nbp = 64, rows = NT - cp - nbp;
-            const T *Dp = F + tile_offset(A.off_Ltop, NT, J - 1);
-            panel_bwd<T>(Dp + 64 * 65 / 2, (rows + 3) / 4 * 4, rows, nbp, gt + cp + nbp, gt + cp);
-            stage_tile(J - 1);
-        }
-        phase_sync();
-    }
-    panel_bwd<T>(F + A.off_P, A.top_pad, NT, NS, gt, g + NL);
-    phase_sync();
-    for (int s = wv; s < 2 * M; s += nw) {
-        T col[W];
-        wave_load_cols_packed<T, W>(F + A.off_Lsep + (int64_t)s * (W * (W + 1) / 2), W, lane, col);
-        T x = lane < W ? g[NL + s * W + lane] : T(0);
-        x = wave_backward<T, W>(col, W, lane, x);
-        if (lane < W) g[NL + s * W + lane] = x;
-    }
-    phase_sync();
-    for (int i = tid; i < NL; i += nt) {
-        int s = i / (2 * M), c = i % (2 * M);
-        T v = g[i];
-        int ax = inv_la_(c, M);
-#pragma unroll
-        for (int r = 0; r < W; ++r)
-            v -= B1[(int64_t)(s * 2 * M + c) * W + r] * g[NL + s * W + r] + B2[(int64_t)(c * 2 * M + s) * W + r] * gt[r * W + ax];
-        g[i] = v * invd[i];
-    }
-    phase_sync();
-    // ---- interface values and interior back-substitution into the patch box
-    const bool full[3] = {true, true, true};
-    for (int idx = tid; idx < W * W * W; idx += nt) {
-        int ax = idx % W, ay = (idx / W) % W, az = idx / (W * W);
-        int ii = iface_interior(ax, ay, az, M, W, NL, NS);
-        if (ii >= 0) {
-            Uo[idx] = g[ii];
-        } else {
-            int pos[3] = {ax, ay, az};
-            Uo[idx] = C.back_interior(pos, full, [&](int a) {
-                int q[3] = {ax, ay, az};
-                q[a] = M;
-                return g[iface_interior(q[0], q[1], q[2], M, W, NL, NS)];
-            });
-        }
-    }
-}
-
-// Boundary-vertex patches: their stars lose cells, and the interface Schur complement
-// splits into independent dense slices (2 full axes: crosses of 4m+1 DOFs; 1 full axis:
-// single DOFs).  desc: vx, vy, vz, kind_x, kind_y, kind_z, nslices, slice size.
-template <typename T, int P>
-__global__ void __launch_bounds__(256) k_patch_boundary(Dims d, const int *__restrict__ desc, const int64_t *__restrict__ off,
-                                                        const T *__restrict__ factor, const T *__restrict__ mu,
-                                                        const T *__restrict__ lam, const T *__restrict__ afc,
-                                                        const T *__restrict__ rF, T *__restrict__ U) {
-    constexpr int M = P - 1, W = 2 * M + 1, MAXN = 4 * M + 1;
-    __shared__ T g[M * MAXN > M * M ? M * MAXN : M * M];
-    __shared__ T smu[24], slam[M], safc[2 * M];
-    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
-    const int pid = blockIdx.x;
-    const int *ds = desc + 8 * pid;
-    const int kind[3] = {ds[3], ds[4], ds[5]};
-    stage_coefficients<T, M>(d, ds[0], ds[1], ds[2], kind, mu, lam, afc, smu, slam, safc);
-    __syncthreads();
-    PatchCtx<T, M> C{d, ds[0], ds[1], ds[2], rF, smu, slam, safc};
-    const int nslices = ds[6], ns = ds[7], n = nslices * ns;
-    const bool full[3] = {kind[0] == AX_FULL, kind[1] == AX_FULL, kind[2] == AX_FULL};
-    int fa = -1, fb = -1, hh = -1, hb = -1, hc = -1;
-    for (int a = 0; a < 3; ++a) {
-        if (full[a]) { if (fa < 0) fa = a; else fb = a; }
-        else { if (hb < 0) hb = a; else hc = a; }
-    }
-    const int nfull = full[0] + full[1] + full[2];
-    if (nfull == 2) hh = hb;
-    auto spos = [&](int a, int t) { return kind[a] == AX_LOW ? M + 1 + t : t; };
-    auto sidx = [&](int a, int pos) { return kind[a] == AX_LOW ? pos - M - 1 : pos; };
-    auto decode = [&](int idx, int pos[3]) {
-        if (nfull == 2) {
-            int t = idx / ns, c = idx % ns;
-            pos[hh] = spos(hh, t);
-            if (c < 2 * M) { pos[fa] = M; pos[fb] = inv_la_(c, M); }
-            else { pos[fb] = M; pos[fa] = c - 2 * M; }
-        } else {  // one full axis
-            int tb = idx % M, tc = idx / M;
-            pos[fa] = M; pos[hb] = spos(hb, tb); pos[hc] = spos(hc, tc);
-        }
-    };
-    auto encode = [&](const int pos[3]) -> int {
-        if (nfull == 2) {
-            int t = sidx(hh, pos[hh]);
-            int c = (pos[fa] == M && pos[fb] != M) ? la_(pos[fb], M) : 2 * M + pos[fa];
-            return t * ns + c;
-        }
-        return sidx(hb, pos[hb]) + M * sidx(hc, pos[hc]);
-    };
-    T *Uo = U + ((int64_t)(ds[2] * (d.ny + 1) + ds[1]) * (d.nx + 1) + ds[0]) * (int64_t)(W * W * W);
-    for (int idx = tid; idx < n; idx += nt) {
-        int pos[3];
-        decode(idx, pos);
-        int ncen = 0, dd = 0;
-        for (int a = 0; a < 3; ++a)
-            if (full[a] && pos[a] == M) { ++ncen; dd = a; }
-        g[idx] = ncen == 1 ? C.condensed(pos, dd) : rF[C.gidx(pos[0], pos[1], pos[2])];
-    }
-    __syncthreads();
-    const T *F = factor + (n > 0 ? off[pid] : 0);
-    if (ns == 1) {
-        for (int t = tid; t < nslices; t += nt) g[t] *= F[t] * F[t];
-    } else if (ns > 1) {
-        for (int t = wv; t < nslices; t += nw) {
-            const T *Ls = F + (int64_t)t * (ns * (ns + 1) / 2);
-            T x = lane < ns ? g[t * ns + lane] : T(0);
-            {
-                T row[MAXN];
-                wave_load_rows_packed<T, MAXN>(Ls, ns, lane, row);
-                x = wave_forward<T, MAXN>(row, ns, lane, x);
-            }
-            {
-                T col[MAXN];
-                wave_load_cols_packed<T, MAXN>(Ls, ns, lane, col);
-                x = wave_backward<T, MAXN>(col, ns, lane, x);
-            }
-            if (lane < ns) g[t * ns + lane] = x;
-        }
-    }
-    __syncthreads();
-    int lo[3], cnt[3];
-    for (int a = 0; a < 3; ++a) {
-        lo[a] = kind[a] == AX_LOW ? M + 1 : 0;
-        cnt[a] = kind[a] == AX_FULL ? W : M;
-    }
-    const int tot = cnt[0] * cnt[1] * cnt[2];
-    for (int idx = tid; idx < tot; idx += nt) {
-        int pos[3] = {lo[0] + idx % cnt[0], lo[1] + (idx / cnt[0]) % cnt[1], lo[2] + idx / (cnt[0] * cnt[1])};
-        int box = (pos[2] * W + pos[1]) * W + pos[0];
-        bool iface = (full[0] && pos[0] == M) || (full[1] && pos[1] == M) || (full[2] && pos[2] == M);
-        if (iface) {
-            Uo[box] = g[encode(pos)];
-        } else {
-            Uo[box] = C.back_interior(pos, full, [&](int a) {
-                int q[3] = {pos[0], pos[1], pos[2]};
-                q[a] = M;
-                return g[encode(q)];
-            });
-        }
-    }
-}
-
 // Additive Schwarz sum z_F = sum_j Rbar_j^T u_j (Sec. 2.5): each free lattice point sums
 // the boxes of the (up to 8) stars that contain it.
 template <typename T>
-__global__ void k_patch_assemble(Dims d, int interior_only, const T *__restrict__ U, T *__restrict__ zF) {
+__global__ void k_patch_assemble(const double *__restrict__ gate, Dims d, int interior_only, const T *__restrict__ U, T *__restrict__ zF) {
+    if (gated(gate)) return;
     const int p = d.p, m = p - 1, w = 2 * m + 1;
     const int64_t n = (int64_t)d.Lx * d.Ly * d.Lz, w3 = (int64_t)w * w * w;
     for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n; idx += (int64_t)gridDim.x * blockDim.x) {
@@ -861,7 +304,8 @@ __global__ void k_patch_assemble(Dims d, int interior_only, const T *__restrict_
 
 // ====================================================================== dense / vector
 template <typename T>
-__global__ void k_dense_gemv(int n, const T *__restrict__ A, const T *__restrict__ x, T *__restrict__ y, T alpha, T beta) {
+__global__ void k_dense_gemv(const double *__restrict__ gate, int n, const T *__restrict__ A, const T *__restrict__ x, T *__restrict__ y, T alpha, T beta) {
+    if (gated(gate)) return;
     const int lane = threadIdx.x & 63;
     const int row = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     if (row >= n) return;
@@ -873,13 +317,15 @@ __global__ void k_dense_gemv(int n, const T *__restrict__ A, const T *__restrict
 }
 
 template <typename Tin, typename Tout>
-__global__ void k_cast(int64_t n, const Tin *__restrict__ x, Tout *__restrict__ y) {
+__global__ void k_cast(const double *__restrict__ gate, int64_t n, const Tin *__restrict__ x, Tout *__restrict__ y) {
+    if (gated(gate)) return;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         y[i] = (Tout)x[i];
 }
 
 template <typename T>
-__global__ void k_fill(int64_t n, T *__restrict__ x, T v) {
+__global__ void k_fill(const double *__restrict__ gate, int64_t n, T *__restrict__ x, T v) {
+    if (gated(gate)) return;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) x[i] = v;
 }
 
@@ -897,14 +343,16 @@ __device__ __forceinline__ double block_sum(double v) {
     return s;
 }
 
-__global__ void k_dot_partial(int64_t n, const double *__restrict__ x, const double *__restrict__ y, double *partials) {
+__global__ void k_dot_partial(const double *__restrict__ gate, int64_t n, const double *__restrict__ x, const double *__restrict__ y, double *partials) {
+    if (gated(gate)) return;
     double s = 0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) s += x[i] * y[i];
     s = block_sum(s);
     if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
-__global__ void k_finalize(int nb, const double *__restrict__ partials, double *scal, int mode) {
+__global__ void k_finalize(const double *__restrict__ gate, int nb, const double *__restrict__ partials, double *scal, int mode) {
+    if (gated(gate)) return;
     double s = 0;
     for (int i = threadIdx.x; i < nb; i += blockDim.x) s += partials[i];
     s = block_sum(s);
@@ -922,12 +370,27 @@ __global__ void k_finalize(int nb, const double *__restrict__ partials, double *
             scal[SC_RZ] = s;
         } else if (mode == 4) {  // r.r
             scal[SC_RR] = s;
+        } else if (mode == 5) {  // r.r after an x update: count it and test for the stop
+            scal[SC_RR] = s;
+            const double it = scal[SC_IT] + 1.0;
+            scal[SC_IT] = it;
+            if (!(s - s == 0.0)) {  // NaN or infinite
+                scal[SC_STATUS] = 2.0;
+                scal[SC_DONE] = 1.0;
+            } else if (s <= scal[SC_RTOL2] * scal[SC_BB]) {
+                scal[SC_STATUS] = 1.0;
+                scal[SC_DONE] = 1.0;
+            } else if (it >= scal[SC_MAXIT]) {
+                scal[SC_STATUS] = 3.0;
+                scal[SC_DONE] = 1.0;
+            }
         }
     }
 }
 
-__global__ void k_pcg_xr(int64_t n, double *__restrict__ x, double *__restrict__ r, const double *__restrict__ p,
+__global__ void k_pcg_xr(const double *__restrict__ gate, int64_t n, double *__restrict__ x, double *__restrict__ r, const double *__restrict__ p,
                          const double *__restrict__ q, const double *__restrict__ scal, double *partials) {
+    if (gated(gate)) return;
     const double alpha = scal[SC_ALPHA];
     double s = 0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -940,180 +403,189 @@ __global__ void k_pcg_xr(int64_t n, double *__restrict__ x, double *__restrict__
     if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
-__global__ void k_pcg_p(int64_t n, double *__restrict__ p, const double *__restrict__ z, const double *__restrict__ scal) {
+__global__ void k_pcg_p(const double *__restrict__ gate, int64_t n, double *__restrict__ p, const double *__restrict__ z, const double *__restrict__ scal) {
+    if (gated(gate)) return;
     const double beta = scal[SC_BETA];
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = z[i] + beta * p[i];
 }
 
 template <typename T>
-__global__ void k_residual(int64_t n, const double *__restrict__ r, const T *Az, T *out) {
+__global__ void k_residual(const double *__restrict__ gate, int64_t n, const double *__restrict__ r, const T *Az, T *out) {
+    if (gated(gate)) return;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         out[i] = (T)r[i] - Az[i];
 }
 
 template <typename T>
-__global__ void k_axpby_to_double(int64_t n, double a, const T *__restrict__ x, double b, double *__restrict__ y) {
+__global__ void k_axpby_to_double(const double *__restrict__ gate, int64_t n, double a, const T *__restrict__ x, double b, double *__restrict__ y) {
+    if (gated(gate)) return;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         y[i] = b == 0.0 ? a * (double)x[i] : a * (double)x[i] + b * y[i];
 }
 
-inline unsigned grid_for(int64_t n, int block = 256) {
-    int64_t g = (n + block - 1) / block;
-    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, 8192));
+__global__ void k_pcg_start(double *scal, double rtol, int max_iterations) {
+    if (threadIdx.x == 0) {
+        const double bb = scal[SC_RR];
+        scal[SC_BB] = bb;
+        scal[SC_RTOL2] = rtol * rtol;
+        scal[SC_IT] = 0.0;
+        scal[SC_MAXIT] = (double)max_iterations;
+        const bool finite = bb - bb == 0.0;
+        scal[SC_STATUS] = !finite ? 2.0 : (bb == 0.0 ? 1.0 : 0.0);
+        scal[SC_DONE] = (!finite || bb == 0.0) ? 1.0 : 0.0;
+    }
+}
+
+__global__ void k_count_active(int count, const double *const *__restrict__ scals, int *active) {
+    int c = 0;
+    for (int i = threadIdx.x; i < count; i += blockDim.x) c += scals[i][SC_DONE] == 0.0 ? 1 : 0;
+    c = wave_sum(c);
+    __shared__ int part[16];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if (lane == 0) part[wv] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int w = 0; w < nw; ++w) t += part[w];
+        *active = t;
+    }
 }
 
 }  // namespace
 
 // ====================================================================== launchers
-#define VSR_P_SWITCH(p, CALL)                                  \
-    switch (p) {                                               \
-        case 2: CALL(2); break;                                \
-        case 3: CALL(3); break;                                \
-        case 4: CALL(4); break;                                \
-        case 5: CALL(5); break;                                \
-        case 6: CALL(6); break;                                \
-        case 7: CALL(7); break;                                \
-        case 8: CALL(8); break;                                \
-        case 9: CALL(9); break;                                \
-        case 10: CALL(10); break;                              \
-        case 11: CALL(11); break;                              \
-        case 12: CALL(12); break;                              \
-        case 13: CALL(13); break;                              \
-        case 14: CALL(14); break;                              \
-        case 15: CALL(15); break;                              \
-        default: throw Error(VSR_EINVAL, "unsupported degree"); \
+template <typename T>
+void launch_op_kron(const Dims &d, const T *AB1d, const T *mu, const T *x, T *y, const Exec &e) {
+    const int64_t ncell = (int64_t)d.nx * d.ny * d.nz;
+    int cpw = std::is_same<T, double>::value ? e.t.op_cpw64 : e.t.op_cpw32;
+    if (cpw != 1 && cpw != 2 && cpw != 4) throw Error(VSR_EINVAL, "op cells per workgroup must be 1, 2 or 4");
+    if ((d.p + 1) * (d.p + 1) > 64) cpw = 1;
+#define CALLC(P, C)                                                                                                 \
+    hipLaunchKernelGGL((k_op_kron<T, P, C>), dim3((unsigned)((ncell + C - 1) / C)), dim3(round64(C * (P + 1) * (P + 1))), \
+                       0, e.s, e.gate, d, AB1d, mu, x, y)
+#define CALL(P)                                                  \
+    if constexpr ((P + 1) * (P + 1) <= 64) {                     \
+        if (cpw == 4) CALLC(P, 4);                               \
+        else if (cpw == 2) CALLC(P, 2);                          \
+        else CALLC(P, 1);                                        \
+    } else {                                                     \
+        CALLC(P, 1);                                             \
     }
-
-static inline unsigned round64(int n) { return (unsigned)((n + 63) / 64 * 64); }
+    VSR_P_SWITCH(d.p, CALL)
+#undef CALL
+#undef CALLC
+}
 
 template <typename T>
-void launch_op_kron(const Dims &d, const T *AB1d, const T *mu, const T *x, T *y, hipStream_t s) {
+void launch_op_general(const Dims &d, const T *IDq, const T *Gw, const T *x, T *y, const Exec &e) {
     int64_t ncell = (int64_t)d.nx * d.ny * d.nz;
-#define CALL(P) hipLaunchKernelGGL((k_op_kron<T, P>), dim3((unsigned)ncell), dim3(round64((P + 1) * (P + 1))), 0, s, d, AB1d, mu, x, y)
+#define CALL(P) \
+    hipLaunchKernelGGL((k_op_general<T, P>), dim3((unsigned)ncell), dim3(round64(QOF(P) * QOF(P))), 0, e.s, e.gate, d, IDq, Gw, x, y)
     VSR_P_SWITCH(d.p, CALL)
 #undef CALL
 }
 
-template <typename T>
-void launch_op_general(const Dims &d, const T *IDq, const T *Gw, const T *x, T *y, hipStream_t s) {
+void launch_load_vector(const Dims &d, const double *IDq, const double *wdet, const double *f, double *b, const Exec &e) {
     int64_t ncell = (int64_t)d.nx * d.ny * d.nz;
-#define CALL(P) hipLaunchKernelGGL((k_op_general<T, P>), dim3((unsigned)ncell), dim3(round64(QOF(P) * QOF(P))), 0, s, d, IDq, Gw, x, y)
-    VSR_P_SWITCH(d.p, CALL)
-#undef CALL
-}
-
-void launch_load_vector(const Dims &d, const double *IDq, const double *wdet, const double *f, double *b, hipStream_t s) {
-    int64_t ncell = (int64_t)d.nx * d.ny * d.nz;
-#define CALL(P) hipLaunchKernelGGL((k_load_vector<P>), dim3((unsigned)ncell), dim3(round64(QOF(P) * QOF(P))), 0, s, d, IDq, wdet, f, b)
+#define CALL(P) \
+    hipLaunchKernelGGL((k_load_vector<P>), dim3((unsigned)ncell), dim3(round64(QOF(P) * QOF(P))), 0, e.s, e.gate, d, IDq, wdet, f, b)
     VSR_P_SWITCH(d.p, CALL)
 #undef CALL
 }
 
 template <typename Tin, typename Tout>
 void launch_axis_pass(const int *rowptr, const int *col, const Tout *w, int axis, const int in_dims[3], const int out_dims[3],
-                      const Tin *in, Tout *out, Tout alpha, Tout beta, hipStream_t s) {
+                      const Tin *in, Tout *out, Tout alpha, Tout beta, const Exec &e) {
     int64_t n = (int64_t)out_dims[0] * out_dims[1] * out_dims[2];
     if (n == 0) return;
-    hipLaunchKernelGGL((k_axis_pass<Tin, Tout>), dim3(grid_for(n)), dim3(256), 0, s, rowptr, col, w, axis, in_dims[0],
-                       in_dims[1], in_dims[2], out_dims[0], out_dims[1], out_dims[2], in, out, alpha, beta);
+    const int bs = e.t.axis_block;
+    if (bs < 64 || bs > 1024 || bs % 64 != 0) throw Error(VSR_EINVAL, "axis block must be a multiple of 64 in [64, 1024]");
+    hipLaunchKernelGGL((k_axis_pass<Tin, Tout>), dim3(grid_for(n, bs)), dim3(bs), 0, e.s, e.gate, rowptr, col, w, axis,
+                       in_dims[0], in_dims[1], in_dims[2], out_dims[0], out_dims[1], out_dims[2], in, out, alpha, beta);
 }
 
 template <typename T>
-void launch_patch_interior(const Dims &d, const PatchArgs &a, int npatch, const int *verts, const T *factor, const T *mu,
-                           const T *lam, const T *afc, const T *rF, T *U, hipStream_t s) {
-    if (npatch == 0) return;
-#define CALL(P) hipLaunchKernelGGL((k_patch_interior<T, P>), dim3(npatch), dim3(256), 0, s, d, a, verts, factor, mu, lam, afc, rF, U)
-    VSR_P_SWITCH(d.p, CALL)
-#undef CALL
-}
-
-template <typename T>
-void launch_patch_boundary(const Dims &d, int npatch, const int *desc, const int64_t *off, const T *factor, const T *mu,
-                           const T *lam, const T *afc, const T *rF, T *U, hipStream_t s) {
-    if (npatch == 0) return;
-#define CALL(P) hipLaunchKernelGGL((k_patch_boundary<T, P>), dim3(npatch), dim3(256), 0, s, d, desc, off, factor, mu, lam, afc, rF, U)
-    VSR_P_SWITCH(d.p, CALL)
-#undef CALL
-}
-
-template <typename T>
-void launch_patch_assemble(const Dims &d, int interior_only, const T *U, T *zF, hipStream_t s) {
+void launch_patch_assemble(const Dims &d, int interior_only, const T *U, T *zF, const Exec &e) {
     int64_t n = (int64_t)d.Lx * d.Ly * d.Lz;
-    hipLaunchKernelGGL((k_patch_assemble<T>), dim3(grid_for(n)), dim3(256), 0, s, d, interior_only, U, zF);
+    hipLaunchKernelGGL((k_patch_assemble<T>), dim3(grid_for(n)), dim3(256), 0, e.s, e.gate, d, interior_only, U, zF);
 }
 
 template <typename T>
-void launch_dense_gemv(int n, const T *A, const T *x, T *y, T alpha, T beta, hipStream_t s) {
+void launch_dense_gemv(int n, const T *A, const T *x, T *y, T alpha, T beta, const Exec &e) {
     if (n == 0) return;
     unsigned blocks = (unsigned)(((int64_t)n * 64 + 255) / 256);
-    hipLaunchKernelGGL((k_dense_gemv<T>), dim3(blocks), dim3(256), 0, s, n, A, x, y, alpha, beta);
+    hipLaunchKernelGGL((k_dense_gemv<T>), dim3(blocks), dim3(256), 0, e.s, e.gate, n, A, x, y, alpha, beta);
 }
 
 template <typename Tin, typename Tout>
-void launch_cast(int64_t n, const Tin *x, Tout *y, hipStream_t s) {
-    hipLaunchKernelGGL((k_cast<Tin, Tout>), dim3(grid_for(n)), dim3(256), 0, s, n, x, y);
+void launch_cast(int64_t n, const Tin *x, Tout *y, const Exec &e) {
+    hipLaunchKernelGGL((k_cast<Tin, Tout>), dim3(grid_for(n)), dim3(256), 0, e.s, e.gate, n, x, y);
 }
 
 template <typename T>
-void launch_fill(int64_t n, T *x, T v, hipStream_t s) {
-    hipLaunchKernelGGL((k_fill<T>), dim3(grid_for(n)), dim3(256), 0, s, n, x, v);
+void launch_fill(int64_t n, T *x, T v, const Exec &e) {
+    hipLaunchKernelGGL((k_fill<T>), dim3(grid_for(n)), dim3(256), 0, e.s, e.gate, n, x, v);
 }
 
-int launch_dot_partial(int64_t n, const double *x, const double *y, double *partials, hipStream_t s) {
+int launch_dot_partial(int64_t n, const double *x, const double *y, double *partials, const Exec &e) {
     int nb = (int)std::min<int64_t>(RED_BLOCKS, std::max<int64_t>(1, (n + 255) / 256));
-    hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(256), 0, s, n, x, y, partials);
+    hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(256), 0, e.s, e.gate, n, x, y, partials);
     return nb;
 }
 
-void launch_finalize(int nb, const double *partials, double *scal, int mode, hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, nb, partials, scal, mode);
+void launch_finalize(int nb, const double *partials, double *scal, int mode, const Exec &e) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, e.s, e.gate, nb, partials, scal, mode);
+}
+
+void launch_pcg_start(double *scal, double rtol, int max_iterations, const Exec &e) {
+    hipLaunchKernelGGL(k_pcg_start, dim3(1), dim3(64), 0, e.s, scal, rtol, max_iterations);
 }
 
 int launch_pcg_xr(int64_t n, double *x, double *r, const double *p, const double *q, const double *scal, double *partials,
-                  hipStream_t s) {
+                  const Exec &e) {
     int nb = (int)std::min<int64_t>(RED_BLOCKS, std::max<int64_t>(1, (n + 255) / 256));
-    hipLaunchKernelGGL(k_pcg_xr, dim3(nb), dim3(256), 0, s, n, x, r, p, q, scal, partials);
+    hipLaunchKernelGGL(k_pcg_xr, dim3(nb), dim3(256), 0, e.s, e.gate, n, x, r, p, q, scal, partials);
     return nb;
 }
 
-void launch_pcg_p(int64_t n, double *p, const double *z, const double *scal, hipStream_t s) {
-    hipLaunchKernelGGL(k_pcg_p, dim3(grid_for(n)), dim3(256), 0, s, n, p, z, scal);
+void launch_pcg_p(int64_t n, double *p, const double *z, const double *scal, const Exec &e) {
+    hipLaunchKernelGGL(k_pcg_p, dim3(grid_for(n)), dim3(256), 0, e.s, e.gate, n, p, z, scal);
 }
 
 template <typename T>
-void launch_residual(int64_t n, const double *r, const T *Az, T *out, hipStream_t s) {
-    hipLaunchKernelGGL((k_residual<T>), dim3(grid_for(n)), dim3(256), 0, s, n, r, Az, out);
+void launch_residual(int64_t n, const double *r, const T *Az, T *out, const Exec &e) {
+    hipLaunchKernelGGL((k_residual<T>), dim3(grid_for(n)), dim3(256), 0, e.s, e.gate, n, r, Az, out);
 }
 
 template <typename T>
-void launch_axpby_to_double(int64_t n, double a, const T *x, double b, double *y, hipStream_t s) {
-    hipLaunchKernelGGL((k_axpby_to_double<T>), dim3(grid_for(n)), dim3(256), 0, s, n, a, x, b, y);
+void launch_axpby_to_double(int64_t n, double a, const T *x, double b, double *y, const Exec &e) {
+    hipLaunchKernelGGL((k_axpby_to_double<T>), dim3(grid_for(n)), dim3(256), 0, e.s, e.gate, n, a, x, b, y);
+}
+
+void launch_count_active(int count, const double *const *scals, int *active, const Exec &e) {
+    hipLaunchKernelGGL(k_count_active, dim3(1), dim3(256), 0, e.s, count, scals, active);
 }
 
 // explicit instantiations
-#define INST(T)                                                                                                         \
-    template void launch_op_kron<T>(const Dims &, const T *, const T *, const T *, T *, hipStream_t);                   \
-    template void launch_op_general<T>(const Dims &, const T *, const T *, const T *, T *, hipStream_t);                \
-    template void launch_patch_interior<T>(const Dims &, const PatchArgs &, int, const int *, const T *, const T *,      \
-                                           const T *, const T *, const T *, T *, hipStream_t);                          \
-    template void launch_patch_boundary<T>(const Dims &, int, const int *, const int64_t *, const T *, const T *,         \
-                                           const T *, const T *, const T *, T *, hipStream_t);                          \
-    template void launch_patch_assemble<T>(const Dims &, int, const T *, T *, hipStream_t);                             \
-    template void launch_dense_gemv<T>(int, const T *, const T *, T *, T, T, hipStream_t);                              \
-    template void launch_fill<T>(int64_t, T *, T, hipStream_t);                                                         \
-    template void launch_residual<T>(int64_t, const double *, const T *, T *, hipStream_t);                             \
-    template void launch_axpby_to_double<T>(int64_t, double, const T *, double, double *, hipStream_t);
+#define INST(T)                                                                                          \
+    template void launch_op_kron<T>(const Dims &, const T *, const T *, const T *, T *, const Exec &);    \
+    template void launch_op_general<T>(const Dims &, const T *, const T *, const T *, T *, const Exec &); \
+    template void launch_patch_assemble<T>(const Dims &, int, const T *, T *, const Exec &);              \
+    template void launch_dense_gemv<T>(int, const T *, const T *, T *, T, T, const Exec &);               \
+    template void launch_fill<T>(int64_t, T *, T, const Exec &);                                          \
+    template void launch_residual<T>(int64_t, const double *, const T *, T *, const Exec &);              \
+    template void launch_axpby_to_double<T>(int64_t, double, const T *, double, double *, const Exec &);
 INST(float)
 INST(double)
 template void launch_axis_pass<double, double>(const int *, const int *, const double *, int, const int *, const int *,
-                                               const double *, double *, double, double, hipStream_t);
+                                               const double *, double *, double, double, const Exec &);
 template void launch_axis_pass<float, float>(const int *, const int *, const float *, int, const int *, const int *,
-                                             const float *, float *, float, float, hipStream_t);
+                                             const float *, float *, float, float, const Exec &);
 template void launch_axis_pass<double, float>(const int *, const int *, const float *, int, const int *, const int *,
-                                              const double *, float *, float, float, hipStream_t);
-template void launch_cast<double, float>(int64_t, const double *, float *, hipStream_t);
-template void launch_cast<float, double>(int64_t, const float *, double *, hipStream_t);
-template void launch_cast<double, double>(int64_t, const double *, double *, hipStream_t);
+                                              const double *, float *, float, float, const Exec &);
+template void launch_cast<double, float>(int64_t, const double *, float *, const Exec &);
+template void launch_cast<float, double>(int64_t, const float *, double *, const Exec &);
+template void launch_cast<double, double>(int64_t, const double *, double *, const Exec &);
 
 }  // namespace vsr

@@ -1,0 +1,5 @@
+// Patch-solve kernels instantiated for float (one translation unit per precision so the
+// two compile in parallel).
+#include "patch_kernels.h"
+
+VSR_INSTANTIATE_PATCH(float)

@@ -36,7 +36,8 @@ class Options(ctypes.Structure):
     _fields_ = [("relax_fp32", ctypes.c_int32), ("cycle", ctypes.c_int32), ("quad_points", ctypes.c_int32),
                 ("lanczos_steps", ctypes.c_int32), ("max_iterations", ctypes.c_int32),
                 ("interior_patches_only", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("omega", ctypes.c_double), ("stream", ctypes.c_void_p)]
+                ("omega", ctypes.c_double), ("stream", ctypes.c_void_p), ("autotune", ctypes.c_int32),
+                ("batch_streams", ctypes.c_int32), ("batch_eager", ctypes.c_int32), ("tune_cache", ctypes.c_char_p)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -80,10 +81,23 @@ def lib():
     L.vsr_factor_info.argtypes = [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
     L.vsr_destroy.argtypes = [P]
     L.vsr_destroy.restype = None
+    L.vsr_get_tuning.argtypes = [P, ctypes.POINTER(ctypes.c_int32)]
+    L.vsr_set_tuning.argtypes = [P, ctypes.POINTER(ctypes.c_int32)]
+    L.vsr_setup_batch.argtypes = [ctypes.c_int32, ctypes.POINTER(Mesh), ctypes.POINTER(ctypes.c_int32),
+                                  ctypes.POINTER(Coefficients), ctypes.POINTER(Options), ctypes.POINTER(P)]
+    L.vsr_batch_size.argtypes = [P]
+    L.vsr_batch_size.restype = ctypes.c_int32
+    L.vsr_batch_member.argtypes = [P, ctypes.c_int32]
+    L.vsr_batch_member.restype = P
+    L.vsr_pcg_solve_batch.argtypes = [P, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
+                                      ctypes.c_double, ctypes.POINTER(SolveInfo)]
+    L.vsr_destroy_batch.argtypes = [P]
+    L.vsr_destroy_batch.restype = None
     L.vsr_last_error.argtypes = []
     L.vsr_last_error.restype = ctypes.c_char_p
     for name in ("vsr_setup", "vsr_load_vector", "vsr_apply_operator", "vsr_apply_relaxation", "vsr_pcg_solve",
-                 "vsr_get_damping", "vsr_set_profiling", "vsr_kernel_stats", "vsr_factor_info"):
+                 "vsr_get_damping", "vsr_set_profiling", "vsr_kernel_stats", "vsr_factor_info", "vsr_get_tuning", "vsr_set_tuning",
+                 "vsr_setup_batch", "vsr_pcg_solve_batch"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -101,43 +115,75 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+class _Inputs:
+    """Host arrays of one problem kept alive while the library reads them."""
+
+    def __init__(self, vertices, kappa=None, mu_override=None):
+        self.V = np.ascontiguousarray(vertices, dtype=np.float64)
+        nz, ny, nx = self.V.shape[0] - 1, self.V.shape[1] - 1, self.V.shape[2] - 1
+        self.shape = (nx, ny, nz)
+        self.mesh = Mesh(nx, ny, nz, self.V.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        self.kappa = None if kappa is None else np.ascontiguousarray(kappa, dtype=np.float64).reshape(-1)
+        self.mu = None if mu_override is None else np.ascontiguousarray(mu_override, dtype=np.float64).reshape(-1)
+        self.coef = Coefficients(
+            None if self.kappa is None else self.kappa.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+            None if self.mu is None else self.mu.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+
+
+def make_options(relax_fp32=False, cycle=0, lanczos_steps=20, max_iterations=1000, interior_patches_only=False, seed=0,
+                 omega=0.0, stream=None, autotune=False, batch_streams=0, batch_eager=False, tune_cache=None):
+    opt = Options()
+    lib().vsr_default_options(ctypes.byref(opt))
+    opt.relax_fp32 = int(bool(relax_fp32))
+    opt.cycle = int(cycle)
+    opt.lanczos_steps = int(lanczos_steps)
+    opt.max_iterations = int(max_iterations)
+    opt.interior_patches_only = int(bool(interior_patches_only))
+    opt.seed = int(seed)
+    opt.omega = float(omega)
+    opt.stream = None if stream is None else ctypes.c_void_p(stream)
+    opt.autotune = int(bool(autotune))
+    opt.batch_streams = int(batch_streams)
+    opt.batch_eager = int(bool(batch_eager))
+    opt.tune_cache = None if tune_cache is None else os.fsencode(tune_cache)
+    return opt
+
+
 class Problem:
     """One discretized Poisson problem and its preconditioner, resident on the GPU."""
 
-    def __init__(self, vertices, p, kappa=None, mu_override=None, relax_fp32=False, cycle=0, lanczos_steps=20,
-                 max_iterations=1000, interior_patches_only=False, seed=0, omega=0.0, stream=None):
+    def __init__(self, vertices, p, kappa=None, mu_override=None, _handle=None, **options):
         L = lib()
-        V = np.ascontiguousarray(vertices, dtype=np.float64)
-        nz, ny, nx = V.shape[0] - 1, V.shape[1] - 1, V.shape[2] - 1
-        self._V = V
-        mesh = Mesh(nx, ny, nz, V.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
-        self._kappa = None if kappa is None else np.ascontiguousarray(kappa, dtype=np.float64).reshape(-1)
-        self._mu = None if mu_override is None else np.ascontiguousarray(mu_override, dtype=np.float64).reshape(-1)
-        coef = Coefficients(
-            None if self._kappa is None else self._kappa.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-            None if self._mu is None else self._mu.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
-        opt = Options()
-        L.vsr_default_options(ctypes.byref(opt))
-        opt.relax_fp32 = int(bool(relax_fp32))
-        opt.cycle = int(cycle)
-        opt.lanczos_steps = int(lanczos_steps)
-        opt.max_iterations = int(max_iterations)
-        opt.interior_patches_only = int(bool(interior_patches_only))
-        opt.seed = int(seed)
-        opt.omega = float(omega)
-        opt.stream = None if stream is None else ctypes.c_void_p(stream)
-        h = ctypes.c_void_p()
-        _check(L.vsr_setup(ctypes.byref(mesh), int(p), ctypes.byref(coef), ctypes.byref(opt), ctypes.byref(h)))
+        self._owned = _handle is None
+        if _handle is None:
+            self._in = _Inputs(vertices, kappa, mu_override)
+            opt = make_options(**options)
+            h = ctypes.c_void_p()
+            _check(L.vsr_setup(ctypes.byref(self._in.mesh), int(p), ctypes.byref(self._in.coef), ctypes.byref(opt),
+                               ctypes.byref(h)))
+            self.shape = self._in.shape
+        else:
+            h = _handle
+            self.shape = None
         self._h = h
         self.p = p
-        self.shape = (nx, ny, nz)
         self.n = int(L.vsr_num_dofs(h))
         self.q = (3 * (p + 1) + 1) // 2
 
+    def tuning(self):
+        """Launch shapes in use: (operator cells/workgroup FP64, FP32, lattice-pass block, panel unroll)."""
+        a = (ctypes.c_int32 * 4)()
+        _check(lib().vsr_get_tuning(self._h, a))
+        return tuple(a)
+
+    def set_tuning(self, shapes):
+        a = (ctypes.c_int32 * 4)(*[int(v) for v in shapes])
+        _check(lib().vsr_set_tuning(self._h, a))
+
     def close(self):
-        if getattr(self, "_h", None) is not None and self._h.value:
+        if getattr(self, "_h", None) is not None and self._h.value and getattr(self, "_owned", True):
             lib().vsr_destroy(self._h)
-            self._h = None
+        self._h = None
 
     def __del__(self):
         try:
@@ -180,6 +226,54 @@ class Problem:
         a, b = ctypes.c_int64(), ctypes.c_int64()
         _check(lib().vsr_factor_info(self._h, ctypes.byref(a), ctypes.byref(b)))
         return a.value, b.value
+
+
+class Batch:
+    """Independent problems solved together by the batched PCG (members on several streams,
+    one lockstep iteration replayed from a hipGraph)."""
+
+    def __init__(self, problems, **options):
+        """problems: list of dicts with keys vertices, p and optionally kappa, mu_override."""
+        L = lib()
+        self._ins = [_Inputs(d["vertices"], d.get("kappa"), d.get("mu_override")) for d in problems]
+        count = len(problems)
+        meshes = (Mesh * count)(*[i.mesh for i in self._ins])
+        coefs = (Coefficients * count)(*[i.coef for i in self._ins])
+        ps = (ctypes.c_int32 * count)(*[int(d["p"]) for d in problems])
+        opt = make_options(**options)
+        h = ctypes.c_void_p()
+        _check(L.vsr_setup_batch(count, meshes, ps, coefs, ctypes.byref(opt), ctypes.byref(h)))
+        self._h = h
+        self.members = [Problem(None, int(d["p"]), _handle=ctypes.c_void_p(L.vsr_batch_member(h, i)))
+                        for i, d in enumerate(problems)]
+
+    def __len__(self):
+        return len(self.members)
+
+    def pcg_solve(self, bs, xs, rtol=1e-8, raise_on_noconv=True):
+        count = len(self.members)
+        if len(bs) != count or len(xs) != count:
+            raise ValueError("one b and one x per member")
+        bp = (ctypes.c_void_p * count)(*[_ptr(b).value for b in bs])
+        xp = (ctypes.c_void_p * count)(*[_ptr(x).value for x in xs])
+        infos = (SolveInfo * count)()
+        st = lib().vsr_pcg_solve_batch(self._h, bp, xp, float(rtol), infos)
+        if st != VSR_OK and (raise_on_noconv or st != VSR_ENOCONV):
+            _check(st)
+        return [dict(infos[i].as_dict(), status=st) for i in range(count)]
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            for m in self.members:
+                m._h = None
+            lib().vsr_destroy_batch(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ---------------------------------------------------------------- learned surrogate

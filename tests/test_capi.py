@@ -43,3 +43,25 @@ def test_error_text_and_defaults_without_gpu_work():
     st = L.vsr_setup(ctypes.byref(mesh), 3, None, None, ctypes.byref(h))
     assert st == vsr.VSR_EINVAL and b"NULL" in L.vsr_last_error()
     assert L.vsr_num_dofs(None) == -1
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libvsr.so not built")
+def test_batch_and_tuning_argument_checks_without_gpu_work():
+    from paper_2107_14758_amd import vsr
+    L = vsr.lib()
+    h = ctypes.c_void_p()
+    opt = vsr.Options()
+    L.vsr_default_options(ctypes.byref(opt))
+    assert opt.autotune == 0 and opt.batch_streams == 0 and opt.batch_eager == 0 and opt.tune_cache is None
+    assert L.vsr_setup_batch(0, None, None, None, ctypes.byref(opt), ctypes.byref(h)) == vsr.VSR_EINVAL
+    meshes = (vsr.Mesh * 1)(vsr.Mesh(2, 2, 2, None))
+    ps = (ctypes.c_int32 * 1)(3)
+    st = L.vsr_setup_batch(1, meshes, ps, None, ctypes.byref(opt), ctypes.byref(h))
+    assert st == vsr.VSR_EINVAL and b"member 0" in L.vsr_last_error()
+    assert L.vsr_batch_size(None) == -1 and L.vsr_batch_member(None, 0) is None
+    shapes = (ctypes.c_int32 * 4)(1, 1, 256, 8)
+    assert L.vsr_set_tuning(None, shapes) == vsr.VSR_EINVAL
+    assert L.vsr_pcg_solve_batch(None, None, None, 1e-8, None) == vsr.VSR_EINVAL
+    # the options record keeps the C layout: the new fields follow the stream pointer
+    assert vsr.Options.autotune.offset == vsr.Options.stream.offset + 8
+    assert vsr.Options.tune_cache.offset == vsr.Options.autotune.offset + 16
