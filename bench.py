@@ -7,6 +7,12 @@ V(1,1) vertex-star FDM/sparse preconditioner with FP32 relaxation under FP64
 PCG (the chosen form).  The plain FP64 path is timed beside it.  Inputs are
 resident in HBM before the timed region starts.
 
+--workload batch64 times the batched solve instead: 64 independent problems of uneven
+size (cells per axis from {4, 6, 8, 12}, degree from {4, 7, 11, 15}, half the meshes
+jittered), members spread over streams, one lockstep iteration replayed from a hipGraph,
+launch shapes autotuned per degree; value = total DOFs of the batch / batch solve time.
+The same members solved one after another are timed beside it.
+
 Prints one JSON line.  --gpus above 1 is rejected: this build runs on one GPU.
 """
 import argparse
@@ -23,6 +29,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 WORKLOAD = "poisson_cart_16x16x16_q7"
+WORKLOADS = ("poisson_cart_16x16x16_q7", "poisson_jitter_8x8x8_q15_lognormal", "poisson_jitter_12x12x12_q11_lognormal")
 
 
 def log(*a):
@@ -30,8 +37,12 @@ def log(*a):
 
 
 def kernel_source_sha():
-    with open(os.path.join(ROOT, "paper_2107_14758_amd", "csrc", "kernels.hip"), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of the sources that define the interior patch-solve kernel."""
+    h = hashlib.sha256()
+    for name in ("patch_kernels.h", "device_common.h"):
+        with open(os.path.join(ROOT, "paper_2107_14758_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic():
@@ -53,8 +64,8 @@ def measured_traffic():
         return None
 
 
-def solve_timed(vsr, torch, w, relax_fp32, steps, warmup, profile):
-    prob = vsr.Problem(w["vertices"], w["p"], kappa=w["kappa"], relax_fp32=relax_fp32, seed=0)
+def solve_timed(vsr, torch, w, relax_fp32, steps, warmup, profile, autotune=False):
+    prob = vsr.Problem(w["vertices"], w["p"], kappa=w["kappa"], relax_fp32=relax_fp32, seed=0, autotune=autotune)
     n = prob.n
     f = torch.tensor(w["f"], dtype=torch.float64, device="cuda")
     b = torch.zeros(n, dtype=torch.float64, device="cuda")
@@ -80,6 +91,57 @@ def solve_timed(vsr, torch, w, relax_fp32, steps, warmup, profile):
     out = dict(n=n, seconds=dt, iterations=iters[-1], info=info, stats=stats, setup_s=info["setup_seconds"],
                patches=npatch, factor_entries=nentries)
     prob.close()
+    return out
+
+
+def batch_timed(vsr, torch, W, steps, warmup):
+    """Batched solve of the members of W (FP32 relaxation, autotuned shapes): seconds per
+    batch solve, and per member the iterations; then the members solved one after another."""
+    t0 = time.perf_counter()
+    def progress(i, m):
+        log(f"[bench] member {i}: {W[i]['n']}^3 cells p={W[i]['p']} n={m.n} set up, "
+            f"{time.perf_counter() - t0:.1f} s")
+
+    B = vsr.Batch([dict(vertices=w["vertices"], p=w["p"], kappa=w["kappa"]) for w in W], progress=progress,
+                  relax_fp32=True, seed=0, autotune=True)
+    setup_s = time.perf_counter() - t0
+    log(f"[bench] batch setup {setup_s:.1f} s")
+    bs, xs = [], []
+    for m, w in zip(B.members, W):
+        b = torch.zeros(m.n, dtype=torch.float64, device="cuda")
+        m.load_vector(torch.tensor(w["f"], dtype=torch.float64, device="cuda"), b)
+        bs.append(b)
+        xs.append(torch.zeros_like(b))
+    for _ in range(warmup):
+        infos = B.pcg_solve(bs, xs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        infos = B.pcg_solve(bs, xs)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    log(f"[bench] batched: {1e3 * dt:.1f} ms per batch solve")
+    # the same members one after another (single solves, same shapes)
+    for m, b, x in zip(B.members, bs, xs):
+        m.pcg_solve(b, x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for m, b, x in zip(B.members, bs, xs):
+        m.pcg_solve(b, x)
+    torch.cuda.synchronize()
+    seq = time.perf_counter() - t0
+    log(f"[bench] sequential single solves: {1e3 * seq:.1f} ms")
+    # dominant kernel: the interior patch solve of the largest member, profiled in a single solve
+    big = max(range(len(W)), key=lambda i: B.members[i].n)
+    m = B.members[big]
+    m.set_profiling(True)
+    m.kernel_stats()
+    m.pcg_solve(bs[big], xs[big])
+    stats = m.kernel_stats()
+    m.set_profiling(False)
+    out = dict(seconds=dt, sequential_seconds=seq, infos=infos, setup_s=setup_s, stats=stats, big=big,
+               shapes={int(W[i]["p"]): B.members[i].tuning() for i in range(len(W))})
+    B.close()
     return out
 
 
@@ -114,6 +176,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--workload", default=WORKLOAD, choices=sorted(list(WORKLOADS) + ["batch64"]))
+    ap.add_argument("--autotune", action="store_true", help="single-problem workloads: autotune launch shapes")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (HBM counter calibration)")
     args = ap.parse_args()
@@ -134,35 +198,35 @@ def main():
         return
     from paper_2107_14758_amd import inputs, vsr
     vsr.lib()
-    w = inputs.workload(WORKLOAD, seed=0)
-    log(f"[bench] workload {WORKLOAD}: {len(w['f'])} cells, p={w['p']}")
-    r32 = solve_timed(vsr, torch, w, True, args.steps, args.warmup, profile=True)
+    if args.workload == "batch64":
+        return main_batch(args, torch, inputs, vsr)
+    wname = args.workload
+    w = inputs.workload(wname, seed=0)
+    p = int(w["p"])
+    ncell = len(w["f"])
+    log(f"[bench] workload {wname}: {ncell} cells, p={p}")
+    r32 = solve_timed(vsr, torch, w, True, args.steps, args.warmup, profile=True, autotune=args.autotune)
     log(f"[bench] fp32-relaxation: {r32['iterations']} iterations, {1e3 * r32['seconds'] / args.steps:.2f} ms/solve")
     r64 = None
     if not args.no_fp64:
-        r64 = solve_timed(vsr, torch, w, False, max(3, args.steps // 4), 1, profile=False)
+        r64 = solve_timed(vsr, torch, w, False, max(3, args.steps // 4), 1, profile=False, autotune=args.autotune)
         log(f"[bench] fp64 plain: {r64['iterations']} iterations, "
             f"{1e3 * r64['seconds'] / max(3, args.steps // 4):.2f} ms/solve")
     n = r32["n"]
     ms = 1e3 * r32["seconds"] / args.steps
     value = n / (ms * 1e-3)
-    launches, total_ms, bytes_per_launch = r32["stats"]
-    avg_ms = total_ms / max(launches, 1)
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": achieved / PEAK_HBM_GBS, "traffic": measured_traffic(),
-                "kernel": "k_patch_interior<float,7>", "avg_launch_ms": avg_ms, "launches": launches,
-                "algorithmic_bytes_per_launch": bytes_per_launch}
+    roofline = patch_roofline(r32["stats"], p, measured_traffic() if wname == WORKLOAD and not args.autotune else None)
+    nc = round(ncell ** (1 / 3))
     out = {
         "metric": "PCG DOF/s to 1e-8 rel. residual, FP32-precond vs FP64 plain; iters at p=7,15",
         "value": value, "unit": "DOF/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64 (PCG, outer operator) + f32 (relaxation, coarse, inner operator)",
         "data": "synthetic (seeded U[-1,1] RHS at quadrature points)",
-        "config": {"workload": WORKLOAD, "cells": [16, 16, 16], "p": 7, "dofs": n, "rtol": 1e-8,
+        "config": {"workload": wname, "cells": [nc, nc, nc], "p": p, "dofs": n, "rtol": 1e-8,
                    "preconditioner": "hybrid V(1,1), vertex-star patches at all vertices, Q1 coarse",
-                   "parallelism": "single GPU"},
-        "iterations_p7": r32["iterations"],
+                   "autotune": bool(args.autotune), "parallelism": "single GPU"},
+        f"iterations_p{p}": r32["iterations"],
         "true_rel_residual": r32["info"]["true_rel_residual"],
         "setup_seconds": r32["setup_s"],
         "patches": r32["patches"], "factor_entries": r32["factor_entries"],
@@ -174,7 +238,50 @@ def main():
                              "iterations": r64["iterations"], "true_rel_residual": r64["info"]["true_rel_residual"]}
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
-        out["cpu_baseline"] = cpu_baseline(7, cells=6)
+        out["cpu_baseline"] = cpu_baseline(p, cells=6 if p <= 7 else 3)
+    print(json.dumps(out), flush=True)
+
+
+def patch_roofline(stats, p, traffic):
+    launches, total_ms, bytes_per_launch = stats
+    avg_ms = total_ms / max(launches, 1)
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": achieved / PEAK_HBM_GBS, "traffic": traffic, "kernel": f"k_patch_interior<float,{p}>",
+            "avg_launch_ms": avg_ms, "launches": launches, "algorithmic_bytes_per_launch": bytes_per_launch}
+
+
+def main_batch(args, torch, inputs, vsr):
+    W = inputs.batch_workload(64, seed=0)
+    n_total = sum((int(w["p"]) * int(w["n"]) - 1) ** 3 for w in W)
+    log(f"[bench] batch of {len(W)} problems, {n_total} DOFs in total")
+    steps, warmup = max(1, min(args.steps, 5)), max(1, min(args.warmup, 1))
+    r = batch_timed(vsr, torch, W, steps, warmup)
+    infos = r["infos"]
+    big = r["big"]
+    out = {
+        "metric": "PCG DOF/s to 1e-8 rel. residual, batch of 64 uneven problems",
+        "value": n_total / r["seconds"], "unit": "DOF/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
+        "ms_per_step": 1e3 * r["seconds"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64 (PCG, outer operator) + f32 (relaxation, coarse, inner operator)",
+        "data": "synthetic (seeded U[-1,1] RHS at quadrature points; seeded sizes, degrees and jitter)",
+        "config": {"workload": "batch64_uneven_p4-15", "problems": len(W), "dofs": n_total, "rtol": 1e-8,
+                   "cells_per_axis": sorted(set(int(w["n"]) for w in W)), "degrees": sorted(set(int(w["p"]) for w in W)),
+                   "launch": "lockstep iteration replayed from one hipGraph over 4 streams",
+                   "autotuned_shapes": {str(k): list(v) for k, v in sorted(r["shapes"].items())},
+                   "parallelism": "single GPU"},
+        "iterations_min_max": [min(i["iterations"] for i in infos), max(i["iterations"] for i in infos)],
+        "max_true_rel_residual": max(i["true_rel_residual"] for i in infos),
+        "setup_seconds": r["setup_s"],
+        "sequential": {"value": n_total / r["sequential_seconds"], "unit": "DOF/s",
+                       "ms": 1e3 * r["sequential_seconds"]},
+        "roofline": patch_roofline(r["stats"], int(W[big]["p"]), None),
+    }
+    out["roofline"]["member"] = f"{W[big]['n']}^3 cells p={W[big]['p']} (largest), single solve"
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline(4, cells=4)
+        out["cpu_baseline"]["sample"] += " (the smallest member class of the batch)"
     print(json.dumps(out), flush=True)
 
 

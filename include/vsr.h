@@ -233,6 +233,12 @@ vsr_status vsr_setup_batch(int32_t count, const vsr_mesh *meshes, const int32_t 
                            const vsr_coefficients *coefs, const vsr_options *opt,
                            vsr_batch **out);
 
+/* Form a batch from `count` problems already set up with vsr_setup.  On success the batch
+ * takes ownership of them (vsr_destroy_batch frees them; do not vsr_destroy them); on
+ * error they stay with the caller.  Only opt->batch_streams and opt->batch_eager are read
+ * (opt may be NULL: defaults).  A problem may belong to one batch only. */
+vsr_status vsr_batch_create(int32_t count, vsr_problem *const *members, const vsr_options *opt, vsr_batch **out);
+
 int32_t vsr_batch_size(const vsr_batch *batch);
 
 /* Member i, owned by the batch (valid until vsr_destroy_batch): use it for

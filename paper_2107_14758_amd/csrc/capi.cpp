@@ -853,23 +853,21 @@ vsr_status vsr_set_tuning(vsr_problem *P, const int32_t shapes[4]) {
     });
 }
 
-vsr_status vsr_setup_batch(int32_t count, const vsr_mesh *meshes, const int32_t *p, const vsr_coefficients *coefs,
-                           const vsr_options *opt, vsr_batch **out) {
+vsr_status vsr_batch_create(int32_t count, vsr_problem *const *members, const vsr_options *opt, vsr_batch **out) {
     return guarded([&] {
         if (!out) throw Error(VSR_EINVAL, "NULL argument");
         *out = nullptr;
-        if (count < 1 || !meshes || !p) throw Error(VSR_EINVAL, "a batch needs count >= 1, meshes and degrees");
+        if (count < 1 || !members) throw Error(VSR_EINVAL, "a batch needs count >= 1 members");
+        for (int32_t i = 0; i < count; ++i) {
+            if (!members[i]) throw Error(VSR_EINVAL, "NULL member " + std::to_string(i));
+            for (int32_t j = 0; j < i; ++j)
+                if (members[j] == members[i]) throw Error(VSR_EINVAL, "member " + std::to_string(i) + " repeated");
+        }
         vsr_options o;
         if (opt) o = *opt;
         else vsr_default_options(&o);
         if (o.batch_streams < 0 || o.batch_streams > 16) throw Error(VSR_EINVAL, "batch_streams must be in [0, 16]");
         auto B = std::make_unique<vsr_batch>();
-        for (int32_t i = 0; i < count; ++i) {
-            vsr_problem *P = nullptr;
-            vsr_status st = vsr_setup(&meshes[i], p[i], coefs ? &coefs[i] : nullptr, &o, &P);
-            if (st != VSR_OK) throw Error(st, "member " + std::to_string(i) + ": " + vsr::g_last_error_text);
-            B->members.push_back(P);
-        }
         const int ns = std::min<int>(o.batch_streams > 0 ? o.batch_streams : 4, count);
         B->streams.resize(ns, nullptr);
         for (auto &st : B->streams) VSR_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
@@ -879,23 +877,45 @@ vsr_status vsr_setup_batch(int32_t count, const vsr_mesh *meshes, const int32_t 
         // largest member first onto the least loaded stream
         std::vector<int> order(count);
         for (int i = 0; i < count; ++i) order[i] = i;
-        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return B->members[a]->n > B->members[b]->n; });
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return members[a]->n > members[b]->n; });
         std::vector<double> load(ns, 0.0);
         B->stream_of.assign(count, 0);
         for (int i : order) {
             int j = (int)(std::min_element(load.begin(), load.end()) - load.begin());
             B->stream_of[i] = j;
-            load[j] += (double)B->members[i]->n;
+            load[j] += (double)members[i]->n;
         }
         std::vector<const double *> sc(count);
-        for (int i = 0; i < count; ++i) sc[i] = B->members[i]->scal;
+        for (int i = 0; i < count; ++i) sc[i] = members[i]->scal;
         VSR_HIP(hipMalloc((void **)&B->scals, sizeof(double *) * count));
         VSR_HIP(hipMemcpy(B->scals, sc.data(), sizeof(double *) * count, hipMemcpyHostToDevice));
         VSR_HIP(hipMalloc((void **)&B->active, sizeof(int)));
         VSR_HIP(hipHostMalloc((void **)&B->host_active, sizeof(int), hipHostMallocDefault));
         B->eager = o.batch_eager != 0;
+        B->members.assign(members, members + count);   // ownership passes only once nothing can fail
         *out = B.release();
     });
+}
+
+vsr_status vsr_setup_batch(int32_t count, const vsr_mesh *meshes, const int32_t *p, const vsr_coefficients *coefs,
+                           const vsr_options *opt, vsr_batch **out) {
+    std::vector<vsr_problem *> made;
+    vsr_status st = guarded([&] {
+        if (!out) throw Error(VSR_EINVAL, "NULL argument");
+        *out = nullptr;
+        if (count < 1 || !meshes || !p) throw Error(VSR_EINVAL, "a batch needs count >= 1, meshes and degrees");
+        for (int32_t i = 0; i < count; ++i) {
+            vsr_problem *P = nullptr;
+            vsr_status s1 = vsr_setup(&meshes[i], p[i], coefs ? &coefs[i] : nullptr, opt, &P);
+            if (s1 != VSR_OK) throw Error(s1, "member " + std::to_string(i) + ": " + vsr::g_last_error_text);
+            made.push_back(P);
+        }
+        vsr_status s2 = vsr_batch_create(count, made.data(), opt, out);
+        if (s2 != VSR_OK) throw Error(s2, vsr::g_last_error_text);
+        made.clear();
+    });
+    for (vsr_problem *P : made) delete P;
+    return st;
 }
 
 int32_t vsr_batch_size(const vsr_batch *B) { return B ? (int32_t)B->members.size() : -1; }

@@ -76,6 +76,24 @@ WORKLOADS = {
 }
 
 
+BATCH_CELLS = (4, 6, 8, 12)
+BATCH_DEGREES = (4, 7, 11, 15)
+
+
+def batch_workload(count=64, seed=0, jitter=0.15):
+    """Independent problems of uneven size for a batched solve: cells per axis drawn from
+    {4, 6, 8, 12}, degree from {4, 7, 11, 15}, half the meshes (a seeded coin per member)
+    with interior vertices jittered by U[-jitter h, jitter h], kappa = 1, RHS U[-1, 1] at the
+    quadrature points.  Returns a list of make_problem dicts."""
+    rng = np.random.default_rng(seed)
+    ns = rng.choice(BATCH_CELLS, count)
+    ps = rng.choice(BATCH_DEGREES, count)
+    jit = rng.random(count) < 0.5
+    seeds = rng.integers(0, 2 ** 31, count)
+    return [make_problem(int(n), int(p), seed=int(sd), jitter=jitter if j else 0.0)
+            for n, p, j, sd in zip(ns, ps, jit, seeds)]
+
+
 def workload(name, seed=0):
     w = WORKLOADS[name]
     return make_problem(w["n"], w["p"], seed=seed, jitter=w["jitter"], lognormal=w["lognormal"])

@@ -85,6 +85,8 @@ def lib():
     L.vsr_set_tuning.argtypes = [P, ctypes.POINTER(ctypes.c_int32)]
     L.vsr_setup_batch.argtypes = [ctypes.c_int32, ctypes.POINTER(Mesh), ctypes.POINTER(ctypes.c_int32),
                                   ctypes.POINTER(Coefficients), ctypes.POINTER(Options), ctypes.POINTER(P)]
+    L.vsr_batch_create.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(Options),
+                                   ctypes.POINTER(P)]
     L.vsr_batch_size.argtypes = [P]
     L.vsr_batch_size.restype = ctypes.c_int32
     L.vsr_batch_member.argtypes = [P, ctypes.c_int32]
@@ -97,7 +99,7 @@ def lib():
     L.vsr_last_error.restype = ctypes.c_char_p
     for name in ("vsr_setup", "vsr_load_vector", "vsr_apply_operator", "vsr_apply_relaxation", "vsr_pcg_solve",
                  "vsr_get_damping", "vsr_set_profiling", "vsr_kernel_stats", "vsr_factor_info", "vsr_get_tuning", "vsr_set_tuning",
-                 "vsr_setup_batch", "vsr_pcg_solve_batch"):
+                 "vsr_setup_batch", "vsr_batch_create", "vsr_pcg_solve_batch"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -232,20 +234,30 @@ class Batch:
     """Independent problems solved together by the batched PCG (members on several streams,
     one lockstep iteration replayed from a hipGraph)."""
 
-    def __init__(self, problems, **options):
-        """problems: list of dicts with keys vertices, p and optionally kappa, mu_override."""
+    def __init__(self, problems, progress=None, **options):
+        """problems: list of dicts with keys vertices, p and optionally kappa, mu_override.
+        Members are set up one at a time (progress(i, member) is called after each), then
+        handed to the batch."""
         L = lib()
-        self._ins = [_Inputs(d["vertices"], d.get("kappa"), d.get("mu_override")) for d in problems]
-        count = len(problems)
-        meshes = (Mesh * count)(*[i.mesh for i in self._ins])
-        coefs = (Coefficients * count)(*[i.coef for i in self._ins])
-        ps = (ctypes.c_int32 * count)(*[int(d["p"]) for d in problems])
-        opt = make_options(**options)
-        h = ctypes.c_void_p()
-        _check(L.vsr_setup_batch(count, meshes, ps, coefs, ctypes.byref(opt), ctypes.byref(h)))
+        members = []
+        try:
+            for i, d in enumerate(problems):
+                members.append(Problem(d["vertices"], int(d["p"]), kappa=d.get("kappa"),
+                                       mu_override=d.get("mu_override"), **options))
+                if progress is not None:
+                    progress(i, members[-1])
+            opt = make_options(**options)
+            handles = (ctypes.c_void_p * len(members))(*[m._h.value for m in members])
+            h = ctypes.c_void_p()
+            _check(L.vsr_batch_create(len(members), handles, ctypes.byref(opt), ctypes.byref(h)))
+        except BaseException:
+            for m in members:
+                m.close()
+            raise
+        for m in members:
+            m._owned = False   # the batch frees them
         self._h = h
-        self.members = [Problem(None, int(d["p"]), _handle=ctypes.c_void_p(L.vsr_batch_member(h, i)))
-                        for i, d in enumerate(problems)]
+        self.members = members
 
     def __len__(self):
         return len(self.members)

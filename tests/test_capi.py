@@ -65,3 +65,14 @@ def test_batch_and_tuning_argument_checks_without_gpu_work():
     # the options record keeps the C layout: the new fields follow the stream pointer
     assert vsr.Options.autotune.offset == vsr.Options.stream.offset + 8
     assert vsr.Options.tune_cache.offset == vsr.Options.autotune.offset + 16
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libvsr.so not built")
+def test_batch_create_argument_checks_without_gpu_work():
+    from paper_2107_14758_amd import vsr
+    L = vsr.lib()
+    h = ctypes.c_void_p()
+    assert L.vsr_batch_create(0, None, None, ctypes.byref(h)) == vsr.VSR_EINVAL
+    null_members = (ctypes.c_void_p * 2)(None, None)
+    st = L.vsr_batch_create(2, null_members, None, ctypes.byref(h))
+    assert st == vsr.VSR_EINVAL and b"NULL member 0" in L.vsr_last_error()
