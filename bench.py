@@ -140,7 +140,8 @@ def batch_timed(vsr, torch, W, steps, warmup):
     stats = m.kernel_stats()
     m.set_profiling(False)
     out = dict(seconds=dt, sequential_seconds=seq, infos=infos, setup_s=setup_s, stats=stats, big=big,
-               shapes={int(W[i]["p"]): B.members[i].tuning() for i in range(len(W))})
+               shapes={f"p{W[i]['p']}-{'jittered' if W[i]['jitter'] else 'cartesian'}": B.members[i].tuning()
+                       for i in range(len(W))})
     B.close()
     return out
 

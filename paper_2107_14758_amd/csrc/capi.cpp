@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -48,8 +49,10 @@ double now_s() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
+// A 1D transfer matrix as a padded band: row o covers inputs start[o] .. start[o] + bw.
 struct Table {
-    int *rowptr = nullptr, *col = nullptr;
+    int *start = nullptr;
+    int bw = 1;
     double *w64 = nullptr;
     float *w32 = nullptr;
     int n_out = 0, n_in = 0;
@@ -158,9 +161,9 @@ void relax_apply(vsr_problem *P, const Tin *in, T *out, T alpha, T beta) {
     const int L[3] = {P->d.Lx, P->d.Ly, P->d.Lz};
     T *t1 = (T *)P->t1, *t2 = (T *)P->t2, *rF = (T *)P->rF, *zF = (T *)P->zF, *U = (T *)P->U;
     const Table *TT = P->tab[0], *Tp = P->tab[1];
-    launch_axis_pass<Tin, T>(TT[0].rowptr, TT[0].col, wt<T>(TT[0]), 0, L, L, in, t1, T(1), T(0), P->ex());
-    launch_axis_pass<T, T>(TT[1].rowptr, TT[1].col, wt<T>(TT[1]), 1, L, L, t1, t2, T(1), T(0), P->ex());
-    launch_axis_pass<T, T>(TT[2].rowptr, TT[2].col, wt<T>(TT[2]), 2, L, L, t2, rF, T(1), T(0), P->ex());
+    launch_axis_pass<Tin, T>(TT[0].start, TT[0].bw, wt<T>(TT[0]), 0, L, L, in, t1, T(1), T(0), P->ex());
+    launch_axis_pass<T, T>(TT[1].start, TT[1].bw, wt<T>(TT[1]), 1, L, L, t1, t2, T(1), T(0), P->ex());
+    launch_axis_pass<T, T>(TT[2].start, TT[2].bw, wt<T>(TT[2]), 2, L, L, t2, rF, T(1), T(0), P->ex());
     hipEvent_t e0 = nullptr, e1 = nullptr;
     const bool prof = P->profiling && !P->capturing;
     if (prof) {
@@ -182,9 +185,9 @@ void relax_apply(vsr_problem *P, const Tin *in, T *out, T alpha, T beta) {
     launch_patch_boundary<T>(P->d, P->n_bnd, P->bdesc, P->boff, (const T *)P->fbnd, (const T *)P->mu_sur, (const T *)P->lam,
                              (const T *)P->afc, rF, U, P->ex());
     launch_patch_assemble<T>(P->d, P->opt.interior_patches_only, U, zF, P->ex());
-    launch_axis_pass<T, T>(Tp[0].rowptr, Tp[0].col, wt<T>(Tp[0]), 0, L, L, zF, t1, T(1), T(0), P->ex());
-    launch_axis_pass<T, T>(Tp[1].rowptr, Tp[1].col, wt<T>(Tp[1]), 1, L, L, t1, t2, T(1), T(0), P->ex());
-    launch_axis_pass<T, T>(Tp[2].rowptr, Tp[2].col, wt<T>(Tp[2]), 2, L, L, t2, out, alpha, beta, P->ex());
+    launch_axis_pass<T, T>(Tp[0].start, Tp[0].bw, wt<T>(Tp[0]), 0, L, L, zF, t1, T(1), T(0), P->ex());
+    launch_axis_pass<T, T>(Tp[1].start, Tp[1].bw, wt<T>(Tp[1]), 1, L, L, t1, t2, T(1), T(0), P->ex());
+    launch_axis_pass<T, T>(Tp[2].start, Tp[2].bw, wt<T>(Tp[2]), 2, L, L, t2, out, alpha, beta, P->ex());
     VSR_HIP(hipGetLastError());
 }
 
@@ -200,13 +203,13 @@ void coarse_apply(vsr_problem *P, const Tin *in, T *out, T alpha, T beta) {
     const int d1[3] = {c[0], L[1], L[2]}, d2[3] = {c[0], c[1], L[2]}, d3[3] = {c[0], c[1], c[2]};
     T *c1 = (T *)P->c1, *c2 = (T *)P->c2, *c3 = (T *)P->c3, *c4 = (T *)P->c4;
     const Table *R = P->tab[2], *Pr = P->tab[3];
-    launch_axis_pass<Tin, T>(R[0].rowptr, R[0].col, wt<T>(R[0]), 0, L, d1, in, c1, T(1), T(0), P->ex());
-    launch_axis_pass<T, T>(R[1].rowptr, R[1].col, wt<T>(R[1]), 1, d1, d2, c1, c2, T(1), T(0), P->ex());
-    launch_axis_pass<T, T>(R[2].rowptr, R[2].col, wt<T>(R[2]), 2, d2, d3, c2, c3, T(1), T(0), P->ex());
+    launch_axis_pass<Tin, T>(R[0].start, R[0].bw, wt<T>(R[0]), 0, L, d1, in, c1, T(1), T(0), P->ex());
+    launch_axis_pass<T, T>(R[1].start, R[1].bw, wt<T>(R[1]), 1, d1, d2, c1, c2, T(1), T(0), P->ex());
+    launch_axis_pass<T, T>(R[2].start, R[2].bw, wt<T>(R[2]), 2, d2, d3, c2, c3, T(1), T(0), P->ex());
     launch_dense_gemv<T>(P->nc, (const T *)P->A0inv, c3, c4, T(1), T(0), P->ex());
-    launch_axis_pass<T, T>(Pr[2].rowptr, Pr[2].col, wt<T>(Pr[2]), 2, d3, d2, c4, c2, T(1), T(0), P->ex());
-    launch_axis_pass<T, T>(Pr[1].rowptr, Pr[1].col, wt<T>(Pr[1]), 1, d2, d1, c2, c1, T(1), T(0), P->ex());
-    launch_axis_pass<T, T>(Pr[0].rowptr, Pr[0].col, wt<T>(Pr[0]), 0, d1, L, c1, out, alpha, beta, P->ex());
+    launch_axis_pass<T, T>(Pr[2].start, Pr[2].bw, wt<T>(Pr[2]), 2, d3, d2, c4, c2, T(1), T(0), P->ex());
+    launch_axis_pass<T, T>(Pr[1].start, Pr[1].bw, wt<T>(Pr[1]), 1, d2, d1, c2, c1, T(1), T(0), P->ex());
+    launch_axis_pass<T, T>(Pr[0].start, Pr[0].bw, wt<T>(Pr[0]), 0, d1, L, c1, out, alpha, beta, P->ex());
     VSR_HIP(hipGetLastError());
 }
 
@@ -369,8 +372,8 @@ bool tune_from_file(const char *path, const std::string &key, Tuning &t) {
     while (std::getline(f, line)) {   // the last entry for a key wins
         if (line.compare(0, key.size(), key) != 0 || line.size() <= key.size() || line[key.size()] != ' ') continue;
         Tuning c;
-        if (std::sscanf(line.c_str() + key.size(), " cpw64=%d cpw32=%d axis_block=%d patch_unroll=%d", &c.op_cpw64,
-                        &c.op_cpw32, &c.axis_block, &c.patch_unroll) == 4) {
+        if (std::sscanf(line.c_str() + key.size(), " cpw64=%d cpw32=%d axis_block=%d patch_unroll=%d split64=%d split32=%d",
+                        &c.op_cpw64, &c.op_cpw32, &c.axis_block, &c.patch_unroll, &c.opg_split64, &c.opg_split32) == 6) {
             t = c;
             found = true;
         }
@@ -435,14 +438,21 @@ void autotune(vsr_problem *P) {
             pick(P->tune.op_cpw32, {1, 2, 4}, [&] { op_apply<float>(P, (const float *)P->z1, (float *)P->az); });
         }
     }
+    if (!P->cartesian) {
+        pick(P->tune.opg_split64, {1, 2}, [&] { op_apply<double>(P, P->vp, P->vq); });
+        if (P->fp32) {
+            launch_cast<double, float>(P->n, P->vp, (float *)P->z1, P->ex());
+            pick(P->tune.opg_split32, {1, 2}, [&] { op_apply<float>(P, (const float *)P->z1, (float *)P->az); });
+        }
+    }
     const int L[3] = {P->d.Lx, P->d.Ly, P->d.Lz};
     auto passes = [&](auto zero) {
         using T = decltype(zero);
         const Table *TT = P->tab[0], *Tp = P->tab[1];
         T *a = (T *)P->t1, *b = (T *)P->t2;
         for (int ax = 0; ax < 3; ++ax) {
-            launch_axis_pass<T, T>(TT[ax].rowptr, TT[ax].col, wt<T>(TT[ax]), ax, L, L, a, b, T(1), T(0), P->ex());
-            launch_axis_pass<T, T>(Tp[ax].rowptr, Tp[ax].col, wt<T>(Tp[ax]), ax, L, L, b, a, T(1), T(0), P->ex());
+            launch_axis_pass<T, T>(TT[ax].start, TT[ax].bw, wt<T>(TT[ax]), ax, L, L, a, b, T(1), T(0), P->ex());
+            launch_axis_pass<T, T>(Tp[ax].start, Tp[ax].bw, wt<T>(Tp[ax]), ax, L, L, b, a, T(1), T(0), P->ex());
         }
     };
     auto patch = [&](auto zero) {
@@ -471,18 +481,44 @@ void autotune(vsr_problem *P) {
     if (P->opt.tune_cache) {
         std::ofstream f(P->opt.tune_cache, std::ios::app);
         f << key << " cpw64=" << P->tune.op_cpw64 << " cpw32=" << P->tune.op_cpw32 << " axis_block=" << P->tune.axis_block
-          << " patch_unroll=" << P->tune.patch_unroll << "\n";
+          << " patch_unroll=" << P->tune.patch_unroll << " split64=" << P->tune.opg_split64
+          << " split32=" << P->tune.opg_split32 << "\n";
     }
 }
 
+// Rows of a 1D transfer matrix touch one contiguous window of inputs; store them as a
+// band of the widest window, each start clamped so the window stays inside the input.
 Table make_table(vsr_problem *P, const AxisTable &t) {
     Table r;
     r.n_out = t.n_out;
     r.n_in = t.n_in;
-    r.rowptr = P->upload(t.rowptr);
-    r.col = P->upload(t.col);
-    r.w64 = P->upload(t.w);
-    r.w32 = P->upload_as<float>(t.w);
+    int bw = 1;
+    for (int o = 0; o < t.n_out; ++o) {
+        int lo = INT32_MAX, hi = -1;
+        for (int k = t.rowptr[o]; k < t.rowptr[o + 1]; ++k) {
+            lo = std::min(lo, t.col[k]);
+            hi = std::max(hi, t.col[k]);
+        }
+        if (hi >= lo) bw = std::max(bw, hi - lo + 1);
+    }
+    bw = std::max(1, std::min(bw, t.n_in));
+    std::vector<int> start(std::max(t.n_out, 1), 0);
+    std::vector<double> w((size_t)std::max(t.n_out, 1) * bw, 0.0);
+    for (int o = 0; o < t.n_out; ++o) {
+        int lo = INT32_MAX;
+        for (int k = t.rowptr[o]; k < t.rowptr[o + 1]; ++k) lo = std::min(lo, t.col[k]);
+        int s0 = lo == INT32_MAX ? 0 : std::max(0, std::min(lo, t.n_in - bw));
+        start[o] = s0;
+        for (int k = t.rowptr[o]; k < t.rowptr[o + 1]; ++k) {
+            int j = t.col[k] - s0;
+            if (j < 0 || j >= bw) throw Error(VSR_EINVAL, "transfer table row does not fit its band");
+            w[(size_t)o * bw + j] += t.w[k];
+        }
+    }
+    r.bw = bw;
+    r.start = P->upload(start);
+    r.w64 = P->upload(w);
+    r.w32 = P->upload_as<float>(w);
     return r;
 }
 
@@ -831,25 +867,29 @@ vsr_status vsr_factor_info(const vsr_problem *P, int64_t *num_patches, int64_t *
 
 void vsr_destroy(vsr_problem *P) { delete P; }
 
-vsr_status vsr_get_tuning(const vsr_problem *P, int32_t shapes[4]) {
+vsr_status vsr_get_tuning(const vsr_problem *P, int32_t shapes[6]) {
     return guarded([&] {
         if (!P || !shapes) throw Error(VSR_EINVAL, "NULL argument");
         shapes[0] = P->tune.op_cpw64;
         shapes[1] = P->tune.op_cpw32;
         shapes[2] = P->tune.axis_block;
         shapes[3] = P->tune.patch_unroll;
+        shapes[4] = P->tune.opg_split64;
+        shapes[5] = P->tune.opg_split32;
     });
 }
 
-vsr_status vsr_set_tuning(vsr_problem *P, const int32_t shapes[4]) {
+vsr_status vsr_set_tuning(vsr_problem *P, const int32_t shapes[6]) {
     return guarded([&] {
         if (!P || !shapes) throw Error(VSR_EINVAL, "NULL argument");
         auto cpw_ok = [](int c) { return c == 1 || c == 2 || c == 4; };
         if (!cpw_ok(shapes[0]) || !cpw_ok(shapes[1])) throw Error(VSR_EINVAL, "operator cells per workgroup must be 1, 2 or 4");
         if (shapes[2] < 64 || shapes[2] > 1024 || shapes[2] % 64) throw Error(VSR_EINVAL, "block must be a multiple of 64 in [64, 1024]");
         if (shapes[3] != 4 && shapes[3] != 8 && shapes[3] != 16) throw Error(VSR_EINVAL, "unroll must be 4, 8 or 16");
+        for (int i = 4; i < 6; ++i)
+            if (shapes[i] < 0 || shapes[i] > 2) throw Error(VSR_EINVAL, "workgroups per cell must be 0, 1 or 2");
         VSR_HIP(hipStreamSynchronize(P->stream));
-        P->tune = Tuning{shapes[0], shapes[1], shapes[2], shapes[3]};
+        P->tune = Tuning{shapes[0], shapes[1], shapes[2], shapes[3], shapes[4], shapes[5]};
     });
 }
 

@@ -20,6 +20,8 @@ struct Tuning {
     int op_cpw32 = 1;       // same, FP32 (both 1, 2 or 4; above 1 only for p <= 7)
     int axis_block = 256;   // threads per block of the 1D lattice passes (64..1024)
     int patch_unroll = 8;   // column loads in flight per thread in the patch panels (4, 8, 16)
+    int opg_split64 = 0;    // workgroups per cell of the general operator, FP64 (1, 2; 0: by size)
+    int opg_split32 = 0;    // same, FP32
 };
 
 // Where a launch goes: its stream, an optional gate (a device flag; when it is nonzero
@@ -39,9 +41,10 @@ void launch_op_general(const Dims &d, const T *IDq, const T *Gw, const T *x, T *
 void launch_load_vector(const Dims &d, const double *IDq, const double *wdet, const double *f, double *b,
                         const Exec &e);
 
-// One 1D lattice pass: out = alpha * (table along `axis`) in + beta * out.
+// One 1D lattice pass: out = alpha * (banded 1D matrix along `axis`) in + beta * out; output o
+// reads in[start[o] + j], j < bw, along the axis with weight w[o * bw + j].
 template <typename Tin, typename Tout>
-void launch_axis_pass(const int *rowptr, const int *col, const Tout *w, int axis, const int in_dims[3],
+void launch_axis_pass(const int *start, int bw, const Tout *w, int axis, const int in_dims[3],
                       const int out_dims[3], const Tin *in, Tout *out, Tout alpha, Tout beta, const Exec &e);
 
 struct PatchArgs {

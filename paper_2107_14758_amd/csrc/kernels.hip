@@ -84,21 +84,29 @@ __global__ void __launch_bounds__(256) k_op_kron(const double *__restrict__ gate
 // General trilinear cell: y_K = (grad phi)^T Gw (grad phi) x_K with the q^3 GLL rule
 // (Sec. 2.1, 2.7).  Thread (b, a) owns one z-column of quadrature points; the x and y
 // contractions run per z-slab through LDS, the z contraction and the metric in registers.
-template <typename T, int P>
-__global__ void __launch_bounds__(1024) k_op_general(const double *__restrict__ gate, Dims d, const T *__restrict__ IDq, const T *__restrict__ Gw,
-                                                     const T *__restrict__ x, T *__restrict__ y) {
+// S workgroups share a cell, each owning a band of ceil(Q/S) b-rows of columns (fewer
+// registers' worth of columns per workgroup: with S = 2 the FP64 column state of p = 14, 15
+// fits without spills); their partial outputs meet in the atomic additions into y.
+constexpr int opg_rows(int P, int S) { return (QOF(P) + S - 1) / S; }
+constexpr int opg_threads(int P, int S) { return (opg_rows(P, S) * QOF(P) + 63) / 64 * 64; }
+
+template <typename T, int P, int S>
+__global__ void __launch_bounds__(opg_threads(P, S)) k_op_general(const double *__restrict__ gate, Dims d,
+                                                                   const T *__restrict__ IDq, const T *__restrict__ Gw,
+                                                                   const T *__restrict__ x, T *__restrict__ y) {
     if (gated(gate)) return;
-    constexpr int N1 = P + 1, Q = QOF(P), Q2 = Q * Q, Q3 = Q2 * Q;
-    __shared__ T sI[Q * N1], sD[Q * N1], xs[N1 * N1], X1[N1 * Q], DX1[N1 * Q], S0[Q2], S1[Q2], S2[Q2];
+    constexpr int N1 = P + 1, Q = QOF(P), Q2 = Q * Q, Q3 = Q2 * Q, BR = opg_rows(P, S);
+    __shared__ T sI[Q * N1], sD[Q * N1], xs[N1 * N1], X1[N1 * Q], DX1[N1 * Q], S0[BR * Q], S1[BR * Q], S2[BR * Q];
     const int tid = threadIdx.x, nt = blockDim.x;
     for (int t = tid; t < Q * N1; t += nt) {
         sI[t] = IDq[t];
         sD[t] = IDq[Q * N1 + t];
     }
-    const int64_t e = blockIdx.x;
+    const int64_t e = blockIdx.x / S;
+    const int b0 = (int)(blockIdx.x % S) * BR, nb = min(BR, Q - b0);
     const int ex = (int)(e % d.nx), ey = (int)((e / d.nx) % d.ny), ez = (int)(e / ((int64_t)d.nx * d.ny));
-    const bool col = tid < Q2;
-    const int b = tid / Q, a = tid % Q;
+    const bool col = tid < nb * Q;
+    const int b = b0 + tid / Q, a = tid % Q;
     T AA[N1], AB[N1], BA[N1];
 #pragma unroll
     for (int k = 0; k < N1; ++k) {
@@ -138,7 +146,7 @@ __global__ void __launch_bounds__(1024) k_op_general(const double *__restrict__ 
 #pragma unroll
     for (int k = 0; k < N1; ++k) AAo[k] = ABo[k] = BAo[k] = 0;
     if (col) {
-        const T *g = Gw + e * 6 * (int64_t)Q3;
+        const T *g = Gw + e * 6 * (int64_t)Q3 + b * Q + a;
         for (int c = 0; c < Q; ++c) {
             T ux = 0, uy = 0, uz = 0;
 #pragma unroll
@@ -147,7 +155,7 @@ __global__ void __launch_bounds__(1024) k_op_general(const double *__restrict__ 
                 uy += sI[c * N1 + k] * AB[k];
                 uz += sD[c * N1 + k] * AA[k];
             }
-            int pt = c * Q2 + tid;
+            const int pt = c * Q2;
             T gxx = g[pt], gyy = g[Q3 + pt], gzz = g[2 * Q3 + pt], gxy = g[3 * Q3 + pt], gxz = g[4 * Q3 + pt],
               gyz = g[5 * Q3 + pt];
             T vx = gxx * ux + gxy * uy + gxz * uz;
@@ -173,9 +181,9 @@ __global__ void __launch_bounds__(1024) k_op_general(const double *__restrict__ 
         for (int t = tid; t < N1 * Q; t += nt) {
             int jj = t / Q, aa = t % Q;
             T s0 = 0, s1 = 0;
-            for (int bb = 0; bb < Q; ++bb) {
-                s0 += sI[bb * N1 + jj] * S0[bb * Q + aa] + sD[bb * N1 + jj] * S1[bb * Q + aa];
-                s1 += sI[bb * N1 + jj] * S2[bb * Q + aa];
+            for (int bb = 0; bb < nb; ++bb) {
+                s0 += sI[(b0 + bb) * N1 + jj] * S0[bb * Q + aa] + sD[(b0 + bb) * N1 + jj] * S1[bb * Q + aa];
+                s1 += sI[(b0 + bb) * N1 + jj] * S2[bb * Q + aa];
             }
             X1[t] = s0;
             DX1[t] = s1;
@@ -238,26 +246,30 @@ __global__ void __launch_bounds__(1024) k_load_vector(const double *__restrict__
 }
 
 // ====================================================================== lattice passes
-// out = alpha * M_axis in + beta * out, with M given by a CSR table over output positions
-// along one axis (the GLL<->FDM basis change of Sec. 2.4 and the Q1 transfers of Sec. 2.5).
+// out = alpha * M_axis in + beta * out for a 1D matrix M applied along `axis` (the GLL <->
+// FDM basis change of Sec. 2.4 and the Q1 transfers of Sec. 2.5).  Output o along the axis
+// reads the window in[start[o] .. start[o] + bw) along that axis with dense weights
+// w[o * bw + j] (zero where M has no entry): a fixed trip count, wave-uniform rows and
+// weights for the y and z passes, and coalesced loads along x.
 template <typename Tin, typename Tout>
-__global__ void k_axis_pass(const double *__restrict__ gate, const int *__restrict__ rowptr, const int *__restrict__ col, const Tout *__restrict__ w,
-                            int axis, int ix, int iy, int iz, int ox, int oy, int oz, const Tin *__restrict__ in,
-                            Tout *__restrict__ out, Tout alpha, Tout beta) {
+__global__ void k_axis_pass(const double *__restrict__ gate, const int *__restrict__ start, const Tout *__restrict__ w,
+                            int bw, int axis, int ix, int iy, int iz, int ox, int oy, int oz,
+                            const Tin *__restrict__ in, Tout *__restrict__ out, Tout alpha, Tout beta) {
     if (gated(gate)) return;
     const int64_t total = (int64_t)ox * oy * oz;
+    const int64_t stride = axis == 0 ? 1 : (axis == 1 ? (int64_t)ix : (int64_t)ix * iy);
     for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
          idx += (int64_t)gridDim.x * blockDim.x) {
-        int cx = (int)(idx % ox);
-        int cy = (int)((idx / ox) % oy);
-        int cz = (int)(idx / ((int64_t)ox * oy));
-        int o = axis == 0 ? cx : (axis == 1 ? cy : cz);
+        const int cx = (int)(idx % ox);
+        const int cy = (int)((idx / ox) % oy);
+        const int cz = (int)(idx / ((int64_t)ox * oy));
+        const int o = axis == 0 ? cx : (axis == 1 ? cy : cz);
+        const int s0 = start[o];
+        const Tin *src = in + ((int64_t)(axis == 2 ? s0 : cz) * iy + (axis == 1 ? s0 : cy)) * ix + (axis == 0 ? s0 : cx);
+        const Tout *wr = w + (int64_t)o * bw;
         Tout s = 0;
-        for (int t = rowptr[o]; t < rowptr[o + 1]; ++t) {
-            int c = col[t];
-            int jx = axis == 0 ? c : cx, jy = axis == 1 ? c : cy, jz = axis == 2 ? c : cz;
-            s += w[t] * (Tout)in[((int64_t)jz * iy + jy) * ix + jx];
-        }
+#pragma unroll 4
+        for (int j = 0; j < bw; ++j) s += wr[j] * (Tout)src[j * stride];
         out[idx] = beta == Tout(0) ? alpha * s : alpha * s + beta * out[idx];
     }
 }
@@ -480,10 +492,19 @@ void launch_op_kron(const Dims &d, const T *AB1d, const T *mu, const T *x, T *y,
 template <typename T>
 void launch_op_general(const Dims &d, const T *IDq, const T *Gw, const T *x, T *y, const Exec &e) {
     int64_t ncell = (int64_t)d.nx * d.ny * d.nz;
-#define CALL(P) \
-    hipLaunchKernelGGL((k_op_general<T, P>), dim3((unsigned)ncell), dim3(round64(QOF(P) * QOF(P))), 0, e.s, e.gate, d, IDq, Gw, x, y)
+    const int split = std::is_same<T, double>::value ? e.t.opg_split64 : e.t.opg_split32;
+    if (split != 0 && split != 1 && split != 2) throw Error(VSR_EINVAL, "operator split must be 0 (default), 1 or 2");
+#define CALLS(P, S) \
+    hipLaunchKernelGGL((k_op_general<T, P, S>), dim3((unsigned)(ncell * S)), dim3(opg_threads(P, S)), 0, e.s, e.gate, d, IDq, Gw, x, y)
+#define CALL(P)                                                                                  \
+    {                                                                                            \
+        const int sp = split ? split : (sizeof(T) == 8 && opg_threads(P, 1) > 512 ? 2 : 1);     \
+        if (sp == 2) CALLS(P, 2);                                                                \
+        else CALLS(P, 1);                                                                        \
+    }
     VSR_P_SWITCH(d.p, CALL)
 #undef CALL
+#undef CALLS
 }
 
 void launch_load_vector(const Dims &d, const double *IDq, const double *wdet, const double *f, double *b, const Exec &e) {
@@ -495,13 +516,13 @@ void launch_load_vector(const Dims &d, const double *IDq, const double *wdet, co
 }
 
 template <typename Tin, typename Tout>
-void launch_axis_pass(const int *rowptr, const int *col, const Tout *w, int axis, const int in_dims[3], const int out_dims[3],
+void launch_axis_pass(const int *start, int bw, const Tout *w, int axis, const int in_dims[3], const int out_dims[3],
                       const Tin *in, Tout *out, Tout alpha, Tout beta, const Exec &e) {
     int64_t n = (int64_t)out_dims[0] * out_dims[1] * out_dims[2];
     if (n == 0) return;
     const int bs = e.t.axis_block;
     if (bs < 64 || bs > 1024 || bs % 64 != 0) throw Error(VSR_EINVAL, "axis block must be a multiple of 64 in [64, 1024]");
-    hipLaunchKernelGGL((k_axis_pass<Tin, Tout>), dim3(grid_for(n, bs)), dim3(bs), 0, e.s, e.gate, rowptr, col, w, axis,
+    hipLaunchKernelGGL((k_axis_pass<Tin, Tout>), dim3(grid_for(n, bs)), dim3(bs), 0, e.s, e.gate, start, w, bw, axis,
                        in_dims[0], in_dims[1], in_dims[2], out_dims[0], out_dims[1], out_dims[2], in, out, alpha, beta);
 }
 
@@ -578,11 +599,11 @@ void launch_count_active(int count, const double *const *scals, int *active, con
     template void launch_axpby_to_double<T>(int64_t, double, const T *, double, double *, const Exec &);
 INST(float)
 INST(double)
-template void launch_axis_pass<double, double>(const int *, const int *, const double *, int, const int *, const int *,
+template void launch_axis_pass<double, double>(const int *, int, const double *, int, const int *, const int *,
                                                const double *, double *, double, double, const Exec &);
-template void launch_axis_pass<float, float>(const int *, const int *, const float *, int, const int *, const int *,
+template void launch_axis_pass<float, float>(const int *, int, const float *, int, const int *, const int *,
                                              const float *, float *, float, float, const Exec &);
-template void launch_axis_pass<double, float>(const int *, const int *, const float *, int, const int *, const int *,
+template void launch_axis_pass<double, float>(const int *, int, const float *, int, const int *, const int *,
                                               const double *, float *, float, float, const Exec &);
 template void launch_cast<double, float>(int64_t, const double *, float *, const Exec &);
 template void launch_cast<float, double>(int64_t, const float *, double *, const Exec &);

@@ -123,7 +123,8 @@ def test_batch_zero_rhs_and_iteration_cap(vsr):
     B.close()
 
 
-@pytest.mark.parametrize("p,jitter,relax_fp32", [(4, 0.0, True), (7, 0.0, False), (5, 0.2, True), (3, 0.0, False)])
+@pytest.mark.parametrize("p,jitter,relax_fp32", [(4, 0.0, True), (7, 0.0, False), (5, 0.2, True), (3, 0.0, False),
+                                                 (6, 0.15, False)])
 def test_every_launch_shape_gives_the_same_solve(vsr, p, jitter, relax_fp32):
     say(f"case shapes p={p} jitter={jitter} fp32={relax_fp32}")
     d, f = member_problem((3, 3, 3), p, jitter, False, seed=40 + p)
@@ -131,8 +132,8 @@ def test_every_launch_shape_gives_the_same_solve(vsr, p, jitter, relax_fp32):
     b = rhs(prob, f)
     x0 = torch.zeros_like(b)
     ref = prob.pcg_solve(b, x0)
-    assert prob.tuning() == (1, 1, 256, 8)
-    for shapes in [(2, 2, 64, 4), (4, 4, 1024, 16), (4, 2, 128, 8), (1, 4, 512, 16)]:
+    assert prob.tuning() == (1, 1, 256, 8, 0, 0)
+    for shapes in [(2, 2, 64, 4, 1, 2), (4, 4, 1024, 16, 2, 1), (4, 2, 128, 8, 2, 2), (1, 4, 512, 16, 1, 1)]:
         prob.set_tuning(shapes)
         x = torch.zeros_like(b)
         info = prob.pcg_solve(b, x)
@@ -142,9 +143,9 @@ def test_every_launch_shape_gives_the_same_solve(vsr, p, jitter, relax_fp32):
         else:
             assert info["iterations"] == ref["iterations"] and rel(x, x0) < 1e-10
     with pytest.raises(vsr.VsrError):
-        prob.set_tuning((3, 1, 256, 8))
+        prob.set_tuning((3, 1, 256, 8, 0, 0))
     with pytest.raises(vsr.VsrError):
-        prob.set_tuning((1, 1, 100, 8))
+        prob.set_tuning((1, 1, 100, 8, 0, 0))
     prob.close()
 
 
@@ -157,7 +158,8 @@ def test_autotune_and_cache_file(vsr, tmp_path):
     say(f"  tuned shapes {t}")
     lines = cache.read_text().splitlines()
     assert len(lines) == 1 and " p=4 prec=f32 op=kron " in lines[0]
-    assert lines[0].endswith(f"cpw64={t[0]} cpw32={t[1]} axis_block={t[2]} patch_unroll={t[3]}")
+    assert lines[0].endswith(f"cpw64={t[0]} cpw32={t[1]} axis_block={t[2]} patch_unroll={t[3]} "
+                             f"split64={t[4]} split32={t[5]}")
     b = rhs(prob, f)
     x = torch.zeros_like(b)
     info = prob.pcg_solve(b, x)
