@@ -136,11 +136,12 @@ vsr_status vsr_pcg_solve(vsr_problem *prob, const double *b_dev, double *x_dev, 
 vsr_status vsr_get_damping(const vsr_problem *prob, double *omega, double *lambda_min,
                            double *lambda_max);
 
-/* Timing of the patch-solve kernels (the dominant kernel).  enable != 0 makes
- * every later relaxation record HIP events around its patch-solve launches on the
- * problem's stream; vsr_kernel_stats returns the launch count, total milliseconds
- * and the algorithmic bytes one launch moves (factor entries read twice plus the
- * patch vectors read and written), and resets the counters. */
+/* Timing of the patch-solve kernel (the dominant kernel; one launch per relaxation
+ * solves the stars of all vertices, interior ones first).  enable != 0 makes every later
+ * relaxation record HIP events around that launch on the problem's stream;
+ * vsr_kernel_stats returns the launch count, total milliseconds and the algorithmic
+ * bytes one launch moves (factor entries read twice plus the patch vectors read and
+ * written), and resets the counters. */
 vsr_status vsr_set_profiling(vsr_problem *prob, int32_t enable);
 vsr_status vsr_kernel_stats(vsr_problem *prob, int64_t *launches, double *total_ms,
                             double *bytes_per_launch);

@@ -79,7 +79,7 @@ struct vsr_problem {
     int64_t *boff = nullptr;
     PatchArgs pa{};
     int64_t factor_entries = 0;       // structurally nonzero entries over all patches
-    double bytes_patch_launch = 0;    // algorithmic bytes of one interior patch-solve launch
+    double bytes_patch_launch = 0;    // algorithmic bytes of one patch-solve launch (all stars)
     Table tab[4][3];                  // [TT, T, PT, P][axis]
     int cdim[3] = {0, 0, 0};
     int nc = 0;
@@ -176,14 +176,12 @@ void relax_apply(vsr_problem *P, const Tin *in, T *out, T alpha, T beta) {
         e1 = P->events[P->events_used].second;
         VSR_HIP(hipEventRecord(e0, P->stream));
     }
-    launch_patch_interior<T>(P->d, P->pa, P->n_int, P->verts, (const T *)P->fint, (const T *)P->mu_sur, (const T *)P->lam,
-                             (const T *)P->afc, rF, U, P->ex());
+    launch_patch_all<T>(P->d, P->pa, P->n_int, P->verts, (const T *)P->fint, P->n_bnd, P->bdesc, P->boff,
+                        (const T *)P->fbnd, (const T *)P->mu_sur, (const T *)P->lam, (const T *)P->afc, rF, U, P->ex());
     if (prof) {
         VSR_HIP(hipEventRecord(e1, P->stream));
         ++P->events_used;
     }
-    launch_patch_boundary<T>(P->d, P->n_bnd, P->bdesc, P->boff, (const T *)P->fbnd, (const T *)P->mu_sur, (const T *)P->lam,
-                             (const T *)P->afc, rF, U, P->ex());
     launch_patch_assemble<T>(P->d, P->opt.interior_patches_only, U, zF, P->ex());
     launch_axis_pass<T, T>(Tp[0].start, Tp[0].bw, wt<T>(Tp[0]), 0, L, L, zF, t1, T(1), T(0), P->ex());
     launch_axis_pass<T, T>(Tp[1].start, Tp[1].bw, wt<T>(Tp[1]), 1, L, L, t1, t2, T(1), T(0), P->ex());
@@ -457,19 +455,20 @@ void autotune(vsr_problem *P) {
     };
     auto patch = [&](auto zero) {
         using T = decltype(zero);
-        launch_patch_interior<T>(P->d, P->pa, P->n_int, P->verts, (const T *)P->fint, (const T *)P->mu_sur,
-                                 (const T *)P->lam, (const T *)P->afc, (const T *)P->rF, (T *)P->U, P->ex());
+        launch_patch_all<T>(P->d, P->pa, P->n_int, P->verts, (const T *)P->fint, P->n_bnd, P->bdesc, P->boff,
+                            (const T *)P->fbnd, (const T *)P->mu_sur, (const T *)P->lam, (const T *)P->afc,
+                            (const T *)P->rF, (T *)P->U, P->ex());
     };
     if (P->fp32) {
         launch_fill<float>(P->n, (float *)P->t1, 1.f, P->ex());
         launch_fill<float>(P->n, (float *)P->rF, 1.f, P->ex());
         pick(P->tune.axis_block, {64, 128, 256, 512, 1024}, [&] { passes(0.f); });
-        if (P->n_int > 0) pick(P->tune.patch_unroll, {4, 8, 16}, [&] { patch(0.f); });
+        if (P->n_int + P->n_bnd > 0) pick(P->tune.patch_unroll, {4, 8, 16}, [&] { patch(0.f); });
     } else {
         launch_fill<double>(P->n, (double *)P->t1, 1.0, P->ex());
         launch_fill<double>(P->n, (double *)P->rF, 1.0, P->ex());
         pick(P->tune.axis_block, {64, 128, 256, 512, 1024}, [&] { passes(0.0); });
-        if (P->n_int > 0) pick(P->tune.patch_unroll, {4, 8, 16}, [&] { patch(0.0); });
+        if (P->n_int + P->n_bnd > 0) pick(P->tune.patch_unroll, {4, 8, 16}, [&] { patch(0.0); });
     }
     // the patch boxes of absent stars must read as zero in the assembly
     const int64_t w3 = (int64_t)P->pa.w * P->pa.w * P->pa.w, nv = (int64_t)(P->d.nx + 1) * (P->d.ny + 1) * (P->d.nz + 1);
@@ -686,14 +685,19 @@ vsr_status vsr_setup(const vsr_mesh *mesh, int32_t p, const vsr_coefficients *co
         int m = L.m, w = L.w;
         int64_t per_patch = (int64_t)L.n_leaf + 2LL * 4 * m * m * w + 2LL * m * w * (w + 1) / 2 +
                             2LL * m * w * L.n_top + (int64_t)L.n_top * (L.n_top + 1) / 2;
-        int64_t bnd_nnz = 0;
+        int64_t bnd_nnz = 0, bnd_box = 0;
         for (int i = 0; i < P->n_bnd; ++i) {
             int ns = S.boundary_desc[8 * i + 7], nsl = S.boundary_desc[8 * i + 6];
             bnd_nnz += (int64_t)nsl * ns * (ns + 1) / 2;
+            int64_t box = 1;   // the part of the star's box inside existing cells
+            for (int a = 0; a < 3; ++a) box *= S.boundary_desc[8 * i + 3 + a] == AX_FULL ? w : m;
+            bnd_box += box;
         }
         P->factor_entries = per_patch * P->n_int + bnd_nnz;
         size_t esz = P->fp32 ? sizeof(float) : sizeof(double);
-        P->bytes_patch_launch = (double)esz * (double)P->n_int * (2.0 * per_patch + 2.0 * (double)w * w * w);
+        // one launch solves every patch: factors read twice (forward, backward), box in and out
+        P->bytes_patch_launch = (double)esz * ((double)P->n_int * (2.0 * per_patch + 2.0 * (double)w * w * w) +
+                                               2.0 * (double)bnd_nnz + 2.0 * (double)bnd_box);
         if (P->fp32) upload_patch_data<float>(P.get(), S, mu_sur);
         else upload_patch_data<double>(P.get(), S, mu_sur);
         // transfer tables

@@ -102,70 +102,39 @@ __device__ void stage_coefficients(const Dims &d, int vx, int vy, int vz, const 
     for (int t = tid; t < 2 * M; t += blockDim.x) safc[t] = afc[t];
 }
 
-// Value of lane `l` (uniform) broadcast to the wavefront through the scalar unit.
+// Triangular solves with the packed inverse Li of a lower Cholesky factor (column k holds
+// rows k..nstore-1 of L^{-1} from offset k nstore - k (k - 1) / 2): y = L^{-1} b and
+// y = L^{-T} b are matrix-vector products whose rows are independent, so a wavefront has
+// no elimination chain.  Lane i returns row i (zero for i >= rows); b is in LDS, read as
+// broadcasts; four partial sums per lane.  Entries outside the triangle or at or beyond
+// `rows` are never loaded.
 template <typename T>
-__device__ __forceinline__ T bcast(T v, int l);
-template <>
-__device__ __forceinline__ float bcast<float>(float v, int l) {
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
-}
-template <>
-__device__ __forceinline__ double bcast<double>(double v, int l) {
-    int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
-    int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
-    return __hiloint2double(hi, lo);
-}
-
-// Dense lower-triangular solves by one wavefront (n <= MAXW <= 64), column-major L with
-// inverse diagonal.  Forward: lane i holds row i of L; each solved value is broadcast
-// and eliminated from the rows below.  Backward (L^T u = y): lane i holds column i of L
-// and the solved u_k is eliminated from the rows above.
-template <typename T, int MAXW>
-__device__ __forceinline__ void wave_load_rows(const T *__restrict__ L, int ld, int n, int lane, T (&row)[MAXW]) {
-#pragma unroll
-    for (int k = 0; k < MAXW; ++k) row[k] = (k < n && lane < n) ? L[(int64_t)k * ld + lane] : T(0);
-}
-// Packed lower triangle (column k holds rows k..n-1 at offset k n - k (k - 1) / 2): lane i
-// receives row i (forward) or column i (backward), zeros above the diagonal.
-template <typename T, int MAXW>
-__device__ __forceinline__ void wave_load_rows_packed(const T *__restrict__ L, int n, int lane, T (&row)[MAXW]) {
-#pragma unroll
-    for (int k = 0; k < MAXW; ++k)
-        row[k] = (k < n && lane < n && lane >= k) ? L[k * n - k * (k - 1) / 2 + (lane - k)] : T(0);
-}
-template <typename T, int MAXW>
-__device__ __forceinline__ void wave_load_cols_packed(const T *__restrict__ L, int n, int lane, T (&col)[MAXW]) {
-    const int base = lane * n - lane * (lane - 1) / 2 - lane;
-#pragma unroll
-    for (int k = 0; k < MAXW; ++k) col[k] = (k < n && lane < n && k >= lane) ? L[base + k] : T(0);
-}
-
-// Both solves rely on the stored upper triangle being zero, so the update is branch-free:
-// lane k takes the solved value, the other lanes subtract their (possibly zero) coefficient.
-template <typename T, int MAXW>
-__device__ __forceinline__ T wave_forward(const T (&row)[MAXW], int n, int lane, T x) {
-#pragma unroll
-    for (int k = 0; k < MAXW; ++k) {
-        if (k < n) {
-            const T dk = bcast(row[k], k);
-            const T yk = bcast(x, k) * dk;
-            x = lane == k ? yk : x - row[k] * yk;
-        }
+__device__ __forceinline__ T tri_inv_mv(const T *__restrict__ Li, int nstore, int k0, int k1, int rows, int lane,
+                                        const T *b) {
+    T acc[4] = {T(0), T(0), T(0), T(0)};
+    int off = k0 * nstore - k0 * (k0 - 1) / 2;   // start of column k0
+    const bool live = lane < rows;
+#pragma unroll 4
+    for (int k = k0; k < k1; ++k) {
+        const T v = (live && lane >= k) ? Li[off + lane - k] : T(0);
+        acc[k & 3] += v * b[k];
+        off += nstore - k;
     }
-    return x;
+    return (acc[0] + acc[1]) + (acc[2] + acc[3]);
 }
 
-template <typename T, int MAXW>
-__device__ __forceinline__ T wave_backward(const T (&col)[MAXW], int n, int lane, T x) {
-#pragma unroll
-    for (int k = MAXW - 1; k >= 0; --k) {
-        if (k < n) {
-            const T dk = bcast(col[k], k);
-            const T uk = bcast(x, k) * dk;
-            x = lane == k ? uk : x - col[k] * uk;
-        }
+template <typename T>
+__device__ __forceinline__ T tri_inv_t_mv(const T *__restrict__ Li, int nstore, int k0, int k1, int rows, int lane,
+                                          const T *b) {
+    T acc[4] = {T(0), T(0), T(0), T(0)};
+    const int base = lane * nstore - lane * (lane - 1) / 2 - lane;   // L^{-1}(k, lane) at base + k
+    const bool live = lane < rows;
+#pragma unroll 4
+    for (int k = k0; k < k1; ++k) {
+        const T v = (live && k >= lane) ? Li[base + k] : T(0);
+        acc[k & 3] += v * b[k];
     }
-    return x;
+    return (acc[0] + acc[1]) + (acc[2] + acc[3]);
 }
 
 template <typename T>
@@ -290,19 +259,17 @@ __device__ __forceinline__ int64_t tile_offset(int64_t off_Ltop, int NT, int J) 
 // Schur complement (leaves, level-1 separator slices, dense top plane), forward and
 // backward, then interior back-substitution.  Output: the patch box of (2m+1)^3 values.
 template <typename T, int P, int UNR>
-__global__ void __launch_bounds__(256) k_patch_interior(const double *__restrict__ gate, Dims d, PatchArgs A,
-                                                        const int *__restrict__ verts,
-                                                        const T *__restrict__ factor, const T *__restrict__ mu,
-                                                        const T *__restrict__ lam, const T *__restrict__ afc,
-                                                        const T *__restrict__ rF, T *__restrict__ U) {
+__device__ __forceinline__ void patch_interior(const int pid, Dims d, PatchArgs A, const int *__restrict__ verts,
+                                               const T *__restrict__ factor, const T *__restrict__ mu,
+                                               const T *__restrict__ lam, const T *__restrict__ afc,
+                                               const T *__restrict__ rF, T *__restrict__ U) {
     constexpr int M = P - 1, W = 2 * M + 1, NL = 4 * M * M, NS = 2 * M * W, NT = W * W, NI = NL + NS + NT;
     constexpr int NTILE = (NT + 63) / 64;
-    if (gated(gate)) return;
     __shared__ T g[NI];
     __shared__ T smu[24], slam[M], safc[2 * M];
     __shared__ T tl[64 * 65 / 2];
+    __shared__ T red[256];
     const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
-    const int pid = blockIdx.x;
     const int kfull[3] = {AX_FULL, AX_FULL, AX_FULL};
     const int vx = verts[3 * pid], vy = verts[3 * pid + 1], vz = verts[3 * pid + 2];
     stage_coefficients<T, M>(d, vx, vy, vz, kfull, mu, lam, afc, smu, slam, safc);
@@ -351,10 +318,7 @@ __global__ void __launch_bounds__(256) k_patch_interior(const double *__restrict
     phase_sync();
     // level-1 separator slices: dense lower solves, one wavefront per slice
     for (int s = wv; s < 2 * M; s += nw) {
-        T row[W];
-        wave_load_rows_packed<T, W>(F + A.off_Lsep + (int64_t)s * (W * (W + 1) / 2), W, lane, row);
-        T x = lane < W ? g[NL + s * W + lane] : T(0);
-        x = wave_forward<T, W>(row, W, lane, x);
+        const T x = tri_inv_mv<T>(F + A.off_Lsep + (int64_t)s * (W * (W + 1) / 2), W, 0, W, W, lane, g + NL + s * W);
         if (lane < W) g[NL + s * W + lane] = x;
     }
     // stage the first top-plane diagonal tile while the level-1 solves finish
@@ -380,14 +344,10 @@ __global__ void __launch_bounds__(256) k_patch_interior(const double *__restrict
     // waves update the rows below while the next diagonal block is staged
     for (int J = 0; J < NTILE; ++J) {
         const int c0 = 64 * J, nb = min(64, NT - c0);
-        if (wv == 0) {
-            T row[64];   // row lane of the block: L(lane, k) at k (129 - k) / 2 + lane - k
-#pragma unroll
-            for (int k = 0; k < 64; ++k) row[k] = k <= lane ? tl[k * (129 - k) / 2 - k + lane] : T(0);
-            T x = lane < nb ? gt[c0 + lane] : T(0);
-            x = wave_forward<T, 64>(row, nb, lane, x);
-            if (lane < nb) gt[c0 + lane] = x;
-        }
+        // diagonal block: y = L^{-1} b from the staged inverse, the k-range split over the waves
+        red[tid] = tri_inv_mv<T>(tl, 64, min(16 * wv, nb), min(16 * wv + 16, nb), nb, lane, gt + c0);
+        phase_sync();
+        if (wv == 0 && lane < nb) gt[c0 + lane] = (red[lane] + red[64 + lane]) + (red[128 + lane] + red[192 + lane]);
         phase_sync();
         const T *D = F + tile_offset(A.off_Ltop, NT, J);
         const int rows = NT - c0 - nb;
@@ -398,15 +358,9 @@ __global__ void __launch_bounds__(256) k_patch_interior(const double *__restrict
     // ---- backward: top plane (tile NTILE-1 is staged)
     for (int J = NTILE - 1; J >= 0; --J) {
         const int c0 = 64 * J, nb = min(64, NT - c0);
-        if (wv == 0) {
-            T col[64];   // column lane of the block: L(k, lane) at lane (129 - lane) / 2 + k - lane
-            const int cb = lane * (129 - lane) / 2 - lane;
-#pragma unroll
-            for (int k = 0; k < 64; ++k) col[k] = k >= lane ? tl[cb + k] : T(0);
-            T x = lane < nb ? gt[c0 + lane] : T(0);
-            x = wave_backward<T, 64>(col, nb, lane, x);
-            if (lane < nb) gt[c0 + lane] = x;
-        }
+        red[tid] = tri_inv_t_mv<T>(tl, 64, min(16 * wv, nb), min(16 * wv + 16, nb), nb, lane, gt + c0);
+        phase_sync();
+        if (wv == 0 && lane < nb) gt[c0 + lane] = (red[lane] + red[64 + lane]) + (red[128 + lane] + red[192 + lane]);
         phase_sync();
         if (J > 0) {
             const int cp = 64 * (J - 1), nbp = 64, rows = NT - cp - nbp;
@@ -419,10 +373,7 @@ __global__ void __launch_bounds__(256) k_patch_interior(const double *__restrict
     panel_bwd<T, UNR>(F + A.off_P, A.top_pad, NT, NS, gt, g + NL);
     phase_sync();
     for (int s = wv; s < 2 * M; s += nw) {
-        T col[W];
-        wave_load_cols_packed<T, W>(F + A.off_Lsep + (int64_t)s * (W * (W + 1) / 2), W, lane, col);
-        T x = lane < W ? g[NL + s * W + lane] : T(0);
-        x = wave_backward<T, W>(col, W, lane, x);
+        const T x = tri_inv_t_mv<T>(F + A.off_Lsep + (int64_t)s * (W * (W + 1) / 2), W, 0, W, W, lane, g + NL + s * W);
         if (lane < W) g[NL + s * W + lane] = x;
     }
     phase_sync();
@@ -458,17 +409,14 @@ __global__ void __launch_bounds__(256) k_patch_interior(const double *__restrict
 // splits into independent dense slices (2 full axes: crosses of 4m+1 DOFs; 1 full axis:
 // single DOFs).  desc: vx, vy, vz, kind_x, kind_y, kind_z, nslices, slice size.
 template <typename T, int P>
-__global__ void __launch_bounds__(256) k_patch_boundary(const double *__restrict__ gate, Dims d, const int *__restrict__ desc,
-                                                        const int64_t *__restrict__ off,
-                                                        const T *__restrict__ factor, const T *__restrict__ mu,
-                                                        const T *__restrict__ lam, const T *__restrict__ afc,
-                                                        const T *__restrict__ rF, T *__restrict__ U) {
+__device__ __forceinline__ void patch_boundary(const int pid, Dims d, const int *__restrict__ desc,
+                                               const int64_t *__restrict__ off, const T *__restrict__ factor,
+                                               const T *__restrict__ mu, const T *__restrict__ lam,
+                                               const T *__restrict__ afc, const T *__restrict__ rF, T *__restrict__ U) {
     constexpr int M = P - 1, W = 2 * M + 1, MAXN = 4 * M + 1;
-    if (gated(gate)) return;
     __shared__ T g[M * MAXN > M * M ? M * MAXN : M * M];
     __shared__ T smu[24], slam[M], safc[2 * M];
     const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
-    const int pid = blockIdx.x;
     const int *ds = desc + 8 * pid;
     const int kind[3] = {ds[3], ds[4], ds[5]};
     stage_coefficients<T, M>(d, ds[0], ds[1], ds[2], kind, mu, lam, afc, smu, slam, safc);
@@ -520,17 +468,9 @@ __global__ void __launch_bounds__(256) k_patch_boundary(const double *__restrict
     } else if (ns > 1) {
         for (int t = wv; t < nslices; t += nw) {
             const T *Ls = F + (int64_t)t * (ns * (ns + 1) / 2);
-            T x = lane < ns ? g[t * ns + lane] : T(0);
-            {
-                T row[MAXN];
-                wave_load_rows_packed<T, MAXN>(Ls, ns, lane, row);
-                x = wave_forward<T, MAXN>(row, ns, lane, x);
-            }
-            {
-                T col[MAXN];
-                wave_load_cols_packed<T, MAXN>(Ls, ns, lane, col);
-                x = wave_backward<T, MAXN>(col, ns, lane, x);
-            }
+            const T y = tri_inv_mv<T>(Ls, ns, 0, ns, ns, lane, g + t * ns);
+            if (lane < ns) g[t * ns + lane] = y;
+            const T x = tri_inv_t_mv<T>(Ls, ns, 0, ns, ns, lane, g + t * ns);
             if (lane < ns) g[t * ns + lane] = x;
         }
     }
@@ -558,7 +498,61 @@ __global__ void __launch_bounds__(256) k_patch_boundary(const double *__restrict
 }
 
 
+template <typename T, int P, int UNR>
+__global__ void __launch_bounds__(256) k_patch_interior(const double *__restrict__ gate, Dims d, PatchArgs A,
+                                                        const int *__restrict__ verts, const T *__restrict__ factor,
+                                                        const T *__restrict__ mu, const T *__restrict__ lam,
+                                                        const T *__restrict__ afc, const T *__restrict__ rF,
+                                                        T *__restrict__ U) {
+    if (gated(gate)) return;
+    patch_interior<T, P, UNR>(blockIdx.x, d, A, verts, factor, mu, lam, afc, rF, U);
+}
+
+template <typename T, int P>
+__global__ void __launch_bounds__(256) k_patch_boundary(const double *__restrict__ gate, Dims d, const int *__restrict__ desc,
+                                                        const int64_t *__restrict__ off, const T *__restrict__ factor,
+                                                        const T *__restrict__ mu, const T *__restrict__ lam,
+                                                        const T *__restrict__ afc, const T *__restrict__ rF,
+                                                        T *__restrict__ U) {
+    if (gated(gate)) return;
+    patch_boundary<T, P>(blockIdx.x, d, desc, off, factor, mu, lam, afc, rF, U);
+}
+
+// Every patch of one relaxation in one launch: the interior-vertex stars first, then the
+// boundary-vertex stars, whose short solves fill the CUs that the last round of interior
+// patches leaves idle.
+template <typename T, int P, int UNR>
+__global__ void __launch_bounds__(256) k_patch_all(const double *__restrict__ gate, Dims d, PatchArgs A, int n_int,
+                                                   const int *__restrict__ verts, const T *__restrict__ fint,
+                                                   const int *__restrict__ desc, const int64_t *__restrict__ off,
+                                                   const T *__restrict__ fbnd, const T *__restrict__ mu,
+                                                   const T *__restrict__ lam, const T *__restrict__ afc,
+                                                   const T *__restrict__ rF, T *__restrict__ U) {
+    if (gated(gate)) return;
+    if ((int)blockIdx.x < n_int) patch_interior<T, P, UNR>(blockIdx.x, d, A, verts, fint, mu, lam, afc, rF, U);
+    else patch_boundary<T, P>(blockIdx.x - n_int, d, desc, off, fbnd, mu, lam, afc, rF, U);
+}
+
 }  // namespace
+
+template <typename T>
+void launch_patch_all(const Dims &d, const PatchArgs &a, int n_int, const int *verts, const T *fint, int n_bnd,
+                      const int *desc, const int64_t *off, const T *fbnd, const T *mu, const T *lam, const T *afc,
+                      const T *rF, T *U, const Exec &e) {
+    if (n_int + n_bnd == 0) return;
+    const int unr = e.t.patch_unroll;
+    if (unr != 4 && unr != 8 && unr != 16) throw Error(VSR_EINVAL, "patch_unroll must be 4, 8 or 16");
+#define CALLU(P, UU)                                                                                              \
+    hipLaunchKernelGGL((k_patch_all<T, P, UU>), dim3(n_int + n_bnd), dim3(256), 0, e.s, e.gate, d, a, n_int, verts, fint, \
+                       desc, off, fbnd, mu, lam, afc, rF, U)
+#define CALL(P)                          \
+    if (unr == 4) CALLU(P, 4);           \
+    else if (unr == 8) CALLU(P, 8);      \
+    else CALLU(P, 16)
+    VSR_P_SWITCH(d.p, CALL)
+#undef CALL
+#undef CALLU
+}
 
 template <typename T>
 void launch_patch_interior(const Dims &d, const PatchArgs &a, int npatch, const int *verts, const T *factor, const T *mu,
@@ -597,4 +591,7 @@ void launch_patch_boundary(const Dims &d, int npatch, const int *desc, const int
                                            const T *, const T *, const T *, T *, const Exec &);                     \
     template void launch_patch_boundary<T>(const Dims &, int, const int *, const int64_t *, const T *, const T *,    \
                                            const T *, const T *, const T *, T *, const Exec &);                     \
+    template void launch_patch_all<T>(const Dims &, const PatchArgs &, int, const int *, const T *, int, const int *, \
+                                      const int64_t *, const T *, const T *, const T *, const T *, const T *, T *,   \
+                                      const Exec &);                                                                \
     }

@@ -139,6 +139,26 @@ static void jacobi_eig(int n, std::vector<double> A, std::vector<double> &ev, st
     for (int i = 0; i < n; ++i) ev[i] = A[(size_t)i * n + i];
 }
 
+// Inverse of the leading n x n block of a row-major lower-triangular L (leading dimension
+// lda), packed column-major into nstore columns: column k holds rows k..nstore-1 from offset
+// k nstore - k (k - 1) / 2; rows or columns at or beyond n are zero.  The inverse of a lower
+// triangle is lower triangular, so it takes the storage of the factor itself; the solves
+// become triangular matrix-vector products with independent rows (no elimination chain).
+static void pack_lower_inverse(int n, const double *L, int lda, int nstore, double *out) {
+    std::vector<double> x((size_t)n);
+    size_t e = 0;
+    for (int k = 0; k < nstore; ++k) {
+        if (k < n) {   // column k of L^{-1}: forward substitution of L x = e_k
+            for (int i = k; i < n; ++i) {
+                double v = i == k ? 1.0 : 0.0;
+                for (int j = k; j < i; ++j) v -= L[(size_t)i * lda + j] * x[j];
+                x[i] = v / L[(size_t)i * lda + i];
+            }
+        }
+        for (int i = k; i < nstore; ++i, ++e) out[e] = (k < n && i < n) ? x[i] : 0.0;
+    }
+}
+
 // Dense Cholesky in place (row-major, lower), returns false on a non-positive pivot.
 static bool cholesky_lower(int n, double *a, int lda) {
     for (int j = 0; j < n; ++j) {
@@ -666,9 +686,7 @@ bool factor_interior(const InteriorLayout &L, std::vector<double> &S, double *ou
         for (int i = 0; i < w; ++i)
             for (int j = 0; j < w; ++j) Ls[(size_t)i * w + j] = at(sep(s, i), sep(s, j));
         if (!cholesky_lower(w, Ls.data(), w)) return false;
-        double *Lo = out + L.off_Lsep + (int64_t)s * (w * (w + 1) / 2);   // packed lower, column-major
-        for (int k = 0, e = 0; k < w; ++k)
-            for (int i = k; i < w; ++i, ++e) Lo[e] = i == k ? 1.0 / Ls[(size_t)i * w + i] : Ls[(size_t)i * w + k];
+        pack_lower_inverse(w, Ls.data(), w, w, out + L.off_Lsep + (int64_t)s * (w * (w + 1) / 2));
         for (int r = 0; r < nt; ++r) {
             double *pr = &Pall[(size_t)r * ncol + s * w];
             for (int j = 0; j < w; ++j) {
@@ -706,14 +724,8 @@ bool factor_interior(const InteriorLayout &L, std::vector<double> &S, double *ou
     if (!cholesky_lower(nt, T.data(), nt)) return false;
     for (int J = 0; J < L.ntiles; ++J) {
         int c0 = 64 * J, nb = std::min(64, nt - c0);
-        double *D = out + L.tile_off[J];   // diagonal block packed as a 64-column lower triangle
-        for (int k = 0, e = 0; k < 64; ++k)
-            for (int i = k; i < 64; ++i, ++e) {
-                double v = 0.0;
-                if (k < nb && i < nb)
-                    v = i == k ? 1.0 / T[(size_t)(c0 + i) * nt + c0 + k] : T[(size_t)(c0 + i) * nt + c0 + k];
-                D[e] = v;
-            }
+        double *D = out + L.tile_off[J];   // inverse of the diagonal block, packed in 64 columns
+        pack_lower_inverse(nb, T.data() + (size_t)c0 * nt + c0, nt, 64, D);
         int rp = L.tile_rows_pad[J], r0 = c0 + nb;
         double *Pn = D + 64 * 65 / 2;
         for (int k = 0; k < 64; ++k)
@@ -725,7 +737,7 @@ bool factor_interior(const InteriorLayout &L, std::vector<double> &S, double *ou
     return true;
 }
 
-// Boundary classes: independent dense slices (column-major, inverse diagonal).
+// Boundary classes: independent dense slices (packed inverses of their Cholesky factors).
 bool factor_slices(const IfaceMap &M, std::vector<double> &S, double *out) {
     int n = M.n, ns = M.ns;
     std::vector<double> Ls((size_t)ns * ns);
@@ -733,9 +745,7 @@ bool factor_slices(const IfaceMap &M, std::vector<double> &S, double *out) {
         for (int i = 0; i < ns; ++i)
             for (int j = 0; j < ns; ++j) Ls[(size_t)i * ns + j] = S[(size_t)(t * ns + i) * n + t * ns + j];
         if (!cholesky_lower(ns, Ls.data(), ns)) return false;
-        double *o = out + (int64_t)t * (ns * (ns + 1) / 2);   // packed lower, column-major
-        for (int k = 0, e = 0; k < ns; ++k)
-            for (int i = k; i < ns; ++i, ++e) o[e] = i == k ? 1.0 / Ls[(size_t)i * ns + i] : Ls[(size_t)i * ns + k];
+        pack_lower_inverse(ns, Ls.data(), ns, ns, out + (int64_t)t * (ns * (ns + 1) / 2));
     }
     return true;
 }
