@@ -97,6 +97,7 @@ struct vsr_problem {
     const double *gate = nullptr;
     Tuning tune{};
     double *vx = nullptr;             // solution of a batched solve
+    vsr_batch *self = nullptr;        // batch of this problem alone (graph-replayed single solves)
     Exec ex() const { return Exec{stream, gate, tune}; }
     // profiling of the interior patch-solve launches
     bool profiling = false;
@@ -549,20 +550,13 @@ struct vsr_batch {
     hipGraphExec_t exec = nullptr;
     const double **scals = nullptr;        // device array of the members' scalar blocks
     int *active = nullptr;                 // device counter of members still iterating
-    int *host_active = nullptr;            // pinned
+    int *host_active = nullptr;            // pinned, two slots (polled one replay behind)
+    hipEvent_t poll[2] = {nullptr, nullptr};
     bool eager = false;
+    bool owns_members = true;
 
-    ~vsr_batch() {
-        if (exec) (void)hipGraphExecDestroy(exec);
-        if (graph) (void)hipGraphDestroy(graph);
-        for (hipEvent_t e : events) (void)hipEventDestroy(e);
-        for (hipStream_t st : streams) (void)hipStreamDestroy(st);
-        if (origin) (void)hipStreamDestroy(origin);
-        if (scals) (void)hipFree(scals);
-        if (active) (void)hipFree(active);
-        if (host_active) (void)hipHostFree(host_active);
-        for (vsr_problem *m : members) delete m;
-    }
+    ~vsr_batch();
+    void solve(const double *const *b_dev, double *const *x_dev, double rtol, vsr_solve_info *infos);
 
     // Run fn(member) for every member on its stream, forked from and joined back to origin.
     template <typename F>
@@ -600,6 +594,154 @@ struct vsr_batch {
         launch_count_active((int)members.size(), scals, active, Exec{origin, nullptr, Tuning{}});
     }
 };
+
+namespace {
+
+void destroy_problem(vsr_problem *P) {
+    if (!P) return;
+    delete P->self;
+    delete P;
+}
+
+// Streams, events, graph state and device scalars of a batch over `members`.
+vsr_batch *make_batch(int count, vsr_problem *const *members, int nstreams, bool eager, bool owns) {
+    auto B = std::make_unique<vsr_batch>();
+    B->owns_members = false;   // until everything below has succeeded
+    const int ns = std::max(1, std::min(nstreams, count));
+    B->streams.resize(ns, nullptr);
+    for (auto &st : B->streams) VSR_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    VSR_HIP(hipStreamCreateWithFlags(&B->origin, hipStreamNonBlocking));
+    B->events.resize(1 + ns, nullptr);
+    for (auto &e : B->events) VSR_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    for (auto &e : B->poll) VSR_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    // largest member first onto the least loaded stream
+    std::vector<int> order(count);
+    for (int i = 0; i < count; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return members[a]->n > members[b]->n; });
+    std::vector<double> load(ns, 0.0);
+    B->stream_of.assign(count, 0);
+    for (int i : order) {
+        int j = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        B->stream_of[i] = j;
+        load[j] += (double)members[i]->n;
+    }
+    std::vector<const double *> sc(count);
+    for (int i = 0; i < count; ++i) sc[i] = members[i]->scal;
+    VSR_HIP(hipMalloc((void **)&B->scals, sizeof(double *) * count));
+    VSR_HIP(hipMemcpy(B->scals, sc.data(), sizeof(double *) * count, hipMemcpyHostToDevice));
+    VSR_HIP(hipMalloc((void **)&B->active, sizeof(int)));
+    VSR_HIP(hipHostMalloc((void **)&B->host_active, 2 * sizeof(int), hipHostMallocDefault));
+    B->eager = eager;
+    B->members.assign(members, members + count);
+    B->owns_members = owns;
+    return B.release();
+}
+
+}  // namespace
+
+vsr_batch::~vsr_batch() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    for (hipEvent_t e : events) (void)hipEventDestroy(e);
+    for (hipEvent_t e : poll)
+        if (e) (void)hipEventDestroy(e);
+    for (hipStream_t st : streams) (void)hipStreamDestroy(st);
+    if (origin) (void)hipStreamDestroy(origin);
+    if (scals) (void)hipFree(scals);
+    if (active) (void)hipFree(active);
+    if (host_active) (void)hipHostFree(host_active);
+    if (owns_members)
+        for (vsr_problem *m : members) destroy_problem(m);
+}
+
+// Lockstep PCG of every member (see vsr_pcg_solve_batch).  The graph of one iteration is
+// recorded at the first solve and replayed; the active count is polled one replay behind,
+// so the GPU always has the next iteration queued (a replay after the last member stops
+// runs gated, doing nothing).
+void vsr_batch::solve(const double *const *b_dev, double *const *x_dev, double rtol, vsr_solve_info *infos) {
+    const int count = (int)members.size();
+    for (vsr_problem *P : members) VSR_HIP(hipStreamSynchronize(P->stream));
+    double t0 = now_s();
+    int maxit = 0;
+    for (vsr_problem *P : members) maxit = std::max(maxit, P->opt.max_iterations > 0 ? P->opt.max_iterations : 1000);
+    {
+        int i = 0;
+        for_members([&](vsr_problem *P) {
+            pcg_init(P, b_dev[i], P->vx);
+            launch_pcg_start(P->scal, rtol, P->opt.max_iterations > 0 ? P->opt.max_iterations : 1000, P->ex());
+            P->gate = P->scal + SC_DONE;
+            pcg_first_direction(P);
+            P->gate = nullptr;
+            ++i;
+        });
+    }
+    if (!eager && !exec) {
+        for (vsr_problem *P : members) P->capturing = true;
+        VSR_HIP(hipStreamBeginCapture(origin, hipStreamCaptureModeThreadLocal));
+        try {
+            iteration();
+        } catch (...) {
+            hipGraph_t g = nullptr;
+            (void)hipStreamEndCapture(origin, &g);
+            if (g) (void)hipGraphDestroy(g);
+            for (vsr_problem *P : members) P->capturing = false;
+            throw;
+        }
+        VSR_HIP(hipStreamEndCapture(origin, &graph));
+        for (vsr_problem *P : members) P->capturing = false;
+        VSR_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    }
+    int replays = 0;
+    for (;;) {
+        if (eager) iteration();
+        else VSR_HIP(hipGraphLaunch(exec, origin));
+        const int slot = replays & 1;
+        VSR_HIP(hipMemcpyAsync(host_active + slot, active, sizeof(int), hipMemcpyDeviceToHost, origin));
+        VSR_HIP(hipEventRecord(poll[slot], origin));
+        ++replays;
+        if (replays >= 2) {   // look at the replay before the one just queued
+            const int j = (replays - 2) & 1;
+            VSR_HIP(hipEventSynchronize(poll[j]));
+            if (host_active[j] == 0) break;
+        }
+        if (replays > maxit + 1) break;
+    }
+    VSR_HIP(hipStreamSynchronize(origin));
+    double t1 = now_s();
+    bool all = true, bad_rhs = false;
+    std::string failed;
+    for (int i = 0; i < count; ++i) {
+        vsr_problem *P = members[i];
+        launch_cast<double, double>(P->n, P->vx, x_dev[i], P->ex());
+        VSR_HIP(hipMemcpyAsync(P->host_scal, P->scal, sizeof(double) * SC_N, hipMemcpyDeviceToHost, P->stream));
+        VSR_HIP(hipStreamSynchronize(P->stream));
+        const double it = P->host_scal[SC_IT], status = P->host_scal[SC_STATUS];
+        const double bb = P->host_scal[SC_BB], rr = P->host_scal[SC_RR];
+        const double tr = true_residual(P, b_dev[i], x_dev[i]);
+        vsr_solve_info loc{};
+        loc.iterations = (int32_t)it;
+        loc.converged = status == 1.0 ? 1 : 0;
+        loc.rel_residual = bb > 0 ? std::sqrt(rr / bb) : 0.0;
+        loc.true_rel_residual = bb > 0 ? tr / std::sqrt(bb) : 0.0;
+        loc.omega = P->omega;
+        loc.lambda_min = P->lmin;
+        loc.lambda_max = P->lmax;
+        loc.setup_seconds = P->setup_seconds;
+        loc.solve_seconds = t1 - t0;
+        if (infos) infos[i] = loc;
+        if (status == 2.0 && bb - bb != 0.0) bad_rhs = true;
+        if (status != 1.0) {
+            all = false;
+            failed += (failed.empty() ? "" : ", ") + std::to_string(i);
+        }
+    }
+    if (bad_rhs) throw Error(VSR_EINVAL, "non-finite right-hand side");
+    if (!all) {
+        if (count == 1) throw Error(VSR_ENOCONV, "PCG did not converge in " + std::to_string((int)members[0]->host_scal[SC_IT]) +
+                                                   " iterations");
+        throw Error(VSR_ENOCONV, "batched PCG: members not converged: " + failed);
+    }
+}
 
 extern "C" {
 
@@ -786,6 +928,16 @@ vsr_status vsr_pcg_solve(vsr_problem *P, const double *b, double *x, double rtol
     vsr_status st = guarded([&] {
         if (!P || !b || !x) throw Error(VSR_EINVAL, "NULL argument");
         if (!(rtol > 0)) throw Error(VSR_EINVAL, "rtol must be positive");
+        if (!P->profiling) {
+            // device-driven: the gated iteration replayed from a graph, the stop polled one
+            // iteration behind (no host round trip between iterations)
+            if (!P->self) P->self = make_batch(1, &P, 1, P->opt.batch_eager != 0, false);
+            const double *bv[1] = {b};
+            double *xv[1] = {x};
+            P->self->solve(bv, xv, rtol, &loc);
+            return;
+        }
+        // host-driven (profiling: every recorded patch launch belongs to a real iteration)
         double t0 = now_s();
         int maxit = P->opt.max_iterations > 0 ? P->opt.max_iterations : 1000;
         pcg_init(P, b, x);
@@ -869,7 +1021,7 @@ vsr_status vsr_factor_info(const vsr_problem *P, int64_t *num_patches, int64_t *
     });
 }
 
-void vsr_destroy(vsr_problem *P) { delete P; }
+void vsr_destroy(vsr_problem *P) { destroy_problem(P); }
 
 vsr_status vsr_get_tuning(const vsr_problem *P, int32_t shapes[6]) {
     return guarded([&] {
@@ -894,6 +1046,8 @@ vsr_status vsr_set_tuning(vsr_problem *P, const int32_t shapes[6]) {
             if (shapes[i] < 0 || shapes[i] > 2) throw Error(VSR_EINVAL, "workgroups per cell must be 0, 1 or 2");
         VSR_HIP(hipStreamSynchronize(P->stream));
         P->tune = Tuning{shapes[0], shapes[1], shapes[2], shapes[3], shapes[4], shapes[5]};
+        delete P->self;   // its recorded iteration holds the old shapes
+        P->self = nullptr;
     });
 }
 
@@ -911,33 +1065,7 @@ vsr_status vsr_batch_create(int32_t count, vsr_problem *const *members, const vs
         if (opt) o = *opt;
         else vsr_default_options(&o);
         if (o.batch_streams < 0 || o.batch_streams > 16) throw Error(VSR_EINVAL, "batch_streams must be in [0, 16]");
-        auto B = std::make_unique<vsr_batch>();
-        const int ns = std::min<int>(o.batch_streams > 0 ? o.batch_streams : 4, count);
-        B->streams.resize(ns, nullptr);
-        for (auto &st : B->streams) VSR_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
-        VSR_HIP(hipStreamCreateWithFlags(&B->origin, hipStreamNonBlocking));
-        B->events.resize(1 + ns, nullptr);
-        for (auto &e : B->events) VSR_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-        // largest member first onto the least loaded stream
-        std::vector<int> order(count);
-        for (int i = 0; i < count; ++i) order[i] = i;
-        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return members[a]->n > members[b]->n; });
-        std::vector<double> load(ns, 0.0);
-        B->stream_of.assign(count, 0);
-        for (int i : order) {
-            int j = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-            B->stream_of[i] = j;
-            load[j] += (double)members[i]->n;
-        }
-        std::vector<const double *> sc(count);
-        for (int i = 0; i < count; ++i) sc[i] = members[i]->scal;
-        VSR_HIP(hipMalloc((void **)&B->scals, sizeof(double *) * count));
-        VSR_HIP(hipMemcpy(B->scals, sc.data(), sizeof(double *) * count, hipMemcpyHostToDevice));
-        VSR_HIP(hipMalloc((void **)&B->active, sizeof(int)));
-        VSR_HIP(hipHostMalloc((void **)&B->host_active, sizeof(int), hipHostMallocDefault));
-        B->eager = o.batch_eager != 0;
-        B->members.assign(members, members + count);   // ownership passes only once nothing can fail
-        *out = B.release();
+        *out = make_batch(count, members, o.batch_streams > 0 ? o.batch_streams : 4, o.batch_eager != 0, true);
     });
 }
 
@@ -974,81 +1102,9 @@ vsr_status vsr_pcg_solve_batch(vsr_batch *B, const double *const *b_dev, double 
     return guarded([&] {
         if (!B || !b_dev || !x_dev) throw Error(VSR_EINVAL, "NULL argument");
         if (!(rtol > 0)) throw Error(VSR_EINVAL, "rtol must be positive");
-        const int count = (int)B->members.size();
-        for (int i = 0; i < count; ++i)
+        for (size_t i = 0; i < B->members.size(); ++i)
             if (!b_dev[i] || !x_dev[i]) throw Error(VSR_EINVAL, "NULL vector of member " + std::to_string(i));
-        // inputs written on the members' own streams are complete before the batch starts
-        for (vsr_problem *P : B->members) VSR_HIP(hipStreamSynchronize(P->stream));
-        double t0 = now_s();
-        int maxit = 0;
-        std::vector<int> idx(count);
-        for (int i = 0; i < count; ++i) idx[i] = i;
-        for (vsr_problem *P : B->members) maxit = std::max(maxit, P->opt.max_iterations > 0 ? P->opt.max_iterations : 1000);
-        // start: x = 0, r = b, stopping data, z = M r, p = z (gated: a zero b stops at once)
-        {
-            int i = 0;
-            B->for_members([&](vsr_problem *P) {
-                pcg_init(P, b_dev[i], P->vx);
-                launch_pcg_start(P->scal, rtol, P->opt.max_iterations > 0 ? P->opt.max_iterations : 1000, P->ex());
-                P->gate = P->scal + SC_DONE;
-                pcg_first_direction(P);
-                P->gate = nullptr;
-                ++i;
-            });
-        }
-        if (!B->eager && !B->exec) {
-            for (vsr_problem *P : B->members) P->capturing = true;
-            VSR_HIP(hipStreamBeginCapture(B->origin, hipStreamCaptureModeThreadLocal));
-            try {
-                B->iteration();
-            } catch (...) {
-                hipGraph_t g = nullptr;
-                (void)hipStreamEndCapture(B->origin, &g);
-                if (g) (void)hipGraphDestroy(g);
-                for (vsr_problem *P : B->members) P->capturing = false;
-                throw;
-            }
-            VSR_HIP(hipStreamEndCapture(B->origin, &B->graph));
-            for (vsr_problem *P : B->members) P->capturing = false;
-            VSR_HIP(hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0));
-        }
-        int replays = 0;
-        for (;;) {
-            if (B->eager) B->iteration();
-            else VSR_HIP(hipGraphLaunch(B->exec, B->origin));
-            ++replays;
-            VSR_HIP(hipMemcpyAsync(B->host_active, B->active, sizeof(int), hipMemcpyDeviceToHost, B->origin));
-            VSR_HIP(hipStreamSynchronize(B->origin));
-            if (*B->host_active == 0 || replays > maxit) break;
-        }
-        double t1 = now_s();
-        bool all = true;
-        std::string failed;
-        for (int i = 0; i < count; ++i) {
-            vsr_problem *P = B->members[i];
-            launch_cast<double, double>(P->n, P->vx, x_dev[i], P->ex());
-            VSR_HIP(hipMemcpyAsync(P->host_scal, P->scal, sizeof(double) * SC_N, hipMemcpyDeviceToHost, P->stream));
-            VSR_HIP(hipStreamSynchronize(P->stream));
-            const double it = P->host_scal[SC_IT], status = P->host_scal[SC_STATUS];
-            const double bb = P->host_scal[SC_BB], rr = P->host_scal[SC_RR];
-            const double tr = true_residual(P, b_dev[i], x_dev[i]);
-            vsr_solve_info loc{};
-            loc.iterations = (int32_t)it;
-            loc.converged = status == 1.0 ? 1 : 0;
-            loc.rel_residual = bb > 0 ? std::sqrt(rr / bb) : 0.0;
-            loc.true_rel_residual = bb > 0 ? tr / std::sqrt(bb) : 0.0;
-            loc.omega = P->omega;
-            loc.lambda_min = P->lmin;
-            loc.lambda_max = P->lmax;
-            loc.setup_seconds = P->setup_seconds;
-            loc.solve_seconds = t1 - t0;
-            if (infos) infos[i] = loc;
-            if (status != 1.0) {
-                all = false;
-                failed += (failed.empty() ? "" : ", ") + std::to_string(i);
-            }
-        }
-        if (!all) throw Error(VSR_ENOCONV, "batched PCG: members not converged: " + failed);
+        B->solve(b_dev, x_dev, rtol, infos);
     });
 }
 

@@ -172,3 +172,30 @@ def test_autotune_and_cache_file(vsr, tmp_path):
     assert again.tuning() == t and len(cache.read_text().splitlines()) == 1
     for q in (prob, plain, again):
         q.close()
+
+
+@pytest.mark.parametrize("relax_fp32", [False, True])
+def test_single_solve_graph_and_host_driven_agree(vsr, relax_fp32):
+    """vsr_pcg_solve replays a recorded iteration with the stop taken on the device unless
+    profiling is on, when the host drives every iteration; both give the same solve."""
+    say(f"case single-solve paths fp32={relax_fp32}")
+    d, f = member_problem((3, 3, 3), 5, 0.15, True, seed=60)
+    prob = vsr.Problem(d["vertices"], 5, kappa=d["kappa"], relax_fp32=relax_fp32, seed=0)
+    b = rhs(prob, f)
+    x_graph, x_host = torch.zeros_like(b), torch.zeros_like(b)
+    info_g = prob.pcg_solve(b, x_graph)
+    prob.set_profiling(True)
+    info_h = prob.pcg_solve(b, x_host)
+    prob.set_profiling(False)
+    launches, total_ms, _ = prob.kernel_stats()
+    say(f"  graph {info_g['iterations']} its, host {info_h['iterations']} its, rel {rel(x_graph, x_host):.1e}, "
+        f"{launches} profiled patch launches")
+    assert launches == info_h["iterations"] * 2 and total_ms > 0   # two relaxations per cycle
+    tol = 1e-6 if relax_fp32 else 1e-10
+    assert abs(info_g["iterations"] - info_h["iterations"]) <= (1 if relax_fp32 else 0)
+    assert rel(x_graph, x_host) < tol
+    x_again = torch.zeros_like(b)
+    info_again = prob.pcg_solve(b * 2.0, x_again)   # the recorded iteration is reused
+    assert info_again["iterations"] == info_g["iterations"] or relax_fp32
+    assert rel(x_again, 2.0 * x_graph) < tol
+    prob.close()
