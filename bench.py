@@ -93,7 +93,7 @@ def solve_timed(vsr, torch, w, relax_fp32, steps, warmup, profile, autotune=Fals
         prob.set_profiling(False)
     npatch, nentries = prob.factor_info()
     out = dict(n=n, seconds=dt, iterations=iters[-1], info=info, stats=stats, setup_s=info["setup_seconds"],
-               patches=npatch, factor_entries=nentries)
+               patches=npatch, factor_entries=nentries, shapes=list(prob.tuning()))
     prob.close()
     return out
 
@@ -230,7 +230,7 @@ def main():
         "data": "synthetic (seeded U[-1,1] RHS at quadrature points)",
         "config": {"workload": wname, "cells": [nc, nc, nc], "p": p, "dofs": n, "rtol": 1e-8,
                    "preconditioner": "hybrid V(1,1), vertex-star patches at all vertices, Q1 coarse",
-                   "autotune": bool(args.autotune), "parallelism": "single GPU"},
+                   "autotune": bool(args.autotune), "launch_shapes": r32["shapes"], "parallelism": "single GPU"},
         f"iterations_p{p}": r32["iterations"],
         "true_rel_residual": r32["info"]["true_rel_residual"],
         "setup_seconds": r32["setup_s"],

@@ -371,8 +371,10 @@ bool tune_from_file(const char *path, const std::string &key, Tuning &t) {
     while (std::getline(f, line)) {   // the last entry for a key wins
         if (line.compare(0, key.size(), key) != 0 || line.size() <= key.size() || line[key.size()] != ' ') continue;
         Tuning c;
-        if (std::sscanf(line.c_str() + key.size(), " cpw64=%d cpw32=%d axis_block=%d patch_unroll=%d split64=%d split32=%d",
-                        &c.op_cpw64, &c.op_cpw32, &c.axis_block, &c.patch_unroll, &c.opg_split64, &c.opg_split32) == 6) {
+        if (std::sscanf(line.c_str() + key.size(),
+                        " cpw64=%d cpw32=%d axis_block=%d patch_unroll=%d split64=%d split32=%d axis_tiled=%d",
+                        &c.op_cpw64, &c.op_cpw32, &c.axis_block, &c.patch_unroll, &c.opg_split64, &c.opg_split32,
+                        &c.axis_tiled) == 7) {
             t = c;
             found = true;
         }
@@ -454,6 +456,22 @@ void autotune(vsr_problem *P) {
             launch_axis_pass<T, T>(Tp[ax].start, Tp[ax].bw, wt<T>(Tp[ax]), ax, L, L, b, a, T(1), T(0), P->ex());
         }
     };
+    // lattice passes: tiled or streamed, jointly with the block size
+    auto pick_passes = [&](auto &&fn) {
+        double best = 1e300;
+        Tuning keep = P->tune;
+        for (int tiled : {0, 1})
+            for (int bs : {64, 128, 256, 512, 1024}) {
+                P->tune.axis_tiled = tiled;
+                P->tune.axis_block = bs;
+                double ms = time_ms(P, fn);
+                if (ms < best) {
+                    best = ms;
+                    keep = P->tune;
+                }
+            }
+        P->tune = keep;
+    };
     auto patch = [&](auto zero) {
         using T = decltype(zero);
         launch_patch_all<T>(P->d, P->pa, P->n_int, P->verts, (const T *)P->fint, P->n_bnd, P->bdesc, P->boff,
@@ -463,12 +481,12 @@ void autotune(vsr_problem *P) {
     if (P->fp32) {
         launch_fill<float>(P->n, (float *)P->t1, 1.f, P->ex());
         launch_fill<float>(P->n, (float *)P->rF, 1.f, P->ex());
-        pick(P->tune.axis_block, {64, 128, 256, 512, 1024}, [&] { passes(0.f); });
+        pick_passes([&] { passes(0.f); });
         if (P->n_int + P->n_bnd > 0) pick(P->tune.patch_unroll, {4, 8, 16}, [&] { patch(0.f); });
     } else {
         launch_fill<double>(P->n, (double *)P->t1, 1.0, P->ex());
         launch_fill<double>(P->n, (double *)P->rF, 1.0, P->ex());
-        pick(P->tune.axis_block, {64, 128, 256, 512, 1024}, [&] { passes(0.0); });
+        pick_passes([&] { passes(0.0); });
         if (P->n_int + P->n_bnd > 0) pick(P->tune.patch_unroll, {4, 8, 16}, [&] { patch(0.0); });
     }
     // the patch boxes of absent stars must read as zero in the assembly
@@ -482,7 +500,7 @@ void autotune(vsr_problem *P) {
         std::ofstream f(P->opt.tune_cache, std::ios::app);
         f << key << " cpw64=" << P->tune.op_cpw64 << " cpw32=" << P->tune.op_cpw32 << " axis_block=" << P->tune.axis_block
           << " patch_unroll=" << P->tune.patch_unroll << " split64=" << P->tune.opg_split64
-          << " split32=" << P->tune.opg_split32 << "\n";
+          << " split32=" << P->tune.opg_split32 << " axis_tiled=" << P->tune.axis_tiled << "\n";
     }
 }
 
@@ -1023,7 +1041,7 @@ vsr_status vsr_factor_info(const vsr_problem *P, int64_t *num_patches, int64_t *
 
 void vsr_destroy(vsr_problem *P) { destroy_problem(P); }
 
-vsr_status vsr_get_tuning(const vsr_problem *P, int32_t shapes[6]) {
+vsr_status vsr_get_tuning(const vsr_problem *P, int32_t shapes[7]) {
     return guarded([&] {
         if (!P || !shapes) throw Error(VSR_EINVAL, "NULL argument");
         shapes[0] = P->tune.op_cpw64;
@@ -1032,10 +1050,11 @@ vsr_status vsr_get_tuning(const vsr_problem *P, int32_t shapes[6]) {
         shapes[3] = P->tune.patch_unroll;
         shapes[4] = P->tune.opg_split64;
         shapes[5] = P->tune.opg_split32;
+        shapes[6] = P->tune.axis_tiled;
     });
 }
 
-vsr_status vsr_set_tuning(vsr_problem *P, const int32_t shapes[6]) {
+vsr_status vsr_set_tuning(vsr_problem *P, const int32_t shapes[7]) {
     return guarded([&] {
         if (!P || !shapes) throw Error(VSR_EINVAL, "NULL argument");
         auto cpw_ok = [](int c) { return c == 1 || c == 2 || c == 4; };
@@ -1044,8 +1063,9 @@ vsr_status vsr_set_tuning(vsr_problem *P, const int32_t shapes[6]) {
         if (shapes[3] != 4 && shapes[3] != 8 && shapes[3] != 16) throw Error(VSR_EINVAL, "unroll must be 4, 8 or 16");
         for (int i = 4; i < 6; ++i)
             if (shapes[i] < 0 || shapes[i] > 2) throw Error(VSR_EINVAL, "workgroups per cell must be 0, 1 or 2");
+        if (shapes[6] != 0 && shapes[6] != 1) throw Error(VSR_EINVAL, "tiled lattice passes must be 0 or 1");
         VSR_HIP(hipStreamSynchronize(P->stream));
-        P->tune = Tuning{shapes[0], shapes[1], shapes[2], shapes[3], shapes[4], shapes[5]};
+        P->tune = Tuning{shapes[0], shapes[1], shapes[2], shapes[3], shapes[4], shapes[5], shapes[6]};
         delete P->self;   // its recorded iteration holds the old shapes
         P->self = nullptr;
     });

@@ -22,6 +22,7 @@ struct Tuning {
     int patch_unroll = 8;   // column loads in flight per thread in the patch panels (4, 8, 16)
     int opg_split64 = 0;    // workgroups per cell of the general operator, FP64 (1, 2; 0: by size)
     int opg_split32 = 0;    // same, FP32
+    int axis_tiled = 0;     // lattice passes with whole lines staged in LDS (1) or streamed (0)
 };
 
 // Where a launch goes: its stream, an optional gate (a device flag; when it is nonzero

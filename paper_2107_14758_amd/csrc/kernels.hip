@@ -251,6 +251,72 @@ __global__ void __launch_bounds__(1024) k_load_vector(const double *__restrict__
 // reads the window in[start[o] .. start[o] + bw) along that axis with dense weights
 // w[o * bw + j] (zero where M has no entry): a fixed trip count, wave-uniform rows and
 // weights for the y and z passes, and coalesced loads along x.
+// The same pass with the lines staged in LDS: a workgroup takes LT whole lines along `axis`
+// (consecutive line indices), reads each input line once from HBM, coalesced (along x for
+// the x pass, across neighbouring lines for the y and z passes), forms the band products
+// from LDS and writes its outputs coalesced (the x pass through an LDS output tile).
+// Line l enumerates the two other coordinates, first one fastest.
+template <typename Tin, typename Tout>
+__global__ void k_axis_tile(const double *__restrict__ gate, const int *__restrict__ start, const Tout *__restrict__ w,
+                            int bw, int axis, int ix, int iy, int iz, int ox, int oy, int oz, int LT,
+                            const Tin *__restrict__ in, Tout *__restrict__ out, Tout alpha, Tout beta) {
+    if (gated(gate)) return;
+    extern __shared__ unsigned char smem_raw[];
+    Tout *tile = reinterpret_cast<Tout *>(smem_raw);
+    const int lin = axis == 0 ? ix : (axis == 1 ? iy : iz);
+    const int lout = axis == 0 ? ox : (axis == 1 ? oy : oz);
+    const int d0 = axis == 0 ? iy : ix, d1 = axis == 2 ? iy : iz;   // the two other extents (same in and out)
+    const int64_t nlines = (int64_t)d0 * d1;
+    const int ld = LT + 1;
+    Tout *otile = tile + (int64_t)lin * ld;   // x pass only
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int64_t l0 = (int64_t)blockIdx.x * LT;
+    const int nl = (int)min<int64_t>(LT, nlines - l0);
+    // element (line l, k along the axis) of an array with axis extent len
+    auto addr = [&](int64_t l, int k, int len) -> int64_t {
+        const int64_t a = l % d0, b = l / d0;
+        if (axis == 0) return (b * d0 + a) * len + k;                 // (y, z) = (a, b)
+        if (axis == 1) return (b * len + k) * (int64_t)ix + a;        // (x, z) = (a, b)
+        return ((int64_t)k * iy + b) * ix + a;                        // (x, y) = (a, b)
+    };
+    if (axis == 0) {
+        for (int t = tid; t < nl * lin; t += nt) {
+            const int l = t / lin, k = t % lin;
+            tile[k * ld + l] = (Tout)in[addr(l0 + l, k, lin)];
+        }
+    } else {
+        for (int t = tid; t < nl * lin; t += nt) {
+            const int l = t % nl, k = t / nl;
+            tile[k * ld + l] = (Tout)in[addr(l0 + l, k, lin)];
+        }
+    }
+    __syncthreads();
+    for (int t = tid; t < nl * lout; t += nt) {
+        const int l = t % nl, o = t / nl;
+        const int s0 = start[o];
+        const Tout *wr = w + (int64_t)o * bw;
+        const Tout *src = tile + (int64_t)s0 * ld + l;
+        Tout s = 0;
+#pragma unroll 4
+        for (int j = 0; j < bw; ++j) s += wr[j] * src[j * ld];
+        if (axis == 0) {
+            otile[o * ld + l] = s;
+        } else {
+            const int64_t q = addr(l0 + l, o, lout);
+            out[q] = beta == Tout(0) ? alpha * s : alpha * s + beta * out[q];
+        }
+    }
+    if (axis == 0) {
+        __syncthreads();
+        for (int t = tid; t < nl * lout; t += nt) {
+            const int l = t / lout, o = t % lout;
+            const int64_t q = addr(l0 + l, o, lout);
+            const Tout s = otile[o * ld + l];
+            out[q] = beta == Tout(0) ? alpha * s : alpha * s + beta * out[q];
+        }
+    }
+}
+
 template <typename Tin, typename Tout>
 __global__ void k_axis_pass(const double *__restrict__ gate, const int *__restrict__ start, const Tout *__restrict__ w,
                             int bw, int axis, int ix, int iy, int iz, int ox, int oy, int oz,
@@ -522,6 +588,19 @@ void launch_axis_pass(const int *start, int bw, const Tout *w, int axis, const i
     if (n == 0) return;
     const int bs = e.t.axis_block;
     if (bs < 64 || bs > 1024 || bs % 64 != 0) throw Error(VSR_EINVAL, "axis block must be a multiple of 64 in [64, 1024]");
+    if (e.t.axis_tiled) {
+        const int LT = sizeof(Tout) == 4 ? 32 : 16;
+        const int lin = in_dims[axis], lout = out_dims[axis];
+        const size_t lds = ((size_t)lin + (axis == 0 ? (size_t)lout : 0)) * (LT + 1) * sizeof(Tout);
+        if (lds <= 64 * 1024) {
+            const int64_t nlines = n / lout;
+            const unsigned blocks = (unsigned)((nlines + LT - 1) / LT);
+            hipLaunchKernelGGL((k_axis_tile<Tin, Tout>), dim3(blocks), dim3(bs), lds, e.s, e.gate, start, w, bw, axis,
+                               in_dims[0], in_dims[1], in_dims[2], out_dims[0], out_dims[1], out_dims[2], LT, in, out,
+                               alpha, beta);
+            return;
+        }
+    }
     hipLaunchKernelGGL((k_axis_pass<Tin, Tout>), dim3(grid_for(n, bs)), dim3(bs), 0, e.s, e.gate, start, w, bw, axis,
                        in_dims[0], in_dims[1], in_dims[2], out_dims[0], out_dims[1], out_dims[2], in, out, alpha, beta);
 }

@@ -174,13 +174,13 @@ class Problem:
 
     def tuning(self):
         """Launch shapes in use: (Cartesian-operator cells/workgroup FP64, FP32, lattice-pass block,
-        panel unroll, general-operator workgroups/cell FP64, FP32)."""
-        a = (ctypes.c_int32 * 6)()
+        panel unroll, general-operator workgroups/cell FP64, FP32, lattice passes staged in LDS)."""
+        a = (ctypes.c_int32 * 7)()
         _check(lib().vsr_get_tuning(self._h, a))
         return tuple(a)
 
     def set_tuning(self, shapes):
-        a = (ctypes.c_int32 * 6)(*[int(v) for v in shapes])
+        a = (ctypes.c_int32 * 7)(*[int(v) for v in shapes])
         _check(lib().vsr_set_tuning(self._h, a))
 
     def close(self):
