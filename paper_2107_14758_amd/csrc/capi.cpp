@@ -87,7 +87,7 @@ struct vsr_problem {
     // work buffers (cycle precision unless noted)
     void *t1 = nullptr, *t2 = nullptr, *rF = nullptr, *zF = nullptr, *U = nullptr;
     void *c1 = nullptr, *c2 = nullptr, *c3 = nullptr, *c4 = nullptr;
-    void *z1 = nullptr, *az = nullptr;
+    void *z1 = nullptr, *az = nullptr, *az2 = nullptr;   // az is zero between cycles
     double *vp = nullptr, *vq = nullptr, *vr = nullptr, *vz = nullptr, *vt = nullptr;
     double *scal = nullptr, *partials = nullptr, *host_scal = nullptr;
     double omega = 1.0, lmin = 0.0, lmax = 0.0;
@@ -95,6 +95,7 @@ struct vsr_problem {
     // launch context: an optional gate (set while a batched solve drives this problem)
     // and the launch shapes chosen by the autotuner
     const double *gate = nullptr;
+    double *mirror = nullptr;         // host-visible copy of the stop flag (batched solves)
     Tuning tune{};
     double *vx = nullptr;             // solution of a batched solve
     vsr_batch *self = nullptr;        // batch of this problem alone (graph-replayed single solves)
@@ -137,9 +138,10 @@ struct vsr_problem {
 
 namespace {
 
+// y = A x; with fill = false y must hold zeros already (kept so by the kernels that used it)
 template <typename T>
-void op_apply(vsr_problem *P, const T *x, T *y) {
-    launch_fill<T>(P->n, y, T(0), P->ex());
+void op_apply(vsr_problem *P, const T *x, T *y, bool fill = true) {
+    if (fill) launch_fill<T>(P->n, y, T(0), P->ex());
     if constexpr (std::is_same<T, double>::value) {
         if (P->cartesian) launch_op_kron<double>(P->d, P->AB64, P->mu64, x, y, P->ex());
         else launch_op_general<double>(P->d, P->IDq64, P->Gw64, x, y, P->ex());
@@ -226,13 +228,15 @@ void precondition(vsr_problem *P, const double *r, double *z, int mode) {
         coarse_apply<T, double>(P, r, z1, T(1), T(1));
     } else {
         // hybrid V(1,1): z1 = w S r; z2 = z1 + C (r - A z1); z = z2 + w S (r - A z2)
+        // (az is zero on entry and the residuals leave it zero)
+        T *az2 = (T *)P->az2;
         relax_apply<T, double>(P, r, z1, w, T(0));
-        op_apply<T>(P, z1, az);
-        launch_residual<T>(P->n, r, az, az, P->ex());
-        coarse_apply<T, T>(P, az, z1, T(1), T(1));
-        op_apply<T>(P, z1, az);
-        launch_residual<T>(P->n, r, az, az, P->ex());
-        relax_apply<T, T>(P, az, z1, w, T(1));
+        op_apply<T>(P, z1, az, false);
+        launch_residual<T>(P->n, r, az, az2, P->ex());
+        coarse_apply<T, T>(P, az2, z1, T(1), T(1));
+        op_apply<T>(P, z1, az, false);
+        launch_residual<T>(P->n, r, az, az2, P->ex());
+        relax_apply<T, T>(P, az2, z1, w, T(1));
     }
     launch_axpby_to_double<T>(P->n, 1.0, z1, 0.0, z, P->ex());
     VSR_HIP(hipGetLastError());
@@ -249,44 +253,44 @@ double read_scalar(vsr_problem *P, int slot) {
     return *P->host_scal;
 }
 
+void dot_into(vsr_problem *P, const double *x, const double *y, int mode) {
+    launch_dot(P->n, x, y, P->partials, P->scal, mode, P->mirror, P->ex());
+}
+
 double dot(vsr_problem *P, const double *x, const double *y) {
-    int nb = launch_dot_partial(P->n, x, y, P->partials, P->ex());
-    launch_finalize(nb, P->partials, P->scal, 0, P->ex());
+    dot_into(P, x, y, 0);
     return read_scalar(P, SC_TMP);
 }
 
 // ---- PCG (Hestenes-Stiefel) in pieces shared by the host-driven and the batched solves.
-// x = 0, r = b, RR = b.b
+// x = 0, r = b, q = 0, RR = b.b
 void pcg_init(vsr_problem *P, const double *b, double *x) {
     launch_fill<double>(P->n, x, 0.0, P->ex());
+    launch_fill<double>(P->n, P->vq, 0.0, P->ex());
     launch_cast<double, double>(P->n, b, P->vr, P->ex());
-    int nb = launch_dot_partial(P->n, b, b, P->partials, P->ex());
-    launch_finalize(nb, P->partials, P->scal, 4, P->ex());
+    dot_into(P, b, b, 4);
 }
 
 // z = M r, RZ = r.z, p = z
 void pcg_first_direction(vsr_problem *P) {
     precond(P, P->vr, P->vz, 0);
-    int nb = launch_dot_partial(P->n, P->vr, P->vz, P->partials, P->ex());
-    launch_finalize(nb, P->partials, P->scal, 3, P->ex());
+    dot_into(P, P->vr, P->vz, 3);
     launch_cast<double, double>(P->n, P->vz, P->vp, P->ex());
 }
 
-// q = A p, alpha = RZ / p.q, x += alpha p, r -= alpha q, RR = r.r; rr_mode 4 leaves the
-// stopping test to the host, 5 counts the update and takes the test on the device
+// q = A p (q is zero on entry), alpha = RZ / p.q, x += alpha p, r -= alpha q, q = 0,
+// RR = r.r; rr_mode 4 leaves the stopping test to the host, 5 counts the update and takes
+// the test on the device
 void pcg_update(vsr_problem *P, double *x, int rr_mode) {
-    op_apply<double>(P, P->vp, P->vq);
-    int nb = launch_dot_partial(P->n, P->vp, P->vq, P->partials, P->ex());
-    launch_finalize(nb, P->partials, P->scal, 1, P->ex());
-    nb = launch_pcg_xr(P->n, x, P->vr, P->vp, P->vq, P->scal, P->partials, P->ex());
-    launch_finalize(nb, P->partials, P->scal, rr_mode, P->ex());
+    op_apply<double>(P, P->vp, P->vq, false);
+    dot_into(P, P->vp, P->vq, 1);
+    launch_pcg_xr(P->n, x, P->vr, P->vp, P->vq, P->scal, P->partials, rr_mode, P->mirror, P->ex());
 }
 
 // z = M r, beta = r.z / RZ, RZ = r.z, p = z + beta p
 void pcg_direction(vsr_problem *P) {
     precond(P, P->vr, P->vz, 0);
-    int nb = launch_dot_partial(P->n, P->vr, P->vz, P->partials, P->ex());
-    launch_finalize(nb, P->partials, P->scal, 2, P->ex());
+    dot_into(P, P->vr, P->vz, 2);
     launch_pcg_p(P->n, P->vp, P->vz, P->scal, P->ex());
 }
 
@@ -314,20 +318,17 @@ void estimate_damping(vsr_problem *P) {
     VSR_HIP(hipMemcpy(P->vr, h.data(), P->n * sizeof(double), hipMemcpyHostToDevice));
     launch_fill<double>(P->n, P->vt, 0.0, P->ex());
     precond(P, P->vr, P->vz, 1);
-    int nb = launch_dot_partial(P->n, P->vr, P->vz, P->partials, P->ex());
-    launch_finalize(nb, P->partials, P->scal, 3, P->ex());
+    dot_into(P, P->vr, P->vz, 3);
     double rz0 = read_scalar(P, SC_RZ);
     launch_cast<double, double>(P->n, P->vz, P->vp, P->ex());
     std::vector<double> alphas, betas;
     for (int j = 0; j < steps; ++j) {
         op_apply<double>(P, P->vp, P->vq);
-        nb = launch_dot_partial(P->n, P->vp, P->vq, P->partials, P->ex());
-        launch_finalize(nb, P->partials, P->scal, 1, P->ex());
-        nb = launch_pcg_xr(P->n, P->vt, P->vr, P->vp, P->vq, P->scal, P->partials, P->ex());
+        dot_into(P, P->vp, P->vq, 1);
+        launch_pcg_xr(P->n, P->vt, P->vr, P->vp, P->vq, P->scal, P->partials, 4, nullptr, P->ex());
         double alpha = read_scalar(P, SC_ALPHA);
         precond(P, P->vr, P->vz, 1);
-        nb = launch_dot_partial(P->n, P->vr, P->vz, P->partials, P->ex());
-        launch_finalize(nb, P->partials, P->scal, 2, P->ex());
+        dot_into(P, P->vr, P->vz, 2);
         double beta = read_scalar(P, SC_BETA);
         double rz = read_scalar(P, SC_RZNEW);
         alphas.push_back(alpha);
@@ -493,6 +494,9 @@ void autotune(vsr_problem *P) {
     const int64_t w3 = (int64_t)P->pa.w * P->pa.w * P->pa.w, nv = (int64_t)(P->d.nx + 1) * (P->d.ny + 1) * (P->d.nz + 1);
     if (P->fp32) launch_fill<float>(nv * w3, (float *)P->U, 0.f, P->ex());
     else launch_fill<double>(nv * w3, (double *)P->U, 0.0, P->ex());
+    // the cycle keeps az at zero between uses
+    if (P->fp32) launch_fill<float>(P->n, (float *)P->az, 0.f, P->ex());
+    else launch_fill<double>(P->n, (double *)P->az, 0.0, P->ex());
     VSR_HIP(hipStreamSynchronize(P->stream));
     std::lock_guard<std::mutex> lk(g_tune_mutex);
     g_tune_cache[key] = P->tune;
@@ -566,9 +570,8 @@ struct vsr_batch {
     std::vector<hipEvent_t> events;        // [0] fork, [1 + j] join of stream j
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    const double **scals = nullptr;        // device array of the members' scalar blocks
-    int *active = nullptr;                 // device counter of members still iterating
-    int *host_active = nullptr;            // pinned, two slots (polled one replay behind)
+    double *host_done = nullptr;           // pinned and mapped: each member's stop flag, written by its kernels
+    double *dev_done = nullptr;            // the same memory as the device sees it
     hipEvent_t poll[2] = {nullptr, nullptr};
     bool eager = false;
     bool owns_members = true;
@@ -590,6 +593,7 @@ struct vsr_batch {
             } catch (...) {
                 P->stream = keep;
                 P->gate = nullptr;
+                P->mirror = nullptr;
                 throw;
             }
             P->stream = keep;
@@ -600,16 +604,24 @@ struct vsr_batch {
         }
     }
 
-    // One lockstep PCG iteration of every member, each gated by its own stop flag, then the
-    // count of members still active.
+    // One lockstep PCG iteration of every member, each gated by its own stop flag (mirrored to
+    // host memory as it changes).
     void iteration() {
-        for_members([](vsr_problem *P) {
+        int i = 0;
+        for_members([&](vsr_problem *P) {
             P->gate = P->scal + SC_DONE;
+            P->mirror = dev_done + i++;
             pcg_update(P, P->vx, 5);
             pcg_direction(P);
             P->gate = nullptr;
+            P->mirror = nullptr;
         });
-        launch_count_active((int)members.size(), scals, active, Exec{origin, nullptr, Tuning{}});
+    }
+    bool all_done() const {
+        const volatile double *f = host_done;
+        for (size_t i = 0; i < members.size(); ++i)
+            if (f[i] == 0.0) return false;
+        return true;
     }
 };
 
@@ -643,12 +655,9 @@ vsr_batch *make_batch(int count, vsr_problem *const *members, int nstreams, bool
         B->stream_of[i] = j;
         load[j] += (double)members[i]->n;
     }
-    std::vector<const double *> sc(count);
-    for (int i = 0; i < count; ++i) sc[i] = members[i]->scal;
-    VSR_HIP(hipMalloc((void **)&B->scals, sizeof(double *) * count));
-    VSR_HIP(hipMemcpy(B->scals, sc.data(), sizeof(double *) * count, hipMemcpyHostToDevice));
-    VSR_HIP(hipMalloc((void **)&B->active, sizeof(int)));
-    VSR_HIP(hipHostMalloc((void **)&B->host_active, 2 * sizeof(int), hipHostMallocDefault));
+    VSR_HIP(hipHostMalloc((void **)&B->host_done, sizeof(double) * count, hipHostMallocMapped | hipHostMallocCoherent));
+    VSR_HIP(hipHostGetDevicePointer((void **)&B->dev_done, B->host_done, 0));
+    for (int i = 0; i < count; ++i) B->host_done[i] = 1.0;
     B->eager = eager;
     B->members.assign(members, members + count);
     B->owns_members = owns;
@@ -665,9 +674,7 @@ vsr_batch::~vsr_batch() {
         if (e) (void)hipEventDestroy(e);
     for (hipStream_t st : streams) (void)hipStreamDestroy(st);
     if (origin) (void)hipStreamDestroy(origin);
-    if (scals) (void)hipFree(scals);
-    if (active) (void)hipFree(active);
-    if (host_active) (void)hipHostFree(host_active);
+    if (host_done) (void)hipHostFree(host_done);
     if (owns_members)
         for (vsr_problem *m : members) destroy_problem(m);
 }
@@ -686,7 +693,8 @@ void vsr_batch::solve(const double *const *b_dev, double *const *x_dev, double r
         int i = 0;
         for_members([&](vsr_problem *P) {
             pcg_init(P, b_dev[i], P->vx);
-            launch_pcg_start(P->scal, rtol, P->opt.max_iterations > 0 ? P->opt.max_iterations : 1000, P->ex());
+            launch_pcg_start(P->scal, rtol, P->opt.max_iterations > 0 ? P->opt.max_iterations : 1000, dev_done + i,
+                             P->ex());
             P->gate = P->scal + SC_DONE;
             pcg_first_direction(P);
             P->gate = nullptr;
@@ -713,14 +721,11 @@ void vsr_batch::solve(const double *const *b_dev, double *const *x_dev, double r
     for (;;) {
         if (eager) iteration();
         else VSR_HIP(hipGraphLaunch(exec, origin));
-        const int slot = replays & 1;
-        VSR_HIP(hipMemcpyAsync(host_active + slot, active, sizeof(int), hipMemcpyDeviceToHost, origin));
-        VSR_HIP(hipEventRecord(poll[slot], origin));
+        VSR_HIP(hipEventRecord(poll[replays & 1], origin));
         ++replays;
-        if (replays >= 2) {   // look at the replay before the one just queued
-            const int j = (replays - 2) & 1;
-            VSR_HIP(hipEventSynchronize(poll[j]));
-            if (host_active[j] == 0) break;
+        if (replays >= 2) {   // wait for the replay before the one just queued, then read the flags
+            VSR_HIP(hipEventSynchronize(poll[(replays - 2) & 1]));
+            if (all_done()) break;
         }
         if (replays > maxit + 1) break;
     }
@@ -887,6 +892,9 @@ vsr_status vsr_setup(const vsr_mesh *mesh, int32_t p, const vsr_coefficients *co
         P->U = alloc_t(nv * w3);
         P->z1 = alloc_t(P->n);
         P->az = alloc_t(P->n);
+        P->az2 = alloc_t(P->n);
+        if (P->fp32) launch_fill<float>(P->n, (float *)P->az, 0.f, P->ex());
+        else launch_fill<double>(P->n, (double *)P->az, 0.0, P->ex());
         P->c1 = alloc_t((int64_t)P->cdim[0] * P->d.Ly * P->d.Lz);
         P->c2 = alloc_t((int64_t)P->cdim[0] * P->cdim[1] * P->d.Lz);
         P->c3 = alloc_t(P->nc);

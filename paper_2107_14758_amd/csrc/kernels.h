@@ -77,29 +77,27 @@ template <typename Tin, typename Tout>
 void launch_cast(int64_t n, const Tin *x, Tout *y, const Exec &e);
 template <typename T>
 void launch_fill(int64_t n, T *x, T v, const Exec &e);
-// partial sums of x.y into partials[nblocks]; returns nblocks used
-int launch_dot_partial(int64_t n, const double *x, const double *y, double *partials, const Exec &e);
-// scal[slot] = sum(partials); mode: 0 plain, 1 alpha = scal[RZ]/sum, 2 beta = sum/scal[RZ] and RZ = sum,
-// 3 RZ = sum, 4 RR = sum, 5 RR = sum and the stopping test of a device-driven PCG (see SC_DONE)
-void launch_finalize(int nb, const double *partials, double *scal, int mode, const Exec &e);
+// x.y reduced into scal (partials: 1024 doubles of scratch; two launches, the second adds the
+// partials in a fixed order).  mode: 0 plain (TMP), 1 p.q -> alpha = RZ / p.q,
+// 2 r.z -> beta = r.z / RZ and RZ = r.z, 3 RZ = r.z, 4 RR = r.r, 5 RR = r.r after an x update
+// with the stopping test of a device-driven PCG (see SC_DONE).  mirror (may be NULL): host-
+// visible copy of DONE written with it.
+void launch_dot(int64_t n, const double *x, const double *y, double *partials, double *scal, int mode, double *mirror,
+                const Exec &e);
 // Start of a device-driven PCG after RR = b.b: BB = RR, IT = 0, stopping data, DONE when b = 0
-// or b is not finite.  Not gated.
-void launch_pcg_start(double *scal, double rtol, int max_iterations, const Exec &e);
-// x += alpha p ; r -= alpha q ; partial r.r
-int launch_pcg_xr(int64_t n, double *x, double *r, const double *p, const double *q, const double *scal,
-                  double *partials, const Exec &e);
+// or b is not finite (mirrored).  Not gated.
+void launch_pcg_start(double *scal, double rtol, int max_iterations, double *mirror, const Exec &e);
+// x += alpha p ; r -= alpha q ; q = 0 ; r.r reduced into scal by mode (4 or 5)
+void launch_pcg_xr(int64_t n, double *x, double *r, const double *p, double *q, double *scal, double *partials, int mode,
+                   double *mirror, const Exec &e);
 // p = z + beta p
 void launch_pcg_p(int64_t n, double *p, const double *z, const double *scal, const Exec &e);
-// out(T) = r(double) - Az(T) ; out may alias Az
+// out(T) = r(double) - Az(T), then Az = 0 ; out must not alias Az
 template <typename T>
-void launch_residual(int64_t n, const double *r, const T *Az, T *out, const Exec &e);
+void launch_residual(int64_t n, const double *r, T *Az, T *out, const Exec &e);
 // y(double) = a * x(T) + b * y
 template <typename T>
 void launch_axpby_to_double(int64_t n, double a, const T *x, double b, double *y, const Exec &e);
-// *active = number of problems whose scal[SC_DONE] is zero (scals: device array of count pointers).
-// Not gated.
-void launch_count_active(int count, const double *const *scals, int *active, const Exec &e);
-
 // Device scalars of one PCG.  A device-driven PCG (batched solves) keeps its stopping state
 // here: DONE is nonzero once the member stops; STATUS 1 converged, 2 non-finite residual,
 // 3 iteration cap; IT counts x updates.

@@ -421,7 +421,45 @@ __device__ __forceinline__ double block_sum(double v) {
     return s;
 }
 
-__global__ void k_dot_partial(const double *__restrict__ gate, int64_t n, const double *__restrict__ x, const double *__restrict__ y, double *partials) {
+// Scalar update of a PCG reduction s into scal (thread 0 of one workgroup).  mode: 0 plain,
+// 1 p.q -> alpha, 2 r.z -> beta (and the shift), 3 initial r.z, 4 r.r, 5 r.r after an x update
+// with the device stopping test (iteration count, DONE and STATUS); `mirror` (may be NULL)
+// receives DONE for a host that polls it.
+__device__ __forceinline__ void apply_mode(double *scal, double s, int mode, double *mirror) {
+    if (mode == 0) {
+        scal[SC_TMP] = s;
+    } else if (mode == 1) {
+        scal[SC_PQ] = s;
+        scal[SC_ALPHA] = scal[SC_RZ] / s;
+    } else if (mode == 2) {
+        scal[SC_RZNEW] = s;
+        scal[SC_BETA] = s / scal[SC_RZ];
+        scal[SC_RZ] = s;
+    } else if (mode == 3) {
+        scal[SC_RZ] = s;
+    } else if (mode == 4) {
+        scal[SC_RR] = s;
+    } else if (mode == 5) {
+        scal[SC_RR] = s;
+        const double it = scal[SC_IT] + 1.0;
+        scal[SC_IT] = it;
+        if (!(s - s == 0.0)) {  // NaN or infinite
+            scal[SC_STATUS] = 2.0;
+            scal[SC_DONE] = 1.0;
+        } else if (s <= scal[SC_RTOL2] * scal[SC_BB]) {
+            scal[SC_STATUS] = 1.0;
+            scal[SC_DONE] = 1.0;
+        } else if (it >= scal[SC_MAXIT]) {
+            scal[SC_STATUS] = 3.0;
+            scal[SC_DONE] = 1.0;
+        }
+        if (mirror) *mirror = scal[SC_DONE];
+    }
+}
+
+// Partial sums of x.y, one per workgroup.
+__global__ void k_dot_partial(const double *__restrict__ gate, int64_t n, const double *__restrict__ x,
+                              const double *__restrict__ y, double *partials) {
     if (gated(gate)) return;
     double s = 0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) s += x[i] * y[i];
@@ -429,45 +467,22 @@ __global__ void k_dot_partial(const double *__restrict__ gate, int64_t n, const 
     if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
-__global__ void k_finalize(const double *__restrict__ gate, int nb, const double *__restrict__ partials, double *scal, int mode) {
+// The partials added in index order (the same order on every run) and applied by `mode`.
+// A separate launch: a last-workgroup reduction inside the producing kernel needs a device-
+// scope release per workgroup, which writes back the L2 of its XCD each time.
+__global__ void k_finalize(const double *__restrict__ gate, int nb, const double *__restrict__ partials, double *scal,
+                           int mode, double *mirror) {
     if (gated(gate)) return;
     double s = 0;
     for (int i = threadIdx.x; i < nb; i += blockDim.x) s += partials[i];
     s = block_sum(s);
-    if (threadIdx.x == 0) {
-        if (mode == 0) {
-            scal[SC_TMP] = s;
-        } else if (mode == 1) {  // p.q -> alpha
-            scal[SC_PQ] = s;
-            scal[SC_ALPHA] = scal[SC_RZ] / s;
-        } else if (mode == 2) {  // r.z (new) -> beta, shift
-            scal[SC_RZNEW] = s;
-            scal[SC_BETA] = s / scal[SC_RZ];
-            scal[SC_RZ] = s;
-        } else if (mode == 3) {  // r.z (initial)
-            scal[SC_RZ] = s;
-        } else if (mode == 4) {  // r.r
-            scal[SC_RR] = s;
-        } else if (mode == 5) {  // r.r after an x update: count it and test for the stop
-            scal[SC_RR] = s;
-            const double it = scal[SC_IT] + 1.0;
-            scal[SC_IT] = it;
-            if (!(s - s == 0.0)) {  // NaN or infinite
-                scal[SC_STATUS] = 2.0;
-                scal[SC_DONE] = 1.0;
-            } else if (s <= scal[SC_RTOL2] * scal[SC_BB]) {
-                scal[SC_STATUS] = 1.0;
-                scal[SC_DONE] = 1.0;
-            } else if (it >= scal[SC_MAXIT]) {
-                scal[SC_STATUS] = 3.0;
-                scal[SC_DONE] = 1.0;
-            }
-        }
-    }
+    if (threadIdx.x == 0) apply_mode(scal, s, mode, mirror);
 }
 
-__global__ void k_pcg_xr(const double *__restrict__ gate, int64_t n, double *__restrict__ x, double *__restrict__ r, const double *__restrict__ p,
-                         const double *__restrict__ q, const double *__restrict__ scal, double *partials) {
+// x += alpha p, r -= alpha q, q = 0 (ready for the next operator apply), partial sums of r.r.
+__global__ void k_pcg_xr(const double *__restrict__ gate, int64_t n, double *__restrict__ x, double *__restrict__ r,
+                         const double *__restrict__ p, double *__restrict__ q, const double *__restrict__ scal,
+                         double *partials) {
     if (gated(gate)) return;
     const double alpha = scal[SC_ALPHA];
     double s = 0;
@@ -475,6 +490,7 @@ __global__ void k_pcg_xr(const double *__restrict__ gate, int64_t n, double *__r
         x[i] += alpha * p[i];
         double ri = r[i] - alpha * q[i];
         r[i] = ri;
+        q[i] = 0.0;
         s += ri * ri;
     }
     s = block_sum(s);
@@ -488,11 +504,15 @@ __global__ void k_pcg_p(const double *__restrict__ gate, int64_t n, double *__re
         p[i] = z[i] + beta * p[i];
 }
 
+// out = r - Az, then Az = 0 (ready for the next operator apply); out must not alias Az.
 template <typename T>
-__global__ void k_residual(const double *__restrict__ gate, int64_t n, const double *__restrict__ r, const T *Az, T *out) {
+__global__ void k_residual(const double *__restrict__ gate, int64_t n, const double *__restrict__ r, T *__restrict__ Az,
+                           T *__restrict__ out) {
     if (gated(gate)) return;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         out[i] = (T)r[i] - Az[i];
+        Az[i] = T(0);
+    }
 }
 
 template <typename T>
@@ -502,7 +522,7 @@ __global__ void k_axpby_to_double(const double *__restrict__ gate, int64_t n, do
         y[i] = b == 0.0 ? a * (double)x[i] : a * (double)x[i] + b * y[i];
 }
 
-__global__ void k_pcg_start(double *scal, double rtol, int max_iterations) {
+__global__ void k_pcg_start(double *scal, double rtol, int max_iterations, double *mirror) {
     if (threadIdx.x == 0) {
         const double bb = scal[SC_RR];
         scal[SC_BB] = bb;
@@ -512,23 +532,11 @@ __global__ void k_pcg_start(double *scal, double rtol, int max_iterations) {
         const bool finite = bb - bb == 0.0;
         scal[SC_STATUS] = !finite ? 2.0 : (bb == 0.0 ? 1.0 : 0.0);
         scal[SC_DONE] = (!finite || bb == 0.0) ? 1.0 : 0.0;
+        if (mirror) *mirror = scal[SC_DONE];
     }
 }
 
-__global__ void k_count_active(int count, const double *const *__restrict__ scals, int *active) {
-    int c = 0;
-    for (int i = threadIdx.x; i < count; i += blockDim.x) c += scals[i][SC_DONE] == 0.0 ? 1 : 0;
-    c = wave_sum(c);
-    __shared__ int part[16];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    if (lane == 0) part[wv] = c;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int t = 0;
-        for (int w = 0; w < nw; ++w) t += part[w];
-        *active = t;
-    }
-}
+
 
 }  // namespace
 
@@ -628,25 +636,22 @@ void launch_fill(int64_t n, T *x, T v, const Exec &e) {
     hipLaunchKernelGGL((k_fill<T>), dim3(grid_for(n)), dim3(256), 0, e.s, e.gate, n, x, v);
 }
 
-int launch_dot_partial(int64_t n, const double *x, const double *y, double *partials, const Exec &e) {
+void launch_dot(int64_t n, const double *x, const double *y, double *partials, double *scal, int mode, double *mirror,
+                const Exec &e) {
     int nb = (int)std::min<int64_t>(RED_BLOCKS, std::max<int64_t>(1, (n + 255) / 256));
     hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(256), 0, e.s, e.gate, n, x, y, partials);
-    return nb;
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, e.s, e.gate, nb, partials, scal, mode, mirror);
 }
 
-void launch_finalize(int nb, const double *partials, double *scal, int mode, const Exec &e) {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, e.s, e.gate, nb, partials, scal, mode);
+void launch_pcg_start(double *scal, double rtol, int max_iterations, double *mirror, const Exec &e) {
+    hipLaunchKernelGGL(k_pcg_start, dim3(1), dim3(64), 0, e.s, scal, rtol, max_iterations, mirror);
 }
 
-void launch_pcg_start(double *scal, double rtol, int max_iterations, const Exec &e) {
-    hipLaunchKernelGGL(k_pcg_start, dim3(1), dim3(64), 0, e.s, scal, rtol, max_iterations);
-}
-
-int launch_pcg_xr(int64_t n, double *x, double *r, const double *p, const double *q, const double *scal, double *partials,
-                  const Exec &e) {
+void launch_pcg_xr(int64_t n, double *x, double *r, const double *p, double *q, double *scal, double *partials, int mode,
+                   double *mirror, const Exec &e) {
     int nb = (int)std::min<int64_t>(RED_BLOCKS, std::max<int64_t>(1, (n + 255) / 256));
     hipLaunchKernelGGL(k_pcg_xr, dim3(nb), dim3(256), 0, e.s, e.gate, n, x, r, p, q, scal, partials);
-    return nb;
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, e.s, e.gate, nb, partials, scal, mode, mirror);
 }
 
 void launch_pcg_p(int64_t n, double *p, const double *z, const double *scal, const Exec &e) {
@@ -654,7 +659,7 @@ void launch_pcg_p(int64_t n, double *p, const double *z, const double *scal, con
 }
 
 template <typename T>
-void launch_residual(int64_t n, const double *r, const T *Az, T *out, const Exec &e) {
+void launch_residual(int64_t n, const double *r, T *Az, T *out, const Exec &e) {
     hipLaunchKernelGGL((k_residual<T>), dim3(grid_for(n)), dim3(256), 0, e.s, e.gate, n, r, Az, out);
 }
 
@@ -663,9 +668,7 @@ void launch_axpby_to_double(int64_t n, double a, const T *x, double b, double *y
     hipLaunchKernelGGL((k_axpby_to_double<T>), dim3(grid_for(n)), dim3(256), 0, e.s, e.gate, n, a, x, b, y);
 }
 
-void launch_count_active(int count, const double *const *scals, int *active, const Exec &e) {
-    hipLaunchKernelGGL(k_count_active, dim3(1), dim3(256), 0, e.s, count, scals, active);
-}
+
 
 // explicit instantiations
 #define INST(T)                                                                                          \
@@ -674,7 +677,7 @@ void launch_count_active(int count, const double *const *scals, int *active, con
     template void launch_patch_assemble<T>(const Dims &, int, const T *, T *, const Exec &);              \
     template void launch_dense_gemv<T>(int, const T *, const T *, T *, T, T, const Exec &);               \
     template void launch_fill<T>(int64_t, T *, T, const Exec &);                                          \
-    template void launch_residual<T>(int64_t, const double *, const T *, T *, const Exec &);              \
+    template void launch_residual<T>(int64_t, const double *, T *, T *, const Exec &);                    \
     template void launch_axpby_to_double<T>(int64_t, double, const T *, double, double *, const Exec &);
 INST(float)
 INST(double)
