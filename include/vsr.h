@@ -90,6 +90,11 @@ typedef struct {
                                 a hipGraph once and replays it */
     const char *tune_cache;  /* autotune: text file of tuned shapes to read and append to;
                                 NULL => in-process cache only */
+    int32_t share_factors;   /* 1: stars of the same class whose cell scalings agree to 11
+                                significant digits (e.g. every interior star of a uniform
+                                Cartesian mesh with constant kappa) are factored once and share
+                                the first one's stored factor (the others' patch matrices differ
+                                from it by ~1e-11 relative).  0: one factor per star (default). */
 } vsr_options;
 
 typedef struct {

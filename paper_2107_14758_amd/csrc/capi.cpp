@@ -75,7 +75,7 @@ struct vsr_problem {
     // relaxation data in the cycle precision
     void *mu_sur = nullptr, *lam = nullptr, *afc = nullptr, *fint = nullptr, *fbnd = nullptr;
     int n_int = 0, n_bnd = 0;
-    int *verts = nullptr, *bdesc = nullptr;
+    int *verts = nullptr, *bdesc = nullptr, *fidx = nullptr;   // fidx: factor of each interior star
     int64_t *boff = nullptr;
     PatchArgs pa{};
     int64_t factor_entries = 0;       // structurally nonzero entries over all patches
@@ -179,7 +179,7 @@ void relax_apply(vsr_problem *P, const Tin *in, T *out, T alpha, T beta) {
         e1 = P->events[P->events_used].second;
         VSR_HIP(hipEventRecord(e0, P->stream));
     }
-    launch_patch_all<T>(P->d, P->pa, P->n_int, P->verts, (const T *)P->fint, P->n_bnd, P->bdesc, P->boff,
+    launch_patch_all<T>(P->d, P->pa, P->n_int, P->verts, P->fidx, (const T *)P->fint, P->n_bnd, P->bdesc, P->boff,
                         (const T *)P->fbnd, (const T *)P->mu_sur, (const T *)P->lam, (const T *)P->afc, rF, U, P->ex());
     if (prof) {
         VSR_HIP(hipEventRecord(e1, P->stream));
@@ -475,7 +475,7 @@ void autotune(vsr_problem *P) {
     };
     auto patch = [&](auto zero) {
         using T = decltype(zero);
-        launch_patch_all<T>(P->d, P->pa, P->n_int, P->verts, (const T *)P->fint, P->n_bnd, P->bdesc, P->boff,
+        launch_patch_all<T>(P->d, P->pa, P->n_int, P->verts, P->fidx, (const T *)P->fint, P->n_bnd, P->bdesc, P->boff,
                             (const T *)P->fbnd, (const T *)P->mu_sur, (const T *)P->lam, (const T *)P->afc,
                             (const T *)P->rF, (T *)P->U, P->ex());
     };
@@ -835,10 +835,12 @@ vsr_status vsr_setup(const vsr_mesh *mesh, int32_t p, const vsr_coefficients *co
         std::vector<double> mu_sur = muo ? std::vector<double>(muo, muo + 3 * P->ncell) : g.mu;
         for (double v : mu_sur)
             if (!(v > 0)) throw Error(VSR_ENOTSPD, "surrogate scalings must be positive");
-        PatchSet S = make_patches(nx, ny, nz, P->od, mu_sur.data(), P->opt.interior_patches_only != 0);
+        PatchSet S = make_patches(nx, ny, nz, P->od, mu_sur.data(), P->opt.interior_patches_only != 0,
+                                  P->opt.share_factors != 0);
         P->n_int = (int)(S.interior_vertices.size() / 3);
         P->n_bnd = (int)S.boundary_off.size();
         P->verts = P->upload(S.interior_vertices);
+        P->fidx = P->upload(S.interior_factor_of);
         P->bdesc = P->upload(S.boundary_desc);
         P->boff = P->upload(S.boundary_off);
         const InteriorLayout &L = S.L;
@@ -858,7 +860,8 @@ vsr_status vsr_setup(const vsr_mesh *mesh, int32_t p, const vsr_coefficients *co
             for (int a = 0; a < 3; ++a) box *= S.boundary_desc[8 * i + 3 + a] == AX_FULL ? w : m;
             bnd_box += box;
         }
-        P->factor_entries = per_patch * P->n_int + bnd_nnz;
+        P->factor_entries = per_patch * S.n_interior_factors + S.boundary_entries;   // stored entries
+        (void)bnd_nnz;
         size_t esz = P->fp32 ? sizeof(float) : sizeof(double);
         // one launch solves every patch: factors read twice (forward, backward), box in and out
         P->bytes_patch_launch = (double)esz * ((double)P->n_int * (2.0 * per_patch + 2.0 * (double)w * w * w) +

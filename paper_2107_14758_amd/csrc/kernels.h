@@ -54,15 +54,9 @@ struct PatchArgs {
     int64_t off_invd, off_B1, off_B2, off_Lsep, off_P, off_Ltop, stride;
 };
 
-template <typename T>
-void launch_patch_interior(const Dims &d, const PatchArgs &a, int npatch, const int *verts, const T *factor,
-                           const T *mu, const T *lam, const T *afc, const T *rF, T *U, const Exec &e);
-template <typename T>
-void launch_patch_boundary(const Dims &d, int npatch, const int *desc, const int64_t *off, const T *factor,
-                           const T *mu, const T *lam, const T *afc, const T *rF, T *U, const Exec &e);
 // All patches in one launch (interior first, then boundary).
 template <typename T>
-void launch_patch_all(const Dims &d, const PatchArgs &a, int n_int, const int *verts, const T *fint, int n_bnd,
+void launch_patch_all(const Dims &d, const PatchArgs &a, int n_int, const int *verts, const int *fidx, const T *fint, int n_bnd,
                       const int *desc, const int64_t *off, const T *fbnd, const T *mu, const T *lam, const T *afc,
                       const T *rF, T *U, const Exec &e);
 template <typename T>

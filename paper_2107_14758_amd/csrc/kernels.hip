@@ -388,9 +388,17 @@ __global__ void k_dense_gemv(const double *__restrict__ gate, int n, const T *__
     const int row = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     if (row >= n) return;
     const T *a = A + (int64_t)row * n;
-    T s = 0;
-    for (int c = lane; c < n; c += 64) s += a[c] * x[c];
-    s = wave_sum(s);
+    // four independent partial sums per lane: four row loads in flight per step
+    T s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+    int c = lane;
+    for (; c + 192 < n; c += 256) {
+        s0 += a[c] * x[c];
+        s1 += a[c + 64] * x[c + 64];
+        s2 += a[c + 128] * x[c + 128];
+        s3 += a[c + 192] * x[c + 192];
+    }
+    for (; c < n; c += 64) s0 += a[c] * x[c];
+    T s = wave_sum((s0 + s1) + (s2 + s3));
     if (lane == 0) y[row] = beta == T(0) ? alpha * s : alpha * s + beta * y[row];
 }
 

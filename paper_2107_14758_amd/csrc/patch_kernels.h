@@ -47,6 +47,17 @@ struct PatchCtx {
             c[a] = pos[a] > M;
             l[a] = c[a] ? pos[a] - M : pos[a] + 1;
         }
+        // both cells' interior lines are loaded before any arithmetic (one round of latency)
+        T rv[2][M];
+#pragma unroll
+        for (int cd = 0; cd < 2; ++cd) {
+            int q[3] = {pos[0], pos[1], pos[2]};
+#pragma unroll
+            for (int t = 1; t <= M; ++t) {
+                q[dd] = cd == 0 ? t - 1 : M + t;
+                rv[cd][t - 1] = rF[gidx(q[0], q[1], q[2])];
+            }
+        }
         T acc = 0;
 #pragma unroll
         for (int cd = 0; cd < 2; ++cd) {
@@ -56,21 +67,19 @@ struct PatchCtx {
             for (int a = 0; a < 3; ++a)
                 if (a != dd) base += mk[a] * lam[l[a] - 1];
             const T mdd = mk[dd];
-            int q[3] = {pos[0], pos[1], pos[2]};
-            T rv[M];
 #pragma unroll
-            for (int t = 1; t <= M; ++t) {
-                q[dd] = cd == 0 ? t - 1 : M + t;
-                rv[t - 1] = rF[gidx(q[0], q[1], q[2])];
-            }
-#pragma unroll
-            for (int t = 1; t <= M; ++t) acc += mdd * afc[cd * M + t - 1] * rv[t - 1] / (base + mdd * lam[t - 1]);
+            for (int t = 1; t <= M; ++t) acc += mdd * afc[cd * M + t - 1] * rv[cd][t - 1] / (base + mdd * lam[t - 1]);
         }
         return g - acc;
     }
     // u_I = A_II^{-1}(r_I - A_IG u_G) at an interior DOF; face(a) gives the interface value
     template <typename F>
     __device__ T back_interior(const int pos[3], const bool full[3], F face) const {
+        return back_interior_r(pos, full, rF[gidx(pos[0], pos[1], pos[2])], face);
+    }
+    // the same with r_I already loaded
+    template <typename F>
+    __device__ T back_interior_r(const int pos[3], const bool full[3], T r, F face) const {
         int c[3], l[3];
         for (int a = 0; a < 3; ++a) {
             c[a] = pos[a] > M;
@@ -78,7 +87,7 @@ struct PatchCtx {
         }
         const T *mk = cmu(c);
         T D = mk[0] * lam[l[0] - 1] + mk[1] * lam[l[1] - 1] + mk[2] * lam[l[2] - 1];
-        T u = rF[gidx(pos[0], pos[1], pos[2])];
+        T u = r;
         for (int a = 0; a < 3; ++a)
             if (full[a]) u -= mk[a] * afc[c[a] * M + l[a] - 1] * face(a);
         return u / D;
@@ -260,7 +269,7 @@ __device__ __forceinline__ int64_t tile_offset(int64_t off_Ltop, int NT, int J) 
 // backward, then interior back-substitution.  Output: the patch box of (2m+1)^3 values.
 template <typename T, int P, int UNR>
 __device__ __forceinline__ void patch_interior(const int pid, Dims d, PatchArgs A, const int *__restrict__ verts,
-                                               const T *__restrict__ factor, const T *__restrict__ mu,
+                                               const int *__restrict__ fidx, const T *__restrict__ factor, const T *__restrict__ mu,
                                                const T *__restrict__ lam, const T *__restrict__ afc,
                                                const T *__restrict__ rF, T *__restrict__ U) {
     constexpr int M = P - 1, W = 2 * M + 1, NL = 4 * M * M, NS = 2 * M * W, NT = W * W, NI = NL + NS + NT;
@@ -275,7 +284,7 @@ __device__ __forceinline__ void patch_interior(const int pid, Dims d, PatchArgs 
     stage_coefficients<T, M>(d, vx, vy, vz, kfull, mu, lam, afc, smu, slam, safc);
     phase_sync();
     PatchCtx<T, M> C{d, vx, vy, vz, rF, smu, slam, safc};
-    const T *F = factor + (int64_t)pid * A.stride;
+    const T *F = factor + (int64_t)fidx[pid] * A.stride;
     T *Uo = U + ((int64_t)(vz * (d.ny + 1) + vy) * (d.nx + 1) + vx) * (int64_t)(W * W * W);
 
     // ---- condensation of the interior DOFs into the interface right-hand side
@@ -387,20 +396,33 @@ __device__ __forceinline__ void patch_interior(const int pid, Dims d, PatchArgs 
         g[i] = v * invd[i];
     }
     phase_sync();
-    // ---- interface values and interior back-substitution into the patch box
+    // ---- interface values and interior back-substitution into the patch box, eight outputs
+    // per thread at a time with their r values loaded first (one round of latency per eight)
     const bool full[3] = {true, true, true};
-    for (int idx = tid; idx < W * W * W; idx += nt) {
-        int ax = idx % W, ay = (idx / W) % W, az = idx / (W * W);
-        int ii = iface_interior(ax, ay, az, M, W, NL, NS);
-        if (ii >= 0) {
-            Uo[idx] = g[ii];
-        } else {
-            int pos[3] = {ax, ay, az};
-            Uo[idx] = C.back_interior(pos, full, [&](int a) {
-                int q[3] = {ax, ay, az};
-                q[a] = M;
-                return g[iface_interior(q[0], q[1], q[2], M, W, NL, NS)];
-            });
+    constexpr int W3 = W * W * W, OB = 8;
+    for (int base = tid; base < W3; base += nt * OB) {
+        T rv[OB];
+#pragma unroll
+        for (int u = 0; u < OB; ++u) {
+            const int idx = base + u * nt;
+            rv[u] = idx < W3 ? rF[C.gidx(idx % W, (idx / W) % W, idx / (W * W))] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < OB; ++u) {
+            const int idx = base + u * nt;
+            if (idx >= W3) break;
+            const int ax = idx % W, ay = (idx / W) % W, az = idx / (W * W);
+            const int ii = iface_interior(ax, ay, az, M, W, NL, NS);
+            if (ii >= 0) {
+                Uo[idx] = g[ii];
+            } else {
+                const int pos[3] = {ax, ay, az};
+                Uo[idx] = C.back_interior_r(pos, full, rv[u], [&](int a) {
+                    int q[3] = {ax, ay, az};
+                    q[a] = M;
+                    return g[iface_interior(q[0], q[1], q[2], M, W, NL, NS)];
+                });
+            }
         }
     }
 }
@@ -498,52 +520,33 @@ __device__ __forceinline__ void patch_boundary(const int pid, Dims d, const int 
 }
 
 
-template <typename T, int P, int UNR>
-__global__ void __launch_bounds__(256) k_patch_interior(const double *__restrict__ gate, Dims d, PatchArgs A,
-                                                        const int *__restrict__ verts, const T *__restrict__ factor,
-                                                        const T *__restrict__ mu, const T *__restrict__ lam,
-                                                        const T *__restrict__ afc, const T *__restrict__ rF,
-                                                        T *__restrict__ U) {
-    if (gated(gate)) return;
-    patch_interior<T, P, UNR>(blockIdx.x, d, A, verts, factor, mu, lam, afc, rF, U);
-}
-
-template <typename T, int P>
-__global__ void __launch_bounds__(256) k_patch_boundary(const double *__restrict__ gate, Dims d, const int *__restrict__ desc,
-                                                        const int64_t *__restrict__ off, const T *__restrict__ factor,
-                                                        const T *__restrict__ mu, const T *__restrict__ lam,
-                                                        const T *__restrict__ afc, const T *__restrict__ rF,
-                                                        T *__restrict__ U) {
-    if (gated(gate)) return;
-    patch_boundary<T, P>(blockIdx.x, d, desc, off, factor, mu, lam, afc, rF, U);
-}
-
 // Every patch of one relaxation in one launch: the interior-vertex stars first, then the
 // boundary-vertex stars, whose short solves fill the CUs that the last round of interior
 // patches leaves idle.
 template <typename T, int P, int UNR>
 __global__ void __launch_bounds__(256) k_patch_all(const double *__restrict__ gate, Dims d, PatchArgs A, int n_int,
-                                                   const int *__restrict__ verts, const T *__restrict__ fint,
+                                                   const int *__restrict__ verts, const int *__restrict__ fidx,
+                                                   const T *__restrict__ fint,
                                                    const int *__restrict__ desc, const int64_t *__restrict__ off,
                                                    const T *__restrict__ fbnd, const T *__restrict__ mu,
                                                    const T *__restrict__ lam, const T *__restrict__ afc,
                                                    const T *__restrict__ rF, T *__restrict__ U) {
     if (gated(gate)) return;
-    if ((int)blockIdx.x < n_int) patch_interior<T, P, UNR>(blockIdx.x, d, A, verts, fint, mu, lam, afc, rF, U);
+    if ((int)blockIdx.x < n_int) patch_interior<T, P, UNR>(blockIdx.x, d, A, verts, fidx, fint, mu, lam, afc, rF, U);
     else patch_boundary<T, P>(blockIdx.x - n_int, d, desc, off, fbnd, mu, lam, afc, rF, U);
 }
 
 }  // namespace
 
 template <typename T>
-void launch_patch_all(const Dims &d, const PatchArgs &a, int n_int, const int *verts, const T *fint, int n_bnd,
+void launch_patch_all(const Dims &d, const PatchArgs &a, int n_int, const int *verts, const int *fidx, const T *fint, int n_bnd,
                       const int *desc, const int64_t *off, const T *fbnd, const T *mu, const T *lam, const T *afc,
                       const T *rF, T *U, const Exec &e) {
     if (n_int + n_bnd == 0) return;
     const int unr = e.t.patch_unroll;
     if (unr != 4 && unr != 8 && unr != 16) throw Error(VSR_EINVAL, "patch_unroll must be 4, 8 or 16");
 #define CALLU(P, UU)                                                                                              \
-    hipLaunchKernelGGL((k_patch_all<T, P, UU>), dim3(n_int + n_bnd), dim3(256), 0, e.s, e.gate, d, a, n_int, verts, fint, \
+    hipLaunchKernelGGL((k_patch_all<T, P, UU>), dim3(n_int + n_bnd), dim3(256), 0, e.s, e.gate, d, a, n_int, verts, fidx, fint, \
                        desc, off, fbnd, mu, lam, afc, rF, U)
 #define CALL(P)                          \
     if (unr == 4) CALLU(P, 4);           \
@@ -554,44 +557,12 @@ void launch_patch_all(const Dims &d, const PatchArgs &a, int n_int, const int *v
 #undef CALLU
 }
 
-template <typename T>
-void launch_patch_interior(const Dims &d, const PatchArgs &a, int npatch, const int *verts, const T *factor, const T *mu,
-                           const T *lam, const T *afc, const T *rF, T *U, const Exec &e) {
-    if (npatch == 0) return;
-    const int unr = e.t.patch_unroll;
-    if (unr != 4 && unr != 8 && unr != 16) throw Error(VSR_EINVAL, "patch_unroll must be 4, 8 or 16");
-#define CALLU(P, UU) \
-    hipLaunchKernelGGL((k_patch_interior<T, P, UU>), dim3(npatch), dim3(256), 0, e.s, e.gate, d, a, verts, factor, mu, lam, \
-                       afc, rF, U)
-#define CALL(P)                          \
-    if (unr == 4) CALLU(P, 4);           \
-    else if (unr == 8) CALLU(P, 8);      \
-    else CALLU(P, 16)
-    VSR_P_SWITCH(d.p, CALL)
-#undef CALL
-#undef CALLU
-}
-
-template <typename T>
-void launch_patch_boundary(const Dims &d, int npatch, const int *desc, const int64_t *off, const T *factor, const T *mu,
-                           const T *lam, const T *afc, const T *rF, T *U, const Exec &e) {
-    if (npatch == 0) return;
-#define CALL(P)                                                                                                     \
-    hipLaunchKernelGGL((k_patch_boundary<T, P>), dim3(npatch), dim3(256), 0, e.s, e.gate, d, desc, off, factor, mu, lam, \
-                       afc, rF, U)
-    VSR_P_SWITCH(d.p, CALL)
-#undef CALL
-}
-
 }  // namespace vsr
 
 #define VSR_INSTANTIATE_PATCH(T)                                                                                     \
     namespace vsr {                                                                                                  \
-    template void launch_patch_interior<T>(const Dims &, const PatchArgs &, int, const int *, const T *, const T *,  \
-                                           const T *, const T *, const T *, T *, const Exec &);                     \
-    template void launch_patch_boundary<T>(const Dims &, int, const int *, const int64_t *, const T *, const T *,    \
-                                           const T *, const T *, const T *, T *, const Exec &);                     \
-    template void launch_patch_all<T>(const Dims &, const PatchArgs &, int, const int *, const T *, int, const int *, \
+    template void launch_patch_all<T>(const Dims &, const PatchArgs &, int, const int *, const int *, const T *, int,   \
+                                      const int *,                                                                   \
                                       const int64_t *, const T *, const T *, const T *, const T *, const T *, T *,   \
                                       const Exec &);                                                                \
     }

@@ -7,7 +7,11 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <map>
+#include <string>
+#include <vector>
 
 #include "vsr_internal.h"
 
@@ -752,7 +756,7 @@ bool factor_slices(const IfaceMap &M, std::vector<double> &S, double *out) {
 
 }  // namespace
 
-PatchSet make_patches(int nx, int ny, int nz, const OneD &od, const double *mu, bool interior_only) {
+PatchSet make_patches(int nx, int ny, int nz, const OneD &od, const double *mu, bool interior_only, bool share) {
     PatchSet P;
     int p = od.p, m = p - 1;
     P.L = interior_layout(p);
@@ -775,12 +779,8 @@ PatchSet make_patches(int nx, int ny, int nz, const OneD &od, const double *mu, 
                 int kk[3] = {kind[0], kind[1], kind[2]};
                 IfaceMap M = make_map(p, kk);
                 P.boundary_desc.insert(P.boundary_desc.end(), {vx, vy, vz, kind[0], kind[1], kind[2], M.nslices, M.ns});
-                P.boundary_off.push_back(P.boundary_entries);
-                P.boundary_entries += (int64_t)M.nslices * (M.ns * (M.ns + 1) / 2);
             }
-    int64_t ni = (int64_t)P.interior_vertices.size() / 3, nb = (int64_t)P.boundary_off.size();
-    P.interior_factor.assign((size_t)(ni * P.L.stride), 0.0);
-    P.boundary_factor.assign((size_t)std::max<int64_t>(P.boundary_entries, 1), 0.0);
+    int64_t ni = (int64_t)P.interior_vertices.size() / 3, nb = (int64_t)P.boundary_desc.size() / 8;
     auto star_of = [&](int vx, int vy, int vz, Star &st) {
         int v[3] = {vx, vy, vz};
         for (int d = 0; d < 3; ++d) st.kind[d] = kind_of(v[d], nv[d]);
@@ -792,29 +792,93 @@ PatchSet make_patches(int nx, int ny, int nz, const OneD &od, const double *mu, 
                     st.mu[cz][cy][cx] = ok ? mu + 3 * ((int64_t)ex + nx * ((int64_t)ey + ny * (int64_t)ez)) : nullptr;
                 }
     };
+    // A star's patch matrix depends only on its class and its cells' scalings.  The key of a
+    // star is its class and those scalings to 11 significant digits: the cell averages of
+    // equal cells differ in the last bits with the cell's position, so stars that agree to
+    // that precision (every interior star of a uniform Cartesian mesh with constant kappa)
+    // share the factor of the first of them.  Without sharing every star gets its own factor.
+    auto key_of = [&](const int32_t *v, const int *kind) {
+        Star st;
+        star_of(v[0], v[1], v[2], st);
+        std::string k = std::to_string(kind[0]) + "," + std::to_string(kind[1]) + "," + std::to_string(kind[2]);
+        char buf[32];
+        for (int cz = 0; cz < 2; ++cz)
+            for (int cy = 0; cy < 2; ++cy)
+                for (int cx = 0; cx < 2; ++cx)
+                    for (int c = 0; c < 3; ++c) {
+                        const double *m3 = st.mu[cz][cy][cx];
+                        std::snprintf(buf, sizeof buf, ",%.10e", m3 ? m3[c] : 0.0);
+                        k += buf;
+                    }
+        return k;
+    };
+    std::vector<int64_t> int_rep;   // a representative interior patch per factor
+    P.interior_factor_of.assign((size_t)ni, 0);
+    {
+        std::map<std::string, int32_t> seen;
+        const int kf[3] = {AX_FULL, AX_FULL, AX_FULL};
+        for (int64_t i = 0; i < ni; ++i) {
+            int32_t f = (int32_t)int_rep.size();
+            if (share) {
+                auto ins = seen.emplace(key_of(&P.interior_vertices[3 * i], kf), f);
+                f = ins.first->second;
+                if (!ins.second) {
+                    P.interior_factor_of[(size_t)i] = f;
+                    continue;
+                }
+            }
+            P.interior_factor_of[(size_t)i] = f;
+            int_rep.push_back(i);
+        }
+    }
+    P.n_interior_factors = (int64_t)int_rep.size();
+    std::vector<int64_t> bnd_rep;   // boundary patches that own their factor
+    P.boundary_off.assign((size_t)nb, 0);
+    {
+        std::map<std::string, int64_t> seen;
+        for (int64_t i = 0; i < nb; ++i) {
+            const int32_t *dsc = &P.boundary_desc[8 * i];
+            const int64_t entries = (int64_t)dsc[6] * (dsc[7] * (dsc[7] + 1) / 2);
+            if (share) {
+                const int kind[3] = {dsc[3], dsc[4], dsc[5]};
+                auto ins = seen.emplace(key_of(dsc, kind), P.boundary_entries);
+                if (!ins.second) {
+                    P.boundary_off[(size_t)i] = ins.first->second;
+                    continue;
+                }
+            }
+            P.boundary_off[(size_t)i] = P.boundary_entries;
+            P.boundary_entries += entries;
+            bnd_rep.push_back(i);
+        }
+    }
+    P.interior_factor.assign((size_t)(P.n_interior_factors * P.L.stride), 0.0);
+    P.boundary_factor.assign((size_t)std::max<int64_t>(P.boundary_entries, 1), 0.0);
     int failed = 0;
     int kfull[3] = {AX_FULL, AX_FULL, AX_FULL};
     IfaceMap Mi = make_map(p, kfull);
+    const int64_t nfi = P.n_interior_factors, nfb = (int64_t)bnd_rep.size();
 #pragma omp parallel
     {
         std::vector<double> S;
 #pragma omp for schedule(dynamic, 1) reduction(+ : failed)
-        for (int64_t i = 0; i < ni; ++i) {
+        for (int64_t f = 0; f < nfi; ++f) {
             Star st;
-            const int32_t *v = &P.interior_vertices[3 * i];
+            const int32_t *v = &P.interior_vertices[3 * int_rep[(size_t)f]];
             star_of(v[0], v[1], v[2], st);
             assemble_schur(od, st, Mi, S);
-            if (!factor_interior(P.L, S, &P.interior_factor[(size_t)(i * P.L.stride)], i == 0)) failed += 1;
+            if (!factor_interior(P.L, S, &P.interior_factor[(size_t)(f * P.L.stride)], f == 0)) failed += 1;
         }
 #pragma omp for schedule(dynamic, 4) reduction(+ : failed)
-        for (int64_t i = 0; i < nb; ++i) {
+        for (int64_t r = 0; r < nfb; ++r) {
+            const int64_t i = bnd_rep[(size_t)r];
             const int32_t *dsc = &P.boundary_desc[8 * i];
             Star st;
             star_of(dsc[0], dsc[1], dsc[2], st);
             if (dsc[6] == 0) continue;
             IfaceMap M = make_map(p, st.kind);
             assemble_schur(od, st, M, S);
-            if (!factor_slices(M, S, &P.boundary_factor[(size_t)P.boundary_off[i]])) failed += 1;
+            if (!factor_slices(M, S, &P.boundary_factor[(size_t)P.boundary_off[(size_t)i]])) failed += 1;
         }
     }
     if (failed) throw Error(VSR_ENOTSPD, "patch Cholesky failed on " + std::to_string(failed) + " patches");

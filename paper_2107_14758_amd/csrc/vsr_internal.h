@@ -70,15 +70,19 @@ struct PatchSet {
     // interior class
     InteriorLayout L;
     std::vector<int32_t> interior_vertices;   // 3 ints per patch (vx, vy, vz)
+    std::vector<int32_t> interior_factor_of;  // per interior patch: index of its factor
+    int64_t n_interior_factors = 0;
     // boundary classes: per patch vx,vy,vz, kind(x,y,z), nslices, slice size, factor offset
     std::vector<int32_t> boundary_desc;       // 8 ints per patch
     std::vector<int64_t> boundary_off;        // factor offset per boundary patch
     int64_t boundary_entries = 0;
     // factors (FP64 on the host; converted to the device precision on upload)
-    std::vector<double> interior_factor;      // n_interior * L.stride
+    std::vector<double> interior_factor;      // n_interior_factors * L.stride
     std::vector<double> boundary_factor;
 };
-PatchSet make_patches(int nx, int ny, int nz, const OneD &od, const double *mu, bool interior_only);
+// share: stars with the same class and bit-identical cell scalings (every interior star of a
+// uniform Cartesian mesh with constant kappa) are factored once and share the factor.
+PatchSet make_patches(int nx, int ny, int nz, const OneD &od, const double *mu, bool interior_only, bool share = false);
 
 // ------------------------------------------------------------------ coarse space
 // Dense inverse of the Q1 Galerkin matrix over interior vertices (row-major, nc x nc).

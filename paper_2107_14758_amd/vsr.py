@@ -37,7 +37,8 @@ class Options(ctypes.Structure):
                 ("lanczos_steps", ctypes.c_int32), ("max_iterations", ctypes.c_int32),
                 ("interior_patches_only", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("omega", ctypes.c_double), ("stream", ctypes.c_void_p), ("autotune", ctypes.c_int32),
-                ("batch_streams", ctypes.c_int32), ("batch_eager", ctypes.c_int32), ("tune_cache", ctypes.c_char_p)]
+                ("batch_streams", ctypes.c_int32), ("batch_eager", ctypes.c_int32), ("tune_cache", ctypes.c_char_p),
+                ("share_factors", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -133,7 +134,8 @@ class _Inputs:
 
 
 def make_options(relax_fp32=False, cycle=0, lanczos_steps=20, max_iterations=1000, interior_patches_only=False, seed=0,
-                 omega=0.0, stream=None, autotune=False, batch_streams=0, batch_eager=False, tune_cache=None):
+                 omega=0.0, stream=None, autotune=False, batch_streams=0, batch_eager=False, tune_cache=None,
+                 share_factors=False):
     opt = Options()
     lib().vsr_default_options(ctypes.byref(opt))
     opt.relax_fp32 = int(bool(relax_fp32))
@@ -148,6 +150,7 @@ def make_options(relax_fp32=False, cycle=0, lanczos_steps=20, max_iterations=100
     opt.batch_streams = int(batch_streams)
     opt.batch_eager = int(bool(batch_eager))
     opt.tune_cache = None if tune_cache is None else os.fsencode(tune_cache)
+    opt.share_factors = int(bool(share_factors))
     return opt
 
 

@@ -65,6 +65,7 @@ def test_batch_and_tuning_argument_checks_without_gpu_work():
     # the options record keeps the C layout: the new fields follow the stream pointer
     assert vsr.Options.autotune.offset == vsr.Options.stream.offset + 8
     assert vsr.Options.tune_cache.offset == vsr.Options.autotune.offset + 16
+    assert vsr.Options.share_factors.offset == vsr.Options.tune_cache.offset + 8 and opt.share_factors == 0
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libvsr.so not built")

@@ -199,3 +199,32 @@ def test_single_solve_graph_and_host_driven_agree(vsr, relax_fp32):
     assert info_again["iterations"] == info_g["iterations"] or relax_fp32
     assert rel(x_again, 2.0 * x_graph) < tol
     prob.close()
+
+
+@pytest.mark.parametrize("relax_fp32", [False, True])
+def test_shared_factors_give_the_same_solve(vsr, relax_fp32):
+    """With share_factors every interior star of a uniform Cartesian mesh with constant kappa
+    uses one stored factor (and the boundary classes one each); the solve is unchanged."""
+    say(f"case shared factors fp32={relax_fp32}")
+    d, f = member_problem((4, 4, 4), 5, 0.0, False, seed=70)
+    own = vsr.Problem(d["vertices"], 5, relax_fp32=relax_fp32, seed=0)
+    shared = vsr.Problem(d["vertices"], 5, relax_fp32=relax_fp32, seed=0, share_factors=True)
+    npatch, entries_own = own.factor_info()
+    npatch2, entries_shared = shared.factor_info()
+    say(f"  {npatch} patches, stored factor entries {entries_own} -> {entries_shared}")
+    assert npatch == npatch2 and entries_shared < entries_own / 10
+    # the shared factor equals each star's own up to rounding of the cell scalings
+    assert abs(own.damping()[0] / shared.damping()[0] - 1) < 1e-9
+    b = rhs(own, f)
+    x1, x2 = torch.zeros_like(b), torch.zeros_like(b)
+    i1, i2 = own.pcg_solve(b, x1), shared.pcg_solve(b, x2)
+    tol = 1e-6 if relax_fp32 else 1e-10
+    assert abs(i1["iterations"] - i2["iterations"]) <= (1 if relax_fp32 else 0)
+    assert rel(x2, x1) < tol
+    # a jittered mesh has no two identical stars
+    dj, _ = member_problem((3, 3, 3), 4, 0.15, True, seed=71)
+    pj = vsr.Problem(dj["vertices"], 4, kappa=dj["kappa"], seed=0, share_factors=True)
+    pj_own = vsr.Problem(dj["vertices"], 4, kappa=dj["kappa"], seed=0)
+    assert pj.factor_info() == pj_own.factor_info()
+    for q in (own, shared, pj, pj_own):
+        q.close()

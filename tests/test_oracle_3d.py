@@ -286,3 +286,17 @@ def test_iterations_nearly_flat_in_p():
         _, it = Solver(d, setup_1d(p)).pcg(d.load_vector(w["f"]))
         its.append(it)
     assert max(its) - min(its) <= 2, its
+
+
+def test_batch_workload_is_seeded_and_uneven():
+    from paper_2107_14758_amd import inputs
+    a = inputs.batch_workload(8, seed=3)
+    b = inputs.batch_workload(8, seed=3)
+    assert [(w["n"], w["p"], w["jitter"]) for w in a] == [(w["n"], w["p"], w["jitter"]) for w in b]
+    assert all(np.array_equal(x["f"], y["f"]) and np.array_equal(x["vertices"], y["vertices"]) for x, y in zip(a, b))
+    full = inputs.batch_workload(64, seed=0)
+    assert {w["n"] for w in full} == {4, 6, 8, 12} and {w["p"] for w in full} == {4, 7, 11, 15}
+    assert 0 < sum(w["jitter"] > 0 for w in full) < 64
+    for w in full[:4]:
+        q = inputs.quadrature_points_per_dir(w["p"])
+        assert w["f"].shape == (w["n"] ** 3, q ** 3) and np.abs(w["f"]).max() <= 1.0
