@@ -99,7 +99,7 @@ def solve_timed(vsr, torch, w, relax_fp32, steps, warmup, profile, autotune=Fals
     return out
 
 
-def batch_timed(vsr, torch, W, steps, warmup):
+def batch_timed(vsr, torch, W, steps, warmup, share_factors=False):
     """Batched solve of the members of W (FP32 relaxation, autotuned shapes): seconds per
     batch solve, and per member the iterations; then the members solved one after another."""
     t0 = time.perf_counter()
@@ -108,7 +108,7 @@ def batch_timed(vsr, torch, W, steps, warmup):
             f"{time.perf_counter() - t0:.1f} s")
 
     B = vsr.Batch([dict(vertices=w["vertices"], p=w["p"], kappa=w["kappa"]) for w in W], progress=progress,
-                  relax_fp32=True, seed=0, autotune=True)
+                  relax_fp32=True, seed=0, autotune=True, share_factors=share_factors)
     setup_s = time.perf_counter() - t0
     log(f"[bench] batch setup {setup_s:.1f} s")
     bs, xs = [], []
@@ -184,6 +184,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--workload", default=WORKLOAD, choices=sorted(list(WORKLOADS) + ["batch64"]))
     ap.add_argument("--autotune", action="store_true", help="single-problem workloads: autotune launch shapes")
+    ap.add_argument("--share-factors", action="store_true",
+                    help="batch64: stars with equal scalings share one stored factor")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (HBM counter calibration)")
     args = ap.parse_args()
@@ -272,7 +274,7 @@ def main_batch(args, torch, inputs, vsr):
     n_total = sum((int(w["p"]) * int(w["n"]) - 1) ** 3 for w in W)
     log(f"[bench] batch of {len(W)} problems, {n_total} DOFs in total")
     steps, warmup = max(1, min(args.steps, 5)), max(1, min(args.warmup, 1))
-    r = batch_timed(vsr, torch, W, steps, warmup)
+    r = batch_timed(vsr, torch, W, steps, warmup, share_factors=args.share_factors)
     infos = r["infos"]
     big = r["big"]
     out = {
@@ -284,6 +286,7 @@ def main_batch(args, torch, inputs, vsr):
         "config": {"workload": "batch64_uneven_p4-15", "problems": len(W), "dofs": n_total, "rtol": 1e-8,
                    "cells_per_axis": sorted(set(int(w["n"]) for w in W)), "degrees": sorted(set(int(w["p"]) for w in W)),
                    "launch": "lockstep iteration replayed from one hipGraph over 4 streams",
+                   "share_factors": bool(args.share_factors),
                    "autotuned_shapes": {str(k): list(v) for k, v in sorted(r["shapes"].items())},
                    "parallelism": "single GPU"},
         "iterations_min_max": [min(i["iterations"] for i in infos), max(i["iterations"] for i in infos)],
