@@ -89,14 +89,32 @@ __global__ void __launch_bounds__(256) k_op_kron(const double *__restrict__ gate
 // fits without spills); their partial outputs meet in the atomic additions into y.
 constexpr int opg_rows(int P, int S) { return (QOF(P) + S - 1) / S; }
 constexpr int opg_threads(int P, int S) { return (opg_rows(P, S) * QOF(P) + 63) / 64 * 64; }
+// z-slabs per chunk: as many as fit in about 60 KB of LDS in either chunked phase
+constexpr int opg_chunk(int P, int S, int bytes) {
+    const int N1 = P + 1, Q = QOF(P), BR = opg_rows(P, S);
+    const int fwd = N1 * N1 + 2 * N1 * Q, bwd = 3 * BR * Q + 2 * N1 * Q;
+    const int per = (fwd > bwd ? fwd : bwd) * bytes;
+    const int kc = (60 * 1024 - 2 * Q * N1 * bytes) / per;
+    return kc < 1 ? 1 : (kc > N1 ? N1 : kc);
+}
 
+// General trilinear cell: y_K = (grad phi)^T Gw (grad phi) x_K with the q^3 GLL rule
+// (Sec. 2.1, 2.7).  Thread (b, a) owns one z-column of quadrature points.  The x and y
+// contractions run through LDS for a chunk of KC z-slabs at a time (three barriers per chunk
+// and direction); the z contraction, the metric and the z back-contraction stay in the
+// column's registers.  S workgroups share a cell, each owning a band of ceil(Q/S) b-rows of
+// columns (with S = 2 the FP64 column state of p = 14, 15 fits without spills); their
+// partial outputs meet in the atomic additions into y.
 template <typename T, int P, int S>
 __global__ void __launch_bounds__(opg_threads(P, S)) k_op_general(const double *__restrict__ gate, Dims d,
                                                                    const T *__restrict__ IDq, const T *__restrict__ Gw,
                                                                    const T *__restrict__ x, T *__restrict__ y) {
     if (gated(gate)) return;
     constexpr int N1 = P + 1, Q = QOF(P), Q2 = Q * Q, Q3 = Q2 * Q, BR = opg_rows(P, S);
-    __shared__ T sI[Q * N1], sD[Q * N1], xs[N1 * N1], X1[N1 * Q], DX1[N1 * Q], S0[BR * Q], S1[BR * Q], S2[BR * Q];
+    constexpr int KC = opg_chunk(P, S, (int)sizeof(T)), NCH = (N1 + KC - 1) / KC;
+    constexpr int FWD = N1 * N1 + 2 * N1 * Q, BWD = 3 * BR * Q + 2 * N1 * Q;
+    __shared__ T sI[Q * N1], sD[Q * N1];
+    __shared__ T buf[KC * (FWD > BWD ? FWD : BWD)];
     const int tid = threadIdx.x, nt = blockDim.x;
     for (int t = tid; t < Q * N1; t += nt) {
         sI[t] = IDq[t];
@@ -108,40 +126,51 @@ __global__ void __launch_bounds__(opg_threads(P, S)) k_op_general(const double *
     const bool col = tid < nb * Q;
     const int b = b0 + tid / Q, a = tid % Q;
     T AA[N1], AB[N1], BA[N1];
+    // ---- forward: x and y contractions, KC slabs at a time
+    T *xs = buf, *X1 = buf + KC * N1 * N1, *DX1 = X1 + KC * N1 * Q;
 #pragma unroll
-    for (int k = 0; k < N1; ++k) {
+    for (int c = 0; c < NCH; ++c) {
+        const int k0 = c * KC, kn = min(KC, N1 - k0);
         __syncthreads();
-        for (int t = tid; t < N1 * N1; t += nt) {
-            int jj = t / N1, ii = t % N1;
-            int K = P * ez + k, J = P * ey + jj, I = P * ex + ii;
+        for (int t = tid; t < kn * N1 * N1; t += nt) {
+            const int kk = t / (N1 * N1), jj = (t / N1) % N1, ii = t % N1;
+            const int K = P * ez + k0 + kk, J = P * ey + jj, I = P * ex + ii;
             xs[t] = is_free(d, K, J, I) ? x[free_index(d, K, J, I)] : T(0);
         }
         __syncthreads();
-        for (int t = tid; t < N1 * Q; t += nt) {
-            int jj = t / Q, aa = t % Q;
+        for (int t = tid; t < kn * N1 * Q; t += nt) {
+            const int kj = t / Q, aa = t % Q;   // kj = kk N1 + jj
             T s0 = 0, s1 = 0;
 #pragma unroll
             for (int ii = 0; ii < N1; ++ii) {
-                s0 += sI[aa * N1 + ii] * xs[jj * N1 + ii];
-                s1 += sD[aa * N1 + ii] * xs[jj * N1 + ii];
+                s0 += sI[aa * N1 + ii] * xs[kj * N1 + ii];
+                s1 += sD[aa * N1 + ii] * xs[kj * N1 + ii];
             }
             X1[t] = s0;
             DX1[t] = s1;
         }
         __syncthreads();
         if (col) {
-            T s0 = 0, s1 = 0, s2 = 0;
 #pragma unroll
-            for (int jj = 0; jj < N1; ++jj) {
-                s0 += sI[b * N1 + jj] * X1[jj * Q + a];
-                s1 += sD[b * N1 + jj] * X1[jj * Q + a];
-                s2 += sI[b * N1 + jj] * DX1[jj * Q + a];
+            for (int kk = 0; kk < KC; ++kk) {
+                const int k = k0 + kk;
+                if (k < N1) {
+                    T s0 = 0, s1 = 0, s2 = 0;
+#pragma unroll
+                    for (int jj = 0; jj < N1; ++jj) {
+                        const T xv = X1[(kk * N1 + jj) * Q + a], dv = DX1[(kk * N1 + jj) * Q + a];
+                        s0 += sI[b * N1 + jj] * xv;
+                        s1 += sD[b * N1 + jj] * xv;
+                        s2 += sI[b * N1 + jj] * dv;
+                    }
+                    AA[k] = s0;
+                    AB[k] = s1;
+                    BA[k] = s2;
+                }
             }
-            AA[k] = s0;
-            AB[k] = s1;
-            BA[k] = s2;
         }
     }
+    // ---- quadrature columns: z contraction, metric, z back-contraction
     T AAo[N1], ABo[N1], BAo[N1];
 #pragma unroll
     for (int k = 0; k < N1; ++k) AAo[k] = ABo[k] = BAo[k] = 0;
@@ -169,31 +198,42 @@ __global__ void __launch_bounds__(opg_threads(P, S)) k_op_general(const double *
             }
         }
     }
+    // ---- backward: y and x back-contractions, KC slabs at a time
+    T *S0 = buf, *S1 = S0 + KC * BR * Q, *S2 = S1 + KC * BR * Q, *Y1 = S2 + KC * BR * Q, *DY1 = Y1 + KC * N1 * Q;
 #pragma unroll
-    for (int k = 0; k < N1; ++k) {
+    for (int c = 0; c < NCH; ++c) {
+        const int k0 = c * KC, kn = min(KC, N1 - k0);
         __syncthreads();
         if (col) {
-            S0[tid] = AAo[k];
-            S1[tid] = ABo[k];
-            S2[tid] = BAo[k];
+#pragma unroll
+            for (int kk = 0; kk < KC; ++kk) {
+                const int k = k0 + kk;
+                if (k < N1) {
+                    S0[kk * BR * Q + tid] = AAo[k];
+                    S1[kk * BR * Q + tid] = ABo[k];
+                    S2[kk * BR * Q + tid] = BAo[k];
+                }
+            }
         }
         __syncthreads();
-        for (int t = tid; t < N1 * Q; t += nt) {
-            int jj = t / Q, aa = t % Q;
+        for (int t = tid; t < kn * N1 * Q; t += nt) {
+            const int kk = t / (N1 * Q), jj = (t / Q) % N1, aa = t % Q;
+            const T *s0p = S0 + kk * BR * Q, *s1p = S1 + kk * BR * Q, *s2p = S2 + kk * BR * Q;
             T s0 = 0, s1 = 0;
             for (int bb = 0; bb < nb; ++bb) {
-                s0 += sI[(b0 + bb) * N1 + jj] * S0[bb * Q + aa] + sD[(b0 + bb) * N1 + jj] * S1[bb * Q + aa];
-                s1 += sI[(b0 + bb) * N1 + jj] * S2[bb * Q + aa];
+                s0 += sI[(b0 + bb) * N1 + jj] * s0p[bb * Q + aa] + sD[(b0 + bb) * N1 + jj] * s1p[bb * Q + aa];
+                s1 += sI[(b0 + bb) * N1 + jj] * s2p[bb * Q + aa];
             }
-            X1[t] = s0;
-            DX1[t] = s1;
+            Y1[t] = s0;
+            DY1[t] = s1;
         }
         __syncthreads();
-        for (int t = tid; t < N1 * N1; t += nt) {
-            int jj = t / N1, ii = t % N1;
+        for (int t = tid; t < kn * N1 * N1; t += nt) {
+            const int kk = t / (N1 * N1), jj = (t / N1) % N1, ii = t % N1;
+            const T *y1 = Y1 + (kk * N1 + jj) * Q, *dy1 = DY1 + (kk * N1 + jj) * Q;
             T s = 0;
-            for (int aa = 0; aa < Q; ++aa) s += sI[aa * N1 + ii] * X1[jj * Q + aa] + sD[aa * N1 + ii] * DX1[jj * Q + aa];
-            int K = P * ez + k, J = P * ey + jj, I = P * ex + ii;
+            for (int aa = 0; aa < Q; ++aa) s += sI[aa * N1 + ii] * y1[aa] + sD[aa * N1 + ii] * dy1[aa];
+            const int K = P * ez + k0 + kk, J = P * ey + jj, I = P * ex + ii;
             if (is_free(d, K, J, I)) atomic_add_global(&y[free_index(d, K, J, I)], s);
         }
     }

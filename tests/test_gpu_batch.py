@@ -214,7 +214,7 @@ def test_shared_factors_give_the_same_solve(vsr, relax_fp32):
     say(f"  {npatch} patches, stored factor entries {entries_own} -> {entries_shared}")
     assert npatch == npatch2 and entries_shared < entries_own / 10
     # the shared factor equals each star's own up to rounding of the cell scalings
-    assert abs(own.damping()[0] / shared.damping()[0] - 1) < 1e-9
+    assert abs(own.damping()[0] / shared.damping()[0] - 1) < (1e-5 if relax_fp32 else 1e-9)
     b = rhs(own, f)
     x1, x2 = torch.zeros_like(b), torch.zeros_like(b)
     i1, i2 = own.pcg_solve(b, x1), shared.pcg_solve(b, x2)
