@@ -212,3 +212,23 @@ def test_error_paths(vsr):
     zero = torch.zeros_like(b)
     info = prob.pcg_solve(zero, x)
     assert info["iterations"] == 0 and float(x.abs().max()) == 0.0
+
+
+def test_gpu_iterations_nearly_flat_in_p(vsr):
+    """p-robustness (Sec. 4): on a fixed Cartesian mesh the PCG iteration count of the full
+    two-level method barely moves with the degree."""
+    print("case iterations vs p", flush=True)
+    its = {}
+    for p in (3, 5, 7, 9, 11):
+        w = inputs.make_problem(4, p, seed=5)
+        prob = vsr.Problem(w["vertices"], p, seed=0, relax_fp32=True)
+        f = torch.tensor(w["f"], dtype=torch.float64, device="cuda")
+        b = torch.zeros(prob.n, dtype=torch.float64, device="cuda")
+        prob.load_vector(f, b)
+        x = torch.zeros_like(b)
+        info = prob.pcg_solve(b, x)
+        assert info["converged"] == 1 and info["true_rel_residual"] <= 1.0001e-8
+        its[p] = info["iterations"]
+        prob.close()
+    print("  iterations", its, flush=True)
+    assert max(its.values()) - min(its.values()) <= 3 and max(its.values()) <= 16
