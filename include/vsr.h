@@ -208,18 +208,18 @@ vsr_status vsr_mlp_train(float *params_dev, float *adam_m_dev, float *adam_v_dev
 vsr_status vsr_surrogate_scalings(int64_t ncell, const double *corners, const double *kappa, int32_t p,
                                   const float *params_dev, int32_t bf16, double *mu_out, int32_t *learned);
 
-/* Launch shapes in use: shapes[0..6] = Cartesian-operator cells per workgroup (FP64,
+/* Launch shapes in use: shapes[0..7] = Cartesian-operator cells per workgroup (FP64,
  * FP32), lattice-pass block size, patch-panel unroll, general-operator workgroups per
  * cell (FP64, FP32; 0 = chosen by size: 2 where one workgroup's FP64 column state would
  * not fit in registers, else 1), lattice passes with whole lines staged in LDS (1) or
- * streamed through the caches (0). */
-vsr_status vsr_get_tuning(const vsr_problem *prob, int32_t shapes[7]);
+ * streamed through the caches (0), threads per patch workgroup. */
+vsr_status vsr_get_tuning(const vsr_problem *prob, int32_t shapes[8]);
 
 /* Set the launch shapes (same order; cells per workgroup in {1, 2, 4}, used only for
  * Cartesian meshes with p <= 7; block a multiple of 64 in [64, 1024]; unroll in
- * {4, 8, 16}; workgroups per cell in {0, 1, 2}; staged passes 0 or 1).  VSR_EINVAL for any
- * other value. */
-vsr_status vsr_set_tuning(vsr_problem *prob, const int32_t shapes[7]);
+ * {4, 8, 16}; workgroups per cell in {0, 1, 2}; staged passes 0 or 1; patch threads 256 or
+ * 512).  VSR_EINVAL for any other value. */
+vsr_status vsr_set_tuning(vsr_problem *prob, const int32_t shapes[8]);
 
 void vsr_destroy(vsr_problem *prob);
 

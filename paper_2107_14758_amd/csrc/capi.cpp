@@ -373,9 +373,10 @@ bool tune_from_file(const char *path, const std::string &key, Tuning &t) {
         if (line.compare(0, key.size(), key) != 0 || line.size() <= key.size() || line[key.size()] != ' ') continue;
         Tuning c;
         if (std::sscanf(line.c_str() + key.size(),
-                        " cpw64=%d cpw32=%d axis_block=%d patch_unroll=%d split64=%d split32=%d axis_tiled=%d",
+                        " cpw64=%d cpw32=%d axis_block=%d patch_unroll=%d split64=%d split32=%d axis_tiled=%d"
+                        " patch_threads=%d",
                         &c.op_cpw64, &c.op_cpw32, &c.axis_block, &c.patch_unroll, &c.opg_split64, &c.opg_split32,
-                        &c.axis_tiled) == 7) {
+                        &c.axis_tiled, &c.patch_threads) == 8) {
             t = c;
             found = true;
         }
@@ -473,6 +474,22 @@ void autotune(vsr_problem *P) {
             }
         P->tune = keep;
     };
+    // patch solves: loads in flight per thread jointly with the workgroup size
+    auto pick_patch = [&](auto &&fn) {
+        double best = 1e300;
+        Tuning keep = P->tune;
+        for (int nth : {256, 512})
+            for (int u : {4, 8, 16}) {
+                P->tune.patch_threads = nth;
+                P->tune.patch_unroll = u;
+                double ms = time_ms(P, fn);
+                if (ms < best) {
+                    best = ms;
+                    keep = P->tune;
+                }
+            }
+        P->tune = keep;
+    };
     auto patch = [&](auto zero) {
         using T = decltype(zero);
         launch_patch_all<T>(P->d, P->pa, P->n_int, P->verts, P->fidx, (const T *)P->fint, P->n_bnd, P->bdesc, P->boff,
@@ -483,12 +500,12 @@ void autotune(vsr_problem *P) {
         launch_fill<float>(P->n, (float *)P->t1, 1.f, P->ex());
         launch_fill<float>(P->n, (float *)P->rF, 1.f, P->ex());
         pick_passes([&] { passes(0.f); });
-        if (P->n_int + P->n_bnd > 0) pick(P->tune.patch_unroll, {4, 8, 16}, [&] { patch(0.f); });
+        if (P->n_int + P->n_bnd > 0) pick_patch([&] { patch(0.f); });
     } else {
         launch_fill<double>(P->n, (double *)P->t1, 1.0, P->ex());
         launch_fill<double>(P->n, (double *)P->rF, 1.0, P->ex());
         pick_passes([&] { passes(0.0); });
-        if (P->n_int + P->n_bnd > 0) pick(P->tune.patch_unroll, {4, 8, 16}, [&] { patch(0.0); });
+        if (P->n_int + P->n_bnd > 0) pick_patch([&] { patch(0.0); });
     }
     // the patch boxes of absent stars must read as zero in the assembly
     const int64_t w3 = (int64_t)P->pa.w * P->pa.w * P->pa.w, nv = (int64_t)(P->d.nx + 1) * (P->d.ny + 1) * (P->d.nz + 1);
@@ -504,7 +521,8 @@ void autotune(vsr_problem *P) {
         std::ofstream f(P->opt.tune_cache, std::ios::app);
         f << key << " cpw64=" << P->tune.op_cpw64 << " cpw32=" << P->tune.op_cpw32 << " axis_block=" << P->tune.axis_block
           << " patch_unroll=" << P->tune.patch_unroll << " split64=" << P->tune.opg_split64
-          << " split32=" << P->tune.opg_split32 << " axis_tiled=" << P->tune.axis_tiled << "\n";
+          << " split32=" << P->tune.opg_split32 << " axis_tiled=" << P->tune.axis_tiled
+          << " patch_threads=" << P->tune.patch_threads << "\n";
     }
 }
 
@@ -1052,7 +1070,7 @@ vsr_status vsr_factor_info(const vsr_problem *P, int64_t *num_patches, int64_t *
 
 void vsr_destroy(vsr_problem *P) { destroy_problem(P); }
 
-vsr_status vsr_get_tuning(const vsr_problem *P, int32_t shapes[7]) {
+vsr_status vsr_get_tuning(const vsr_problem *P, int32_t shapes[8]) {
     return guarded([&] {
         if (!P || !shapes) throw Error(VSR_EINVAL, "NULL argument");
         shapes[0] = P->tune.op_cpw64;
@@ -1062,10 +1080,11 @@ vsr_status vsr_get_tuning(const vsr_problem *P, int32_t shapes[7]) {
         shapes[4] = P->tune.opg_split64;
         shapes[5] = P->tune.opg_split32;
         shapes[6] = P->tune.axis_tiled;
+        shapes[7] = P->tune.patch_threads;
     });
 }
 
-vsr_status vsr_set_tuning(vsr_problem *P, const int32_t shapes[7]) {
+vsr_status vsr_set_tuning(vsr_problem *P, const int32_t shapes[8]) {
     return guarded([&] {
         if (!P || !shapes) throw Error(VSR_EINVAL, "NULL argument");
         auto cpw_ok = [](int c) { return c == 1 || c == 2 || c == 4; };
@@ -1075,8 +1094,9 @@ vsr_status vsr_set_tuning(vsr_problem *P, const int32_t shapes[7]) {
         for (int i = 4; i < 6; ++i)
             if (shapes[i] < 0 || shapes[i] > 2) throw Error(VSR_EINVAL, "workgroups per cell must be 0, 1 or 2");
         if (shapes[6] != 0 && shapes[6] != 1) throw Error(VSR_EINVAL, "tiled lattice passes must be 0 or 1");
+        if (shapes[7] != 256 && shapes[7] != 512) throw Error(VSR_EINVAL, "patch threads must be 256 or 512");
         VSR_HIP(hipStreamSynchronize(P->stream));
-        P->tune = Tuning{shapes[0], shapes[1], shapes[2], shapes[3], shapes[4], shapes[5], shapes[6]};
+        P->tune = Tuning{shapes[0], shapes[1], shapes[2], shapes[3], shapes[4], shapes[5], shapes[6], shapes[7]};
         delete P->self;   // its recorded iteration holds the old shapes
         P->self = nullptr;
     });

@@ -23,6 +23,7 @@ struct Tuning {
     int opg_split64 = 0;    // workgroups per cell of the general operator, FP64 (1, 2; 0: by size)
     int opg_split32 = 0;    // same, FP32
     int axis_tiled = 0;     // lattice passes with whole lines staged in LDS (1) or streamed (0)
+    int patch_threads = 256;   // threads per patch workgroup (256 or 512: more panel loads in flight)
 };
 
 // Where a launch goes: its stream, an optional gate (a device flag; when it is nonzero

@@ -252,6 +252,18 @@ __device__ __forceinline__ void phase_sync() {
     __builtin_amdgcn_sched_barrier(0);
 }
 
+// Sum of the wavefronts' 64-row partials (pairwise for 4 and 8 wavefronts).
+template <typename T>
+__device__ __forceinline__ T sum_waves(const T *red, int nw, int lane) {
+    if (nw == 4) return (red[lane] + red[64 + lane]) + (red[128 + lane] + red[192 + lane]);
+    if (nw == 8)
+        return ((red[lane] + red[64 + lane]) + (red[128 + lane] + red[192 + lane])) +
+               ((red[256 + lane] + red[320 + lane]) + (red[384 + lane] + red[448 + lane]));
+    T s = 0;
+    for (int w = 0; w < nw; ++w) s += red[64 * w + lane];
+    return s;
+}
+
 // Offset of top-plane tile J inside one interior-patch factor (diagonal 64x64 block, then
 // the panel of rows below it padded to a multiple of 4).
 __device__ __forceinline__ int64_t tile_offset(int64_t off_Ltop, int NT, int J) {
@@ -277,7 +289,7 @@ __device__ __forceinline__ void patch_interior(const int pid, Dims d, PatchArgs 
     __shared__ T g[NI];
     __shared__ T smu[24], slam[M], safc[2 * M];
     __shared__ T tl[64 * 65 / 2];
-    __shared__ T red[256];
+    __shared__ T red[512];   // one 64-row partial per wavefront (at most 8)
     const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
     const int kfull[3] = {AX_FULL, AX_FULL, AX_FULL};
     const int vx = verts[3 * pid], vy = verts[3 * pid + 1], vz = verts[3 * pid + 2];
@@ -336,13 +348,13 @@ __device__ __forceinline__ void patch_interior(const int pid, Dims d, PatchArgs 
     // offset k (129 - k) / 2); 9 independent loads per thread
     auto stage_tile = [&](int J) {
         const T *D = F + tile_offset(A.off_Ltop, NT, J);
-        constexpr int NP = 64 * 65 / 2, R = (NP + 255) / 256;
+        constexpr int NP = 64 * 65 / 2, R = (NP + 255) / 256;   // loads per thread with 256 threads
         T v[R];
 #pragma unroll
-        for (int u = 0; u < R; ++u) v[u] = tid + 256 * u < NP ? D[tid + 256 * u] : T(0);
+        for (int u = 0; u < R; ++u) v[u] = tid + nt * u < NP ? D[tid + nt * u] : T(0);
 #pragma unroll
         for (int u = 0; u < R; ++u)
-            if (tid + 256 * u < NP) tl[tid + 256 * u] = v[u];
+            if (tid + nt * u < NP) tl[tid + nt * u] = v[u];
     };
     stage_tile(0);
     phase_sync();
@@ -354,9 +366,10 @@ __device__ __forceinline__ void patch_interior(const int pid, Dims d, PatchArgs 
     for (int J = 0; J < NTILE; ++J) {
         const int c0 = 64 * J, nb = min(64, NT - c0);
         // diagonal block: y = L^{-1} b from the staged inverse, the k-range split over the waves
-        red[tid] = tri_inv_mv<T>(tl, 64, min(16 * wv, nb), min(16 * wv + 16, nb), nb, lane, gt + c0);
+        const int kw = 64 / nw;   // columns of the block per wavefront
+        red[tid] = tri_inv_mv<T>(tl, 64, min(kw * wv, nb), min(kw * wv + kw, nb), nb, lane, gt + c0);
         phase_sync();
-        if (wv == 0 && lane < nb) gt[c0 + lane] = (red[lane] + red[64 + lane]) + (red[128 + lane] + red[192 + lane]);
+        if (wv == 0 && lane < nb) gt[c0 + lane] = sum_waves(red, nw, lane);
         phase_sync();
         const T *D = F + tile_offset(A.off_Ltop, NT, J);
         const int rows = NT - c0 - nb;
@@ -367,9 +380,10 @@ __device__ __forceinline__ void patch_interior(const int pid, Dims d, PatchArgs 
     // ---- backward: top plane (tile NTILE-1 is staged)
     for (int J = NTILE - 1; J >= 0; --J) {
         const int c0 = 64 * J, nb = min(64, NT - c0);
-        red[tid] = tri_inv_t_mv<T>(tl, 64, min(16 * wv, nb), min(16 * wv + 16, nb), nb, lane, gt + c0);
+        const int kw = 64 / nw;
+        red[tid] = tri_inv_t_mv<T>(tl, 64, min(kw * wv, nb), min(kw * wv + kw, nb), nb, lane, gt + c0);
         phase_sync();
-        if (wv == 0 && lane < nb) gt[c0 + lane] = (red[lane] + red[64 + lane]) + (red[128 + lane] + red[192 + lane]);
+        if (wv == 0 && lane < nb) gt[c0 + lane] = sum_waves(red, nw, lane);
         phase_sync();
         if (J > 0) {
             const int cp = 64 * (J - 1), nbp = 64, rows = NT - cp - nbp;
@@ -523,8 +537,8 @@ __device__ __forceinline__ void patch_boundary(const int pid, Dims d, const int 
 // Every patch of one relaxation in one launch: the interior-vertex stars first, then the
 // boundary-vertex stars, whose short solves fill the CUs that the last round of interior
 // patches leaves idle.
-template <typename T, int P, int UNR>
-__global__ void __launch_bounds__(256) k_patch_all(const double *__restrict__ gate, Dims d, PatchArgs A, int n_int,
+template <typename T, int P, int UNR, int NTH>
+__global__ void __launch_bounds__(NTH) k_patch_all(const double *__restrict__ gate, Dims d, PatchArgs A, int n_int,
                                                    const int *__restrict__ verts, const int *__restrict__ fidx,
                                                    const T *__restrict__ fint,
                                                    const int *__restrict__ desc, const int64_t *__restrict__ off,
@@ -543,18 +557,23 @@ void launch_patch_all(const Dims &d, const PatchArgs &a, int n_int, const int *v
                       const int *desc, const int64_t *off, const T *fbnd, const T *mu, const T *lam, const T *afc,
                       const T *rF, T *U, const Exec &e) {
     if (n_int + n_bnd == 0) return;
-    const int unr = e.t.patch_unroll;
+    const int unr = e.t.patch_unroll, nth = e.t.patch_threads;
     if (unr != 4 && unr != 8 && unr != 16) throw Error(VSR_EINVAL, "patch_unroll must be 4, 8 or 16");
-#define CALLU(P, UU)                                                                                              \
-    hipLaunchKernelGGL((k_patch_all<T, P, UU>), dim3(n_int + n_bnd), dim3(256), 0, e.s, e.gate, d, a, n_int, verts, fidx, fint, \
+    if (nth != 256 && nth != 512) throw Error(VSR_EINVAL, "patch_threads must be 256 or 512");
+#define CALLT(P, UU, NN)                                                                                          \
+    hipLaunchKernelGGL((k_patch_all<T, P, UU, NN>), dim3(n_int + n_bnd), dim3(NN), 0, e.s, e.gate, d, a, n_int, verts, fidx, fint, \
                        desc, off, fbnd, mu, lam, afc, rF, U)
+#define CALLU(P, UU)                  \
+    if (nth == 512) CALLT(P, UU, 512); \
+    else CALLT(P, UU, 256)
 #define CALL(P)                          \
-    if (unr == 4) CALLU(P, 4);           \
-    else if (unr == 8) CALLU(P, 8);      \
-    else CALLU(P, 16)
+    if (unr == 4) { CALLU(P, 4); }       \
+    else if (unr == 8) { CALLU(P, 8); }  \
+    else { CALLU(P, 16); }
     VSR_P_SWITCH(d.p, CALL)
 #undef CALL
 #undef CALLU
+#undef CALLT
 }
 
 }  // namespace vsr
