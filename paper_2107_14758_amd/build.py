@@ -18,7 +18,8 @@ COMMON = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
 ]
-SOURCES = [("kernels.hip", ["-x", "hip"]), ("patch_f32.hip", ["-x", "hip"]), ("patch_f64.hip", ["-x", "hip"]),
+SOURCES = [("kernels.hip", ["-x", "hip"]), ("transfer.hip", ["-x", "hip"]), ("patch_f32.hip", ["-x", "hip"]),
+           ("patch_f64.hip", ["-x", "hip"]),
            ("surrogate.hip", ["-x", "hip"]), ("setup.cpp", []), ("capi.cpp", []),
            ("surrogate_capi.cpp", [])]
 

@@ -81,13 +81,17 @@ struct vsr_problem {
     int64_t factor_entries = 0;       // structurally nonzero entries over all patches
     double bytes_patch_launch = 0;    // algorithmic bytes of one patch-solve launch (all stars)
     Table tab[4][3];                  // [TT, T, PT, P][axis]
+    double *xm64[4] = {};             // cell blocks of T^T, T, P^T, P (transfer_block)
+    float *xm32[4] = {};
     int cdim[3] = {0, 0, 0};
     int nc = 0;
     void *A0inv = nullptr;
     // work buffers (cycle precision unless noted)
     void *t1 = nullptr, *t2 = nullptr, *rF = nullptr, *zF = nullptr, *U = nullptr;
     void *c1 = nullptr, *c2 = nullptr, *c3 = nullptr, *c4 = nullptr;
-    void *z1 = nullptr, *az = nullptr, *az2 = nullptr;   // az is zero between cycles
+    void *z1 = nullptr, *res = nullptr;   // cycle iterate and cycle residual
+    double *E64 = nullptr;                // element vectors of the operator (2 slots per cell)
+    void *E32 = nullptr;
     double *vp = nullptr, *vq = nullptr, *vr = nullptr, *vz = nullptr, *vt = nullptr;
     double *scal = nullptr, *partials = nullptr, *host_scal = nullptr;
     double omega = 1.0, lmin = 0.0, lmax = 0.0;
@@ -138,17 +142,43 @@ struct vsr_problem {
 
 namespace {
 
-// y = A x; with fill = false y must hold zeros already (kept so by the kernels that used it)
+// The cell-local operator into the element vector of precision T; returns its slots per cell.
 template <typename T>
-void op_apply(vsr_problem *P, const T *x, T *y, bool fill = true) {
-    if (fill) launch_fill<T>(P->n, y, T(0), P->ex());
+int op_cells(vsr_problem *P, const T *x, T *E) {
     if constexpr (std::is_same<T, double>::value) {
-        if (P->cartesian) launch_op_kron<double>(P->d, P->AB64, P->mu64, x, y, P->ex());
-        else launch_op_general<double>(P->d, P->IDq64, P->Gw64, x, y, P->ex());
+        if (P->cartesian) {
+            launch_op_kron<double>(P->d, P->AB64, P->mu64, x, E, P->ex());
+            return 1;
+        }
+        return launch_op_general<double>(P->d, P->IDq64, P->Gw64, x, E, P->ex());
     } else {
-        if (P->cartesian) launch_op_kron<float>(P->d, P->AB32, P->mu32, x, y, P->ex());
-        else launch_op_general<float>(P->d, P->IDq32, P->Gw32, x, y, P->ex());
+        if (P->cartesian) {
+            launch_op_kron<float>(P->d, P->AB32, P->mu32, x, E, P->ex());
+            return 1;
+        }
+        return launch_op_general<float>(P->d, P->IDq32, P->Gw32, x, E, P->ex());
     }
+}
+
+template <typename T>
+T *elem(vsr_problem *P) {
+    if constexpr (std::is_same<T, double>::value) return P->E64;
+    else return (T *)P->E32;
+}
+
+// y = A x
+template <typename T>
+void op_apply(vsr_problem *P, const T *x, T *y) {
+    const int slots = op_cells<T>(P, x, elem<T>(P));
+    launch_gather<T>(P->d, slots, elem<T>(P), nullptr, y, P->ex());
+    VSR_HIP(hipGetLastError());
+}
+
+// out = r - A x (out in T)
+template <typename T>
+void op_residual(vsr_problem *P, const double *r, const T *x, T *out) {
+    const int slots = op_cells<T>(P, x, elem<T>(P));
+    launch_gather<T>(P->d, slots, elem<T>(P), r, out, P->ex());
     VSR_HIP(hipGetLastError());
 }
 
@@ -158,15 +188,19 @@ const T *wt(const Table &t) {
     else return t.w32;
 }
 
+template <typename T>
+const T *xm(const vsr_problem *P, int kind) {
+    if constexpr (std::is_same<T, double>::value) return P->xm64[kind];
+    else return P->xm32[kind];
+}
+
 // out = alpha * S in + beta * out,  S = T (sum_j Rbar_j^T A_j^{-1} Rbar_j) T^T  (Sec. 2.4-2.6)
 template <typename T, typename Tin>
 void relax_apply(vsr_problem *P, const Tin *in, T *out, T alpha, T beta) {
-    const int L[3] = {P->d.Lx, P->d.Ly, P->d.Lz};
-    T *t1 = (T *)P->t1, *t2 = (T *)P->t2, *rF = (T *)P->rF, *zF = (T *)P->zF, *U = (T *)P->U;
-    const Table *TT = P->tab[0], *Tp = P->tab[1];
-    launch_axis_pass<Tin, T>(TT[0].start, TT[0].bw, wt<T>(TT[0]), 0, L, L, in, t1, T(1), T(0), P->ex());
-    launch_axis_pass<T, T>(TT[1].start, TT[1].bw, wt<T>(TT[1]), 1, L, L, t1, t2, T(1), T(0), P->ex());
-    launch_axis_pass<T, T>(TT[2].start, TT[2].bw, wt<T>(TT[2]), 2, L, L, t2, rF, T(1), T(0), P->ex());
+    const int L[3] = {P->d.Lx, P->d.Ly, P->d.Lz}, NC[3] = {P->d.nx, P->d.ny, P->d.nz};
+    T *rF = (T *)P->rF, *zF = (T *)P->zF, *U = (T *)P->U;
+    launch_transfer<Tin, T>(XFER_FDM_RESTRICT, P->d.p, NC, L, L, xm<T>(P, XFER_FDM_RESTRICT), in, rF, T(1), T(0),
+                            P->ex());
     hipEvent_t e0 = nullptr, e1 = nullptr;
     const bool prof = P->profiling && !P->capturing;
     if (prof) {
@@ -186,9 +220,7 @@ void relax_apply(vsr_problem *P, const Tin *in, T *out, T alpha, T beta) {
         ++P->events_used;
     }
     launch_patch_assemble<T>(P->d, P->opt.interior_patches_only, U, zF, P->ex());
-    launch_axis_pass<T, T>(Tp[0].start, Tp[0].bw, wt<T>(Tp[0]), 0, L, L, zF, t1, T(1), T(0), P->ex());
-    launch_axis_pass<T, T>(Tp[1].start, Tp[1].bw, wt<T>(Tp[1]), 1, L, L, t1, t2, T(1), T(0), P->ex());
-    launch_axis_pass<T, T>(Tp[2].start, Tp[2].bw, wt<T>(Tp[2]), 2, L, L, t2, out, alpha, beta, P->ex());
+    launch_transfer<T, T>(XFER_FDM_PROLONG, P->d.p, NC, L, L, xm<T>(P, XFER_FDM_PROLONG), zF, out, alpha, beta, P->ex());
     VSR_HIP(hipGetLastError());
 }
 
@@ -199,25 +231,23 @@ void coarse_apply(vsr_problem *P, const Tin *in, T *out, T alpha, T beta) {
         if (beta == T(0)) launch_fill<T>(P->n, out, T(0), P->ex());
         return;
     }
-    const int L[3] = {P->d.Lx, P->d.Ly, P->d.Lz};
+    const int L[3] = {P->d.Lx, P->d.Ly, P->d.Lz}, NC[3] = {P->d.nx, P->d.ny, P->d.nz};
     const int *c = P->cdim;
-    const int d1[3] = {c[0], L[1], L[2]}, d2[3] = {c[0], c[1], L[2]}, d3[3] = {c[0], c[1], c[2]};
-    T *c1 = (T *)P->c1, *c2 = (T *)P->c2, *c3 = (T *)P->c3, *c4 = (T *)P->c4;
-    const Table *R = P->tab[2], *Pr = P->tab[3];
-    launch_axis_pass<Tin, T>(R[0].start, R[0].bw, wt<T>(R[0]), 0, L, d1, in, c1, T(1), T(0), P->ex());
-    launch_axis_pass<T, T>(R[1].start, R[1].bw, wt<T>(R[1]), 1, d1, d2, c1, c2, T(1), T(0), P->ex());
-    launch_axis_pass<T, T>(R[2].start, R[2].bw, wt<T>(R[2]), 2, d2, d3, c2, c3, T(1), T(0), P->ex());
+    T *c3 = (T *)P->c3, *c4 = (T *)P->c4;
+    launch_transfer<Tin, T>(XFER_COARSE_RESTRICT, P->d.p, NC, L, c, xm<T>(P, XFER_COARSE_RESTRICT), in, c3, T(1), T(0),
+                            P->ex());
     launch_dense_gemv<T>(P->nc, (const T *)P->A0inv, c3, c4, T(1), T(0), P->ex());
-    launch_axis_pass<T, T>(Pr[2].start, Pr[2].bw, wt<T>(Pr[2]), 2, d3, d2, c4, c2, T(1), T(0), P->ex());
-    launch_axis_pass<T, T>(Pr[1].start, Pr[1].bw, wt<T>(Pr[1]), 1, d2, d1, c2, c1, T(1), T(0), P->ex());
-    launch_axis_pass<T, T>(Pr[0].start, Pr[0].bw, wt<T>(Pr[0]), 0, d1, L, c1, out, alpha, beta, P->ex());
+    launch_transfer<T, T>(XFER_COARSE_PROLONG, P->d.p, NC, c, L, xm<T>(P, XFER_COARSE_PROLONG), c4, out, alpha, beta,
+                          P->ex());
     VSR_HIP(hipGetLastError());
 }
 
 // z = M r in the cycle precision T; mode 0: preconditioner, 1: relaxation, 2: coarse.
+// dot_mode >= 0: r.z is reduced into the PCG scalars by that mode (see launch_dot) in the
+// same pass that writes z.
 template <typename T>
-void precondition(vsr_problem *P, const double *r, double *z, int mode) {
-    T *z1 = (T *)P->z1, *az = (T *)P->az;
+void precondition(vsr_problem *P, const double *r, double *z, int mode, int dot_mode) {
+    T *z1 = (T *)P->z1;
     const T w = (T)P->omega;
     if (mode == 1) {
         relax_apply<T, double>(P, r, z1, T(1), T(0));
@@ -228,23 +258,25 @@ void precondition(vsr_problem *P, const double *r, double *z, int mode) {
         coarse_apply<T, double>(P, r, z1, T(1), T(1));
     } else {
         // hybrid V(1,1): z1 = w S r; z2 = z1 + C (r - A z1); z = z2 + w S (r - A z2)
-        // (az is zero on entry and the residuals leave it zero)
-        T *az2 = (T *)P->az2;
+        T *res = (T *)P->res;
         relax_apply<T, double>(P, r, z1, w, T(0));
-        op_apply<T>(P, z1, az, false);
-        launch_residual<T>(P->n, r, az, az2, P->ex());
-        coarse_apply<T, T>(P, az2, z1, T(1), T(1));
-        op_apply<T>(P, z1, az, false);
-        launch_residual<T>(P->n, r, az, az2, P->ex());
-        relax_apply<T, T>(P, az2, z1, w, T(1));
+        op_residual<T>(P, r, z1, res);
+        coarse_apply<T, T>(P, res, z1, T(1), T(1));
+        op_residual<T>(P, r, z1, res);
+        relax_apply<T, T>(P, res, z1, w, T(1));
     }
-    launch_axpby_to_double<T>(P->n, 1.0, z1, 0.0, z, P->ex());
+    if (dot_mode >= 0) {
+        const int nb = launch_axpby_to_double<T>(P->n, 1.0, z1, 0.0, z, P->ex(), r, P->partials);
+        launch_finalize(nb, P->partials, P->scal, dot_mode, P->mirror, P->ex());
+    } else {
+        launch_axpby_to_double<T>(P->n, 1.0, z1, 0.0, z, P->ex());
+    }
     VSR_HIP(hipGetLastError());
 }
 
-void precond(vsr_problem *P, const double *r, double *z, int mode) {
-    if (P->fp32) precondition<float>(P, r, z, mode);
-    else precondition<double>(P, r, z, mode);
+void precond(vsr_problem *P, const double *r, double *z, int mode, int dot_mode = -1) {
+    if (P->fp32) precondition<float>(P, r, z, mode, dot_mode);
+    else precondition<double>(P, r, z, mode, dot_mode);
 }
 
 double read_scalar(vsr_problem *P, int slot) {
@@ -263,41 +295,37 @@ double dot(vsr_problem *P, const double *x, const double *y) {
 }
 
 // ---- PCG (Hestenes-Stiefel) in pieces shared by the host-driven and the batched solves.
-// x = 0, r = b, q = 0, RR = b.b
+// x = 0, r = b, RR = b.b
 void pcg_init(vsr_problem *P, const double *b, double *x) {
     launch_fill<double>(P->n, x, 0.0, P->ex());
-    launch_fill<double>(P->n, P->vq, 0.0, P->ex());
     launch_cast<double, double>(P->n, b, P->vr, P->ex());
     dot_into(P, b, b, 4);
 }
 
 // z = M r, RZ = r.z, p = z
 void pcg_first_direction(vsr_problem *P) {
-    precond(P, P->vr, P->vz, 0);
-    dot_into(P, P->vr, P->vz, 3);
+    precond(P, P->vr, P->vz, 0, 3);
     launch_cast<double, double>(P->n, P->vz, P->vp, P->ex());
 }
 
-// q = A p (q is zero on entry), alpha = RZ / p.q, x += alpha p, r -= alpha q, q = 0,
-// RR = r.r; rr_mode 4 leaves the stopping test to the host, 5 counts the update and takes
-// the test on the device
+// q = A p, alpha = RZ / p.q, x += alpha p, r -= alpha q, RR = r.r; rr_mode 4 leaves the
+// stopping test to the host, 5 counts the update and takes the test on the device
 void pcg_update(vsr_problem *P, double *x, int rr_mode) {
-    op_apply<double>(P, P->vp, P->vq, false);
-    dot_into(P, P->vp, P->vq, 1);
+    const int slots = op_cells<double>(P, P->vp, P->E64);
+    launch_gather<double>(P->d, slots, P->E64, nullptr, P->vq, P->ex(), P->vp, P->partials);
+    launch_finalize((int)gather_blocks(P->d), P->partials, P->scal, 1, P->mirror, P->ex());
     launch_pcg_xr(P->n, x, P->vr, P->vp, P->vq, P->scal, P->partials, rr_mode, P->mirror, P->ex());
 }
 
 // z = M r, beta = r.z / RZ, RZ = r.z, p = z + beta p
 void pcg_direction(vsr_problem *P) {
-    precond(P, P->vr, P->vz, 0);
-    dot_into(P, P->vr, P->vz, 2);
+    precond(P, P->vr, P->vz, 0, 2);
     launch_pcg_p(P->n, P->vp, P->vz, P->scal, P->ex());
 }
 
 // ||b - A x||_2 in FP64 (ungated)
 double true_residual(vsr_problem *P, const double *b, const double *x) {
-    op_apply<double>(P, x, P->vq);
-    launch_residual<double>(P->n, b, P->vq, P->vt, P->ex());
+    op_residual<double>(P, b, x, P->vt);
     return std::sqrt(std::max(0.0, dot(P, P->vt, P->vt)));
 }
 
@@ -438,14 +466,14 @@ void autotune(vsr_problem *P) {
         pick(P->tune.op_cpw64, {1, 2, 4}, [&] { op_apply<double>(P, P->vp, P->vq); });
         if (P->fp32) {
             launch_cast<double, float>(P->n, P->vp, (float *)P->z1, P->ex());
-            pick(P->tune.op_cpw32, {1, 2, 4}, [&] { op_apply<float>(P, (const float *)P->z1, (float *)P->az); });
+            pick(P->tune.op_cpw32, {1, 2, 4}, [&] { op_apply<float>(P, (const float *)P->z1, (float *)P->res); });
         }
     }
     if (!P->cartesian) {
         pick(P->tune.opg_split64, {1, 2}, [&] { op_apply<double>(P, P->vp, P->vq); });
         if (P->fp32) {
             launch_cast<double, float>(P->n, P->vp, (float *)P->z1, P->ex());
-            pick(P->tune.opg_split32, {1, 2}, [&] { op_apply<float>(P, (const float *)P->z1, (float *)P->az); });
+            pick(P->tune.opg_split32, {1, 2}, [&] { op_apply<float>(P, (const float *)P->z1, (float *)P->res); });
         }
     }
     const int L[3] = {P->d.Lx, P->d.Ly, P->d.Lz};
@@ -511,9 +539,6 @@ void autotune(vsr_problem *P) {
     const int64_t w3 = (int64_t)P->pa.w * P->pa.w * P->pa.w, nv = (int64_t)(P->d.nx + 1) * (P->d.ny + 1) * (P->d.nz + 1);
     if (P->fp32) launch_fill<float>(nv * w3, (float *)P->U, 0.f, P->ex());
     else launch_fill<double>(nv * w3, (double *)P->U, 0.0, P->ex());
-    // the cycle keeps az at zero between uses
-    if (P->fp32) launch_fill<float>(P->n, (float *)P->az, 0.f, P->ex());
-    else launch_fill<double>(P->n, (double *)P->az, 0.0, P->ex());
     VSR_HIP(hipStreamSynchronize(P->stream));
     std::lock_guard<std::mutex> lk(g_tune_mutex);
     g_tune_cache[key] = P->tune;
@@ -895,6 +920,11 @@ vsr_status vsr_setup(const vsr_mesh *mesh, int32_t p, const vsr_coefficients *co
             P->tab[3][ax] = make_table(P.get(), table_coarse_prolong(nc3[ax], P->od));
             P->cdim[ax] = nc3[ax] - 1;
         }
+        for (int k = 0; k < 4; ++k) {
+            const std::vector<double> M = transfer_block(k, P->od);
+            P->xm64[k] = P->upload(M);
+            P->xm32[k] = P->upload_as<float>(M);
+        }
         // coarse space
         std::vector<double> A0inv = make_coarse_inverse(nx, ny, nz, P->od, g);
         P->nc = P->cdim[0] * P->cdim[1] * P->cdim[2];
@@ -912,10 +942,12 @@ vsr_status vsr_setup(const vsr_mesh *mesh, int32_t p, const vsr_coefficients *co
         P->zF = alloc_t(P->n);
         P->U = alloc_t(nv * w3);
         P->z1 = alloc_t(P->n);
-        P->az = alloc_t(P->n);
-        P->az2 = alloc_t(P->n);
-        if (P->fp32) launch_fill<float>(P->n, (float *)P->az, 0.f, P->ex());
-        else launch_fill<double>(P->n, (double *)P->az, 0.0, P->ex());
+        P->res = alloc_t(P->n);
+        {
+            const int64_t eb = (int64_t)P->ncell * (p + 1) * (p + 1) * (p + 1) * 2;   // up to 2 slots per cell
+            P->E64 = P->dalloc<double>(eb);
+            if (P->fp32) P->E32 = P->dalloc<float>(eb);
+        }
         P->c1 = alloc_t((int64_t)P->cdim[0] * P->d.Ly * P->d.Lz);
         P->c2 = alloc_t((int64_t)P->cdim[0] * P->cdim[1] * P->d.Lz);
         P->c3 = alloc_t(P->nc);
@@ -926,7 +958,8 @@ vsr_status vsr_setup(const vsr_mesh *mesh, int32_t p, const vsr_coefficients *co
         P->vz = P->dalloc<double>(P->n);
         P->vt = P->dalloc<double>(P->n);
         P->scal = P->dalloc<double>(SC_N);
-        P->partials = P->dalloc<double>(1024);
+        // partial sums: dot passes (at most 8192 workgroups) and the lattice-line gathers
+        P->partials = P->dalloc<double>(std::max<int64_t>(8192, gather_blocks(P->d)));
         VSR_HIP(hipHostMalloc((void **)&P->host_scal, sizeof(double) * SC_N, hipHostMallocDefault));
         if (P->fp32) launch_fill<float>(nv * w3, (float *)P->U, 0.f, P->ex());
         else launch_fill<double>(nv * w3, (double *)P->U, 0.0, P->ex());

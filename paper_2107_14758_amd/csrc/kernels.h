@@ -34,11 +34,25 @@ struct Exec {
     Tuning t{};
 };
 
-// y += A x (y must be zeroed by the caller); Cartesian (separable) or general metric.
+// Cell-local operator y_K = A^K x_K into the element vector E ((p+1)^3 values per cell, in
+// rows of x across cells: local node (k, j, i) of cell (ex, ey, ez) at
+// (((ez ny + ey)(p+1) + k)(p+1) + j) nx (p+1) + ex (p+1) + i).  Cartesian (separable) cells:
+// one slot.  General metric: `slots` partial slots (the return value), slot s at
+// s ncell (p+1)^3.  launch_gather turns E into the lattice vector.
 template <typename T>
-void launch_op_kron(const Dims &d, const T *AB1d, const T *mu, const T *x, T *y, const Exec &e);
+void launch_op_kron(const Dims &d, const T *AB1d, const T *mu, const T *x, T *E, const Exec &e);
 template <typename T>
-void launch_op_general(const Dims &d, const T *IDq, const T *Gw, const T *x, T *y, const Exec &e);
+int launch_op_general(const Dims &d, const T *IDq, const T *Gw, const T *x, T *E, const Exec &e);
+// out = sum over the cells and slots that share each free node of E (r == nullptr), or
+// out = r - that sum (in T).  Deterministic: a fixed summation order, no atomics.  With
+// dotv, also the partial sums of dotv . out, one per workgroup (gather_blocks of them), into
+// partials for launch_finalize.
+template <typename T>
+void launch_gather(const Dims &d, int slots, const T *E, const double *r, T *out, const Exec &e,
+                   const double *dotv = nullptr, double *partials = nullptr);
+int64_t gather_blocks(const Dims &d);
+// Adds nb partial sums in a fixed order and applies them to scal by mode (see launch_dot).
+void launch_finalize(int nb, const double *partials, double *scal, int mode, double *mirror, const Exec &e);
 // b += sum_K R_K^T (I x I x I)^T (wdet .* f)
 void launch_load_vector(const Dims &d, const double *IDq, const double *wdet, const double *f, double *b,
                         const Exec &e);
@@ -48,6 +62,15 @@ void launch_load_vector(const Dims &d, const double *IDq, const double *wdet, co
 template <typename Tin, typename Tout>
 void launch_axis_pass(const int *start, int bw, const Tout *w, int axis, const int in_dims[3],
                       const int out_dims[3], const Tin *in, Tout *out, Tout alpha, Tout beta, const Exec &e);
+
+// Lattice transfers, each in one launch (M x M x M with a cell-blocked 1D map M):
+// FDM restriction r~ = T^T r and prolongation z = T z~ on the free fine lattice (Sec. 2.4);
+// Q1 restriction P^T (fine -> interior coarse vertices) and prolongation P (Sec. 2.5).
+// kind is one of XFER_* (vsr_internal.h) and M its OA x K block matrix (transfer_block);
+// out = alpha * (map) in + beta * out.
+template <typename Tin, typename T>
+void launch_transfer(int kind, int p, const int ncell[3], const int in_dims[3], const int out_dims[3], const T *M,
+                     const Tin *in, T *out, T alpha, T beta, const Exec &e);
 
 struct PatchArgs {
     int m, w;
@@ -82,17 +105,16 @@ void launch_dot(int64_t n, const double *x, const double *y, double *partials, d
 // Start of a device-driven PCG after RR = b.b: BB = RR, IT = 0, stopping data, DONE when b = 0
 // or b is not finite (mirrored).  Not gated.
 void launch_pcg_start(double *scal, double rtol, int max_iterations, double *mirror, const Exec &e);
-// x += alpha p ; r -= alpha q ; q = 0 ; r.r reduced into scal by mode (4 or 5)
-void launch_pcg_xr(int64_t n, double *x, double *r, const double *p, double *q, double *scal, double *partials, int mode,
+// x += alpha p ; r -= alpha q ; r.r reduced into scal by mode (4 or 5)
+void launch_pcg_xr(int64_t n, double *x, double *r, const double *p, const double *q, double *scal, double *partials, int mode,
                    double *mirror, const Exec &e);
 // p = z + beta p
 void launch_pcg_p(int64_t n, double *p, const double *z, const double *scal, const Exec &e);
-// out(T) = r(double) - Az(T), then Az = 0 ; out must not alias Az
+// y(double) = a * x(T) + b * y; with dotv, also the partial sums of dotv . y (one per
+// workgroup; the return value is their count) into partials for launch_finalize
 template <typename T>
-void launch_residual(int64_t n, const double *r, T *Az, T *out, const Exec &e);
-// y(double) = a * x(T) + b * y
-template <typename T>
-void launch_axpby_to_double(int64_t n, double a, const T *x, double b, double *y, const Exec &e);
+int launch_axpby_to_double(int64_t n, double a, const T *x, double b, double *y, const Exec &e,
+                           const double *dotv = nullptr, double *partials = nullptr);
 // Device scalars of one PCG.  A device-driven PCG (batched solves) keeps its stopping state
 // here: DONE is nonzero once the member stops; STATUS 1 converged, 2 non-finite residual,
 // 3 iteration cap; IT counts x updates.

@@ -13,22 +13,51 @@ namespace vsr {
 namespace {
 using namespace dev;
 
+// Sum over a workgroup (valid in thread 0), wavefronts added in a fixed order.
+__device__ __forceinline__ double block_sum(double v) {
+    __shared__ double part[16];
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if (lane == 0) part[wv] = v;
+    __syncthreads();
+    double s = 0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < nw; ++i) s += part[i];
+    return s;
+}
+
 // ====================================================================== operator
+// Element vectors hold (p+1)^3 values per cell laid out across cells row by row: row
+// ((ez ny + ey)(p+1) + k)(p+1) + j holds the x-rows (local i) of the cells ex = 0 .. nx-1
+// one after another, so the lattice nodes of one x-line read one contiguous run.  Slot s
+// of a general-operator split starts at s ncell (p+1)^3.
+template <int N1>
+__device__ __forceinline__ int64_t elem_index(const Dims &d, int ex, int ey, int ez, int k, int j, int i) {
+    return ((((int64_t)ez * d.ny + ey) * N1 + k) * N1 + j) * ((int64_t)d.nx * N1) + (int64_t)ex * N1 + i;
+}
+
 // Separable (Cartesian) cell operator, eq. (kron) of Sec. 2.2:
-// A^K = mu1 B x B x A + mu2 B x A x B + mu3 A x B x B, evaluated per z-slab in LDS with
-// the z contraction done per (j, i) column in registers.
+// A^K = mu1 B x B x A + mu2 B x A x B + mu3 A x B x B.  Thread (j, i) of a cell owns one
+// z-column.  The cell's values are staged KC z-slabs at a time (one global round trip per
+// chunk; all slabs at once where they fit); the x and y contractions run through LDS with
+// this thread's rows of A and B in registers, and each slab's result is folded at once into
+// the column's z contraction (A and B read there at wave-uniform addresses).  The cell's
+// (p+1)^3 results go to its block of the element vector E with plain stores; k_gather sums
+// the blocks that share a lattice node (no atomics).
+template <int P, int BYTES>
+constexpr int kron_chunk() {
+    constexpr int N1 = P + 1, per = 3 * N1 * N1 * BYTES, kc = (48 * 1024) / per;
+    return kc < 1 ? 1 : (kc > N1 ? N1 : kc);
+}
+
 template <typename T, int P, int CPW>
 __global__ void __launch_bounds__(256) k_op_kron(const double *__restrict__ gate, Dims d, const T *__restrict__ AB1d,
-                                                 const T *__restrict__ mu, const T *__restrict__ x, T *__restrict__ y) {
+                                                 const T *__restrict__ mu, const T *__restrict__ x, T *__restrict__ E) {
     if (gated(gate)) return;
-    constexpr int N1 = P + 1, N2 = N1 * N1;
-    __shared__ T sA[N2], sB[N2], xs[CPW][N2], as[CPW][N2], bs[CPW][N2];
+    constexpr int N1 = P + 1, N2 = N1 * N1, KC = kron_chunk<P, (int)sizeof(T) * CPW>(), NCH = (N1 + KC - 1) / KC;
+    __shared__ T xs[CPW][KC * N2], as[CPW][KC * N2], bs[CPW][KC * N2];
     const int tid = threadIdx.x;
-    for (int t = tid; t < N2; t += blockDim.x) {
-        sA[t] = AB1d[t];
-        sB[t] = AB1d[N2 + t];
-    }
-    // CPW cells per workgroup, N2 threads each (thread (j, i) of its cell owns one z-column)
+    // CPW cells per workgroup, N2 threads each
     const int sub = tid / N2, lt = tid - sub * N2;
     const int64_t ncell = (int64_t)d.nx * d.ny * d.nz;
     const int64_t e = (int64_t)blockIdx.x * CPW + sub;
@@ -38,55 +67,67 @@ __global__ void __launch_bounds__(256) k_op_kron(const double *__restrict__ gate
     const T m0 = active ? mu[3 * ec] : T(0), m1 = active ? mu[3 * ec + 1] : T(0), m2 = active ? mu[3 * ec + 2] : T(0);
     const int j = lt / N1, i = lt % N1;
     const int sb = active ? sub : 0;
-    T wv[N1], sv[N1];
+    const T *A1 = AB1d, *B1 = AB1d + N2;
+    T Ai[N1], Bi[N1], Aj[N1], Bj[N1], acc[N1];
 #pragma unroll
-    for (int k = 0; k < N1; ++k) {
-        __syncthreads();
+    for (int t = 0; t < N1; ++t) {
+        Ai[t] = A1[i * N1 + t];
+        Bi[t] = B1[i * N1 + t];
+        Aj[t] = A1[j * N1 + t];
+        Bj[t] = B1[j * N1 + t];
+        acc[t] = T(0);
+    }
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+        const int k0 = c * KC, kn = min(KC, N1 - k0);
+        if (c > 0) __syncthreads();
         if (active) {
-            int K = P * ez + k, J = P * ey + j, I = P * ex + i;
-            xs[sb][lt] = is_free(d, K, J, I) ? x[free_index(d, K, J, I)] : T(0);
+#pragma unroll
+            for (int kk = 0; kk < KC; ++kk) {
+                const int K = P * ez + k0 + kk, J = P * ey + j, I = P * ex + i;
+                if (kk < kn) xs[sb][kk * N2 + lt] = is_free(d, K, J, I) ? x[free_index(d, K, J, I)] : T(0);
+            }
         }
         __syncthreads();
         if (active) {
-            T a = 0, b = 0;
+#pragma unroll 1
+            for (int kk = 0; kk < kn; ++kk) {
+                T a = 0, b = 0;
 #pragma unroll
-            for (int ii = 0; ii < N1; ++ii) {
-                a += sA[i * N1 + ii] * xs[sb][j * N1 + ii];
-                b += sB[i * N1 + ii] * xs[sb][j * N1 + ii];
+                for (int ii = 0; ii < N1; ++ii) {
+                    const T v = xs[sb][kk * N2 + j * N1 + ii];
+                    a += Ai[ii] * v;
+                    b += Bi[ii] * v;
+                }
+                as[sb][kk * N2 + lt] = a;
+                bs[sb][kk * N2 + lt] = b;
             }
-            as[sb][lt] = a;
-            bs[sb][lt] = b;
         }
         __syncthreads();
         if (active) {
-            T c1 = 0, c2 = 0, c3 = 0;
+#pragma unroll 1
+            for (int kk = 0; kk < kn; ++kk) {
+                T c1 = 0, c2 = 0, c3 = 0;
 #pragma unroll
-            for (int jj = 0; jj < N1; ++jj) {
-                c1 += sB[j * N1 + jj] * as[sb][jj * N1 + i];
-                c2 += sA[j * N1 + jj] * bs[sb][jj * N1 + i];
-                c3 += sB[j * N1 + jj] * bs[sb][jj * N1 + i];
+                for (int jj = 0; jj < N1; ++jj) {
+                    const T va = as[sb][kk * N2 + jj * N1 + i], vb = bs[sb][kk * N2 + jj * N1 + i];
+                    c1 += Bj[jj] * va;
+                    c2 += Aj[jj] * vb;
+                    c3 += Bj[jj] * vb;
+                }
+                const T w = m0 * c1 + m1 * c2, sv = m2 * c3;
+#pragma unroll
+                for (int k = 0; k < N1; ++k) acc[k] += B1[k * N1 + k0 + kk] * w + A1[k * N1 + k0 + kk] * sv;
             }
-            wv[k] = m0 * c1 + m1 * c2;
-            sv[k] = m2 * c3;
         }
     }
     if (!active) return;
 #pragma unroll
-    for (int k = 0; k < N1; ++k) {
-        T acc = 0;
-#pragma unroll
-        for (int kk = 0; kk < N1; ++kk) acc += sB[k * N1 + kk] * wv[kk] + sA[k * N1 + kk] * sv[kk];
-        int K = P * ez + k, J = P * ey + j, I = P * ex + i;
-        if (is_free(d, K, J, I)) atomic_add_global(&y[free_index(d, K, J, I)], acc);
-    }
+    for (int k = 0; k < N1; ++k) E[elem_index<N1>(d, ex, ey, ez, k, j, i)] = acc[k];
 }
 
-// General trilinear cell: y_K = (grad phi)^T Gw (grad phi) x_K with the q^3 GLL rule
-// (Sec. 2.1, 2.7).  Thread (b, a) owns one z-column of quadrature points; the x and y
-// contractions run per z-slab through LDS, the z contraction and the metric in registers.
-// S workgroups share a cell, each owning a band of ceil(Q/S) b-rows of columns (fewer
-// registers' worth of columns per workgroup: with S = 2 the FP64 column state of p = 14, 15
-// fits without spills); their partial outputs meet in the atomic additions into y.
+// Launch geometry of the general operator: S workgroups per cell, each with ceil(Q/S)
+// b-rows of Q quadrature columns.
 constexpr int opg_rows(int P, int S) { return (QOF(P) + S - 1) / S; }
 constexpr int opg_threads(int P, int S) { return (opg_rows(P, S) * QOF(P) + 63) / 64 * 64; }
 // z-slabs per chunk: as many as fit in about 60 KB of LDS in either chunked phase
@@ -103,16 +144,18 @@ constexpr int opg_chunk(int P, int S, int bytes) {
 // contractions run through LDS for a chunk of KC z-slabs at a time (three barriers per chunk
 // and direction); the z contraction, the metric and the z back-contraction stay in the
 // column's registers.  S workgroups share a cell, each owning a band of ceil(Q/S) b-rows of
-// columns (with S = 2 the FP64 column state of p = 14, 15 fits without spills); their
-// partial outputs meet in the atomic additions into y.
+// columns (with S = 2 the FP64 column state of p = 14, 15 fits in registers); each writes
+// its partial (p+1)^3 block to its own slot of the element vector E, and k_gather sums the
+// slots and the cells that share a node.
 template <typename T, int P, int S>
 __global__ void __launch_bounds__(opg_threads(P, S)) k_op_general(const double *__restrict__ gate, Dims d,
                                                                    const T *__restrict__ IDq, const T *__restrict__ Gw,
-                                                                   const T *__restrict__ x, T *__restrict__ y) {
+                                                                   const T *__restrict__ x, T *__restrict__ E) {
     if (gated(gate)) return;
     constexpr int N1 = P + 1, Q = QOF(P), Q2 = Q * Q, Q3 = Q2 * Q, BR = opg_rows(P, S);
     constexpr int KC = opg_chunk(P, S, (int)sizeof(T)), NCH = (N1 + KC - 1) / KC;
     constexpr int FWD = N1 * N1 + 2 * N1 * Q, BWD = 3 * BR * Q + 2 * N1 * Q;
+    constexpr int NTH = opg_threads(P, S), NX = KC * N1 * N1, NLX = (NX + NTH - 1) / NTH;
     __shared__ T sI[Q * N1], sD[Q * N1];
     __shared__ T buf[KC * (FWD > BWD ? FWD : BWD)];
     const int tid = threadIdx.x, nt = blockDim.x;
@@ -131,11 +174,20 @@ __global__ void __launch_bounds__(opg_threads(P, S)) k_op_general(const double *
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
         const int k0 = c * KC, kn = min(KC, N1 - k0);
-        __syncthreads();
-        for (int t = tid; t < kn * N1 * N1; t += nt) {
+        // the chunk's loads all in flight before the first LDS store
+        T xv[NLX];
+#pragma unroll
+        for (int l = 0; l < NLX; ++l) {
+            const int t = tid + l * NTH;
             const int kk = t / (N1 * N1), jj = (t / N1) % N1, ii = t % N1;
             const int K = P * ez + k0 + kk, J = P * ey + jj, I = P * ex + ii;
-            xs[t] = is_free(d, K, J, I) ? x[free_index(d, K, J, I)] : T(0);
+            xv[l] = (t < kn * N1 * N1 && is_free(d, K, J, I)) ? x[free_index(d, K, J, I)] : T(0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int l = 0; l < NLX; ++l) {
+            const int t = tid + l * NTH;
+            if (t < kn * N1 * N1) xs[t] = xv[l];
         }
         __syncthreads();
         for (int t = tid; t < kn * N1 * Q; t += nt) {
@@ -175,8 +227,17 @@ __global__ void __launch_bounds__(opg_threads(P, S)) k_op_general(const double *
 #pragma unroll
     for (int k = 0; k < N1; ++k) AAo[k] = ABo[k] = BAo[k] = 0;
     if (col) {
+        // metric of point c + 1 loaded while point c is computed
         const T *g = Gw + e * 6 * (int64_t)Q3 + b * Q + a;
+        T gn[6];
+#pragma unroll
+        for (int m = 0; m < 6; ++m) gn[m] = g[m * Q3];
         for (int c = 0; c < Q; ++c) {
+            const T gxx = gn[0], gyy = gn[1], gzz = gn[2], gxy = gn[3], gxz = gn[4], gyz = gn[5];
+            if (c + 1 < Q) {
+#pragma unroll
+                for (int m = 0; m < 6; ++m) gn[m] = g[m * Q3 + (c + 1) * Q2];
+            }
             T ux = 0, uy = 0, uz = 0;
 #pragma unroll
             for (int k = 0; k < N1; ++k) {
@@ -184,9 +245,6 @@ __global__ void __launch_bounds__(opg_threads(P, S)) k_op_general(const double *
                 uy += sI[c * N1 + k] * AB[k];
                 uz += sD[c * N1 + k] * AA[k];
             }
-            const int pt = c * Q2;
-            T gxx = g[pt], gyy = g[Q3 + pt], gzz = g[2 * Q3 + pt], gxy = g[3 * Q3 + pt], gxz = g[4 * Q3 + pt],
-              gyz = g[5 * Q3 + pt];
             T vx = gxx * ux + gxy * uy + gxz * uz;
             T vy = gxy * ux + gyy * uy + gyz * uz;
             T vz = gxz * ux + gyz * uy + gzz * uz;
@@ -233,9 +291,67 @@ __global__ void __launch_bounds__(opg_threads(P, S)) k_op_general(const double *
             const T *y1 = Y1 + (kk * N1 + jj) * Q, *dy1 = DY1 + (kk * N1 + jj) * Q;
             T s = 0;
             for (int aa = 0; aa < Q; ++aa) s += sI[aa * N1 + ii] * y1[aa] + sD[aa * N1 + ii] * dy1[aa];
-            const int K = P * ez + k0 + kk, J = P * ey + jj, I = P * ex + ii;
-            if (is_free(d, K, J, I)) atomic_add_global(&y[free_index(d, K, J, I)], s);
+            E[(int64_t)(blockIdx.x % S) * (d.nx * d.ny * d.nz) * (N1 * N1 * N1) +
+              elem_index<N1>(d, ex, ey, ez, k0 + kk, jj, ii)] = s;
         }
+    }
+}
+
+// Assembly of an element vector: every free lattice node sums the blocks of the (up to 8)
+// cells that contain it, each with its S slots, in a fixed order.  r == nullptr: out = sum;
+// else out = r - sum (the residual of the cycle, in T).  A workgroup covers XB nodes of one
+// x-line: the line's (y, z) position and cells are uniform across it.
+constexpr int XB = 128;
+
+template <int P>
+__device__ __forceinline__ int axis_cells(int g, int c[2], int l[2]) {
+    const int q = g / P, rem = g - q * P;
+    if (rem == 0) {   // on a cell face: the cell below (local P) and the one above (local 0)
+        c[0] = q - 1; l[0] = P; c[1] = q; l[1] = 0;
+        return 2;
+    }
+    c[0] = q; l[0] = rem; c[1] = q; l[1] = rem;
+    return 1;
+}
+
+template <typename T, int P>
+__global__ void __launch_bounds__(XB) k_gather(const double *__restrict__ gate, Dims d, int slots, const T *__restrict__ E,
+                                                const double *__restrict__ r, T *__restrict__ out,
+                                                const double *__restrict__ dotv, double *__restrict__ partials) {
+    if (gated(gate)) return;
+    constexpr int N1 = P + 1, N3 = N1 * N1 * N1;
+    const int xblocks = (d.Lx + XB - 1) / XB;
+    const int line = (int)(blockIdx.x / xblocks), I0 = (int)(blockIdx.x - (int64_t)line * xblocks) * XB + threadIdx.x + 1;
+    const bool live = I0 <= d.Lx;
+    const int I = live ? I0 : d.Lx;
+    const int J = line % d.Ly + 1, K = line / d.Ly + 1;
+    int cx[2], lx[2], cy[2], ly[2], cz[2], lz[2];
+    const int mx = axis_cells<P>(I, cx, lx), my = axis_cells<P>(J, cy, ly), mz = axis_cells<P>(K, cz, lz);
+    const int64_t slot = (int64_t)d.nx * d.ny * d.nz * N3, rowlen = (int64_t)d.nx * N1;
+    const int x0 = cx[0] * N1 + lx[0];   // with two cells along x their entries are adjacent (x0, x0 + 1)
+    // all candidate loads issued together (predicated), then summed in a fixed order
+    T v[2][4][2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int zc = t >> 1, yc = t & 1;
+            const bool ok = s < slots && zc < mz && yc < my;
+            const T *row = E + (ok ? s * slot + ((((int64_t)cz[zc] * d.ny + cy[yc]) * N1 + lz[zc]) * N1 + ly[yc]) * rowlen + x0 : 0);
+            v[s][t][0] = ok ? row[0] : T(0);
+            v[s][t][1] = ok && mx == 2 ? row[1] : T(0);
+        }
+    T sum = T(0);
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) sum += v[s][t][0] + v[s][t][1];
+    const int64_t idx = ((int64_t)(K - 1) * d.Ly + (J - 1)) * d.Lx + (I - 1);
+    const T o = r == nullptr ? sum : (T)r[idx] - sum;
+    if (live) out[idx] = o;
+    if (dotv != nullptr) {   // partial sum of dotv . out for this workgroup
+        const double prod = block_sum(live ? dotv[idx] * (double)o : 0.0);
+        if (threadIdx.x == 0) partials[blockIdx.x] = prod;
     }
 }
 
@@ -382,42 +498,46 @@ __global__ void k_axis_pass(const double *__restrict__ gate, const int *__restri
 
 // Additive Schwarz sum z_F = sum_j Rbar_j^T u_j (Sec. 2.5): each free lattice point sums
 // the boxes of the (up to 8) stars that contain it.
-template <typename T>
-__global__ void k_patch_assemble(const double *__restrict__ gate, Dims d, int interior_only, const T *__restrict__ U, T *__restrict__ zF) {
+template <typename T, int P>
+__global__ void __launch_bounds__(XB) k_patch_assemble(const double *__restrict__ gate, Dims d, int interior_only,
+                                                        const T *__restrict__ U, T *__restrict__ zF) {
     if (gated(gate)) return;
-    const int p = d.p, m = p - 1, w = 2 * m + 1;
-    const int64_t n = (int64_t)d.Lx * d.Ly * d.Lz, w3 = (int64_t)w * w * w;
-    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n; idx += (int64_t)gridDim.x * blockDim.x) {
-        int P3[3] = {(int)(idx % d.Lx) + 1, (int)((idx / d.Lx) % d.Ly) + 1, (int)(idx / ((int64_t)d.Lx * d.Ly)) + 1};
-        int ncell[3] = {d.nx, d.ny, d.nz};
-        int v[3][2], a[3][2], nc[3];
-        for (int ax = 0; ax < 3; ++ax) {
-            int Pp = P3[ax];
-            nc[ax] = 0;
-            if (Pp % p == 0) {
-                v[ax][0] = Pp / p; a[ax][0] = m; nc[ax] = 1;
-            } else {
-                int e = Pp / p, al = Pp % p;
-                v[ax][0] = e; a[ax][0] = m + al;
-                v[ax][1] = e + 1; a[ax][1] = al - 1;
-                nc[ax] = 2;
-            }
-            if (interior_only) {
-                int k = 0;
-                for (int t = 0; t < nc[ax]; ++t)
-                    if (v[ax][t] >= 1 && v[ax][t] <= ncell[ax] - 1) { v[ax][k] = v[ax][t]; a[ax][k] = a[ax][t]; ++k; }
-                nc[ax] = k;
-            }
+    constexpr int m = P - 1, w = 2 * m + 1, w3 = w * w * w;
+    const int xblocks = (d.Lx + XB - 1) / XB;
+    const int line = (int)(blockIdx.x / xblocks), I = (int)(blockIdx.x - (int64_t)line * xblocks) * XB + threadIdx.x + 1;
+    if (I > d.Lx) return;
+    const int P3[3] = {I, line % d.Ly + 1, line / d.Ly + 1};
+    const int ncell[3] = {d.nx, d.ny, d.nz};
+    // the stars (vertices v) whose boxes hold this node, and its position a in each box
+    int v[3][2], a[3][2], nc[3];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        const int Pp = P3[ax], e = Pp / P, al = Pp - e * P;
+        if (al == 0) {
+            v[ax][0] = e; a[ax][0] = m; v[ax][1] = e; a[ax][1] = m; nc[ax] = 1;
+        } else {
+            v[ax][0] = e; a[ax][0] = m + al; v[ax][1] = e + 1; a[ax][1] = al - 1; nc[ax] = 2;
         }
-        T s = 0;
-        for (int tz = 0; tz < nc[2]; ++tz)
-            for (int ty = 0; ty < nc[1]; ++ty)
-                for (int tx = 0; tx < nc[0]; ++tx) {
-                    int64_t vid = ((int64_t)v[2][tz] * (d.ny + 1) + v[1][ty]) * (d.nx + 1) + v[0][tx];
-                    s += U[vid * w3 + ((int64_t)a[2][tz] * w + a[1][ty]) * w + a[0][tx]];
-                }
-        zF[idx] = s;
+        if (interior_only) {
+            int k = 0;
+            for (int t = 0; t < nc[ax]; ++t)
+                if (v[ax][t] >= 1 && v[ax][t] <= ncell[ax] - 1) { v[ax][k] = v[ax][t]; a[ax][k] = a[ax][t]; ++k; }
+            nc[ax] = k;
+        }
     }
+    // all (up to 8) box loads issued together (predicated), then summed in a fixed order
+    T val[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const int tz = t >> 2, ty = (t >> 1) & 1, tx = t & 1;
+        const bool ok = tz < nc[2] && ty < nc[1] && tx < nc[0];
+        const int64_t vid = ((int64_t)v[2][tz] * (d.ny + 1) + v[1][ty]) * (d.nx + 1) + v[0][tx];
+        val[t] = ok ? U[vid * w3 + (a[2][tz] * w + a[1][ty]) * w + a[0][tx]] : T(0);
+    }
+    T s = 0;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) s += val[t];
+    zF[((int64_t)(P3[2] - 1) * d.Ly + (P3[1] - 1)) * d.Lx + (I - 1)] = s;
 }
 
 // ====================================================================== dense / vector
@@ -457,17 +577,6 @@ __global__ void k_fill(const double *__restrict__ gate, int64_t n, T *__restrict
 
 constexpr int RED_BLOCKS = 1024;
 
-__device__ __forceinline__ double block_sum(double v) {
-    __shared__ double part[16];
-    v = wave_sum(v);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    if (lane == 0) part[wv] = v;
-    __syncthreads();
-    double s = 0;
-    if (threadIdx.x == 0)
-        for (int i = 0; i < nw; ++i) s += part[i];
-    return s;
-}
 
 // Scalar update of a PCG reduction s into scal (thread 0 of one workgroup).  mode: 0 plain,
 // 1 p.q -> alpha, 2 r.z -> beta (and the shift), 3 initial r.z, 4 r.r, 5 r.r after an x update
@@ -518,18 +627,29 @@ __global__ void k_dot_partial(const double *__restrict__ gate, int64_t n, const 
 // The partials added in index order (the same order on every run) and applied by `mode`.
 // A separate launch: a last-workgroup reduction inside the producing kernel needs a device-
 // scope release per workgroup, which writes back the L2 of its XCD each time.
-__global__ void k_finalize(const double *__restrict__ gate, int nb, const double *__restrict__ partials, double *scal,
-                           int mode, double *mirror) {
+// One workgroup of FIN_THREADS adds the nb partials: four independent loads in flight per
+// thread, a fixed order throughout.
+constexpr int FIN_THREADS = 1024;
+__global__ void __launch_bounds__(FIN_THREADS) k_finalize(const double *__restrict__ gate, int nb,
+                                                          const double *__restrict__ partials, double *scal, int mode,
+                                                          double *mirror) {
     if (gated(gate)) return;
-    double s = 0;
-    for (int i = threadIdx.x; i < nb; i += blockDim.x) s += partials[i];
-    s = block_sum(s);
+    double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+    int i = threadIdx.x;
+    for (; i + 3 * FIN_THREADS < nb; i += 4 * FIN_THREADS) {
+        s0 += partials[i];
+        s1 += partials[i + FIN_THREADS];
+        s2 += partials[i + 2 * FIN_THREADS];
+        s3 += partials[i + 3 * FIN_THREADS];
+    }
+    for (; i < nb; i += FIN_THREADS) s0 += partials[i];
+    const double s = block_sum((s0 + s1) + (s2 + s3));
     if (threadIdx.x == 0) apply_mode(scal, s, mode, mirror);
 }
 
-// x += alpha p, r -= alpha q, q = 0 (ready for the next operator apply), partial sums of r.r.
+// x += alpha p, r -= alpha q, partial sums of r.r.
 __global__ void k_pcg_xr(const double *__restrict__ gate, int64_t n, double *__restrict__ x, double *__restrict__ r,
-                         const double *__restrict__ p, double *__restrict__ q, const double *__restrict__ scal,
+                         const double *__restrict__ p, const double *__restrict__ q, const double *__restrict__ scal,
                          double *partials) {
     if (gated(gate)) return;
     const double alpha = scal[SC_ALPHA];
@@ -538,7 +658,6 @@ __global__ void k_pcg_xr(const double *__restrict__ gate, int64_t n, double *__r
         x[i] += alpha * p[i];
         double ri = r[i] - alpha * q[i];
         r[i] = ri;
-        q[i] = 0.0;
         s += ri * ri;
     }
     s = block_sum(s);
@@ -553,21 +672,21 @@ __global__ void k_pcg_p(const double *__restrict__ gate, int64_t n, double *__re
 }
 
 // out = r - Az, then Az = 0 (ready for the next operator apply); out must not alias Az.
+// y = a x + b y in FP64; with dotv, the workgroup's partial sum of dotv . y into partials
 template <typename T>
-__global__ void k_residual(const double *__restrict__ gate, int64_t n, const double *__restrict__ r, T *__restrict__ Az,
-                           T *__restrict__ out) {
+__global__ void k_axpby_to_double(const double *__restrict__ gate, int64_t n, double a, const T *__restrict__ x, double b,
+                                  double *__restrict__ y, const double *__restrict__ dotv, double *__restrict__ partials) {
     if (gated(gate)) return;
+    double s = 0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        out[i] = (T)r[i] - Az[i];
-        Az[i] = T(0);
+        const double yi = b == 0.0 ? a * (double)x[i] : a * (double)x[i] + b * y[i];
+        y[i] = yi;
+        if (dotv != nullptr) s += dotv[i] * yi;
     }
-}
-
-template <typename T>
-__global__ void k_axpby_to_double(const double *__restrict__ gate, int64_t n, double a, const T *__restrict__ x, double b, double *__restrict__ y) {
-    if (gated(gate)) return;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        y[i] = b == 0.0 ? a * (double)x[i] : a * (double)x[i] + b * y[i];
+    if (dotv != nullptr) {
+        s = block_sum(s);
+        if (threadIdx.x == 0) partials[blockIdx.x] = s;
+    }
 }
 
 __global__ void k_pcg_start(double *scal, double rtol, int max_iterations, double *mirror) {
@@ -590,14 +709,14 @@ __global__ void k_pcg_start(double *scal, double rtol, int max_iterations, doubl
 
 // ====================================================================== launchers
 template <typename T>
-void launch_op_kron(const Dims &d, const T *AB1d, const T *mu, const T *x, T *y, const Exec &e) {
+void launch_op_kron(const Dims &d, const T *AB1d, const T *mu, const T *x, T *E, const Exec &e) {
     const int64_t ncell = (int64_t)d.nx * d.ny * d.nz;
     int cpw = std::is_same<T, double>::value ? e.t.op_cpw64 : e.t.op_cpw32;
     if (cpw != 1 && cpw != 2 && cpw != 4) throw Error(VSR_EINVAL, "op cells per workgroup must be 1, 2 or 4");
     if ((d.p + 1) * (d.p + 1) > 64) cpw = 1;
 #define CALLC(P, C)                                                                                                 \
     hipLaunchKernelGGL((k_op_kron<T, P, C>), dim3((unsigned)((ncell + C - 1) / C)), dim3(round64(C * (P + 1) * (P + 1))), \
-                       0, e.s, e.gate, d, AB1d, mu, x, y)
+                       0, e.s, e.gate, d, AB1d, mu, x, E)
 #define CALL(P)                                                  \
     if constexpr ((P + 1) * (P + 1) <= 64) {                     \
         if (cpw == 4) CALLC(P, 4);                               \
@@ -612,22 +731,27 @@ void launch_op_kron(const Dims &d, const T *AB1d, const T *mu, const T *x, T *y,
 }
 
 template <typename T>
-void launch_op_general(const Dims &d, const T *IDq, const T *Gw, const T *x, T *y, const Exec &e) {
+int launch_op_general(const Dims &d, const T *IDq, const T *Gw, const T *x, T *E, const Exec &e) {
     int64_t ncell = (int64_t)d.nx * d.ny * d.nz;
     const int split = std::is_same<T, double>::value ? e.t.opg_split64 : e.t.opg_split32;
     if (split != 0 && split != 1 && split != 2) throw Error(VSR_EINVAL, "operator split must be 0 (default), 1 or 2");
+    int slots = 1;
 #define CALLS(P, S) \
-    hipLaunchKernelGGL((k_op_general<T, P, S>), dim3((unsigned)(ncell * S)), dim3(opg_threads(P, S)), 0, e.s, e.gate, d, IDq, Gw, x, y)
+    hipLaunchKernelGGL((k_op_general<T, P, S>), dim3((unsigned)(ncell * S)), dim3(opg_threads(P, S)), 0, e.s, e.gate, d, IDq, Gw, x, E)
 #define CALL(P)                                                                                  \
     {                                                                                            \
         const int sp = split ? split : (sizeof(T) == 8 && opg_threads(P, 1) > 512 ? 2 : 1);     \
+        slots = sp;                                                                              \
         if (sp == 2) CALLS(P, 2);                                                                \
         else CALLS(P, 1);                                                                        \
     }
     VSR_P_SWITCH(d.p, CALL)
 #undef CALL
 #undef CALLS
+    return slots;
 }
+
+
 
 void launch_load_vector(const Dims &d, const double *IDq, const double *wdet, const double *f, double *b, const Exec &e) {
     int64_t ncell = (int64_t)d.nx * d.ny * d.nz;
@@ -661,10 +785,29 @@ void launch_axis_pass(const int *start, int bw, const Tout *w, int axis, const i
                        in_dims[0], in_dims[1], in_dims[2], out_dims[0], out_dims[1], out_dims[2], in, out, alpha, beta);
 }
 
+// one workgroup per XB nodes of an x-line
+inline unsigned line_blocks(const Dims &d) { return (unsigned)(((d.Lx + XB - 1) / XB) * (int64_t)d.Ly * d.Lz); }
+
 template <typename T>
 void launch_patch_assemble(const Dims &d, int interior_only, const T *U, T *zF, const Exec &e) {
-    int64_t n = (int64_t)d.Lx * d.Ly * d.Lz;
-    hipLaunchKernelGGL((k_patch_assemble<T>), dim3(grid_for(n)), dim3(256), 0, e.s, e.gate, d, interior_only, U, zF);
+#define CALL(P) hipLaunchKernelGGL((k_patch_assemble<T, P>), dim3(line_blocks(d)), dim3(XB), 0, e.s, e.gate, d, interior_only, U, zF)
+    VSR_P_SWITCH(d.p, CALL)
+#undef CALL
+}
+
+template <typename T>
+void launch_gather(const Dims &d, int slots, const T *E, const double *r, T *out, const Exec &e, const double *dotv,
+                   double *partials) {
+#define CALL(P) \
+    hipLaunchKernelGGL((k_gather<T, P>), dim3(line_blocks(d)), dim3(XB), 0, e.s, e.gate, d, slots, E, r, out, dotv, partials)
+    VSR_P_SWITCH(d.p, CALL)
+#undef CALL
+}
+
+int64_t gather_blocks(const Dims &d) { return line_blocks(d); }
+
+void launch_finalize(int nb, const double *partials, double *scal, int mode, double *mirror, const Exec &e) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_THREADS), 0, e.s, e.gate, nb, partials, scal, mode, mirror);
 }
 
 template <typename T>
@@ -688,32 +831,31 @@ void launch_dot(int64_t n, const double *x, const double *y, double *partials, d
                 const Exec &e) {
     int nb = (int)std::min<int64_t>(RED_BLOCKS, std::max<int64_t>(1, (n + 255) / 256));
     hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(256), 0, e.s, e.gate, n, x, y, partials);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, e.s, e.gate, nb, partials, scal, mode, mirror);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_THREADS), 0, e.s, e.gate, nb, partials, scal, mode, mirror);
 }
 
 void launch_pcg_start(double *scal, double rtol, int max_iterations, double *mirror, const Exec &e) {
     hipLaunchKernelGGL(k_pcg_start, dim3(1), dim3(64), 0, e.s, scal, rtol, max_iterations, mirror);
 }
 
-void launch_pcg_xr(int64_t n, double *x, double *r, const double *p, double *q, double *scal, double *partials, int mode,
+void launch_pcg_xr(int64_t n, double *x, double *r, const double *p, const double *q, double *scal, double *partials, int mode,
                    double *mirror, const Exec &e) {
     int nb = (int)std::min<int64_t>(RED_BLOCKS, std::max<int64_t>(1, (n + 255) / 256));
     hipLaunchKernelGGL(k_pcg_xr, dim3(nb), dim3(256), 0, e.s, e.gate, n, x, r, p, q, scal, partials);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, e.s, e.gate, nb, partials, scal, mode, mirror);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_THREADS), 0, e.s, e.gate, nb, partials, scal, mode, mirror);
 }
 
 void launch_pcg_p(int64_t n, double *p, const double *z, const double *scal, const Exec &e) {
     hipLaunchKernelGGL(k_pcg_p, dim3(grid_for(n)), dim3(256), 0, e.s, e.gate, n, p, z, scal);
 }
 
-template <typename T>
-void launch_residual(int64_t n, const double *r, T *Az, T *out, const Exec &e) {
-    hipLaunchKernelGGL((k_residual<T>), dim3(grid_for(n)), dim3(256), 0, e.s, e.gate, n, r, Az, out);
-}
 
 template <typename T>
-void launch_axpby_to_double(int64_t n, double a, const T *x, double b, double *y, const Exec &e) {
-    hipLaunchKernelGGL((k_axpby_to_double<T>), dim3(grid_for(n)), dim3(256), 0, e.s, e.gate, n, a, x, b, y);
+int launch_axpby_to_double(int64_t n, double a, const T *x, double b, double *y, const Exec &e, const double *dotv,
+                           double *partials) {
+    const unsigned nb = grid_for(n);
+    hipLaunchKernelGGL((k_axpby_to_double<T>), dim3(nb), dim3(256), 0, e.s, e.gate, n, a, x, b, y, dotv, partials);
+    return (int)nb;
 }
 
 
@@ -721,12 +863,14 @@ void launch_axpby_to_double(int64_t n, double a, const T *x, double b, double *y
 // explicit instantiations
 #define INST(T)                                                                                          \
     template void launch_op_kron<T>(const Dims &, const T *, const T *, const T *, T *, const Exec &);    \
-    template void launch_op_general<T>(const Dims &, const T *, const T *, const T *, T *, const Exec &); \
+    template int launch_op_general<T>(const Dims &, const T *, const T *, const T *, T *, const Exec &);  \
     template void launch_patch_assemble<T>(const Dims &, int, const T *, T *, const Exec &);              \
     template void launch_dense_gemv<T>(int, const T *, const T *, T *, T, T, const Exec &);               \
     template void launch_fill<T>(int64_t, T *, T, const Exec &);                                          \
-    template void launch_residual<T>(int64_t, const double *, T *, T *, const Exec &);                    \
-    template void launch_axpby_to_double<T>(int64_t, double, const T *, double, double *, const Exec &);
+    template void launch_gather<T>(const Dims &, int, const T *, const double *, T *, const Exec &, const double *, \
+                                   double *);                                                                    \
+    template int launch_axpby_to_double<T>(int64_t, double, const T *, double, double *, const Exec &, const double *, \
+                                           double *);
 INST(float)
 INST(double)
 template void launch_axis_pass<double, double>(const int *, int, const double *, int, const int *, const int *,

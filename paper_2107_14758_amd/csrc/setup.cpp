@@ -1074,6 +1074,49 @@ AxisTable table_coarse_prolong(int ncell, const OneD &od) {
     return finish(rows, ncell - 1);
 }
 
+// Cell blocks of the same four maps.  Cell e owns the free positions P = e p + 1 .. e p + p
+// (its interior nodes and its high vertex); a = P - e p - 1.
+std::vector<double> transfer_block(int kind, const OneD &od) {
+    const int p = od.p, n1 = p + 1;
+    auto Tm = [&](int i, int j) { return od.T[(size_t)i * n1 + j]; };
+    std::vector<double> M;
+    if (kind == XFER_FDM_RESTRICT) {
+        // inputs P = e p + 1 + s, s < 2p - 1: this cell's interior, its high vertex, the next cell's interior
+        const int K = 2 * p - 1;
+        M.assign((size_t)p * K, 0.0);
+        for (int a = 0; a < p - 1; ++a)
+            for (int s = 0; s < p - 1; ++s) M[(size_t)a * K + s] = Tm(s + 1, a + 1);
+        for (int s = 0; s < p - 1; ++s) M[(size_t)(p - 1) * K + s] = Tm(s + 1, p);
+        M[(size_t)(p - 1) * K + p - 1] = 1.0;
+        for (int s = p; s < K; ++s) M[(size_t)(p - 1) * K + s] = Tm(s - p + 1, 0);
+    } else if (kind == XFER_FDM_PROLONG) {
+        // inputs P = e p + s, s <= p: the cell's closure
+        const int K = p + 1;
+        M.assign((size_t)p * K, 0.0);
+        for (int a = 0; a < p - 1; ++a)
+            for (int s = 0; s < K; ++s) M[(size_t)a * K + s] = Tm(a + 1, s);
+        M[(size_t)(p - 1) * K + p] = 1.0;
+    } else if (kind == XFER_COARSE_RESTRICT) {
+        // the coarse vertex e + 1 from the fine positions P = e p + 1 + s around it
+        const int K = 2 * p - 1;
+        M.assign((size_t)K, 0.0);
+        for (int s = 0; s < p - 1; ++s) M[s] = 0.5 * (1 + od.xi[s + 1]);
+        M[p - 1] = 1.0;
+        for (int s = p; s < K; ++s) M[s] = 0.5 * (1 - od.xi[s - p + 1]);
+    } else if (kind == XFER_COARSE_PROLONG) {
+        // inputs: the coarse vertices e and e + 1
+        M.assign((size_t)p * 2, 0.0);
+        for (int a = 0; a < p - 1; ++a) {
+            M[(size_t)a * 2] = 0.5 * (1 - od.xi[a + 1]);
+            M[(size_t)a * 2 + 1] = 0.5 * (1 + od.xi[a + 1]);
+        }
+        M[(size_t)(p - 1) * 2 + 1] = 1.0;
+    } else {
+        throw Error(VSR_EINVAL, "unknown transfer kind");
+    }
+    return M;
+}
+
 // ============================================================ Sturm bisection
 static int sturm_count(const std::vector<double> &d, const std::vector<double> &e, double x) {
     int cnt = 0;

@@ -99,6 +99,15 @@ AxisTable table_fdm_prolong(int ncell, const OneD &od);    // T
 AxisTable table_coarse_restrict(int ncell, const OneD &od);// P^T
 AxisTable table_coarse_prolong(int ncell, const OneD &od); // P
 
+// Cell block of a lattice transfer (row-major OA x K) for launch_transfer: along an axis,
+// cell e maps inputs e*in_step + in_off + s to outputs e*out_step + a.
+//   XFER_FDM_RESTRICT   T^T: OA = p, K = 2p-1 (in_step p, in_off 0, out_step p)
+//   XFER_FDM_PROLONG    T:   OA = p, K = p+1  (p, -1, p)
+//   XFER_COARSE_RESTRICT P^T: OA = 1, K = 2p-1 (p, 0, 1)
+//   XFER_COARSE_PROLONG P:   OA = p, K = 2    (1, -1, p)
+enum { XFER_FDM_RESTRICT = 0, XFER_FDM_PROLONG = 1, XFER_COARSE_RESTRICT = 2, XFER_COARSE_PROLONG = 3 };
+std::vector<double> transfer_block(int kind, const OneD &od);
+
 // Symmetric tridiagonal extreme eigenvalues by Sturm bisection.
 void tridiag_extremes(const std::vector<double> &d, const std::vector<double> &e, double &lmin, double &lmax);
 

@@ -49,6 +49,9 @@ CASES = [
     ("jit_3x3x2_p3_kappa", (3, 3, 2), 3, 0.15, True),
     ("jit_2x3x3_p5_kappa", (2, 3, 3), 5, 0.15, True),
     ("jit_2x2x2_p7", (2, 2, 2), 7, 0.2, False),
+    # the general operator takes its z-slabs in several chunks from p = 8 (FP64) and p = 11 (FP32)
+    ("jit_2x2x2_p8_kappa", (2, 2, 2), 8, 0.15, True),
+    ("jit_2x2x2_p11_kappa", (2, 2, 2), 11, 0.15, True),
 ]
 
 
