@@ -79,7 +79,7 @@ typedef struct {
     double omega;            /* > 0: use this damping instead of the Lanczos estimate */
     void *stream;            /* hipStream_t; NULL => default stream */
     int32_t autotune;        /* 1: pick launch shapes (cells or workgroups per cell of the
-                                operator, lattice-pass block size, patch-panel unroll) by timing the
+                                operator, patch-panel unroll and workgroup size) by timing the
                                 candidates on this problem at setup, once per (GPU
                                 architecture, p, precision, operator kind) per process and
                                 per cache file; 0: fixed defaults.  Shapes never change the
@@ -208,18 +208,16 @@ vsr_status vsr_mlp_train(float *params_dev, float *adam_m_dev, float *adam_v_dev
 vsr_status vsr_surrogate_scalings(int64_t ncell, const double *corners, const double *kappa, int32_t p,
                                   const float *params_dev, int32_t bf16, double *mu_out, int32_t *learned);
 
-/* Launch shapes in use: shapes[0..7] = Cartesian-operator cells per workgroup (FP64,
- * FP32), lattice-pass block size, patch-panel unroll, general-operator workgroups per
- * cell (FP64, FP32; 0 = chosen by size: 2 where one workgroup's FP64 column state would
- * not fit in registers, else 1), lattice passes with whole lines staged in LDS (1) or
- * streamed through the caches (0), threads per patch workgroup. */
-vsr_status vsr_get_tuning(const vsr_problem *prob, int32_t shapes[8]);
+/* Launch shapes in use: shapes[0..5] = Cartesian-operator cells per workgroup (FP64,
+ * FP32), patch-panel unroll, general-operator workgroups per cell (FP64, FP32; 0 = chosen
+ * by size: 2 where one workgroup's FP64 column state would not fit in registers, else 1),
+ * threads per patch workgroup. */
+vsr_status vsr_get_tuning(const vsr_problem *prob, int32_t shapes[6]);
 
 /* Set the launch shapes (same order; cells per workgroup in {1, 2, 4}, used only for
- * Cartesian meshes with p <= 7; block a multiple of 64 in [64, 1024]; unroll in
- * {4, 8, 16}; workgroups per cell in {0, 1, 2}; staged passes 0 or 1; patch threads 256 or
- * 512).  VSR_EINVAL for any other value. */
-vsr_status vsr_set_tuning(vsr_problem *prob, const int32_t shapes[8]);
+ * Cartesian meshes with p <= 7; unroll in {4, 8, 16}; workgroups per cell in {0, 1, 2};
+ * patch threads 256 or 512).  VSR_EINVAL for any other value. */
+vsr_status vsr_set_tuning(vsr_problem *prob, const int32_t shapes[6]);
 
 void vsr_destroy(vsr_problem *prob);
 

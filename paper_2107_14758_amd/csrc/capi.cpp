@@ -49,15 +49,6 @@ double now_s() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-// A 1D transfer matrix as a padded band: row o covers inputs start[o] .. start[o] + bw.
-struct Table {
-    int *start = nullptr;
-    int bw = 1;
-    double *w64 = nullptr;
-    float *w32 = nullptr;
-    int n_out = 0, n_in = 0;
-};
-
 }  // namespace
 
 struct vsr_problem {
@@ -80,15 +71,14 @@ struct vsr_problem {
     PatchArgs pa{};
     int64_t factor_entries = 0;       // structurally nonzero entries over all patches
     double bytes_patch_launch = 0;    // algorithmic bytes of one patch-solve launch (all stars)
-    Table tab[4][3];                  // [TT, T, PT, P][axis]
     double *xm64[4] = {};             // cell blocks of T^T, T, P^T, P (transfer_block)
     float *xm32[4] = {};
     int cdim[3] = {0, 0, 0};
     int nc = 0;
     void *A0inv = nullptr;
     // work buffers (cycle precision unless noted)
-    void *t1 = nullptr, *t2 = nullptr, *rF = nullptr, *zF = nullptr, *U = nullptr;
-    void *c1 = nullptr, *c2 = nullptr, *c3 = nullptr, *c4 = nullptr;
+    void *rF = nullptr, *zF = nullptr, *U = nullptr;
+    void *c3 = nullptr, *c4 = nullptr;    // coarse right-hand side and solution
     void *z1 = nullptr, *res = nullptr;   // cycle iterate and cycle residual
     double *E64 = nullptr;                // element vectors of the operator (2 slots per cell)
     void *E32 = nullptr;
@@ -180,12 +170,6 @@ void op_residual(vsr_problem *P, const double *r, const T *x, T *out) {
     const int slots = op_cells<T>(P, x, elem<T>(P));
     launch_gather<T>(P->d, slots, elem<T>(P), r, out, P->ex());
     VSR_HIP(hipGetLastError());
-}
-
-template <typename T>
-const T *wt(const Table &t) {
-    if constexpr (std::is_same<T, double>::value) return t.w64;
-    else return t.w32;
 }
 
 template <typename T>
@@ -401,10 +385,9 @@ bool tune_from_file(const char *path, const std::string &key, Tuning &t) {
         if (line.compare(0, key.size(), key) != 0 || line.size() <= key.size() || line[key.size()] != ' ') continue;
         Tuning c;
         if (std::sscanf(line.c_str() + key.size(),
-                        " cpw64=%d cpw32=%d axis_block=%d patch_unroll=%d split64=%d split32=%d axis_tiled=%d"
-                        " patch_threads=%d",
-                        &c.op_cpw64, &c.op_cpw32, &c.axis_block, &c.patch_unroll, &c.opg_split64, &c.opg_split32,
-                        &c.axis_tiled, &c.patch_threads) == 8) {
+                        " cpw64=%d cpw32=%d patch_unroll=%d split64=%d split32=%d patch_threads=%d",
+                        &c.op_cpw64, &c.op_cpw32, &c.patch_unroll, &c.opg_split64, &c.opg_split32,
+                        &c.patch_threads) == 6) {
             t = c;
             found = true;
         }
@@ -476,32 +459,6 @@ void autotune(vsr_problem *P) {
             pick(P->tune.opg_split32, {1, 2}, [&] { op_apply<float>(P, (const float *)P->z1, (float *)P->res); });
         }
     }
-    const int L[3] = {P->d.Lx, P->d.Ly, P->d.Lz};
-    auto passes = [&](auto zero) {
-        using T = decltype(zero);
-        const Table *TT = P->tab[0], *Tp = P->tab[1];
-        T *a = (T *)P->t1, *b = (T *)P->t2;
-        for (int ax = 0; ax < 3; ++ax) {
-            launch_axis_pass<T, T>(TT[ax].start, TT[ax].bw, wt<T>(TT[ax]), ax, L, L, a, b, T(1), T(0), P->ex());
-            launch_axis_pass<T, T>(Tp[ax].start, Tp[ax].bw, wt<T>(Tp[ax]), ax, L, L, b, a, T(1), T(0), P->ex());
-        }
-    };
-    // lattice passes: tiled or streamed, jointly with the block size
-    auto pick_passes = [&](auto &&fn) {
-        double best = 1e300;
-        Tuning keep = P->tune;
-        for (int tiled : {0, 1})
-            for (int bs : {64, 128, 256, 512, 1024}) {
-                P->tune.axis_tiled = tiled;
-                P->tune.axis_block = bs;
-                double ms = time_ms(P, fn);
-                if (ms < best) {
-                    best = ms;
-                    keep = P->tune;
-                }
-            }
-        P->tune = keep;
-    };
     // patch solves: loads in flight per thread jointly with the workgroup size
     auto pick_patch = [&](auto &&fn) {
         double best = 1e300;
@@ -525,14 +482,10 @@ void autotune(vsr_problem *P) {
                             (const T *)P->rF, (T *)P->U, P->ex());
     };
     if (P->fp32) {
-        launch_fill<float>(P->n, (float *)P->t1, 1.f, P->ex());
         launch_fill<float>(P->n, (float *)P->rF, 1.f, P->ex());
-        pick_passes([&] { passes(0.f); });
         if (P->n_int + P->n_bnd > 0) pick_patch([&] { patch(0.f); });
     } else {
-        launch_fill<double>(P->n, (double *)P->t1, 1.0, P->ex());
         launch_fill<double>(P->n, (double *)P->rF, 1.0, P->ex());
-        pick_passes([&] { passes(0.0); });
         if (P->n_int + P->n_bnd > 0) pick_patch([&] { patch(0.0); });
     }
     // the patch boxes of absent stars must read as zero in the assembly
@@ -544,47 +497,10 @@ void autotune(vsr_problem *P) {
     g_tune_cache[key] = P->tune;
     if (P->opt.tune_cache) {
         std::ofstream f(P->opt.tune_cache, std::ios::app);
-        f << key << " cpw64=" << P->tune.op_cpw64 << " cpw32=" << P->tune.op_cpw32 << " axis_block=" << P->tune.axis_block
+        f << key << " cpw64=" << P->tune.op_cpw64 << " cpw32=" << P->tune.op_cpw32
           << " patch_unroll=" << P->tune.patch_unroll << " split64=" << P->tune.opg_split64
-          << " split32=" << P->tune.opg_split32 << " axis_tiled=" << P->tune.axis_tiled
-          << " patch_threads=" << P->tune.patch_threads << "\n";
+          << " split32=" << P->tune.opg_split32 << " patch_threads=" << P->tune.patch_threads << "\n";
     }
-}
-
-// Rows of a 1D transfer matrix touch one contiguous window of inputs; store them as a
-// band of the widest window, each start clamped so the window stays inside the input.
-Table make_table(vsr_problem *P, const AxisTable &t) {
-    Table r;
-    r.n_out = t.n_out;
-    r.n_in = t.n_in;
-    int bw = 1;
-    for (int o = 0; o < t.n_out; ++o) {
-        int lo = INT32_MAX, hi = -1;
-        for (int k = t.rowptr[o]; k < t.rowptr[o + 1]; ++k) {
-            lo = std::min(lo, t.col[k]);
-            hi = std::max(hi, t.col[k]);
-        }
-        if (hi >= lo) bw = std::max(bw, hi - lo + 1);
-    }
-    bw = std::max(1, std::min(bw, t.n_in));
-    std::vector<int> start(std::max(t.n_out, 1), 0);
-    std::vector<double> w((size_t)std::max(t.n_out, 1) * bw, 0.0);
-    for (int o = 0; o < t.n_out; ++o) {
-        int lo = INT32_MAX;
-        for (int k = t.rowptr[o]; k < t.rowptr[o + 1]; ++k) lo = std::min(lo, t.col[k]);
-        int s0 = lo == INT32_MAX ? 0 : std::max(0, std::min(lo, t.n_in - bw));
-        start[o] = s0;
-        for (int k = t.rowptr[o]; k < t.rowptr[o + 1]; ++k) {
-            int j = t.col[k] - s0;
-            if (j < 0 || j >= bw) throw Error(VSR_EINVAL, "transfer table row does not fit its band");
-            w[(size_t)o * bw + j] += t.w[k];
-        }
-    }
-    r.bw = bw;
-    r.start = P->upload(start);
-    r.w64 = P->upload(w);
-    r.w32 = P->upload_as<float>(w);
-    return r;
 }
 
 template <typename T>
@@ -911,15 +827,9 @@ vsr_status vsr_setup(const vsr_mesh *mesh, int32_t p, const vsr_coefficients *co
                                                2.0 * (double)bnd_nnz + 2.0 * (double)bnd_box);
         if (P->fp32) upload_patch_data<float>(P.get(), S, mu_sur);
         else upload_patch_data<double>(P.get(), S, mu_sur);
-        // transfer tables
-        int nc3[3] = {nx, ny, nz};
-        for (int ax = 0; ax < 3; ++ax) {
-            P->tab[0][ax] = make_table(P.get(), table_fdm_restrict(nc3[ax], P->od));
-            P->tab[1][ax] = make_table(P.get(), table_fdm_prolong(nc3[ax], P->od));
-            P->tab[2][ax] = make_table(P.get(), table_coarse_restrict(nc3[ax], P->od));
-            P->tab[3][ax] = make_table(P.get(), table_coarse_prolong(nc3[ax], P->od));
-            P->cdim[ax] = nc3[ax] - 1;
-        }
+        // lattice transfers: the cell blocks of T^T, T, P^T, P
+        const int nc3[3] = {nx, ny, nz};
+        for (int ax = 0; ax < 3; ++ax) P->cdim[ax] = nc3[ax] - 1;
         for (int k = 0; k < 4; ++k) {
             const std::vector<double> M = transfer_block(k, P->od);
             P->xm64[k] = P->upload(M);
@@ -936,8 +846,6 @@ vsr_status vsr_setup(const vsr_mesh *mesh, int32_t p, const vsr_coefficients *co
             return P->fp32 ? (void *)P->dalloc<float>(cnt) : (void *)P->dalloc<double>(cnt);
         };
         (void)es;
-        P->t1 = alloc_t(P->n);
-        P->t2 = alloc_t(P->n);
         P->rF = alloc_t(P->n);
         P->zF = alloc_t(P->n);
         P->U = alloc_t(nv * w3);
@@ -948,8 +856,6 @@ vsr_status vsr_setup(const vsr_mesh *mesh, int32_t p, const vsr_coefficients *co
             P->E64 = P->dalloc<double>(eb);
             if (P->fp32) P->E32 = P->dalloc<float>(eb);
         }
-        P->c1 = alloc_t((int64_t)P->cdim[0] * P->d.Ly * P->d.Lz);
-        P->c2 = alloc_t((int64_t)P->cdim[0] * P->cdim[1] * P->d.Lz);
         P->c3 = alloc_t(P->nc);
         P->c4 = alloc_t(P->nc);
         P->vp = P->dalloc<double>(P->n);
@@ -1103,33 +1009,36 @@ vsr_status vsr_factor_info(const vsr_problem *P, int64_t *num_patches, int64_t *
 
 void vsr_destroy(vsr_problem *P) { destroy_problem(P); }
 
-vsr_status vsr_get_tuning(const vsr_problem *P, int32_t shapes[8]) {
+vsr_status vsr_get_tuning(const vsr_problem *P, int32_t shapes[6]) {
     return guarded([&] {
         if (!P || !shapes) throw Error(VSR_EINVAL, "NULL argument");
         shapes[0] = P->tune.op_cpw64;
         shapes[1] = P->tune.op_cpw32;
-        shapes[2] = P->tune.axis_block;
-        shapes[3] = P->tune.patch_unroll;
-        shapes[4] = P->tune.opg_split64;
-        shapes[5] = P->tune.opg_split32;
-        shapes[6] = P->tune.axis_tiled;
-        shapes[7] = P->tune.patch_threads;
+        shapes[2] = P->tune.patch_unroll;
+        shapes[3] = P->tune.opg_split64;
+        shapes[4] = P->tune.opg_split32;
+        shapes[5] = P->tune.patch_threads;
     });
 }
 
-vsr_status vsr_set_tuning(vsr_problem *P, const int32_t shapes[8]) {
+vsr_status vsr_set_tuning(vsr_problem *P, const int32_t shapes[6]) {
     return guarded([&] {
         if (!P || !shapes) throw Error(VSR_EINVAL, "NULL argument");
         auto cpw_ok = [](int c) { return c == 1 || c == 2 || c == 4; };
         if (!cpw_ok(shapes[0]) || !cpw_ok(shapes[1])) throw Error(VSR_EINVAL, "operator cells per workgroup must be 1, 2 or 4");
-        if (shapes[2] < 64 || shapes[2] > 1024 || shapes[2] % 64) throw Error(VSR_EINVAL, "block must be a multiple of 64 in [64, 1024]");
-        if (shapes[3] != 4 && shapes[3] != 8 && shapes[3] != 16) throw Error(VSR_EINVAL, "unroll must be 4, 8 or 16");
-        for (int i = 4; i < 6; ++i)
+        if (shapes[2] != 4 && shapes[2] != 8 && shapes[2] != 16) throw Error(VSR_EINVAL, "unroll must be 4, 8 or 16");
+        for (int i = 3; i < 5; ++i)
             if (shapes[i] < 0 || shapes[i] > 2) throw Error(VSR_EINVAL, "workgroups per cell must be 0, 1 or 2");
-        if (shapes[6] != 0 && shapes[6] != 1) throw Error(VSR_EINVAL, "tiled lattice passes must be 0 or 1");
-        if (shapes[7] != 256 && shapes[7] != 512) throw Error(VSR_EINVAL, "patch threads must be 256 or 512");
+        if (shapes[5] != 256 && shapes[5] != 512) throw Error(VSR_EINVAL, "patch threads must be 256 or 512");
         VSR_HIP(hipStreamSynchronize(P->stream));
-        P->tune = Tuning{shapes[0], shapes[1], shapes[2], shapes[3], shapes[4], shapes[5], shapes[6], shapes[7]};
+        Tuning t;
+        t.op_cpw64 = shapes[0];
+        t.op_cpw32 = shapes[1];
+        t.patch_unroll = shapes[2];
+        t.opg_split64 = shapes[3];
+        t.opg_split32 = shapes[4];
+        t.patch_threads = shapes[5];
+        P->tune = t;
         delete P->self;   // its recorded iteration holds the old shapes
         P->self = nullptr;
     });

@@ -18,11 +18,9 @@ struct Dims {
 struct Tuning {
     int op_cpw64 = 1;       // cells per workgroup of the Cartesian operator kernel, FP64
     int op_cpw32 = 1;       // same, FP32 (both 1, 2 or 4; above 1 only for p <= 7)
-    int axis_block = 256;   // threads per block of the 1D lattice passes (64..1024)
     int patch_unroll = 8;   // column loads in flight per thread in the patch panels (4, 8, 16)
     int opg_split64 = 0;    // workgroups per cell of the general operator, FP64 (1, 2; 0: by size)
     int opg_split32 = 0;    // same, FP32
-    int axis_tiled = 0;     // lattice passes with whole lines staged in LDS (1) or streamed (0)
     int patch_threads = 256;   // threads per patch workgroup (256 or 512: more panel loads in flight)
 };
 
@@ -56,12 +54,6 @@ void launch_finalize(int nb, const double *partials, double *scal, int mode, dou
 // b += sum_K R_K^T (I x I x I)^T (wdet .* f)
 void launch_load_vector(const Dims &d, const double *IDq, const double *wdet, const double *f, double *b,
                         const Exec &e);
-
-// One 1D lattice pass: out = alpha * (banded 1D matrix along `axis`) in + beta * out; output o
-// reads in[start[o] + j], j < bw, along the axis with weight w[o * bw + j].
-template <typename Tin, typename Tout>
-void launch_axis_pass(const int *start, int bw, const Tout *w, int axis, const int in_dims[3],
-                      const int out_dims[3], const Tin *in, Tout *out, Tout alpha, Tout beta, const Exec &e);
 
 // Lattice transfers, each in one launch (M x M x M with a cell-blocked 1D map M):
 // FDM restriction r~ = T^T r and prolongation z = T z~ on the free fine lattice (Sec. 2.4);

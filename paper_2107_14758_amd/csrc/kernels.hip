@@ -1,6 +1,6 @@
-// HIP kernels for gfx950 (CDNA4, wave64): operator, load vector, lattice passes, patch
-// assembly, dense coarse solve and the PCG vector kernels.  The patch solves live in
-// patch_kernels.h.
+// HIP kernels for gfx950 (CDNA4, wave64): operator and element-vector gather, load vector,
+// patch assembly, dense coarse solve and the PCG vector kernels.  The patch solves live in
+// patch_kernels.h, the lattice transfers in transfer.hip.
 //
 // Method references: Brubeck & Farrell, "A scalable and robust vertex-star relaxation for
 // high-order FEM", Sec. 2.
@@ -401,101 +401,7 @@ __global__ void __launch_bounds__(1024) k_load_vector(const double *__restrict__
     }
 }
 
-// ====================================================================== lattice passes
-// out = alpha * M_axis in + beta * out for a 1D matrix M applied along `axis` (the GLL <->
-// FDM basis change of Sec. 2.4 and the Q1 transfers of Sec. 2.5).  Output o along the axis
-// reads the window in[start[o] .. start[o] + bw) along that axis with dense weights
-// w[o * bw + j] (zero where M has no entry): a fixed trip count, wave-uniform rows and
-// weights for the y and z passes, and coalesced loads along x.
-// The same pass with the lines staged in LDS: a workgroup takes LT whole lines along `axis`
-// (consecutive line indices), reads each input line once from HBM, coalesced (along x for
-// the x pass, across neighbouring lines for the y and z passes), forms the band products
-// from LDS and writes its outputs coalesced (the x pass through an LDS output tile).
-// Line l enumerates the two other coordinates, first one fastest.
-template <typename Tin, typename Tout>
-__global__ void k_axis_tile(const double *__restrict__ gate, const int *__restrict__ start, const Tout *__restrict__ w,
-                            int bw, int axis, int ix, int iy, int iz, int ox, int oy, int oz, int LT,
-                            const Tin *__restrict__ in, Tout *__restrict__ out, Tout alpha, Tout beta) {
-    if (gated(gate)) return;
-    extern __shared__ unsigned char smem_raw[];
-    Tout *tile = reinterpret_cast<Tout *>(smem_raw);
-    const int lin = axis == 0 ? ix : (axis == 1 ? iy : iz);
-    const int lout = axis == 0 ? ox : (axis == 1 ? oy : oz);
-    const int d0 = axis == 0 ? iy : ix, d1 = axis == 2 ? iy : iz;   // the two other extents (same in and out)
-    const int64_t nlines = (int64_t)d0 * d1;
-    const int ld = LT + 1;
-    Tout *otile = tile + (int64_t)lin * ld;   // x pass only
-    const int tid = threadIdx.x, nt = blockDim.x;
-    const int64_t l0 = (int64_t)blockIdx.x * LT;
-    const int nl = (int)min<int64_t>(LT, nlines - l0);
-    // element (line l, k along the axis) of an array with axis extent len
-    auto addr = [&](int64_t l, int k, int len) -> int64_t {
-        const int64_t a = l % d0, b = l / d0;
-        if (axis == 0) return (b * d0 + a) * len + k;                 // (y, z) = (a, b)
-        if (axis == 1) return (b * len + k) * (int64_t)ix + a;        // (x, z) = (a, b)
-        return ((int64_t)k * iy + b) * ix + a;                        // (x, y) = (a, b)
-    };
-    if (axis == 0) {
-        for (int t = tid; t < nl * lin; t += nt) {
-            const int l = t / lin, k = t % lin;
-            tile[k * ld + l] = (Tout)in[addr(l0 + l, k, lin)];
-        }
-    } else {
-        for (int t = tid; t < nl * lin; t += nt) {
-            const int l = t % nl, k = t / nl;
-            tile[k * ld + l] = (Tout)in[addr(l0 + l, k, lin)];
-        }
-    }
-    __syncthreads();
-    for (int t = tid; t < nl * lout; t += nt) {
-        const int l = t % nl, o = t / nl;
-        const int s0 = start[o];
-        const Tout *wr = w + (int64_t)o * bw;
-        const Tout *src = tile + (int64_t)s0 * ld + l;
-        Tout s = 0;
-#pragma unroll 4
-        for (int j = 0; j < bw; ++j) s += wr[j] * src[j * ld];
-        if (axis == 0) {
-            otile[o * ld + l] = s;
-        } else {
-            const int64_t q = addr(l0 + l, o, lout);
-            out[q] = beta == Tout(0) ? alpha * s : alpha * s + beta * out[q];
-        }
-    }
-    if (axis == 0) {
-        __syncthreads();
-        for (int t = tid; t < nl * lout; t += nt) {
-            const int l = t / lout, o = t % lout;
-            const int64_t q = addr(l0 + l, o, lout);
-            const Tout s = otile[o * ld + l];
-            out[q] = beta == Tout(0) ? alpha * s : alpha * s + beta * out[q];
-        }
-    }
-}
-
-template <typename Tin, typename Tout>
-__global__ void k_axis_pass(const double *__restrict__ gate, const int *__restrict__ start, const Tout *__restrict__ w,
-                            int bw, int axis, int ix, int iy, int iz, int ox, int oy, int oz,
-                            const Tin *__restrict__ in, Tout *__restrict__ out, Tout alpha, Tout beta) {
-    if (gated(gate)) return;
-    const int64_t total = (int64_t)ox * oy * oz;
-    const int64_t stride = axis == 0 ? 1 : (axis == 1 ? (int64_t)ix : (int64_t)ix * iy);
-    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
-         idx += (int64_t)gridDim.x * blockDim.x) {
-        const int cx = (int)(idx % ox);
-        const int cy = (int)((idx / ox) % oy);
-        const int cz = (int)(idx / ((int64_t)ox * oy));
-        const int o = axis == 0 ? cx : (axis == 1 ? cy : cz);
-        const int s0 = start[o];
-        const Tin *src = in + ((int64_t)(axis == 2 ? s0 : cz) * iy + (axis == 1 ? s0 : cy)) * ix + (axis == 0 ? s0 : cx);
-        const Tout *wr = w + (int64_t)o * bw;
-        Tout s = 0;
-#pragma unroll 4
-        for (int j = 0; j < bw; ++j) s += wr[j] * (Tout)src[j * stride];
-        out[idx] = beta == Tout(0) ? alpha * s : alpha * s + beta * out[idx];
-    }
-}
-
+// ====================================================================== patch assembly
 // Additive Schwarz sum z_F = sum_j Rbar_j^T u_j (Sec. 2.5): each free lattice point sums
 // the boxes of the (up to 8) stars that contain it.
 template <typename T, int P>
@@ -761,29 +667,6 @@ void launch_load_vector(const Dims &d, const double *IDq, const double *wdet, co
 #undef CALL
 }
 
-template <typename Tin, typename Tout>
-void launch_axis_pass(const int *start, int bw, const Tout *w, int axis, const int in_dims[3], const int out_dims[3],
-                      const Tin *in, Tout *out, Tout alpha, Tout beta, const Exec &e) {
-    int64_t n = (int64_t)out_dims[0] * out_dims[1] * out_dims[2];
-    if (n == 0) return;
-    const int bs = e.t.axis_block;
-    if (bs < 64 || bs > 1024 || bs % 64 != 0) throw Error(VSR_EINVAL, "axis block must be a multiple of 64 in [64, 1024]");
-    if (e.t.axis_tiled) {
-        const int LT = sizeof(Tout) == 4 ? 32 : 16;
-        const int lin = in_dims[axis], lout = out_dims[axis];
-        const size_t lds = ((size_t)lin + (axis == 0 ? (size_t)lout : 0)) * (LT + 1) * sizeof(Tout);
-        if (lds <= 64 * 1024) {
-            const int64_t nlines = n / lout;
-            const unsigned blocks = (unsigned)((nlines + LT - 1) / LT);
-            hipLaunchKernelGGL((k_axis_tile<Tin, Tout>), dim3(blocks), dim3(bs), lds, e.s, e.gate, start, w, bw, axis,
-                               in_dims[0], in_dims[1], in_dims[2], out_dims[0], out_dims[1], out_dims[2], LT, in, out,
-                               alpha, beta);
-            return;
-        }
-    }
-    hipLaunchKernelGGL((k_axis_pass<Tin, Tout>), dim3(grid_for(n, bs)), dim3(bs), 0, e.s, e.gate, start, w, bw, axis,
-                       in_dims[0], in_dims[1], in_dims[2], out_dims[0], out_dims[1], out_dims[2], in, out, alpha, beta);
-}
 
 // one workgroup per XB nodes of an x-line
 inline unsigned line_blocks(const Dims &d) { return (unsigned)(((d.Lx + XB - 1) / XB) * (int64_t)d.Ly * d.Lz); }
@@ -873,12 +756,6 @@ int launch_axpby_to_double(int64_t n, double a, const T *x, double b, double *y,
                                            double *);
 INST(float)
 INST(double)
-template void launch_axis_pass<double, double>(const int *, int, const double *, int, const int *, const int *,
-                                               const double *, double *, double, double, const Exec &);
-template void launch_axis_pass<float, float>(const int *, int, const float *, int, const int *, const int *,
-                                             const float *, float *, float, float, const Exec &);
-template void launch_axis_pass<double, float>(const int *, int, const float *, int, const int *, const int *,
-                                              const double *, float *, float, float, const Exec &);
 template void launch_cast<double, float>(int64_t, const double *, float *, const Exec &);
 template void launch_cast<float, double>(int64_t, const float *, double *, const Exec &);
 template void launch_cast<double, double>(int64_t, const double *, double *, const Exec &);

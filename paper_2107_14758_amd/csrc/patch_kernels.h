@@ -167,9 +167,10 @@ __device__ __forceinline__ Vec4<double> load4<double>(const double *p) {
 // y[r] -= sum_c M[c * ld + r] x[c] for r < nrows (ld multiple of 4, M 16-byte aligned);
 // x, y in LDS.  Work split over (row quads) x (column chunks), accumulated with LDS atomics;
 // each thread keeps U column loads in flight.
-template <typename T, int U = 8>
+template <typename T, int U, int NTH>
 __device__ void panel_fwd(const T *__restrict__ M, int ld, int nrows, int ncols, const T *x, T *y) {
-    const int tid = threadIdx.x, nt = blockDim.x;
+    const int tid = threadIdx.x;
+    constexpr int nt = NTH;
     const int nq = (nrows + 3) / 4;
     if (nq == 0 || ncols == 0) return;
     int nch = max(1, min((ncols + U - 1) / U, nt / nq));
@@ -212,9 +213,10 @@ __device__ void panel_fwd(const T *__restrict__ M, int ld, int nrows, int ncols,
 
 // y[c] -= sum_r M[c * ld + r] x[r] for c < ncols: a thread streams one (column, row chunk)
 // with U loads in flight; chunks of one column meet in an LDS atomic.
-template <typename T, int U = 8>
+template <typename T, int U, int NTH>
 __device__ void panel_bwd(const T *__restrict__ M, int ld, int nrows, int ncols, const T *x, T *y) {
-    const int tid = threadIdx.x, nt = blockDim.x;
+    const int tid = threadIdx.x;
+    constexpr int nt = NTH;
     const int nq = (nrows + 3) / 4;
     if (nq == 0 || ncols == 0) return;
     int nrc = max(1, min((nq + U - 1) / U, nt / ncols));
@@ -279,7 +281,7 @@ __device__ __forceinline__ int64_t tile_offset(int64_t off_Ltop, int NT, int J) 
 // diagonal interior block, then the nested-dissection Cholesky factor of the interface
 // Schur complement (leaves, level-1 separator slices, dense top plane), forward and
 // backward, then interior back-substitution.  Output: the patch box of (2m+1)^3 values.
-template <typename T, int P, int UNR>
+template <typename T, int P, int UNR, int NTH>
 __device__ __forceinline__ void patch_interior(const int pid, Dims d, PatchArgs A, const int *__restrict__ verts,
                                                const int *__restrict__ fidx, const T *__restrict__ factor, const T *__restrict__ mu,
                                                const T *__restrict__ lam, const T *__restrict__ afc,
@@ -290,7 +292,8 @@ __device__ __forceinline__ void patch_interior(const int pid, Dims d, PatchArgs 
     __shared__ T smu[24], slam[M], safc[2 * M];
     __shared__ T tl[64 * 65 / 2];
     __shared__ T red[512];   // one 64-row partial per wavefront (at most 8)
-    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
+    constexpr int nt = NTH, nw = NTH / 64;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int kfull[3] = {AX_FULL, AX_FULL, AX_FULL};
     const int vx = verts[3 * pid], vy = verts[3 * pid + 1], vz = verts[3 * pid + 2];
     stage_coefficients<T, M>(d, vx, vy, vz, kfull, mu, lam, afc, smu, slam, safc);
@@ -359,7 +362,7 @@ __device__ __forceinline__ void patch_interior(const int pid, Dims d, PatchArgs 
     stage_tile(0);
     phase_sync();
     // level-1 panels update the top plane
-    panel_fwd<T, UNR>(F + A.off_P, A.top_pad, NT, NS, g + NL, gt);
+    panel_fwd<T, UNR, NTH>(F + A.off_P, A.top_pad, NT, NS, g + NL, gt);
     phase_sync();
     // dense top plane, 64-column tiles: wave 0 solves the diagonal block from LDS, then all
     // waves update the rows below while the next diagonal block is staged
@@ -373,7 +376,7 @@ __device__ __forceinline__ void patch_interior(const int pid, Dims d, PatchArgs 
         phase_sync();
         const T *D = F + tile_offset(A.off_Ltop, NT, J);
         const int rows = NT - c0 - nb;
-        panel_fwd<T, UNR>(D + 64 * 65 / 2, (rows + 3) / 4 * 4, rows, nb, gt + c0, gt + c0 + nb);
+        panel_fwd<T, UNR, NTH>(D + 64 * 65 / 2, (rows + 3) / 4 * 4, rows, nb, gt + c0, gt + c0 + nb);
         if (J + 1 < NTILE) stage_tile(J + 1);
         phase_sync();
     }
@@ -388,12 +391,12 @@ __device__ __forceinline__ void patch_interior(const int pid, Dims d, PatchArgs 
         if (J > 0) {
             const int cp = 64 * (J - 1), nbp = 64, rows = NT - cp - nbp;
             const T *Dp = F + tile_offset(A.off_Ltop, NT, J - 1);
-            panel_bwd<T, UNR>(Dp + 64 * 65 / 2, (rows + 3) / 4 * 4, rows, nbp, gt + cp + nbp, gt + cp);
+            panel_bwd<T, UNR, NTH>(Dp + 64 * 65 / 2, (rows + 3) / 4 * 4, rows, nbp, gt + cp + nbp, gt + cp);
             stage_tile(J - 1);
         }
         phase_sync();
     }
-    panel_bwd<T, UNR>(F + A.off_P, A.top_pad, NT, NS, gt, g + NL);
+    panel_bwd<T, UNR, NTH>(F + A.off_P, A.top_pad, NT, NS, gt, g + NL);
     phase_sync();
     for (int s = wv; s < 2 * M; s += nw) {
         const T x = tri_inv_t_mv<T>(F + A.off_Lsep + (int64_t)s * (W * (W + 1) / 2), W, 0, W, W, lane, g + NL + s * W);
@@ -444,7 +447,7 @@ __device__ __forceinline__ void patch_interior(const int pid, Dims d, PatchArgs 
 // Boundary-vertex patches: their stars lose cells, and the interface Schur complement
 // splits into independent dense slices (2 full axes: crosses of 4m+1 DOFs; 1 full axis:
 // single DOFs).  desc: vx, vy, vz, kind_x, kind_y, kind_z, nslices, slice size.
-template <typename T, int P>
+template <typename T, int P, int NTH>
 __device__ __forceinline__ void patch_boundary(const int pid, Dims d, const int *__restrict__ desc,
                                                const int64_t *__restrict__ off, const T *__restrict__ factor,
                                                const T *__restrict__ mu, const T *__restrict__ lam,
@@ -452,7 +455,8 @@ __device__ __forceinline__ void patch_boundary(const int pid, Dims d, const int 
     constexpr int M = P - 1, W = 2 * M + 1, MAXN = 4 * M + 1;
     __shared__ T g[M * MAXN > M * M ? M * MAXN : M * M];
     __shared__ T smu[24], slam[M], safc[2 * M];
-    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
+    constexpr int nt = NTH, nw = NTH / 64;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int *ds = desc + 8 * pid;
     const int kind[3] = {ds[3], ds[4], ds[5]};
     stage_coefficients<T, M>(d, ds[0], ds[1], ds[2], kind, mu, lam, afc, smu, slam, safc);
@@ -546,8 +550,8 @@ __global__ void __launch_bounds__(NTH) k_patch_all(const double *__restrict__ ga
                                                    const T *__restrict__ lam, const T *__restrict__ afc,
                                                    const T *__restrict__ rF, T *__restrict__ U) {
     if (gated(gate)) return;
-    if ((int)blockIdx.x < n_int) patch_interior<T, P, UNR>(blockIdx.x, d, A, verts, fidx, fint, mu, lam, afc, rF, U);
-    else patch_boundary<T, P>(blockIdx.x - n_int, d, desc, off, fbnd, mu, lam, afc, rF, U);
+    if ((int)blockIdx.x < n_int) patch_interior<T, P, UNR, NTH>(blockIdx.x, d, A, verts, fidx, fint, mu, lam, afc, rF, U);
+    else patch_boundary<T, P, NTH>(blockIdx.x - n_int, d, desc, off, fbnd, mu, lam, afc, rF, U);
 }
 
 }  // namespace

@@ -994,88 +994,11 @@ std::vector<double> make_coarse_inverse(int nx, int ny, int nz, const OneD &od, 
     return inv;
 }
 
-// ============================================================ lattice transfer tables
-// Free lattice positions along an axis: full positions P = 1 .. p*ncell - 1 (index P-1).
-static AxisTable finish(std::vector<std::vector<std::pair<int, double>>> &rows, int n_in) {
-    AxisTable t;
-    t.n_out = (int)rows.size();
-    t.n_in = n_in;
-    t.rowptr.push_back(0);
-    for (auto &r : rows) {
-        for (auto &e : r) {
-            t.col.push_back(e.first);
-            t.w.push_back(e.second);
-        }
-        t.rowptr.push_back((int32_t)t.col.size());
-    }
-    return t;
-}
-
-AxisTable table_fdm_restrict(int ncell, const OneD &od) {
-    int p = od.p, n1 = p + 1, L = p * ncell - 1;
-    std::vector<std::vector<std::pair<int, double>>> rows(L);
-    for (int P = 1; P <= L; ++P) {
-        auto &r = rows[P - 1];
-        if (P % p == 0) {
-            r.push_back({P - 1, 1.0});
-            for (int b = 1; b < p; ++b) r.push_back({P - p + b - 1, od.T[(size_t)b * n1 + p]});
-            for (int b = 1; b < p; ++b) r.push_back({P + b - 1, od.T[(size_t)b * n1 + 0]});
-        } else {
-            int e = P / p, a = P % p;
-            for (int b = 1; b < p; ++b) r.push_back({p * e + b - 1, od.T[(size_t)b * n1 + a]});
-        }
-    }
-    return finish(rows, L);
-}
-
-AxisTable table_fdm_prolong(int ncell, const OneD &od) {
-    int p = od.p, n1 = p + 1, L = p * ncell - 1;
-    std::vector<std::vector<std::pair<int, double>>> rows(L);
-    for (int P = 1; P <= L; ++P) {
-        auto &r = rows[P - 1];
-        if (P % p == 0) {
-            r.push_back({P - 1, 1.0});
-        } else {
-            int e = P / p, a = P % p;
-            if (e >= 1) r.push_back({p * e - 1, od.T[(size_t)a * n1 + 0]});
-            for (int b = 1; b < p; ++b) r.push_back({p * e + b - 1, od.T[(size_t)a * n1 + b]});
-            if (e + 1 <= ncell - 1) r.push_back({p * (e + 1) - 1, od.T[(size_t)a * n1 + p]});
-        }
-    }
-    return finish(rows, L);
-}
-
-AxisTable table_coarse_restrict(int ncell, const OneD &od) {
-    int p = od.p, L = p * ncell - 1;
-    std::vector<std::vector<std::pair<int, double>>> rows(ncell - 1);
-    for (int v = 1; v <= ncell - 1; ++v) {
-        auto &r = rows[v - 1];
-        int P = p * v;
-        for (int b = 1; b < p; ++b) r.push_back({P - p + b - 1, 0.5 * (1 + od.xi[b])});
-        r.push_back({P - 1, 1.0});
-        for (int b = 1; b < p; ++b) r.push_back({P + b - 1, 0.5 * (1 - od.xi[b])});
-    }
-    return finish(rows, L);
-}
-
-AxisTable table_coarse_prolong(int ncell, const OneD &od) {
-    int p = od.p, L = p * ncell - 1;
-    std::vector<std::vector<std::pair<int, double>>> rows(L);
-    for (int P = 1; P <= L; ++P) {
-        auto &r = rows[P - 1];
-        if (P % p == 0) {
-            r.push_back({P / p - 1, 1.0});
-        } else {
-            int e = P / p, a = P % p;
-            if (e >= 1) r.push_back({e - 1, 0.5 * (1 - od.xi[a])});
-            if (e + 1 <= ncell - 1) r.push_back({e, 0.5 * (1 + od.xi[a])});
-        }
-    }
-    return finish(rows, ncell - 1);
-}
-
-// Cell blocks of the same four maps.  Cell e owns the free positions P = e p + 1 .. e p + p
-// (its interior nodes and its high vertex); a = P - e p - 1.
+// ============================================================ lattice transfers
+// Cell blocks of the FDM transfers T^T and T (Sec. 2.4: T maps FDM coefficients to GLL
+// values; column b of the reference T holds the GLL values of FDM function b) and of the Q1
+// transfers P^T and P (Sec. 2.5).  Free lattice positions along an axis are P = 1 .. p n - 1;
+// cell e owns P = e p + 1 .. e p + p (its interior nodes and its high vertex), a = P - e p - 1.
 std::vector<double> transfer_block(int kind, const OneD &od) {
     const int p = od.p, n1 = p + 1;
     auto Tm = [&](int i, int j) { return od.T[(size_t)i * n1 + j]; };

@@ -88,17 +88,6 @@ PatchSet make_patches(int nx, int ny, int nz, const OneD &od, const double *mu, 
 // Dense inverse of the Q1 Galerkin matrix over interior vertices (row-major, nc x nc).
 std::vector<double> make_coarse_inverse(int nx, int ny, int nz, const OneD &od, const Geometry &g);
 
-// 1D lattice operators (CSR rows over output positions) for the axis passes.
-struct AxisTable {
-    int n_out = 0, n_in = 0;
-    std::vector<int32_t> rowptr, col;
-    std::vector<double> w;
-};
-AxisTable table_fdm_restrict(int ncell, const OneD &od);   // T^T
-AxisTable table_fdm_prolong(int ncell, const OneD &od);    // T
-AxisTable table_coarse_restrict(int ncell, const OneD &od);// P^T
-AxisTable table_coarse_prolong(int ncell, const OneD &od); // P
-
 // Cell block of a lattice transfer (row-major OA x K) for launch_transfer: along an axis,
 // cell e maps inputs e*in_step + in_off + s to outputs e*out_step + a.
 //   XFER_FDM_RESTRICT   T^T: OA = p, K = 2p-1 (in_step p, in_off 0, out_step p)

@@ -176,15 +176,14 @@ class Problem:
         self.q = (3 * (p + 1) + 1) // 2
 
     def tuning(self):
-        """Launch shapes in use: (Cartesian-operator cells/workgroup FP64, FP32, lattice-pass block,
-        panel unroll, general-operator workgroups/cell FP64, FP32, lattice passes staged in LDS,
-        threads per patch workgroup)."""
-        a = (ctypes.c_int32 * 8)()
+        """Launch shapes in use: (Cartesian-operator cells/workgroup FP64, FP32, panel unroll,
+        general-operator workgroups/cell FP64, FP32, threads per patch workgroup)."""
+        a = (ctypes.c_int32 * 6)()
         _check(lib().vsr_get_tuning(self._h, a))
         return tuple(a)
 
     def set_tuning(self, shapes):
-        a = (ctypes.c_int32 * 8)(*[int(v) for v in shapes])
+        a = (ctypes.c_int32 * 6)(*[int(v) for v in shapes])
         _check(lib().vsr_set_tuning(self._h, a))
 
     def close(self):

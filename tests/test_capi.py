@@ -59,7 +59,7 @@ def test_batch_and_tuning_argument_checks_without_gpu_work():
     st = L.vsr_setup_batch(1, meshes, ps, None, ctypes.byref(opt), ctypes.byref(h))
     assert st == vsr.VSR_EINVAL and b"member 0" in L.vsr_last_error()
     assert L.vsr_batch_size(None) == -1 and L.vsr_batch_member(None, 0) is None
-    shapes = (ctypes.c_int32 * 8)(1, 1, 256, 8, 0, 0, 1, 256)
+    shapes = (ctypes.c_int32 * 6)(1, 1, 8, 0, 0, 256)
     assert L.vsr_set_tuning(None, shapes) == vsr.VSR_EINVAL
     assert L.vsr_pcg_solve_batch(None, None, None, 1e-8, None) == vsr.VSR_EINVAL
     # the options record keeps the C layout: the new fields follow the stream pointer
