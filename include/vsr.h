@@ -216,7 +216,8 @@ vsr_status vsr_get_tuning(const vsr_problem *prob, int32_t shapes[6]);
 
 /* Set the launch shapes (same order; cells per workgroup in {1, 2, 4}, used only for
  * Cartesian meshes with p <= 7; unroll in {4, 8, 16}; workgroups per cell in {0, 1, 2};
- * patch threads 256 or 512).  VSR_EINVAL for any other value. */
+ * patch threads 256, 512 or 1024, the last with an unroll of 4 or 8).  VSR_EINVAL for any
+ * other value. */
 vsr_status vsr_set_tuning(vsr_problem *prob, const int32_t shapes[6]);
 
 void vsr_destroy(vsr_problem *prob);

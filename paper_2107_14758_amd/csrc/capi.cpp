@@ -463,8 +463,9 @@ void autotune(vsr_problem *P) {
     auto pick_patch = [&](auto &&fn) {
         double best = 1e300;
         Tuning keep = P->tune;
-        for (int nth : {256, 512})
+        for (int nth : {256, 512, 1024})
             for (int u : {4, 8, 16}) {
+                if (nth == 1024 && u == 16) continue;   // 128 VGPRs at 1024 threads
                 P->tune.patch_threads = nth;
                 P->tune.patch_unroll = u;
                 double ms = time_ms(P, fn);
@@ -1029,7 +1030,9 @@ vsr_status vsr_set_tuning(vsr_problem *P, const int32_t shapes[6]) {
         if (shapes[2] != 4 && shapes[2] != 8 && shapes[2] != 16) throw Error(VSR_EINVAL, "unroll must be 4, 8 or 16");
         for (int i = 3; i < 5; ++i)
             if (shapes[i] < 0 || shapes[i] > 2) throw Error(VSR_EINVAL, "workgroups per cell must be 0, 1 or 2");
-        if (shapes[5] != 256 && shapes[5] != 512) throw Error(VSR_EINVAL, "patch threads must be 256 or 512");
+        if (shapes[5] != 256 && shapes[5] != 512 && shapes[5] != 1024)
+            throw Error(VSR_EINVAL, "patch threads must be 256, 512 or 1024");
+        if (shapes[5] == 1024 && shapes[2] == 16) throw Error(VSR_EINVAL, "1024 patch threads take an unroll of 4 or 8");
         VSR_HIP(hipStreamSynchronize(P->stream));
         Tuning t;
         t.op_cpw64 = shapes[0];

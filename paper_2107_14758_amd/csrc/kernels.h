@@ -21,7 +21,7 @@ struct Tuning {
     int patch_unroll = 8;   // column loads in flight per thread in the patch panels (4, 8, 16)
     int opg_split64 = 0;    // workgroups per cell of the general operator, FP64 (1, 2; 0: by size)
     int opg_split32 = 0;    // same, FP32
-    int patch_threads = 256;   // threads per patch workgroup (256 or 512: more panel loads in flight)
+    int patch_threads = 256;   // threads per patch workgroup (256, 512, or 1024 with unroll 4 or 8)
 };
 
 // Where a launch goes: its stream, an optional gate (a device flag; when it is nonzero

@@ -211,14 +211,45 @@ __device__ void panel_fwd(const T *__restrict__ M, int ld, int nrows, int ncols,
     }
 }
 
-// y[c] -= sum_r M[c * ld + r] x[r] for c < ncols: a thread streams one (column, row chunk)
-// with U loads in flight; chunks of one column meet in an LDS atomic.
+// y[c] -= sum_r M[c * ld + r] x[r] for c < ncols.
+// Long columns (at least 48 row quads): a wavefront takes G = min(U, 8) columns at a time
+// and its lanes split their rows, so every load instruction reads whole cache lines; G
+// loads in flight per lane; the G sums are reduced across the wavefront and stored by lane
+// 0 (each column has one owner, no atomics).  Short columns: a thread streams one (column, row chunk) with
+// U loads in flight; chunks of one column meet in an LDS atomic.
 template <typename T, int U, int NTH>
 __device__ void panel_bwd(const T *__restrict__ M, int ld, int nrows, int ncols, const T *x, T *y) {
     const int tid = threadIdx.x;
-    constexpr int nt = NTH;
+    constexpr int nt = NTH, NW = NTH / 64;
     const int nq = (nrows + 3) / 4;
     if (nq == 0 || ncols == 0) return;
+    if (nq >= 48) {
+        constexpr int G = U > 8 ? 8 : U;   // columns per wavefront step
+        const int lane = tid & 63, wv = tid >> 6;
+        for (int c0 = wv * G; c0 < ncols; c0 += NW * G) {
+            T acc[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) acc[g] = T(0);
+            for (int q = lane; q < nq; q += 64) {
+                const int r = 4 * q;
+                const T x0 = x[r], x1 = r + 1 < nrows ? x[r + 1] : T(0), x2 = r + 2 < nrows ? x[r + 2] : T(0),
+                        x3 = r + 3 < nrows ? x[r + 3] : T(0);
+                Vec4<T> v[G];
+#pragma unroll
+                for (int g = 0; g < G; ++g)
+                    if (c0 + g < ncols) v[g] = load4(M + (int64_t)(c0 + g) * ld + r);
+#pragma unroll
+                for (int g = 0; g < G; ++g)
+                    if (c0 + g < ncols) acc[g] += (v[g].v[0] * x0 + v[g].v[1] * x1) + (v[g].v[2] * x2 + v[g].v[3] * x3);
+            }
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const T sg = wave_sum(acc[g]);
+                if (lane == 0 && c0 + g < ncols) y[c0 + g] -= sg;
+            }
+        }
+        return;
+    }
     int nrc = max(1, min((nq + U - 1) / U, nt / ncols));
     int chunk = (nq + nrc - 1) / nrc;
     for (int task = tid; task < ncols * nrc; task += nt) {
@@ -291,7 +322,7 @@ __device__ __forceinline__ void patch_interior(const int pid, Dims d, PatchArgs 
     __shared__ T g[NI];
     __shared__ T smu[24], slam[M], safc[2 * M];
     __shared__ T tl[64 * 65 / 2];
-    __shared__ T red[512];   // one 64-row partial per wavefront (at most 8)
+    __shared__ T red[NTH];   // one 64-row partial per wavefront
     constexpr int nt = NTH, nw = NTH / 64;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int kfull[3] = {AX_FULL, AX_FULL, AX_FULL};
@@ -563,13 +594,16 @@ void launch_patch_all(const Dims &d, const PatchArgs &a, int n_int, const int *v
     if (n_int + n_bnd == 0) return;
     const int unr = e.t.patch_unroll, nth = e.t.patch_threads;
     if (unr != 4 && unr != 8 && unr != 16) throw Error(VSR_EINVAL, "patch_unroll must be 4, 8 or 16");
-    if (nth != 256 && nth != 512) throw Error(VSR_EINVAL, "patch_threads must be 256 or 512");
+    if (nth != 256 && nth != 512 && nth != 1024) throw Error(VSR_EINVAL, "patch_threads must be 256, 512 or 1024");
+    if (nth == 1024 && unr == 16) throw Error(VSR_EINVAL, "1024 patch threads take an unroll of 4 or 8");
 #define CALLT(P, UU, NN)                                                                                          \
     hipLaunchKernelGGL((k_patch_all<T, P, UU, NN>), dim3(n_int + n_bnd), dim3(NN), 0, e.s, e.gate, d, a, n_int, verts, fidx, fint, \
                        desc, off, fbnd, mu, lam, afc, rF, U)
-#define CALLU(P, UU)                  \
-    if (nth == 512) CALLT(P, UU, 512); \
-    else CALLT(P, UU, 256)
+#define CALLU(P, UU)                                       \
+    if (nth == 512) CALLT(P, UU, 512);                      \
+    else if (nth == 1024) {                                 \
+        if constexpr (UU < 16) CALLT(P, UU, 1024);          \
+    } else CALLT(P, UU, 256)
 #define CALL(P)                          \
     if (unr == 4) { CALLU(P, 4); }       \
     else if (unr == 8) { CALLU(P, 8); }  \
