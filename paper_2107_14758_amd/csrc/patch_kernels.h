@@ -212,7 +212,7 @@ __device__ void panel_fwd(const T *__restrict__ M, int ld, int nrows, int ncols,
 }
 
 // y[c] -= sum_r M[c * ld + r] x[r] for c < ncols.
-// Long columns (at least 48 row quads): a wavefront takes G = min(U, 8) columns at a time
+// Long columns (at least 32 row quads): a wavefront takes G = min(U, 8) columns at a time
 // and its lanes split their rows, so every load instruction reads whole cache lines; G
 // loads in flight per lane; the G sums are reduced across the wavefront and stored by lane
 // 0 (each column has one owner, no atomics).  Short columns: a thread streams one (column, row chunk) with
@@ -223,7 +223,7 @@ __device__ void panel_bwd(const T *__restrict__ M, int ld, int nrows, int ncols,
     constexpr int nt = NTH, NW = NTH / 64;
     const int nq = (nrows + 3) / 4;
     if (nq == 0 || ncols == 0) return;
-    if (nq >= 48) {
+    if (nq >= 32) {
         constexpr int G = U > 8 ? 8 : U;   // columns per wavefront step
         const int lane = tid & 63, wv = tid >> 6;
         for (int c0 = wv * G; c0 < ncols; c0 += NW * G) {
