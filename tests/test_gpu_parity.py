@@ -235,3 +235,19 @@ def test_gpu_iterations_nearly_flat_in_p(vsr):
         prob.close()
     print("  iterations", its, flush=True)
     assert max(its.values()) - min(its.values()) <= 3 and max(its.values()) <= 16
+
+
+@pytest.mark.parametrize("shape,p,jit", [((4, 3, 3), 7, 0.0), ((3, 3, 2), 8, 0.15)])
+def test_operator_is_bitwise_repeatable(vsr, shape, p, jit):
+    """Cell results are summed per node by a gather in a fixed order (no atomics), so two
+    applies of the FP64 operator agree bit for bit (Cartesian and general-metric paths)."""
+    say("case operator repeatability", shape, p)
+    V, kappa, f = mesh(shape, p, seed=21, jitter=jit, lognormal=jit > 0)
+    prob = vsr.Problem(V, p, kappa=kappa, omega=1.0)
+    x = dev(np.random.default_rng(22).uniform(-1, 1, prob.n))
+    y1 = torch.zeros_like(x)
+    y2 = torch.zeros_like(x)
+    prob.apply_operator(x, y1)
+    prob.apply_operator(x, y2)
+    assert torch.equal(y1, y2)
+    prob.close()
