@@ -297,8 +297,9 @@ __device__ __forceinline__ T sum_waves(const T *red, int nw, int lane) {
     return s;
 }
 
-// Offset of top-plane tile J inside one interior-patch factor (diagonal 64x64 block, then
-// the panel of rows below it padded to a multiple of 4).
+// Offset of top-plane tile J inside one interior-patch factor.  Every tile before it holds
+// its diagonal block packed in 64 columns, then the panel of rows below it padded to a
+// multiple of 4 (only the last tile, which has no panel, is packed in its own width).
 __device__ __forceinline__ int64_t tile_offset(int64_t off_Ltop, int NT, int J) {
     int64_t o = off_Ltop;
     for (int j = 0; j < J; ++j) {
@@ -378,11 +379,15 @@ __device__ __forceinline__ void patch_interior(const int pid, Dims d, PatchArgs 
     }
     // stage the first top-plane diagonal tile while the level-1 solves finish
     T *gt = g + NL + NS;
-    // stage a packed 64-column diagonal block verbatim (column k holds rows k..63 from
-    // offset k (129 - k) / 2); 9 independent loads per thread
+    // stage a packed diagonal block verbatim (column k holds rows k..ns-1 from offset
+    // k ns - k (k - 1) / 2; ns = 64, or the last block's own width NBL); all loads in flight
+    // before the first LDS store
+    constexpr int NBL = NT - 64 * (NTILE - 1);
+    auto tile_ns = [](int J) { return J + 1 < NTILE ? 64 : NBL; };
     auto stage_tile = [&](int J) {
         const T *D = F + tile_offset(A.off_Ltop, NT, J);
-        constexpr int NP = 64 * 65 / 2, R = (NP + 255) / 256;   // loads per thread with 256 threads
+        const int ns = tile_ns(J), NP = ns * (ns + 1) / 2;
+        constexpr int R = (64 * 65 / 2 + NTH - 1) / NTH;
         T v[R];
 #pragma unroll
         for (int u = 0; u < R; ++u) v[u] = tid + nt * u < NP ? D[tid + nt * u] : T(0);
@@ -401,7 +406,7 @@ __device__ __forceinline__ void patch_interior(const int pid, Dims d, PatchArgs 
         const int c0 = 64 * J, nb = min(64, NT - c0);
         // diagonal block: y = L^{-1} b from the staged inverse, the k-range split over the waves
         const int kw = 64 / nw;   // columns of the block per wavefront
-        red[tid] = tri_inv_mv<T>(tl, 64, min(kw * wv, nb), min(kw * wv + kw, nb), nb, lane, gt + c0);
+        red[tid] = tri_inv_mv<T>(tl, tile_ns(J), min(kw * wv, nb), min(kw * wv + kw, nb), nb, lane, gt + c0);
         phase_sync();
         if (wv == 0 && lane < nb) gt[c0 + lane] = sum_waves(red, nw, lane);
         phase_sync();
@@ -415,7 +420,7 @@ __device__ __forceinline__ void patch_interior(const int pid, Dims d, PatchArgs 
     for (int J = NTILE - 1; J >= 0; --J) {
         const int c0 = 64 * J, nb = min(64, NT - c0);
         const int kw = 64 / nw;
-        red[tid] = tri_inv_t_mv<T>(tl, 64, min(kw * wv, nb), min(kw * wv + kw, nb), nb, lane, gt + c0);
+        red[tid] = tri_inv_t_mv<T>(tl, tile_ns(J), min(kw * wv, nb), min(kw * wv + kw, nb), nb, lane, gt + c0);
         phase_sync();
         if (wv == 0 && lane < nb) gt[c0 + lane] = sum_waves(red, nw, lane);
         phase_sync();

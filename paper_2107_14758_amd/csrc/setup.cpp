@@ -453,7 +453,9 @@ InteriorLayout interior_layout(int p) {
         int rp = (int)round_up(rows, 4);
         L.tile_off.push_back(o);
         L.tile_rows_pad.push_back(rp);
-        o += 64 * 65 / 2 + (int64_t)64 * rp;
+        // the diagonal block is packed in 64 columns; the last (possibly narrower) block in its own width
+        const int ns = J + 1 < L.ntiles ? 64 : nb;
+        o += ns * (ns + 1) / 2 + (int64_t)64 * rp;
     }
     L.stride = round_up(o, 64);
     return L;
@@ -728,8 +730,8 @@ bool factor_interior(const InteriorLayout &L, std::vector<double> &S, double *ou
     if (!cholesky_lower(nt, T.data(), nt)) return false;
     for (int J = 0; J < L.ntiles; ++J) {
         int c0 = 64 * J, nb = std::min(64, nt - c0);
-        double *D = out + L.tile_off[J];   // inverse of the diagonal block, packed in 64 columns
-        pack_lower_inverse(nb, T.data() + (size_t)c0 * nt + c0, nt, 64, D);
+        double *D = out + L.tile_off[J];   // inverse of the diagonal block, packed in 64 columns (the last in nb)
+        pack_lower_inverse(nb, T.data() + (size_t)c0 * nt + c0, nt, J + 1 < L.ntiles ? 64 : nb, D);
         int rp = L.tile_rows_pad[J], r0 = c0 + nb;
         double *Pn = D + 64 * 65 / 2;
         for (int k = 0; k < 64; ++k)
