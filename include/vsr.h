@@ -230,9 +230,11 @@ void vsr_destroy(vsr_problem *prob);
  * further work (its kernels return at once).  Members are spread over
  * options.batch_streams streams (largest first onto the least loaded stream) so
  * small members run concurrently; one lockstep iteration of all members is
- * recorded into a hipGraph and replayed until none is active (one 4-byte
- * readback per replay).  Each member gives the same iterates as vsr_pcg_solve
- * on it up to the order of floating-point atomic additions.
+ * recorded into a hipGraph and replayed until none is active (the stop flags sit
+ * in mapped host memory and are read one replay behind, so the next replay is
+ * always queued).  Each member gives the same iterates as vsr_pcg_solve on it up
+ * to the order of the floating-point additions that the patch panels make with
+ * LDS atomics.
  * ------------------------------------------------------------------------- */
 typedef struct vsr_batch vsr_batch;
 
