@@ -807,11 +807,13 @@ vsr_status vsr_setup(const vsr_mesh *mesh, int32_t p, const vsr_coefficients *co
         PatchArgs &a = P->pa;
         a.m = L.m; a.w = L.w; a.n_leaf = L.n_leaf; a.n_sep = L.n_sep; a.n_top = L.n_top; a.n_iface = L.n_iface;
         a.top_pad = L.top_pad; a.ntiles = L.ntiles;
-        a.off_invd = L.off_invd; a.off_B1 = L.off_B1; a.off_B2 = L.off_B2; a.off_Lsep = L.off_Lsep; a.off_P = L.off_P;
+        a.off_invd = L.off_invd; a.off_B1 = L.off_B1; a.off_B2 = L.off_B2; a.off_Lsep = L.off_Lsep; a.off_Sy = L.off_Sy;
         a.off_Ltop = L.off_Ltop; a.stride = L.stride;
         int m = L.m, w = L.w;
+        // stored entries of one interior factor: leaves, B1 and B2, level-1 slice inverses, the
+        // y-diagonal top x separator block, the top-plane factor
         int64_t per_patch = (int64_t)L.n_leaf + 2LL * 4 * m * m * w + 2LL * m * w * (w + 1) / 2 +
-                            2LL * m * w * L.n_top + (int64_t)L.n_top * (L.n_top + 1) / 2;
+                            2LL * m * w * w + (int64_t)L.n_top * (L.n_top + 1) / 2;
         int64_t bnd_nnz = 0, bnd_box = 0;
         for (int i = 0; i < P->n_bnd; ++i) {
             int ns = S.boundary_desc[8 * i + 7], nsl = S.boundary_desc[8 * i + 6];

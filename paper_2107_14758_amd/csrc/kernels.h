@@ -67,7 +67,7 @@ void launch_transfer(int kind, int p, const int ncell[3], const int in_dims[3], 
 struct PatchArgs {
     int m, w;
     int n_leaf, n_sep, n_top, n_iface, top_pad, ntiles;
-    int64_t off_invd, off_B1, off_B2, off_Lsep, off_P, off_Ltop, stride;
+    int64_t off_invd, off_B1, off_B2, off_Lsep, off_Sy, off_Ltop, stride;
 };
 
 // All patches in one launch (interior first, then boundary).

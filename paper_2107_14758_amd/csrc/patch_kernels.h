@@ -324,6 +324,7 @@ __device__ __forceinline__ void patch_interior(const int pid, Dims d, PatchArgs 
     __shared__ T smu[24], slam[M], safc[2 * M];
     __shared__ T tl[64 * 65 / 2];
     __shared__ T red[NTH];   // one 64-row partial per wavefront
+    __shared__ T zs[NS], wl[NL];   // level-1 and leaf work vectors of the top x level-1 coupling
     constexpr int nt = NTH, nw = NTH / 64;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int kfull[3] = {AX_FULL, AX_FULL, AX_FULL};
@@ -397,8 +398,37 @@ __device__ __forceinline__ void patch_interior(const int pid, Dims d, PatchArgs 
     };
     stage_tile(0);
     phase_sync();
-    // level-1 panels update the top plane
-    panel_fwd<T, UNR, NTH>(F + A.off_P, A.top_pad, NT, NS, g + NL, gt);
+    // the level-1 solution updates the top plane: g_T -= L_TS y_S with L_TS = S''_TS L_SS^{-T}
+    // and S''_TS = S_TS - L_TL L_SL^T (S_TS: the raw Schur block, y-diagonal and stored; the
+    // leaf blocks and the slice inverses are the ones used above), so the dense panel is
+    // never formed
+    const T *Sy = F + A.off_Sy;
+    constexpr int LS = W * (W + 1) / 2;
+    for (int s = wv; s < 2 * M; s += nw) {   // z = L_SS^{-T} y_S
+        const T zv = tri_inv_t_mv<T>(F + A.off_Lsep + (int64_t)s * LS, W, 0, W, W, lane, g + NL + s * W);
+        if (lane < W) zs[s * W + lane] = zv;
+    }
+    phase_sync();
+    for (int i = tid; i < NL; i += nt) {     // w_L = L_SL^T z (leaf (s, c) meets slice s)
+        const int sl = i / (2 * M);
+        T acc = 0;
+#pragma unroll
+        for (int r = 0; r < W; ++r) acc += B1[(int64_t)i * W + r] * zs[sl * W + r];
+        wl[i] = acc;
+    }
+    phase_sync();
+    for (int i = tid; i < NT; i += nt) {     // g_T -= S_TS z - L_TL w_L
+        const int ay = i / W, ax = i % W;
+        T acc = 0;
+#pragma unroll
+        for (int s = 0; s < 2 * M; ++s) acc += Sy[(int64_t)s * NT + i] * zs[s * W + ay];
+        if (ax != M) {
+            const int lx = la_(ax, M);
+#pragma unroll
+            for (int c = 0; c < 2 * M; ++c) acc -= B2[(int64_t)(lx * 2 * M + c) * W + ay] * wl[c * 2 * M + lx];
+        }
+        gt[i] -= acc;
+    }
     phase_sync();
     // dense top plane, 64-column tiles: wave 0 solves the diagonal block from LDS, then all
     // waves update the rows below while the next diagonal block is staged
@@ -432,7 +462,29 @@ __device__ __forceinline__ void patch_interior(const int pid, Dims d, PatchArgs 
         }
         phase_sync();
     }
-    panel_bwd<T, UNR, NTH>(F + A.off_P, A.top_pad, NT, NS, gt, g + NL);
+    // y_S -= L_TS^T x_T = L_SS^{-1} (S_TS^T x_T - L_SL (L_TL^T x_T))
+    for (int i = tid; i < NL; i += nt) {     // w_L = L_TL^T x_T (leaf (c, lx) meets top column lx)
+        const int c = i / (2 * M), lx = i % (2 * M), ax = inv_la_(lx, M);
+        T acc = 0;
+#pragma unroll
+        for (int ay = 0; ay < W; ++ay) acc += B2[(int64_t)(lx * 2 * M + c) * W + ay] * gt[ay * W + ax];
+        wl[i] = acc;
+    }
+    phase_sync();
+    for (int i = tid; i < NS; i += nt) {     // h = S_TS^T x_T - L_SL w_L
+        const int s = i / W, r = i % W;
+        T acc = 0;
+#pragma unroll
+        for (int ax = 0; ax < W; ++ax) acc += Sy[(int64_t)s * NT + r * W + ax] * gt[r * W + ax];
+#pragma unroll
+        for (int c = 0; c < 2 * M; ++c) acc -= B1[(int64_t)(s * 2 * M + c) * W + r] * wl[s * 2 * M + c];
+        zs[i] = acc;
+    }
+    phase_sync();
+    for (int s = wv; s < 2 * M; s += nw) {   // y_S -= L_SS^{-1} h
+        const T d = tri_inv_mv<T>(F + A.off_Lsep + (int64_t)s * LS, W, 0, W, W, lane, zs + s * W);
+        if (lane < W) g[NL + s * W + lane] -= d;
+    }
     phase_sync();
     for (int s = wv; s < 2 * M; s += nw) {
         const T x = tri_inv_t_mv<T>(F + A.off_Lsep + (int64_t)s * (W * (W + 1) / 2), W, 0, W, W, lane, g + NL + s * W);

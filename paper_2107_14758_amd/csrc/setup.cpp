@@ -444,7 +444,10 @@ InteriorLayout interior_layout(int p) {
     o = round_up(o, 4);
     L.off_Lsep = o; o += (int64_t)2 * m * (w * (w + 1) / 2);
     o = round_up(o, 4);
-    L.off_P = o; o += (int64_t)2 * m * w * L.top_pad;
+    // raw top-plane x level-1 Schur block, y-diagonal: Sy[s][ay][ax] couples top (ax, ay) with
+    // separator (s, ay) (it replaces the dense panel L_TS = (S_TS - L_TL L_SL^T) L_SS^{-T})
+    L.off_Sy = o; o += (int64_t)w * w * 2 * m;
+    o = round_up(o, 4);
     L.off_Ltop = o;
     L.ntiles = (L.n_top + 63) / 64;
     for (int J = 0; J < L.ntiles; ++J) {
@@ -660,6 +663,15 @@ bool factor_interior(const InteriorLayout &L, std::vector<double> &S, double *ou
                 B2[((size_t)lx * 2 * m + c) * w + r] = at(top(r, inv_la(lx)), leaf(c, lx)) * invd[leaf(c, lx)];
     std::memcpy(out + L.off_B1, B1.data(), B1.size() * sizeof(double));
     std::memcpy(out + L.off_B2, B2.data(), B2.size() * sizeof(double));
+    // the raw top x separator block before the leaves update it: it couples top (ax, ay) only
+    // with separators (s, ay) (both sides' 1D factors meet in one interior line)
+    for (int ay = 0; ay < w; ++ay)
+        for (int ax = 0; ax < w; ++ax)
+            for (int s = 0; s < 2 * m; ++s) {
+                for (int r = 0; r < w; ++r)
+                    if (r != ay && at(top(ay, ax), sep(s, r)) != 0.0) return false;
+                out[L.off_Sy + ((int64_t)s * w + ay) * w + ax] = at(top(ay, ax), sep(s, ay));
+            }
     // Schur updates by the leaves
     for (int s = 0; s < 2 * m; ++s)
         for (int r1 = 0; r1 < w; ++r1)
@@ -702,11 +714,7 @@ bool factor_interior(const InteriorLayout &L, std::vector<double> &S, double *ou
             }
         }
     }
-    for (int col = 0; col < ncol; ++col) {
-        double *Po = out + L.off_P + (int64_t)col * L.top_pad;
-        for (int r = 0; r < nt; ++r) Po[r] = Pall[(size_t)r * ncol + col];
-        for (int r = nt; r < L.top_pad; ++r) Po[r] = 0.0;
-    }
+    // (Pall itself is not stored: the solve applies it as (S_TS - L_TL L_SL^T) L_SS^{-T})
     // top plane: S_top -= Pall Pall^T (lower triangle), then dense Cholesky
     std::vector<double> T((size_t)nt * nt);
     for (int i = 0; i < nt; ++i)

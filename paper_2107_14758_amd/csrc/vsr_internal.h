@@ -57,8 +57,8 @@ enum AxisKind : int { AX_FULL = 0, AX_LOW = 1, AX_HIGH = 2 };
 struct InteriorLayout {
     int m = 0, w = 0;           // w = 2m+1
     int n_leaf = 0, n_sep = 0, n_top = 0, n_iface = 0;
-    int top_pad = 0;            // rows of every panel column, padded to a multiple of 4
-    int64_t off_invd = 0, off_B1 = 0, off_B2 = 0, off_Lsep = 0, off_P = 0, off_Ltop = 0;
+    int top_pad = 0;            // top-plane size padded to a multiple of 4
+    int64_t off_invd = 0, off_B1 = 0, off_B2 = 0, off_Lsep = 0, off_Sy = 0, off_Ltop = 0;
     int ntiles = 0;
     std::vector<int64_t> tile_off;   // offset of tile J (diag block 64x64 then panel below)
     std::vector<int> tile_rows_pad;  // padded row count of the panel below tile J
