@@ -17,8 +17,8 @@ struct Dims {
 // arithmetic of any output value.
 struct Tuning {
     int op_cpw64 = 1;       // cells per workgroup of the Cartesian operator kernel, FP64
-    int op_cpw32 = 1;       // same, FP32 (both 1, 2 or 4; above 1 only for p <= 7)
-    int patch_unroll = 8;   // column loads in flight per thread in the patch panels (4, 8, 16)
+    int op_cpw32 = 4;       // same, FP32 (both 1, 2 or 4; above 1 only for p <= 7)
+    int patch_unroll = 4;   // column loads in flight per thread in the patch panels (4, 8, 16)
     int opg_split64 = 0;    // workgroups per cell of the general operator, FP64 (1, 2; 0: by size)
     int opg_split32 = 0;    // same, FP32
     int patch_threads = 256;   // threads per patch workgroup (256, 512, or 1024 with unroll 4 or 8)

@@ -132,7 +132,7 @@ def test_every_launch_shape_gives_the_same_solve(vsr, p, jitter, relax_fp32):
     b = rhs(prob, f)
     x0 = torch.zeros_like(b)
     ref = prob.pcg_solve(b, x0)
-    assert prob.tuning() == (1, 1, 8, 0, 0, 256)
+    assert prob.tuning() == (1, 4, 4, 0, 0, 256)
     for shapes in [(2, 2, 4, 1, 2, 512), (4, 4, 16, 2, 1, 256), (4, 2, 8, 2, 2, 1024), (1, 4, 16, 1, 1, 512),
                    (1, 1, 4, 0, 0, 1024)]:
         prob.set_tuning(shapes)
