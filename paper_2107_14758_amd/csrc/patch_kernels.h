@@ -325,14 +325,24 @@ __device__ __forceinline__ void patch_interior(const int pid, Dims d, PatchArgs 
     __shared__ T tl[64 * 65 / 2];
     __shared__ T red[NTH];   // one 64-row partial per wavefront
     __shared__ T zs[NS], wl[NL];   // level-1 and leaf work vectors of the top x level-1 coupling
+    // the 2m slice inverses are applied four times (forward, the coupling, backward twice):
+    // staged once in LDS while they fit in 8 KB, else read from the factor each time
+    constexpr int LS = W * (W + 1) / 2, NSEP = 2 * M * LS;
+    constexpr bool SEP_LDS = NSEP * sizeof(T) <= 8192;
+    __shared__ T sL[SEP_LDS ? NSEP : 1];
     constexpr int nt = NTH, nw = NTH / 64;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int kfull[3] = {AX_FULL, AX_FULL, AX_FULL};
     const int vx = verts[3 * pid], vy = verts[3 * pid + 1], vz = verts[3 * pid + 2];
+    const T *F = factor + (int64_t)fidx[pid] * A.stride;
+    if constexpr (SEP_LDS) {
+#pragma unroll 1
+        for (int i = tid; i < NSEP; i += nt) sL[i] = F[A.off_Lsep + i];
+    }
+    const T *Lsep = SEP_LDS ? (const T *)sL : F + A.off_Lsep;
     stage_coefficients<T, M>(d, vx, vy, vz, kfull, mu, lam, afc, smu, slam, safc);
     phase_sync();
     PatchCtx<T, M> C{d, vx, vy, vz, rF, smu, slam, safc};
-    const T *F = factor + (int64_t)fidx[pid] * A.stride;
     T *Uo = U + ((int64_t)(vz * (d.ny + 1) + vy) * (d.nx + 1) + vx) * (int64_t)(W * W * W);
 
     // ---- condensation of the interior DOFs into the interface right-hand side
@@ -375,7 +385,7 @@ __device__ __forceinline__ void patch_interior(const int pid, Dims d, PatchArgs 
     phase_sync();
     // level-1 separator slices: dense lower solves, one wavefront per slice
     for (int s = wv; s < 2 * M; s += nw) {
-        const T x = tri_inv_mv<T>(F + A.off_Lsep + (int64_t)s * (W * (W + 1) / 2), W, 0, W, W, lane, g + NL + s * W);
+        const T x = tri_inv_mv<T>(Lsep + s * LS, W, 0, W, W, lane, g + NL + s * W);
         if (lane < W) g[NL + s * W + lane] = x;
     }
     // stage the first top-plane diagonal tile while the level-1 solves finish
@@ -403,9 +413,8 @@ __device__ __forceinline__ void patch_interior(const int pid, Dims d, PatchArgs 
     // leaf blocks and the slice inverses are the ones used above), so the dense panel is
     // never formed
     const T *Sy = F + A.off_Sy;
-    constexpr int LS = W * (W + 1) / 2;
     for (int s = wv; s < 2 * M; s += nw) {   // z = L_SS^{-T} y_S
-        const T zv = tri_inv_t_mv<T>(F + A.off_Lsep + (int64_t)s * LS, W, 0, W, W, lane, g + NL + s * W);
+        const T zv = tri_inv_t_mv<T>(Lsep + s * LS, W, 0, W, W, lane, g + NL + s * W);
         if (lane < W) zs[s * W + lane] = zv;
     }
     phase_sync();
@@ -482,12 +491,12 @@ __device__ __forceinline__ void patch_interior(const int pid, Dims d, PatchArgs 
     }
     phase_sync();
     for (int s = wv; s < 2 * M; s += nw) {   // y_S -= L_SS^{-1} h
-        const T d = tri_inv_mv<T>(F + A.off_Lsep + (int64_t)s * LS, W, 0, W, W, lane, zs + s * W);
+        const T d = tri_inv_mv<T>(Lsep + s * LS, W, 0, W, W, lane, zs + s * W);
         if (lane < W) g[NL + s * W + lane] -= d;
     }
     phase_sync();
     for (int s = wv; s < 2 * M; s += nw) {
-        const T x = tri_inv_t_mv<T>(F + A.off_Lsep + (int64_t)s * (W * (W + 1) / 2), W, 0, W, W, lane, g + NL + s * W);
+        const T x = tri_inv_t_mv<T>(Lsep + s * LS, W, 0, W, W, lane, g + NL + s * W);
         if (lane < W) g[NL + s * W + lane] = x;
     }
     phase_sync();
