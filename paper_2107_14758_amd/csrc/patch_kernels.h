@@ -41,22 +41,32 @@ struct PatchCtx {
     // r_F at a face DOF minus the condensed interior lines of its two cells along axis dd:
     // g = r_G - A_GI A_II^{-1} r_I (Sec. 2.6), A_II = mu . lambda, A_GI = mu_dd A_F[interior, vertex].
     __device__ T condensed(const int pos[3], int dd) const {
-        T g = rF[gidx(pos[0], pos[1], pos[2])];
-        int c[3], l[3];
-        for (int a = 0; a < 3; ++a) {
-            c[a] = pos[a] > M;
-            l[a] = c[a] ? pos[a] - M : pos[a] + 1;
-        }
         // both cells' interior lines are loaded before any arithmetic (one round of latency)
-        T rv[2][M];
+        T rv[2 * M + 1];
+        load_line(pos, dd, rv);
+        return condense_line(pos, dd, rv);
+    }
+    // the values condensed() reads: r at the face DOF, then the interior line of the cell
+    // below it along dd and that of the cell above
+    __device__ void load_line(const int pos[3], int dd, T *rv) const {
+        rv[0] = rF[gidx(pos[0], pos[1], pos[2])];
 #pragma unroll
         for (int cd = 0; cd < 2; ++cd) {
             int q[3] = {pos[0], pos[1], pos[2]};
 #pragma unroll
             for (int t = 1; t <= M; ++t) {
                 q[dd] = cd == 0 ? t - 1 : M + t;
-                rv[cd][t - 1] = rF[gidx(q[0], q[1], q[2])];
+                rv[1 + cd * M + t - 1] = rF[gidx(q[0], q[1], q[2])];
             }
+        }
+    }
+    __device__ T condense_line(const int pos[3], int dd, const T *rl) const {
+        const T g = rl[0];
+        const T *rv[2] = {rl + 1, rl + 1 + M};
+        int c[3], l[3];
+        for (int a = 0; a < 3; ++a) {
+            c[a] = pos[a] > M;
+            l[a] = c[a] ? pos[a] - M : pos[a] + 1;
         }
         T acc = 0;
 #pragma unroll
@@ -335,9 +345,14 @@ __device__ __forceinline__ void patch_interior(const int pid, Dims d, PatchArgs 
     const int kfull[3] = {AX_FULL, AX_FULL, AX_FULL};
     const int vx = verts[3 * pid], vy = verts[3 * pid + 1], vz = verts[3 * pid + 2];
     const T *F = factor + (int64_t)fidx[pid] * A.stride;
-    if constexpr (SEP_LDS) {
-#pragma unroll 1
-        for (int i = tid; i < NSEP; i += nt) sL[i] = F[A.off_Lsep + i];
+    if constexpr (SEP_LDS) {   // every load in flight before the first LDS store
+        constexpr int RS = (NSEP + NTH - 1) / NTH;
+        T sv[RS];
+#pragma unroll
+        for (int u = 0; u < RS; ++u) sv[u] = tid + nt * u < NSEP ? F[A.off_Lsep + tid + nt * u] : T(0);
+#pragma unroll
+        for (int u = 0; u < RS; ++u)
+            if (tid + nt * u < NSEP) sL[tid + nt * u] = sv[u];
     }
     const T *Lsep = SEP_LDS ? (const T *)sL : F + A.off_Lsep;
     stage_coefficients<T, M>(d, vx, vy, vz, kfull, mu, lam, afc, smu, slam, safc);
@@ -346,8 +361,7 @@ __device__ __forceinline__ void patch_interior(const int pid, Dims d, PatchArgs 
     T *Uo = U + ((int64_t)(vz * (d.ny + 1) + vy) * (d.nx + 1) + vx) * (int64_t)(W * W * W);
 
     // ---- condensation of the interior DOFs into the interface right-hand side
-    for (int idx = tid; idx < NI; idx += nt) {
-        int pos[3];
+    auto iface_pos = [&](int idx, int pos[3]) {   // position of interface DOF idx; returns its axis
         if (idx < NL) {
             pos[2] = inv_la_(idx / (2 * M), M); pos[0] = inv_la_(idx % (2 * M), M); pos[1] = M;
         } else if (idx < NL + NS) {
@@ -357,8 +371,12 @@ __device__ __forceinline__ void patch_interior(const int pid, Dims d, PatchArgs 
             int t = idx - NL - NS;
             pos[1] = t / W; pos[0] = t % W; pos[2] = M;
         }
-        int ncen = (pos[0] == M) + (pos[1] == M) + (pos[2] == M);
-        int dd = pos[0] == M ? 0 : (pos[1] == M ? 1 : 2);
+        return pos[0] == M ? 0 : (pos[1] == M ? 1 : 2);
+    };
+    for (int idx = tid; idx < NI; idx += nt) {
+        int pos[3];
+        const int dd = iface_pos(idx, pos);
+        const int ncen = (pos[0] == M) + (pos[1] == M) + (pos[2] == M);
         g[idx] = ncen == 1 ? C.condensed(pos, dd) : rF[C.gidx(pos[0], pos[1], pos[2])];
     }
     phase_sync();
@@ -510,10 +528,11 @@ __device__ __forceinline__ void patch_interior(const int pid, Dims d, PatchArgs 
         g[i] = v * invd[i];
     }
     phase_sync();
-    // ---- interface values and interior back-substitution into the patch box, eight outputs
-    // per thread at a time with their r values loaded first (one round of latency per eight)
+    // ---- interface values and interior back-substitution into the patch box, OB outputs
+    // per thread at a time with their r values loaded first (one round of latency per OB):
+    // the whole box in one round while that takes at most 12 per thread, else 8 at a time
     const bool full[3] = {true, true, true};
-    constexpr int W3 = W * W * W, OB = 8;
+    constexpr int W3 = W * W * W, OB1 = (W3 + NTH - 1) / NTH, OB = OB1 <= 12 ? OB1 : 8;
     for (int base = tid; base < W3; base += nt * OB) {
         T rv[OB];
 #pragma unroll
@@ -638,8 +657,15 @@ __device__ __forceinline__ void patch_boundary(const int pid, Dims d, const int 
 // Every patch of one relaxation in one launch: the interior-vertex stars first, then the
 // boundary-vertex stars, whose short solves fill the CUs that the last round of interior
 // patches leaves idle.
+// Waves per SIMD the compiler must leave room for: 8 (64 VGPRs) for the 256-thread FP32
+// kernels up to degree 7 with panel unroll 4, whose solves are latency-bound and gain
+// more from the extra resident patch than they lose to the tighter register budget.
 template <typename T, int P, int UNR, int NTH>
-__global__ void __launch_bounds__(NTH) k_patch_all(const double *__restrict__ gate, Dims d, PatchArgs A, int n_int,
+constexpr int patch_min_waves() { return sizeof(T) == 4 && P <= 7 && UNR <= 4 && NTH == 256 ? 8 : 1; }
+
+template <typename T, int P, int UNR, int NTH>
+__global__ void __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(patch_min_waves<T, P, UNR, NTH>())))
+k_patch_all(const double *__restrict__ gate, Dims d, PatchArgs A, int n_int,
                                                    const int *__restrict__ verts, const int *__restrict__ fidx,
                                                    const T *__restrict__ fint,
                                                    const int *__restrict__ desc, const int64_t *__restrict__ off,
