@@ -500,14 +500,49 @@ __device__ __forceinline__ void patch_interior(const int pid, Dims d, PatchArgs 
         wl[i] = acc;
     }
     phase_sync();
-    for (int i = tid; i < NS; i += nt) {     // h = S_TS^T x_T - L_SL w_L
-        const int s = i / W, r = i % W;
-        T acc = 0;
+    if constexpr (W > 16) {   // h = S_TS^T x_T - L_SL w_L
+        // S_TS^T x_T row by row: each half-wavefront reads one (s, r) row of W consecutive
+        // entries (a thread per row would stride W through the block and thrash the L1),
+        // RB rows in flight, then a butterfly sum within the half
+        static_assert(W <= 32, "one row per half-wavefront");
+        constexpr int RB = 16;
+        const int half = lane >> 5, gl = lane & 31, a = gl < W ? gl : W - 1;
+        for (int base = 2 * wv; base < NS; base += 2 * nw * RB) {
+            T v[RB];
 #pragma unroll
-        for (int ax = 0; ax < W; ++ax) acc += Sy[(int64_t)s * NT + r * W + ax] * gt[r * W + ax];
+            for (int u = 0; u < RB; ++u) {
+                const int row = base + half + 2 * nw * u, rr = row < NS ? row : NS - 1;
+                const int s = rr / W, r = rr % W;
+                const T e = Sy[(int64_t)s * NT + r * W + a] * gt[r * W + a];
+                v[u] = row < NS && gl < W ? e : T(0);
+            }
 #pragma unroll
-        for (int c = 0; c < 2 * M; ++c) acc -= B1[(int64_t)(s * 2 * M + c) * W + r] * wl[s * 2 * M + c];
-        zs[i] = acc;
+            for (int u = 0; u < RB; ++u) {
+                T x = v[u];
+#pragma unroll
+                for (int off = 16; off > 0; off >>= 1) x += __shfl_xor(x, off, 32);
+                const int row = base + half + 2 * nw * u;
+                if (gl == 0 && row < NS) zs[row] = x;
+            }
+        }
+        phase_sync();
+        for (int i = tid; i < NS; i += nt) {
+            const int s = i / W, r = i % W;
+            T acc = zs[i];
+#pragma unroll
+            for (int c = 0; c < 2 * M; ++c) acc -= B1[(int64_t)(s * 2 * M + c) * W + r] * wl[s * 2 * M + c];
+            zs[i] = acc;
+        }
+    } else {
+        for (int i = tid; i < NS; i += nt) {
+            const int s = i / W, r = i % W;
+            T acc = 0;
+#pragma unroll
+            for (int ax = 0; ax < W; ++ax) acc += Sy[(int64_t)s * NT + r * W + ax] * gt[r * W + ax];
+#pragma unroll
+            for (int c = 0; c < 2 * M; ++c) acc -= B1[(int64_t)(s * 2 * M + c) * W + r] * wl[s * 2 * M + c];
+            zs[i] = acc;
+        }
     }
     phase_sync();
     for (int s = wv; s < 2 * M; s += nw) {   // y_S -= L_SS^{-1} h
