@@ -336,11 +336,12 @@ __device__ __forceinline__ void patch_interior(const int pid, Dims d, PatchArgs 
     __shared__ T red[NTH];   // one 64-row partial per wavefront
     __shared__ T zs[NS], wl[NL];   // level-1 and leaf work vectors of the top x level-1 coupling
     // the 2m slice inverses are applied four times (forward, the coupling, backward twice):
-    // staged once in LDS while they fit in 8 KB, and in FP32 from degree 11 on (18-49 KB:
-    // meshes at those degrees have few patches per CU, so the LDS costs no residency),
-    // else read from the factor each time
+    // staged once in LDS while they fit in 9 KB (FP64 p=7 included: its registers already
+    // hold it to 4 workgroups per CU, and the LDS fits 4), and in FP32 from degree 11 on
+    // (18-49 KB: meshes at those degrees have few patches per CU, so the LDS costs no
+    // residency), else read from the factor each time
     constexpr int LS = W * (W + 1) / 2, NSEP = 2 * M * LS;
-    constexpr bool SEP_LDS = NSEP * sizeof(T) <= 8192 || (sizeof(T) == 4 && P >= 11);
+    constexpr bool SEP_LDS = NSEP * sizeof(T) <= 9216 || (sizeof(T) == 4 && P >= 11);
     __shared__ T sL[SEP_LDS ? NSEP : 1];
     constexpr int nt = NTH, nw = NTH / 64;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
