@@ -178,9 +178,11 @@ const T *xm(const vsr_problem *P, int kind) {
     else return P->xm32[kind];
 }
 
-// out = alpha * S in + beta * out,  S = T (sum_j Rbar_j^T A_j^{-1} Rbar_j) T^T  (Sec. 2.4-2.6)
+// out = alpha * S in + beta * out,  S = T (sum_j Rbar_j^T A_j^{-1} Rbar_j) T^T  (Sec. 2.4-2.6);
+// out64, dotv and partials as for launch_transfer (the prolongation writes out)
 template <typename T, typename Tin>
-void relax_apply(vsr_problem *P, const Tin *in, T *out, T alpha, T beta) {
+void relax_apply(vsr_problem *P, const Tin *in, T *out, T alpha, T beta, double *out64 = nullptr,
+                 const double *dotv = nullptr, double *partials = nullptr) {
     const int L[3] = {P->d.Lx, P->d.Ly, P->d.Lz}, NC[3] = {P->d.nx, P->d.ny, P->d.nz};
     T *rF = (T *)P->rF, *zF = (T *)P->zF, *U = (T *)P->U;
     launch_transfer<Tin, T>(XFER_FDM_RESTRICT, P->d.p, NC, L, L, xm<T>(P, XFER_FDM_RESTRICT), in, rF, T(1), T(0),
@@ -204,7 +206,8 @@ void relax_apply(vsr_problem *P, const Tin *in, T *out, T alpha, T beta) {
         ++P->events_used;
     }
     launch_patch_assemble<T>(P->d, P->opt.interior_patches_only, U, zF, P->ex());
-    launch_transfer<T, T>(XFER_FDM_PROLONG, P->d.p, NC, L, L, xm<T>(P, XFER_FDM_PROLONG), zF, out, alpha, beta, P->ex());
+    launch_transfer<T, T>(XFER_FDM_PROLONG, P->d.p, NC, L, L, xm<T>(P, XFER_FDM_PROLONG), zF, out, alpha, beta, P->ex(),
+                          out64, dotv, partials);
     VSR_HIP(hipGetLastError());
 }
 
@@ -247,7 +250,16 @@ void precondition(vsr_problem *P, const double *r, double *z, int mode, int dot_
         op_residual<T>(P, r, z1, res);
         coarse_apply<T, T>(P, res, z1, T(1), T(1));
         op_residual<T>(P, r, z1, res);
-        relax_apply<T, T>(P, res, z1, w, T(1));
+        // the last prolongation also writes z in FP64 and, when asked, the partials of r.z
+        const bool dot = dot_mode >= 0;
+        relax_apply<T, T>(P, res, z1, w, T(1), z, dot ? r : nullptr, dot ? P->partials : nullptr);
+        if (dot) {
+            const int NC[3] = {P->d.nx, P->d.ny, P->d.nz};
+            launch_finalize(transfer_blocks(XFER_FDM_PROLONG, P->d.p, NC), P->partials, P->scal, dot_mode, P->mirror,
+                            P->ex());
+        }
+        VSR_HIP(hipGetLastError());
+        return;
     }
     if (dot_mode >= 0) {
         const int nb = launch_axpby_to_double<T>(P->n, 1.0, z1, 0.0, z, P->ex(), r, P->partials);
@@ -868,7 +880,9 @@ vsr_status vsr_setup(const vsr_mesh *mesh, int32_t p, const vsr_coefficients *co
         P->vt = P->dalloc<double>(P->n);
         P->scal = P->dalloc<double>(SC_N);
         // partial sums: dot passes (at most 8192 workgroups) and the lattice-line gathers
-        P->partials = P->dalloc<double>(std::max<int64_t>(8192, gather_blocks(P->d)));
+        const int NCp[3] = {P->d.nx, P->d.ny, P->d.nz};
+        P->partials = P->dalloc<double>(std::max<int64_t>(
+            std::max<int64_t>(8192, gather_blocks(P->d)), transfer_blocks(XFER_FDM_PROLONG, P->d.p, NCp)));
         VSR_HIP(hipHostMalloc((void **)&P->host_scal, sizeof(double) * SC_N, hipHostMallocDefault));
         if (P->fp32) launch_fill<float>(nv * w3, (float *)P->U, 0.f, P->ex());
         else launch_fill<double>(nv * w3, (double *)P->U, 0.0, P->ex());

@@ -59,10 +59,16 @@ void launch_load_vector(const Dims &d, const double *IDq, const double *wdet, co
 // FDM restriction r~ = T^T r and prolongation z = T z~ on the free fine lattice (Sec. 2.4);
 // Q1 restriction P^T (fine -> interior coarse vertices) and prolongation P (Sec. 2.5).
 // kind is one of XFER_* (vsr_internal.h) and M its OA x K block matrix (transfer_block);
-// out = alpha * (map) in + beta * out.
+// out = alpha * (map) in + beta * out.  With out64 non-null every output is also stored
+// there widened to FP64; with partials non-null too, each workgroup leaves its sum of
+// dotv . out64 over the outputs it owns in partials[block] (transfer_blocks of them, zeros
+// from workgroups that own none) for launch_finalize.
 template <typename Tin, typename T>
 void launch_transfer(int kind, int p, const int ncell[3], const int in_dims[3], const int out_dims[3], const T *M,
-                     const Tin *in, T *out, T alpha, T beta, const Exec &e);
+                     const Tin *in, T *out, T alpha, T beta, const Exec &e, double *out64 = nullptr,
+                     const double *dotv = nullptr, double *partials = nullptr);
+// Workgroups of one launch_transfer of this kind.
+int transfer_blocks(int kind, int p, const int ncell[3]);
 
 struct PatchArgs {
     int m, w;

@@ -20,6 +20,19 @@ using namespace dev;
 constexpr int XFER_THREADS = 256;
 constexpr int XFER_LDS_BUDGET = 48 * 1024;
 
+// Sum over the workgroup, valid in thread 0 (fixed order: waves by index).
+__device__ __forceinline__ double xfer_block_sum(double v) {
+    __shared__ double part[XFER_THREADS / 64];
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) part[wv] = v;
+    __syncthreads();
+    double s = 0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < XFER_THREADS / 64; ++i) s += part[i];
+    return s;
+}
+
 // Per axis, cell e maps inputs e*IS + in_off + s (s < K) to outputs e*out_step + a (a < OA)
 // with the OA x K row-major matrix M.  out = alpha * (M x M x M) in + beta * out.
 // A workgroup takes a brick of CX x CY x 1 cells: their windows along x and y overlap and
@@ -29,7 +42,8 @@ template <typename Tin, typename T, int OA, int K, int IS, int CX, int CY>
 __global__ void __launch_bounds__(XFER_THREADS)
     k_transfer(const double *__restrict__ gate, const T *__restrict__ M, int ncx, int ncy, int ncz, int in_off,
                int out_step, int ix, int iy, int iz, int ox, int oy, int oz, const Tin *__restrict__ in,
-               T *__restrict__ out, T alpha, T beta) {
+               T *__restrict__ out, T alpha, T beta, double *__restrict__ out64, const double *__restrict__ dotv,
+               double *__restrict__ partials) {
     if (gated(gate)) return;
     constexpr int KX = K + (CX - 1) * IS, KY = K + (CY - 1) * IS;   // window extents along x and y
     constexpr int AX = CX * OA, AY = CY * OA;                       // outputs along x and y
@@ -50,7 +64,10 @@ __global__ void __launch_bounds__(XFER_THREADS)
     // bricks so that the overlapping windows meet in the same L2
     const int nbx = (ncx + CX - 1) / CX, nby = (ncy + CY - 1) / CY, nb = nbx * nby * ncz, per = (nb + 7) / 8;
     const int brick = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
-    if (brick >= nb) return;
+    if (brick >= nb) {
+        if (partials != nullptr && threadIdx.x == 0) partials[blockIdx.x] = 0.0;
+        return;
+    }
     const int bx = brick % nbx, by = (brick / nbx) % nby, ez = brick / (nbx * nby);
     const int tid = threadIdx.x;
     const int x0 = bx * CX * IS + in_off, y0 = by * CY * IS + in_off, z0 = ez * IS + in_off;
@@ -126,6 +143,7 @@ __global__ void __launch_bounds__(XFER_THREADS)
         }
         __syncthreads();
     }
+    double prod = 0.0;
     if (tid < AX * AY) {
         const int xo = (bx * CX + za / OA) * out_step + za % OA, yo = (by * CY + zb / OA) * out_step + zb % OA;
         if (xo < ox && yo < oy) {
@@ -134,10 +152,19 @@ __global__ void __launch_bounds__(XFER_THREADS)
                 const int zo = ez * out_step + c;
                 if (zo < oz) {
                     const int64_t q = ((int64_t)zo * oy + yo) * ox + xo;
-                    out[q] = beta == T(0) ? alpha * acc[c] : alpha * acc[c] + beta * out[q];
+                    const T v = beta == T(0) ? alpha * acc[c] : alpha * acc[c] + beta * out[q];
+                    out[q] = v;
+                    if (out64 != nullptr) {
+                        out64[q] = (double)v;
+                        if (dotv != nullptr) prod += dotv[q] * (double)v;
+                    }
                 }
             }
         }
+    }
+    if (partials != nullptr) {
+        prod = xfer_block_sum(prod);
+        if (tid == 0) partials[blockIdx.x] = prod;
     }
 }
 
@@ -150,18 +177,30 @@ constexpr int brick_y(int kind, int OA) { return kind != XFER_FDM_RESTRICT && 4 
 
 }  // namespace
 
+int transfer_blocks(int kind, int p, const int ncell[3]) {
+    const int OA = kind == XFER_COARSE_RESTRICT ? 1 : p, CX = brick_x(kind, OA), CY = brick_y(kind, OA);
+    const int nb = ((ncell[0] + CX - 1) / CX) * ((ncell[1] + CY - 1) / CY) * ncell[2];
+    return 8 * ((nb + 7) / 8);
+}
+
 template <typename Tin, typename T>
 void launch_transfer(int kind, int p, const int ncell[3], const int in_dims[3], const int out_dims[3], const T *M,
-                     const Tin *in, T *out, T alpha, T beta, const Exec &e) {
+                     const Tin *in, T *out, T alpha, T beta, const Exec &e, double *out64, const double *dotv,
+                     double *partials) {
     const int nc = ncell[0] * ncell[1] * ncell[2];
-    if (nc == 0 || (int64_t)out_dims[0] * out_dims[1] * out_dims[2] == 0) return;
+    if (nc == 0 || (int64_t)out_dims[0] * out_dims[1] * out_dims[2] == 0) {
+        const int nb = transfer_blocks(kind, p, ncell);
+        if (partials != nullptr && nb > 0) launch_fill<double>(nb, partials, 0.0, e);
+        return;
+    }
 #define GO(KIND, OA, K, IS, IO, OS)                                                                                    \
     {                                                                                                                  \
         constexpr int CX = brick_x(KIND, OA), CY = brick_y(KIND, OA);                                                  \
         const int nb = ((ncell[0] + CX - 1) / CX) * ((ncell[1] + CY - 1) / CY) * ncell[2];                            \
         hipLaunchKernelGGL((k_transfer<Tin, T, OA, K, IS, CX, CY>), dim3(8u * (unsigned)((nb + 7) / 8)),              \
                            dim3(XFER_THREADS), 0, e.s, e.gate, M, ncell[0], ncell[1], ncell[2], IO, OS, in_dims[0],   \
-                           in_dims[1], in_dims[2], out_dims[0], out_dims[1], out_dims[2], in, out, alpha, beta);      \
+                           in_dims[1], in_dims[2], out_dims[0], out_dims[1], out_dims[2], in, out, alpha, beta,       \
+                           out64, dotv, partials);                                                                    \
     }
 #define CALL(P)                                                               \
     switch (kind) {                                                           \
@@ -177,10 +216,13 @@ void launch_transfer(int kind, int p, const int ncell[3], const int in_dims[3], 
 }
 
 template void launch_transfer<double, double>(int, int, const int *, const int *, const int *, const double *,
-                                              const double *, double *, double, double, const Exec &);
+                                              const double *, double *, double, double, const Exec &, double *,
+                                              const double *, double *);
 template void launch_transfer<float, float>(int, int, const int *, const int *, const int *, const float *,
-                                            const float *, float *, float, float, const Exec &);
+                                            const float *, float *, float, float, const Exec &, double *,
+                                            const double *, double *);
 template void launch_transfer<double, float>(int, int, const int *, const int *, const int *, const float *,
-                                             const double *, float *, float, float, const Exec &);
+                                             const double *, float *, float, float, const Exec &, double *,
+                                             const double *, double *);
 
 }  // namespace vsr
