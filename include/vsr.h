@@ -95,6 +95,12 @@ typedef struct {
                                 Cartesian mesh with constant kappa) are factored once and share
                                 the first one's stored factor (the others' patch matrices differ
                                 from it by ~1e-11 relative).  0: one factor per star (default). */
+    int32_t deterministic;   /* 1: every patch-panel partial sum is taken by one thread in a fixed
+                                order instead of being combined with LDS atomics, so relaxations,
+                                preconditioner applies and PCG iterates repeat bit for bit from run
+                                to run (the operator, load vector, transfers, assembly and dot
+                                products are always in a fixed order); slower panels.
+                                0: atomics where they are faster (default). */
 } vsr_options;
 
 typedef struct {

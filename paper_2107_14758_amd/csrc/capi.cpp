@@ -821,6 +821,7 @@ vsr_status vsr_setup(const vsr_mesh *mesh, int32_t p, const vsr_coefficients *co
         a.top_pad = L.top_pad; a.ntiles = L.ntiles;
         a.off_invd = L.off_invd; a.off_B1 = L.off_B1; a.off_B2 = L.off_B2; a.off_Lsep = L.off_Lsep; a.off_Sy = L.off_Sy;
         a.off_Ltop = L.off_Ltop; a.stride = L.stride;
+        a.det = P->opt.deterministic != 0;
         int m = L.m, w = L.w;
         // stored entries of one interior factor: leaves, B1 and B2, level-1 slice inverses, the
         // y-diagonal top x separator block, the top-plane factor
@@ -905,8 +906,8 @@ int64_t vsr_num_dofs(const vsr_problem *prob) { return prob ? prob->n : -1; }
 vsr_status vsr_load_vector(vsr_problem *P, const double *f, double *b) {
     return guarded([&] {
         if (!P || !f || !b) throw Error(VSR_EINVAL, "NULL argument");
-        launch_fill<double>(P->n, b, 0.0, P->ex());
-        launch_load_vector(P->d, P->IDq64, P->wdet, f, b, P->ex());
+        launch_load_vector(P->d, P->IDq64, P->wdet, f, P->E64, P->ex());
+        launch_gather<double>(P->d, 1, P->E64, nullptr, b, P->ex());
         VSR_HIP(hipGetLastError());
     });
 }

@@ -51,8 +51,9 @@ void launch_gather(const Dims &d, int slots, const T *E, const double *r, T *out
 int64_t gather_blocks(const Dims &d);
 // Adds nb partial sums in a fixed order and applies them to scal by mode (see launch_dot).
 void launch_finalize(int nb, const double *partials, double *scal, int mode, double *mirror, const Exec &e);
-// b += sum_K R_K^T (I x I x I)^T (wdet .* f)
-void launch_load_vector(const Dims &d, const double *IDq, const double *wdet, const double *f, double *b,
+// Cell blocks E_K = (I x I x I)^T (wdet .* f) of the load vector, in the element-vector
+// layout (one slot); launch_gather with slots = 1 turns them into b = sum_K R_K^T E_K.
+void launch_load_vector(const Dims &d, const double *IDq, const double *wdet, const double *f, double *E,
                         const Exec &e);
 
 // Lattice transfers, each in one launch (M x M x M with a cell-blocked 1D map M):
@@ -74,6 +75,7 @@ struct PatchArgs {
     int m, w;
     int n_leaf, n_sep, n_top, n_iface, top_pad, ntiles;
     int64_t off_invd, off_B1, off_B2, off_Lsep, off_Sy, off_Ltop, stride;
+    int det;   // 1: every panel sum taken by one thread in a fixed order (no LDS atomics)
 };
 
 // All patches in one launch (interior first, then boundary).

@@ -355,10 +355,11 @@ __global__ void __launch_bounds__(XB) k_gather(const double *__restrict__ gate, 
     }
 }
 
-// Load vector (Sec. 2.1): b += sum_K R_K^T (I x I x I)^T (w |det DF| f).
+// Load vector (Sec. 2.1), cell part: E_K = (I x I x I)^T (w |det DF| f) into the cell's block
+// of the element vector; k_gather sums the blocks that share a node in a fixed order.
 template <int P>
 __global__ void __launch_bounds__(1024) k_load_vector(const double *__restrict__ gate, Dims d, const double *__restrict__ IDq, const double *__restrict__ wdet,
-                                                      const double *__restrict__ f, double *__restrict__ bvec) {
+                                                      const double *__restrict__ f, double *__restrict__ E) {
     if (gated(gate)) return;
     constexpr int N1 = P + 1, Q = QOF(P), Q2 = Q * Q, Q3 = Q2 * Q;
     __shared__ double sI[Q * N1], X1[N1 * Q], S0[Q2];
@@ -395,8 +396,7 @@ __global__ void __launch_bounds__(1024) k_load_vector(const double *__restrict__
             int jj = t / N1, ii = t % N1;
             double s = 0;
             for (int aa = 0; aa < Q; ++aa) s += sI[aa * N1 + ii] * X1[jj * Q + aa];
-            int K = P * ez + k, J = P * ey + jj, I = P * ex + ii;
-            if (is_free(d, K, J, I)) atomic_add_global(&bvec[free_index(d, K, J, I)], s);
+            E[elem_index<N1>(d, ex, ey, ez, k, jj, ii)] = s;
         }
     }
 }
@@ -659,10 +659,10 @@ int launch_op_general(const Dims &d, const T *IDq, const T *Gw, const T *x, T *E
 
 
 
-void launch_load_vector(const Dims &d, const double *IDq, const double *wdet, const double *f, double *b, const Exec &e) {
+void launch_load_vector(const Dims &d, const double *IDq, const double *wdet, const double *f, double *E, const Exec &e) {
     int64_t ncell = (int64_t)d.nx * d.ny * d.nz;
 #define CALL(P) \
-    hipLaunchKernelGGL((k_load_vector<P>), dim3((unsigned)ncell), dim3(round64(QOF(P) * QOF(P))), 0, e.s, e.gate, d, IDq, wdet, f, b)
+    hipLaunchKernelGGL((k_load_vector<P>), dim3((unsigned)ncell), dim3(round64(QOF(P) * QOF(P))), 0, e.s, e.gate, d, IDq, wdet, f, E)
     VSR_P_SWITCH(d.p, CALL)
 #undef CALL
 }

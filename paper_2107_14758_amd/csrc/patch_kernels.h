@@ -176,14 +176,15 @@ __device__ __forceinline__ Vec4<double> load4<double>(const double *p) {
 
 // y[r] -= sum_c M[c * ld + r] x[c] for r < nrows (ld multiple of 4, M 16-byte aligned);
 // x, y in LDS.  Work split over (row quads) x (column chunks), accumulated with LDS atomics;
-// each thread keeps U column loads in flight.
+// each thread keeps U column loads in flight.  det: one chunk per row quad, so every sum is
+// taken by one thread in column order (no atomics; bitwise repeatable, fewer threads busy).
 template <typename T, int U, int NTH>
-__device__ void panel_fwd(const T *__restrict__ M, int ld, int nrows, int ncols, const T *x, T *y) {
+__device__ void panel_fwd(const T *__restrict__ M, int ld, int nrows, int ncols, const T *x, T *y, bool det) {
     const int tid = threadIdx.x;
     constexpr int nt = NTH;
     const int nq = (nrows + 3) / 4;
     if (nq == 0 || ncols == 0) return;
-    int nch = max(1, min((ncols + U - 1) / U, nt / nq));
+    int nch = det ? 1 : max(1, min((ncols + U - 1) / U, nt / nq));
     int chunk = (ncols + nch - 1) / nch;
     for (int task = tid; task < nq * nch; task += nt) {
         int rq = task % nq, ch = task / nq;
@@ -226,9 +227,10 @@ __device__ void panel_fwd(const T *__restrict__ M, int ld, int nrows, int ncols,
 // and its lanes split their rows, so every load instruction reads whole cache lines; G
 // loads in flight per lane; the G sums are reduced across the wavefront and stored by lane
 // 0 (each column has one owner, no atomics).  Short columns: a thread streams one (column, row chunk) with
-// U loads in flight; chunks of one column meet in an LDS atomic.
+// U loads in flight; chunks of one column meet in an LDS atomic (det: one chunk per column,
+// summed by one thread in row order).
 template <typename T, int U, int NTH>
-__device__ void panel_bwd(const T *__restrict__ M, int ld, int nrows, int ncols, const T *x, T *y) {
+__device__ void panel_bwd(const T *__restrict__ M, int ld, int nrows, int ncols, const T *x, T *y, bool det) {
     const int tid = threadIdx.x;
     constexpr int nt = NTH, NW = NTH / 64;
     const int nq = (nrows + 3) / 4;
@@ -260,7 +262,7 @@ __device__ void panel_bwd(const T *__restrict__ M, int ld, int nrows, int ncols,
         }
         return;
     }
-    int nrc = max(1, min((nq + U - 1) / U, nt / ncols));
+    int nrc = det ? 1 : max(1, min((nq + U - 1) / U, nt / ncols));
     int chunk = (nq + nrc - 1) / nrc;
     for (int task = tid; task < ncols * nrc; task += nt) {
         int c = task % ncols, rc = task / ncols;
@@ -472,7 +474,7 @@ __device__ __forceinline__ void patch_interior(const int pid, Dims d, PatchArgs 
         phase_sync();
         const T *D = F + tile_offset(A.off_Ltop, NT, J);
         const int rows = NT - c0 - nb;
-        panel_fwd<T, UNR, NTH>(D + 64 * 65 / 2, (rows + 3) / 4 * 4, rows, nb, gt + c0, gt + c0 + nb);
+        panel_fwd<T, UNR, NTH>(D + 64 * 65 / 2, (rows + 3) / 4 * 4, rows, nb, gt + c0, gt + c0 + nb, A.det != 0);
         if (J + 1 < NTILE) stage_tile(J + 1);
         phase_sync();
     }
@@ -487,7 +489,7 @@ __device__ __forceinline__ void patch_interior(const int pid, Dims d, PatchArgs 
         if (J > 0) {
             const int cp = 64 * (J - 1), nbp = 64, rows = NT - cp - nbp;
             const T *Dp = F + tile_offset(A.off_Ltop, NT, J - 1);
-            panel_bwd<T, UNR, NTH>(Dp + 64 * 65 / 2, (rows + 3) / 4 * 4, rows, nbp, gt + cp + nbp, gt + cp);
+            panel_bwd<T, UNR, NTH>(Dp + 64 * 65 / 2, (rows + 3) / 4 * 4, rows, nbp, gt + cp + nbp, gt + cp, A.det != 0);
             stage_tile(J - 1);
         }
         phase_sync();

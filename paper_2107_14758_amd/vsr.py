@@ -38,7 +38,7 @@ class Options(ctypes.Structure):
                 ("interior_patches_only", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("omega", ctypes.c_double), ("stream", ctypes.c_void_p), ("autotune", ctypes.c_int32),
                 ("batch_streams", ctypes.c_int32), ("batch_eager", ctypes.c_int32), ("tune_cache", ctypes.c_char_p),
-                ("share_factors", ctypes.c_int32)]
+                ("share_factors", ctypes.c_int32), ("deterministic", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -111,9 +111,17 @@ def _check(status):
         raise VsrError(status, lib().vsr_last_error().decode())
 
 
-def _ptr(t):
+def _ptr(t, numel=None):
+    """Device pointer of a contiguous float64 CUDA tensor holding exactly `numel` values.
+
+    The kernels read or write exactly that many entries through the pointer, so a
+    shorter tensor is rejected here instead of being overrun on the device."""
     import torch
-    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("vectors must be contiguous float64 CUDA tensors")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"vector has {t.numel()} entries, expected {numel}")
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
         raise TypeError("vectors must be contiguous float64 CUDA tensors")
     return ctypes.c_void_p(t.data_ptr())
 
@@ -123,11 +131,18 @@ class _Inputs:
 
     def __init__(self, vertices, kappa=None, mu_override=None):
         self.V = np.ascontiguousarray(vertices, dtype=np.float64)
+        if self.V.ndim != 4 or self.V.shape[3] != 3 or min(self.V.shape[:3]) < 2:
+            raise ValueError(f"vertices must have shape (nz+1, ny+1, nx+1, 3), got {self.V.shape}")
         nz, ny, nx = self.V.shape[0] - 1, self.V.shape[1] - 1, self.V.shape[2] - 1
+        ncell = nx * ny * nz
         self.shape = (nx, ny, nz)
         self.mesh = Mesh(nx, ny, nz, self.V.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
         self.kappa = None if kappa is None else np.ascontiguousarray(kappa, dtype=np.float64).reshape(-1)
         self.mu = None if mu_override is None else np.ascontiguousarray(mu_override, dtype=np.float64).reshape(-1)
+        if self.kappa is not None and self.kappa.size != ncell:
+            raise ValueError(f"kappa has {self.kappa.size} values, expected one per cell ({ncell})")
+        if self.mu is not None and self.mu.size != 3 * ncell:
+            raise ValueError(f"mu_override has {self.mu.size} values, expected 3 per cell ({3 * ncell})")
         self.coef = Coefficients(
             None if self.kappa is None else self.kappa.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
             None if self.mu is None else self.mu.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
@@ -135,7 +150,7 @@ class _Inputs:
 
 def make_options(relax_fp32=False, cycle=0, lanczos_steps=20, max_iterations=1000, interior_patches_only=False, seed=0,
                  omega=0.0, stream=None, autotune=False, batch_streams=0, batch_eager=False, tune_cache=None,
-                 share_factors=False):
+                 share_factors=False, deterministic=False):
     opt = Options()
     lib().vsr_default_options(ctypes.byref(opt))
     opt.relax_fp32 = int(bool(relax_fp32))
@@ -151,6 +166,7 @@ def make_options(relax_fp32=False, cycle=0, lanczos_steps=20, max_iterations=100
     opt.batch_eager = int(bool(batch_eager))
     opt.tune_cache = None if tune_cache is None else os.fsencode(tune_cache)
     opt.share_factors = int(bool(share_factors))
+    opt.deterministic = int(bool(deterministic))
     return opt
 
 
@@ -174,6 +190,7 @@ class Problem:
         self.p = p
         self.n = int(L.vsr_num_dofs(h))
         self.q = (3 * (p + 1) + 1) // 2
+        self.ncell = None if self.shape is None else self.shape[0] * self.shape[1] * self.shape[2]
 
     def tuning(self):
         """Launch shapes in use: (Cartesian-operator cells/workgroup FP64, FP32, panel unroll,
@@ -198,17 +215,17 @@ class Problem:
             pass
 
     def load_vector(self, f, b):
-        _check(lib().vsr_load_vector(self._h, _ptr(f), _ptr(b)))
+        _check(lib().vsr_load_vector(self._h, _ptr(f, None if self.ncell is None else self.ncell * self.q ** 3), _ptr(b, self.n)))
 
     def apply_operator(self, x, y):
-        _check(lib().vsr_apply_operator(self._h, _ptr(x), _ptr(y)))
+        _check(lib().vsr_apply_operator(self._h, _ptr(x, self.n), _ptr(y, self.n)))
 
     def apply_relaxation(self, r, z, mode=0):
-        _check(lib().vsr_apply_relaxation(self._h, _ptr(r), _ptr(z), int(mode)))
+        _check(lib().vsr_apply_relaxation(self._h, _ptr(r, self.n), _ptr(z, self.n), int(mode)))
 
     def pcg_solve(self, b, x, rtol=1e-8, raise_on_noconv=True):
         info = SolveInfo()
-        st = lib().vsr_pcg_solve(self._h, _ptr(b), _ptr(x), float(rtol), ctypes.byref(info))
+        st = lib().vsr_pcg_solve(self._h, _ptr(b, self.n), _ptr(x, self.n), float(rtol), ctypes.byref(info))
         if st != VSR_OK and (raise_on_noconv or st != VSR_ENOCONV):
             _check(st)
         out = info.as_dict()
@@ -270,8 +287,8 @@ class Batch:
         count = len(self.members)
         if len(bs) != count or len(xs) != count:
             raise ValueError("one b and one x per member")
-        bp = (ctypes.c_void_p * count)(*[_ptr(b).value for b in bs])
-        xp = (ctypes.c_void_p * count)(*[_ptr(x).value for x in xs])
+        bp = (ctypes.c_void_p * count)(*[_ptr(b, m.n).value for b, m in zip(bs, self.members)])
+        xp = (ctypes.c_void_p * count)(*[_ptr(x, m.n).value for x, m in zip(xs, self.members)])
         infos = (SolveInfo * count)()
         st = lib().vsr_pcg_solve_batch(self._h, bp, xp, float(rtol), infos)
         if st != VSR_OK and (raise_on_noconv or st != VSR_ENOCONV):
@@ -320,11 +337,30 @@ def _dp(a):
     return None if a is None else a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
-def _tp(t, dtype):
+def _tp(t, dtype, numel=None):
+    """Device pointer of a contiguous CUDA tensor of `dtype` holding exactly `numel` values."""
     import torch
-    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"expected a contiguous {dtype} CUDA tensor")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"tensor has {t.numel()} entries, expected {numel}")
+    if not (t.is_cuda and t.dtype == dtype and t.is_contiguous()):
         raise TypeError(f"expected a contiguous {dtype} CUDA tensor")
     return ctypes.c_void_p(t.data_ptr())
+
+
+def _rows(X, width, name):
+    """Number of rows of a (rows, width) sample matrix."""
+    if X.dim() != 2 or X.shape[1] != width:
+        raise ValueError(f"{name} must have shape (n, {width}), got {tuple(X.shape)}")
+    return int(X.shape[0])
+
+
+def _cells(corners):
+    C = np.ascontiguousarray(corners, dtype=np.float64)
+    if C.ndim < 2 or C.size != 24 * C.shape[0]:
+        raise ValueError(f"corners must hold 24 values per cell, got shape {C.shape}")
+    return C
 
 
 def mesh_corners(vertices):
@@ -346,9 +382,11 @@ def mlp_num_params():
 def surrogate_features(corners, p, kappa=None):
     import torch
     L = _setup_surrogate_signatures()
-    C = np.ascontiguousarray(corners, dtype=np.float64)
+    C = _cells(corners)
     n = C.shape[0]
     k = None if kappa is None else np.ascontiguousarray(kappa, dtype=np.float64)
+    if k is not None and k.size != n:
+        raise ValueError("kappa must hold one value per cell")
     X = torch.empty((n, 74), dtype=torch.float32, device="cuda")
     mu = np.empty((n, 3))
     _check(L.vsr_surrogate_features(n, _dp(C), _dp(k), int(p), _tp(X, torch.float32), _dp(mu)))
@@ -357,8 +395,10 @@ def surrogate_features(corners, p, kappa=None):
 
 def surrogate_ratio(corners, mu):
     L = _setup_surrogate_signatures()
-    C = np.ascontiguousarray(corners, dtype=np.float64)
+    C = _cells(corners)
     m = np.ascontiguousarray(mu, dtype=np.float64)
+    if m.size != 3 * C.shape[0]:
+        raise ValueError("mu must hold 3 values per cell")
     r = np.empty(C.shape[0])
     _check(L.vsr_surrogate_ratio(C.shape[0], _dp(C), _dp(m), _dp(r)))
     return r
@@ -366,7 +406,7 @@ def surrogate_ratio(corners, mu):
 
 def surrogate_labels(corners, p):
     L = _setup_surrogate_signatures()
-    C = np.ascontiguousarray(corners, dtype=np.float64)
+    C = _cells(corners)
     d = np.empty((C.shape[0], 3))
     r = np.empty(C.shape[0])
     _check(L.vsr_surrogate_labels(C.shape[0], _dp(C), int(p), _dp(d), _dp(r)))
@@ -376,8 +416,9 @@ def surrogate_labels(corners, p):
 def mlp_forward(params, X, bf16=True):
     import torch
     L = _setup_surrogate_signatures()
-    Y = torch.empty((X.shape[0], 3), dtype=torch.float32, device="cuda")
-    _check(L.vsr_mlp_forward(_tp(params, torch.float32), int(bool(bf16)), _tp(X, torch.float32), X.shape[0],
+    n = _rows(X, 74, "X")
+    Y = torch.empty((n, 3), dtype=torch.float32, device="cuda")
+    _check(L.vsr_mlp_forward(_tp(params, torch.float32, mlp_num_params()), int(bool(bf16)), _tp(X, torch.float32), n,
                              _tp(Y, torch.float32)))
     return Y
 
@@ -385,19 +426,26 @@ def mlp_forward(params, X, bf16=True):
 def mlp_gradient(params, X, T, bf16=True):
     import torch
     L = _setup_surrogate_signatures()
+    n = _rows(X, 74, "X")
     g = torch.empty_like(params)
     loss = torch.empty(1, dtype=torch.float32, device="cuda")
-    _check(L.vsr_mlp_gradient(_tp(params, torch.float32), int(bool(bf16)), _tp(X, torch.float32),
-                              _tp(T, torch.float32), X.shape[0], _tp(g, torch.float32), _tp(loss, torch.float32)))
+    _check(L.vsr_mlp_gradient(_tp(params, torch.float32, mlp_num_params()), int(bool(bf16)), _tp(X, torch.float32),
+                              _tp(T, torch.float32, 3 * n), n, _tp(g, torch.float32), _tp(loss, torch.float32)))
     return g, loss
 
 
 def mlp_train(params, m, v, X, T, order, batch, steps, step0=0, lr=1e-3, bf16=True):
     import torch
     L = _setup_surrogate_signatures()
+    n = _rows(X, 74, "X")
+    npar = mlp_num_params()
+    if order.numel() < int(steps) * int(batch):
+        raise ValueError(f"order has {order.numel()} entries, {int(steps) * int(batch)} needed")
+    if order.numel() and (int(order.min()) < 0 or int(order.max()) >= n):
+        raise ValueError("order holds a row index outside [0, n)")
     losses = torch.empty(steps, dtype=torch.float32, device="cuda")
-    _check(L.vsr_mlp_train(_tp(params, torch.float32), _tp(m, torch.float32), _tp(v, torch.float32),
-                           int(bool(bf16)), _tp(X, torch.float32), _tp(T, torch.float32), X.shape[0],
+    _check(L.vsr_mlp_train(_tp(params, torch.float32, npar), _tp(m, torch.float32, npar), _tp(v, torch.float32, npar),
+                           int(bool(bf16)), _tp(X, torch.float32), _tp(T, torch.float32, 3 * n), n,
                            _tp(order, torch.int32), int(batch), int(steps), int(step0), float(lr),
                            _tp(losses, torch.float32)))
     return losses
@@ -406,10 +454,13 @@ def mlp_train(params, m, v, X, T, order, batch, steps, step0=0, lr=1e-3, bf16=Tr
 def surrogate_scalings(corners, p, params, kappa=None, bf16=True):
     import torch
     L = _setup_surrogate_signatures()
-    C = np.ascontiguousarray(corners, dtype=np.float64)
+    C = _cells(corners)
     k = None if kappa is None else np.ascontiguousarray(kappa, dtype=np.float64)
+    if k is not None and k.size != C.shape[0]:
+        raise ValueError("kappa must hold one value per cell")
     mu = np.empty((C.shape[0], 3))
     used = np.empty(C.shape[0], dtype=np.int32)
-    _check(L.vsr_surrogate_scalings(C.shape[0], _dp(C), _dp(k), int(p), _tp(params, torch.float32), int(bool(bf16)),
+    _check(L.vsr_surrogate_scalings(C.shape[0], _dp(C), _dp(k), int(p), _tp(params, torch.float32, mlp_num_params()),
+                                    int(bool(bf16)),
                                     _dp(mu), used.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
     return mu, used

@@ -3,6 +3,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -77,3 +78,36 @@ def test_batch_create_argument_checks_without_gpu_work():
     null_members = (ctypes.c_void_p * 2)(None, None)
     st = L.vsr_batch_create(2, null_members, None, ctypes.byref(h))
     assert st == vsr.VSR_EINVAL and b"NULL member 0" in L.vsr_last_error()
+
+
+def test_binding_rejects_wrong_lengths_and_shapes_before_any_device_call():
+    """The kernels read and write exactly n entries through each vector pointer, so the
+    binding checks every length (and the host arrays' shapes) before calling the library."""
+    torch = pytest.importorskip("torch")
+    from paper_2107_14758_amd import inputs, vsr
+    V = inputs.cube_vertices(2, 3, 2)
+    with pytest.raises(ValueError):
+        vsr._Inputs(V[..., :2])                       # two coordinates per vertex
+    with pytest.raises(ValueError):
+        vsr._Inputs(V, kappa=np.ones(11))              # 12 cells
+    with pytest.raises(ValueError):
+        vsr._Inputs(V, mu_override=np.ones(35))
+    ok = vsr._Inputs(V, kappa=np.ones(12), mu_override=np.ones((12, 3)))
+    assert ok.shape == (2, 3, 2)
+    # a problem handle stand-in: only the sizes are read before the length checks fire
+    prob = object.__new__(vsr.Problem)
+    prob._h, prob._owned, prob.p, prob.q = ctypes.c_void_p(), False, 3, 6
+    prob.n, prob.ncell = 5 * 8 * 5, 12
+    short, right = torch.zeros(prob.n - 1, dtype=torch.float64), torch.zeros(prob.n, dtype=torch.float64)
+    for call in (lambda: prob.apply_operator(short, right), lambda: prob.apply_relaxation(short, right, 1),
+                 lambda: prob.pcg_solve(short, right),
+                 lambda: prob.load_vector(torch.zeros(12 * 6 ** 3 - 1, dtype=torch.float64), right),
+                 lambda: vsr._ptr(short, prob.n)):
+        with pytest.raises(ValueError):
+            call()
+    with pytest.raises(TypeError):                      # right length, but host memory
+        prob.apply_operator(right, right.clone())
+    with pytest.raises(ValueError):
+        vsr._rows(torch.zeros(4, 73), 74, "X")
+    with pytest.raises(ValueError):
+        vsr._cells(np.zeros((3, 23)))

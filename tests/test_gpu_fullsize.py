@@ -1,11 +1,18 @@
 """GPU parity at the full workload sizes, in the configuration bench.py times.
 
-The oracle cannot solve these sizes quickly, so each check uses what it can
-compute exactly: the full operator apply and load vector (sum factorization is
-cheap), the relaxation on sampled cells (the values on a cell's nodes depend
-only on the patches of the cell's eight vertices), and properties of the
-solution (true residual recomputed by the oracle, FP32 vs FP64 agreement).
+The oracle cannot solve these sizes within a test, so each check uses what it can
+compute: the full operator apply and load vector (sum factorization is cheap), the
+relaxation on sampled cells (the values on a cell's nodes depend only on the patches
+of the cell's eight vertices), the true residual recomputed by the oracle's operator,
+and the oracle's own PCG solution, stored at 2048 sampled entries (with its iteration
+count, damping and norms) by tests/golden/make_fullsize_oracle.py, which calls only
+the oracle.  The FP64 solve must match it to 1e-10 and the FP32-relaxation solve
+(the benchmarked form) to 1e-6, entry by entry (max-abs over the sample) and in the
+2-norm over the sample.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -25,8 +32,27 @@ WORKLOADS = [
 ]
 
 
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
 def say(*a):
     print(*a, flush=True)
+
+
+def golden(name):
+    path = os.path.join(GOLDEN, f"oracle_pcg_{name}.json")
+    if not os.path.exists(path):
+        return None
+    g = json.load(open(path))
+    g["idx"] = np.array(g["indices"], dtype=np.int64)
+    g["xs"] = np.array([float.fromhex(v) for v in g["x_sample_hex"]])
+    return g
+
+
+def sampled_errors(x, g):
+    """(max-abs error / max |x_oracle|, 2-norm error / 2-norm of x_oracle), over the sample."""
+    e = x[g["idx"]] - g["xs"]
+    return float(np.abs(e).max() / np.abs(g["xs"]).max()), float(np.linalg.norm(e) / np.linalg.norm(g["xs"]))
 
 
 def rel(a, b):
@@ -102,6 +128,7 @@ def test_fullsize(vsr, name, cells):
     # FP64 and FP32-relaxation solves: true residual by the oracle's operator
     x64 = torch.zeros_like(y)
     info64 = prob64.pcg_solve(b, x64)
+    damping64 = prob64.damping()
     prob64.close()
     prob32 = vsr.Problem(w["vertices"], p, kappa=w["kappa"], seed=0, relax_fp32=True)
     x32 = torch.zeros_like(y)
@@ -115,3 +142,18 @@ def test_fullsize(vsr, name, cells):
     assert res64 <= 1.0001e-8 and res32 <= 1.0001e-8
     assert info32["iterations"] <= info64["iterations"] + 2
     assert rel(xh32, xh64) < 1e-6
+    # the oracle's own solution (stored samples)
+    g = golden(name)
+    if g is None:
+        pytest.skip(f"no stored oracle solution for {name} (tests/golden/make_fullsize_oracle.py writes it)")
+    assert g["n"] == d.n and abs(np.linalg.norm(b_o) - g["b_norm2"]) <= 1e-12 * g["b_norm2"]
+    e64 = sampled_errors(xh64, g)
+    e32 = sampled_errors(xh32, g)
+    say(f"  vs oracle x: fp64 max {e64[0]:.2e} 2-norm {e64[1]:.2e}; fp32 max {e32[0]:.2e} 2-norm {e32[1]:.2e}; "
+        f"oracle iterations {g['iterations']}")
+    om, lmin, lmax = damping64
+    assert abs(om - g["omega"]) < 1e-9 * g["omega"] and abs(lmax - g["lambda_max"]) < 1e-9 * g["lambda_max"]
+    assert info64["iterations"] == g["iterations"]
+    assert info32["iterations"] <= g["iterations"] + 2
+    assert max(e64) <= 1e-10
+    assert max(e32) <= 1e-6

@@ -31,6 +31,16 @@ def rel(a, b):
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
 
 
+def relmax(a, b):
+    """Element-wise: the largest entry error over the largest entry of the reference."""
+    return float(np.max(np.abs(a - b))) / max(float(np.max(np.abs(b))), 1e-300)
+
+
+def close(a, b, tol):
+    """a matches b within tol both in the 2-norm and entry by entry (max-abs)."""
+    return rel(a, b) <= tol and relmax(a, b) <= tol
+
+
 def mesh(shape, p, seed=0, jitter=0.0, lognormal=False):
     nx, ny, nz = shape
     rng = np.random.default_rng(seed)
@@ -76,10 +86,10 @@ def test_operator_and_load_vector(vsr, name, shape, p, jit, logn):
     x = np.random.default_rng(2).uniform(-1, 1, d.n)
     y = torch.zeros(d.n, dtype=torch.float64, device="cuda")
     prob.apply_operator(dev(x), y)
-    assert rel(host(y), d.apply(x)) < 1e-12
+    assert close(host(y), d.apply(x), 1e-12)
     b = torch.zeros_like(y)
     prob.load_vector(dev(f), b)
-    assert rel(host(b), d.load_vector(f)) < 1e-12
+    assert close(host(b), d.load_vector(f), 1e-12)
 
 
 @pytest.mark.parametrize("name,shape,p,jit,logn", CASES)
@@ -93,11 +103,11 @@ def test_relaxation_modes(vsr, name, shape, p, jit, logn):
     r = np.random.default_rng(4).uniform(-1, 1, d.n)
     z = torch.zeros(d.n, dtype=torch.float64, device="cuda")
     prob.apply_relaxation(dev(r), z, 1)
-    assert rel(host(z), s.relax(r)) < 1e-11
+    assert close(host(z), s.relax(r), 1e-11)
     prob.apply_relaxation(dev(r), z, 2)
-    assert rel(host(z), s.coarse(r)) < 1e-11
+    assert close(host(z), s.coarse(r), 1e-11)
     prob.apply_relaxation(dev(r), z, 0)
-    assert rel(host(z), s.precondition(r)) < 1e-11
+    assert close(host(z), s.precondition(r), 1e-11)
 
 
 def test_interior_only_relaxation_and_exact_single_patch(vsr):
@@ -141,7 +151,7 @@ def test_damping_and_pcg_fp64(vsr, name, shape, p, jit, logn):
     info = prob.pcg_solve(dev(b), x)
     assert info["converged"] == 1 and info["iterations"] == it_o
     assert info["true_rel_residual"] <= 1.0001e-8
-    assert rel(host(x), x_o) < 1e-10
+    assert close(host(x), x_o, 1e-10)
 
 
 @pytest.mark.parametrize("name,shape,p,jit,logn", CASES[1:])
@@ -157,14 +167,111 @@ def test_fp32_relaxation(vsr, name, shape, p, jit, logn):
     r = np.random.default_rng(9).uniform(-1, 1, d.n)
     z = torch.zeros(d.n, dtype=torch.float64, device="cuda")
     prob.apply_relaxation(dev(r), z, 1)
-    assert rel(host(z), s.relax(r)) < 1e-5
+    assert close(host(z), s.relax(r), 1e-5)
     b = d.load_vector(f)
     x_o, it_o = s.pcg(b)
     x = torch.zeros(d.n, dtype=torch.float64, device="cuda")
     info = prob.pcg_solve(dev(b), x)
     assert info["converged"] == 1 and info["iterations"] <= it_o + 2
     assert info["true_rel_residual"] <= 1.0001e-8
-    assert rel(host(x), x_o) < 1e-6
+    assert close(host(x), x_o, 1e-6)
+
+
+@pytest.mark.parametrize("name,shape,p,jit,logn", CASES[1:])
+def test_fp32_preconditioner_and_coarse_apply(vsr, name, shape, p, jit, logn):
+    # FP32 coarse correction (mode 2) and the full FP32 V(1,1) cycle with its two FP32 inner
+    # operator applies (mode 0), one apply each, against the FP64 oracle at the 1e-5 bound
+    say("case", name)
+    V, kappa, f = mesh(shape, p, seed=14, jitter=jit, lognormal=logn)
+    d = Discretization(V, p, kappa)
+    s = Solver(d, setup_1d(p), omega=0.41)
+    prob = vsr.Problem(V, p, kappa=kappa, omega=0.41, relax_fp32=True)
+    r = np.random.default_rng(15).uniform(-1, 1, d.n)
+    z = torch.zeros(d.n, dtype=torch.float64, device="cuda")
+    prob.apply_relaxation(dev(r), z, 2)
+    assert close(host(z), s.coarse(r), 1e-5)
+    prob.apply_relaxation(dev(r), z, 0)
+    assert close(host(z), s.precondition(r), 1e-5)
+
+
+# Degrees 11 and 15 on jittered, log-normal 3^3 meshes: 8 interior stars with the full
+# nested-dissection factor (several top-plane tiles), 56 boundary stars.
+HIGH = [("jit_3x3x3_p11_kappa", (3, 3, 3), 11), ("jit_3x3x3_p15_kappa", (3, 3, 3), 15)]
+_oracle_high = {}
+
+
+def oracle_high(name, shape, p):
+    if name not in _oracle_high:
+        V, kappa, f = mesh(shape, p, seed=40 + p, jitter=0.15, lognormal=True)
+        d = Discretization(V, p, kappa)
+        s = Solver(d, setup_1d(p), seed=5)
+        b = d.load_vector(f)
+        x_o, it_o = s.pcg(b)
+        _oracle_high[name] = (V, kappa, b, s, x_o, it_o)
+    return _oracle_high[name]
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("fp32", [False, True], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("name,shape,p", HIGH)
+def test_pcg_high_degree(vsr, name, shape, p, fp32):
+    say("case", name, "fp32" if fp32 else "fp64")
+    V, kappa, b, s, x_o, it_o = oracle_high(name, shape, p)
+    prob = vsr.Problem(V, p, kappa=kappa, seed=5, relax_fp32=fp32)
+    w, lmin, lmax = prob.damping()
+    if not fp32:   # the Lanczos estimate runs the FP64 relaxation
+        assert abs(w - s.omega) < 1e-9 * s.omega
+    x = torch.zeros(len(b), dtype=torch.float64, device="cuda")
+    info = prob.pcg_solve(dev(b), x)
+    say(f"  iterations {info['iterations']} (oracle {it_o}) true residual {info['true_rel_residual']:.2e}")
+    assert info["converged"] == 1 and info["true_rel_residual"] <= 1.0001e-8
+    if fp32:
+        assert info["iterations"] <= it_o + 2
+        assert close(host(x), x_o, 1e-6)
+    else:
+        assert info["iterations"] == it_o
+        assert close(host(x), x_o, 1e-10)
+    prob.close()
+
+
+@pytest.mark.parametrize("fp32", [False, True], ids=["fp64", "fp32"])
+def test_deterministic_option_repeats_bit_for_bit(vsr, fp32):
+    """With deterministic = 1 every patch-panel sum is taken by one thread in a fixed order, so
+    relaxations and whole PCG solves repeat bit for bit; the results still match the oracle.
+    p = 7 on a 4 x 3 x 3 mesh: the first top-plane tile's panel is split over several threads
+    per row in the default mode (the case the option changes)."""
+    say("case deterministic", "fp32" if fp32 else "fp64")
+    V, kappa, f = mesh((4, 3, 3), 7, seed=16, jitter=0.1, lognormal=True)
+    d = Discretization(V, 7, kappa)
+    s = Solver(d, setup_1d(7), seed=2)
+    prob = vsr.Problem(V, 7, kappa=kappa, seed=2, relax_fp32=fp32, deterministic=True)
+    r = dev(np.random.default_rng(17).uniform(-1, 1, d.n))
+    zs = []
+    for _ in range(3):
+        z = torch.zeros_like(r)
+        prob.apply_relaxation(r, z, 1)
+        zs.append(z)
+    torch.cuda.synchronize()
+    assert all(torch.equal(zs[0], z) for z in zs[1:])
+    assert close(host(zs[0]), s.relax(host(r)), 1e-5 if fp32 else 1e-11)
+    b = dev(d.load_vector(f))
+    b2 = torch.zeros_like(b)
+    prob.load_vector(dev(f), b2)
+    b3 = torch.zeros_like(b)
+    prob.load_vector(dev(f), b3)
+    torch.cuda.synchronize()
+    assert torch.equal(b2, b3)                       # the load vector never uses atomics
+    xs, its = [], []
+    for _ in range(2):
+        x = torch.zeros_like(b)
+        info = prob.pcg_solve(b, x)
+        xs.append(x)
+        its.append(info["iterations"])
+    torch.cuda.synchronize()
+    assert its[0] == its[1] and torch.equal(xs[0], xs[1])
+    x_o, it_o = s.pcg(host(b))
+    assert close(host(xs[0]), x_o, 1e-6 if fp32 else 1e-10)
+    prob.close()
 
 
 def test_additive_cycle(vsr):
