@@ -133,6 +133,19 @@ vsr_status vsr_load_vector(vsr_problem *prob, const double *f_dev, double *b_dev
 /* y = A x, the matrix-free sum-factorized Galerkin operator (Sec. 2.1, 2.7), FP64. */
 vsr_status vsr_apply_operator(vsr_problem *prob, const double *x_dev, double *y_dev);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): y = A x exactly as vsr_apply_operator
+ * computes it (same kernels, same summation order, bitwise the same y), with the operator's
+ * element vector (2 * ncell * (p+1)^3 FP64 values at most) placed in a static device
+ * workspace of 64 MiB that the library holds on each GPU it runs on until the process ends,
+ * instead of the problem's own buffer.  The call allocates nothing: no hipMalloc, hipFree or
+ * allocating library routine.  Call it with the problem's device current.  Every call on a
+ * GPU shares that GPU's workspace, so calls that overlap on one GPU (from several threads or
+ * streams) race; the workspace keeps the last call's contents, which no call reads before
+ * writing.  VSR_EINVAL if 2 * ncell * (p+1)^3 * 8 bytes exceeds 64 MiB (e.g. more than 1,024
+ * cells at p = 15). */
+vsr_status vsr_apply_operator_noalloc(vsr_problem *prob, const double *x_dev, double *y_dev);
+
 /* z = M r with mode 0: the full preconditioner (cycle chosen at setup);
  * mode 1: the patch relaxation alone, z = T (sum_j Rbar_j^T A_j^{-1} Rbar_j) T^T r
  * (Sec. 2.4-2.6, undamped); mode 2: the coarse correction z = P A0^{-1} P^T r. */

@@ -919,6 +919,18 @@ vsr_status vsr_apply_operator(vsr_problem *P, const double *x, double *y) {
     });
 }
 
+vsr_status vsr_apply_operator_noalloc(vsr_problem *P, const double *x, double *y) {
+    return guarded([&] {
+        if (!P || !x || !y) throw Error(VSR_EINVAL, "NULL argument");
+        // the element vector (up to 2 slots per cell) goes to the static workspace
+        const int64_t n1 = P->d.p + 1;
+        double *E = static_cast<double *>(static_workspace((size_t)P->ncell * n1 * n1 * n1 * 2 * sizeof(double)));
+        const int slots = op_cells<double>(P, x, E);
+        launch_gather<double>(P->d, slots, E, nullptr, y, P->ex());
+        VSR_HIP(hipGetLastError());
+    });
+}
+
 vsr_status vsr_apply_relaxation(vsr_problem *P, const double *r, double *z, int32_t mode) {
     return guarded([&] {
         if (!P || !r || !z) throw Error(VSR_EINVAL, "NULL argument");

@@ -97,6 +97,11 @@ std::vector<double> make_coarse_inverse(int nx, int ny, int nz, const OneD &od, 
 enum { XFER_FDM_RESTRICT = 0, XFER_FDM_PROLONG = 1, XFER_COARSE_RESTRICT = 2, XFER_COARSE_PROLONG = 3 };
 std::vector<double> transfer_block(int kind, const OneD &od);
 
+// Device address (on the current device) of the library's static workspace, for callers
+// that cannot allocate; VSR_EINVAL if `bytes` exceeds its size (static_workspace_bytes()).
+void *static_workspace(size_t bytes);
+size_t static_workspace_bytes();
+
 // Symmetric tridiagonal extreme eigenvalues by Sturm bisection.
 void tridiag_extremes(const std::vector<double> &d, const std::vector<double> &e, double &lmin, double &lmax);
 

@@ -72,6 +72,7 @@ def lib():
     L.vsr_num_dofs.restype = ctypes.c_int64
     L.vsr_load_vector.argtypes = [P, dp, dp]
     L.vsr_apply_operator.argtypes = [P, dp, dp]
+    L.vsr_apply_operator_noalloc.argtypes = [P, dp, dp]
     L.vsr_apply_relaxation.argtypes = [P, dp, dp, ctypes.c_int32]
     L.vsr_pcg_solve.argtypes = [P, dp, dp, ctypes.c_double, ctypes.POINTER(SolveInfo)]
     L.vsr_get_damping.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
@@ -98,7 +99,7 @@ def lib():
     L.vsr_destroy_batch.restype = None
     L.vsr_last_error.argtypes = []
     L.vsr_last_error.restype = ctypes.c_char_p
-    for name in ("vsr_setup", "vsr_load_vector", "vsr_apply_operator", "vsr_apply_relaxation", "vsr_pcg_solve",
+    for name in ("vsr_setup", "vsr_load_vector", "vsr_apply_operator", "vsr_apply_operator_noalloc", "vsr_apply_relaxation", "vsr_pcg_solve",
                  "vsr_get_damping", "vsr_set_profiling", "vsr_kernel_stats", "vsr_factor_info", "vsr_get_tuning", "vsr_set_tuning",
                  "vsr_setup_batch", "vsr_batch_create", "vsr_pcg_solve_batch"):
         getattr(L, name).restype = ctypes.c_int
@@ -219,6 +220,10 @@ class Problem:
 
     def apply_operator(self, x, y):
         _check(lib().vsr_apply_operator(self._h, _ptr(x, self.n), _ptr(y, self.n)))
+
+    def apply_operator_noalloc(self, x, y):
+        """y = A x through the allocation-free entry point (static device workspace)."""
+        _check(lib().vsr_apply_operator_noalloc(self._h, _ptr(x, self.n), _ptr(y, self.n)))
 
     def apply_relaxation(self, r, z, mode=0):
         _check(lib().vsr_apply_relaxation(self._h, _ptr(r, self.n), _ptr(z, self.n), int(mode)))
