@@ -165,4 +165,5 @@ def test_learned_surrogate_gain(vsr):
     say("  PCG iterations " + ", ".join(f"{k} {i} ({t * 1e3:.1f} ms)" for k, (i, t, _) in its.items()))
     for k in its:
         assert its[k][2] <= 1.0001e-8
-    assert its["learned"][0] <= its["averaged"][0] + 1
+    # the learned scalings must not cost iterations against the averaged surrogate
+    assert its["learned"][0] <= its["averaged"][0]
