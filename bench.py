@@ -64,6 +64,24 @@ def measured_traffic():
         return None
 
 
+def error_vs_oracle(name, x):
+    """Error of a solution against the FP64 oracle's PCG solution of the same workload, stored
+    at sampled entries by tests/golden/make_fullsize_oracle.py (None if not stored): max-abs
+    error over max |x_oracle| and 2-norm error over the 2-norm of x_oracle, on the sample."""
+    path = os.path.join(ROOT, "tests", "golden", f"oracle_pcg_{name}.json")
+    if not os.path.exists(path):
+        return None
+    g = json.load(open(path))
+    idx = np.array(g["indices"], dtype=np.int64)
+    xo = np.array([float.fromhex(v) for v in g["x_sample_hex"]])
+    if g["n"] != len(x):
+        return None
+    e = x[idx] - xo
+    return {"max_abs_rel": float(np.abs(e).max() / np.abs(xo).max()),
+            "norm2_rel": float(np.linalg.norm(e) / np.linalg.norm(xo)),
+            "sampled_entries": int(len(idx)), "oracle_iterations": int(g["iterations"])}
+
+
 def solve_timed(vsr, torch, w, relax_fp32, steps, warmup, profile, autotune=False, share_factors=False):
     prob = vsr.Problem(w["vertices"], w["p"], kappa=w["kappa"], relax_fp32=relax_fp32, seed=0, autotune=autotune,
                        share_factors=share_factors)
@@ -93,8 +111,9 @@ def solve_timed(vsr, torch, w, relax_fp32, steps, warmup, profile, autotune=Fals
         stats = prob.kernel_stats()
         prob.set_profiling(False)
     npatch, nentries = prob.factor_info()
+    torch.cuda.synchronize()
     out = dict(n=n, seconds=dt, iterations=iters[-1], info=info, stats=stats, setup_s=info["setup_seconds"],
-               patches=npatch, factor_entries=nentries, shapes=list(prob.tuning()))
+               patches=npatch, factor_entries=nentries, shapes=list(prob.tuning()), x=x.cpu().numpy())
     prob.close()
     return out
 
@@ -151,28 +170,48 @@ def batch_timed(vsr, torch, W, steps, warmup, share_factors=False):
     return out
 
 
-def cpu_baseline(p, cells=4, seed=0):
-    """The FP64 oracle (untuned) on a bounded sample of the workload: the same degree,
-    RHS distribution and solver on a cells^3 Cartesian mesh; PCG solve time only."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(p, cells=6, seed=0, workload=WORKLOAD):
+    """The FP64 oracle (untuned) on a bounded sample of the workload: a cells^3 Cartesian mesh
+    at the same degree, with the same right-hand side distribution, preconditioner and
+    tolerance (a full solve of the 16^3 Q7 workload takes the oracle minutes of setup and
+    solve).  The PCG solve is timed (setup excluded) twice: with numpy's BLAS pool held to one
+    thread, which is the headline (the oracle's patch loops are single-threaded Python, so one
+    thread is what it uses), and with the pool at its default size."""
+    from threadpoolctl import threadpool_info, threadpool_limits
+
     from oracle.fdm1d import setup_1d
     from oracle.operator import Discretization
     from oracle.solver import Solver
     from paper_2107_14758_amd import inputs
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
-    except Exception:
-        cores = 1
     w = inputs.make_problem(cells, p, seed=seed)
     d = Discretization(w["vertices"], p)
     b = d.load_vector(w["f"])
     s = Solver(d, setup_1d(p), seed=0)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        _, it = s.pcg(b)
+        dt1 = time.perf_counter() - t0
+    pool = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
     t0 = time.perf_counter()
-    _, it = s.pcg(b)
-    dt = time.perf_counter() - t0
-    return {"value": d.n / dt, "unit": "DOF/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"oracle PCG solve (setup excluded) on a {cells}x{cells}x{cells}-cell Cartesian mesh at p={p}, "
-                      f"{d.n} DOFs, {it} iterations, {dt:.1f} s; same RHS distribution and preconditioner"}
+    _, it2 = s.pcg(b)
+    dtn = time.perf_counter() - t0
+    return {"value": d.n / dt1, "unit": "DOF/s", "cores": 1, "kind": "oracle",
+            "sample": f"{workload}: the oracle's PCG solve (setup excluded) on a {cells}x{cells}x{cells}-cell "
+                      f"Cartesian mesh at p={p} ({d.n} DOFs, {it} iterations, {dt1:.1f} s) with the same degree, "
+                      f"right-hand side distribution, preconditioner and tolerance",
+            "threads": 1, "nproc": os.cpu_count(), "cpu_model": cpu_model(),
+            "blas_pool": {"value": d.n / dtn, "threads": int(pool), "seconds": dtn, "iterations": it2,
+                          "note": "numpy BLAS pool at its default size; the patch loops stay single-threaded"}}
 
 
 def main():
@@ -240,10 +279,12 @@ def main():
         "patches": r32["patches"], "factor_entries": r32["factor_entries"],
         "roofline": roofline,
     }
+    out["fp32_err_vs_oracle"] = error_vs_oracle(wname, r32["x"])
     if r64:
         ms64 = 1e3 * r64["seconds"] / max(3, args.steps // 4)
         out["fp64_plain"] = {"value": n / (ms64 * 1e-3), "unit": "DOF/s", "ms_per_step": ms64,
-                             "iterations": r64["iterations"], "true_rel_residual": r64["info"]["true_rel_residual"]}
+                             "iterations": r64["iterations"], "true_rel_residual": r64["info"]["true_rel_residual"],
+                             "err_vs_oracle": error_vs_oracle(wname, r64["x"])}
     if wname == WORKLOAD and not args.no_fp64:
         # iterations and rates at p = 15 on the 8^3 jittered log-normal workload
         w15 = inputs.workload("poisson_jitter_8x8x8_q15_lognormal", seed=0)
@@ -267,7 +308,7 @@ def main():
         log(f"[bench] shared factors: {rs['iterations']} iterations, {ms_s:.2f} ms/solve")
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
-        out["cpu_baseline"] = cpu_baseline(p, cells=6 if p <= 7 else 3)
+        out["cpu_baseline"] = cpu_baseline(p, cells=8 if p <= 7 else 3, workload=wname)
     print(json.dumps(out), flush=True)
 
 
@@ -310,7 +351,7 @@ def main_batch(args, torch, inputs, vsr):
     out["roofline"]["member"] = f"{W[big]['n']}^3 cells p={W[big]['p']} (largest), single solve"
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
-        out["cpu_baseline"] = cpu_baseline(4, cells=4)
+        out["cpu_baseline"] = cpu_baseline(4, cells=4, workload="batch64_uneven_p4-15")
         out["cpu_baseline"]["sample"] += " (the smallest member class of the batch)"
     print(json.dumps(out), flush=True)
 
