@@ -17,6 +17,7 @@ relaxation for high-order FEM", Sec. 2):
                    and sum-factorized, and the load vector (Sec. 2.1)
 * ``transfer``  -- GLL<->FDM basis change and the Q1 coarse space (Sec. 2.4, 2.5)
 * ``patches``   -- vertex-star patches and their solves (Sec. 2.5, 2.6)
+* ``gmg``       -- geometric multigrid for the Q1 coarse problem (Sec. 2.8)
 * ``solver``    -- Lanczos damping, hybrid V(1,1) preconditioner, PCG (Sec. 2.5, 2.8)
 
 Everything is float64 numpy/scipy.  Library primitives (matmul, symmetric

@@ -5,7 +5,9 @@ Test infrastructure only (see ``oracle/__init__``).
 * Relaxation (Sec. 2.5): S r = sum_j Rbar_j^T A_j^{-1} Rbar_j r with the
   surrogate patch matrices, applied in the FDM basis through the change of
   basis of Sec. 2.4:  S r = T (sum_j Rbar_j^T A_F,j^{-1} Rbar_j) T^T r.
-* Coarse correction (Sec. 2.5): C r = P A_0^{-1} P^T r, dense Cholesky of A_0.
+* Coarse correction (Sec. 2.5): C r = P A_0^{-1} P^T r, dense Cholesky of A_0
+  (coarse="direct"), or C r = P B P^T r with B one V(1,1) cycle of geometric
+  multigrid for A_0 (coarse="gmg", Sec. 2.8 and ``gmg``).
 * Hybrid V(1,1) (Sec. 2.5, multiplicative between the two levels, additive
   among patches):  z1 = w S r;  z2 = z1 + C (r - A z1);  z = z2 + w S (r - A z2).
   The fully additive variant is z = S r + C r.
@@ -24,6 +26,7 @@ import numpy as np
 import scipy.linalg as sla
 
 from . import transfer
+from .gmg import Q1Multigrid
 from .patches import Patches
 
 ALPHA = 0.25
@@ -52,13 +55,21 @@ def uniform_pm1(seed, n):
 
 class Solver:
     def __init__(self, disc, od, mu=None, omega=None, lanczos_steps=20, seed=0, cycle="hybrid",
-                 interior_only=False):
+                 interior_only=False, coarse="direct"):
         self.disc = disc
         self.od = od
         self.patches = Patches(disc, od, mu, interior_only)
         self.T = od["T"]
-        self.A0 = transfer.coarse_matrix(disc) if disc.nx > 1 and disc.ny > 1 and disc.nz > 1 else None
-        self.A0chol = sla.cho_factor(self.A0, lower=True) if self.A0 is not None and self.A0.size else None
+        has_coarse = disc.nx > 1 and disc.ny > 1 and disc.nz > 1
+        self.mg = None
+        self.A0 = self.A0chol = None
+        if coarse == "gmg":
+            self.mg = Q1Multigrid.for_discretization(disc) if has_coarse else None
+        elif coarse == "direct":
+            self.A0 = transfer.coarse_matrix(disc) if has_coarse else None
+            self.A0chol = sla.cho_factor(self.A0, lower=True) if self.A0 is not None and self.A0.size else None
+        else:
+            raise ValueError("coarse must be 'direct' or 'gmg'")
         self.cycle = cycle
         self.lanczos = None
         if omega is None:
@@ -77,6 +88,9 @@ class Solver:
         return transfer.fdm_prolong(self.disc, self.T, uF)
 
     def coarse(self, r):
+        if self.mg is not None:
+            rc = transfer.coarse_restrict(self.disc, r)
+            return transfer.coarse_prolong(self.disc, self.mg.vcycle(rc))
         if self.A0chol is None:
             return np.zeros_like(r)
         rc = transfer.coarse_restrict(self.disc, r)
