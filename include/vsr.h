@@ -101,6 +101,12 @@ typedef struct {
                                 to run (the operator, load vector, transfers, assembly and dot
                                 products are always in a fixed order); slower panels.
                                 0: atomics where they are faster (default). */
+    int32_t coarse_solver;   /* solver of the Q1 coarse problem (Sec. 2.5, 2.8): 1: dense inverse
+                                of its Galerkin matrix (exact); 2: one V(1,1) cycle of geometric
+                                multigrid (damped point-Jacobi with weight 2/3 on every level, 2x2x2
+                                cell coarsening while every axis has an even number >= 4 of cells,
+                                Galerkin levels, dense inverse on the coarsest level); 0 (default):
+                                dense up to 8,000 coarse unknowns (21^3 cells), multigrid above */
 } vsr_options;
 
 typedef struct {

@@ -76,6 +76,9 @@ struct vsr_problem {
     int cdim[3] = {0, 0, 0};
     int nc = 0;
     void *A0inv = nullptr;
+    int coarse_gmg = 0;               // 1: the coarse problem is solved by a multigrid V-cycle
+    MGCycle<float> mg32{};
+    MGCycle<double> mg64{};
     // work buffers (cycle precision unless noted)
     void *rF = nullptr, *zF = nullptr, *U = nullptr;
     void *c3 = nullptr, *c4 = nullptr;    // coarse right-hand side and solution
@@ -131,6 +134,41 @@ struct vsr_problem {
 };
 
 namespace {
+
+// Dense coarse inverse up to this many Q1 unknowns (21^3 cells) under coarse_solver = 0.
+constexpr int kAutoDenseCoarse = 8000;
+
+// Device copy of a multigrid hierarchy in the cycle precision T.  Level 0's right-hand side and
+// solution are the coarse-space vectors c3 and c4 of the Q1 transfers.
+template <typename T>
+void build_mg(vsr_problem *P, const MGHierarchyHost &H, MGCycle<T> &M) {
+    M = MGCycle<T>{};
+    M.nlev = (int)H.levels.size();
+    M.cinv = (const T *)P->A0inv;
+    for (int l = 0; l < M.nlev; ++l) {
+        const MGLevelHost &h = H.levels[l];
+        MGLevel<T> &L = M.L[l];
+        L.cx = h.cx; L.cy = h.cy; L.cz = h.cz;
+        const int64_t nv = (int64_t)(h.cx - 1) * (h.cy - 1) * (h.cz - 1);
+        std::vector<double> dinv(nv);
+        for (int64_t i = 0; i < nv; ++i) {
+            const double dg = h.st[(size_t)13 * nv + i];
+            if (!(dg > 0)) throw Error(VSR_ENOTSPD, "non-positive diagonal in a multigrid level");
+            dinv[i] = 1.0 / dg;
+        }
+        L.st = P->upload_as<T>(h.st);
+        L.dinv = P->upload_as<T>(dinv);
+        L.r = P->dalloc<T>(nv);
+        L.t = P->dalloc<T>(nv);
+        if (l == 0) {
+            L.b = (T *)P->c3;
+            L.x = (T *)P->c4;
+        } else {
+            L.b = P->dalloc<T>(nv);
+            L.x = P->dalloc<T>(nv);
+        }
+    }
+}
 
 // The cell-local operator into the element vector of precision T; returns its slots per cell.
 template <typename T>
@@ -223,7 +261,12 @@ void coarse_apply(vsr_problem *P, const Tin *in, T *out, T alpha, T beta) {
     T *c3 = (T *)P->c3, *c4 = (T *)P->c4;
     launch_transfer<Tin, T>(XFER_COARSE_RESTRICT, P->d.p, NC, L, c, xm<T>(P, XFER_COARSE_RESTRICT), in, c3, T(1), T(0),
                             P->ex());
-    launch_dense_gemv<T>(P->nc, (const T *)P->A0inv, c3, c4, T(1), T(0), P->ex());
+    if (P->coarse_gmg) {
+        if constexpr (std::is_same<T, double>::value) launch_mg_vcycle<double>(P->mg64, P->ex());
+        else launch_mg_vcycle<float>(P->mg32, P->ex());
+    } else {
+        launch_dense_gemv<T>(P->nc, (const T *)P->A0inv, c3, c4, T(1), T(0), P->ex());
+    }
     launch_transfer<T, T>(XFER_COARSE_PROLONG, P->d.p, NC, c, L, xm<T>(P, XFER_COARSE_PROLONG), c4, out, alpha, beta,
                           P->ex());
     VSR_HIP(hipGetLastError());
@@ -851,10 +894,20 @@ vsr_status vsr_setup(const vsr_mesh *mesh, int32_t p, const vsr_coefficients *co
             P->xm64[k] = P->upload(M);
             P->xm32[k] = P->upload_as<float>(M);
         }
-        // coarse space
-        std::vector<double> A0inv = make_coarse_inverse(nx, ny, nz, P->od, g);
+        // coarse space: dense inverse of the Q1 matrix, or its multigrid hierarchy (Sec. 2.8)
         P->nc = P->cdim[0] * P->cdim[1] * P->cdim[2];
-        P->A0inv = P->fp32 ? (void *)P->upload_as<float>(A0inv) : (void *)P->upload(A0inv);
+        if (P->opt.coarse_solver < 0 || P->opt.coarse_solver > 2)
+            throw Error(VSR_EINVAL, "coarse_solver must be 0 (automatic), 1 (dense) or 2 (multigrid)");
+        P->coarse_gmg = P->opt.coarse_solver == 2 || (P->opt.coarse_solver == 0 && P->nc > kAutoDenseCoarse);
+        MGHierarchyHost H;
+        if (P->coarse_gmg) {
+            H = make_mg_hierarchy(nx, ny, nz, P->od, g);
+            if ((int)H.levels.size() > kMGMaxLevels) throw Error(VSR_EINVAL, "too many multigrid levels");
+            P->A0inv = P->fp32 ? (void *)P->upload_as<float>(H.coarsest_inverse) : (void *)P->upload(H.coarsest_inverse);
+        } else {
+            std::vector<double> A0inv = make_coarse_inverse(nx, ny, nz, P->od, g);
+            P->A0inv = P->fp32 ? (void *)P->upload_as<float>(A0inv) : (void *)P->upload(A0inv);
+        }
         // work buffers
         size_t es = esz;
         int64_t w3 = (int64_t)w * w * w;
@@ -874,6 +927,10 @@ vsr_status vsr_setup(const vsr_mesh *mesh, int32_t p, const vsr_coefficients *co
         }
         P->c3 = alloc_t(P->nc);
         P->c4 = alloc_t(P->nc);
+        if (P->coarse_gmg) {
+            if (P->fp32) build_mg<float>(P.get(), H, P->mg32);
+            else build_mg<double>(P.get(), H, P->mg64);
+        }
         P->vp = P->dalloc<double>(P->n);
         P->vq = P->dalloc<double>(P->n);
         P->vr = P->dalloc<double>(P->n);

@@ -90,6 +90,32 @@ void launch_patch_assemble(const Dims &d, int interior_only, const T *U, T *zF, 
 template <typename T>
 void launch_dense_gemv(int n, const T *A, const T *x, T *y, T alpha, T beta, const Exec &e);
 
+// Geometric multigrid for the p-coarse (Q1) problem (Sec. 2.8).  Level l has cx x cy x cz
+// cells and (cx-1)(cy-1)(cz-1) interior vertices (x fastest); st: its 27-point stencil stored
+// [s][vertex], s = (dz+1) 9 + (dy+1) 3 + (dx+1); dinv: inverse diagonal; x, b, r, t: work
+// vectors (solution, right-hand side, residual, corrected iterate).  Level l+1 halves every
+// axis; transfers are trilinear in index space.  cinv: dense inverse of the last level.
+constexpr int kMGMaxLevels = 12;
+constexpr int64_t kMGTailVertices = 8192;   // levels this small run in one single-workgroup launch
+constexpr int64_t kMGTailCoarsest = 1024;   // coarsest solved inside that launch up to this size
+template <typename T>
+struct MGLevel {
+    int cx = 0, cy = 0, cz = 0;
+    const T *st = nullptr, *dinv = nullptr;
+    T *x = nullptr, *b = nullptr, *r = nullptr, *t = nullptr;
+};
+template <typename T>
+struct MGCycle {
+    int nlev = 0;
+    T omega = T(2) / T(3);   // damped point-Jacobi weight
+    const T *cinv = nullptr;
+    MGLevel<T> L[kMGMaxLevels];
+};
+// One V(1,1) cycle from zero: L[0].x = B L[0].b (one Jacobi step before and after the coarse
+// correction on every level, the coarsest solved with cinv).  nlev = 1 is the direct solve.
+template <typename T>
+void launch_mg_vcycle(const MGCycle<T> &M, const Exec &e);
+
 // ---- vector kernels (double unless noted)
 template <typename Tin, typename Tout>
 void launch_cast(int64_t n, const Tin *x, Tout *y, const Exec &e);

@@ -897,20 +897,10 @@ PatchSet make_patches(int nx, int ny, int nz, const OneD &od, const double *mu, 
 }
 
 // ============================================================ coarse space (Sec. 2.5)
-std::vector<double> make_coarse_inverse(int nx, int ny, int nz, const OneD &od, const Geometry &g) {
-    int cx = nx - 1, cy = ny - 1, cz = nz - 1;
-    int64_t nc = (int64_t)cx * cy * cz;
-    if (nc == 0) return {};
-    int q = od.q;
-    int64_t nq3 = (int64_t)q * q * q;
-    int64_t bw = (int64_t)cx * cy + cx + 1;   // half bandwidth in lexicographic order
-    // banded lower storage: Ab[i][k] = A0(i, i - bw + k), k in [0, bw]
-    std::vector<double> Ab((size_t)nc * (bw + 1), 0.0);
-    auto add = [&](int64_t i, int64_t j, double v) {
-        if (j > i || i - j > bw) return;
-        Ab[(size_t)i * (bw + 1) + (j - i + bw)] += v;
-    };
-    // Q1 reference gradients at the quadrature points
+// Q1 reference gradients at the q^3 quadrature points: gr[(pt * 8 + corner) * 3 + axis].
+static std::vector<double> q1_gradients(const OneD &od) {
+    const int q = od.q;
+    const int64_t nq3 = (int64_t)q * q * q;
     std::vector<double> gr((size_t)nq3 * 8 * 3);
     for (int c = 0; c < q; ++c)
         for (int b = 0; b < q; ++b)
@@ -929,32 +919,56 @@ std::vector<double> make_coarse_inverse(int nx, int ny, int nz, const OneD &od, 
                             gr[(pt * 8 + loc) * 3 + 2] = N[0] * N[1] * dN[2];
                         }
             }
+    return gr;
+}
+
+// Q1 element matrix of cell e under the operator's quadrature (corners x fastest).
+static void q1_element(const OneD &od, const Geometry &g, const std::vector<double> &gr, int64_t e, double K[8][8]) {
+    const int q = od.q;
+    const int64_t nq3 = (int64_t)q * q * q;
+    for (int s = 0; s < 8; ++s)
+        for (int t = 0; t < 8; ++t) K[s][t] = 0.0;
+    for (int64_t pt = 0; pt < nq3; ++pt) {
+        double G[3][3];
+        if (!g.Gw.empty()) {
+            const double *o = &g.Gw[(e * 6) * nq3 + pt];
+            G[0][0] = o[0]; G[1][1] = o[nq3]; G[2][2] = o[2 * nq3];
+            G[0][1] = G[1][0] = o[3 * nq3]; G[0][2] = G[2][0] = o[4 * nq3]; G[1][2] = G[2][1] = o[5 * nq3];
+        } else {
+            int a = (int)(pt % q), b = (int)((pt / q) % q), c = (int)(pt / ((int64_t)q * q));
+            double w = od.wq[a] * od.wq[b] * od.wq[c];
+            for (int r = 0; r < 3; ++r)
+                for (int s2 = 0; s2 < 3; ++s2) G[r][s2] = r == s2 ? w * g.mu[e * 3 + r] : 0.0;
+        }
+        for (int s = 0; s < 8; ++s) {
+            const double *gs = &gr[(pt * 8 + s) * 3];
+            double Gg[3];
+            for (int r = 0; r < 3; ++r) Gg[r] = G[r][0] * gs[0] + G[r][1] * gs[1] + G[r][2] * gs[2];
+            for (int t = 0; t < 8; ++t) {
+                const double *gt = &gr[(pt * 8 + t) * 3];
+                K[t][s] += gt[0] * Gg[0] + gt[1] * Gg[1] + gt[2] * Gg[2];
+            }
+        }
+    }
+}
+
+std::vector<double> make_coarse_inverse(int nx, int ny, int nz, const OneD &od, const Geometry &g) {
+    int cx = nx - 1, cy = ny - 1, cz = nz - 1;
+    int64_t nc = (int64_t)cx * cy * cz;
+    if (nc == 0) return {};
+    int64_t bw = (int64_t)cx * cy + cx + 1;   // half bandwidth in lexicographic order
+    // banded lower storage: Ab[i][k] = A0(i, i - bw + k), k in [0, bw]
+    std::vector<double> Ab((size_t)nc * (bw + 1), 0.0);
+    auto add = [&](int64_t i, int64_t j, double v) {
+        if (j > i || i - j > bw) return;
+        Ab[(size_t)i * (bw + 1) + (j - i + bw)] += v;
+    };
+    const std::vector<double> gr = q1_gradients(od);
     int64_t ncell = (int64_t)nx * ny * nz;
     for (int64_t e = 0; e < ncell; ++e) {
         int i = (int)(e % nx), j = (int)((e / nx) % ny), k = (int)(e / ((int64_t)nx * ny));
-        double K[8][8] = {{0}};
-        for (int64_t pt = 0; pt < nq3; ++pt) {
-            double G[3][3];
-            if (!g.Gw.empty()) {
-                const double *o = &g.Gw[(e * 6) * nq3 + pt];
-                G[0][0] = o[0]; G[1][1] = o[nq3]; G[2][2] = o[2 * nq3];
-                G[0][1] = G[1][0] = o[3 * nq3]; G[0][2] = G[2][0] = o[4 * nq3]; G[1][2] = G[2][1] = o[5 * nq3];
-            } else {
-                int a = (int)(pt % q), b = (int)((pt / q) % q), c = (int)(pt / ((int64_t)q * q));
-                double w = od.wq[a] * od.wq[b] * od.wq[c];
-                for (int r = 0; r < 3; ++r)
-                    for (int s = 0; s < 3; ++s) G[r][s] = r == s ? w * g.mu[e * 3 + r] : 0.0;
-            }
-            for (int s = 0; s < 8; ++s) {
-                const double *gs = &gr[(pt * 8 + s) * 3];
-                double Gg[3];
-                for (int r = 0; r < 3; ++r) Gg[r] = G[r][0] * gs[0] + G[r][1] * gs[1] + G[r][2] * gs[2];
-                for (int t = 0; t < 8; ++t) {
-                    const double *gt = &gr[(pt * 8 + t) * 3];
-                    K[t][s] += gt[0] * Gg[0] + gt[1] * Gg[1] + gt[2] * Gg[2];
-                }
-            }
-        }
+        double K[8][8];
+        q1_element(od, g, gr, e, K);
         int64_t id[8];
         for (int cc = 0; cc < 2; ++cc)
             for (int bb = 0; bb < 2; ++bb)
@@ -1002,6 +1016,160 @@ std::vector<double> make_coarse_inverse(int nx, int ny, int nz, const OneD &od, 
         for (int64_t i = 0; i < nc; ++i) inv[(size_t)i * nc + col] = x[i];
     }
     return inv;
+}
+
+// ============================================================ Q1 geometric multigrid (Sec. 2.8)
+// The p-coarse problem solved by geometric multigrid: level 0 is the Q1 Galerkin matrix of the
+// mesh over its interior vertices, stored as a 27-point stencil per vertex; each next level
+// merges 2 x 2 x 2 cells (while every axis has an even number of at least 4 cells) and is the
+// Galerkin product P^T A P with the trilinear index-space interpolation P (fine vertex 2I takes
+// coarse vertex I, fine vertex 2I +- 1 half of I and half of its neighbour; Dirichlet zeros on
+// the boundary).
+std::vector<double> q1_stencil(int nx, int ny, int nz, const OneD &od, const Geometry &g) {
+    const int cx = nx - 1, cy = ny - 1, cz = nz - 1;
+    const int64_t nv = (int64_t)cx * cy * cz;
+    std::vector<double> st((size_t)27 * nv, 0.0);
+    if (nv == 0) return st;
+    const std::vector<double> gr = q1_gradients(od);
+    const int64_t ncell = (int64_t)nx * ny * nz;
+    for (int64_t e = 0; e < ncell; ++e) {
+        const int i = (int)(e % nx), j = (int)((e / nx) % ny), k = (int)(e / ((int64_t)nx * ny));
+        double K[8][8];
+        q1_element(od, g, gr, e, K);
+        for (int s = 0; s < 8; ++s) {
+            const int sx = i + (s & 1), sy = j + ((s >> 1) & 1), sz = k + (s >> 2);
+            if (sx < 1 || sx > cx || sy < 1 || sy > cy || sz < 1 || sz > cz) continue;
+            const int64_t row = (sx - 1) + (int64_t)cx * ((sy - 1) + (int64_t)cy * (sz - 1));
+            for (int t = 0; t < 8; ++t) {
+                const int tx = i + (t & 1), ty = j + ((t >> 1) & 1), tz = k + (t >> 2);
+                if (tx < 1 || tx > cx || ty < 1 || ty > cy || tz < 1 || tz > cz) continue;
+                const int sidx = (tz - sz + 1) * 9 + (ty - sy + 1) * 3 + (tx - sx + 1);
+                st[(size_t)sidx * nv + row] += K[s][t];
+            }
+        }
+    }
+    return st;
+}
+
+static bool mg_coarsenable(int cx, int cy, int cz) {
+    return cx % 2 == 0 && cy % 2 == 0 && cz % 2 == 0 && cx >= 4 && cy >= 4 && cz >= 4;
+}
+
+// A_c = P^T A_f P for the stencil A_f of a level with (cx, cy, cz) cells.
+static MGLevelHost galerkin_coarsen(const MGLevelHost &f) {
+    MGLevelHost c;
+    c.cx = f.cx / 2; c.cy = f.cy / 2; c.cz = f.cz / 2;
+    const int fx = f.cx - 1, fy = f.cy - 1, fz = f.cz - 1;          // fine interior extents
+    const int ux = c.cx - 1, uy = c.cy - 1, uz = c.cz - 1;          // coarse interior extents
+    const int64_t nvf = (int64_t)fx * fy * fz, nvc = (int64_t)ux * uy * uz;
+    c.st.assign((size_t)27 * nvc, 0.0);
+    // 1D interpolation weights of fine index i (1..f-1) from coarse J: J = i/2 (weight 1) for
+    // even i, J = (i -+ 1)/2 (weights 1/2) for odd i; coarse boundary vertices are dropped
+    auto parents = [](int i, int nc_cells, int J[2], double w[2]) {
+        if (i % 2 == 0) {
+            J[0] = i / 2; w[0] = 1.0; J[1] = -1; w[1] = 0.0;
+        } else {
+            J[0] = (i - 1) / 2; w[0] = 0.5; J[1] = (i + 1) / 2; w[1] = 0.5;
+        }
+        for (int t = 0; t < 2; ++t)
+            if (J[t] < 1 || J[t] > nc_cells - 1) { J[t] = -1; w[t] = 0.0; }
+    };
+#pragma omp parallel for schedule(static)
+    for (int64_t I = 0; I < nvc; ++I) {
+        const int Ix = 1 + (int)(I % ux), Iy = 1 + (int)((I / ux) % uy), Iz = 1 + (int)(I / ((int64_t)ux * uy));
+        double acc[27] = {0};
+        for (int dz = -1; dz <= 1; ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    // fine vertex i in the support of coarse vertex I, with P[i, I]
+                    const int ix = 2 * Ix + dx, iy = 2 * Iy + dy, iz = 2 * Iz + dz;
+                    const double wi = (dx ? 0.5 : 1.0) * (dy ? 0.5 : 1.0) * (dz ? 0.5 : 1.0);
+                    const int64_t row = (ix - 1) + (int64_t)fx * ((iy - 1) + (int64_t)fy * (iz - 1));
+                    for (int ez = -1; ez <= 1; ++ez)
+                        for (int ey = -1; ey <= 1; ++ey)
+                            for (int ex = -1; ex <= 1; ++ex) {
+                                const int jx = ix + ex, jy = iy + ey, jz = iz + ez;
+                                if (jx < 1 || jx > fx || jy < 1 || jy > fy || jz < 1 || jz > fz) continue;
+                                const double a = f.st[(size_t)((ez + 1) * 9 + (ey + 1) * 3 + (ex + 1)) * nvf + row];
+                                if (a == 0.0) continue;
+                                int Jx[2], Jy[2], Jz[2];
+                                double wx[2], wy[2], wz[2];
+                                parents(jx, c.cx, Jx, wx);
+                                parents(jy, c.cy, Jy, wy);
+                                parents(jz, c.cz, Jz, wz);
+                                for (int a3 = 0; a3 < 2; ++a3)
+                                    for (int a2 = 0; a2 < 2; ++a2)
+                                        for (int a1 = 0; a1 < 2; ++a1) {
+                                            if (Jx[a1] < 0 || Jy[a2] < 0 || Jz[a3] < 0) continue;
+                                            const int sidx = (Jz[a3] - Iz + 1) * 9 + (Jy[a2] - Iy + 1) * 3 + (Jx[a1] - Ix + 1);
+                                            acc[sidx] += wi * a * wx[a1] * wy[a2] * wz[a3];
+                                        }
+                            }
+                }
+        for (int s = 0; s < 27; ++s) c.st[(size_t)s * nvc + I] = acc[s];
+    }
+    return c;
+}
+
+// Dense inverse of a level's matrix from its stencil (dense Cholesky; small levels only).
+static std::vector<double> stencil_inverse(const MGLevelHost &L) {
+    const int ux = L.cx - 1, uy = L.cy - 1, uz = L.cz - 1;
+    const int64_t n = (int64_t)ux * uy * uz;
+    std::vector<double> A((size_t)n * n, 0.0);
+    for (int64_t i = 0; i < n; ++i) {
+        const int x = (int)(i % ux), y = (int)((i / ux) % uy), z = (int)(i / ((int64_t)ux * uy));
+        for (int s = 0; s < 27; ++s) {
+            const int jx = x + s % 3 - 1, jy = y + (s / 3) % 3 - 1, jz = z + s / 9 - 1;
+            if (jx < 0 || jx >= ux || jy < 0 || jy >= uy || jz < 0 || jz >= uz) continue;
+            A[(size_t)i * n + jx + (int64_t)ux * (jy + (int64_t)uy * jz)] = L.st[(size_t)s * n + i];
+        }
+    }
+    // symmetrize the rounding of the Galerkin products, then L L^T
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = 0; j < i; ++j) A[(size_t)i * n + j] = A[(size_t)j * n + i] = 0.5 * (A[(size_t)i * n + j] + A[(size_t)j * n + i]);
+    for (int64_t j = 0; j < n; ++j) {
+        double d = A[(size_t)j * n + j];
+        for (int64_t k = 0; k < j; ++k) d -= A[(size_t)j * n + k] * A[(size_t)j * n + k];
+        if (!(d > 0)) throw Error(VSR_ENOTSPD, "coarsest multigrid matrix is not positive definite");
+        d = std::sqrt(d);
+        A[(size_t)j * n + j] = d;
+        for (int64_t i = j + 1; i < n; ++i) {
+            double s = A[(size_t)i * n + j];
+            for (int64_t k = 0; k < j; ++k) s -= A[(size_t)i * n + k] * A[(size_t)j * n + k];
+            A[(size_t)i * n + j] = s / d;
+        }
+    }
+    std::vector<double> inv((size_t)n * n);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t col = 0; col < n; ++col) {
+        std::vector<double> x(n, 0.0);
+        x[col] = 1.0;
+        for (int64_t i = col; i < n; ++i) {
+            double s = x[i];
+            for (int64_t k = col; k < i; ++k) s -= A[(size_t)i * n + k] * x[k];
+            x[i] = s / A[(size_t)i * n + i];
+        }
+        for (int64_t i = n - 1; i >= 0; --i) {
+            double s = x[i];
+            for (int64_t k = i + 1; k < n; ++k) s -= A[(size_t)k * n + i] * x[k];
+            x[i] = s / A[(size_t)i * n + i];
+        }
+        for (int64_t i = 0; i < n; ++i) inv[(size_t)i * n + col] = x[i];
+    }
+    return inv;
+}
+
+MGHierarchyHost make_mg_hierarchy(int nx, int ny, int nz, const OneD &od, const Geometry &g) {
+    MGHierarchyHost H;
+    MGLevelHost L0;
+    L0.cx = nx; L0.cy = ny; L0.cz = nz;
+    L0.st = q1_stencil(nx, ny, nz, od, g);
+    H.levels.push_back(std::move(L0));
+    while (mg_coarsenable(H.levels.back().cx, H.levels.back().cy, H.levels.back().cz))
+        H.levels.push_back(galerkin_coarsen(H.levels.back()));
+    // a single level is the direct solve: its inverse is the one of the dense coarse path
+    H.coarsest_inverse = H.levels.size() == 1 ? make_coarse_inverse(nx, ny, nz, od, g) : stencil_inverse(H.levels.back());
+    return H;
 }
 
 // ============================================================ lattice transfers

@@ -88,6 +88,23 @@ PatchSet make_patches(int nx, int ny, int nz, const OneD &od, const double *mu, 
 // Dense inverse of the Q1 Galerkin matrix over interior vertices (row-major, nc x nc).
 std::vector<double> make_coarse_inverse(int nx, int ny, int nz, const OneD &od, const Geometry &g);
 
+// ------------------------------------------------------------------ Q1 geometric multigrid
+// Levels of the p-coarse (Q1) problem (Sec. 2.8): level 0 is the Q1 Galerkin matrix of the mesh
+// over its interior vertices; each next level merges 2 x 2 x 2 cells while every axis has an
+// even number of at least 4 cells, and is the Galerkin product P^T A P with trilinear
+// index-space interpolation.  Stencils hold 27 coefficients per interior vertex, stored
+// [s][vertex] with s = (dz+1) 9 + (dy+1) 3 + (dx+1) and vertices x fastest.
+struct MGLevelHost {
+    int cx = 0, cy = 0, cz = 0;   // cells per axis; (cx-1)(cy-1)(cz-1) interior vertices
+    std::vector<double> st;       // 27 x nv
+};
+struct MGHierarchyHost {
+    std::vector<MGLevelHost> levels;
+    std::vector<double> coarsest_inverse;   // dense inverse of the last level, row-major
+};
+std::vector<double> q1_stencil(int nx, int ny, int nz, const OneD &od, const Geometry &g);
+MGHierarchyHost make_mg_hierarchy(int nx, int ny, int nz, const OneD &od, const Geometry &g);
+
 // Cell block of a lattice transfer (row-major OA x K) for launch_transfer: along an axis,
 // cell e maps inputs e*in_step + in_off + s to outputs e*out_step + a.
 //   XFER_FDM_RESTRICT   T^T: OA = p, K = 2p-1 (in_step p, in_off 0, out_step p)

@@ -38,7 +38,8 @@ class Options(ctypes.Structure):
                 ("interior_patches_only", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("omega", ctypes.c_double), ("stream", ctypes.c_void_p), ("autotune", ctypes.c_int32),
                 ("batch_streams", ctypes.c_int32), ("batch_eager", ctypes.c_int32), ("tune_cache", ctypes.c_char_p),
-                ("share_factors", ctypes.c_int32), ("deterministic", ctypes.c_int32)]
+                ("share_factors", ctypes.c_int32), ("deterministic", ctypes.c_int32),
+                ("coarse_solver", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -151,7 +152,7 @@ class _Inputs:
 
 def make_options(relax_fp32=False, cycle=0, lanczos_steps=20, max_iterations=1000, interior_patches_only=False, seed=0,
                  omega=0.0, stream=None, autotune=False, batch_streams=0, batch_eager=False, tune_cache=None,
-                 share_factors=False, deterministic=False):
+                 share_factors=False, deterministic=False, coarse_solver="auto"):
     opt = Options()
     lib().vsr_default_options(ctypes.byref(opt))
     opt.relax_fp32 = int(bool(relax_fp32))
@@ -168,6 +169,10 @@ def make_options(relax_fp32=False, cycle=0, lanczos_steps=20, max_iterations=100
     opt.tune_cache = None if tune_cache is None else os.fsencode(tune_cache)
     opt.share_factors = int(bool(share_factors))
     opt.deterministic = int(bool(deterministic))
+    codes = {"auto": 0, "dense": 1, "gmg": 2}
+    if coarse_solver not in codes:
+        raise ValueError("coarse_solver must be 'auto', 'dense' or 'gmg'")
+    opt.coarse_solver = codes[coarse_solver]
     return opt
 
 
