@@ -29,7 +29,8 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 WORKLOAD = "poisson_cart_16x16x16_q7"
-WORKLOADS = ("poisson_cart_16x16x16_q7", "poisson_jitter_8x8x8_q15_lognormal", "poisson_jitter_12x12x12_q11_lognormal")
+WORKLOADS = ("poisson_cart_16x16x16_q7", "poisson_jitter_8x8x8_q15_lognormal", "poisson_jitter_12x12x12_q11_lognormal",
+             "poisson_cart_32x32x32_q7")
 
 
 def log(*a):
@@ -82,9 +83,10 @@ def error_vs_oracle(name, x):
             "sampled_entries": int(len(idx)), "oracle_iterations": int(g["iterations"])}
 
 
-def solve_timed(vsr, torch, w, relax_fp32, steps, warmup, profile, autotune=False, share_factors=False):
+def solve_timed(vsr, torch, w, relax_fp32, steps, warmup, profile, autotune=False, share_factors=False,
+                coarse_solver="auto"):
     prob = vsr.Problem(w["vertices"], w["p"], kappa=w["kappa"], relax_fp32=relax_fp32, seed=0, autotune=autotune,
-                       share_factors=share_factors)
+                       share_factors=share_factors, coarse_solver=coarse_solver)
     n = prob.n
     f = torch.tensor(w["f"], dtype=torch.float64, device="cuda")
     b = torch.zeros(n, dtype=torch.float64, device="cuda")
@@ -306,6 +308,23 @@ def main():
                                  "iterations": rs["iterations"], "true_rel_residual": rs["info"]["true_rel_residual"],
                                  "patch_kernel_ms": total_ms / max(launches, 1), "factor_entries": rs["factor_entries"]}
         log(f"[bench] shared factors: {rs['iterations']} iterations, {ms_s:.2f} ms/solve")
+        # the coarse problem by geometric multigrid instead of the dense inverse (Sec. 2.8)
+        rg = solve_timed(vsr, torch, w, True, args.steps, 1, profile=False, coarse_solver="gmg")
+        ms_g = 1e3 * rg["seconds"] / args.steps
+        out["gmg_coarse"] = {"value": rg["n"] / (ms_g * 1e-3), "unit": "DOF/s", "ms_per_step": ms_g,
+                             "iterations": rg["iterations"], "true_rel_residual": rg["info"]["true_rel_residual"]}
+        log(f"[bench] multigrid coarse solve: {rg['iterations']} iterations, {ms_g:.2f} ms/solve")
+        # h-scaling: 32^3 cells at p = 7 (11.1M DOFs), coarse problem by multigrid (29,791 Q1
+        # unknowns: the dense inverse would hold 7 GB and take hours to form)
+        w32 = inputs.workload("poisson_cart_32x32x32_q7", seed=0)
+        r32h = solve_timed(vsr, torch, w32, True, 3, 1, profile=False)
+        ms_h = 1e3 * r32h["seconds"] / 3
+        out["h_scaling"] = {"workload": "poisson_cart_32x32x32_q7", "dofs": r32h["n"], "coarse_solver": "gmg",
+                            "value": r32h["n"] / (ms_h * 1e-3), "unit": "DOF/s", "ms_per_step": ms_h,
+                            "iterations": r32h["iterations"], "setup_seconds": r32h["setup_s"],
+                            "true_rel_residual": r32h["info"]["true_rel_residual"]}
+        log(f"[bench] 32^3 Q7: {r32h['iterations']} iterations, {ms_h:.1f} ms/solve, setup {r32h['setup_s']:.1f} s")
+        del w32, r32h
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(p, cells=8 if p <= 7 else 3, workload=wname)

@@ -96,8 +96,8 @@ void launch_dense_gemv(int n, const T *A, const T *x, T *y, T alpha, T beta, con
 // vectors (solution, right-hand side, residual, corrected iterate).  Level l+1 halves every
 // axis; transfers are trilinear in index space.  cinv: dense inverse of the last level.
 constexpr int kMGMaxLevels = 12;
-constexpr int64_t kMGTailVertices = 8192;   // levels this small run in one single-workgroup launch
-constexpr int64_t kMGTailCoarsest = 1024;   // coarsest solved inside that launch up to this size
+constexpr int64_t kMGTailVertices = 1024;   // levels this small run in one single-workgroup launch
+constexpr int64_t kMGTailCoarsest = 128;    // coarsest solved inside that launch up to this size
 template <typename T>
 struct MGLevel {
     int cx = 0, cy = 0, cz = 0;

@@ -67,12 +67,14 @@ def make_problem(n, p, seed=0, jitter=0.0, lognormal=False, ell=0.25, var=1.0):
     return dict(vertices=V, kappa=kappa, f=f, p=p, q=q, n=n, seed=seed, jitter=jitter)
 
 
-# The five workloads: (cells per axis, degree, jitter, log-normal coefficient).
+# The workloads: (cells per axis, degree, jitter, log-normal coefficient).
 WORKLOADS = {
     "poisson_cart_2x2x2_q3": dict(n=2, p=3, jitter=0.0, lognormal=False),
     "poisson_cart_16x16x16_q7": dict(n=16, p=7, jitter=0.0, lognormal=False),
     "poisson_jitter_8x8x8_q15_lognormal": dict(n=8, p=15, jitter=0.15, lognormal=True),
     "poisson_jitter_12x12x12_q11_lognormal": dict(n=12, p=11, jitter=0.2, lognormal=True),
+    # h-scaling of the 16^3 Q7 workload: eight times the cells, beyond the dense coarse inverse
+    "poisson_cart_32x32x32_q7": dict(n=32, p=7, jitter=0.0, lognormal=False),
 }
 
 

@@ -141,3 +141,26 @@ def test_automatic_coarse_solver_choice(vsr):
         prob.close()
     assert np.array_equal(outs[0], outs[1])
     assert not np.array_equal(outs[1], outs[2])
+
+
+def test_32cubed_q7_solve_with_multigrid_coarse_problem(vsr):
+    """h-scaling: 32^3 cells at p = 7 (11.1M DOFs) with the default coarse solver, which is
+    multigrid here (29,791 Q1 unknowns; the dense inverse would be 7 GB).  The library's FP64
+    true residual must reach 1e-8 and the iteration count stay within two of the 16^3 count
+    (the paper's near h-independence, Table tab:poisson-iter)."""
+    say("case 32^3 q7")
+    its = {}
+    for n in (16, 32):
+        w = inputs.make_problem(n, 7, seed=0)
+        prob = vsr.Problem(w["vertices"], 7, seed=0, relax_fp32=True)
+        b = torch.zeros(prob.n, dtype=torch.float64, device="cuda")
+        prob.load_vector(dev(w["f"]), b)
+        x = torch.zeros_like(b)
+        info = prob.pcg_solve(b, x)
+        say(f"  {n}^3: n={prob.n} iterations {info['iterations']} true residual {info['true_rel_residual']:.2e} "
+            f"setup {info['setup_seconds']:.1f} s solve {1e3 * info['solve_seconds']:.1f} ms")
+        assert info["converged"] and info["true_rel_residual"] <= 1.0001e-8
+        its[n] = info["iterations"]
+        prob.close()
+        del b, x
+    assert its[32] <= its[16] + 2
