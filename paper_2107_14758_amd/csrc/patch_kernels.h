@@ -156,6 +156,35 @@ __device__ __forceinline__ T tri_inv_t_mv(const T *__restrict__ Li, int nstore, 
     return (acc[0] + acc[1]) + (acc[2] + acc[3]);
 }
 
+// Value of v in lane k (k uniform across the wavefront).
+template <typename T>
+__device__ __forceinline__ T lane_value(T v, int k);
+template <>
+__device__ __forceinline__ float lane_value<float>(float v, int k) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
+}
+template <>
+__device__ __forceinline__ double lane_value<double>(double v, int k) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), k), hi = __builtin_amdgcn_readlane(__double2hiint(v), k);
+    return __hiloint2double(hi, lo);
+}
+
+// tri_inv_t_mv over all `rows` columns with b held one entry per lane (lane k holds b[k]):
+// the same products summed in the same order, no LDS round trip for b.
+template <typename T>
+__device__ __forceinline__ T tri_inv_t_mv_lanes(const T *__restrict__ Li, int nstore, int rows, int lane, T b) {
+    T acc[4] = {T(0), T(0), T(0), T(0)};
+    const int base = lane * nstore - lane * (lane - 1) / 2 - lane;
+    const bool live = lane < rows;
+#pragma unroll 4
+    for (int k = 0; k < rows; ++k) {
+        const T bk = lane_value(b, k);
+        const T v = (live && k >= lane) ? Li[base + k] : T(0);
+        acc[k & 3] += v * bk;
+    }
+    return (acc[0] + acc[1]) + (acc[2] + acc[3]);
+}
+
 template <typename T>
 struct Vec4 {
     T v[4];
@@ -378,38 +407,34 @@ __device__ __forceinline__ void patch_interior(const int pid, Dims d, PatchArgs 
         }
         return pos[0] == M ? 0 : (pos[1] == M ? 1 : 2);
     };
+    // ---- forward: the leaves' diagonal block is applied as their values are condensed
+    const T *invd = F + A.off_invd, *B1 = F + A.off_B1, *B2 = F + A.off_B2;
     for (int idx = tid; idx < NI; idx += nt) {
         int pos[3];
         const int dd = iface_pos(idx, pos);
         const int ncen = (pos[0] == M) + (pos[1] == M) + (pos[2] == M);
-        g[idx] = ncen == 1 ? C.condensed(pos, dd) : rF[C.gidx(pos[0], pos[1], pos[2])];
+        const T dl = idx < NL ? invd[idx] : T(1);
+        const T gv = ncen == 1 ? C.condensed(pos, dd) : rF[C.gidx(pos[0], pos[1], pos[2])];
+        g[idx] = idx < NL ? gv * dl : gv;
     }
     phase_sync();
-    // ---- forward: leaves (diagonal)
-    const T *invd = F + A.off_invd, *B1 = F + A.off_B1, *B2 = F + A.off_B2;
-    for (int i = tid; i < NL; i += nt) g[i] *= invd[i];
-    phase_sync();
-    // leaf columns update their level-1 slice and their top-plane line
-    for (int task = tid; task < 2 * NS; task += nt) {
-        if (task < NS) {
-            int s = task / W, r = task % W;
-            T acc = 0;
+    // leaf columns update their level-1 slice (their top-plane update, g_T -= L_TL y_L, is
+    // folded into the coupling below, which reads L_TL anyway: g_T is not used before it)
+    for (int task = tid; task < NS; task += nt) {
+        int s = task / W, r = task % W;
+        T acc = 0;
 #pragma unroll
-            for (int c = 0; c < 2 * M; ++c) acc += B1[(int64_t)(s * 2 * M + c) * W + r] * g[s * 2 * M + c];
-            g[NL + s * W + r] -= acc;
-        } else {
-            int t = task - NS, lx = t / W, ay = t % W;
-            T acc = 0;
-#pragma unroll
-            for (int c = 0; c < 2 * M; ++c) acc += B2[(int64_t)(lx * 2 * M + c) * W + ay] * g[c * 2 * M + lx];
-            g[NL + NS + ay * W + inv_la_(lx, M)] -= acc;
-        }
+        for (int c = 0; c < 2 * M; ++c) acc += B1[(int64_t)(s * 2 * M + c) * W + r] * g[s * 2 * M + c];
+        g[NL + s * W + r] -= acc;
     }
     phase_sync();
-    // level-1 separator slices: dense lower solves, one wavefront per slice
+    // level-1 separator slices, one wavefront per slice: the dense lower solve y_S, then at
+    // once (from the lanes' registers) z = L_SS^{-T} y_S for the top x level-1 coupling below
     for (int s = wv; s < 2 * M; s += nw) {
         const T x = tri_inv_mv<T>(Lsep + s * LS, W, 0, W, W, lane, g + NL + s * W);
         if (lane < W) g[NL + s * W + lane] = x;
+        const T zv = tri_inv_t_mv_lanes<T>(Lsep + s * LS, W, W, lane, x);
+        if (lane < W) zs[s * W + lane] = zv;
     }
     // stage the first top-plane diagonal tile while the level-1 solves finish
     T *gt = g + NL + NS;
@@ -436,11 +461,6 @@ __device__ __forceinline__ void patch_interior(const int pid, Dims d, PatchArgs 
     // leaf blocks and the slice inverses are the ones used above), so the dense panel is
     // never formed
     const T *Sy = F + A.off_Sy;
-    for (int s = wv; s < 2 * M; s += nw) {   // z = L_SS^{-T} y_S
-        const T zv = tri_inv_t_mv<T>(Lsep + s * LS, W, 0, W, W, lane, g + NL + s * W);
-        if (lane < W) zs[s * W + lane] = zv;
-    }
-    phase_sync();
     for (int i = tid; i < NL; i += nt) {     // w_L = L_SL^T z (leaf (s, c) meets slice s)
         const int sl = i / (2 * M);
         T acc = 0;
@@ -449,7 +469,7 @@ __device__ __forceinline__ void patch_interior(const int pid, Dims d, PatchArgs 
         wl[i] = acc;
     }
     phase_sync();
-    for (int i = tid; i < NT; i += nt) {     // g_T -= S_TS z - L_TL w_L
+    for (int i = tid; i < NT; i += nt) {     // g_T -= L_TL y_L + S_TS z - L_TL w_L
         const int ay = i / W, ax = i % W;
         T acc = 0;
 #pragma unroll
@@ -457,7 +477,7 @@ __device__ __forceinline__ void patch_interior(const int pid, Dims d, PatchArgs 
         if (ax != M) {
             const int lx = la_(ax, M);
 #pragma unroll
-            for (int c = 0; c < 2 * M; ++c) acc -= B2[(int64_t)(lx * 2 * M + c) * W + ay] * wl[c * 2 * M + lx];
+            for (int c = 0; c < 2 * M; ++c) acc += B2[(int64_t)(lx * 2 * M + c) * W + ay] * (g[c * 2 * M + lx] - wl[c * 2 * M + lx]);
         }
         gt[i] -= acc;
     }
@@ -470,8 +490,10 @@ __device__ __forceinline__ void patch_interior(const int pid, Dims d, PatchArgs 
         const int kw = 64 / nw;   // columns of the block per wavefront
         red[tid] = tri_inv_mv<T>(tl, tile_ns(J), min(kw * wv, nb), min(kw * wv + kw, nb), nb, lane, gt + c0);
         phase_sync();
-        if (wv == 0 && lane < nb) gt[c0 + lane] = sum_waves(red, nw, lane);
-        phase_sync();
+        // every wavefront adds the partials itself and stores the (identical) solved block, so it
+        // goes on to the panel without a second barrier: it reads only values its own lanes
+        // stored, and the LDS operations of one wavefront are performed in order
+        if (lane < nb) gt[c0 + lane] = sum_waves(red, nw, lane);
         const T *D = F + tile_offset(A.off_Ltop, NT, J);
         const int rows = NT - c0 - nb;
         panel_fwd<T, UNR, NTH>(D + 64 * 65 / 2, (rows + 3) / 4 * 4, rows, nb, gt + c0, gt + c0 + nb, A.det != 0);
@@ -484,8 +506,7 @@ __device__ __forceinline__ void patch_interior(const int pid, Dims d, PatchArgs 
         const int kw = 64 / nw;
         red[tid] = tri_inv_t_mv<T>(tl, tile_ns(J), min(kw * wv, nb), min(kw * wv + kw, nb), nb, lane, gt + c0);
         phase_sync();
-        if (wv == 0 && lane < nb) gt[c0 + lane] = sum_waves(red, nw, lane);
-        phase_sync();
+        if (lane < nb) gt[c0 + lane] = sum_waves(red, nw, lane);   // as in the forward pass
         if (J > 0) {
             const int cp = 64 * (J - 1), nbp = 64, rows = NT - cp - nbp;
             const T *Dp = F + tile_offset(A.off_Ltop, NT, J - 1);
@@ -548,23 +569,18 @@ __device__ __forceinline__ void patch_interior(const int pid, Dims d, PatchArgs 
         }
     }
     phase_sync();
-    for (int s = wv; s < 2 * M; s += nw) {   // y_S -= L_SS^{-1} h
+    for (int s = wv; s < 2 * M; s += nw) {   // y_S -= L_SS^{-1} h, then x_S = L_SS^{-T} y_S
         const T d = tri_inv_mv<T>(Lsep + s * LS, W, 0, W, W, lane, zs + s * W);
-        if (lane < W) g[NL + s * W + lane] -= d;
-    }
-    phase_sync();
-    for (int s = wv; s < 2 * M; s += nw) {
-        const T x = tri_inv_t_mv<T>(Lsep + s * LS, W, 0, W, W, lane, g + NL + s * W);
+        const T y = lane < W ? g[NL + s * W + lane] - d : T(0);
+        const T x = tri_inv_t_mv_lanes<T>(Lsep + s * LS, W, W, lane, y);
         if (lane < W) g[NL + s * W + lane] = x;
     }
     phase_sync();
-    for (int i = tid; i < NL; i += nt) {
+    for (int i = tid; i < NL; i += nt) {     // y_L = D_L^{-1} (y_L - L_SL^T y_S - L_TL^T x_T); the last is w_L
         int s = i / (2 * M), c = i % (2 * M);
-        T v = g[i];
-        int ax = inv_la_(c, M);
+        T v = g[i] - wl[i];
 #pragma unroll
-        for (int r = 0; r < W; ++r)
-            v -= B1[(int64_t)(s * 2 * M + c) * W + r] * g[NL + s * W + r] + B2[(int64_t)(c * 2 * M + s) * W + r] * gt[r * W + ax];
+        for (int r = 0; r < W; ++r) v -= B1[(int64_t)(s * 2 * M + c) * W + r] * g[NL + s * W + r];
         g[i] = v * invd[i];
     }
     phase_sync();
