@@ -1,7 +1,7 @@
 """GPU parity of the multigrid coarse solve (Sec. 2.8) against the oracle's geometric multigrid.
 
 Covers every launch path of the V-cycle: the whole cycle in one single-workgroup launch
-(levels of at most 8,192 vertices), a large finest level in per-level launches above that
+(levels of at most 1,024 vertices), large finer levels in per-level launches above that
 launch, a large finest level above a coarsest level solved by the dense inverse across the
 GPU, and a mesh that cannot be coarsened (the direct solve).  FP64 results must match the
 oracle to 1e-12 per apply and 1e-10 per solve; FP32 coarse corrections to 1e-5.
