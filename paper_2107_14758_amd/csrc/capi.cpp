@@ -61,8 +61,8 @@ struct vsr_problem {
     std::vector<void *> allocs;
 
     // operator data (FP64 and FP32 copies)
-    double *AB64 = nullptr, *IDq64 = nullptr, *mu64 = nullptr, *Gw64 = nullptr, *wdet = nullptr;
-    float *AB32 = nullptr, *IDq32 = nullptr, *mu32 = nullptr, *Gw32 = nullptr;
+    double *AB64 = nullptr, *IDq64 = nullptr, *mu64 = nullptr, *geo64 = nullptr, *wdet = nullptr;
+    float *AB32 = nullptr, *IDq32 = nullptr, *mu32 = nullptr, *geo32 = nullptr;
     // relaxation data in the cycle precision
     void *mu_sur = nullptr, *lam = nullptr, *afc = nullptr, *fint = nullptr, *fbnd = nullptr;
     int n_int = 0, n_bnd = 0;
@@ -178,13 +178,13 @@ int op_cells(vsr_problem *P, const T *x, T *E) {
             launch_op_kron<double>(P->d, P->AB64, P->mu64, x, E, P->ex());
             return 1;
         }
-        return launch_op_general<double>(P->d, P->IDq64, P->Gw64, x, E, P->ex());
+        return launch_op_general<double>(P->d, P->IDq64, P->geo64, x, E, P->ex());
     } else {
         if (P->cartesian) {
             launch_op_kron<float>(P->d, P->AB32, P->mu32, x, E, P->ex());
             return 1;
         }
-        return launch_op_general<float>(P->d, P->IDq32, P->Gw32, x, E, P->ex());
+        return launch_op_general<float>(P->d, P->IDq32, P->geo32, x, E, P->ex());
     }
 }
 
@@ -830,11 +830,13 @@ vsr_status vsr_setup(const vsr_mesh *mesh, int32_t p, const vsr_coefficients *co
             for (int64_t e = 0; e < P->ncell; ++e)
                 if (!(kappa[e] > 0)) throw Error(VSR_ENOTSPD, "kappa must be positive");
         int n1 = p + 1;
-        std::vector<double> ab(2 * n1 * n1), idq(2 * (size_t)qdef * n1);
+        std::vector<double> ab(2 * n1 * n1), idq(2 * (size_t)qdef * n1 + 2 * (size_t)qdef);
         std::copy(P->od.A.begin(), P->od.A.end(), ab.begin());
         std::copy(P->od.B.begin(), P->od.B.end(), ab.begin() + n1 * n1);
         std::copy(P->od.Iq.begin(), P->od.Iq.end(), idq.begin());
         std::copy(P->od.Dq.begin(), P->od.Dq.end(), idq.begin() + (size_t)qdef * n1);
+        std::copy(P->od.xq.begin(), P->od.xq.end(), idq.begin() + 2 * (size_t)qdef * n1);
+        std::copy(P->od.wq.begin(), P->od.wq.end(), idq.begin() + 2 * (size_t)qdef * n1 + qdef);
         P->AB64 = P->upload(ab);
         P->AB32 = P->upload_as<float>(ab);
         P->IDq64 = P->upload(idq);
@@ -843,8 +845,11 @@ vsr_status vsr_setup(const vsr_mesh *mesh, int32_t p, const vsr_coefficients *co
         P->mu32 = P->upload_as<float>(g.mu);
         P->wdet = P->upload(g.wdet);
         if (!g.cartesian) {
-            P->Gw64 = P->upload(g.Gw);
-            if (P->fp32) P->Gw32 = P->upload_as<float>(g.Gw);
+            // the operator evaluates the metric from these per-cell corner data (the host's
+            // metric stays on the host for the coarse matrices)
+            const std::vector<double> cg = make_cell_geometry(nx, ny, nz, mesh->vertices, kappa);
+            P->geo64 = P->upload(cg);
+            if (P->fp32) P->geo32 = P->upload_as<float>(cg);
         }
         // patches (separable surrogate, Sec. 2.7)
         std::vector<double> mu_sur = muo ? std::vector<double>(muo, muo + 3 * P->ncell) : g.mu;

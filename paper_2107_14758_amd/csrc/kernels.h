@@ -39,8 +39,14 @@ struct Exec {
 // s ncell (p+1)^3.  launch_gather turns E into the lattice vector.
 template <typename T>
 void launch_op_kron(const Dims &d, const T *AB1d, const T *mu, const T *x, T *E, const Exec &e);
+// General (trilinear) cells: IDq = [Iq (q x (p+1)), Dq (q x (p+1)), GLL points x_q (q), weights
+// w_q (q)]; geo: kGeoStride values per cell, the halved edge differences of its corners
+// X[c][b][a] (x fastest): 0.5 (X[c][b][1] - X[c][b][0]) at 3 (2c + b), 0.5 (X[c][1][a] -
+// X[c][0][a]) at 12 + 3 (2c + a), 0.5 (X[1][b][a] - X[0][b][a]) at 24 + 3 (2b + a), then kappa
+// at 36 (make_cell_geometry).
+constexpr int kGeoStride = 40;
 template <typename T>
-int launch_op_general(const Dims &d, const T *IDq, const T *Gw, const T *x, T *E, const Exec &e);
+int launch_op_general(const Dims &d, const T *IDq, const T *geo, const T *x, T *E, const Exec &e);
 // out = sum over the cells and slots that share each free node of E (r == nullptr), or
 // out = r - that sum (in T).  Deterministic: a fixed summation order, no atomics.  With
 // dotv, also the partial sums of dotv . out, one per workgroup (gather_blocks of them), into

@@ -135,11 +135,11 @@ constexpr int opg_chunk(int P, int S, int bytes) {
     const int N1 = P + 1, Q = QOF(P), BR = opg_rows(P, S);
     const int fwd = N1 * N1 + 2 * N1 * Q, bwd = 3 * BR * Q + 2 * N1 * Q;
     const int per = (fwd > bwd ? fwd : bwd) * bytes;
-    const int kc = (60 * 1024 - 2 * Q * N1 * bytes) / per;
+    const int kc = (60 * 1024 - (4 * Q * N1 + 19 * Q) * bytes) / per;
     return kc < 1 ? 1 : (kc > N1 ? N1 : kc);
 }
 
-// General trilinear cell: y_K = (grad phi)^T Gw (grad phi) x_K with the q^3 GLL rule
+// General trilinear cell: y_K = (grad phi)^T G w (grad phi) x_K with the q^3 GLL rule
 // (Sec. 2.1, 2.7).  Thread (b, a) owns one z-column of quadrature points.  The x and y
 // contractions run through LDS for a chunk of KC z-slabs at a time (three barriers per chunk
 // and direction); the z contraction, the metric and the z back-contraction stay in the
@@ -149,21 +149,42 @@ constexpr int opg_chunk(int P, int S, int bytes) {
 // slots and the cells that share a node.
 template <typename T, int P, int S>
 __global__ void __launch_bounds__(opg_threads(P, S)) k_op_general(const double *__restrict__ gate, Dims d,
-                                                                   const T *__restrict__ IDq, const T *__restrict__ Gw,
+                                                                   const T *__restrict__ IDq, const T *__restrict__ geo,
                                                                    const T *__restrict__ x, T *__restrict__ E) {
     if (gated(gate)) return;
     constexpr int N1 = P + 1, Q = QOF(P), Q2 = Q * Q, Q3 = Q2 * Q, BR = opg_rows(P, S);
     constexpr int KC = opg_chunk(P, S, (int)sizeof(T)), NCH = (N1 + KC - 1) / KC;
     constexpr int FWD = N1 * N1 + 2 * N1 * Q, BWD = 3 * BR * Q + 2 * N1 * Q;
     constexpr int NTH = opg_threads(P, S), NX = KC * N1 * N1, NLX = (NX + NTH - 1) / NTH;
-    __shared__ T sI[Q * N1], sD[Q * N1];
+    // the 1D matrices row-major ([a][i]: read with i varying across lanes) and transposed
+    // ([i][a]: read with a varying across lanes), so that no phase strides lanes by a row
+    __shared__ T sI[Q * N1], sD[Q * N1], sIt[N1 * Q], sDt[N1 * Q];
+    // Metric tables of the trilinear map (Sec. 2.7): the Jacobian columns along a quadrature
+    // column (a, b) are dx/dxi = n0(zeta) E1[0][b] + n1(zeta) E1[1][b], dx/deta = n0(zeta)
+    // E2[0][a] + n1(zeta) E2[1][a], and dx/dzeta = n0(eta) A3[0][a] + n1(eta) A3[1][a] (fixed):
+    // the halved corner edge differences interpolated along the other reference axes.
+    __shared__ T sE1[6 * Q], sE2[6 * Q], sA3[6 * Q], sW[Q];
     __shared__ T buf[KC * (FWD > BWD ? FWD : BWD)];
     const int tid = threadIdx.x, nt = blockDim.x;
-    for (int t = tid; t < Q * N1; t += nt) {
-        sI[t] = IDq[t];
-        sD[t] = IDq[Q * N1 + t];
-    }
     const int64_t e = blockIdx.x / S;
+    for (int t = tid; t < Q * N1; t += nt) {
+        const T vi = IDq[t], vd = IDq[Q * N1 + t];
+        sI[t] = vi;
+        sD[t] = vd;
+        sIt[(t % N1) * Q + t / N1] = vi;
+        sDt[(t % N1) * Q + t / N1] = vd;
+    }
+    {
+        const T *cg = geo + e * kGeoStride, *xq = IDq + 2 * Q * N1;
+        for (int t = tid; t < 6 * Q; t += nt) {
+            const int r = t / Q, qq = t % Q, cc = r / 3, dd = r % 3;
+            const T n0 = T(0.5) * (T(1) - xq[qq]), n1 = T(0.5) * (T(1) + xq[qq]);
+            sE1[t] = n0 * cg[(cc * 2 + 0) * 3 + dd] + n1 * cg[(cc * 2 + 1) * 3 + dd];
+            sE2[t] = n0 * cg[12 + (cc * 2 + 0) * 3 + dd] + n1 * cg[12 + (cc * 2 + 1) * 3 + dd];
+            sA3[t] = n0 * cg[24 + (cc * 2 + 0) * 3 + dd] + n1 * cg[24 + (cc * 2 + 1) * 3 + dd];
+        }
+        for (int t = tid; t < Q; t += nt) sW[t] = IDq[2 * Q * N1 + Q + t];
+    }
     const int b0 = (int)(blockIdx.x % S) * BR, nb = min(BR, Q - b0);
     const int ex = (int)(e % d.nx), ey = (int)((e / d.nx) % d.ny), ez = (int)(e / ((int64_t)d.nx * d.ny));
     const bool col = tid < nb * Q;
@@ -195,8 +216,8 @@ __global__ void __launch_bounds__(opg_threads(P, S)) k_op_general(const double *
             T s0 = 0, s1 = 0;
 #pragma unroll
             for (int ii = 0; ii < N1; ++ii) {
-                s0 += sI[aa * N1 + ii] * xs[kj * N1 + ii];
-                s1 += sD[aa * N1 + ii] * xs[kj * N1 + ii];
+                s0 += sIt[ii * Q + aa] * xs[kj * N1 + ii];
+                s1 += sDt[ii * Q + aa] * xs[kj * N1 + ii];
             }
             X1[t] = s0;
             DX1[t] = s1;
@@ -211,9 +232,9 @@ __global__ void __launch_bounds__(opg_threads(P, S)) k_op_general(const double *
 #pragma unroll
                     for (int jj = 0; jj < N1; ++jj) {
                         const T xv = X1[(kk * N1 + jj) * Q + a], dv = DX1[(kk * N1 + jj) * Q + a];
-                        s0 += sI[b * N1 + jj] * xv;
-                        s1 += sD[b * N1 + jj] * xv;
-                        s2 += sI[b * N1 + jj] * dv;
+                        s0 += sIt[jj * Q + b] * xv;
+                        s1 += sDt[jj * Q + b] * xv;
+                        s2 += sIt[jj * Q + b] * dv;
                     }
                     AA[k] = s0;
                     AB[k] = s1;
@@ -227,17 +248,37 @@ __global__ void __launch_bounds__(opg_threads(P, S)) k_op_general(const double *
 #pragma unroll
     for (int k = 0; k < N1; ++k) AAo[k] = ABo[k] = BAo[k] = 0;
     if (col) {
-        // metric of point c + 1 loaded while point c is computed
-        const T *g = Gw + e * 6 * (int64_t)Q3 + b * Q + a;
-        T gn[6];
+        // The weighted metric w kappa |det J| J^{-1} J^{-T} (Sec. 2.7) at point (a, b, c) from
+        // the tables above instead of a stream from memory.  Rows of J^{-1} are cross products
+        // of J's columns over det J, so G_mn = w kappa (c_m . c_n) / det J (det J > 0 is checked
+        // at setup).  The table reads in the loop are kept there (not held in registers).
+        const T *xq = IDq + 2 * Q * N1;
+        const T eta = xq[b], nb0 = T(0.5) * (T(1) - eta), nb1 = T(0.5) * (T(1) + eta);
+        T J3[3];
 #pragma unroll
-        for (int m = 0; m < 6; ++m) gn[m] = g[m * Q3];
+        for (int dd = 0; dd < 3; ++dd) J3[dd] = nb0 * sA3[dd * Q + a] + nb1 * sA3[(3 + dd) * Q + a];
+        const T wab = sW[a] * sW[b] * geo[e * kGeoStride + 36];
         for (int c = 0; c < Q; ++c) {
-            const T gxx = gn[0], gyy = gn[1], gzz = gn[2], gxy = gn[3], gxz = gn[4], gyz = gn[5];
-            if (c + 1 < Q) {
+            int ia = a, ib = b;
+            asm volatile("" : "+v"(ia), "+v"(ib));
+            const T zeta = xq[c], nc0 = T(0.5) * (T(1) - zeta), nc1 = T(0.5) * (T(1) + zeta);
+            T J1[3], J2[3];
 #pragma unroll
-                for (int m = 0; m < 6; ++m) gn[m] = g[m * Q3 + (c + 1) * Q2];
+            for (int dd = 0; dd < 3; ++dd) {
+                J1[dd] = nc0 * sE1[dd * Q + ib] + nc1 * sE1[(3 + dd) * Q + ib];
+                J2[dd] = nc0 * sE2[dd * Q + ia] + nc1 * sE2[(3 + dd) * Q + ia];
             }
+            const T c1[3] = {J2[1] * J3[2] - J2[2] * J3[1], J2[2] * J3[0] - J2[0] * J3[2], J2[0] * J3[1] - J2[1] * J3[0]};
+            const T c2[3] = {J3[1] * J1[2] - J3[2] * J1[1], J3[2] * J1[0] - J3[0] * J1[2], J3[0] * J1[1] - J3[1] * J1[0]};
+            const T c3[3] = {J1[1] * J2[2] - J1[2] * J2[1], J1[2] * J2[0] - J1[0] * J2[2], J1[0] * J2[1] - J1[1] * J2[0]};
+            const T det = J1[0] * c1[0] + J1[1] * c1[1] + J1[2] * c1[2];
+            const T sc = wab * sW[c] / det;
+            const T gxx = sc * (c1[0] * c1[0] + c1[1] * c1[1] + c1[2] * c1[2]);
+            const T gyy = sc * (c2[0] * c2[0] + c2[1] * c2[1] + c2[2] * c2[2]);
+            const T gzz = sc * (c3[0] * c3[0] + c3[1] * c3[1] + c3[2] * c3[2]);
+            const T gxy = sc * (c1[0] * c2[0] + c1[1] * c2[1] + c1[2] * c2[2]);
+            const T gxz = sc * (c1[0] * c3[0] + c1[1] * c3[1] + c1[2] * c3[2]);
+            const T gyz = sc * (c2[0] * c3[0] + c2[1] * c3[1] + c2[2] * c3[2]);
             T ux = 0, uy = 0, uz = 0;
 #pragma unroll
             for (int k = 0; k < N1; ++k) {
@@ -279,8 +320,8 @@ __global__ void __launch_bounds__(opg_threads(P, S)) k_op_general(const double *
             const T *s0p = S0 + kk * BR * Q, *s1p = S1 + kk * BR * Q, *s2p = S2 + kk * BR * Q;
             T s0 = 0, s1 = 0;
             for (int bb = 0; bb < nb; ++bb) {
-                s0 += sI[(b0 + bb) * N1 + jj] * s0p[bb * Q + aa] + sD[(b0 + bb) * N1 + jj] * s1p[bb * Q + aa];
-                s1 += sI[(b0 + bb) * N1 + jj] * s2p[bb * Q + aa];
+                s0 += sIt[jj * Q + b0 + bb] * s0p[bb * Q + aa] + sDt[jj * Q + b0 + bb] * s1p[bb * Q + aa];
+                s1 += sIt[jj * Q + b0 + bb] * s2p[bb * Q + aa];
             }
             Y1[t] = s0;
             DY1[t] = s1;
@@ -637,13 +678,13 @@ void launch_op_kron(const Dims &d, const T *AB1d, const T *mu, const T *x, T *E,
 }
 
 template <typename T>
-int launch_op_general(const Dims &d, const T *IDq, const T *Gw, const T *x, T *E, const Exec &e) {
+int launch_op_general(const Dims &d, const T *IDq, const T *geo, const T *x, T *E, const Exec &e) {
     int64_t ncell = (int64_t)d.nx * d.ny * d.nz;
     const int split = std::is_same<T, double>::value ? e.t.opg_split64 : e.t.opg_split32;
     if (split != 0 && split != 1 && split != 2) throw Error(VSR_EINVAL, "operator split must be 0 (default), 1 or 2");
     int slots = 1;
 #define CALLS(P, S) \
-    hipLaunchKernelGGL((k_op_general<T, P, S>), dim3((unsigned)(ncell * S)), dim3(opg_threads(P, S)), 0, e.s, e.gate, d, IDq, Gw, x, E)
+    hipLaunchKernelGGL((k_op_general<T, P, S>), dim3((unsigned)(ncell * S)), dim3(opg_threads(P, S)), 0, e.s, e.gate, d, IDq, geo, x, E)
 #define CALL(P)                                                                                  \
     {                                                                                            \
         const int sp = split ? split : (sizeof(T) == 8 && opg_threads(P, 1) > 512 ? 2 : 1);     \

@@ -13,6 +13,7 @@
 #include <string>
 #include <vector>
 
+#include "kernels.h"
 #include "vsr_internal.h"
 
 namespace vsr {
@@ -894,6 +895,33 @@ PatchSet make_patches(int nx, int ny, int nz, const OneD &od, const double *mu, 
     if (failed) throw Error(VSR_ENOTSPD, "patch Cholesky failed on " + std::to_string(failed) + " patches");
     (void)m;
     return P;
+}
+
+// Per-cell data from which the operator kernels evaluate the metric of the trilinear map
+// (Sec. 2.7) at any point: the halved edge differences of the 8 corners along each reference
+// axis and the cell's kappa, kGeoStride values per cell (layout in kernels.h).
+std::vector<double> make_cell_geometry(int nx, int ny, int nz, const double *V, const double *kappa) {
+    const int64_t ncell = (int64_t)nx * ny * nz;
+    std::vector<double> out((size_t)ncell * kGeoStride, 0.0);
+    auto vid = [&](int i, int j, int k) { return 3 * ((int64_t)i + (nx + 1) * ((int64_t)j + (ny + 1) * (int64_t)k)); };
+    for (int64_t e = 0; e < ncell; ++e) {
+        const int i = (int)(e % nx), j = (int)((e / nx) % ny), k = (int)(e / ((int64_t)nx * ny));
+        double X[2][2][2][3];
+        for (int c = 0; c < 2; ++c)
+            for (int b = 0; b < 2; ++b)
+                for (int a = 0; a < 2; ++a)
+                    for (int d = 0; d < 3; ++d) X[c][b][a][d] = V[vid(i + a, j + b, k + c) + d];
+        double *o = &out[(size_t)e * kGeoStride];
+        for (int u = 0; u < 2; ++u)
+            for (int v = 0; v < 2; ++v)
+                for (int d = 0; d < 3; ++d) {
+                    o[(u * 2 + v) * 3 + d] = 0.5 * (X[u][v][1][d] - X[u][v][0][d]);        // d/dxi: (c, b)
+                    o[12 + (u * 2 + v) * 3 + d] = 0.5 * (X[u][1][v][d] - X[u][0][v][d]);   // d/deta: (c, a)
+                    o[24 + (u * 2 + v) * 3 + d] = 0.5 * (X[1][u][v][d] - X[0][u][v][d]);   // d/dzeta: (b, a)
+                }
+        o[36] = kappa ? kappa[e] : 1.0;
+    }
+    return out;
 }
 
 // ============================================================ coarse space (Sec. 2.5)

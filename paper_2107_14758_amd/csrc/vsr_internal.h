@@ -46,6 +46,8 @@ struct Geometry {
 };
 Geometry make_geometry(int nx, int ny, int nz, const double *vertices, const double *kappa,
                        const OneD &od, bool keep_metric);
+// Halved corner edge differences and kappa per cell, for the operator's on-the-fly metric.
+std::vector<double> make_cell_geometry(int nx, int ny, int nz, const double *vertices, const double *kappa);
 
 // ------------------------------------------------------------------ patches
 // Box coordinates of a patch run over [0, 2m] per axis (m = p-1); the star's
