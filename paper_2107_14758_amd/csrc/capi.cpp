@@ -83,6 +83,8 @@ struct vsr_problem {
     void *rF = nullptr, *zF = nullptr, *U = nullptr;
     void *c3 = nullptr, *c4 = nullptr;    // coarse right-hand side and solution
     void *z1 = nullptr, *res = nullptr;   // cycle iterate and cycle residual
+    void *rF0 = nullptr, *c0 = nullptr, *e8 = nullptr;   // T^T r, P^T r and per-cell Q1 corner values
+                                                        // of the Cartesian V-cycle
     double *E64 = nullptr;                // element vectors of the operator (2 slots per cell)
     void *E32 = nullptr;
     double *vp = nullptr, *vq = nullptr, *vr = nullptr, *vz = nullptr, *vt = nullptr;
@@ -218,13 +220,16 @@ const T *xm(const vsr_problem *P, int kind) {
 
 // out = alpha * S in + beta * out,  S = T (sum_j Rbar_j^T A_j^{-1} Rbar_j) T^T  (Sec. 2.4-2.6);
 // out64, dotv and partials as for launch_transfer (the prolongation writes out)
+// rF_given (may be NULL): T^T of the input, already formed (in is then not read).
 template <typename T, typename Tin>
 void relax_apply(vsr_problem *P, const Tin *in, T *out, T alpha, T beta, double *out64 = nullptr,
-                 const double *dotv = nullptr, double *partials = nullptr) {
+                 const double *dotv = nullptr, double *partials = nullptr, const T *rF_given = nullptr) {
     const int L[3] = {P->d.Lx, P->d.Ly, P->d.Lz}, NC[3] = {P->d.nx, P->d.ny, P->d.nz};
-    T *rF = (T *)P->rF, *zF = (T *)P->zF, *U = (T *)P->U;
-    launch_transfer<Tin, T>(XFER_FDM_RESTRICT, P->d.p, NC, L, L, xm<T>(P, XFER_FDM_RESTRICT), in, rF, T(1), T(0),
-                            P->ex());
+    const T *rF = rF_given ? rF_given : (const T *)P->rF;
+    T *zF = (T *)P->zF, *U = (T *)P->U;
+    if (!rF_given)
+        launch_transfer<Tin, T>(XFER_FDM_RESTRICT, P->d.p, NC, L, L, xm<T>(P, XFER_FDM_RESTRICT), in, (T *)P->rF, T(1),
+                                T(0), P->ex());
     hipEvent_t e0 = nullptr, e1 = nullptr;
     const bool prof = P->profiling && !P->capturing;
     if (prof) {
@@ -249,6 +254,28 @@ void relax_apply(vsr_problem *P, const Tin *in, T *out, T alpha, T beta, double 
     VSR_HIP(hipGetLastError());
 }
 
+template <typename T>
+const T *ab(const vsr_problem *P) {
+    if constexpr (std::is_same<T, double>::value) return P->AB64;
+    else return P->AB32;
+}
+template <typename T>
+const T *mu_of(const vsr_problem *P) {
+    if constexpr (std::is_same<T, double>::value) return P->mu64;
+    else return P->mu32;
+}
+
+// c4 = A0^{-1} c3: dense inverse or multigrid V-cycle
+template <typename T>
+void coarse_solve(vsr_problem *P) {
+    if (P->coarse_gmg) {
+        if constexpr (std::is_same<T, double>::value) launch_mg_vcycle<double>(P->mg64, P->ex());
+        else launch_mg_vcycle<float>(P->mg32, P->ex());
+    } else {
+        launch_dense_gemv<T>(P->nc, (const T *)P->A0inv, (const T *)P->c3, (T *)P->c4, T(1), T(0), P->ex());
+    }
+}
+
 // out = alpha * P A0^{-1} P^T in + beta * out  (Sec. 2.5)
 template <typename T, typename Tin>
 void coarse_apply(vsr_problem *P, const Tin *in, T *out, T alpha, T beta) {
@@ -261,12 +288,7 @@ void coarse_apply(vsr_problem *P, const Tin *in, T *out, T alpha, T beta) {
     T *c3 = (T *)P->c3, *c4 = (T *)P->c4;
     launch_transfer<Tin, T>(XFER_COARSE_RESTRICT, P->d.p, NC, L, c, xm<T>(P, XFER_COARSE_RESTRICT), in, c3, T(1), T(0),
                             P->ex());
-    if (P->coarse_gmg) {
-        if constexpr (std::is_same<T, double>::value) launch_mg_vcycle<double>(P->mg64, P->ex());
-        else launch_mg_vcycle<float>(P->mg32, P->ex());
-    } else {
-        launch_dense_gemv<T>(P->nc, (const T *)P->A0inv, c3, c4, T(1), T(0), P->ex());
-    }
+    coarse_solve<T>(P);
     launch_transfer<T, T>(XFER_COARSE_PROLONG, P->d.p, NC, c, L, xm<T>(P, XFER_COARSE_PROLONG), c4, out, alpha, beta,
                           P->ex());
     VSR_HIP(hipGetLastError());
@@ -286,6 +308,34 @@ void precondition(vsr_problem *P, const double *r, double *z, int mode, int dot_
     } else if (P->opt.cycle == 1) {
         relax_apply<T, double>(P, r, z1, T(1), T(0));
         coarse_apply<T, double>(P, r, z1, T(1), T(1));
+    } else if (P->cartesian) {
+        // hybrid V(1,1) on separable cells, with the two cycle residuals only ever restricted:
+        // T^T (r - A z2) = T^T r - sum_K R_K^T That^T A^K z2_K and P^T (r - A z1) likewise, the
+        // restrictions applied per cell by the operator kernel (Sec. 2.4, 2.5)
+        const int L[3] = {P->d.Lx, P->d.Ly, P->d.Lz}, NC[3] = {P->d.nx, P->d.ny, P->d.nz};
+        T *rF0 = (T *)P->rF0, *rF = (T *)P->rF, *c0 = (T *)P->c0, *c3 = (T *)P->c3, *c4 = (T *)P->c4, *e8 = (T *)P->e8;
+        const T *AB = ab<T>(P), *mu = mu_of<T>(P);
+        launch_transfer<double, T>(XFER_FDM_RESTRICT, P->d.p, NC, L, L, xm<T>(P, XFER_FDM_RESTRICT), r, rF0, T(1), T(0),
+                                   P->ex());
+        launch_transfer<double, T>(XFER_COARSE_RESTRICT, P->d.p, NC, L, P->cdim, xm<T>(P, XFER_COARSE_RESTRICT), r, c0,
+                                   T(1), T(0), P->ex());
+        relax_apply<T, T>(P, nullptr, z1, w, T(0), nullptr, nullptr, nullptr, rF0);   // z1 = w S r
+        if (P->nc > 0) {
+            launch_op_kron_restrict<T>(P->d, 2, AB, mu, z1, e8, P->ex());  // c3 = P^T (r - A z1)
+            launch_coarse_gather<T>(P->d, c0, e8, c3, P->ex());
+            coarse_solve<T>(P);                                             // c4 = A0^{-1} c3
+            launch_transfer<T, T>(XFER_COARSE_PROLONG, P->d.p, NC, P->cdim, L, xm<T>(P, XFER_COARSE_PROLONG), c4, z1,
+                                  T(1), T(1), P->ex());                     // z2 = z1 + P c4
+        }
+        launch_op_kron_restrict<T>(P->d, 1, AB, mu, z1, elem<T>(P), P->ex());   // rF = T^T (r - A z2)
+        launch_gather_sub<T>(P->d, elem<T>(P), rF0, rF, P->ex());
+        const bool dot = dot_mode >= 0;
+        relax_apply<T, T>(P, nullptr, z1, w, T(1), z, dot ? r : nullptr, dot ? P->partials : nullptr, rF);
+        if (dot)
+            launch_finalize(transfer_blocks(XFER_FDM_PROLONG, P->d.p, NC), P->partials, P->scal, dot_mode, P->mirror,
+                            P->ex());
+        VSR_HIP(hipGetLastError());
+        return;
     } else {
         // hybrid V(1,1): z1 = w S r; z2 = z1 + C (r - A z1); z = z2 + w S (r - A z2)
         T *res = (T *)P->res;
@@ -830,9 +880,15 @@ vsr_status vsr_setup(const vsr_mesh *mesh, int32_t p, const vsr_coefficients *co
             for (int64_t e = 0; e < P->ncell; ++e)
                 if (!(kappa[e] > 0)) throw Error(VSR_ENOTSPD, "kappa must be positive");
         int n1 = p + 1;
-        std::vector<double> ab(2 * n1 * n1), idq(2 * (size_t)qdef * n1 + 2 * (size_t)qdef);
+        // [A, B, That, linear hats at the GLL nodes] for the Cartesian operator and its restrictions
+        std::vector<double> ab(3 * n1 * n1 + 2 * n1), idq(2 * (size_t)qdef * n1 + 2 * (size_t)qdef);
         std::copy(P->od.A.begin(), P->od.A.end(), ab.begin());
         std::copy(P->od.B.begin(), P->od.B.end(), ab.begin() + n1 * n1);
+        std::copy(P->od.T.begin(), P->od.T.end(), ab.begin() + 2 * n1 * n1);
+        for (int k = 0; k < n1; ++k) {
+            ab[3 * n1 * n1 + k] = 0.5 * (1.0 - P->od.xi[k]);
+            ab[3 * n1 * n1 + n1 + k] = 0.5 * (1.0 + P->od.xi[k]);
+        }
         std::copy(P->od.Iq.begin(), P->od.Iq.end(), idq.begin());
         std::copy(P->od.Dq.begin(), P->od.Dq.end(), idq.begin() + (size_t)qdef * n1);
         std::copy(P->od.xq.begin(), P->od.xq.end(), idq.begin() + 2 * (size_t)qdef * n1);
@@ -932,6 +988,11 @@ vsr_status vsr_setup(const vsr_mesh *mesh, int32_t p, const vsr_coefficients *co
         }
         P->c3 = alloc_t(P->nc);
         P->c4 = alloc_t(P->nc);
+        if (P->cartesian) {
+            P->rF0 = alloc_t(P->n);
+            P->c0 = alloc_t(P->nc);
+            P->e8 = alloc_t(P->ncell * 8);
+        }
         if (P->coarse_gmg) {
             if (P->fp32) build_mg<float>(P.get(), H, P->mg32);
             else build_mg<double>(P.get(), H, P->mg64);

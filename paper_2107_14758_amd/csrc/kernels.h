@@ -47,6 +47,20 @@ void launch_op_kron(const Dims &d, const T *AB1d, const T *mu, const T *x, T *E,
 constexpr int kGeoStride = 40;
 template <typename T>
 int launch_op_general(const Dims &d, const T *IDq, const T *geo, const T *x, T *E, const Exec &e);
+// Cartesian operator followed by a restriction of the cell results (Sec. 2.4, 2.5): kind 1
+// stores (That^T x3) (A^K x_K) per cell in the element-vector layout (launch_gather_sub then
+// assembles FDM covectors), kind 2 stores the 8 Q1 corner values (N^T x3) (A^K x_K) per cell
+// at E[8 cell + corner] (launch_coarse_gather assembles them).  Entries at Dirichlet nodes are
+// dropped first.  AB1d = [A, B, That (node x function), Nh (2 x (p+1): the linear hats at the
+// GLL nodes)], each row-major.
+template <typename T>
+void launch_op_kron_restrict(const Dims &d, int kind, const T *AB1d, const T *mu, const T *x, T *E, const Exec &e);
+// out = rT - (the single-slot element vector E summed per free node), all in T.
+template <typename T>
+void launch_gather_sub(const Dims &d, const T *E, const T *rT, T *out, const Exec &e);
+// c3 = c0 - (the per-cell corner values e8 summed over the 8 cells around each interior vertex).
+template <typename T>
+void launch_coarse_gather(const Dims &d, const T *c0, const T *e8, T *c3, const Exec &e);
 // out = sum over the cells and slots that share each free node of E (r == nullptr), or
 // out = r - that sum (in T).  Deterministic: a fixed summation order, no atomics.  With
 // dotv, also the partial sums of dotv . out, one per workgroup (gather_blocks of them), into

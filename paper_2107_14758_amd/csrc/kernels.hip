@@ -50,7 +50,16 @@ constexpr int kron_chunk() {
     return kc < 1 ? 1 : (kc > N1 ? N1 : kc);
 }
 
-template <typename T, int P, int CPW>
+// Epilogues of the Cartesian operator.  The residual of the V-cycle is only ever restricted:
+// to FDM covectors (T^T) before a relaxation, to the Q1 space (P^T) before the coarse solve.
+// Both maps act cell by cell on an assembled vector, T^T sum_K R_K^T y_K = sum_K R_K^T (That^T
+// x3) y_K (Sec. 2.4: a node's value depends only on the FDM functions of its cell's closure;
+// likewise for the Q1 interpolation), once the entries of y_K at Dirichlet nodes are dropped.
+// EPI_FDM stores (That^T x3) y_K in place of y_K (assembled by k_gather into FDM covectors);
+// EPI_Q1 stores the 8 corner values (N^T x3) y_K per cell (assembled by k_coarse_gather).
+enum { EPI_NONE = 0, EPI_FDM = 1, EPI_Q1 = 2 };
+
+template <typename T, int P, int CPW, int EPI = EPI_NONE>
 __global__ void __launch_bounds__(256) k_op_kron(const double *__restrict__ gate, Dims d, const T *__restrict__ AB1d,
                                                  const T *__restrict__ mu, const T *__restrict__ x, T *__restrict__ E) {
     if (gated(gate)) return;
@@ -121,9 +130,113 @@ __global__ void __launch_bounds__(256) k_op_kron(const double *__restrict__ gate
             }
         }
     }
-    if (!active) return;
+    if constexpr (EPI == EPI_NONE) {
+        if (!active) return;
 #pragma unroll
-    for (int k = 0; k < N1; ++k) E[elem_index<N1>(d, ex, ey, ez, k, j, i)] = acc[k];
+        for (int k = 0; k < N1; ++k) E[elem_index<N1>(d, ex, ey, ez, k, j, i)] = acc[k];
+    } else {
+        // drop the entries at Dirichlet nodes (the assembled vector has none there)
+#pragma unroll
+        for (int k = 0; k < N1; ++k)
+            if (!active || !is_free(d, P * ez + k, P * ey + j, P * ex + i)) acc[k] = T(0);
+        if constexpr (EPI == EPI_FDM) {
+            // out(c, b, a) = sum That[k][c] That[j][b] That[i][a] y(k, j, i): z in registers, x
+            // and y through LDS, KC slabs at a time; That = AB1d[2 N2 ..] (node x function)
+            const T *Th = AB1d + 2 * N2;
+            T az[N1];
+#pragma unroll
+            for (int c = 0; c < N1; ++c) {
+                T sacc = 0;
+#pragma unroll
+                for (int k = 0; k < N1; ++k) sacc += Th[k * N1 + c] * acc[k];
+                az[c] = sacc;
+            }
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch) {
+                const int c0 = ch * KC, cn = min(KC, N1 - c0);
+                __syncthreads();
+                if (active) {
+#pragma unroll
+                    for (int cc = 0; cc < KC; ++cc)
+                        if (cc < cn) xs[sb][cc * N2 + lt] = az[c0 + cc];
+                }
+                __syncthreads();
+                if (active) {
+#pragma unroll 1
+                    for (int cc = 0; cc < cn; ++cc) {
+                        T sacc = 0;
+#pragma unroll
+                        for (int ii = 0; ii < N1; ++ii) sacc += Th[ii * N1 + i] * xs[sb][cc * N2 + j * N1 + ii];
+                        as[sb][cc * N2 + lt] = sacc;
+                    }
+                }
+                __syncthreads();
+                if (active) {
+#pragma unroll 1
+                    for (int cc = 0; cc < cn; ++cc) {
+                        T sacc = 0;
+#pragma unroll
+                        for (int jj = 0; jj < N1; ++jj) sacc += Th[jj * N1 + j] * as[sb][cc * N2 + jj * N1 + i];
+                        E[elem_index<N1>(d, ex, ey, ez, c0 + cc, j, i)] = sacc;
+                    }
+                }
+            }
+        } else {
+            // 8 corner values (c, b, a) in {0,1}^3: sum N_c(k) N_b(j) N_a(i) y(k, j, i) with the
+            // linear hats at the GLL nodes, Nh = AB1d[3 N2 ..] ([corner side][node])
+            const T *Nh = AB1d + 3 * N2;
+            T m0 = 0, m1 = 0;
+#pragma unroll
+            for (int k = 0; k < N1; ++k) {
+                m0 += Nh[k] * acc[k];
+                m1 += Nh[N1 + k] * acc[k];
+            }
+            const T wa[2] = {Nh[i], Nh[N1 + i]}, wb[2] = {Nh[j], Nh[N1 + j]};
+            // reduce over the cell's N2 threads through LDS, KC corners at a time
+#pragma unroll
+            for (int q0 = 0; q0 < 8; q0 += KC) {
+                __syncthreads();
+                if (active) {
+#pragma unroll
+                    for (int qq = 0; qq < KC; ++qq) {
+                        const int q = q0 + qq;
+                        if (q < 8) xs[sb][qq * N2 + lt] = ((q >> 2) ? m1 : m0) * wb[(q >> 1) & 1] * wa[q & 1];
+                    }
+                }
+                __syncthreads();
+                if (active && lt < KC && q0 + lt < 8) {
+                    T sacc = 0;
+                    for (int t = 0; t < N2; ++t) sacc += xs[sb][lt * N2 + t];
+                    E[ec * 8 + q0 + lt] = sacc;
+                }
+            }
+        }
+    }
+}
+
+// c3[v] = c0[v] - sum over the 8 cells around interior vertex v of their corner value at v
+// (the Q1 restriction of an element vector summed per coarse vertex, fixed order).
+template <typename T>
+__global__ void __launch_bounds__(256) k_coarse_gather(const double *__restrict__ gate, Dims d, const T *__restrict__ c0,
+                                                       const T *__restrict__ e8, T *__restrict__ c3) {
+    if (gated(gate)) return;
+    const int ux = d.nx - 1, uy = d.ny - 1, uz = d.nz - 1;
+    const int64_t nv = (int64_t)ux * uy * uz;
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nv) return;
+    const int vx = (int)(v % ux) + 1, vy = (int)((v / ux) % uy) + 1, vz = (int)(v / ((int64_t)ux * uy)) + 1;
+    T vals[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        // cell (vx - 1 + ax, ...) sees vertex v as its corner (1 - ax, 1 - ay, 1 - az)
+        const int ax = q & 1, ay = (q >> 1) & 1, az = q >> 2;
+        const int64_t cell = ((int64_t)(vz - 1 + az) * d.ny + (vy - 1 + ay)) * d.nx + (vx - 1 + ax);
+        vals[q] = e8[cell * 8 + ((1 - az) * 2 + (1 - ay)) * 2 + (1 - ax)];
+    }
+    T sum = 0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) sum += vals[q];
+    c3[v] = c0[v] - sum;
 }
 
 // Launch geometry of the general operator: S workgroups per cell, each with ceil(Q/S)
@@ -358,7 +471,8 @@ __device__ __forceinline__ int axis_cells(int g, int c[2], int l[2]) {
 template <typename T, int P>
 __global__ void __launch_bounds__(XB) k_gather(const double *__restrict__ gate, Dims d, int slots, const T *__restrict__ E,
                                                 const double *__restrict__ r, T *__restrict__ out,
-                                                const double *__restrict__ dotv, double *__restrict__ partials) {
+                                                const double *__restrict__ dotv, double *__restrict__ partials,
+                                                const T *__restrict__ rT) {
     if (gated(gate)) return;
     constexpr int N1 = P + 1, N3 = N1 * N1 * N1;
     const int xblocks = (d.Lx + XB - 1) / XB;
@@ -388,7 +502,7 @@ __global__ void __launch_bounds__(XB) k_gather(const double *__restrict__ gate, 
 #pragma unroll
         for (int t = 0; t < 4; ++t) sum += v[s][t][0] + v[s][t][1];
     const int64_t idx = ((int64_t)(K - 1) * d.Ly + (J - 1)) * d.Lx + (I - 1);
-    const T o = r == nullptr ? sum : (T)r[idx] - sum;
+    const T o = rT != nullptr ? rT[idx] - sum : (r == nullptr ? sum : (T)r[idx] - sum);
     if (live) out[idx] = o;
     if (dotv != nullptr) {   // partial sum of dotv . out for this workgroup
         const double prod = block_sum(live ? dotv[idx] * (double)o : 0.0);
@@ -723,9 +837,53 @@ template <typename T>
 void launch_gather(const Dims &d, int slots, const T *E, const double *r, T *out, const Exec &e, const double *dotv,
                    double *partials) {
 #define CALL(P) \
-    hipLaunchKernelGGL((k_gather<T, P>), dim3(line_blocks(d)), dim3(XB), 0, e.s, e.gate, d, slots, E, r, out, dotv, partials)
+    hipLaunchKernelGGL((k_gather<T, P>), dim3(line_blocks(d)), dim3(XB), 0, e.s, e.gate, d, slots, E, r, out, dotv, partials, \
+                       (const T *)nullptr)
     VSR_P_SWITCH(d.p, CALL)
 #undef CALL
+}
+
+template <typename T>
+void launch_gather_sub(const Dims &d, const T *E, const T *rT, T *out, const Exec &e) {
+#define CALL(P)                                                                                                   \
+    hipLaunchKernelGGL((k_gather<T, P>), dim3(line_blocks(d)), dim3(XB), 0, e.s, e.gate, d, 1, E, (const double *)nullptr, \
+                       out, (const double *)nullptr, (double *)nullptr, rT)
+    VSR_P_SWITCH(d.p, CALL)
+#undef CALL
+}
+
+template <typename T>
+void launch_op_kron_restrict(const Dims &d, int kind, const T *AB1d, const T *mu, const T *x, T *E, const Exec &e) {
+    const int64_t ncell = (int64_t)d.nx * d.ny * d.nz;
+    int cpw = std::is_same<T, double>::value ? e.t.op_cpw64 : e.t.op_cpw32;
+    if (cpw != 1 && cpw != 2 && cpw != 4) throw Error(VSR_EINVAL, "op cells per workgroup must be 1, 2 or 4");
+    if (kind != EPI_FDM && kind != EPI_Q1) throw Error(VSR_EINVAL, "unknown operator restriction");
+    if ((d.p + 1) * (d.p + 1) > 64) cpw = 1;
+#define CALLE(P, C, K)                                                                                              \
+    hipLaunchKernelGGL((k_op_kron<T, P, C, K>), dim3((unsigned)((ncell + C - 1) / C)), dim3(round64(C * (P + 1) * (P + 1))), \
+                       0, e.s, e.gate, d, AB1d, mu, x, E)
+#define CALLC(P, C)                        \
+    if (kind == EPI_FDM) CALLE(P, C, EPI_FDM); \
+    else CALLE(P, C, EPI_Q1)
+#define CALL(P)                                                  \
+    if constexpr ((P + 1) * (P + 1) <= 64) {                     \
+        if (cpw == 4) { CALLC(P, 4); }                           \
+        else if (cpw == 2) { CALLC(P, 2); }                      \
+        else { CALLC(P, 1); }                                    \
+    } else {                                                     \
+        CALLC(P, 1);                                             \
+    }
+    VSR_P_SWITCH(d.p, CALL)
+#undef CALL
+#undef CALLC
+#undef CALLE
+}
+
+template <typename T>
+void launch_coarse_gather(const Dims &d, const T *c0, const T *e8, T *c3, const Exec &e) {
+    const int64_t nv = (int64_t)(d.nx - 1) * (d.ny - 1) * (d.nz - 1);
+    if (nv == 0) return;
+    hipLaunchKernelGGL((k_coarse_gather<T>), dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, e.s, e.gate, d, c0, e8, c3);
 }
 
 int64_t gather_blocks(const Dims &d) { return line_blocks(d); }
@@ -793,6 +951,9 @@ int launch_axpby_to_double(int64_t n, double a, const T *x, double b, double *y,
     template void launch_fill<T>(int64_t, T *, T, const Exec &);                                          \
     template void launch_gather<T>(const Dims &, int, const T *, const double *, T *, const Exec &, const double *, \
                                    double *);                                                                    \
+    template void launch_gather_sub<T>(const Dims &, const T *, const T *, T *, const Exec &);                   \
+    template void launch_op_kron_restrict<T>(const Dims &, int, const T *, const T *, const T *, T *, const Exec &); \
+    template void launch_coarse_gather<T>(const Dims &, const T *, const T *, T *, const Exec &);              \
     template int launch_axpby_to_double<T>(int64_t, double, const T *, double, double *, const Exec &, const double *, \
                                            double *);
 INST(float)
