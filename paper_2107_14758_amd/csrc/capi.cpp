@@ -96,6 +96,7 @@ struct vsr_problem {
     const double *gate = nullptr;
     double *mirror = nullptr;         // host-visible copy of the stop flag (batched solves)
     Tuning tune{};
+    uint64_t tune_version = 0;        // bumped by every vsr_set_tuning
     double *vx = nullptr;             // solution of a batched solve
     vsr_batch *self = nullptr;        // batch of this problem alone (graph-replayed single solves)
     Exec ex() const { return Exec{stream, gate, tune}; }
@@ -640,6 +641,7 @@ struct vsr_batch {
     hipEvent_t poll[2] = {nullptr, nullptr};
     bool eager = false;
     bool owns_members = true;
+    std::vector<uint64_t> recorded_tune;   // each member's tune_version when the graph was recorded
 
     ~vsr_batch();
     void solve(const double *const *b_dev, double *const *x_dev, double rtol, vsr_solve_info *infos);
@@ -766,7 +768,19 @@ void vsr_batch::solve(const double *const *b_dev, double *const *x_dev, double r
             ++i;
         });
     }
+    if (exec) {   // a member retuned since the recording: the graph holds its old launch shapes
+        bool stale = recorded_tune.size() != members.size();
+        for (size_t k = 0; k < members.size() && !stale; ++k) stale = recorded_tune[k] != members[k]->tune_version;
+        if (stale) {
+            VSR_HIP(hipGraphExecDestroy(exec));
+            VSR_HIP(hipGraphDestroy(graph));
+            exec = nullptr;
+            graph = nullptr;
+        }
+    }
     if (!eager && !exec) {
+        recorded_tune.clear();
+        for (vsr_problem *P : members) recorded_tune.push_back(P->tune_version);
         for (vsr_problem *P : members) P->capturing = true;
         VSR_HIP(hipStreamBeginCapture(origin, hipStreamCaptureModeThreadLocal));
         try {
@@ -1194,7 +1208,8 @@ vsr_status vsr_set_tuning(vsr_problem *P, const int32_t shapes[6]) {
         t.opg_split32 = shapes[4];
         t.patch_threads = shapes[5];
         P->tune = t;
-        delete P->self;   // its recorded iteration holds the old shapes
+        ++P->tune_version;   // recorded iterations (its own, a batch's) are re-recorded at their next solve
+        delete P->self;
         P->self = nullptr;
     });
 }

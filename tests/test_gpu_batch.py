@@ -231,3 +231,28 @@ def test_shared_factors_give_the_same_solve(vsr, relax_fp32):
     assert pj.factor_info() == pj_own.factor_info()
     for q in (own, shared, pj, pj_own):
         q.close()
+
+
+def test_retuning_a_member_between_batch_solves(vsr):
+    """A member retuned after the batch recorded its iteration: the next batch solve records the
+    iteration again with the new launch shapes and still matches the member's single solve."""
+    say("case batch retune")
+    probs, fs = zip(*[member_problem(*m, seed=40 + i) for i, m in enumerate(MEMBERS[:3])])
+    B = vsr.Batch(list(probs), relax_fp32=False, seed=0, batch_streams=2)
+    bs = [rhs(m, f) for m, f in zip(B.members, fs)]
+    xs = [torch.zeros_like(b) for b in bs]
+    B.pcg_solve(bs, xs)
+    m = B.members[1]
+    old = m.tuning()
+    new = (2, 2, 8 if old[2] != 8 else 4, 1 if old[3] != 1 else 2, 2 if old[4] != 2 else 1, 512 if old[5] != 512 else 256)
+    m.set_tuning(new)
+    assert m.tuning() == new
+    xs = [torch.zeros_like(b) for b in bs]
+    infos = B.pcg_solve(bs, xs)
+    for i, (mm, b, x, info) in enumerate(zip(B.members, bs, xs, infos)):
+        x1 = torch.zeros_like(b)
+        ref = mm.pcg_solve(b, x1)
+        say(f"  member {i}: its {info['iterations']} vs {ref['iterations']}, x rel diff {rel(x, x1):.1e}")
+        assert info["converged"] == 1 and info["iterations"] == ref["iterations"]
+        assert rel(x, x1) < 1e-10
+    B.close()
