@@ -80,7 +80,7 @@ struct vsr_problem {
     MGCycle<float> mg32{};
     MGCycle<double> mg64{};
     // work buffers (cycle precision unless noted)
-    void *rF = nullptr, *zF = nullptr, *U = nullptr;
+    void *rF = nullptr, *U = nullptr;
     void *c3 = nullptr, *c4 = nullptr;    // coarse right-hand side and solution
     void *z1 = nullptr, *res = nullptr;   // cycle iterate and cycle residual
     void *rF0 = nullptr, *c0 = nullptr, *e8 = nullptr;   // T^T r, P^T r and per-cell Q1 corner values
@@ -227,7 +227,7 @@ void relax_apply(vsr_problem *P, const Tin *in, T *out, T alpha, T beta, double 
                  const double *dotv = nullptr, double *partials = nullptr, const T *rF_given = nullptr) {
     const int L[3] = {P->d.Lx, P->d.Ly, P->d.Lz}, NC[3] = {P->d.nx, P->d.ny, P->d.nz};
     const T *rF = rF_given ? rF_given : (const T *)P->rF;
-    T *zF = (T *)P->zF, *U = (T *)P->U;
+    T *U = (T *)P->U;
     if (!rF_given)
         launch_transfer<Tin, T>(XFER_FDM_RESTRICT, P->d.p, NC, L, L, xm<T>(P, XFER_FDM_RESTRICT), in, (T *)P->rF, T(1),
                                 T(0), P->ex());
@@ -249,9 +249,9 @@ void relax_apply(vsr_problem *P, const Tin *in, T *out, T alpha, T beta, double 
         VSR_HIP(hipEventRecord(e1, P->stream));
         ++P->events_used;
     }
-    launch_patch_assemble<T>(P->d, P->opt.interior_patches_only, U, zF, P->ex());
-    launch_transfer<T, T>(XFER_FDM_PROLONG, P->d.p, NC, L, L, xm<T>(P, XFER_FDM_PROLONG), zF, out, alpha, beta, P->ex(),
-                          out64, dotv, partials);
+    // scatter-add of the star boxes fused into the prolongation's window loads
+    launch_transfer<T, T>(XFER_FDM_PROLONG, P->d.p, NC, L, L, xm<T>(P, XFER_FDM_PROLONG), U, out, alpha, beta, P->ex(),
+                          out64, dotv, partials, P->opt.interior_patches_only ? 2 : 1);
     VSR_HIP(hipGetLastError());
 }
 
@@ -991,7 +991,6 @@ vsr_status vsr_setup(const vsr_mesh *mesh, int32_t p, const vsr_coefficients *co
         };
         (void)es;
         P->rF = alloc_t(P->n);
-        P->zF = alloc_t(P->n);
         P->U = alloc_t(nv * w3);
         P->z1 = alloc_t(P->n);
         P->res = alloc_t(P->n);

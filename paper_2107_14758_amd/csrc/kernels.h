@@ -84,10 +84,13 @@ void launch_load_vector(const Dims &d, const double *IDq, const double *wdet, co
 // there widened to FP64; with partials non-null too, each workgroup leaves its sum of
 // dotv . out64 over the outputs it owns in partials[block] (transfer_blocks of them, zeros
 // from workgroups that own none) for launch_finalize.
+// box_mode (XFER_FDM_PROLONG only): 1 = in holds the patch solves' star boxes ((2p-1)^3 per mesh
+// vertex) and the prolongation reads their assembled sum (the scatter-add of Sec. 2.5) instead of
+// a lattice vector; 2 = the same with only the interior vertices' stars; 0 = a lattice vector.
 template <typename Tin, typename T>
 void launch_transfer(int kind, int p, const int ncell[3], const int in_dims[3], const int out_dims[3], const T *M,
                      const Tin *in, T *out, T alpha, T beta, const Exec &e, double *out64 = nullptr,
-                     const double *dotv = nullptr, double *partials = nullptr);
+                     const double *dotv = nullptr, double *partials = nullptr, int box_mode = 0);
 // Workgroups of one launch_transfer of this kind.
 int transfer_blocks(int kind, int p, const int ncell[3]);
 
@@ -103,8 +106,6 @@ template <typename T>
 void launch_patch_all(const Dims &d, const PatchArgs &a, int n_int, const int *verts, const int *fidx, const T *fint, int n_bnd,
                       const int *desc, const int64_t *off, const T *fbnd, const T *mu, const T *lam, const T *afc,
                       const T *rF, T *U, const Exec &e);
-template <typename T>
-void launch_patch_assemble(const Dims &d, int interior_only, const T *U, T *zF, const Exec &e);
 
 // y = alpha * A x + beta * y for a dense row-major n x n matrix.
 template <typename T>

@@ -33,17 +33,59 @@ __device__ __forceinline__ double xfer_block_sum(double v) {
     return s;
 }
 
+// Value of the assembled star boxes (sum over the stars whose boxes hold it, Sec. 2.5) at free
+// lattice node (I, J, K), 1-based: the patch scatter-add evaluated where the prolongation
+// needs it.  Boxes are (2p-1)^3 per mesh vertex, x fastest; interior_only drops the stars of
+// boundary vertices.  Every candidate load is issued before the fixed-order sum.
+template <typename T, int P>
+__device__ __forceinline__ T star_box_sum(const T *__restrict__ U, int nx, int ny, int nz, int interior_only, int I, int J,
+                                          int K) {
+    constexpr int m = P - 1, w = 2 * m + 1, w3 = w * w * w;
+    const int P3[3] = {I, J, K}, ncell[3] = {nx, ny, nz};
+    int v[3][2], a[3][2], nc[3];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        const int Pp = P3[ax], e = Pp / P, al = Pp - e * P;
+        if (al == 0) {
+            v[ax][0] = e; a[ax][0] = m; v[ax][1] = e; a[ax][1] = m; nc[ax] = 1;
+        } else {
+            v[ax][0] = e; a[ax][0] = m + al; v[ax][1] = e + 1; a[ax][1] = al - 1; nc[ax] = 2;
+        }
+        if (interior_only) {
+            int k = 0;
+            for (int t = 0; t < nc[ax]; ++t)
+                if (v[ax][t] >= 1 && v[ax][t] <= ncell[ax] - 1) { v[ax][k] = v[ax][t]; a[ax][k] = a[ax][t]; ++k; }
+            nc[ax] = k;
+        }
+    }
+    T val[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const int tz = t >> 2, ty = (t >> 1) & 1, tx = t & 1;
+        const bool ok = tz < nc[2] && ty < nc[1] && tx < nc[0];
+        const int64_t vid = ((int64_t)v[2][tz] * (ny + 1) + v[1][ty]) * (nx + 1) + v[0][tx];
+        val[t] = ok ? U[vid * w3 + (a[2][tz] * w + a[1][ty]) * w + a[0][tx]] : T(0);
+    }
+    T sum = 0;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) sum += val[t];
+    return sum;
+}
+
 // Per axis, cell e maps inputs e*IS + in_off + s (s < K) to outputs e*out_step + a (a < OA)
 // with the OA x K row-major matrix M.  out = alpha * (M x M x M) in + beta * out.
 // A workgroup takes a brick of CX x CY x 1 cells: their windows along x and y overlap and
 // are staged once (KX = K + (CX-1) IS by KY = K + (CY-1) IS values per z-plane).  The z
 // inputs are taken UC planes at a time so that the window fits the LDS budget.
-template <typename Tin, typename T, int OA, int K, int IS, int CX, int CY>
+// BOXES (the FDM prolongation only): in holds the star boxes of the patch solves, and the
+// window is their assembled sum (star_box_sum; box_mode 2 = interior stars only) instead of a
+// lattice vector, so the scatter-add needs no pass of its own.
+template <typename Tin, typename T, int OA, int K, int IS, int CX, int CY, bool BOXES = false>
 __global__ void __launch_bounds__(XFER_THREADS)
     k_transfer(const double *__restrict__ gate, const T *__restrict__ M, int ncx, int ncy, int ncz, int in_off,
                int out_step, int ix, int iy, int iz, int ox, int oy, int oz, const Tin *__restrict__ in,
                T *__restrict__ out, T alpha, T beta, double *__restrict__ out64, const double *__restrict__ dotv,
-               double *__restrict__ partials) {
+               double *__restrict__ partials, int box_mode) {
     if (gated(gate)) return;
     constexpr int KX = K + (CX - 1) * IS, KY = K + (CY - 1) * IS;   // window extents along x and y
     constexpr int AX = CX * OA, AY = CY * OA;                       // outputs along x and y
@@ -86,9 +128,12 @@ __global__ void __launch_bounds__(XFER_THREADS)
             const int i = tid + l * XFER_THREADS;
             const int s = i % KX, t = (i / KX) % KY, u = i / (KX * KY);
             const int xi = x0 + s, yi = y0 + t, zi = z0 + u0 + u;
-            wv[l] = (i < NW && u < uc && xi >= 0 && xi < ix && yi >= 0 && yi < iy && zi >= 0 && zi < iz)
-                        ? (T)in[((int64_t)zi * iy + yi) * ix + xi]
-                        : T(0);
+            const bool inside = i < NW && u < uc && xi >= 0 && xi < ix && yi >= 0 && yi < iy && zi >= 0 && zi < iz;
+            if constexpr (BOXES)
+                wv[l] = inside ? star_box_sum<T, OA>((const T *)in, ncx, ncy, ncz, box_mode == 2, xi + 1, yi + 1, zi + 1)
+                               : T(0);
+            else
+                wv[l] = inside ? (T)in[((int64_t)zi * iy + yi) * ix + xi] : T(0);
         }
 #pragma unroll
         for (int l = 0; l < NL; ++l) {
@@ -186,7 +231,7 @@ int transfer_blocks(int kind, int p, const int ncell[3]) {
 template <typename Tin, typename T>
 void launch_transfer(int kind, int p, const int ncell[3], const int in_dims[3], const int out_dims[3], const T *M,
                      const Tin *in, T *out, T alpha, T beta, const Exec &e, double *out64, const double *dotv,
-                     double *partials) {
+                     double *partials, int box_mode) {
     const int nc = ncell[0] * ncell[1] * ncell[2];
     if (nc == 0 || (int64_t)out_dims[0] * out_dims[1] * out_dims[2] == 0) {
         const int nb = transfer_blocks(kind, p, ncell);
@@ -197,10 +242,19 @@ void launch_transfer(int kind, int p, const int ncell[3], const int in_dims[3], 
     {                                                                                                                  \
         constexpr int CX = brick_x(KIND, OA), CY = brick_y(KIND, OA);                                                  \
         const int nb = ((ncell[0] + CX - 1) / CX) * ((ncell[1] + CY - 1) / CY) * ncell[2];                            \
-        hipLaunchKernelGGL((k_transfer<Tin, T, OA, K, IS, CX, CY>), dim3(8u * (unsigned)((nb + 7) / 8)),              \
-                           dim3(XFER_THREADS), 0, e.s, e.gate, M, ncell[0], ncell[1], ncell[2], IO, OS, in_dims[0],   \
-                           in_dims[1], in_dims[2], out_dims[0], out_dims[1], out_dims[2], in, out, alpha, beta,       \
-                           out64, dotv, partials);                                                                    \
+        if (box_mode != 0) {                                                                                           \
+            if constexpr (KIND == XFER_FDM_PROLONG && std::is_same<Tin, T>::value)                                     \
+                hipLaunchKernelGGL((k_transfer<Tin, T, OA, K, IS, CX, CY, true>), dim3(8u * (unsigned)((nb + 7) / 8)), \
+                                   dim3(XFER_THREADS), 0, e.s, e.gate, M, ncell[0], ncell[1], ncell[2], IO, OS,        \
+                                   in_dims[0], in_dims[1], in_dims[2], out_dims[0], out_dims[1], out_dims[2], in, out, \
+                                   alpha, beta, out64, dotv, partials, box_mode);                                      \
+            else throw Error(VSR_EINVAL, "star-box input is for the FDM prolongation only");                           \
+        } else {                                                                                                       \
+            hipLaunchKernelGGL((k_transfer<Tin, T, OA, K, IS, CX, CY>), dim3(8u * (unsigned)((nb + 7) / 8)),          \
+                               dim3(XFER_THREADS), 0, e.s, e.gate, M, ncell[0], ncell[1], ncell[2], IO, OS, in_dims[0], \
+                               in_dims[1], in_dims[2], out_dims[0], out_dims[1], out_dims[2], in, out, alpha, beta,   \
+                               out64, dotv, partials, 0);                                                             \
+        }                                                                                                              \
     }
 #define CALL(P)                                                               \
     switch (kind) {                                                           \
@@ -217,12 +271,12 @@ void launch_transfer(int kind, int p, const int ncell[3], const int in_dims[3], 
 
 template void launch_transfer<double, double>(int, int, const int *, const int *, const int *, const double *,
                                               const double *, double *, double, double, const Exec &, double *,
-                                              const double *, double *);
+                                              const double *, double *, int);
 template void launch_transfer<float, float>(int, int, const int *, const int *, const int *, const float *,
                                             const float *, float *, float, float, const Exec &, double *,
-                                            const double *, double *);
+                                            const double *, double *, int);
 template void launch_transfer<double, float>(int, int, const int *, const int *, const int *, const float *,
                                              const double *, float *, float, float, const Exec &, double *,
-                                             const double *, double *);
+                                             const double *, double *, int);
 
 }  // namespace vsr
