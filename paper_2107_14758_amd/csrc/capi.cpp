@@ -80,7 +80,7 @@ struct vsr_problem {
     MGCycle<float> mg32{};
     MGCycle<double> mg64{};
     // work buffers (cycle precision unless noted)
-    void *rF = nullptr, *U = nullptr;
+    void *rF = nullptr, *zF = nullptr, *U = nullptr;   // zF: assembled patch solutions (p > 7)
     void *c3 = nullptr, *c4 = nullptr;    // coarse right-hand side and solution
     void *z1 = nullptr, *res = nullptr;   // cycle iterate and cycle residual
     void *rF0 = nullptr, *c0 = nullptr, *e8 = nullptr;   // T^T r, P^T r and per-cell Q1 corner values
@@ -249,9 +249,18 @@ void relax_apply(vsr_problem *P, const Tin *in, T *out, T alpha, T beta, double 
         VSR_HIP(hipEventRecord(e1, P->stream));
         ++P->events_used;
     }
-    // scatter-add of the star boxes fused into the prolongation's window loads
-    launch_transfer<T, T>(XFER_FDM_PROLONG, P->d.p, NC, L, L, xm<T>(P, XFER_FDM_PROLONG), U, out, alpha, beta, P->ex(),
-                          out64, dotv, partials, P->opt.interior_patches_only ? 2 : 1);
+    if (P->d.p <= kFusedScatterMaxP) {
+        // scatter-add of the star boxes fused into the prolongation's window loads (measured
+        // faster up to degree 7; above it the windows' scattered box loads cost more than a
+        // separate assembly pass)
+        launch_transfer<T, T>(XFER_FDM_PROLONG, P->d.p, NC, L, L, xm<T>(P, XFER_FDM_PROLONG), U, out, alpha, beta,
+                              P->ex(), out64, dotv, partials, P->opt.interior_patches_only ? 2 : 1);
+    } else {
+        T *zF = (T *)P->zF;
+        launch_patch_assemble<T>(P->d, P->opt.interior_patches_only, U, zF, P->ex());
+        launch_transfer<T, T>(XFER_FDM_PROLONG, P->d.p, NC, L, L, xm<T>(P, XFER_FDM_PROLONG), zF, out, alpha, beta,
+                              P->ex(), out64, dotv, partials);
+    }
     VSR_HIP(hipGetLastError());
 }
 
@@ -991,6 +1000,7 @@ vsr_status vsr_setup(const vsr_mesh *mesh, int32_t p, const vsr_coefficients *co
         };
         (void)es;
         P->rF = alloc_t(P->n);
+        if (p > kFusedScatterMaxP) P->zF = alloc_t(P->n);
         P->U = alloc_t(nv * w3);
         P->z1 = alloc_t(P->n);
         P->res = alloc_t(P->n);

@@ -107,6 +107,12 @@ void launch_patch_all(const Dims &d, const PatchArgs &a, int n_int, const int *v
                       const int *desc, const int64_t *off, const T *fbnd, const T *mu, const T *lam, const T *afc,
                       const T *rF, T *U, const Exec &e);
 
+// Additive Schwarz sum z_F = sum_j Rbar_j^T u_j (Sec. 2.5) into a lattice vector (degrees above
+// kFusedScatterMaxP; up to it the prolongation reads the star boxes itself).
+template <typename T>
+void launch_patch_assemble(const Dims &d, int interior_only, const T *U, T *zF, const Exec &e);
+constexpr int kFusedScatterMaxP = 7;
+
 // y = alpha * A x + beta * y for a dense row-major n x n matrix.
 template <typename T>
 void launch_dense_gemv(int n, const T *A, const T *x, T *y, T alpha, T beta, const Exec &e);
