@@ -21,6 +21,10 @@ Test infrastructure only (see ``oracle/__init__``).
 * PCG (Sec. 2.8): x0 = 0, stop when the Euclidean norm of the recursively
   updated residual is at most rtol ||b||_2; the iteration count is the number
   of updates of x.
+* Condition estimate (Sec. 4, Table tab:poisson-cond): kappa(P^{-1} A) by
+  CG-Lanczos on the solve itself, i.e. the extreme eigenvalues of the Lanczos
+  tridiagonal built from the k step lengths and the k - 1 direction updates
+  of the PCG run.
 """
 import numpy as np
 import scipy.linalg as sla
@@ -51,6 +55,21 @@ def uniform_pm1(seed, n):
     """splitmix64 outputs mapped to [-1, 1) through their top 53 bits."""
     z = splitmix64(seed, n)
     return (z >> np.uint64(11)).astype(np.float64) * (2.0 ** -53) * 2.0 - 1.0
+
+
+def lanczos_extremes(alphas, betas):
+    """Extreme eigenvalues of the Lanczos tridiagonal of k (P)CG steps with step lengths
+    alpha_0..alpha_{k-1} and direction updates beta_0..beta_{k-2} (a k-th beta is ignored):
+    diagonal 1/alpha_j + beta_{j-1}/alpha_{j-1}, off-diagonal sqrt(beta_j)/alpha_j (the CG-Lanczos
+    relation, Saad, Iterative Methods for Sparse Linear Systems, Sec. 6.7.3)."""
+    k = len(alphas)
+    Tk = np.zeros((k, k))
+    for j in range(k):
+        Tk[j, j] = 1.0 / alphas[j] + (betas[j - 1] / alphas[j - 1] if j > 0 else 0.0)
+        if j + 1 < k:
+            Tk[j, j + 1] = Tk[j + 1, j] = np.sqrt(betas[j]) / alphas[j]
+    ev = np.linalg.eigvalsh(Tk)
+    return float(ev[0]), float(ev[-1])
 
 
 class Solver:
@@ -107,6 +126,7 @@ class Solver:
 
     # ---- damping -----------------------------------------------------------------
     def estimate_extremes(self, steps, seed):
+        """Extreme eigenvalues of S A from `steps` CG steps preconditioned by S."""
         r = uniform_pm1(seed, self.disc.n)
         z = self.relax(r)
         rz0 = rz = float(r @ z)
@@ -125,40 +145,42 @@ class Solver:
                 break
             p = z + beta * p
             rz = rz_new
-        k = len(alphas)
-        Tk = np.zeros((k, k))
-        for j in range(k):
-            Tk[j, j] = 1.0 / alphas[j] + (betas[j - 1] / alphas[j - 1] if j > 0 else 0.0)
-            if j + 1 < k:
-                Tk[j, j + 1] = Tk[j + 1, j] = np.sqrt(betas[j]) / alphas[j]
-        ev = np.linalg.eigvalsh(Tk)
-        return float(ev[0]), float(ev[-1])
+        return lanczos_extremes(alphas, betas)
 
     # ---- Krylov solve --------------------------------------------------------------
-    def pcg(self, b, rtol=1e-8, maxit=1000, history=False):
+    def pcg(self, b, rtol=1e-8, maxit=1000, history=False, lanczos=False):
+        """x, iterations [, residual norms] [, (lmin, lmax) of the run's Lanczos tridiagonal]."""
         b = np.asarray(b, dtype=np.float64)
         x = np.zeros_like(b)
         r = b.copy()
         bn = float(np.linalg.norm(b))
         hist = [bn]
-        if bn == 0.0:
-            return (x, 0, hist) if history else (x, 0)
-        z = self.precondition(r)
-        p = z.copy()
-        rz = float(r @ z)
+        alphas, betas = [], []
         it = 0
-        while it < maxit:
-            q = self.A(p)
-            alpha = rz / float(p @ q)
-            x += alpha * p
-            r -= alpha * q
-            it += 1
-            rn = float(np.linalg.norm(r))
-            hist.append(rn)
-            if rn <= rtol * bn:
-                break
+        if bn > 0.0:
             z = self.precondition(r)
-            rz_new = float(r @ z)
-            p = z + (rz_new / rz) * p
-            rz = rz_new
-        return (x, it, hist) if history else (x, it)
+            p = z.copy()
+            rz = float(r @ z)
+            while it < maxit:
+                q = self.A(p)
+                alpha = rz / float(p @ q)
+                alphas.append(alpha)
+                x += alpha * p
+                r -= alpha * q
+                it += 1
+                rn = float(np.linalg.norm(r))
+                hist.append(rn)
+                if rn <= rtol * bn:
+                    break
+                z = self.precondition(r)
+                rz_new = float(r @ z)
+                beta = rz_new / rz
+                betas.append(beta)
+                p = z + beta * p
+                rz = rz_new
+        out = (x, it)
+        if history:
+            out += (hist,)
+        if lanczos:
+            out += (lanczos_extremes(alphas, betas) if alphas else (0.0, 0.0),)
+        return out

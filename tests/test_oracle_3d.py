@@ -12,7 +12,7 @@ from oracle.fdm1d import setup_1d
 from oracle.gll import lagrange
 from oracle.operator import Discretization, kron3, separable_cell_matrix
 from oracle.patches import Patches
-from oracle.solver import ALPHA, Solver
+from oracle.solver import ALPHA, Solver, lanczos_extremes
 from paper_2107_14758_amd import inputs
 
 
@@ -275,6 +275,55 @@ def test_lanczos_inside_dense_spectrum_and_pcg_matches_direct():
     assert np.linalg.norm(x - xd) / np.linalg.norm(xd) < 1e-6
     xa, ita = Solver(d, od, cycle="additive").pcg(b)
     assert ita > it
+
+
+def test_cg_lanczos_extremes_of_a_known_spectrum():
+    # n CG steps on a diagonal SPD matrix from a start vector with every eigencomponent:
+    # the Lanczos tridiagonal is then similar to the matrix, so its extremes are exact
+    lam = np.array([0.5, 0.9, 1.3, 2.0, 3.7, 4.1, 6.25])
+    A = np.diag(lam)
+    r = np.linspace(1.0, 2.0, lam.size)
+    p, rz = r.copy(), float(r @ r)
+    alphas, betas = [], []
+    for _ in range(lam.size):
+        q = A @ p
+        alphas.append(rz / float(p @ q))
+        r = r - alphas[-1] * q
+        rz_new = float(r @ r)
+        betas.append(rz_new / rz)
+        p, rz = r + betas[-1] * p, rz_new
+    lmin, lmax = lanczos_extremes(alphas, betas)
+    assert abs(lmin - 0.5) < 1e-10 and abs(lmax - 6.25) < 1e-10
+    # a trailing beta does not change the k x k tridiagonal
+    assert lanczos_extremes(alphas, betas[:-1]) == (lmin, lmax)
+    # one step: the Rayleigh quotient of the start vector
+    r0 = np.linspace(1.0, 2.0, lam.size)
+    l1 = lanczos_extremes(alphas[:1], [])
+    assert abs(l1[0] - (r0 @ A @ r0) / (r0 @ r0)) < 1e-12 and l1[0] == l1[1]
+
+
+def test_pcg_condition_estimate_matches_dense_spectrum():
+    # Table tab:poisson-cond method: kappa(P^{-1} A) from the solve's own coefficients.  On a
+    # small problem solved to a tight tolerance the Ritz extremes reach those of the dense
+    # preconditioned operator M A; at rtol 1e-8 they are already inside and close.
+    d, w = jittered(2, 3, kappa=True)
+    s = Solver(d, setup_1d(3))
+    A = d.assemble().toarray()
+    M = np.stack([s.precondition(e) for e in np.eye(d.n)], axis=1)
+    ev = np.sort(np.linalg.eigvals(M @ A).real)
+    # a right-hand side with every eigencomponent; the Ritz extremes approach the spectrum's
+    # ends from inside (here lmin to 1e-14; the top eigenvalue 1 of the multiplicative cycle
+    # converges last: 0.99269, 0.99992 and 0.999993 at rtol 1e-8, 1e-13 and 1e-15)
+    g = np.random.default_rng(4).standard_normal(d.n)
+    x, it, (lmin, lmax) = s.pcg(g, rtol=1e-13, lanczos=True)
+    assert abs(lmin - ev[0]) < 1e-9 * ev[0] and 0 <= ev[-1] - lmax < 2e-4 * ev[-1]
+    b = d.load_vector(w["f"])
+    x8, it8, hist, (l8, u8) = s.pcg(b, rtol=1e-8, history=True, lanczos=True)
+    assert len(hist) == it8 + 1
+    assert ev[0] - 1e-10 <= l8 and u8 <= ev[-1] + 1e-10
+    assert (u8 / l8) > 0.9 * (ev[-1] / ev[0])
+    # x is unchanged by asking for the estimate
+    np.testing.assert_array_equal(x8, s.pcg(b, rtol=1e-8)[0])
 
 
 def test_iterations_nearly_flat_in_p():
