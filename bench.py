@@ -277,6 +277,7 @@ def main():
                    "autotune": bool(args.autotune), "launch_shapes": r32["shapes"], "parallelism": "single GPU"},
         f"iterations_p{p}": r32["iterations"],
         "true_rel_residual": r32["info"]["true_rel_residual"],
+        "kappa_estimate": r32["info"]["kappa_estimate"],
         "setup_seconds": r32["setup_s"],
         "patches": r32["patches"], "factor_entries": r32["factor_entries"],
         "roofline": roofline,
@@ -296,7 +297,7 @@ def main():
         out["p15"] = {"workload": "poisson_jitter_8x8x8_q15_lognormal", "dofs": a["n"],
                       "value": a["n"] / (a["seconds"] / 2), "fp64_plain_value": b["n"] / (b["seconds"] / 2),
                       "iterations": a["iterations"], "iterations_fp64": b["iterations"], "unit": "DOF/s",
-                      "true_rel_residual": a["info"]["true_rel_residual"]}
+                      "true_rel_residual": a["info"]["true_rel_residual"], "kappa_estimate": a["info"]["kappa_estimate"]}
         log(f"[bench] p=15: {a['iterations']} iterations, {1e3 * a['seconds'] / 2:.1f} ms/solve FP32-relaxation, "
             f"{1e3 * b['seconds'] / 2:.1f} ms FP64")
         # every interior star of this mesh is the same: one stored factor shared by all (an option,

@@ -107,6 +107,16 @@ typedef struct {
                                 cell coarsening while every axis has an even number >= 4 of cells,
                                 Galerkin levels, dense inverse on the coarsest level); 0 (default):
                                 dense up to 8,000 coarse unknowns (21^3 cells), multigrid above */
+    int32_t stagnation_window; /* relax_fp32 only: a solve whose ||r||_2 has not fallen below
+                                stagnation_factor times its reference value (||b||_2 at the start,
+                                then each value that did fall below it) for this many consecutive
+                                iterations stops as stagnated and continues from its x with the
+                                FP64 relaxation: PCG on A e = b - A x to the remaining tolerance,
+                                x += e.  The FP64 setup of the same problem this needs is made at
+                                the first stagnation and kept with the problem (twice its device
+                                memory from then on).  0 => 10; < 0: never.  Solves in profiling
+                                mode do not test for stagnation. */
+    double stagnation_factor; /* see stagnation_window; 0 => 1 (any decrease counts) */
 } vsr_options;
 
 typedef struct {
@@ -116,6 +126,16 @@ typedef struct {
     double true_rel_residual;  /* ||b - A x||_2 / ||b||_2 recomputed in FP64 at exit */
     double omega, lambda_min, lambda_max;  /* damping and its Lanczos estimates */
     double setup_seconds, solve_seconds;
+    /* CG-Lanczos on the solve itself (Sec. 4, Table tab:poisson-cond): extreme eigenvalues of the
+     * tridiagonal built from this run's step lengths alpha_j and direction updates beta_j
+     * (diagonal 1/alpha_j + beta_{j-1}/alpha_{j-1}, off-diagonal sqrt(beta_j)/alpha_j), which
+     * approach the extreme eigenvalues of P^{-1} A from inside, and their ratio, the estimate
+     * of kappa(P^{-1} A).  All three are 0 when no step was taken (b = 0) or a step length
+     * was not positive. */
+    double ritz_min, ritz_max, kappa_estimate;
+    int32_t fp64_iterations;   /* iterations taken on the FP64 relaxation after a stagnation
+                                  (included in iterations; the Ritz values are those of the
+                                  FP32-relaxation run); 0 if none */
 } vsr_solve_info;
 
 /* Fill *opt with the defaults listed above (all zero except the library's defaults). */

@@ -99,6 +99,11 @@ struct vsr_problem {
     uint64_t tune_version = 0;        // bumped by every vsr_set_tuning
     double *vx = nullptr;             // solution of a batched solve
     vsr_batch *self = nullptr;        // batch of this problem alone (graph-replayed single solves)
+    // host copies of the setup inputs, for the FP64 setup a stagnated FP32 solve continues on
+    int in_nx = 0, in_ny = 0, in_nz = 0;
+    std::vector<double> in_vertices, in_kappa, in_mu;
+    vsr_problem *twin = nullptr;      // that FP64 setup (made at the first stagnation)
+    double *ve = nullptr;             // its correction e
     Exec ex() const { return Exec{stream, gate, tune}; }
     // profiling of the interior patch-solve launches
     bool profiling = false;
@@ -428,6 +433,35 @@ double true_residual(vsr_problem *P, const double *b, const double *x) {
     return std::sqrt(std::max(0.0, dot(P, P->vt, P->vt)));
 }
 
+// Extreme eigenvalues of the Lanczos tridiagonal of k CG steps: step lengths alpha_0..k-1,
+// direction updates beta_0..k-2 (CG-Lanczos relation; Saad, Iterative Methods for Sparse
+// Linear Systems, Sec. 6.7.3).
+void lanczos_extremes(const std::vector<double> &alphas, const std::vector<double> &betas, double &lo, double &hi) {
+    const int k = (int)alphas.size();
+    std::vector<double> dg(k), of(std::max(k - 1, 0));
+    for (int j = 0; j < k; ++j) {
+        dg[j] = 1.0 / alphas[j] + (j ? betas[j - 1] / alphas[j - 1] : 0.0);
+        if (j + 1 < k) of[j] = std::sqrt(betas[j]) / alphas[j];
+    }
+    tridiag_extremes(dg, of, lo, hi);
+}
+
+// Condition estimate of the last PCG run from the (alpha, beta) record behind the device
+// scalars (see SC_NA); na is the record's length read with the scalars.
+void ritz_of_run(vsr_problem *P, int na, vsr_solve_info &info) {
+    info.ritz_min = info.ritz_max = info.kappa_estimate = 0.0;
+    if (na < 1) return;
+    std::vector<double> h(2 * (size_t)na);
+    VSR_HIP(hipMemcpy(h.data(), P->scal + SC_N, h.size() * sizeof(double), hipMemcpyDeviceToHost));
+    std::vector<double> alphas(na), betas(na - 1);
+    for (int j = 0; j < na; ++j) alphas[j] = h[2 * j];
+    for (int j = 0; j + 1 < na; ++j) betas[j] = h[2 * j + 1];
+    for (double a : alphas)
+        if (!(a > 0) || !std::isfinite(a)) return;   // breakdown: no estimate
+    lanczos_extremes(alphas, betas, info.ritz_min, info.ritz_max);
+    if (info.ritz_min > 0) info.kappa_estimate = info.ritz_max / info.ritz_min;
+}
+
 // splitmix64 (Steele, Lea & Flood 2014): output i of the stream seeded with `seed`
 uint64_t splitmix64_at(uint64_t seed, uint64_t i) {
     uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ULL;
@@ -464,13 +498,7 @@ void estimate_damping(vsr_problem *P) {
         if (rz <= 1e-28 * rz0) break;
         launch_pcg_p(P->n, P->vp, P->vz, P->scal, P->ex());
     }
-    int k = (int)alphas.size();
-    std::vector<double> dg(k), of(std::max(k - 1, 0));
-    for (int j = 0; j < k; ++j) {
-        dg[j] = 1.0 / alphas[j] + (j ? betas[j - 1] / alphas[j - 1] : 0.0);
-        if (j + 1 < k) of[j] = std::sqrt(betas[j]) / alphas[j];
-    }
-    tridiag_extremes(dg, of, P->lmin, P->lmax);
+    lanczos_extremes(alphas, betas, P->lmin, P->lmax);
     const double a = 0.25;
     P->omega = 2.0 / ((1 + a) * P->lmax + (1 - a) * P->lmin);
 }
@@ -705,6 +733,7 @@ namespace {
 
 void destroy_problem(vsr_problem *P) {
     if (!P) return;
+    destroy_problem(P->twin);
     delete P->self;
     delete P;
 }
@@ -755,6 +784,68 @@ vsr_batch::~vsr_batch() {
         for (vsr_problem *m : members) destroy_problem(m);
 }
 
+// Stagnation test window of a device-driven PCG on P (FP32 relaxation only; 0: no test).
+int stagnation_window(const vsr_problem *P) {
+    if (!P->fp32 || P->opt.stagnation_window < 0) return 0;
+    return P->opt.stagnation_window > 0 ? P->opt.stagnation_window : 10;
+}
+
+// The FP64-relaxation setup of an FP32 problem, from the inputs kept at its setup.
+vsr_problem *make_fp64_twin(vsr_problem *P) {
+    if (P->in_vertices.empty()) throw Error(VSR_EINVAL, "no setup inputs kept for a stagnation restart");
+    vsr_mesh m{P->in_nx, P->in_ny, P->in_nz, P->in_vertices.data()};
+    vsr_coefficients c{P->in_kappa.empty() ? nullptr : P->in_kappa.data(),
+                       P->in_mu.empty() ? nullptr : P->in_mu.data()};
+    vsr_options o = P->opt;
+    o.relax_fp32 = 0;
+    vsr_problem *Q = nullptr;
+    if (vsr_setup(&m, P->d.p, &c, &o, &Q) != VSR_OK)
+        throw Error(VSR_ENOMEM, std::string("FP64 setup for the stagnation restart failed: ") + g_last_error_text);
+    try {
+        Q->ve = Q->dalloc<double>(Q->n);
+        Q->self = make_batch(1, &Q, 1, Q->opt.batch_eager != 0, false);
+    } catch (...) {
+        destroy_problem(Q);
+        throw;
+    }
+    return Q;
+}
+
+struct Continued {
+    int iterations = 0;
+    bool converged = false;
+    double rel_residual = 0;   // recursive residual of the continuation over ||b||_2
+};
+
+// A stagnated FP32-relaxation solve continued from its x with the FP64 relaxation: PCG on
+// A e = r, r = b - A x, to the tolerance rtol ||b||_2 / ||r||_2, then x += e.
+Continued continue_fp64(vsr_problem *P, const double *b, double *x, double rtol, double bb) {
+    if (!P->twin) P->twin = make_fp64_twin(P);
+    vsr_problem *Q = P->twin;
+    op_residual<double>(P, b, x, P->vt);
+    const double rn = std::sqrt(std::max(0.0, dot(P, P->vt, P->vt)));   // synchronizes P's stream
+    const double bn = std::sqrt(bb);
+    Continued c;
+    c.rel_residual = rn / bn;
+    if (rn <= rtol * bn) {
+        c.converged = true;
+        return c;
+    }
+    const double *bv[1] = {P->vt};
+    double *xv[1] = {Q->ve};
+    vsr_solve_info qi{};
+    try {
+        Q->self->solve(bv, xv, rtol * bn / rn, &qi);
+    } catch (const Error &e) {
+        if (e.status != VSR_ENOCONV) throw;
+    }
+    launch_axpby_to_double<double>(P->n, 1.0, Q->ve, 1.0, x, P->ex());
+    c.iterations = qi.iterations;
+    c.converged = qi.converged != 0;
+    c.rel_residual = qi.rel_residual * rn / bn;
+    return c;
+}
+
 // Lockstep PCG of every member (see vsr_pcg_solve_batch).  The graph of one iteration is
 // recorded at the first solve and replayed; the active count is polled one replay behind,
 // so the GPU always has the next iteration queued (a replay after the last member stops
@@ -769,8 +860,9 @@ void vsr_batch::solve(const double *const *b_dev, double *const *x_dev, double r
         int i = 0;
         for_members([&](vsr_problem *P) {
             pcg_init(P, b_dev[i], P->vx);
-            launch_pcg_start(P->scal, rtol, P->opt.max_iterations > 0 ? P->opt.max_iterations : 1000, dev_done + i,
-                             P->ex());
+            launch_pcg_start(P->scal, rtol, P->opt.max_iterations > 0 ? P->opt.max_iterations : 1000,
+                             stagnation_window(P), P->opt.stagnation_factor > 0 ? P->opt.stagnation_factor : 1.0,
+                             dev_done + i, P->ex());
             P->gate = P->scal + SC_DONE;
             pcg_first_direction(P);
             P->gate = nullptr;
@@ -826,19 +918,31 @@ void vsr_batch::solve(const double *const *b_dev, double *const *x_dev, double r
         launch_cast<double, double>(P->n, P->vx, x_dev[i], P->ex());
         VSR_HIP(hipMemcpyAsync(P->host_scal, P->scal, sizeof(double) * SC_N, hipMemcpyDeviceToHost, P->stream));
         VSR_HIP(hipStreamSynchronize(P->stream));
-        const double it = P->host_scal[SC_IT], status = P->host_scal[SC_STATUS];
+        const double it = P->host_scal[SC_IT];
+        double status = P->host_scal[SC_STATUS];
         const double bb = P->host_scal[SC_BB], rr = P->host_scal[SC_RR];
-        const double tr = true_residual(P, b_dev[i], x_dev[i]);
+        const int na = it > 0 ? (int)P->host_scal[SC_NA] : 0;
         vsr_solve_info loc{};
         loc.iterations = (int32_t)it;
-        loc.converged = status == 1.0 ? 1 : 0;
         loc.rel_residual = bb > 0 ? std::sqrt(rr / bb) : 0.0;
+        loc.solve_seconds = t1 - t0;
+        if (status == 4.0) {   // stagnated: continue on the FP64 relaxation
+            const double tc = now_s();
+            Continued c = continue_fp64(P, b_dev[i], x_dev[i], rtol, bb);
+            loc.iterations += c.iterations;
+            loc.fp64_iterations = c.iterations;
+            loc.rel_residual = c.rel_residual;
+            loc.solve_seconds += now_s() - tc;
+            status = c.converged ? 1.0 : 3.0;
+        }
+        const double tr = true_residual(P, b_dev[i], x_dev[i]);
+        loc.converged = status == 1.0 ? 1 : 0;
         loc.true_rel_residual = bb > 0 ? tr / std::sqrt(bb) : 0.0;
         loc.omega = P->omega;
         loc.lambda_min = P->lmin;
         loc.lambda_max = P->lmax;
         loc.setup_seconds = P->setup_seconds;
-        loc.solve_seconds = t1 - t0;
+        ritz_of_run(P, na, loc);
         if (infos) infos[i] = loc;
         if (status == 2.0 && bb - bb != 0.0) bad_rhs = true;
         if (status != 1.0) {
@@ -848,8 +952,8 @@ void vsr_batch::solve(const double *const *b_dev, double *const *x_dev, double r
     }
     if (bad_rhs) throw Error(VSR_EINVAL, "non-finite right-hand side");
     if (!all) {
-        if (count == 1) throw Error(VSR_ENOCONV, "PCG did not converge in " + std::to_string((int)members[0]->host_scal[SC_IT]) +
-                                                   " iterations");
+        if (count == 1) throw Error(VSR_ENOCONV, "PCG did not converge in " + std::to_string(infos ? infos[0].iterations :
+                                                   (int)members[0]->host_scal[SC_IT]) + " iterations");
         throw Error(VSR_ENOCONV, "batched PCG: members not converged: " + failed);
     }
 }
@@ -895,6 +999,16 @@ vsr_status vsr_setup(const vsr_mesh *mesh, int32_t p, const vsr_coefficients *co
         if (muo)
             for (int64_t e = 0; e < 3 * P->ncell; ++e)
                 if (!std::isfinite(muo[e])) throw Error(VSR_EINVAL, "non-finite mu_override");
+        if (!(P->opt.stagnation_factor >= 0 && P->opt.stagnation_factor <= 1))
+            throw Error(VSR_EINVAL, "stagnation_factor must be in [0, 1]");
+        if (P->fp32 && P->opt.stagnation_window >= 0) {
+            P->in_nx = nx;
+            P->in_ny = ny;
+            P->in_nz = nz;
+            P->in_vertices.assign(mesh->vertices, mesh->vertices + 3 * nv);
+            if (kappa) P->in_kappa.assign(kappa, kappa + P->ncell);
+            if (muo) P->in_mu.assign(muo, muo + 3 * P->ncell);
+        }
         // 1D data and geometry
         P->od = make_1d(p, qdef);
         Geometry g = make_geometry(nx, ny, nz, mesh->vertices, kappa, P->od, false);
@@ -1025,7 +1139,12 @@ vsr_status vsr_setup(const vsr_mesh *mesh, int32_t p, const vsr_coefficients *co
         P->vr = P->dalloc<double>(P->n);
         P->vz = P->dalloc<double>(P->n);
         P->vt = P->dalloc<double>(P->n);
-        P->scal = P->dalloc<double>(SC_N);
+        {   // scalars and the (alpha, beta) record of one PCG run (max_iterations pairs)
+            const int hcap = P->opt.max_iterations > 0 ? P->opt.max_iterations : 1000;
+            std::vector<double> s0(SC_N + 2 * (size_t)hcap, 0.0);
+            s0[SC_HCAP] = (double)hcap;
+            P->scal = P->upload(s0);
+        }
         // partial sums: dot passes (at most 8192 workgroups) and the lattice-line gathers
         const int NCp[3] = {P->d.nx, P->d.ny, P->d.nz};
         P->partials = P->dalloc<double>(std::max<int64_t>(
@@ -1125,6 +1244,7 @@ vsr_status vsr_pcg_solve(vsr_problem *P, const double *b, double *x, double rtol
         }
         VSR_HIP(hipStreamSynchronize(P->stream));
         double t1 = now_s();
+        ritz_of_run(P, it > 0 ? (int)read_scalar(P, SC_NA) : 0, loc);
         double tr = true_residual(P, b, x);
         double bn = std::sqrt(bb);
         loc.iterations = it;

@@ -155,9 +155,11 @@ void launch_fill(int64_t n, T *x, T v, const Exec &e);
 // visible copy of DONE written with it.
 void launch_dot(int64_t n, const double *x, const double *y, double *partials, double *scal, int mode, double *mirror,
                 const Exec &e);
-// Start of a device-driven PCG after RR = b.b: BB = RR, IT = 0, stopping data, DONE when b = 0
-// or b is not finite (mirrored).  Not gated.
-void launch_pcg_start(double *scal, double rtol, int max_iterations, double *mirror, const Exec &e);
+// Start of a device-driven PCG after RR = b.b: BB = RR, IT = 0, stopping data (stagnation
+// test over `window` iterations for a drop of r.r below factor^2 of its reference; window 0:
+// none), DONE when b = 0 or b is not finite (mirrored).  Not gated.
+void launch_pcg_start(double *scal, double rtol, int max_iterations, int window, double factor, double *mirror,
+                      const Exec &e);
 // x += alpha p ; r -= alpha q ; r.r reduced into scal by mode (4 or 5)
 void launch_pcg_xr(int64_t n, double *x, double *r, const double *p, const double *q, double *scal, double *partials, int mode,
                    double *mirror, const Exec &e);
@@ -170,11 +172,18 @@ int launch_axpby_to_double(int64_t n, double a, const T *x, double b, double *y,
                            const double *dotv = nullptr, double *partials = nullptr);
 // Device scalars of one PCG.  A device-driven PCG (batched solves) keeps its stopping state
 // here: DONE is nonzero once the member stops; STATUS 1 converged, 2 non-finite residual,
-// 3 iteration cap; IT counts x updates.
+// 3 iteration cap, 4 stagnated (r.r has not fallen below SFAC2 times its reference value
+// REF for WIN consecutive iterations; REF is b.b at the start and each r.r that did fall
+// below it; SINCE counts the iterations since; WIN 0: no test); IT counts x updates.
+// Behind the SC_N scalars lie HCAP pairs
+// (alpha_j, beta_j) of the current (P)CG run: an initial r.z (mode 3) empties the record,
+// every step length (mode 1) appends alpha_j and counts it in NA, every direction update
+// (mode 2) stores beta_{NA-1}; steps past HCAP are not recorded.  They are the
+// coefficients of the run's Lanczos tridiagonal (condition estimate of P^{-1} A).
 enum {
     SC_PQ = 0, SC_RZ = 1, SC_RR = 2, SC_ALPHA = 3, SC_BETA = 4, SC_RZNEW = 5, SC_TMP = 6,
-    SC_DONE = 8, SC_BB = 9, SC_RTOL2 = 10, SC_IT = 11, SC_MAXIT = 12, SC_STATUS = 13,
-    SC_N = 16
+    SC_NA = 7, SC_DONE = 8, SC_BB = 9, SC_RTOL2 = 10, SC_IT = 11, SC_MAXIT = 12, SC_STATUS = 13,
+    SC_HCAP = 14, SC_REF = 15, SC_SINCE = 16, SC_WIN = 17, SC_SFAC2 = 18, SC_N = 24
 };
 
 }  // namespace vsr

@@ -640,7 +640,8 @@ constexpr int RED_BLOCKS = 1024;
 
 
 // Scalar update of a PCG reduction s into scal (thread 0 of one workgroup).  mode: 0 plain,
-// 1 p.q -> alpha, 2 r.z -> beta (and the shift), 3 initial r.z, 4 r.r, 5 r.r after an x update
+// 1 p.q -> alpha (recorded), 2 r.z -> beta (recorded, and the shift), 3 initial r.z (empties the
+// record of alphas and betas), 4 r.r, 5 r.r after an x update
 // with the device stopping test (iteration count, DONE and STATUS); `mirror` (may be NULL)
 // receives DONE for a host that polls it.
 __device__ __forceinline__ void apply_mode(double *scal, double s, int mode, double *mirror) {
@@ -648,19 +649,33 @@ __device__ __forceinline__ void apply_mode(double *scal, double s, int mode, dou
         scal[SC_TMP] = s;
     } else if (mode == 1) {
         scal[SC_PQ] = s;
-        scal[SC_ALPHA] = scal[SC_RZ] / s;
+        const double alpha = scal[SC_RZ] / s;
+        scal[SC_ALPHA] = alpha;
+        const int k = (int)scal[SC_NA];
+        if (k < (int)scal[SC_HCAP]) {
+            scal[SC_N + 2 * k] = alpha;
+            scal[SC_NA] = (double)(k + 1);
+        }
     } else if (mode == 2) {
         scal[SC_RZNEW] = s;
-        scal[SC_BETA] = s / scal[SC_RZ];
+        const double beta = s / scal[SC_RZ];
+        scal[SC_BETA] = beta;
         scal[SC_RZ] = s;
+        const int k = (int)scal[SC_NA];
+        if (k >= 1) scal[SC_N + 2 * (k - 1) + 1] = beta;
     } else if (mode == 3) {
         scal[SC_RZ] = s;
+        scal[SC_NA] = 0.0;
     } else if (mode == 4) {
         scal[SC_RR] = s;
     } else if (mode == 5) {
         scal[SC_RR] = s;
         const double it = scal[SC_IT] + 1.0;
         scal[SC_IT] = it;
+        double since = 0.0;
+        if (s < scal[SC_SFAC2] * scal[SC_REF]) scal[SC_REF] = s;
+        else since = scal[SC_SINCE] + 1.0;
+        scal[SC_SINCE] = since;
         if (!(s - s == 0.0)) {  // NaN or infinite
             scal[SC_STATUS] = 2.0;
             scal[SC_DONE] = 1.0;
@@ -669,6 +684,9 @@ __device__ __forceinline__ void apply_mode(double *scal, double s, int mode, dou
             scal[SC_DONE] = 1.0;
         } else if (it >= scal[SC_MAXIT]) {
             scal[SC_STATUS] = 3.0;
+            scal[SC_DONE] = 1.0;
+        } else if (scal[SC_WIN] > 0.0 && since >= scal[SC_WIN]) {
+            scal[SC_STATUS] = 4.0;
             scal[SC_DONE] = 1.0;
         }
         if (mirror) *mirror = scal[SC_DONE];
@@ -750,13 +768,17 @@ __global__ void k_axpby_to_double(const double *__restrict__ gate, int64_t n, do
     }
 }
 
-__global__ void k_pcg_start(double *scal, double rtol, int max_iterations, double *mirror) {
+__global__ void k_pcg_start(double *scal, double rtol, int max_iterations, int window, double factor, double *mirror) {
     if (threadIdx.x == 0) {
         const double bb = scal[SC_RR];
         scal[SC_BB] = bb;
         scal[SC_RTOL2] = rtol * rtol;
         scal[SC_IT] = 0.0;
         scal[SC_MAXIT] = (double)max_iterations;
+        scal[SC_REF] = bb;
+        scal[SC_SINCE] = 0.0;
+        scal[SC_WIN] = (double)window;
+        scal[SC_SFAC2] = factor * factor;
         const bool finite = bb - bb == 0.0;
         scal[SC_STATUS] = !finite ? 2.0 : (bb == 0.0 ? 1.0 : 0.0);
         scal[SC_DONE] = (!finite || bb == 0.0) ? 1.0 : 0.0;
@@ -916,8 +938,9 @@ void launch_dot(int64_t n, const double *x, const double *y, double *partials, d
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_THREADS), 0, e.s, e.gate, nb, partials, scal, mode, mirror);
 }
 
-void launch_pcg_start(double *scal, double rtol, int max_iterations, double *mirror, const Exec &e) {
-    hipLaunchKernelGGL(k_pcg_start, dim3(1), dim3(64), 0, e.s, scal, rtol, max_iterations, mirror);
+void launch_pcg_start(double *scal, double rtol, int max_iterations, int window, double factor, double *mirror,
+                      const Exec &e) {
+    hipLaunchKernelGGL(k_pcg_start, dim3(1), dim3(64), 0, e.s, scal, rtol, max_iterations, window, factor, mirror);
 }
 
 void launch_pcg_xr(int64_t n, double *x, double *r, const double *p, const double *q, double *scal, double *partials, int mode,

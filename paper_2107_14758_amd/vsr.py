@@ -39,14 +39,17 @@ class Options(ctypes.Structure):
                 ("omega", ctypes.c_double), ("stream", ctypes.c_void_p), ("autotune", ctypes.c_int32),
                 ("batch_streams", ctypes.c_int32), ("batch_eager", ctypes.c_int32), ("tune_cache", ctypes.c_char_p),
                 ("share_factors", ctypes.c_int32), ("deterministic", ctypes.c_int32),
-                ("coarse_solver", ctypes.c_int32)]
+                ("coarse_solver", ctypes.c_int32), ("stagnation_window", ctypes.c_int32),
+                ("stagnation_factor", ctypes.c_double)]
 
 
 class SolveInfo(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32),
                 ("rel_residual", ctypes.c_double), ("true_rel_residual", ctypes.c_double),
                 ("omega", ctypes.c_double), ("lambda_min", ctypes.c_double), ("lambda_max", ctypes.c_double),
-                ("setup_seconds", ctypes.c_double), ("solve_seconds", ctypes.c_double)]
+                ("setup_seconds", ctypes.c_double), ("solve_seconds", ctypes.c_double),
+                ("ritz_min", ctypes.c_double), ("ritz_max", ctypes.c_double), ("kappa_estimate", ctypes.c_double),
+                ("fp64_iterations", ctypes.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -152,7 +155,8 @@ class _Inputs:
 
 def make_options(relax_fp32=False, cycle=0, lanczos_steps=20, max_iterations=1000, interior_patches_only=False, seed=0,
                  omega=0.0, stream=None, autotune=False, batch_streams=0, batch_eager=False, tune_cache=None,
-                 share_factors=False, deterministic=False, coarse_solver="auto"):
+                 share_factors=False, deterministic=False, coarse_solver="auto", stagnation_window=0,
+                 stagnation_factor=0.0):
     opt = Options()
     lib().vsr_default_options(ctypes.byref(opt))
     opt.relax_fp32 = int(bool(relax_fp32))
@@ -173,6 +177,8 @@ def make_options(relax_fp32=False, cycle=0, lanczos_steps=20, max_iterations=100
     if coarse_solver not in codes:
         raise ValueError("coarse_solver must be 'auto', 'dense' or 'gmg'")
     opt.coarse_solver = codes[coarse_solver]
+    opt.stagnation_window = int(stagnation_window)
+    opt.stagnation_factor = float(stagnation_factor)
     return opt
 
 

@@ -9,8 +9,10 @@ hybrid V(1,1) vertex-star preconditioner (Sec. 2.5, 2.8: x0 = 0, stop at
 
   oracle_pcg_<workload>.json
 
-with the iteration count, the damping and its Lanczos estimates, the final
-recursive residual, ||x||_2, max |x|, and x at SAMPLES entries drawn uniformly
+with the iteration count, the damping and its Lanczos estimates, the extreme
+Ritz values of the solve's own Lanczos tridiagonal (condition estimate, Table
+tab:poisson-cond), the final recursive residual, ||x||_2, max |x|, and x at
+SAMPLES entries drawn uniformly
 without replacement by numpy's PCG64 generator seeded with SAMPLE_SEED (values
 as exact hexadecimal floats).  A full solve of the 16^3 Q7 workload takes the
 oracle about half an hour on 8 cores, so the GPU tests compare against these
@@ -54,13 +56,13 @@ def main(names):
         b = d.load_vector(w["f"])
         s = Solver(d, setup_1d(p), seed=0)
         print(f"{name}: n={d.n}, omega={s.omega:.6f}, setup {time.time() - t0:.0f} s", flush=True)
-        x, it, hist = s.pcg(b, rtol=1e-8, history=True)
+        x, it, hist, (rmin, rmax) = s.pcg(b, rtol=1e-8, history=True, lanczos=True)
         idx = sample_indices(d.n)
         out = {
             "workload": name, "seed": 0, "p": p, "n": int(d.n), "rtol": 1e-8,
             "solver": "oracle.solver.Solver(seed=0).pcg, FP64, hybrid V(1,1), patches at all vertices",
             "iterations": int(it), "omega": s.omega, "lambda_min": s.lanczos[0], "lambda_max": s.lanczos[1],
-            "final_rel_residual": hist[-1] / hist[0], "b_norm2": float(np.linalg.norm(b)),
+            "ritz_min": rmin, "ritz_max": rmax, "final_rel_residual": hist[-1] / hist[0], "b_norm2": float(np.linalg.norm(b)),
             "x_norm2": float(np.linalg.norm(x)), "x_maxabs": float(np.abs(x).max()),
             "sample_seed": SAMPLE_SEED, "indices": [int(i) for i in idx],
             "x_sample_hex": [float(v).hex() for v in x[idx]],

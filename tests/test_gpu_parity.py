@@ -146,12 +146,25 @@ def test_damping_and_pcg_fp64(vsr, name, shape, p, jit, logn):
     assert abs(lmax - s.lanczos[1]) < 1e-9 * s.lanczos[1]
     assert abs(w - s.omega) < 1e-9 * s.omega
     b = d.load_vector(f)
-    x_o, it_o = s.pcg(b)
+    x_o, it_o, (rmin, rmax) = s.pcg(b, lanczos=True)
     x = torch.zeros(d.n, dtype=torch.float64, device="cuda")
     info = prob.pcg_solve(dev(b), x)
     assert info["converged"] == 1 and info["iterations"] == it_o
     assert info["true_rel_residual"] <= 1.0001e-8
     assert close(host(x), x_o, 1e-10)
+    # condition estimate from the run's own coefficients (Table tab:poisson-cond method),
+    # device-driven and host-driven solves
+    say(f"  kappa {info['kappa_estimate']:.6f} (oracle {rmax / rmin:.6f})")
+    assert abs(info["ritz_min"] - rmin) <= 1e-8 * rmin and abs(info["ritz_max"] - rmax) <= 1e-8 * rmax
+    assert abs(info["kappa_estimate"] - rmax / rmin) <= 1e-8 * rmax / rmin
+    prob.set_profiling(True)
+    info_h = prob.pcg_solve(dev(b), x)
+    prob.set_profiling(False)
+    assert info_h["iterations"] == it_o
+    assert abs(info_h["kappa_estimate"] - rmax / rmin) <= 1e-8 * rmax / rmin
+    # b = 0: no step, no estimate
+    info0 = prob.pcg_solve(dev(np.zeros(d.n)), x)
+    assert info0["iterations"] == 0 and info0["kappa_estimate"] == 0.0
 
 
 @pytest.mark.parametrize("name,shape,p,jit,logn", CASES[1:])
@@ -284,6 +297,47 @@ def test_additive_cycle(vsr):
     z = torch.zeros(d.n, dtype=torch.float64, device="cuda")
     prob.apply_relaxation(dev(r), z, 0)
     assert rel(host(z), s.precondition(r)) < 1e-11
+
+
+def test_fp32_stagnation_continues_on_fp64_relaxation(vsr):
+    # Failure recovery: an FP32-relaxation solve whose ||r||_2 has not dropped by
+    # stagnation_factor within stagnation_window iterations continues from its x on the FP64
+    # relaxation.  Forced from the host: the hybrid cycle reduces ||r||_2 about 4x per
+    # iteration here, so a 1000x drop within 2 iterations is never met and the FP32 run stops
+    # after exactly 2 iterations.
+    say("case stagnation restart")
+    p = 3
+    V, kappa, f = mesh((3, 3, 2), p, seed=7, jitter=0.15, lognormal=True)
+    d = Discretization(V, p, kappa)
+    s = Solver(d, setup_1d(p), seed=3)
+    b = d.load_vector(f)
+    x_o, it_o, hist = s.pcg(b, history=True)
+    assert all(h1 < h0 for h0, h1 in zip(hist, hist[1:])) and hist[2] > 1e-3 * hist[0]
+    prob = vsr.Problem(V, p, kappa=kappa, seed=3, relax_fp32=True, stagnation_window=2, stagnation_factor=1e-3)
+    x = torch.zeros(d.n, dtype=torch.float64, device="cuda")
+    for _ in range(2):   # the second solve reuses the FP64 setup made by the first
+        info = prob.pcg_solve(dev(b), x)
+        say(f"  iterations {info['iterations']} ({info['fp64_iterations']} on FP64), oracle {it_o}, "
+            f"true residual {info['true_rel_residual']:.2e}")
+        assert info["converged"] == 1 and info["iterations"] - info["fp64_iterations"] == 2
+        assert it_o - 2 <= info["fp64_iterations"] <= it_o
+        assert info["true_rel_residual"] <= 1.01e-8
+        assert close(host(x), x_o, 1e-6)
+    # window < 0: no test; the default window and factor: this solve never stagnates
+    for kw in ({"stagnation_window": -1, "stagnation_factor": 1e-3}, {}):
+        q = vsr.Problem(V, p, kappa=kappa, seed=3, relax_fp32=True, **kw)
+        info = q.pcg_solve(dev(b), x)
+        assert info["converged"] == 1 and info["fp64_iterations"] == 0 and info["iterations"] <= it_o + 2
+        q.close()
+    # FP64 problems have nothing to fall back on: no test
+    q = vsr.Problem(V, p, kappa=kappa, seed=3, stagnation_window=2, stagnation_factor=1e-3)
+    info = q.pcg_solve(dev(b), x)
+    assert info["iterations"] == it_o and info["fp64_iterations"] == 0
+    q.close()
+    with pytest.raises(vsr.VsrError) as e:
+        vsr.Problem(V, p, relax_fp32=True, stagnation_factor=2.0)
+    assert e.value.status == vsr.VSR_EINVAL
+    prob.close()
 
 
 def test_error_paths(vsr):
