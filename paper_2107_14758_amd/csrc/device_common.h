@@ -21,6 +21,15 @@ __device__ __forceinline__ int64_t free_index(const Dims &d, int K, int J, int I
     return ((int64_t)(K - 1) * d.Ly + (J - 1)) * d.Lx + (I - 1);
 }
 
+// Element vectors hold (p+1)^3 values per cell laid out across cells row by row: row
+// ((ez ny + ey)(p+1) + k)(p+1) + j holds the x-rows (local i) of the cells ex = 0 .. nx-1
+// one after another, so the lattice nodes of one x-line read one contiguous run.  Slot s
+// of a general-operator split starts at s ncell (p+1)^3.
+template <int N1>
+__device__ __forceinline__ int64_t elem_index(const Dims &d, int ex, int ey, int ez, int k, int j, int i) {
+    return ((((int64_t)ez * d.ny + ey) * N1 + k) * N1 + j) * ((int64_t)d.nx * N1) + (int64_t)ex * N1 + i;
+}
+
 template <typename T>
 __device__ __forceinline__ void atomic_add_global(T *p, T v) {
     unsafeAtomicAdd(p, v);

@@ -45,8 +45,15 @@ void launch_op_kron(const Dims &d, const T *AB1d, const T *mu, const T *x, T *E,
 // X[c][0][a]) at 12 + 3 (2c + a), 0.5 (X[1][b][a] - X[0][b][a]) at 24 + 3 (2b + a), then kappa
 // at 36 (make_cell_geometry).
 constexpr int kGeoStride = 40;
+// Returns the number of element-vector slots written (workgroups per cell).  In FP64 from
+// degree kOpgMfmaMinP on, the x and y contractions run on the matrix cores (op_mfma.hip):
+// 8^3 cells at p = 15 take 0.15 instead of 0.39 ms; below it the padding of q to 32 costs
+// more than the matrix cores gain, and in FP32 they gain nothing measurable.
+constexpr int kOpgMfmaMinP = 13;
 template <typename T>
 int launch_op_general(const Dims &d, const T *IDq, const T *geo, const T *x, T *E, const Exec &e);
+template <typename T>
+int launch_op_general_mfma(const Dims &d, int split, const T *IDq, const T *geo, const T *x, T *E, const Exec &e);
 // Cartesian operator followed by a restriction of the cell results (Sec. 2.4, 2.5): kind 1
 // stores (That^T x3) (A^K x_K) per cell in the element-vector layout (launch_gather_sub then
 // assembles FDM covectors), kind 2 stores the 8 Q1 corner values (N^T x3) (A^K x_K) per cell

@@ -27,14 +27,6 @@ __device__ __forceinline__ double block_sum(double v) {
 }
 
 // ====================================================================== operator
-// Element vectors hold (p+1)^3 values per cell laid out across cells row by row: row
-// ((ez ny + ey)(p+1) + k)(p+1) + j holds the x-rows (local i) of the cells ex = 0 .. nx-1
-// one after another, so the lattice nodes of one x-line read one contiguous run.  Slot s
-// of a general-operator split starts at s ncell (p+1)^3.
-template <int N1>
-__device__ __forceinline__ int64_t elem_index(const Dims &d, int ex, int ey, int ez, int k, int j, int i) {
-    return ((((int64_t)ez * d.ny + ey) * N1 + k) * N1 + j) * ((int64_t)d.nx * N1) + (int64_t)ex * N1 + i;
-}
 
 // Separable (Cartesian) cell operator, eq. (kron) of Sec. 2.2:
 // A^K = mu1 B x B x A + mu2 B x A x B + mu3 A x B x B.  Thread (j, i) of a cell owns one
@@ -818,6 +810,8 @@ int launch_op_general(const Dims &d, const T *IDq, const T *geo, const T *x, T *
     int64_t ncell = (int64_t)d.nx * d.ny * d.nz;
     const int split = std::is_same<T, double>::value ? e.t.opg_split64 : e.t.opg_split32;
     if (split != 0 && split != 1 && split != 2) throw Error(VSR_EINVAL, "operator split must be 0 (default), 1 or 2");
+    if (std::is_same<T, double>::value && d.p >= kOpgMfmaMinP)
+        return launch_op_general_mfma<T>(d, split ? split : 1, IDq, geo, x, E, e);
     int slots = 1;
 #define CALLS(P, S) \
     hipLaunchKernelGGL((k_op_general<T, P, S>), dim3((unsigned)(ncell * S)), dim3(opg_threads(P, S)), 0, e.s, e.gate, d, IDq, geo, x, E)

@@ -92,6 +92,29 @@ def test_operator_and_load_vector(vsr, name, shape, p, jit, logn):
     assert close(host(b), d.load_vector(f), 1e-12)
 
 
+@pytest.mark.parametrize("shape,p", [((3, 2, 2), 13), ((2, 3, 2), 14), ((2, 2, 3), 15)])
+def test_general_operator_on_matrix_cores(vsr, shape, p):
+    # FP64 from p = 13 the general operator's x and y contractions run as 16x16x4 MFMA tiles
+    # (q = 21 .. 24 padded to 32), one or two workgroups per cell (the planes split in two)
+    say("case matrix-core operator", shape, p)
+    V, kappa, f = mesh(shape, p, seed=31, jitter=0.2, lognormal=True)
+    d = Discretization(V, p, kappa)
+    prob = vsr.Problem(V, p, kappa=kappa, omega=1.0)
+    x = dev(np.random.default_rng(32).uniform(-1, 1, d.n))
+    ref = d.apply(host(x))
+    base = list(prob.tuning())
+    for split in (1, 2):
+        prob.set_tuning(tuple(base[:3] + [split] + base[4:]))
+        y1 = torch.zeros_like(x)
+        y2 = torch.zeros_like(x)
+        prob.apply_operator(x, y1)
+        prob.apply_operator(x, y2)
+        say(f"  split {split}: max-abs {relmax(host(y1), ref):.2e}")
+        assert close(host(y1), ref, 1e-12)
+        assert torch.equal(y1, y2)
+    prob.close()
+
+
 @pytest.mark.parametrize("name,shape,p,jit,logn", CASES)
 def test_relaxation_modes(vsr, name, shape, p, jit, logn):
     say("case", name)
