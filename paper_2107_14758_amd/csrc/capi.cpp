@@ -1065,9 +1065,10 @@ vsr_status vsr_setup(const vsr_mesh *mesh, int32_t p, const vsr_coefficients *co
         a.det = P->opt.deterministic != 0;
         int m = L.m, w = L.w;
         // stored entries of one interior factor: leaves, B1 and B2, level-1 slice inverses, the
-        // y-diagonal top x separator block, the top-plane factor
+        // y-diagonal top x separator block, the top plane's inverse Schur complement
+        const int64_t top_entries = (int64_t)L.n_top * (L.n_top + 1) / 2;
         int64_t per_patch = (int64_t)L.n_leaf + 2LL * 4 * m * m * w + 2LL * m * w * (w + 1) / 2 +
-                            2LL * m * w * w + (int64_t)L.n_top * (L.n_top + 1) / 2;
+                            2LL * m * w * w + top_entries;
         int64_t bnd_nnz = 0, bnd_box = 0;
         for (int i = 0; i < P->n_bnd; ++i) {
             int ns = S.boundary_desc[8 * i + 7], nsl = S.boundary_desc[8 * i + 6];
@@ -1079,9 +1080,12 @@ vsr_status vsr_setup(const vsr_mesh *mesh, int32_t p, const vsr_coefficients *co
         P->factor_entries = per_patch * S.n_interior_factors + S.boundary_entries;   // stored entries
         (void)bnd_nnz;
         size_t esz = P->fp32 ? sizeof(float) : sizeof(double);
-        // one launch solves every patch: factors read twice (forward, backward), box in and out
-        P->bytes_patch_launch = (double)esz * ((double)P->n_int * (2.0 * per_patch + 2.0 * (double)w * w * w) +
-                                               2.0 * (double)bnd_nnz + 2.0 * (double)bnd_box);
+        // one launch solves every patch: factors read twice (forward, backward) except the top
+        // plane's inverse (read once), box in and out
+        P->bytes_patch_launch =
+            (double)esz * ((double)P->n_int * (2.0 * (double)(per_patch - top_entries) + (double)top_entries +
+                                               2.0 * (double)w * w * w) +
+                           2.0 * (double)bnd_nnz + 2.0 * (double)bnd_box);
         if (P->fp32) upload_patch_data<float>(P.get(), S, mu_sur);
         else upload_patch_data<double>(P.get(), S, mu_sur);
         // lattice transfers: the cell blocks of T^T, T, P^T, P

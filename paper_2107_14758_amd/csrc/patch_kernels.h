@@ -156,6 +156,26 @@ __device__ __forceinline__ T tri_inv_t_mv(const T *__restrict__ Li, int nstore, 
     return (acc[0] + acc[1]) + (acc[2] + acc[3]);
 }
 
+// Symmetric S stored as its packed lower triangle (column k holds rows k..nstore-1 from
+// offset k nstore - k (k - 1) / 2): lane i returns sum over k in [k0, k1) of S(i, k) b[k]
+// (zero for i >= rows), reading S(i, k) from column k below the diagonal and from column i
+// above it; b in LDS, read as broadcasts.
+template <typename T>
+__device__ __forceinline__ T sym_packed_mv(const T *__restrict__ Sp, int nstore, int k0, int k1, int rows, int lane,
+                                           const T *b) {
+    T acc[4] = {T(0), T(0), T(0), T(0)};
+    int off = k0 * nstore - k0 * (k0 - 1) / 2;                          // start of column k0
+    const int base = lane * nstore - lane * (lane - 1) / 2 - lane;      // S(k, lane) at base + k, k >= lane
+    const bool live = lane < rows;
+#pragma unroll 4
+    for (int k = k0; k < k1; ++k) {
+        const T v = live ? (lane >= k ? Sp[off + lane - k] : Sp[base + k]) : T(0);
+        acc[k & 3] += v * b[k];
+        off += nstore - k;
+    }
+    return (acc[0] + acc[1]) + (acc[2] + acc[3]);
+}
+
 // Value of v in lane k (k uniform across the wavefront).
 template <typename T>
 __device__ __forceinline__ T lane_value(T v, int k);
@@ -319,6 +339,101 @@ __device__ void panel_bwd(const T *__restrict__ M, int ld, int nrows, int ncols,
     }
 }
 
+// Lane move by a DPP control (row_mask and bank_mask select the lanes written; lanes whose
+// source lies outside the row read 0).
+template <int CTRL, int RM, int BM>
+__device__ __forceinline__ float dpp_mov(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, RM, BM, true));
+}
+template <int CTRL, int RM, int BM>
+__device__ __forceinline__ double dpp_mov(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, RM, BM, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, RM, BM, true);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the wavefront's 64 lanes, returned in every lane: DPP row shifts sum each 16-lane
+// row into its lane 15, row broadcasts carry the row sums into lane 63, and a readlane
+// returns it (vector ALU only; no LDS-routed shuffles).
+template <typename T>
+__device__ __forceinline__ T wave_total(T v) {
+    T s = v + dpp_mov<0x111, 0xf, 0xf>(v) + dpp_mov<0x112, 0xf, 0xf>(v) + dpp_mov<0x113, 0xf, 0xf>(v);
+    s += dpp_mov<0x114, 0xf, 0xe>(s);   // row_shr:4 into banks 1-3
+    s += dpp_mov<0x118, 0xf, 0xc>(s);   // row_shr:8 into banks 2-3: lane 15 of a row holds its sum
+    s += dpp_mov<0x142, 0xa, 0xf>(s);   // row_bcast:15 into rows 1 and 3
+    s += dpp_mov<0x143, 0xc, 0xf>(s);   // row_bcast:31 into rows 2 and 3: lane 63 holds the total
+    return lane_value(s, 63);
+}
+
+// One pass over a panel M of a symmetric matrix (column c holds rows r < nrows at
+// M[c ld + r], ld a multiple of 4, 16-byte aligned) that applies it both ways:
+// yB[r] -= sum_c M(r, c) xJ[c] for every row, and the return value of lane c (c < ncols) is
+// this wavefront's share of sum_r M(r, c) xB[r] (the caller adds the wavefronts' shares).
+// The NW wavefronts form NWR row groups times NW / NWR column groups; a lane owns up to RQ
+// row quads of its group (its rows' sums stay in registers) and each column's sum is
+// reduced across the wavefront, so every entry is loaded once.  With one column group every
+// sum is taken in a fixed order and yB is written (assign: yB = -sum); with several, the
+// groups' row sums meet in LDS atomics (yB must hold its start value).
+template <typename T, int NTH, int RQ, int NWR>
+__device__ T panel_sym(const T *__restrict__ M, int ld, int nrows, int ncols, const T *xJ, const T *xB, T *yB,
+                       bool assign) {
+    constexpr int NW = NTH / 64, NWC = NW / NWR, G = 4;   // G columns' loads in flight per step
+    static_assert(NW % NWR == 0, "whole column groups");
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, rg = wv % NWR, cg = wv / NWR;
+    const int nq = (nrows + 3) / 4, per = (nq + NWR - 1) / NWR;
+    const int qb = rg * per, qe = min(nq, qb + per);
+    const int cper = (ncols + NWC - 1) / NWC, cb = cg * cper, ce = min(ncols, cb + cper);
+    T a[RQ][4], xb[RQ][4];
+#pragma unroll
+    for (int t = 0; t < RQ; ++t) {
+        const int q = qb + lane + 64 * t;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            a[t][u] = T(0);
+            xb[t][u] = q < qe && 4 * q + u < nrows ? xB[4 * q + u] : T(0);
+        }
+    }
+    T mine = T(0);
+    for (int c0 = cb; c0 < ce; c0 += G) {
+        Vec4<T> v[G][RQ];
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+#pragma unroll
+            for (int t = 0; t < RQ; ++t) {
+                const int q = qb + lane + 64 * t;
+                if (c0 + g < ce && q < qe) v[g][t] = load4(M + (int64_t)(c0 + g) * ld + 4 * q);
+                else v[g][t] = Vec4<T>{{T(0), T(0), T(0), T(0)}};
+            }
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const T xc = c0 + g < ce ? xJ[c0 + g] : T(0);
+            T s = 0;
+#pragma unroll
+            for (int t = 0; t < RQ; ++t) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    a[t][u] += v[g][t].v[u] * xc;
+                    s += v[g][t].v[u] * xb[t][u];
+                }
+            }
+            s = wave_total(s);
+            if (lane == c0 + g) mine = s;
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < RQ; ++t) {
+        const int q = qb + lane + 64 * t;
+        if (q < qe)
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (4 * q + u < nrows) {
+                    if constexpr (NWC == 1) yB[4 * q + u] = (assign ? T(0) : yB[4 * q + u]) - a[t][u];
+                    else atomicAdd(&yB[4 * q + u], -a[t][u]);
+                }
+    }
+    return mine;
+}
+
 // Workgroup barrier that also stops the compiler from moving instructions between the
 // phases it separates (interleaving phases raises register pressure and forces spills).
 __device__ __forceinline__ void phase_sync() {
@@ -365,7 +480,18 @@ __device__ __forceinline__ void patch_interior(const int pid, Dims d, PatchArgs 
     __shared__ T smu[24], slam[M], safc[2 * M];
     __shared__ T tl[64 * 65 / 2];
     __shared__ T red[NTH];   // one 64-row partial per wavefront
-    __shared__ T zs[NS], wl[NL];   // level-1 and leaf work vectors of the top x level-1 coupling
+    // level-1 and leaf work vectors of the top x level-1 coupling; while the top plane is
+    // applied (neither is live then) the same memory holds -x_T (NS + NL >= NT)
+    __shared__ T zw[NS + NL];
+    T *const zs = zw, *const wl = zw + NS, *const xt = zw;
+    // panel_sym's shape: row groups of at most 64 row quads of the tallest panel (whole
+    // wavefronts' worth of lanes), the wavefronts left over split the columns; one row
+    // group per wavefront (no atomics) in the deterministic mode
+    constexpr int TOP_NQ = NT > 64 ? (NT - 64 + 3) / 4 : 1;
+    constexpr int TOP_NWR0 = (TOP_NQ + 63) / 64 < NTH / 64 ? (TOP_NQ + 63) / 64 : NTH / 64;
+    constexpr int TOP_NWR = TOP_NWR0 <= 1 ? 1 : (TOP_NWR0 <= 2 ? 2 : (TOP_NWR0 <= 4 ? 4 : NTH / 64));
+    constexpr int TOP_RQ = (TOP_NQ + 64 * TOP_NWR - 1) / (64 * TOP_NWR);
+    constexpr int TOP_RQD = (TOP_NQ + NTH - 1) / NTH;
     // the 2m slice inverses are applied four times (forward, the coupling, backward twice):
     // staged once in LDS while they fit in 9 KB (FP64 p=7 included: its registers already
     // hold it to 4 workgroups per CU, and the LDS fits 4), and in FP32 from degree 11 on
@@ -482,39 +608,38 @@ __device__ __forceinline__ void patch_interior(const int pid, Dims d, PatchArgs 
         gt[i] -= acc;
     }
     phase_sync();
-    // dense top plane, 64-column tiles: wave 0 solves the diagonal block from LDS, then all
-    // waves update the rows below while the next diagonal block is staged
+    // dense top plane: x_T = S_T^{-1} g_T with the stored inverse of the top plane's Schur
+    // complement (S_T = L_T L_T^T; one symmetric product instead of the two triangular
+    // sweeps), 64-column tiles of its lower triangle, each read once: per tile the diagonal
+    // block from LDS (the k-range split over the wavefronts) and the panel below it both ways.
+    // xt accumulates -x_T (the first tile's products start it: tile 0's panel covers every
+    // row below it).
+    static_assert(NS + NL >= NT, "xt fits the coupling's work vectors");
+    const bool top_atomic = !A.det && TOP_NWR < nw;   // column groups meet in LDS atomics
+    if (top_atomic) {   // they need -x_T to start at zero (zs, wl are no longer read)
+        for (int i = tid; i < NT; i += nt) xt[i] = T(0);
+        phase_sync();
+    }
     for (int J = 0; J < NTILE; ++J) {
         const int c0 = 64 * J, nb = min(64, NT - c0);
-        // diagonal block: y = L^{-1} b from the staged inverse, the k-range split over the waves
-        const int kw = 64 / nw;   // columns of the block per wavefront
-        red[tid] = tri_inv_mv<T>(tl, tile_ns(J), min(kw * wv, nb), min(kw * wv + kw, nb), nb, lane, gt + c0);
-        phase_sync();
-        // every wavefront adds the partials itself and stores the (identical) solved block, so it
-        // goes on to the panel without a second barrier: it reads only values its own lanes
-        // stored, and the LDS operations of one wavefront are performed in order
-        if (lane < nb) gt[c0 + lane] = sum_waves(red, nw, lane);
+        const int kw = 64 / nw;
+        T part = sym_packed_mv<T>(tl, tile_ns(J), min(kw * wv, nb), min(kw * wv + kw, nb), nb, lane, gt + c0);
         const T *D = F + tile_offset(A.off_Ltop, NT, J);
         const int rows = NT - c0 - nb;
-        panel_fwd<T, UNR, NTH>(D + 64 * 65 / 2, (rows + 3) / 4 * 4, rows, nb, gt + c0, gt + c0 + nb, A.det != 0);
+        if (top_atomic)
+            part += panel_sym<T, NTH, TOP_RQ, TOP_NWR>(D + 64 * 65 / 2, (rows + 3) / 4 * 4, rows, nb, gt + c0,
+                                                       gt + c0 + nb, xt + c0 + nb, false);
+        else
+            part += panel_sym<T, NTH, TOP_RQD, NTH / 64>(D + 64 * 65 / 2, (rows + 3) / 4 * 4, rows, nb, gt + c0,
+                                                         gt + c0 + nb, xt + c0 + nb, J == 0);
+        red[tid] = part;
+        phase_sync();
+        if (wv == 0 && lane < nb) xt[c0 + lane] = (J == 0 && !top_atomic ? T(0) : xt[c0 + lane]) - sum_waves(red, nw, lane);
         if (J + 1 < NTILE) stage_tile(J + 1);
         phase_sync();
     }
-    // ---- backward: top plane (tile NTILE-1 is staged)
-    for (int J = NTILE - 1; J >= 0; --J) {
-        const int c0 = 64 * J, nb = min(64, NT - c0);
-        const int kw = 64 / nw;
-        red[tid] = tri_inv_t_mv<T>(tl, tile_ns(J), min(kw * wv, nb), min(kw * wv + kw, nb), nb, lane, gt + c0);
-        phase_sync();
-        if (lane < nb) gt[c0 + lane] = sum_waves(red, nw, lane);   // as in the forward pass
-        if (J > 0) {
-            const int cp = 64 * (J - 1), nbp = 64, rows = NT - cp - nbp;
-            const T *Dp = F + tile_offset(A.off_Ltop, NT, J - 1);
-            panel_bwd<T, UNR, NTH>(Dp + 64 * 65 / 2, (rows + 3) / 4 * 4, rows, nbp, gt + cp + nbp, gt + cp, A.det != 0);
-            stage_tile(J - 1);
-        }
-        phase_sync();
-    }
+    for (int i = tid; i < NT; i += nt) gt[i] = -xt[i];
+    phase_sync();
     // y_S -= L_TS^T x_T = L_SS^{-1} (S_TS^T x_T - L_SL (L_TL^T x_T))
     for (int i = tid; i < NL; i += nt) {     // w_L = L_TL^T x_T (leaf (c, lx) meets top column lx)
         const int c = i / (2 * M), lx = i % (2 * M), ax = inv_la_(lx, M);

@@ -164,6 +164,40 @@ static void pack_lower_inverse(int n, const double *L, int lda, int nstore, doub
     }
 }
 
+// Lower triangle of a symmetric n x n block A (row-major, lda) packed like pack_lower_inverse
+// (column k holds rows k..nstore-1 from offset k nstore - k (k - 1) / 2; zero beyond n).
+static void pack_lower(int n, const double *A, int lda, int nstore, double *out) {
+    size_t e = 0;
+    for (int k = 0; k < nstore; ++k)
+        for (int i = k; i < nstore; ++i, ++e) out[e] = (k < n && i < n) ? A[(size_t)i * lda + k] : 0.0;
+}
+
+// S^{-1} = L^{-T} L^{-1} from the lower Cholesky factor L of S (row-major, lda): the columns
+// of L^{-1} by forward substitution (C[j][i] = (L^{-1})[i][j], i >= j), then the lower
+// triangle of their Gram matrix, (S^{-1})[i][j] = sum_{k >= i} C[i][k] C[j][k] for i >= j.
+static void inverse_from_cholesky(int n, const double *L, int lda, std::vector<double> &Sinv) {
+    std::vector<double> C((size_t)n * n, 0.0);
+    for (int j = 0; j < n; ++j) {
+        double *x = &C[(size_t)j * n];
+        for (int i = j; i < n; ++i) {
+            const double *li = L + (size_t)i * lda;
+            double v = i == j ? 1.0 : 0.0;
+            for (int k = j; k < i; ++k) v -= li[k] * x[k];
+            x[i] = v / li[i];
+        }
+    }
+    Sinv.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) {
+        const double *ci = &C[(size_t)i * n];
+        for (int j = 0; j <= i; ++j) {
+            const double *cj = &C[(size_t)j * n];
+            double t = 0;
+            for (int k = i; k < n; ++k) t += ci[k] * cj[k];
+            Sinv[(size_t)i * n + j] = t;
+        }
+    }
+}
+
 // Dense Cholesky in place (row-major, lower), returns false on a non-positive pivot.
 static bool cholesky_lower(int n, double *a, int lda) {
     for (int j = 0; j < n; ++j) {
@@ -737,16 +771,20 @@ bool factor_interior(const InteriorLayout &L, std::vector<double> &S, double *ou
                 }
             }
     if (!cholesky_lower(nt, T.data(), nt)) return false;
+    // the solve applies the top plane's S_T^{-1} = L^{-T} L^{-1} (symmetric) in one pass
+    // instead of the two triangular sweeps: its lower triangle in 64-column tiles
+    std::vector<double> Si;
+    inverse_from_cholesky(nt, T.data(), nt, Si);
     for (int J = 0; J < L.ntiles; ++J) {
         int c0 = 64 * J, nb = std::min(64, nt - c0);
-        double *D = out + L.tile_off[J];   // inverse of the diagonal block, packed in 64 columns (the last in nb)
-        pack_lower_inverse(nb, T.data() + (size_t)c0 * nt + c0, nt, J + 1 < L.ntiles ? 64 : nb, D);
+        double *D = out + L.tile_off[J];   // diagonal block, packed in 64 columns (the last in nb)
+        pack_lower(nb, Si.data() + (size_t)c0 * nt + c0, nt, J + 1 < L.ntiles ? 64 : nb, D);
         int rp = L.tile_rows_pad[J], r0 = c0 + nb;
         double *Pn = D + 64 * 65 / 2;
         for (int k = 0; k < 64; ++k)
             for (int rr = 0; rr < rp; ++rr) {
                 int r = r0 + rr;
-                Pn[(size_t)k * rp + rr] = (k < nb && r < nt) ? T[(size_t)r * nt + c0 + k] : 0.0;
+                Pn[(size_t)k * rp + rr] = (k < nb && r < nt) ? Si[(size_t)r * nt + c0 + k] : 0.0;
             }
     }
     return true;
