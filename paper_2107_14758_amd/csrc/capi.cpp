@@ -262,7 +262,7 @@ void relax_apply(vsr_problem *P, const Tin *in, T *out, T alpha, T beta, double 
                               P->ex(), out64, dotv, partials, P->opt.interior_patches_only ? 2 : 1);
     } else {
         T *zF = (T *)P->zF;
-        launch_patch_assemble<T>(P->d, P->opt.interior_patches_only, U, zF, P->ex());
+        launch_patch_assemble<T>(P->d, U, zF, P->ex());
         launch_transfer<T, T>(XFER_FDM_PROLONG, P->d.p, NC, L, L, xm<T>(P, XFER_FDM_PROLONG), zF, out, alpha, beta,
                               P->ex(), out64, dotv, partials);
     }
@@ -632,10 +632,9 @@ void autotune(vsr_problem *P) {
         launch_fill<double>(P->n, (double *)P->rF, 1.0, P->ex());
         if (P->n_int + P->n_bnd > 0) pick_patch([&] { patch(0.0); });
     }
-    // the patch boxes of absent stars must read as zero in the assembly
-    const int64_t w3 = (int64_t)P->pa.w * P->pa.w * P->pa.w, nv = (int64_t)(P->d.nx + 1) * (P->d.ny + 1) * (P->d.nz + 1);
-    if (P->fp32) launch_fill<float>(nv * w3, (float *)P->U, 0.f, P->ex());
-    else launch_fill<double>(nv * w3, (double *)P->U, 0.0, P->ex());
+    // nodes that no star of a parity class covers must read as zero in the assembly
+    if (P->fp32) launch_fill<float>(patch_solution_entries(P->d), (float *)P->U, 0.f, P->ex());
+    else launch_fill<double>(patch_solution_entries(P->d), (double *)P->U, 0.0, P->ex());
     VSR_HIP(hipStreamSynchronize(P->stream));
     std::lock_guard<std::mutex> lk(g_tune_mutex);
     g_tune_cache[key] = P->tune;
@@ -1112,14 +1111,13 @@ vsr_status vsr_setup(const vsr_mesh *mesh, int32_t p, const vsr_coefficients *co
         }
         // work buffers
         size_t es = esz;
-        int64_t w3 = (int64_t)w * w * w;
         auto alloc_t = [&](int64_t cnt) -> void * {
             return P->fp32 ? (void *)P->dalloc<float>(cnt) : (void *)P->dalloc<double>(cnt);
         };
         (void)es;
         P->rF = alloc_t(P->n);
         if (p > kFusedScatterMaxP) P->zF = alloc_t(P->n);
-        P->U = alloc_t(nv * w3);
+        P->U = alloc_t(patch_solution_entries(P->d));   // the star boxes (see launch_patch_all)
         P->z1 = alloc_t(P->n);
         P->res = alloc_t(P->n);
         {
@@ -1154,8 +1152,8 @@ vsr_status vsr_setup(const vsr_mesh *mesh, int32_t p, const vsr_coefficients *co
         P->partials = P->dalloc<double>(std::max<int64_t>(
             std::max<int64_t>(8192, gather_blocks(P->d)), transfer_blocks(XFER_FDM_PROLONG, P->d.p, NCp)));
         VSR_HIP(hipHostMalloc((void **)&P->host_scal, sizeof(double) * SC_N, hipHostMallocDefault));
-        if (P->fp32) launch_fill<float>(nv * w3, (float *)P->U, 0.f, P->ex());
-        else launch_fill<double>(nv * w3, (double *)P->U, 0.0, P->ex());
+        if (P->fp32) launch_fill<float>(patch_solution_entries(P->d), (float *)P->U, 0.f, P->ex());
+        else launch_fill<double>(patch_solution_entries(P->d), (double *)P->U, 0.0, P->ex());
         P->vx = P->dalloc<double>(P->n);
         if (P->opt.autotune) autotune(P.get());
         // damping (Sec. 2.5)

@@ -30,6 +30,22 @@ __device__ __forceinline__ int64_t elem_index(const Dims &d, int ex, int ey, int
     return ((((int64_t)ez * d.ny + ey) * N1 + k) * N1 + j) * ((int64_t)d.nx * N1) + (int64_t)ex * N1 + i;
 }
 
+// Above degree kFusedScatterMaxP the patch solutions (star boxes of (2p-1)^3 nodes around
+// each mesh vertex) are kept as 8 lattice vectors, one per vertex-parity class (vx mod 2,
+// vy mod 2, vz mod 2): boxes of stars of one class do not overlap (their vertices are two
+// cells apart along some axis), so a star writes its box into its class's vector, and nodes
+// no star of the class covers stay zero.  The scatter-add of the boxes (Sec. 2.5) at a
+// lattice node is then the sum of the 8 vectors' entries there.
+__device__ __forceinline__ int64_t star_class(int vx, int vy, int vz) { return (vx & 1) + 2 * (vy & 1) + 4 * (vz & 1); }
+
+template <typename T>
+__device__ __forceinline__ T star_box_sum(const T *__restrict__ U, int64_t n, int64_t idx) {
+    T v[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) v[c] = U[c * n + idx];
+    return ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
+}
+
 template <typename T>
 __device__ __forceinline__ void atomic_add_global(T *p, T v) {
     unsafeAtomicAdd(p, v);

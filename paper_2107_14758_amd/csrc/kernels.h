@@ -91,9 +91,10 @@ void launch_load_vector(const Dims &d, const double *IDq, const double *wdet, co
 // there widened to FP64; with partials non-null too, each workgroup leaves its sum of
 // dotv . out64 over the outputs it owns in partials[block] (transfer_blocks of them, zeros
 // from workgroups that own none) for launch_finalize.
-// box_mode (XFER_FDM_PROLONG only): 1 = in holds the patch solves' star boxes ((2p-1)^3 per mesh
-// vertex) and the prolongation reads their assembled sum (the scatter-add of Sec. 2.5) instead of
-// a lattice vector; 2 = the same with only the interior vertices' stars; 0 = a lattice vector.
+// box_mode (XFER_FDM_PROLONG up to degree kFusedScatterMaxP): 1 = in holds the patch solves'
+// star boxes ((2p-1)^3 per mesh vertex) and the prolongation reads their assembled sum (the
+// scatter-add of Sec. 2.5) instead of a lattice vector; 2 = the same with only the interior
+// vertices' stars; 0 = a lattice vector.
 template <typename Tin, typename T>
 void launch_transfer(int kind, int p, const int ncell[3], const int in_dims[3], const int out_dims[3], const T *M,
                      const Tin *in, T *out, T alpha, T beta, const Exec &e, double *out64 = nullptr,
@@ -108,7 +109,12 @@ struct PatchArgs {
     int det;   // 1: every panel sum taken by one thread in a fixed order (no LDS atomics)
 };
 
-// All patches in one launch (interior first, then boundary).
+// All patches in one launch (interior first, then boundary).  U receives the patch
+// solutions (patch_solution_entries values): up to degree kFusedScatterMaxP one (2p-1)^3
+// box per mesh vertex, read by the fused prolongation; above it 8 lattice vectors of n free
+// nodes each, one per vertex-parity class (vx mod 2) + 2 (vy mod 2) + 4 (vz mod 2), read by
+// launch_patch_assemble.  Either way, entries no star writes must hold zero (the caller
+// zeroes U once; the kernel writes its stars' entries only).
 template <typename T>
 void launch_patch_all(const Dims &d, const PatchArgs &a, int n_int, const int *verts, const int *fidx, const T *fint, int n_bnd,
                       const int *desc, const int64_t *off, const T *fbnd, const T *mu, const T *lam, const T *afc,
@@ -117,8 +123,14 @@ void launch_patch_all(const Dims &d, const PatchArgs &a, int n_int, const int *v
 // Additive Schwarz sum z_F = sum_j Rbar_j^T u_j (Sec. 2.5) into a lattice vector (degrees above
 // kFusedScatterMaxP; up to it the prolongation reads the star boxes itself).
 template <typename T>
-void launch_patch_assemble(const Dims &d, int interior_only, const T *U, T *zF, const Exec &e);
+void launch_patch_assemble(const Dims &d, const T *U, T *zF, const Exec &e);
 constexpr int kFusedScatterMaxP = 7;
+// Length of U for launch_patch_all.
+inline int64_t patch_solution_entries(const Dims &d) {
+    const int64_t w = 2 * d.p - 1;
+    return d.p <= kFusedScatterMaxP ? (int64_t)(d.nx + 1) * (d.ny + 1) * (d.nz + 1) * w * w * w
+                                    : 8 * (int64_t)d.Lx * d.Ly * d.Lz;
+}
 
 // y = alpha * A x + beta * y for a dense row-major n x n matrix.
 template <typename T>

@@ -549,48 +549,15 @@ __global__ void __launch_bounds__(1024) k_load_vector(const double *__restrict__
 }
 
 // ====================================================================== patch assembly
-// Additive Schwarz sum z_F = sum_j Rbar_j^T u_j (Sec. 2.5): each free lattice point sums
-// the boxes of the (up to 8) stars that contain it.
-template <typename T, int P>
-__global__ void __launch_bounds__(XB) k_patch_assemble(const double *__restrict__ gate, Dims d, int interior_only,
-                                                        const T *__restrict__ U, T *__restrict__ zF) {
+// Additive Schwarz sum z_F = sum_j Rbar_j^T u_j (Sec. 2.5): each free lattice node sums the
+// 8 vertex-parity vectors of the star boxes (star_box_sum).
+template <typename T>
+__global__ void __launch_bounds__(XB) k_patch_assemble(const double *__restrict__ gate, Dims d, const T *__restrict__ U,
+                                                        T *__restrict__ zF) {
     if (gated(gate)) return;
-    constexpr int m = P - 1, w = 2 * m + 1, w3 = w * w * w;
-    const int xblocks = (d.Lx + XB - 1) / XB;
-    const int line = (int)(blockIdx.x / xblocks), I = (int)(blockIdx.x - (int64_t)line * xblocks) * XB + threadIdx.x + 1;
-    if (I > d.Lx) return;
-    const int P3[3] = {I, line % d.Ly + 1, line / d.Ly + 1};
-    const int ncell[3] = {d.nx, d.ny, d.nz};
-    // the stars (vertices v) whose boxes hold this node, and its position a in each box
-    int v[3][2], a[3][2], nc[3];
-#pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-        const int Pp = P3[ax], e = Pp / P, al = Pp - e * P;
-        if (al == 0) {
-            v[ax][0] = e; a[ax][0] = m; v[ax][1] = e; a[ax][1] = m; nc[ax] = 1;
-        } else {
-            v[ax][0] = e; a[ax][0] = m + al; v[ax][1] = e + 1; a[ax][1] = al - 1; nc[ax] = 2;
-        }
-        if (interior_only) {
-            int k = 0;
-            for (int t = 0; t < nc[ax]; ++t)
-                if (v[ax][t] >= 1 && v[ax][t] <= ncell[ax] - 1) { v[ax][k] = v[ax][t]; a[ax][k] = a[ax][t]; ++k; }
-            nc[ax] = k;
-        }
-    }
-    // all (up to 8) box loads issued together (predicated), then summed in a fixed order
-    T val[8];
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-        const int tz = t >> 2, ty = (t >> 1) & 1, tx = t & 1;
-        const bool ok = tz < nc[2] && ty < nc[1] && tx < nc[0];
-        const int64_t vid = ((int64_t)v[2][tz] * (d.ny + 1) + v[1][ty]) * (d.nx + 1) + v[0][tx];
-        val[t] = ok ? U[vid * w3 + (a[2][tz] * w + a[1][ty]) * w + a[0][tx]] : T(0);
-    }
-    T s = 0;
-#pragma unroll
-    for (int t = 0; t < 8; ++t) s += val[t];
-    zF[((int64_t)(P3[2] - 1) * d.Ly + (P3[1] - 1)) * d.Lx + (I - 1)] = s;
+    const int64_t n = (int64_t)d.Lx * d.Ly * d.Lz, i = (int64_t)blockIdx.x * XB + threadIdx.x;
+    if (i >= n) return;
+    zF[i] = star_box_sum<T>(U, n, i);
 }
 
 // ====================================================================== dense / vector
@@ -843,10 +810,9 @@ void launch_load_vector(const Dims &d, const double *IDq, const double *wdet, co
 inline unsigned line_blocks(const Dims &d) { return (unsigned)(((d.Lx + XB - 1) / XB) * (int64_t)d.Ly * d.Lz); }
 
 template <typename T>
-void launch_patch_assemble(const Dims &d, int interior_only, const T *U, T *zF, const Exec &e) {
-#define CALL(P) hipLaunchKernelGGL((k_patch_assemble<T, P>), dim3(line_blocks(d)), dim3(XB), 0, e.s, e.gate, d, interior_only, U, zF)
-    VSR_P_SWITCH(d.p, CALL)
-#undef CALL
+void launch_patch_assemble(const Dims &d, const T *U, T *zF, const Exec &e) {
+    const int64_t n = (int64_t)d.Lx * d.Ly * d.Lz;
+    hipLaunchKernelGGL((k_patch_assemble<T>), dim3((unsigned)((n + XB - 1) / XB)), dim3(XB), 0, e.s, e.gate, d, U, zF);
 }
 
 template <typename T>
@@ -968,7 +934,7 @@ int launch_axpby_to_double(int64_t n, double a, const T *x, double b, double *y,
     template void launch_gather<T>(const Dims &, int, const T *, const double *, T *, const Exec &, const double *, \
                                    double *);                                                                    \
     template void launch_gather_sub<T>(const Dims &, const T *, const T *, T *, const Exec &);                   \
-    template void launch_patch_assemble<T>(const Dims &, int, const T *, T *, const Exec &);                   \
+    template void launch_patch_assemble<T>(const Dims &, const T *, T *, const Exec &);                   \
     template void launch_op_kron_restrict<T>(const Dims &, int, const T *, const T *, const T *, T *, const Exec &); \
     template void launch_coarse_gather<T>(const Dims &, const T *, const T *, T *, const Exec &);              \
     template int launch_axpby_to_double<T>(int64_t, double, const T *, double, double *, const Exec &, const double *, \

@@ -518,7 +518,13 @@ __device__ __forceinline__ void patch_interior(const int pid, Dims d, PatchArgs 
     stage_coefficients<T, M>(d, vx, vy, vz, kfull, mu, lam, afc, smu, slam, safc);
     phase_sync();
     PatchCtx<T, M> C{d, vx, vy, vz, rF, smu, slam, safc};
-    T *Uo = U + ((int64_t)(vz * (d.ny + 1) + vy) * (d.nx + 1) + vx) * (int64_t)(W * W * W);
+    // the star box: up to degree kFusedScatterMaxP stored as the vertex's own box, above it
+    // in the lattice vector of the star's vertex-parity class (boxes of one class do not
+    // overlap) at the lattice nodes it covers (see launch_patch_all)
+    constexpr bool PARITY = P > kFusedScatterMaxP;
+    T *Uc = PARITY ? U + star_class(vx, vy, vz) * ((int64_t)d.Lx * d.Ly * d.Lz)
+                   : U + ((int64_t)(vz * (d.ny + 1) + vy) * (d.nx + 1) + vx) * (int64_t)(W * W * W);
+    const int X0 = vx * P - M, Y0 = vy * P - M, Z0 = vz * P - M;   // lattice node of box position 0
 
     // ---- condensation of the interior DOFs into the interface right-hand side
     auto iface_pos = [&](int idx, int pos[3]) {   // position of interface DOF idx; returns its axis
@@ -727,16 +733,19 @@ __device__ __forceinline__ void patch_interior(const int pid, Dims d, PatchArgs 
             if (idx >= W3) break;
             const int ax = idx % W, ay = (idx / W) % W, az = idx / (W * W);
             const int ii = iface_interior(ax, ay, az, M, W, NL, NS);
+            T val;
             if (ii >= 0) {
-                Uo[idx] = g[ii];
+                val = g[ii];
             } else {
                 const int pos[3] = {ax, ay, az};
-                Uo[idx] = C.back_interior_r(pos, full, rv[u], [&](int a) {
+                val = C.back_interior_r(pos, full, rv[u], [&](int a) {
                     int q[3] = {ax, ay, az};
                     q[a] = M;
                     return g[iface_interior(q[0], q[1], q[2], M, W, NL, NS)];
                 });
             }
+            if constexpr (PARITY) Uc[free_index(d, Z0 + az, Y0 + ay, X0 + ax)] = val;
+            else Uc[idx] = val;
         }
     }
 }
@@ -789,7 +798,10 @@ __device__ __forceinline__ void patch_boundary(const int pid, Dims d, const int 
         }
         return sidx(hb, pos[hb]) + M * sidx(hc, pos[hc]);
     };
-    T *Uo = U + ((int64_t)(ds[2] * (d.ny + 1) + ds[1]) * (d.nx + 1) + ds[0]) * (int64_t)(W * W * W);
+    constexpr bool PARITY = P > kFusedScatterMaxP;   // the layouts of patch_interior
+    T *Uc = PARITY ? U + star_class(ds[0], ds[1], ds[2]) * ((int64_t)d.Lx * d.Ly * d.Lz)
+                   : U + ((int64_t)(ds[2] * (d.ny + 1) + ds[1]) * (d.nx + 1) + ds[0]) * (int64_t)(W * W * W);
+    const int X0 = ds[0] * P - M, Y0 = ds[1] * P - M, Z0 = ds[2] * P - M;
     for (int idx = tid; idx < n; idx += nt) {
         int pos[3];
         decode(idx, pos);
@@ -820,17 +832,19 @@ __device__ __forceinline__ void patch_boundary(const int pid, Dims d, const int 
     const int tot = cnt[0] * cnt[1] * cnt[2];
     for (int idx = tid; idx < tot; idx += nt) {
         int pos[3] = {lo[0] + idx % cnt[0], lo[1] + (idx / cnt[0]) % cnt[1], lo[2] + idx / (cnt[0] * cnt[1])};
-        int box = (pos[2] * W + pos[1]) * W + pos[0];
         bool iface = (full[0] && pos[0] == M) || (full[1] && pos[1] == M) || (full[2] && pos[2] == M);
+        T val;
         if (iface) {
-            Uo[box] = g[encode(pos)];
+            val = g[encode(pos)];
         } else {
-            Uo[box] = C.back_interior(pos, full, [&](int a) {
+            val = C.back_interior(pos, full, [&](int a) {
                 int q[3] = {pos[0], pos[1], pos[2]};
                 q[a] = M;
                 return g[encode(q)];
             });
         }
+        if constexpr (PARITY) Uc[free_index(d, Z0 + pos[2], Y0 + pos[1], X0 + pos[0])] = val;
+        else Uc[(pos[2] * W + pos[1]) * W + pos[0]] = val;
     }
 }
 

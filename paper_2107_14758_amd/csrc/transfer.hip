@@ -34,11 +34,12 @@ __device__ __forceinline__ double xfer_block_sum(double v) {
 }
 
 // Value of the assembled star boxes (sum over the stars whose boxes hold it, Sec. 2.5) at free
-// lattice node (I, J, K), 1-based: the patch scatter-add evaluated where the prolongation
-// needs it.  Boxes are (2p-1)^3 per mesh vertex, x fastest; interior_only drops the stars of
-// boundary vertices.  Every candidate load is issued before the fixed-order sum.
+// lattice node (I, J, K), 1-based, with the boxes stored per mesh vertex ((2p-1)^3 each, x
+// fastest; the layout up to degree kFusedScatterMaxP): the patch scatter-add evaluated where
+// the prolongation needs it; interior_only drops the stars of boundary vertices.  Every
+// candidate load is issued before the fixed-order sum.
 template <typename T, int P>
-__device__ __forceinline__ T star_box_sum(const T *__restrict__ U, int nx, int ny, int nz, int interior_only, int I, int J,
+__device__ __forceinline__ T star_box_gather(const T *__restrict__ U, int nx, int ny, int nz, int interior_only, int I, int J,
                                           int K) {
     constexpr int m = P - 1, w = 2 * m + 1, w3 = w * w * w;
     const int P3[3] = {I, J, K}, ncell[3] = {nx, ny, nz};
@@ -77,9 +78,9 @@ __device__ __forceinline__ T star_box_sum(const T *__restrict__ U, int nx, int n
 // A workgroup takes a brick of CX x CY x 1 cells: their windows along x and y overlap and
 // are staged once (KX = K + (CX-1) IS by KY = K + (CY-1) IS values per z-plane).  The z
 // inputs are taken UC planes at a time so that the window fits the LDS budget.
-// BOXES (the FDM prolongation only): in holds the star boxes of the patch solves, and the
-// window is their assembled sum (star_box_sum; box_mode 2 = interior stars only) instead of a
-// lattice vector, so the scatter-add needs no pass of its own.
+// BOXES (the FDM prolongation up to degree kFusedScatterMaxP): in holds the star boxes of the
+// patch solves, and the window is their assembled sum (star_box_gather; box_mode 2 = interior
+// stars only) instead of a lattice vector, so the scatter-add needs no pass of its own.
 template <typename Tin, typename T, int OA, int K, int IS, int CX, int CY, bool BOXES = false>
 __global__ void __launch_bounds__(XFER_THREADS)
     k_transfer(const double *__restrict__ gate, const T *__restrict__ M, int ncx, int ncy, int ncz, int in_off,
@@ -130,7 +131,7 @@ __global__ void __launch_bounds__(XFER_THREADS)
             const int xi = x0 + s, yi = y0 + t, zi = z0 + u0 + u;
             const bool inside = i < NW && u < uc && xi >= 0 && xi < ix && yi >= 0 && yi < iy && zi >= 0 && zi < iz;
             if constexpr (BOXES)
-                wv[l] = inside ? star_box_sum<T, OA>((const T *)in, ncx, ncy, ncz, box_mode == 2, xi + 1, yi + 1, zi + 1)
+                wv[l] = inside ? star_box_gather<T, OA>((const T *)in, ncx, ncy, ncz, box_mode == 2, xi + 1, yi + 1, zi + 1)
                                : T(0);
             else
                 wv[l] = inside ? (T)in[((int64_t)zi * iy + yi) * ix + xi] : T(0);
