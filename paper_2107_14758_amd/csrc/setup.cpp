@@ -164,6 +164,17 @@ static void pack_lower_inverse(int n, const double *L, int lda, int nstore, doub
     }
 }
 
+// sum_k a[k] b[k] over k < n with eight independent partial sums, so that the dense setup
+// loops (Schur updates, Cholesky, inverses) are not serialized on the latency of one add
+static inline double dot8(const double *a, const double *b, int n) {
+    double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int k = 0;
+    for (; k + 8 <= n; k += 8)
+        for (int u = 0; u < 8; ++u) s[u] += a[k + u] * b[k + u];
+    for (; k < n; ++k) s[0] += a[k] * b[k];
+    return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+}
+
 // Lower triangle of a symmetric n x n block A (row-major, lda) packed like pack_lower_inverse
 // (column k holds rows k..nstore-1 from offset k nstore - k (k - 1) / 2; zero beyond n).
 static void pack_lower(int n, const double *A, int lda, int nstore, double *out) {
@@ -181,8 +192,7 @@ static void inverse_from_cholesky(int n, const double *L, int lda, std::vector<d
         double *x = &C[(size_t)j * n];
         for (int i = j; i < n; ++i) {
             const double *li = L + (size_t)i * lda;
-            double v = i == j ? 1.0 : 0.0;
-            for (int k = j; k < i; ++k) v -= li[k] * x[k];
+            const double v = (i == j ? 1.0 : 0.0) - dot8(li + j, x + j, i - j);
             x[i] = v / li[i];
         }
     }
@@ -191,9 +201,7 @@ static void inverse_from_cholesky(int n, const double *L, int lda, std::vector<d
         const double *ci = &C[(size_t)i * n];
         for (int j = 0; j <= i; ++j) {
             const double *cj = &C[(size_t)j * n];
-            double t = 0;
-            for (int k = i; k < n; ++k) t += ci[k] * cj[k];
-            Sinv[(size_t)i * n + j] = t;
+            Sinv[(size_t)i * n + j] = dot8(ci + i, cj + i, n - i);
         }
     }
 }
@@ -201,17 +209,14 @@ static void inverse_from_cholesky(int n, const double *L, int lda, std::vector<d
 // Dense Cholesky in place (row-major, lower), returns false on a non-positive pivot.
 static bool cholesky_lower(int n, double *a, int lda) {
     for (int j = 0; j < n; ++j) {
-        double d = a[(size_t)j * lda + j];
-        for (int k = 0; k < j; ++k) d -= a[(size_t)j * lda + k] * a[(size_t)j * lda + k];
+        double d = a[(size_t)j * lda + j] - dot8(a + (size_t)j * lda, a + (size_t)j * lda, j);
         if (!(d > 0.0)) return false;
         d = std::sqrt(d);
         a[(size_t)j * lda + j] = d;
         double inv = 1.0 / d;
         for (int i = j + 1; i < n; ++i) {
-            double s = a[(size_t)i * lda + j];
             const double *ri = a + (size_t)i * lda, *rj = a + (size_t)j * lda;
-            for (int k = 0; k < j; ++k) s -= ri[k] * rj[k];
-            a[(size_t)i * lda + j] = s * inv;
+            a[(size_t)i * lda + j] = (a[(size_t)i * lda + j] - dot8(ri, rj, j)) * inv;
         }
     }
     return true;
@@ -584,7 +589,15 @@ void assemble_schur(const OneD &od, const Star &st, const IfaceMap &M, std::vect
     int n = M.n;
     S.assign((size_t)n * n, 0.0);
     const double *Af = od.Af.data(), *Bf = od.Bf.data();
-    std::vector<int> ids, lz, ly, lx;
+    // 1D partners: the j with A_F[i][j] or B_F[i][j] nonzero (an interior FDM function
+    // couples to itself and the two vertex functions only).  A pair of cell nodes couples
+    // only if it is a partner pair along every axis (each term of the Kronecker sum has an
+    // A_F or B_F factor per axis), so only those pairs are visited.
+    std::vector<std::vector<int>> partner(n1);
+    for (int i = 0; i < n1; ++i)
+        for (int j = 0; j < n1; ++j)
+            if (Af[i * n1 + j] != 0.0 || Bf[i * n1 + j] != 0.0) partner[i].push_back(j);
+    std::vector<int> ids, lz, ly, lx, cell_node((size_t)n1 * n1 * n1);
     for (int cz = 0; cz < 2; ++cz)
         for (int cy = 0; cy < 2; ++cy)
             for (int cx = 0; cx < 2; ++cx) {
@@ -614,13 +627,19 @@ void assemble_schur(const OneD &od, const Star &st, const IfaceMap &M, std::vect
                             lz.push_back(az + 1 - cz * p);
                         }
                 int nc = (int)ids.size();
+                std::fill(cell_node.begin(), cell_node.end(), -1);
+                for (int s = 0; s < nc; ++s) cell_node[((size_t)lz[s] * n1 + ly[s]) * n1 + lx[s]] = s;
                 for (int s = 0; s < nc; ++s)
-                    for (int t = 0; t < nc; ++t) {
-                        double bz = Bf[lz[s] * n1 + lz[t]], by = Bf[ly[s] * n1 + ly[t]], bx = Bf[lx[s] * n1 + lx[t]];
-                        double az_ = Af[lz[s] * n1 + lz[t]], ay_ = Af[ly[s] * n1 + ly[t]], ax_ = Af[lx[s] * n1 + lx[t]];
-                        double v = mu[0] * bz * by * ax_ + mu[1] * bz * ay_ * bx + mu[2] * az_ * by * bx;
-                        if (v != 0.0) S[(size_t)ids[s] * n + ids[t]] += v;
-                    }
+                    for (int jz : partner[lz[s]])
+                        for (int jy : partner[ly[s]])
+                            for (int jx : partner[lx[s]]) {
+                                const int t = cell_node[((size_t)jz * n1 + jy) * n1 + jx];
+                                if (t < 0) continue;
+                                double bz = Bf[lz[s] * n1 + jz], by = Bf[ly[s] * n1 + jy], bx = Bf[lx[s] * n1 + jx];
+                                double az_ = Af[lz[s] * n1 + jz], ay_ = Af[ly[s] * n1 + jy], ax_ = Af[lx[s] * n1 + jx];
+                                double v = mu[0] * bz * by * ax_ + mu[1] * bz * ay_ * bx + mu[2] * az_ * by * bx;
+                                if (v != 0.0) S[(size_t)ids[s] * n + ids[t]] += v;
+                            }
                 // condensation of the cell's interior DOFs
                 int e[3];
                 for (int d = 0; d < 3; ++d) e[d] = cc[d] == 0 ? p : 0;
@@ -743,8 +762,7 @@ bool factor_interior(const InteriorLayout &L, std::vector<double> &S, double *ou
         for (int r = 0; r < nt; ++r) {
             double *pr = &Pall[(size_t)r * ncol + s * w];
             for (int j = 0; j < w; ++j) {
-                double v = at(nl + ns + r, sep(s, j));
-                for (int k = 0; k < j; ++k) v -= pr[k] * Ls[(size_t)j * w + k];
+                const double v = at(nl + ns + r, sep(s, j)) - dot8(pr, Ls.data() + (size_t)j * w, j);
                 pr[j] = v / Ls[(size_t)j * w + j];
             }
         }
@@ -764,9 +782,7 @@ bool factor_interior(const InteriorLayout &L, std::vector<double> &S, double *ou
                     int jmax = std::min(je, i + 1);
                     for (int j = jb; j < jmax; ++j) {
                         const double *pj = &Pall[(size_t)j * ncol];
-                        double t = 0;
-                        for (int k = kb; k < ke; ++k) t += pi[k] * pj[k];
-                        T[(size_t)i * nt + j] -= t;
+                        T[(size_t)i * nt + j] -= dot8(pi + kb, pj + kb, ke - kb);
                     }
                 }
             }
