@@ -138,6 +138,37 @@ typedef struct {
                                   FP32-relaxation run); 0 if none */
 } vsr_solve_info;
 
+/* ---- Primal linear elasticity with the SDC relaxation (Sec. 3.1) -------------------------
+ * a(v, u) = int 2 mu eps(v) : eps(u) + lambda div v div u, Q_p in each displacement
+ * component, homogeneous Dirichlet conditions on the whole boundary, on a tensor grid of
+ * axis-aligned boxes.  A displacement vector (device, FP64) holds 3 n values, component
+ * after component, each in the scalar layout above (n = vsr_num_dofs of the same mesh).  The
+ * preconditioner is the hybrid V(1,1) of Sec. 2.5 with the SDC relaxation (block-Jacobi over
+ * the components; component j's block solved by the vertex-star FDM patches with the exact
+ * separable scalings of A_jj on boxes) and Q1 in every component as the coarse space (exact
+ * dense solve, at most 12,000 coarse unknowns). */
+typedef struct vsr_elasticity vsr_elasticity;
+
+/* opt: relax_fp32 (the component relaxations in FP32), lanczos_steps, seed, omega,
+ * max_iterations, stream and deterministic are used; NULL = defaults.  Returns VSR_EINVAL for a
+ * mesh that is not a tensor grid of boxes, mu <= 0 or lambda < 0. */
+vsr_status vsr_elasticity_setup(const vsr_mesh *mesh, int32_t p, double mu, double lambda, const vsr_options *opt,
+                                vsr_elasticity **out);
+int64_t vsr_elasticity_num_dofs(const vsr_elasticity *el);
+/* b = [b_1; b_2; b_3] from the body force f_dev: 3 blocks of ncell q^3 values (the samples of
+ * vsr_load_vector), one per component. */
+vsr_status vsr_elasticity_load_vector(vsr_elasticity *el, const double *f_dev, double *b_dev);
+vsr_status vsr_elasticity_apply_operator(vsr_elasticity *el, const double *x_dev, double *y_dev);
+/* mode 0: the hybrid V(1,1) preconditioner; 1: the SDC relaxation alone (undamped); 2: the
+ * coarse correction. */
+vsr_status vsr_elasticity_apply_relaxation(vsr_elasticity *el, const double *r_dev, double *z_dev, int32_t mode);
+vsr_status vsr_elasticity_damping(const vsr_elasticity *el, double *omega, double *lambda_min, double *lambda_max);
+/* PCG (Sec. 2.8) from x = 0 until ||r||_2 <= rtol ||b||_2 (host-driven; info as for
+ * vsr_pcg_solve, without stagnation handling). */
+vsr_status vsr_elasticity_pcg_solve(vsr_elasticity *el, const double *b_dev, double *x_dev, double rtol,
+                                    vsr_solve_info *info);
+void vsr_elasticity_destroy(vsr_elasticity *el);
+
 /* Fill *opt with the defaults listed above (all zero except the library's defaults). */
 void vsr_default_options(vsr_options *opt);
 

@@ -20,7 +20,7 @@ COMMON = [
 ]
 SOURCES = [("kernels.hip", ["-x", "hip"]), ("transfer.hip", ["-x", "hip"]), ("patch_f32.hip", ["-x", "hip"]),
            ("patch_f64.hip", ["-x", "hip"]),
-           ("surrogate.hip", ["-x", "hip"]), ("noalloc.hip", ["-x", "hip"]), ("mg.hip", ["-x", "hip"]), ("op_mfma.hip", ["-x", "hip"]), ("setup.cpp", []), ("capi.cpp", []),
+           ("surrogate.hip", ["-x", "hip"]), ("noalloc.hip", ["-x", "hip"]), ("mg.hip", ["-x", "hip"]), ("op_mfma.hip", ["-x", "hip"]), ("elastic.hip", ["-x", "hip"]), ("setup.cpp", []), ("capi.cpp", []),
            ("surrogate_capi.cpp", [])]
 
 

@@ -957,6 +957,124 @@ void vsr_batch::solve(const double *const *b_dev, double *const *x_dev, double r
     }
 }
 
+// ---- primal linear elasticity with the SDC relaxation (Sec. 3.1) ----------------------------
+// The SDC preconditioner is block-Jacobi over the displacement components; on box cells each
+// diagonal block A_jj is the scalar separable operator with per-axis coefficients
+// (mu + (mu + lam) [a = j]) times the Poisson scalings, so component j's relaxation is the
+// scalar vertex-star FDM relaxation of a scalar problem set up with those scalings.
+struct vsr_elasticity {
+    vsr_problem *comp[3] = {nullptr, nullptr, nullptr};   // per component: its SDC relaxation
+    Dims d{};
+    int64_t n = 0;       // free nodes per component (the vector has 3 n entries)
+    int64_t ncell = 0;
+    int nc = 0;          // interior vertices per component (coarse space)
+    double mu = 0, lam = 0;
+    double omega = 1, lmin = 0, lmax = 0, setup_seconds = 0;
+    hipStream_t stream = nullptr;
+    std::vector<void *> allocs;
+    double *M1 = nullptr, *coef = nullptr, *E = nullptr, *A0inv = nullptr, *c0 = nullptr, *c1 = nullptr;
+    double *vr = nullptr, *vz = nullptr, *vp = nullptr, *vq = nullptr, *vt = nullptr, *vu = nullptr;
+    Exec ex() const { return Exec{stream, nullptr, Tuning{}}; }
+    template <typename T>
+    T *dalloc(size_t count) {
+        void *p = nullptr;
+        size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+        if (hipMalloc(&p, bytes) != hipSuccess) throw Error(VSR_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+        allocs.push_back(p);
+        return static_cast<T *>(p);
+    }
+    ~vsr_elasticity() {
+        for (vsr_problem *c : comp) destroy_problem(c);
+        for (void *p : allocs) (void)hipFree(p);
+    }
+};
+
+namespace {
+
+// y = A x for the 3-component vector (x, y: 3 n, component after component)
+void el_op(vsr_elasticity *L, const double *x, double *y) {
+    launch_op_elastic_box(L->d, L->M1, L->coef, L->mu, L->lam, x, L->E, L->ex());
+    const int64_t slot = L->ncell * (int64_t)(L->d.p + 1) * (L->d.p + 1) * (L->d.p + 1);
+    for (int c = 0; c < 3; ++c) launch_gather<double>(L->d, 1, L->E + c * slot, nullptr, y + c * L->n, L->ex());
+}
+
+double el_dot(vsr_elasticity *L, const double *x, const double *y) {
+    vsr_problem *P = L->comp[0];
+    launch_dot(3 * L->n, x, y, P->partials, P->scal, 0, nullptr, L->ex());
+    return read_scalar(P, SC_TMP);
+}
+
+// z = S r: component j's scalar FDM vertex-star relaxation (undamped)
+void el_relax(vsr_elasticity *L, const double *r, double *z) {
+    for (int c = 0; c < 3; ++c) precond(L->comp[c], r + c * L->n, z + c * L->n, 1);
+}
+
+// z = P A0^{-1} P^T r with Q1 in every component
+void el_coarse(vsr_elasticity *L, const double *r, double *z) {
+    if (L->nc == 0) {
+        launch_fill<double>(3 * L->n, z, 0.0, L->ex());
+        return;
+    }
+    vsr_problem *P = L->comp[0];
+    const int Ld[3] = {L->d.Lx, L->d.Ly, L->d.Lz}, NC[3] = {L->d.nx, L->d.ny, L->d.nz};
+    for (int c = 0; c < 3; ++c)
+        launch_transfer<double, double>(XFER_COARSE_RESTRICT, L->d.p, NC, Ld, P->cdim, P->xm64[XFER_COARSE_RESTRICT],
+                                        r + c * L->n, L->c0 + c * L->nc, 1.0, 0.0, L->ex());
+    launch_dense_gemv<double>(3 * L->nc, L->A0inv, L->c0, L->c1, 1.0, 0.0, L->ex());
+    for (int c = 0; c < 3; ++c)
+        launch_transfer<double, double>(XFER_COARSE_PROLONG, L->d.p, NC, P->cdim, Ld, P->xm64[XFER_COARSE_PROLONG],
+                                        L->c1 + c * L->nc, z + c * L->n, 1.0, 0.0, L->ex());
+}
+
+// mode 0: the hybrid V(1,1) z1 = w S r, z2 = z1 + C (r - A z1), z = z2 + w S (r - A z2);
+// mode 1: S r; mode 2: C r.  r and z must not alias the work vectors vt, vu.
+void el_precond(vsr_elasticity *L, const double *r, double *z, int mode) {
+    const int64_t N = 3 * L->n;
+    if (mode == 1) return el_relax(L, r, z);
+    if (mode == 2) return el_coarse(L, r, z);
+    double *t = L->vt, *u = L->vu;
+    el_relax(L, r, z);                                                        // z = S r
+    launch_axpby_to_double<double>(N, 0.0, z, L->omega, z, L->ex());          // z1 = w S r
+    el_op(L, z, t);
+    launch_axpby_to_double<double>(N, 1.0, r, -1.0, t, L->ex());              // t = r - A z1
+    el_coarse(L, t, u);
+    launch_axpby_to_double<double>(N, 1.0, u, 1.0, z, L->ex());               // z2
+    el_op(L, z, t);
+    launch_axpby_to_double<double>(N, 1.0, r, -1.0, t, L->ex());              // t = r - A z2
+    el_relax(L, t, u);
+    launch_axpby_to_double<double>(N, L->omega, u, 1.0, z, L->ex());          // z = z2 + w S t
+}
+
+// CG-Lanczos on S A from the splitmix64 start vector (the scalar estimate's recipe, 3 n entries)
+void el_damping(vsr_elasticity *L, int steps, uint64_t seed) {
+    const int64_t N = 3 * L->n;
+    std::vector<double> h(N);
+    for (int64_t i = 0; i < N; ++i) h[i] = (double)(splitmix64_at(seed, (uint64_t)i) >> 11) * 0x1.0p-53 * 2.0 - 1.0;
+    VSR_HIP(hipMemcpy(L->vr, h.data(), N * sizeof(double), hipMemcpyHostToDevice));
+    el_relax(L, L->vr, L->vz);
+    double rz = el_dot(L, L->vr, L->vz);
+    const double rz0 = rz;
+    launch_axpby_to_double<double>(N, 1.0, L->vz, 0.0, L->vp, L->ex());
+    std::vector<double> alphas, betas;
+    for (int j = 0; j < steps; ++j) {
+        el_op(L, L->vp, L->vq);
+        const double alpha = rz / el_dot(L, L->vp, L->vq);
+        if (!(alpha > 0) || !std::isfinite(alpha)) throw Error(VSR_ENOCONV, "Lanczos breakdown");
+        launch_axpby_to_double<double>(N, -alpha, L->vq, 1.0, L->vr, L->ex());
+        el_relax(L, L->vr, L->vz);
+        const double rzn = el_dot(L, L->vr, L->vz);
+        alphas.push_back(alpha);
+        betas.push_back(rzn / rz);
+        if (rzn <= 1e-28 * rz0) break;
+        launch_axpby_to_double<double>(N, 1.0, L->vz, betas.back(), L->vp, L->ex());
+        rz = rzn;
+    }
+    lanczos_extremes(alphas, betas, L->lmin, L->lmax);
+    L->omega = 2.0 / ((1 + 0.25) * L->lmax + (1 - 0.25) * L->lmin);
+}
+
+}  // namespace
+
 extern "C" {
 
 void vsr_default_options(vsr_options *opt) {
@@ -1403,6 +1521,234 @@ vsr_status vsr_pcg_solve_batch(vsr_batch *B, const double *const *b_dev, double 
 }
 
 void vsr_destroy_batch(vsr_batch *B) { delete B; }
+
+vsr_status vsr_elasticity_setup(const vsr_mesh *mesh, int32_t p, double mu, double lambda, const vsr_options *opt,
+                                vsr_elasticity **out) {
+    return guarded([&] {
+        if (!mesh || !out || !mesh->vertices) throw Error(VSR_EINVAL, "NULL argument");
+        *out = nullptr;
+        if (!(mu > 0) || !(lambda >= 0) || !std::isfinite(mu) || !std::isfinite(lambda))
+            throw Error(VSR_EINVAL, "need mu > 0 and lambda >= 0");
+        if (p < 2 || p > 15) throw Error(VSR_EINVAL, "p must be in [2, 15]");
+        const int nx = mesh->nx, ny = mesh->ny, nz = mesh->nz;
+        if (nx < 2 || ny < 2 || nz < 2) throw Error(VSR_EINVAL, "every mesh axis needs at least 2 cells");
+        const double t0 = now_s();
+        // axis-aligned boxes: vertex (k, j, i) = (X[i], Y[j], Z[k])
+        const double *V = mesh->vertices;
+        auto vert = [&](int k, int j, int i, int a) { return V[3 * (((int64_t)k * (ny + 1) + j) * (nx + 1) + i) + a]; };
+        std::vector<double> X(nx + 1), Y(ny + 1), Z(nz + 1);
+        for (int i = 0; i <= nx; ++i) X[i] = vert(0, 0, i, 0);
+        for (int j = 0; j <= ny; ++j) Y[j] = vert(0, j, 0, 1);
+        for (int k = 0; k <= nz; ++k) Z[k] = vert(k, 0, 0, 2);
+        double scale = 0;
+        for (double v : X) scale = std::max(scale, std::fabs(v));
+        for (double v : Y) scale = std::max(scale, std::fabs(v));
+        for (double v : Z) scale = std::max(scale, std::fabs(v));
+        const double tol = 1e-12 * std::max(scale, 1e-300);
+        for (int k = 0; k <= nz; ++k)
+            for (int j = 0; j <= ny; ++j)
+                for (int i = 0; i <= nx; ++i)
+                    if (!(std::fabs(vert(k, j, i, 0) - X[i]) <= tol && std::fabs(vert(k, j, i, 1) - Y[j]) <= tol &&
+                          std::fabs(vert(k, j, i, 2) - Z[k]) <= tol))
+                        throw Error(VSR_EINVAL, "elasticity needs a mesh of axis-aligned boxes (a tensor grid)");
+        for (int i = 0; i < nx; ++i) if (!(X[i + 1] > X[i])) throw Error(VSR_EMESH, "cell with non-positive length");
+        for (int j = 0; j < ny; ++j) if (!(Y[j + 1] > Y[j])) throw Error(VSR_EMESH, "cell with non-positive length");
+        for (int k = 0; k < nz; ++k) if (!(Z[k + 1] > Z[k])) throw Error(VSR_EMESH, "cell with non-positive length");
+        auto L = std::make_unique<vsr_elasticity>();
+        vsr_options o;
+        if (opt) o = *opt;
+        else vsr_default_options(&o);
+        L->mu = mu;
+        L->lam = lambda;
+        L->stream = (hipStream_t)o.stream;
+        const int64_t ncell = (int64_t)nx * ny * nz;
+        // SDC scalings of each component (exact on boxes): (mu + (mu + lam) [a = j]) |J| (2 / h_a)^2
+        std::vector<double> coef((size_t)ncell * 12);
+        std::vector<std::vector<double>> mus(3, std::vector<double>((size_t)ncell * 3));
+        for (int k = 0; k < nz; ++k)
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i < nx; ++i) {
+                    const int64_t e = ((int64_t)k * ny + j) * nx + i;
+                    const double h[3] = {X[i + 1] - X[i], Y[j + 1] - Y[j], Z[k + 1] - Z[k]};
+                    const double vol = h[0] * h[1] * h[2] / 8.0;
+                    for (int c = 0; c < 3; ++c)
+                        for (int a = 0; a < 3; ++a) {
+                            const double kk = (mu + (a == c ? mu + lambda : 0.0)) * vol * (2 / h[a]) * (2 / h[a]);
+                            coef[e * 12 + 3 * c + a] = kk;
+                            mus[c][e * 3 + a] = kk;
+                        }
+                    coef[e * 12 + 9] = vol * (2 / h[0]) * (2 / h[1]);
+                    coef[e * 12 + 10] = vol * (2 / h[0]) * (2 / h[2]);
+                    coef[e * 12 + 11] = vol * (2 / h[1]) * (2 / h[2]);
+                }
+        // the component problems: their patches and FDM transfers give the SDC relaxation (no
+        // damping estimate of their own; the multigrid coarse setup is the cheap one they skip using)
+        vsr_options oc = o;
+        oc.omega = 1.0;
+        oc.coarse_solver = 2;
+        oc.autotune = 0;
+        for (int c = 0; c < 3; ++c) {
+            vsr_coefficients cf{nullptr, mus[c].data()};
+            vsr_status st = vsr_setup(mesh, p, &cf, &oc, &L->comp[c]);
+            if (st != VSR_OK) throw Error(st, g_last_error_text);
+        }
+        vsr_problem *P0 = L->comp[0];
+        L->d = P0->d;
+        L->n = P0->n;
+        L->ncell = ncell;
+        const int n1 = p + 1;
+        // 1-D matrices A, B, C (C[a][b] = sum_q w_q l_a'(x_q) l_b(x_q)) and C^T
+        const OneD &od = P0->od;
+        std::vector<double> M1(4 * (size_t)n1 * n1, 0.0);
+        for (int a = 0; a < n1; ++a)
+            for (int b = 0; b < n1; ++b) {
+                M1[a * n1 + b] = od.A[a * n1 + b];
+                M1[n1 * n1 + a * n1 + b] = od.B[a * n1 + b];
+                double cab = 0;
+                for (int q = 0; q < od.q; ++q) cab += od.wq[q] * od.Dq[q * n1 + a] * od.Iq[q * n1 + b];
+                M1[2 * n1 * n1 + a * n1 + b] = cab;
+                M1[3 * n1 * n1 + b * n1 + a] = cab;
+            }
+        L->M1 = L->dalloc<double>(M1.size());
+        VSR_HIP(hipMemcpy(L->M1, M1.data(), M1.size() * sizeof(double), hipMemcpyHostToDevice));
+        L->coef = L->dalloc<double>(coef.size());
+        VSR_HIP(hipMemcpy(L->coef, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice));
+        L->E = L->dalloc<double>(3 * (size_t)ncell * n1 * n1 * n1);
+        const int64_t N = 3 * L->n;
+        L->vr = L->dalloc<double>(N);
+        L->vz = L->dalloc<double>(N);
+        L->vp = L->dalloc<double>(N);
+        L->vq = L->dalloc<double>(N);
+        L->vt = L->dalloc<double>(N);
+        L->vu = L->dalloc<double>(N);
+        // vector Q1 coarse space, exact solve
+        L->nc = (nx - 1) * (ny - 1) * (nz - 1);
+        if (L->nc > 0) {
+            if (3LL * L->nc > 12000) throw Error(VSR_EINVAL, "elasticity coarse space limited to 12,000 unknowns");
+            std::vector<double> A0 = elasticity_q1_matrix(X, Y, Z, od, mu, lambda);
+            std::vector<double> A0i = spd_inverse(3 * L->nc, A0);
+            L->A0inv = L->dalloc<double>(A0i.size());
+            VSR_HIP(hipMemcpy(L->A0inv, A0i.data(), A0i.size() * sizeof(double), hipMemcpyHostToDevice));
+            L->c0 = L->dalloc<double>(3 * L->nc);
+            L->c1 = L->dalloc<double>(3 * L->nc);
+        }
+        if (o.omega > 0) L->omega = o.omega;
+        else el_damping(L.get(), o.lanczos_steps > 0 ? o.lanczos_steps : 20, o.seed);
+        VSR_HIP(hipStreamSynchronize(L->stream));
+        L->setup_seconds = now_s() - t0;
+        *out = L.release();
+    });
+}
+
+int64_t vsr_elasticity_num_dofs(const vsr_elasticity *L) { return L ? 3 * L->n : -1; }
+
+vsr_status vsr_elasticity_load_vector(vsr_elasticity *L, const double *f, double *b) {
+    return guarded([&] {
+        if (!L || !f || !b) throw Error(VSR_EINVAL, "NULL argument");
+        const int q = L->comp[0]->d.q;
+        const int64_t per = L->ncell * (int64_t)q * q * q;
+        for (int c = 0; c < 3; ++c) {
+            vsr_status st = vsr_load_vector(L->comp[c], f + c * per, b + c * L->n);
+            if (st != VSR_OK) throw Error(st, g_last_error_text);
+        }
+    });
+}
+
+vsr_status vsr_elasticity_apply_operator(vsr_elasticity *L, const double *x, double *y) {
+    return guarded([&] {
+        if (!L || !x || !y) throw Error(VSR_EINVAL, "NULL argument");
+        el_op(L, x, y);
+        VSR_HIP(hipGetLastError());
+    });
+}
+
+vsr_status vsr_elasticity_apply_relaxation(vsr_elasticity *L, const double *r, double *z, int32_t mode) {
+    return guarded([&] {
+        if (!L || !r || !z) throw Error(VSR_EINVAL, "NULL argument");
+        if (mode < 0 || mode > 2) throw Error(VSR_EINVAL, "mode must be 0, 1 or 2");
+        el_precond(L, r, z, mode);
+        VSR_HIP(hipGetLastError());
+    });
+}
+
+vsr_status vsr_elasticity_damping(const vsr_elasticity *L, double *omega, double *lmin, double *lmax) {
+    return guarded([&] {
+        if (!L) throw Error(VSR_EINVAL, "NULL argument");
+        if (omega) *omega = L->omega;
+        if (lmin) *lmin = L->lmin;
+        if (lmax) *lmax = L->lmax;
+    });
+}
+
+vsr_status vsr_elasticity_pcg_solve(vsr_elasticity *L, const double *b, double *x, double rtol, vsr_solve_info *info) {
+    vsr_solve_info loc{};
+    vsr_status st = guarded([&] {
+        if (!L || !b || !x) throw Error(VSR_EINVAL, "NULL argument");
+        if (!(rtol > 0)) throw Error(VSR_EINVAL, "rtol must be positive");
+        const int64_t N = 3 * L->n;
+        const int maxit = L->comp[0]->opt.max_iterations > 0 ? L->comp[0]->opt.max_iterations : 1000;
+        VSR_HIP(hipStreamSynchronize(L->stream));
+        const double t0 = now_s();
+        launch_fill<double>(N, x, 0.0, L->ex());
+        launch_axpby_to_double<double>(N, 1.0, b, 0.0, L->vr, L->ex());
+        const double bb = el_dot(L, b, b);
+        if (!std::isfinite(bb)) throw Error(VSR_EINVAL, "non-finite right-hand side");
+        double rr = bb, rz = 0;
+        int it = 0;
+        bool conv = bb == 0.0;
+        std::vector<double> alphas, betas;
+        if (!conv) {
+            el_precond(L, L->vr, L->vz, 0);
+            launch_axpby_to_double<double>(N, 1.0, L->vz, 0.0, L->vp, L->ex());
+            rz = el_dot(L, L->vr, L->vz);
+            while (it < maxit) {
+                el_op(L, L->vp, L->vq);
+                const double alpha = rz / el_dot(L, L->vp, L->vq);
+                alphas.push_back(alpha);
+                launch_axpby_to_double<double>(N, alpha, L->vp, 1.0, x, L->ex());
+                launch_axpby_to_double<double>(N, -alpha, L->vq, 1.0, L->vr, L->ex());
+                ++it;
+                rr = el_dot(L, L->vr, L->vr);
+                if (!std::isfinite(rr)) break;
+                if (rr <= rtol * rtol * bb) {
+                    conv = true;
+                    break;
+                }
+                el_precond(L, L->vr, L->vz, 0);
+                const double rzn = el_dot(L, L->vr, L->vz);
+                betas.push_back(rzn / rz);
+                launch_axpby_to_double<double>(N, 1.0, L->vz, betas.back(), L->vp, L->ex());
+                rz = rzn;
+            }
+        }
+        VSR_HIP(hipStreamSynchronize(L->stream));
+        const double t1 = now_s();
+        el_op(L, x, L->vt);
+        launch_axpby_to_double<double>(N, 1.0, b, -1.0, L->vt, L->ex());
+        const double tr = std::sqrt(std::max(0.0, el_dot(L, L->vt, L->vt)));
+        const double bn = std::sqrt(bb);
+        loc.iterations = it;
+        loc.converged = conv ? 1 : 0;
+        loc.rel_residual = bn > 0 ? std::sqrt(rr) / bn : 0.0;
+        loc.true_rel_residual = bn > 0 ? tr / bn : 0.0;
+        loc.omega = L->omega;
+        loc.lambda_min = L->lmin;
+        loc.lambda_max = L->lmax;
+        loc.setup_seconds = L->setup_seconds;
+        loc.solve_seconds = t1 - t0;
+        bool ok = !alphas.empty();
+        for (double a : alphas) ok = ok && a > 0 && std::isfinite(a);
+        if (ok) {
+            lanczos_extremes(alphas, betas, loc.ritz_min, loc.ritz_max);
+            if (loc.ritz_min > 0) loc.kappa_estimate = loc.ritz_max / loc.ritz_min;
+        }
+        if (!conv) throw Error(VSR_ENOCONV, "PCG did not converge in " + std::to_string(it) + " iterations");
+    });
+    if (info && L) *info = loc;
+    return st;
+}
+
+void vsr_elasticity_destroy(vsr_elasticity *L) { delete L; }
 
 const char *vsr_last_error(void) { return vsr::g_last_error_text.c_str(); }
 

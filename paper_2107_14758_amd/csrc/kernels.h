@@ -124,6 +124,14 @@ void launch_patch_all(const Dims &d, const PatchArgs &a, int n_int, const int *v
 // kFusedScatterMaxP; up to it the prolongation reads the star boxes itself).
 template <typename T>
 void launch_patch_assemble(const Dims &d, const T *U, T *zF, const Exec &e);
+// Primal linear elasticity on axis-aligned cells (Sec. 3.1), FP64: the three components'
+// cell results of y = A x into E (three element vectors of ncell (p+1)^3, one per output
+// component; launch_gather sums each).  M1: the 1-D matrices A, B, C, C^T ((p+1)^2 each,
+// row = test index; C[a][b] = int phi_a' phi_b); coef: 12 per cell (k[c][a] at 3c + a, then
+// s_xy, s_xz, s_yz); x: 3 n values, component after component.
+void launch_op_elastic_box(const Dims &d, const double *M1, const double *coef, double mu, double lam, const double *x,
+                           double *E, const Exec &e);
+
 constexpr int kFusedScatterMaxP = 7;
 // Length of U for launch_patch_all.
 inline int64_t patch_solution_entries(const Dims &d) {

@@ -1333,4 +1333,80 @@ void tridiag_extremes(const std::vector<double> &d, const std::vector<double> &e
     lmax = kth(n - 1);
 }
 
+
+// ------------------------------------------------------------------ linear elasticity (Sec. 3.1)
+std::vector<double> spd_inverse(int n, const std::vector<double> &A) {
+    std::vector<double> L(A);
+    if (!cholesky_lower(n, L.data(), n)) throw Error(VSR_ENOTSPD, "non-positive pivot in a dense Cholesky factor");
+    std::vector<double> Si;
+    inverse_from_cholesky(n, L.data(), n, Si);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < i; ++j) Si[(size_t)j * n + i] = Si[(size_t)i * n + j];
+    return Si;
+}
+
+std::vector<double> elasticity_q1_matrix(const std::vector<double> &X, const std::vector<double> &Y,
+                                         const std::vector<double> &Z, const OneD &od, double mu, double lam) {
+    const int nx = (int)X.size() - 1, ny = (int)Y.size() - 1, nz = (int)Z.size() - 1;
+    const int ux = nx - 1, uy = ny - 1, uz = nz - 1, nc = ux * uy * uz, N = 3 * nc;
+    std::vector<double> A0((size_t)N * N, 0.0);
+    if (nc == 0) return A0;
+    // 1-D Q1 matrices on [-1, 1] with the operator's q-point rule: K = int N' N', M = int N N,
+    // G[t][u] = int N_t' N_u (test function differentiated)
+    double K1[2][2] = {}, M1[2][2] = {}, G1[2][2] = {};
+    for (size_t k = 0; k < od.xq.size(); ++k) {
+        const double x = od.xq[k], w = od.wq[k];
+        const double Nv[2] = {0.5 * (1 - x), 0.5 * (1 + x)}, dN[2] = {-0.5, 0.5};
+        for (int t = 0; t < 2; ++t)
+            for (int u = 0; u < 2; ++u) {
+                K1[t][u] += w * dN[t] * dN[u];
+                M1[t][u] += w * Nv[t] * Nv[u];
+                G1[t][u] += w * dN[t] * Nv[u];
+            }
+    }
+    const double *coords[3] = {X.data(), Y.data(), Z.data()};
+    for (int ez = 0; ez < nz; ++ez)
+        for (int ey = 0; ey < ny; ++ey)
+            for (int ex = 0; ex < nx; ++ex) {
+                const int e3[3] = {ex, ey, ez};
+                double h[3];
+                for (int a = 0; a < 3; ++a) h[a] = coords[a][e3[a] + 1] - coords[a][e3[a]];
+                const double vol = h[0] * h[1] * h[2] / 8.0;
+                // I_ij(a, b) = int d_i phi_a d_j phi_b: per axis K (i = j = axis), G (test
+                // derivative), G^T (trial derivative) or M
+                auto Iij = [&](int i, int j, const int ta[3], const int tb[3]) {
+                    double v = vol;
+                    for (int ax = 0; ax < 3; ++ax) {
+                        const int t = ta[ax], u = tb[ax];
+                        if (ax == i && ax == j) v *= K1[t][u] * (2 / h[ax]) * (2 / h[ax]);
+                        else if (ax == i) v *= G1[t][u] * (2 / h[ax]);
+                        else if (ax == j) v *= G1[u][t] * (2 / h[ax]);
+                        else v *= M1[t][u];
+                    }
+                    return v;
+                };
+                for (int a = 0; a < 8; ++a)
+                    for (int b = 0; b < 8; ++b) {
+                        const int ta[3] = {a & 1, (a >> 1) & 1, a >> 2}, tb[3] = {b & 1, (b >> 1) & 1, b >> 2};
+                        const int va[3] = {ex + ta[0], ey + ta[1], ez + ta[2]}, vb[3] = {ex + tb[0], ey + tb[1], ez + tb[2]};
+                        bool inner = true;
+                        for (int ax = 0; ax < 3; ++ax) {
+                            const int nn = ax == 0 ? nx : (ax == 1 ? ny : nz);
+                            inner = inner && va[ax] >= 1 && va[ax] <= nn - 1 && vb[ax] >= 1 && vb[ax] <= nn - 1;
+                        }
+                        if (!inner) continue;
+                        const int ia = ((va[2] - 1) * uy + (va[1] - 1)) * ux + (va[0] - 1);
+                        const int ib = ((vb[2] - 1) * uy + (vb[1] - 1)) * ux + (vb[0] - 1);
+                        const double lap = Iij(0, 0, ta, tb) + Iij(1, 1, ta, tb) + Iij(2, 2, ta, tb);
+                        for (int c = 0; c < 3; ++c)
+                            for (int e = 0; e < 3; ++e) {
+                                // mu (delta_ce grad.grad + d_e phi_a d_c phi_b) + lam d_c phi_a d_e phi_b
+                                double v = mu * Iij(e, c, ta, tb) + lam * Iij(c, e, ta, tb);
+                                if (c == e) v += mu * lap;
+                                A0[(size_t)(c * nc + ia) * N + e * nc + ib] += v;
+                            }
+                    }
+            }
+    return A0;
+}
 }  // namespace vsr

@@ -124,4 +124,13 @@ size_t static_workspace_bytes();
 // Symmetric tridiagonal extreme eigenvalues by Sturm bisection.
 void tridiag_extremes(const std::vector<double> &d, const std::vector<double> &e, double &lmin, double &lmax);
 
+// Linear elasticity (Sec. 3.1): the inverse of a dense SPD matrix (row-major, symmetric
+// output; throws on a non-positive pivot), and the Q1 Galerkin matrix of a(v, u) = int 2 mu
+// eps(v):eps(u) + lam div v div u on the tensor grid of box cells with vertex coordinates X, Y,
+// Z (one per axis), over the interior vertices, rows [component][vertex] (x fastest), the
+// 1-D integrals taken with od's quadrature.
+std::vector<double> spd_inverse(int n, const std::vector<double> &A);
+std::vector<double> elasticity_q1_matrix(const std::vector<double> &X, const std::vector<double> &Y,
+                                         const std::vector<double> &Z, const OneD &od, double mu, double lam);
+
 }  // namespace vsr

@@ -103,9 +103,23 @@ def lib():
     L.vsr_destroy_batch.restype = None
     L.vsr_last_error.argtypes = []
     L.vsr_last_error.restype = ctypes.c_char_p
+    L.vsr_elasticity_setup.argtypes = [ctypes.POINTER(Mesh), ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                       ctypes.POINTER(Options), ctypes.POINTER(P)]
+    L.vsr_elasticity_num_dofs.argtypes = [P]
+    L.vsr_elasticity_num_dofs.restype = ctypes.c_int64
+    L.vsr_elasticity_load_vector.argtypes = [P, dp, dp]
+    L.vsr_elasticity_apply_operator.argtypes = [P, dp, dp]
+    L.vsr_elasticity_apply_relaxation.argtypes = [P, dp, dp, ctypes.c_int32]
+    L.vsr_elasticity_damping.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_double)]
+    L.vsr_elasticity_pcg_solve.argtypes = [P, dp, dp, ctypes.c_double, ctypes.POINTER(SolveInfo)]
+    L.vsr_elasticity_destroy.argtypes = [P]
+    L.vsr_elasticity_destroy.restype = None
     for name in ("vsr_setup", "vsr_load_vector", "vsr_apply_operator", "vsr_apply_operator_noalloc", "vsr_apply_relaxation", "vsr_pcg_solve",
                  "vsr_get_damping", "vsr_set_profiling", "vsr_kernel_stats", "vsr_factor_info", "vsr_get_tuning", "vsr_set_tuning",
-                 "vsr_setup_batch", "vsr_batch_create", "vsr_pcg_solve_batch"):
+                 "vsr_setup_batch", "vsr_batch_create", "vsr_pcg_solve_batch", "vsr_elasticity_setup",
+                 "vsr_elasticity_load_vector", "vsr_elasticity_apply_operator", "vsr_elasticity_apply_relaxation",
+                 "vsr_elasticity_damping", "vsr_elasticity_pcg_solve"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -480,3 +494,58 @@ def surrogate_scalings(corners, p, params, kappa=None, bf16=True):
                                     int(bool(bf16)),
                                     _dp(mu), used.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
     return mu, used
+
+
+class Elasticity:
+    """Primal linear elasticity (Sec. 3.1) with the SDC relaxation, resident on the GPU: Lame
+    parameters mu, lam on a tensor grid of boxes; vectors hold 3 n values, component after
+    component."""
+
+    def __init__(self, vertices, p, mu, lam, **options):
+        L = lib()
+        self._in = _Inputs(vertices, None, None)
+        opt = make_options(**options)
+        h = ctypes.c_void_p()
+        _check(L.vsr_elasticity_setup(ctypes.byref(self._in.mesh), int(p), float(mu), float(lam), ctypes.byref(opt),
+                                      ctypes.byref(h)))
+        self._h = h
+        self.p = p
+        self.n = int(L.vsr_elasticity_num_dofs(h))
+        self.q = (3 * (p + 1) + 1) // 2
+        nz, ny, nx = self._in.shape[0], self._in.shape[1], self._in.shape[2]
+        self.ncell = nx * ny * nz
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().vsr_elasticity_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def load_vector(self, f, b):
+        _check(lib().vsr_elasticity_load_vector(self._h, _ptr(f, 3 * self.ncell * self.q ** 3), _ptr(b, self.n)))
+
+    def apply_operator(self, x, y):
+        _check(lib().vsr_elasticity_apply_operator(self._h, _ptr(x, self.n), _ptr(y, self.n)))
+
+    def apply_relaxation(self, r, z, mode=0):
+        _check(lib().vsr_elasticity_apply_relaxation(self._h, _ptr(r, self.n), _ptr(z, self.n), int(mode)))
+
+    def damping(self):
+        w, a, b = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _check(lib().vsr_elasticity_damping(self._h, ctypes.byref(w), ctypes.byref(a), ctypes.byref(b)))
+        return w.value, a.value, b.value
+
+    def pcg_solve(self, b, x, rtol=1e-8, raise_on_noconv=True):
+        info = SolveInfo()
+        st = lib().vsr_elasticity_pcg_solve(self._h, _ptr(b, self.n), _ptr(x, self.n), float(rtol), ctypes.byref(info))
+        if st != VSR_OK and (raise_on_noconv or st != VSR_ENOCONV):
+            _check(st)
+        out = info.as_dict()
+        out["status"] = st
+        return out
+
