@@ -223,7 +223,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--workload", default=WORKLOAD, choices=sorted(list(WORKLOADS) + ["batch64"]))
+    ap.add_argument("--no-table", action="store_true", help="elasticity: skip the iteration table over p and lambda")
+    ap.add_argument("--workload", default=WORKLOAD, choices=sorted(list(WORKLOADS) + ["batch64", "elasticity_8x8x8"]))
     ap.add_argument("--autotune", action="store_true", help="single-problem workloads: autotune launch shapes")
     ap.add_argument("--share-factors", action="store_true",
                     help="batch64: stars with equal scalings share one stored factor")
@@ -249,6 +250,8 @@ def main():
     vsr.lib()
     if args.workload == "batch64":
         return main_batch(args, torch, inputs, vsr)
+    if args.workload == "elasticity_8x8x8":
+        return main_elasticity(args, torch, inputs, vsr)
     wname = args.workload
     w = inputs.workload(wname, seed=0)
     p = int(w["p"])
@@ -339,6 +342,124 @@ def patch_roofline(stats, p, traffic):
     return {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": achieved / PEAK_HBM_GBS, "traffic": traffic, "kernel": f"k_patch_all<float,{p}>",
             "avg_launch_ms": avg_ms, "launches": launches, "algorithmic_bytes_per_launch": bytes_per_launch}
+
+
+def elasticity_problem(n, p, seed=0):
+    """Primal elasticity workload: the unit cube in n^3 boxes, a seeded U[-1, 1] body force
+    sampled at every quadrature point of every cell, per component."""
+    rng = np.random.default_rng(seed)
+    q = inputs_mod().quadrature_points_per_dir(p)
+    f = np.stack([inputs_mod().rhs_samples(n ** 3, q ** 3, rng) for _ in range(3)])
+    return inputs_mod().cube_vertices(n, n, n), f
+
+
+def inputs_mod():
+    from paper_2107_14758_amd import inputs
+    return inputs
+
+
+def elasticity_solve_timed(vsr, torch, n, p, mu, lam, relax_fp32, steps, warmup):
+    V, f = elasticity_problem(n, p)
+    g = vsr.Elasticity(V, p, mu, lam, relax_fp32=relax_fp32, seed=0)
+    b = torch.zeros(g.n, dtype=torch.float64, device="cuda")
+    g.load_vector(torch.tensor(f, device="cuda"), b)
+    x = torch.zeros_like(b)
+    info = None
+    for _ in range(warmup):
+        info = g.pcg_solve(b, x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        info = g.pcg_solve(b, x)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / max(steps, 1)
+    return g, b, x, info, dt
+
+
+def main_elasticity(args, torch, inputs, vsr):
+    """Primal linear elasticity with the SDC relaxation (Sec. 3.1) on the paper's mesh (8^3
+    boxes of the unit cube), mu = 1: the headline rate at p = 7, lam = 1, the iteration table
+    over p and lam of Table tab:primal_elasticity, the operator kernel's rate, and the oracle on
+    a bounded sample."""
+    n, p, lam = 8, 7, 1.0
+    g, b, x, info, dt = elasticity_solve_timed(vsr, torch, n, p, 1.0, lam, True, args.steps, args.warmup)
+    log(f"[bench] elasticity 8^3 p=7 lam=1: {info['iterations']} iterations, {1e3 * dt:.2f} ms/solve, setup {info['setup_seconds']:.1f} s")
+    # operator: kernel + three gathers, timed over 20 applies
+    y = torch.zeros_like(b)
+    for _ in range(3):
+        g.apply_operator(x, y)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(20):
+        g.apply_operator(x, y)
+    e1.record()
+    torch.cuda.synchronize()
+    op_us = 1e3 * e0.elapsed_time(e1) / 20
+    n1 = p + 1
+    op_flops = n ** 3 * 21 * 3 * 2 * n1 ** 4          # 21 Kronecker terms, three 1-D passes each
+    out = {
+        "metric": "PCG DOF/s to 1e-8 rel. residual, SDC-relaxation elasticity", "value": g.n / dt, "unit": "DOF/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * dt, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64 (PCG, operator) + f32 (component relaxations, coarse)",
+        "data": "synthetic (seeded U[-1,1] body force at quadrature points)",
+        "config": {"workload": "elasticity_8x8x8_q7", "cells": [n, n, n], "p": p, "mu": 1.0, "lambda": lam, "dofs": g.n,
+                   "rtol": 1e-8, "preconditioner": "hybrid V(1,1), SDC vertex-star FDM relaxation, vector Q1 coarse",
+                   "boundary": "homogeneous Dirichlet on the whole boundary", "parallelism": "single GPU"},
+        "iterations": info["iterations"], "kappa_estimate": info["kappa_estimate"],
+        "true_rel_residual": info["true_rel_residual"], "setup_seconds": info["setup_seconds"],
+        "operator": {"kernel": "k_op_elastic_box<7> + 3 k_gather", "avg_us": op_us, "flops": op_flops,
+                     "achieved_tflops": op_flops / (op_us * 1e-6) / 1e12, "bound": "alu",
+                     "peak_tflops": 78.6, "frac": op_flops / (op_us * 1e-6) / 78.6e12},
+    }
+    g.close()
+    if not args.no_fp64:
+        g64, _, _, info64, dt64 = elasticity_solve_timed(vsr, torch, n, p, 1.0, lam, False, max(3, args.steps // 4), 1)
+        out["fp64_plain"] = {"value": g64.n / dt64, "ms_per_step": 1e3 * dt64, "iterations": info64["iterations"]}
+        g64.close()
+    table = {}
+    for pp in (() if args.no_table else (3, 7, 15)):
+        row = {}
+        for lm in (0.0, 1.0, 10.0, 100.0, 1000.0):
+            gg, _, _, ii, dtt = elasticity_solve_timed(vsr, torch, n, pp, 1.0, lm, True, 1, 0)
+            row[str(lm)] = {"iterations": ii["iterations"], "kappa_estimate": round(ii["kappa_estimate"], 3),
+                            "ms": round(1e3 * dtt, 2)}
+            log(f"[bench] p={pp} lam={lm}: {ii['iterations']} iterations, kappa {ii['kappa_estimate']:.2f}")
+            gg.close()
+        table[f"p{pp}"] = row
+    if table:
+        out["iterations_table"] = table
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = elasticity_cpu_baseline(vsr, torch)
+    print(json.dumps(out), flush=True)
+
+
+def elasticity_cpu_baseline(vsr, torch, n=4, p=7):
+    """The oracle's SDC PCG solve (setup excluded) on a 4^3-box sample at p = 7, lam = 1, and
+    the GPU solution's error against it."""
+    import threadpoolctl
+    from oracle.elasticity import Elasticity as OE, SDCSolver
+    from oracle.fdm1d import setup_1d
+    from oracle.operator import Discretization
+    V, f = elasticity_problem(n, p)
+    with threadpoolctl.threadpool_limits(1):
+        d = Discretization(V, p)
+        el = OE(d, 1.0, 1.0)
+        s = SDCSolver(el, setup_1d(p), seed=0)
+        bo = el.load_vector(f)
+        t0 = time.perf_counter()
+        xo, it, _ = s.pcg(bo)
+        dt = time.perf_counter() - t0
+    g = vsr.Elasticity(V, p, 1.0, 1.0, relax_fp32=True, seed=0)
+    b = torch.tensor(bo, device="cuda")
+    x = torch.zeros_like(b)
+    info = g.pcg_solve(b, x)
+    xg = x.cpu().numpy()
+    g.close()
+    return {"value": el.n / dt, "unit": "DOF/s", "cores": 1, "kind": "oracle", "threads": 1,
+            "sample": f"elasticity {n}^3 boxes, p={p}, lam=1: the oracle's PCG solve (setup excluded), "
+                      f"{el.n} DOFs, {it} iterations, {dt:.1f} s",
+            "gpu_fp32_err_vs_oracle": float(np.abs(xg - xo).max() / np.abs(xo).max()),
+            "gpu_iterations": info["iterations"], "oracle_iterations": it}
 
 
 def main_batch(args, torch, inputs, vsr):

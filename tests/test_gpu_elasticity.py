@@ -55,7 +55,8 @@ def vsr():
 CASES = [("uniform_2x2x2_p2", (2, 2, 2), 2, False, 1.0, 0.0),
          ("stretched_3x2x4_p3", (3, 2, 4), 3, True, 1.3, 2.9),
          ("stretched_2x3x2_p5", (2, 3, 2), 5, True, 0.7, 10.0),
-         ("uniform_2x2x3_p7", (2, 2, 3), 7, False, 1.0, 1.0)]
+         ("uniform_2x2x3_p7", (2, 2, 3), 7, False, 1.0, 1.0),
+         ("stretched_2x3x2_p15", (2, 3, 2), 15, True, 1.1, 4.0)]   # 1-D matrices read from global memory
 
 
 @pytest.mark.parametrize("name,shape,p,stretched,mu,lam", CASES)
