@@ -971,6 +971,8 @@ struct vsr_elasticity {
     double mu = 0, lam = 0;
     double omega = 1, lmin = 0, lmax = 0, setup_seconds = 0;
     hipStream_t stream = nullptr;
+    hipStream_t side[2] = {nullptr, nullptr};   // components 1 and 2 run their relaxations here
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
     std::vector<void *> allocs;
     double *M1 = nullptr, *coef = nullptr, *E = nullptr, *A0inv = nullptr, *c0 = nullptr, *c1 = nullptr;
     double *vr = nullptr, *vz = nullptr, *vp = nullptr, *vq = nullptr, *vt = nullptr, *vu = nullptr;
@@ -984,8 +986,26 @@ struct vsr_elasticity {
         return static_cast<T *>(p);
     }
     ~vsr_elasticity() {
+        for (hipStream_t s : side)
+            if (s) (void)hipStreamSynchronize(s);
         for (vsr_problem *c : comp) destroy_problem(c);
         for (void *p : allocs) (void)hipFree(p);
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
+        for (hipStream_t s : side)
+            if (s) (void)hipStreamDestroy(s);
+    }
+    // Run fn(c, stream) for the three components, component 0 on `stream`, 1 and 2 on the side
+    // streams, forked from and joined back to `stream`.
+    template <typename F>
+    void per_component(F &&fn) {
+        VSR_HIP(hipEventRecord(ev[0], stream));
+        for (hipStream_t s : side) VSR_HIP(hipStreamWaitEvent(s, ev[0], 0));
+        for (int c = 0; c < 3; ++c) fn(c, c == 0 ? stream : side[c - 1]);
+        for (int j = 0; j < 2; ++j) {
+            VSR_HIP(hipEventRecord(ev[1 + j], side[j]));
+            VSR_HIP(hipStreamWaitEvent(stream, ev[1 + j], 0));
+        }
     }
 };
 
@@ -994,8 +1014,7 @@ namespace {
 // y = A x for the 3-component vector (x, y: 3 n, component after component)
 void el_op(vsr_elasticity *L, const double *x, double *y) {
     launch_op_elastic_box(L->d, L->M1, L->coef, L->mu, L->lam, x, L->E, L->ex());
-    const int64_t slot = L->ncell * (int64_t)(L->d.p + 1) * (L->d.p + 1) * (L->d.p + 1);
-    for (int c = 0; c < 3; ++c) launch_gather<double>(L->d, 1, L->E + c * slot, nullptr, y + c * L->n, L->ex());
+    launch_gather_components<double>(L->d, 3, L->E, y, L->ex());
 }
 
 double el_dot(vsr_elasticity *L, const double *x, const double *y) {
@@ -1004,9 +1023,28 @@ double el_dot(vsr_elasticity *L, const double *x, const double *y) {
     return read_scalar(P, SC_TMP);
 }
 
-// z = S r: component j's scalar FDM vertex-star relaxation (undamped)
+// z_c = S_c r_c: component c's scalar FDM vertex-star relaxation (undamped), in its working
+// precision, written to z in FP64 by the prolongation.  The three are independent and run
+// concurrently, one stream each.
+template <typename T>
+void el_relax_component(vsr_problem *P, const double *r, double *z) {
+    relax_apply<T, double>(P, r, (T *)P->z1, T(1), T(0), z);
+}
+
 void el_relax(vsr_elasticity *L, const double *r, double *z) {
-    for (int c = 0; c < 3; ++c) precond(L->comp[c], r + c * L->n, z + c * L->n, 1);
+    L->per_component([&](int c, hipStream_t s) {
+        vsr_problem *P = L->comp[c];
+        const hipStream_t keep = P->stream;
+        P->stream = s;
+        try {
+            if (P->fp32) el_relax_component<float>(P, r + c * L->n, z + c * L->n);
+            else el_relax_component<double>(P, r + c * L->n, z + c * L->n);
+        } catch (...) {
+            P->stream = keep;
+            throw;
+        }
+        P->stream = keep;
+    });
 }
 
 // z = P A0^{-1} P^T r with Q1 in every component
@@ -1017,13 +1055,15 @@ void el_coarse(vsr_elasticity *L, const double *r, double *z) {
     }
     vsr_problem *P = L->comp[0];
     const int Ld[3] = {L->d.Lx, L->d.Ly, L->d.Lz}, NC[3] = {L->d.nx, L->d.ny, L->d.nz};
-    for (int c = 0; c < 3; ++c)
+    L->per_component([&](int c, hipStream_t s) {
         launch_transfer<double, double>(XFER_COARSE_RESTRICT, L->d.p, NC, Ld, P->cdim, P->xm64[XFER_COARSE_RESTRICT],
-                                        r + c * L->n, L->c0 + c * L->nc, 1.0, 0.0, L->ex());
+                                        r + c * L->n, L->c0 + c * L->nc, 1.0, 0.0, Exec{s, nullptr, Tuning{}});
+    });
     launch_dense_gemv<double>(3 * L->nc, L->A0inv, L->c0, L->c1, 1.0, 0.0, L->ex());
-    for (int c = 0; c < 3; ++c)
+    L->per_component([&](int c, hipStream_t s) {
         launch_transfer<double, double>(XFER_COARSE_PROLONG, L->d.p, NC, P->cdim, Ld, P->xm64[XFER_COARSE_PROLONG],
-                                        L->c1 + c * L->nc, z + c * L->n, 1.0, 0.0, L->ex());
+                                        L->c1 + c * L->nc, z + c * L->n, 1.0, 0.0, Exec{s, nullptr, Tuning{}});
+    });
 }
 
 // mode 0: the hybrid V(1,1) z1 = w S r, z2 = z1 + C (r - A z1), z = z2 + w S (r - A z2);
@@ -1561,6 +1601,8 @@ vsr_status vsr_elasticity_setup(const vsr_mesh *mesh, int32_t p, double mu, doub
         L->mu = mu;
         L->lam = lambda;
         L->stream = (hipStream_t)o.stream;
+        for (hipStream_t &s : L->side) VSR_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        for (hipEvent_t &e : L->ev) VSR_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         const int64_t ncell = (int64_t)nx * ny * nz;
         // SDC scalings of each component (exact on boxes): (mu + (mu + lam) [a = j]) |J| (2 / h_a)^2
         std::vector<double> coef((size_t)ncell * 12);

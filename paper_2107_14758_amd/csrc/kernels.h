@@ -75,6 +75,10 @@ void launch_coarse_gather(const Dims &d, const T *c0, const T *e8, T *c3, const 
 template <typename T>
 void launch_gather(const Dims &d, int slots, const T *E, const double *r, T *out, const Exec &e,
                    const double *dotv = nullptr, double *partials = nullptr);
+// ncomp independent gathers in one launch: out + c n = the sum of the single-slot element
+// vector E + c ncell (p+1)^3 per free node, for c < ncomp (n = free nodes).
+template <typename T>
+void launch_gather_components(const Dims &d, int ncomp, const T *E, T *out, const Exec &e);
 int64_t gather_blocks(const Dims &d);
 // Adds nb partial sums in a fixed order and applies them to scal by mode (see launch_dot).
 void launch_finalize(int nb, const double *partials, double *scal, int mode, double *mirror, const Exec &e);
@@ -126,7 +130,7 @@ template <typename T>
 void launch_patch_assemble(const Dims &d, const T *U, T *zF, const Exec &e);
 // Primal linear elasticity on axis-aligned cells (Sec. 3.1), FP64: the three components'
 // cell results of y = A x into E (three element vectors of ncell (p+1)^3, one per output
-// component; launch_gather sums each).  M1: the 1-D matrices A, B, C, C^T ((p+1)^2 each,
+// component; launch_gather_components sums them).  M1: the 1-D matrices A, B, C, C^T ((p+1)^2 each,
 // row = test index; C[a][b] = int phi_a' phi_b); coef: 12 per cell (k[c][a] at 3c + a, then
 // s_xy, s_xz, s_yz); x: 3 n values, component after component.
 void launch_op_elastic_box(const Dims &d, const double *M1, const double *coef, double mu, double lam, const double *x,

@@ -467,6 +467,10 @@ __global__ void __launch_bounds__(XB) k_gather(const double *__restrict__ gate, 
                                                 const T *__restrict__ rT) {
     if (gated(gate)) return;
     constexpr int N1 = P + 1, N3 = N1 * N1 * N1;
+    if (gridDim.y > 1) {   // independent components (r, rT, dotv unused): E and out per blockIdx.y
+        E += (int64_t)blockIdx.y * slots * d.nx * d.ny * d.nz * N3;
+        out += (int64_t)blockIdx.y * d.Lx * d.Ly * d.Lz;
+    }
     const int xblocks = (d.Lx + XB - 1) / XB;
     const int line = (int)(blockIdx.x / xblocks), I0 = (int)(blockIdx.x - (int64_t)line * xblocks) * XB + threadIdx.x + 1;
     const bool live = I0 <= d.Lx;
@@ -826,6 +830,15 @@ void launch_gather(const Dims &d, int slots, const T *E, const double *r, T *out
 }
 
 template <typename T>
+void launch_gather_components(const Dims &d, int ncomp, const T *E, T *out, const Exec &e) {
+#define CALL(P)                                                                                                   \
+    hipLaunchKernelGGL((k_gather<T, P>), dim3(line_blocks(d), (unsigned)ncomp), dim3(XB), 0, e.s, e.gate, d, 1, E,          \
+                       (const double *)nullptr, out, (const double *)nullptr, (double *)nullptr, (const T *)nullptr)
+    VSR_P_SWITCH(d.p, CALL)
+#undef CALL
+}
+
+template <typename T>
 void launch_gather_sub(const Dims &d, const T *E, const T *rT, T *out, const Exec &e) {
 #define CALL(P)                                                                                                   \
     hipLaunchKernelGGL((k_gather<T, P>), dim3(line_blocks(d)), dim3(XB), 0, e.s, e.gate, d, 1, E, (const double *)nullptr, \
@@ -934,6 +947,7 @@ int launch_axpby_to_double(int64_t n, double a, const T *x, double b, double *y,
     template void launch_gather<T>(const Dims &, int, const T *, const double *, T *, const Exec &, const double *, \
                                    double *);                                                                    \
     template void launch_gather_sub<T>(const Dims &, const T *, const T *, T *, const Exec &);                   \
+    template void launch_gather_components<T>(const Dims &, int, const T *, T *, const Exec &);                  \
     template void launch_patch_assemble<T>(const Dims &, const T *, T *, const Exec &);                   \
     template void launch_op_kron_restrict<T>(const Dims &, int, const T *, const T *, const T *, T *, const Exec &); \
     template void launch_coarse_gather<T>(const Dims &, const T *, const T *, T *, const Exec &);              \
