@@ -973,10 +973,13 @@ struct vsr_elasticity {
     hipStream_t stream = nullptr;
     hipStream_t side[2] = {nullptr, nullptr};   // components 1 and 2 run their relaxations here
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t it_ev[2] = {nullptr, nullptr};   // end of the x, r update of the last two iterations
+    const double *gate = nullptr;               // during a solve: the stop flag every launch checks
+    double *host_done = nullptr, *dev_done = nullptr;   // mapped host copy of the stop flag
     std::vector<void *> allocs;
     double *M1 = nullptr, *coef = nullptr, *E = nullptr, *A0inv = nullptr, *c0 = nullptr, *c1 = nullptr;
     double *vr = nullptr, *vz = nullptr, *vp = nullptr, *vq = nullptr, *vt = nullptr, *vu = nullptr;
-    Exec ex() const { return Exec{stream, nullptr, Tuning{}}; }
+    Exec ex() const { return Exec{stream, gate, Tuning{}}; }
     template <typename T>
     T *dalloc(size_t count) {
         void *p = nullptr;
@@ -986,10 +989,14 @@ struct vsr_elasticity {
         return static_cast<T *>(p);
     }
     ~vsr_elasticity() {
+        if (stream) (void)hipStreamSynchronize(stream);
         for (hipStream_t s : side)
             if (s) (void)hipStreamSynchronize(s);
         for (vsr_problem *c : comp) destroy_problem(c);
         for (void *p : allocs) (void)hipFree(p);
+        if (host_done) (void)hipHostFree(host_done);
+        for (hipEvent_t e : it_ev)
+            if (e) (void)hipEventDestroy(e);
         for (hipEvent_t e : ev)
             if (e) (void)hipEventDestroy(e);
         for (hipStream_t s : side)
@@ -1035,15 +1042,19 @@ void el_relax(vsr_elasticity *L, const double *r, double *z) {
     L->per_component([&](int c, hipStream_t s) {
         vsr_problem *P = L->comp[c];
         const hipStream_t keep = P->stream;
+        const double *keep_gate = P->gate;
         P->stream = s;
+        P->gate = L->gate;
         try {
             if (P->fp32) el_relax_component<float>(P, r + c * L->n, z + c * L->n);
             else el_relax_component<double>(P, r + c * L->n, z + c * L->n);
         } catch (...) {
             P->stream = keep;
+            P->gate = keep_gate;
             throw;
         }
         P->stream = keep;
+        P->gate = keep_gate;
     });
 }
 
@@ -1057,12 +1068,12 @@ void el_coarse(vsr_elasticity *L, const double *r, double *z) {
     const int Ld[3] = {L->d.Lx, L->d.Ly, L->d.Lz}, NC[3] = {L->d.nx, L->d.ny, L->d.nz};
     L->per_component([&](int c, hipStream_t s) {
         launch_transfer<double, double>(XFER_COARSE_RESTRICT, L->d.p, NC, Ld, P->cdim, P->xm64[XFER_COARSE_RESTRICT],
-                                        r + c * L->n, L->c0 + c * L->nc, 1.0, 0.0, Exec{s, nullptr, Tuning{}});
+                                        r + c * L->n, L->c0 + c * L->nc, 1.0, 0.0, Exec{s, L->gate, Tuning{}});
     });
     launch_dense_gemv<double>(3 * L->nc, L->A0inv, L->c0, L->c1, 1.0, 0.0, L->ex());
     L->per_component([&](int c, hipStream_t s) {
         launch_transfer<double, double>(XFER_COARSE_PROLONG, L->d.p, NC, P->cdim, Ld, P->xm64[XFER_COARSE_PROLONG],
-                                        L->c1 + c * L->nc, z + c * L->n, 1.0, 0.0, Exec{s, nullptr, Tuning{}});
+                                        L->c1 + c * L->nc, z + c * L->n, 1.0, 0.0, Exec{s, L->gate, Tuning{}});
     });
 }
 
@@ -1603,6 +1614,10 @@ vsr_status vsr_elasticity_setup(const vsr_mesh *mesh, int32_t p, double mu, doub
         L->stream = (hipStream_t)o.stream;
         for (hipStream_t &s : L->side) VSR_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
         for (hipEvent_t &e : L->ev) VSR_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        for (hipEvent_t &e : L->it_ev) VSR_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        VSR_HIP(hipHostMalloc((void **)&L->host_done, sizeof(double), hipHostMallocMapped | hipHostMallocCoherent));
+        VSR_HIP(hipHostGetDevicePointer((void **)&L->dev_done, L->host_done, 0));
+        *L->host_done = 0.0;
         const int64_t ncell = (int64_t)nx * ny * nz;
         // SDC scalings of each component (exact on boxes): (mu + (mu + lam) [a = j]) |J| (2 / h_a)^2
         std::vector<double> coef((size_t)ncell * 12);
@@ -1728,43 +1743,50 @@ vsr_status vsr_elasticity_pcg_solve(vsr_elasticity *L, const double *b, double *
         if (!L || !b || !x) throw Error(VSR_EINVAL, "NULL argument");
         if (!(rtol > 0)) throw Error(VSR_EINVAL, "rtol must be positive");
         const int64_t N = 3 * L->n;
-        const int maxit = L->comp[0]->opt.max_iterations > 0 ? L->comp[0]->opt.max_iterations : 1000;
+        vsr_problem *P = L->comp[0];   // its scalars and partials serve the 3n-vector PCG
+        const int maxit = P->opt.max_iterations > 0 ? P->opt.max_iterations : 1000;
         VSR_HIP(hipStreamSynchronize(L->stream));
         const double t0 = now_s();
+        // device-driven: step lengths, directions and the stopping test stay on the device;
+        // every launch after the start checks the stop flag, and the host polls its mapped
+        // copy one iteration behind, so the GPU never waits for the host between iterations
+        L->gate = nullptr;
+        *L->host_done = 0.0;
         launch_fill<double>(N, x, 0.0, L->ex());
         launch_axpby_to_double<double>(N, 1.0, b, 0.0, L->vr, L->ex());
-        const double bb = el_dot(L, b, b);
-        if (!std::isfinite(bb)) throw Error(VSR_EINVAL, "non-finite right-hand side");
-        double rr = bb, rz = 0;
-        int it = 0;
-        bool conv = bb == 0.0;
-        std::vector<double> alphas, betas;
-        if (!conv) {
+        launch_dot(N, b, b, P->partials, P->scal, 4, nullptr, L->ex());                  // RR = b.b
+        launch_pcg_start(P->scal, rtol, maxit, 0, 0.0, L->dev_done, L->ex());
+        L->gate = P->scal + SC_DONE;
+        try {
             el_precond(L, L->vr, L->vz, 0);
+            launch_dot(N, L->vr, L->vz, P->partials, P->scal, 3, nullptr, L->ex());    // RZ = r.z
             launch_axpby_to_double<double>(N, 1.0, L->vz, 0.0, L->vp, L->ex());
-            rz = el_dot(L, L->vr, L->vz);
-            while (it < maxit) {
+            for (int enq = 1;; ++enq) {
                 el_op(L, L->vp, L->vq);
-                const double alpha = rz / el_dot(L, L->vp, L->vq);
-                alphas.push_back(alpha);
-                launch_axpby_to_double<double>(N, alpha, L->vp, 1.0, x, L->ex());
-                launch_axpby_to_double<double>(N, -alpha, L->vq, 1.0, L->vr, L->ex());
-                ++it;
-                rr = el_dot(L, L->vr, L->vr);
-                if (!std::isfinite(rr)) break;
-                if (rr <= rtol * rtol * bb) {
-                    conv = true;
-                    break;
-                }
+                launch_dot(N, L->vp, L->vq, P->partials, P->scal, 1, nullptr, L->ex());   // alpha = RZ / p.q
+                launch_pcg_xr(N, x, L->vr, L->vp, L->vq, P->scal, P->partials, 5, L->dev_done, L->ex());
+                VSR_HIP(hipEventRecord(L->it_ev[enq & 1], L->stream));
+                if (enq >= maxit) break;
                 el_precond(L, L->vr, L->vz, 0);
-                const double rzn = el_dot(L, L->vr, L->vz);
-                betas.push_back(rzn / rz);
-                launch_axpby_to_double<double>(N, 1.0, L->vz, betas.back(), L->vp, L->ex());
-                rz = rzn;
+                launch_dot(N, L->vr, L->vz, P->partials, P->scal, 2, nullptr, L->ex());   // beta, RZ
+                launch_pcg_p(N, L->vp, L->vz, P->scal, L->ex());
+                if (enq >= 2) {
+                    VSR_HIP(hipEventSynchronize(L->it_ev[(enq - 1) & 1]));
+                    if (*(volatile double *)L->host_done != 0.0) break;
+                }
             }
+        } catch (...) {
+            L->gate = nullptr;
+            throw;
         }
+        L->gate = nullptr;
         VSR_HIP(hipStreamSynchronize(L->stream));
         const double t1 = now_s();
+        VSR_HIP(hipMemcpy(P->host_scal, P->scal, SC_N * sizeof(double), hipMemcpyDeviceToHost));
+        const double bb = P->host_scal[SC_BB], rr = P->host_scal[SC_RR], status = P->host_scal[SC_STATUS];
+        const int it = (int)P->host_scal[SC_IT], na = (int)P->host_scal[SC_NA];
+        if (!std::isfinite(bb)) throw Error(VSR_EINVAL, "non-finite right-hand side");
+        const bool conv = status == 1.0;
         el_op(L, x, L->vt);
         launch_axpby_to_double<double>(N, 1.0, b, -1.0, L->vt, L->ex());
         const double tr = std::sqrt(std::max(0.0, el_dot(L, L->vt, L->vt)));
@@ -1778,12 +1800,7 @@ vsr_status vsr_elasticity_pcg_solve(vsr_elasticity *L, const double *b, double *
         loc.lambda_max = L->lmax;
         loc.setup_seconds = L->setup_seconds;
         loc.solve_seconds = t1 - t0;
-        bool ok = !alphas.empty();
-        for (double a : alphas) ok = ok && a > 0 && std::isfinite(a);
-        if (ok) {
-            lanczos_extremes(alphas, betas, loc.ritz_min, loc.ritz_max);
-            if (loc.ritz_min > 0) loc.kappa_estimate = loc.ritz_max / loc.ritz_min;
-        }
+        ritz_of_run(P, it > 0 ? na : 0, loc);
         if (!conv) throw Error(VSR_ENOCONV, "PCG did not converge in " + std::to_string(it) + " iterations");
     });
     if (info && L) *info = loc;

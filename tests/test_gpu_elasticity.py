@@ -121,6 +121,31 @@ def test_damping_and_pcg(vsr, name, shape, p, stretched, mu, lam):
     g32.close()
 
 
+def test_pcg_zero_rhs_iteration_cap_and_repeat(vsr):
+    """The device-driven solve: b = 0 stops before any iteration with x = 0; an iteration cap
+    below the needed count reports non-convergence after exactly that many updates; a second
+    solve of the same system repeats the first bit for bit (the three component relaxations run
+    on separate streams, which must not change any result)."""
+    V = grid((3, 2, 3), True, seed=4)
+    d = Discretization(V, 3)
+    g = vsr.Elasticity(V, 3, 1.0, 5.0, max_iterations=4)
+    b = torch.zeros(g.n, dtype=torch.float64, device="cuda")
+    x = torch.full_like(b, 7.0)
+    info = g.pcg_solve(b, x)
+    assert info["converged"] == 1 and info["iterations"] == 0 and float(x.abs().max()) == 0.0
+    f = np.random.default_rng(9).uniform(-1, 1, (3, d.ncell, d.q, d.q, d.q))
+    g.load_vector(dev(f), b)
+    info = g.pcg_solve(b, x, raise_on_noconv=False)
+    assert info["status"] == vsr.VSR_ENOCONV and info["converged"] == 0 and info["iterations"] == 4
+    g.close()
+    g = vsr.Elasticity(V, 3, 1.0, 5.0, relax_fp32=True, deterministic=True)   # panel sums in a fixed order
+    x1, x2 = torch.zeros_like(b), torch.zeros_like(b)
+    i1 = g.pcg_solve(b, x1)
+    i2 = g.pcg_solve(b, x2)
+    assert i1["iterations"] == i2["iterations"] and torch.equal(x1, x2)
+    g.close()
+
+
 def test_errors(vsr):
     V = inputs.jitter_vertices(inputs.cube_vertices(2, 2, 2), 0.1, np.random.default_rng(0))
     with pytest.raises(vsr.VsrError) as e:
