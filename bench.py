@@ -13,6 +13,11 @@ jittered), members spread over streams, one lockstep iteration replayed from a h
 launch shapes autotuned per degree; value = total DOFs of the batch / batch solve time.
 The same members solved one after another are timed beside it.
 
+--workload elasticity_8x8x8 times primal linear elasticity with the SDC relaxation (Sec.
+3.1) on 8^3 boxes at Q7 (lambda = mu = 1), the operator's rate and the iteration table over
+p in {3, 7, 15} and lambda in {0, 1, 10, 100, 1000}; the default line carries the same solve
+as its "elasticity" entry.
+
 Prints one JSON line.  --gpus above 1 is rejected: this build runs on one GPU.
 """
 import argparse
@@ -329,6 +334,13 @@ def main():
                             "true_rel_residual": r32h["info"]["true_rel_residual"]}
         log(f"[bench] 32^3 Q7: {r32h['iterations']} iterations, {ms_h:.1f} ms/solve, setup {r32h['setup_s']:.1f} s")
         del w32, r32h
+        # primal linear elasticity with the SDC relaxation (Sec. 3.1): 8^3 boxes, Q7, mu = lam = 1
+        ge, _, _, ie, dte = elasticity_solve_timed(vsr, torch, 8, 7, 1.0, 1.0, True, args.steps, 2)
+        out["elasticity"] = {"workload": "elasticity_8x8x8_q7", "dofs": ge.n, "value": ge.n / dte, "unit": "DOF/s",
+                             "ms_per_step": 1e3 * dte, "iterations": ie["iterations"],
+                             "kappa_estimate": ie["kappa_estimate"], "true_rel_residual": ie["true_rel_residual"]}
+        ge.close()
+        log(f"[bench] elasticity 8^3 Q7: {ie['iterations']} iterations, {1e3 * dte:.2f} ms/solve")
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(p, cells=8 if p <= 7 else 3, workload=wname)
