@@ -162,6 +162,14 @@ def batch_timed(vsr, torch, W, steps, warmup, share_factors=False):
     torch.cuda.synchronize()
     seq = time.perf_counter() - t0
     log(f"[bench] sequential single solves: {1e3 * seq:.1f} ms")
+    # each member alone (synchronised around it): where the sequential time goes
+    member_s = []
+    for m, b, x in zip(B.members, bs, xs):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        m.pcg_solve(b, x)
+        torch.cuda.synchronize()
+        member_s.append(time.perf_counter() - t1)
     # dominant kernel: the patch solve of the largest member, profiled in a single solve
     big = max(range(len(W)), key=lambda i: B.members[i].n)
     m = B.members[big]
@@ -170,7 +178,7 @@ def batch_timed(vsr, torch, W, steps, warmup, share_factors=False):
     m.pcg_solve(bs[big], xs[big])
     stats = m.kernel_stats()
     m.set_profiling(False)
-    out = dict(seconds=dt, sequential_seconds=seq, infos=infos, setup_s=setup_s, stats=stats, big=big,
+    out = dict(seconds=dt, sequential_seconds=seq, member_seconds=member_s, infos=infos, setup_s=setup_s, stats=stats, big=big,
                shapes={f"p{W[i]['p']}-{'jittered' if W[i]['jitter'] else 'cartesian'}": B.members[i].tuning()
                        for i in range(len(W))})
     B.close()
@@ -412,7 +420,7 @@ def main_elasticity(args, torch, inputs, vsr):
     out = {
         "metric": "PCG DOF/s to 1e-8 rel. residual, SDC-relaxation elasticity", "value": g.n / dt, "unit": "DOF/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * dt, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64 (PCG, operator) + f32 (component relaxations, coarse)",
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64 (PCG, operator, coarse solve) + f32 (component relaxations)",
         "data": "synthetic (seeded U[-1,1] body force at quadrature points)",
         "config": {"workload": "elasticity_8x8x8_q7", "cells": [n, n, n], "p": p, "mu": 1.0, "lambda": lam, "dofs": g.n,
                    "rtol": 1e-8, "preconditioner": "hybrid V(1,1), SDC vertex-star FDM relaxation, vector Q1 coarse",
@@ -501,6 +509,14 @@ def main_batch(args, torch, inputs, vsr):
                        "ms": 1e3 * r["sequential_seconds"]},
         "roofline": patch_roofline(r["stats"], int(W[big]["p"]), None),
     }
+    # the members of at least 1M DOFs fill the GPU on their own; overlap in the batch can only
+    # hide the time of the others
+    ms = r["member_seconds"]
+    dofs = [(int(w["p"]) * int(w["n"]) - 1) ** 3 for w in W]
+    large = [i for i in range(len(W)) if dofs[i] >= 1_000_000]
+    out["members"] = {"ms_each": [round(1e3 * t, 3) for t in ms], "dofs_each": dofs,
+                      "large_count": len(large), "large_ms": 1e3 * sum(ms[i] for i in large),
+                      "small_ms": 1e3 * sum(ms[i] for i in range(len(W)) if i not in large)}
     out["roofline"]["member"] = f"{W[big]['n']}^3 cells p={W[big]['p']} (largest), single solve"
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
