@@ -10,10 +10,13 @@
 // (from mu d_d v_c d_c u_d + lam d_c v_c d_d u_d): 21 terms per cell, 7 per output component.
 //
 // One workgroup per cell in three groups of whole wavefronts, group c computing output
-// component c; in group c thread (j, i) owns one z-column.  The input components pass through
-// LDS one at a time; on each, every group runs up to three of its terms (the diagonal block's
-// three on its own component, the coupling block's two on the others), each term's x
-// contraction through the group's own LDS slab and its y and z contractions in registers.
+// component c.  The input components pass through LDS one at a time; on each, every group
+// runs up to three of its terms (the diagonal block's three on its own component, the
+// coupling block's two on the others).  Up to p = 11 each (j, i) column of a group has two
+// threads, each owning half of the z planes: a term's x and y contractions run plane by
+// plane through the group's LDS slabs and its z contraction reads the y results of all
+// planes back from LDS.  Above p = 11 (three groups of two threads per column would exceed
+// 1,024 threads) one thread owns the column and keeps the y and z contractions in registers.
 // The cell's results go to three element vectors (one per component) for the gather.
 #include "device_common.h"
 
@@ -24,8 +27,14 @@ namespace {
 constexpr int MA = 0, MB = 1, MC = 2, MCT = 3;   // the 1-D matrices
 constexpr int kElasticCoef = 12;                 // per cell: k[c][a] at 3 c + a (9), then s_xy, s_xz, s_yz
 
-// Threads of one output component's group: whole wavefronts covering the (p+1)^2 columns.
-constexpr int el_group(int p) { return (p + 1) * (p + 1) < 64 ? 64 : ((p + 1) * (p + 1) + 63) / 64 * 64; }
+// Whole wavefronts covering t threads.
+constexpr int el_waves(int t) { return t < 64 ? 64 : (t + 63) / 64 * 64; }
+// Threads per (j, i) column: two while three groups of them fit a workgroup of 1,024.
+constexpr int el_halves(int p) { return 3 * el_waves(2 * (p + 1) * (p + 1)) <= 1024 ? 2 : 1; }
+// Threads of one output component's group.
+constexpr int el_group(int p) { return el_waves(el_halves(p) * (p + 1) * (p + 1)); }
+static_assert(3 * el_group(11) <= 1024 && el_halves(11) == 2 && el_halves(12) == 1 && 3 * el_group(15) <= 1024,
+              "workgroup sizes");
 
 // The matrix on `axis` (0 = x, 1 = y, 2 = z) of term s of block (C, D): for C == D the
 // stiffness A on axis s and B elsewhere; for C != D term 0 is mu's (C^T on axis C, C on axis
@@ -36,6 +45,55 @@ constexpr int term_mat(int axis, int C, int D, int s) {
     return axis == C ? mc : (axis == D ? md : MB);
 }
 constexpr bool has_term(int C, int D, int s) { return C == D || s < 2; }
+
+// Planes k0 <= k < k0 + KH (below N1) of X = (I x I x Mx) xs, for column (j, i)
+template <int N1, int KH>
+__device__ __forceinline__ void x_half(const double *Mx, const double *xs, double *X, int j, int i, int k0) {
+#pragma unroll
+    for (int kk = 0; kk < KH; ++kk) {
+        const int k = k0 + kk;
+        if (k < N1) {
+            double s = 0;
+#pragma unroll
+            for (int ii = 0; ii < N1; ++ii) s += Mx[i * N1 + ii] * xs[(k * N1 + j) * N1 + ii];
+            X[(k * N1 + j) * N1 + i] = s;
+        }
+    }
+}
+
+// The same planes of Yv = (I x My x I) X
+template <int N1, int KH>
+__device__ __forceinline__ void y_half(const double *My, const double *X, double *Yv, int j, int i, int k0) {
+#pragma unroll
+    for (int kk = 0; kk < KH; ++kk) {
+        const int k = k0 + kk;
+        if (k < N1) {
+            double s = 0;
+#pragma unroll
+            for (int jj = 0; jj < N1; ++jj) s += My[j * N1 + jj] * X[(k * N1 + jj) * N1 + i];
+            Yv[(k * N1 + j) * N1 + i] = s;
+        }
+    }
+}
+
+// y[kk] += w ((Mz x I x I) Yv)[k0 + kk] for column (j, i)
+template <int N1, int KH>
+__device__ __forceinline__ void z_half(const double *Mz, const double *Yv, int j, int i, int k0, double w,
+                                       double (&y)[KH]) {
+    double Yc[N1];
+#pragma unroll
+    for (int kk = 0; kk < N1; ++kk) Yc[kk] = Yv[(kk * N1 + j) * N1 + i];
+#pragma unroll
+    for (int kk = 0; kk < KH; ++kk) {
+        const int k = k0 + kk;
+        if (k < N1) {
+            double s = 0;
+#pragma unroll
+            for (int m = 0; m < N1; ++m) s += Mz[k * N1 + m] * Yc[m];
+            y[kk] += w * s;
+        }
+    }
+}
 
 // X = (I x I x Mx) xs for the group's columns
 template <int N1>
@@ -75,11 +133,12 @@ __global__ void __launch_bounds__(3 * el_group(P))
     k_op_elastic_box(const double *__restrict__ gate, Dims d, const double *__restrict__ M1, const double *__restrict__ coef,
                      double mu, double lam, const double *__restrict__ x, double *__restrict__ E) {
     if (gated(gate)) return;
-    constexpr int N1 = P + 1, N2 = N1 * N1, N3 = N2 * N1, NG = el_group(P);
+    constexpr int N1 = P + 1, N2 = N1 * N1, N3 = N2 * N1, NG = el_group(P), H = el_halves(P);
+    constexpr int KH = (N1 + H - 1) / H;   // z planes per thread
     // A, B, C, C^T: [m][row = test][col = trial], in LDS (at p = 15 with the cell blocks 139 KB)
     __shared__ double sM[4 * N2];
-    __shared__ double xs[N3];          // the input component's cell block [k][j][i]
-    __shared__ double Xs[3 * N3];      // per group: after the x contraction
+    __shared__ double xs[N3];                   // the input component's cell block [k][j][i]
+    __shared__ double Xs[(H == 2 ? 6 : 3) * N3];   // per group: after the x (and the y) contraction
     const int tid = threadIdx.x;
     const int g = tid / NG, lt = tid - g * NG;
     const int64_t e = blockIdx.x;
@@ -87,16 +146,19 @@ __global__ void __launch_bounds__(3 * el_group(P))
     for (int t = tid; t < 4 * N2; t += blockDim.x) sM[t] = M1[t];
     const double *cf = coef + e * kElasticCoef;
     double *X = Xs + g * N3;
-    const bool col = lt < N2;
-    const int j = lt / N1, i = lt % N1;
+    double *Yv = Xs + (3 + g) * N3;   // used only with two threads per column
+    const bool col = lt < H * N2;
+    const int h = lt / N2, c2 = lt - h * N2;   // half, column
+    const int j = c2 / N1, i = c2 % N1, k0 = h * KH;
     const int64_t n = (int64_t)d.Lx * d.Ly * d.Lz;
-    double y[N1];
+    double y[KH];
 #pragma unroll
-    for (int k = 0; k < N1; ++k) y[k] = 0.0;
+    for (int k = 0; k < KH; ++k) y[k] = 0.0;
     // Input component D: load it, then terms 0 and 1 of every group and term 2 of group D.
-    // Barriers: after the load (xs ready), after each x pass (X ready), after each y/z pass
-    // (X free again); the last y/z pass of a component also frees xs for the next load.  The
-    // loops stay rolled: one copy of the contractions, their registers allocated once.
+    // Barriers: after the load (xs ready), after each contraction pass (its slab ready), and
+    // after the last pass of a term (the slabs free again); the last term of a component also
+    // frees xs for the next load.  The loops stay rolled: one copy of the contractions, their
+    // registers allocated once.
 #pragma unroll 1
     for (int D = 0; D < 3; ++D) {
         for (int t = tid; t < N3; t += blockDim.x) {
@@ -112,16 +174,26 @@ __global__ void __launch_bounds__(3 * el_group(P))
             const double *Mx = sM + term_mat(0, g, D, S) * N2, *My = sM + term_mat(1, g, D, S) * N2,
                          *Mz = sM + term_mat(2, g, D, S) * N2;
             const double w = g == D ? cf[3 * D + S] : (S == 0 ? mu : lam) * cf[9 + g + D - 1];   // s_xy, s_xz, s_yz at 9..11
-            if (active) x_pass<N1>(Mx, xs, X, j, i);
-            __syncthreads();
-            if (active) yz_pass<N1>(My, Mz, X, j, i, w, y);
-            __syncthreads();
+            if constexpr (H == 2) {
+                if (active) x_half<N1, KH>(Mx, xs, X, j, i, k0);
+                __syncthreads();
+                if (active) y_half<N1, KH>(My, X, Yv, j, i, k0);
+                __syncthreads();
+                if (active) z_half<N1, KH>(Mz, Yv, j, i, k0, w, y);
+                __syncthreads();
+            } else {
+                if (active) x_pass<N1>(Mx, xs, X, j, i);
+                __syncthreads();
+                if (active) yz_pass<N1>(My, Mz, X, j, i, w, y);
+                __syncthreads();
+            }
         }
     }
     if (col) {
         const int64_t slot = (int64_t)d.nx * d.ny * d.nz * N3;
 #pragma unroll
-        for (int k = 0; k < N1; ++k) E[g * slot + elem_index<N1>(d, ex, ey, ez, k, j, i)] = y[k];
+        for (int kk = 0; kk < KH; ++kk)
+            if (k0 + kk < N1) E[g * slot + elem_index<N1>(d, ex, ey, ez, k0 + kk, j, i)] = y[kk];
     }
 }
 

@@ -87,7 +87,10 @@ def test_operator_load_and_relaxations(vsr, name, shape, p, stretched, mu, lam):
     g.close()
 
 
-@pytest.mark.parametrize("name,shape,p,stretched,mu,lam", CASES[1:3])
+PCG_CASES = CASES[1:3] + [("stretched_3x3x2_p7_lam50", (3, 3, 2), 7, True, 1.0, 50.0)]   # 59 iterations
+
+
+@pytest.mark.parametrize("name,shape,p,stretched,mu,lam", PCG_CASES)
 def test_damping_and_pcg(vsr, name, shape, p, stretched, mu, lam):
     say("case", name)
     V = grid(shape, stretched, seed=2)
