@@ -163,8 +163,11 @@ vsr_status vsr_elasticity_apply_operator(vsr_elasticity *el, const double *x_dev
  * coarse correction. */
 vsr_status vsr_elasticity_apply_relaxation(vsr_elasticity *el, const double *r_dev, double *z_dev, int32_t mode);
 vsr_status vsr_elasticity_damping(const vsr_elasticity *el, double *omega, double *lambda_min, double *lambda_max);
-/* PCG (Sec. 2.8) from x = 0 until ||r||_2 <= rtol ||b||_2 (host-driven; info as for
- * vsr_pcg_solve, without stagnation handling). */
+/* PCG (Sec. 2.8) from x = 0 until ||r||_2 <= rtol ||b||_2, driven from the device (scalars
+ * and the stopping test on the GPU; the host polls one iteration behind).  info as for
+ * vsr_pcg_solve, without stagnation handling.  Returns VSR_ENOCONV at max_iterations and
+ * VSR_EINVAL for a non-finite b.  The three component relaxations run on two extra streams
+ * forked from and joined back to the solve's stream; calls on one object must not overlap. */
 vsr_status vsr_elasticity_pcg_solve(vsr_elasticity *el, const double *b_dev, double *x_dev, double rtol,
                                     vsr_solve_info *info);
 void vsr_elasticity_destroy(vsr_elasticity *el);
