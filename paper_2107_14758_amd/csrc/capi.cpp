@@ -1066,15 +1066,12 @@ void el_coarse(vsr_elasticity *L, const double *r, double *z) {
     }
     vsr_problem *P = L->comp[0];
     const int Ld[3] = {L->d.Lx, L->d.Ly, L->d.Lz}, NC[3] = {L->d.nx, L->d.ny, L->d.nz};
-    L->per_component([&](int c, hipStream_t s) {
-        launch_transfer<double, double>(XFER_COARSE_RESTRICT, L->d.p, NC, Ld, P->cdim, P->xm64[XFER_COARSE_RESTRICT],
-                                        r + c * L->n, L->c0 + c * L->nc, 1.0, 0.0, Exec{s, L->gate, Tuning{}});
-    });
+    // the three components' restrictions in one launch, the coupled solve, the three prolongations
+    launch_transfer<double, double>(XFER_COARSE_RESTRICT, L->d.p, NC, Ld, P->cdim, P->xm64[XFER_COARSE_RESTRICT], r,
+                                    L->c0, 1.0, 0.0, L->ex(), nullptr, nullptr, nullptr, 0, 3);
     launch_dense_gemv<double>(3 * L->nc, L->A0inv, L->c0, L->c1, 1.0, 0.0, L->ex());
-    L->per_component([&](int c, hipStream_t s) {
-        launch_transfer<double, double>(XFER_COARSE_PROLONG, L->d.p, NC, P->cdim, Ld, P->xm64[XFER_COARSE_PROLONG],
-                                        L->c1 + c * L->nc, z + c * L->n, 1.0, 0.0, Exec{s, L->gate, Tuning{}});
-    });
+    launch_transfer<double, double>(XFER_COARSE_PROLONG, L->d.p, NC, P->cdim, Ld, P->xm64[XFER_COARSE_PROLONG], L->c1,
+                                    z, 1.0, 0.0, L->ex(), nullptr, nullptr, nullptr, 0, 3);
 }
 
 // mode 0: the hybrid V(1,1) z1 = w S r, z2 = z1 + C (r - A z1), z = z2 + w S (r - A z2);

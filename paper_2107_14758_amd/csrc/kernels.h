@@ -98,11 +98,12 @@ void launch_load_vector(const Dims &d, const double *IDq, const double *wdet, co
 // box_mode (XFER_FDM_PROLONG up to degree kFusedScatterMaxP): 1 = in holds the patch solves'
 // star boxes ((2p-1)^3 per mesh vertex) and the prolongation reads their assembled sum (the
 // scatter-add of Sec. 2.5) instead of a lattice vector; 2 = the same with only the interior
-// vertices' stars; 0 = a lattice vector.
+// vertices' stars; 0 = a lattice vector.  ncomp > 1: that many independent vectors one after
+// another in `in` and in `out` (lattice input only, no out64, dotv or partials), one launch.
 template <typename Tin, typename T>
 void launch_transfer(int kind, int p, const int ncell[3], const int in_dims[3], const int out_dims[3], const T *M,
                      const Tin *in, T *out, T alpha, T beta, const Exec &e, double *out64 = nullptr,
-                     const double *dotv = nullptr, double *partials = nullptr, int box_mode = 0);
+                     const double *dotv = nullptr, double *partials = nullptr, int box_mode = 0, int ncomp = 1);
 // Workgroups of one launch_transfer of this kind.
 int transfer_blocks(int kind, int p, const int ncell[3]);
 

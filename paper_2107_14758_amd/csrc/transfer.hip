@@ -88,6 +88,10 @@ __global__ void __launch_bounds__(XFER_THREADS)
                T *__restrict__ out, T alpha, T beta, double *__restrict__ out64, const double *__restrict__ dotv,
                double *__restrict__ partials, int box_mode) {
     if (gated(gate)) return;
+    if (gridDim.y > 1) {   // independent components (lattice input, no out64 / dot): blockIdx.y selects one
+        in += blockIdx.y * (int64_t)ix * iy * iz;
+        out += blockIdx.y * (int64_t)ox * oy * oz;
+    }
     constexpr int KX = K + (CX - 1) * IS, KY = K + (CY - 1) * IS;   // window extents along x and y
     constexpr int AX = CX * OA, AY = CY * OA;                       // outputs along x and y
     constexpr int KXP = KX | 1, KYP = KY | 1;   // odd row pitches: strided LDS reads hit distinct banks
@@ -232,7 +236,9 @@ int transfer_blocks(int kind, int p, const int ncell[3]) {
 template <typename Tin, typename T>
 void launch_transfer(int kind, int p, const int ncell[3], const int in_dims[3], const int out_dims[3], const T *M,
                      const Tin *in, T *out, T alpha, T beta, const Exec &e, double *out64, const double *dotv,
-                     double *partials, int box_mode) {
+                     double *partials, int box_mode, int ncomp) {
+    if (ncomp < 1 || (ncomp > 1 && (out64 != nullptr || dotv != nullptr || partials != nullptr || box_mode != 0)))
+        throw Error(VSR_EINVAL, "transfer components: lattice input without FP64 copy or dot only");
     const int nc = ncell[0] * ncell[1] * ncell[2];
     if (nc == 0 || (int64_t)out_dims[0] * out_dims[1] * out_dims[2] == 0) {
         const int nb = transfer_blocks(kind, p, ncell);
@@ -251,7 +257,7 @@ void launch_transfer(int kind, int p, const int ncell[3], const int in_dims[3], 
                                    alpha, beta, out64, dotv, partials, box_mode);                                      \
             else throw Error(VSR_EINVAL, "star-box input is for the FDM prolongation only");                           \
         } else {                                                                                                       \
-            hipLaunchKernelGGL((k_transfer<Tin, T, OA, K, IS, CX, CY>), dim3(8u * (unsigned)((nb + 7) / 8)),          \
+            hipLaunchKernelGGL((k_transfer<Tin, T, OA, K, IS, CX, CY>), dim3(8u * (unsigned)((nb + 7) / 8), (unsigned)ncomp), \
                                dim3(XFER_THREADS), 0, e.s, e.gate, M, ncell[0], ncell[1], ncell[2], IO, OS, in_dims[0], \
                                in_dims[1], in_dims[2], out_dims[0], out_dims[1], out_dims[2], in, out, alpha, beta,   \
                                out64, dotv, partials, 0);                                                             \
@@ -272,12 +278,12 @@ void launch_transfer(int kind, int p, const int ncell[3], const int in_dims[3], 
 
 template void launch_transfer<double, double>(int, int, const int *, const int *, const int *, const double *,
                                               const double *, double *, double, double, const Exec &, double *,
-                                              const double *, double *, int);
+                                              const double *, double *, int, int);
 template void launch_transfer<float, float>(int, int, const int *, const int *, const int *, const float *,
                                             const float *, float *, float, float, const Exec &, double *,
-                                            const double *, double *, int);
+                                            const double *, double *, int, int);
 template void launch_transfer<double, float>(int, int, const int *, const int *, const int *, const float *,
                                              const double *, float *, float, float, const Exec &, double *,
-                                             const double *, double *, int);
+                                             const double *, double *, int, int);
 
 }  // namespace vsr
