@@ -973,7 +973,11 @@ struct vsr_elasticity {
     hipStream_t stream = nullptr;
     hipStream_t side[2] = {nullptr, nullptr};   // components 1 and 2 run their relaxations here
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
-    hipEvent_t it_ev[2] = {nullptr, nullptr};   // end of the x, r update of the last two iterations
+    hipEvent_t it_ev[2] = {nullptr, nullptr};   // end of the last two iterations
+    hipStream_t origin = nullptr;               // the solve's own stream (graph capture needs one)
+    hipGraph_t graph = nullptr;                 // one PCG iteration, recorded for the output vector graph_x
+    hipGraphExec_t exec = nullptr;
+    const double *graph_x = nullptr;
     const double *gate = nullptr;               // during a solve: the stop flag every launch checks
     double *host_done = nullptr, *dev_done = nullptr;   // mapped host copy of the stop flag
     std::vector<void *> allocs;
@@ -994,6 +998,10 @@ struct vsr_elasticity {
             if (s) (void)hipStreamSynchronize(s);
         for (vsr_problem *c : comp) destroy_problem(c);
         for (void *p : allocs) (void)hipFree(p);
+        if (origin) (void)hipStreamSynchronize(origin);
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (origin) (void)hipStreamDestroy(origin);
         if (host_done) (void)hipHostFree(host_done);
         for (hipEvent_t e : it_ev)
             if (e) (void)hipEventDestroy(e);
@@ -1612,6 +1620,7 @@ vsr_status vsr_elasticity_setup(const vsr_mesh *mesh, int32_t p, double mu, doub
         for (hipStream_t &s : L->side) VSR_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
         for (hipEvent_t &e : L->ev) VSR_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         for (hipEvent_t &e : L->it_ev) VSR_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        VSR_HIP(hipStreamCreateWithFlags(&L->origin, hipStreamNonBlocking));
         VSR_HIP(hipHostMalloc((void **)&L->host_done, sizeof(double), hipHostMallocMapped | hipHostMallocCoherent));
         VSR_HIP(hipHostGetDevicePointer((void **)&L->dev_done, L->host_done, 0));
         *L->host_done = 0.0;
@@ -1754,28 +1763,63 @@ vsr_status vsr_elasticity_pcg_solve(vsr_elasticity *L, const double *b, double *
         launch_dot(N, b, b, P->partials, P->scal, 4, nullptr, L->ex());                  // RR = b.b
         launch_pcg_start(P->scal, rtol, maxit, 0, 0.0, L->dev_done, L->ex());
         L->gate = P->scal + SC_DONE;
+        const hipStream_t user = L->stream;
+        auto iteration = [&] {
+            el_op(L, L->vp, L->vq);
+            launch_dot(N, L->vp, L->vq, P->partials, P->scal, 1, nullptr, L->ex());       // alpha = RZ / p.q
+            launch_pcg_xr(N, x, L->vr, L->vp, L->vq, P->scal, P->partials, 5, L->dev_done, L->ex());
+            el_precond(L, L->vr, L->vz, 0);
+            launch_dot(N, L->vr, L->vz, P->partials, P->scal, 2, nullptr, L->ex());       // beta, RZ
+            launch_pcg_p(N, L->vp, L->vz, P->scal, L->ex());
+        };
         try {
             el_precond(L, L->vr, L->vz, 0);
             launch_dot(N, L->vr, L->vz, P->partials, P->scal, 3, nullptr, L->ex());    // RZ = r.z
             launch_axpby_to_double<double>(N, 1.0, L->vz, 0.0, L->vp, L->ex());
-            for (int enq = 1;; ++enq) {
-                el_op(L, L->vp, L->vq);
-                launch_dot(N, L->vp, L->vq, P->partials, P->scal, 1, nullptr, L->ex());   // alpha = RZ / p.q
-                launch_pcg_xr(N, x, L->vr, L->vp, L->vq, P->scal, P->partials, 5, L->dev_done, L->ex());
-                VSR_HIP(hipEventRecord(L->it_ev[enq & 1], L->stream));
-                if (enq >= maxit) break;
-                el_precond(L, L->vr, L->vz, 0);
-                launch_dot(N, L->vr, L->vz, P->partials, P->scal, 2, nullptr, L->ex());   // beta, RZ
-                launch_pcg_p(N, L->vp, L->vz, P->scal, L->ex());
+            // the iterations run on the library's own stream, forked from the caller's, one
+            // recorded graph per iteration (its fork to the component streams and its joins
+            // are edges of the graph); the graph holds x's address and is recorded again for
+            // another x
+            VSR_HIP(hipEventRecord(L->ev[0], user));
+            VSR_HIP(hipStreamWaitEvent(L->origin, L->ev[0], 0));
+            L->stream = L->origin;
+            if (!L->exec || L->graph_x != x) {
+                if (L->exec) VSR_HIP(hipGraphExecDestroy(L->exec));
+                if (L->graph) VSR_HIP(hipGraphDestroy(L->graph));
+                L->exec = nullptr;
+                L->graph = nullptr;
+                L->graph_x = nullptr;
+                VSR_HIP(hipStreamBeginCapture(L->origin, hipStreamCaptureModeThreadLocal));
+                try {
+                    iteration();
+                } catch (...) {
+                    hipGraph_t g = nullptr;
+                    (void)hipStreamEndCapture(L->origin, &g);
+                    if (g) (void)hipGraphDestroy(g);
+                    throw;
+                }
+                VSR_HIP(hipStreamEndCapture(L->origin, &L->graph));
+                VSR_HIP(hipGraphInstantiate(&L->exec, L->graph, nullptr, nullptr, 0));
+                L->graph_x = x;
+            }
+            // the device stops by itself (DONE) at convergence or at max_iterations; the host
+            // stops queueing once the replay before the last one queued shows DONE
+            for (int enq = 1; enq <= maxit + 1; ++enq) {
+                VSR_HIP(hipGraphLaunch(L->exec, L->origin));
+                VSR_HIP(hipEventRecord(L->it_ev[enq & 1], L->origin));
                 if (enq >= 2) {
                     VSR_HIP(hipEventSynchronize(L->it_ev[(enq - 1) & 1]));
                     if (*(volatile double *)L->host_done != 0.0) break;
                 }
             }
         } catch (...) {
+            L->stream = user;
             L->gate = nullptr;
             throw;
         }
+        VSR_HIP(hipEventRecord(L->ev[0], L->origin));
+        VSR_HIP(hipStreamWaitEvent(user, L->ev[0], 0));
+        L->stream = user;
         L->gate = nullptr;
         VSR_HIP(hipStreamSynchronize(L->stream));
         const double t1 = now_s();

@@ -128,7 +128,8 @@ def test_pcg_zero_rhs_iteration_cap_and_repeat(vsr):
     """The device-driven solve: b = 0 stops before any iteration with x = 0; an iteration cap
     below the needed count reports non-convergence after exactly that many updates; a second
     solve of the same system repeats the first bit for bit (the three component relaxations run
-    on separate streams, which must not change any result)."""
+    on separate streams, which must not change any result), also when a later solve replays the
+    iteration recorded by an earlier one."""
     V = grid((3, 2, 3), True, seed=4)
     d = Discretization(V, 3)
     g = vsr.Elasticity(V, 3, 1.0, 5.0, max_iterations=4)
@@ -144,8 +145,16 @@ def test_pcg_zero_rhs_iteration_cap_and_repeat(vsr):
     g = vsr.Elasticity(V, 3, 1.0, 5.0, relax_fp32=True, deterministic=True)   # panel sums in a fixed order
     x1, x2 = torch.zeros_like(b), torch.zeros_like(b)
     i1 = g.pcg_solve(b, x1)
-    i2 = g.pcg_solve(b, x2)
+    i2 = g.pcg_solve(b, x2)   # recorded again for the new output vector
     assert i1["iterations"] == i2["iterations"] and torch.equal(x1, x2)
+    # the recorded iteration replayed by later solves into the same x, with other work between
+    y = torch.zeros_like(b)
+    for _ in range(2):
+        g.apply_operator(x1, y)
+        g.apply_relaxation(b, y, 0)
+        x3 = x2.clone()
+        i3 = g.pcg_solve(b, x2)
+        assert i3["iterations"] == i1["iterations"] and torch.equal(x2, x3)
     g.close()
 
 
