@@ -166,8 +166,10 @@ vsr_status vsr_elasticity_damping(const vsr_elasticity *el, double *omega, doubl
 /* PCG (Sec. 2.8) from x = 0 until ||r||_2 <= rtol ||b||_2, driven from the device (scalars
  * and the stopping test on the GPU; the host polls one iteration behind).  info as for
  * vsr_pcg_solve, without stagnation handling.  Returns VSR_ENOCONV at max_iterations and
- * VSR_EINVAL for a non-finite b.  The three component relaxations run on two extra streams
- * forked from and joined back to the solve's stream; calls on one object must not overlap. */
+ * VSR_EINVAL for a non-finite b.  The iterations run on the library's own stream, forked from
+ * and joined back to the options' stream, as replays of one recorded iteration (kept for the
+ * next solve into the same x_dev), the three component relaxations on two more streams; calls
+ * on one object must not overlap. */
 vsr_status vsr_elasticity_pcg_solve(vsr_elasticity *el, const double *b_dev, double *x_dev, double rtol,
                                     vsr_solve_info *info);
 void vsr_elasticity_destroy(vsr_elasticity *el);
