@@ -420,7 +420,7 @@ def main_elasticity(args, torch, inputs, vsr):
     out = {
         "metric": "PCG DOF/s to 1e-8 rel. residual, SDC-relaxation elasticity", "value": g.n / dt, "unit": "DOF/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * dt, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64 (PCG, operator, coarse solve) + f32 (component relaxations)",
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64 (PCG, outer operator) + f32 (V-cycle: component relaxations, inner operators, coarse solve)",
         "data": "synthetic (seeded U[-1,1] body force at quadrature points)",
         "config": {"workload": "elasticity_8x8x8_q7", "cells": [n, n, n], "p": p, "mu": 1.0, "lambda": lam, "dofs": g.n,
                    "rtol": 1e-8, "preconditioner": "hybrid V(1,1), SDC vertex-star FDM relaxation, vector Q1 coarse",

@@ -981,8 +981,14 @@ struct vsr_elasticity {
     const double *gate = nullptr;               // during a solve: the stop flag every launch checks
     double *host_done = nullptr, *dev_done = nullptr;   // mapped host copy of the stop flag
     std::vector<void *> allocs;
-    double *M1 = nullptr, *coef = nullptr, *E = nullptr, *A0inv = nullptr, *c0 = nullptr, *c1 = nullptr;
-    double *vr = nullptr, *vz = nullptr, *vp = nullptr, *vq = nullptr, *vt = nullptr, *vu = nullptr;
+    double *M1 = nullptr, *coef = nullptr, *E = nullptr, *A0inv = nullptr;
+    double *vr = nullptr, *vz = nullptr, *vp = nullptr, *vq = nullptr, *vt = nullptr;
+    // the V-cycle in its precision (FP32 with relax_fp32, else FP64): 1-D matrices, cell
+    // coefficients and coarse inverse in that precision (FP32 copies; the FP64 ones otherwise),
+    // the cycle's iterate z1 and residual t (3 n each), the coarse vectors (3 nc each)
+    bool fp32 = false;
+    float *M1f = nullptr, *coeff = nullptr, *A0f = nullptr;
+    void *cz = nullptr, *ct = nullptr, *cc0 = nullptr, *cc1 = nullptr;
     Exec ex() const { return Exec{stream, gate, Tuning{}}; }
     template <typename T>
     T *dalloc(size_t count) {
@@ -1026,9 +1032,9 @@ struct vsr_elasticity {
 
 namespace {
 
-// y = A x for the 3-component vector (x, y: 3 n, component after component)
+// y = A x for the 3-component vector (x, y: 3 n, component after component), FP64
 void el_op(vsr_elasticity *L, const double *x, double *y) {
-    launch_op_elastic_box(L->d, L->M1, L->coef, L->mu, L->lam, x, L->E, L->ex());
+    launch_op_elastic_box<double>(L->d, L->M1, L->coef, L->mu, L->lam, x, L->E, L->ex());
     launch_gather_components<double>(L->d, 3, L->E, y, L->ex());
 }
 
@@ -1038,15 +1044,29 @@ double el_dot(vsr_elasticity *L, const double *x, const double *y) {
     return read_scalar(P, SC_TMP);
 }
 
-// z_c = S_c r_c: component c's scalar FDM vertex-star relaxation (undamped), in its working
-// precision, written to z in FP64 by the prolongation.  The three are independent and run
-// concurrently, one stream each.
+template <typename T> const T *el_m1(const vsr_elasticity *L);
+template <> const double *el_m1<double>(const vsr_elasticity *L) { return L->M1; }
+template <> const float *el_m1<float>(const vsr_elasticity *L) { return L->M1f; }
+template <typename T> const T *el_coef(const vsr_elasticity *L);
+template <> const double *el_coef<double>(const vsr_elasticity *L) { return L->coef; }
+template <> const float *el_coef<float>(const vsr_elasticity *L) { return L->coeff; }
+template <typename T> const T *el_a0(const vsr_elasticity *L);
+template <> const double *el_a0<double>(const vsr_elasticity *L) { return L->A0inv; }
+template <> const float *el_a0<float>(const vsr_elasticity *L) { return L->A0f; }
+
+// t = r - A z in the cycle's precision T (r in FP64); the element vector E holds T values here
 template <typename T>
-void el_relax_component(vsr_problem *P, const double *r, double *z) {
-    relax_apply<T, double>(P, r, (T *)P->z1, T(1), T(0), z);
+void el_residual(vsr_elasticity *L, const double *r, const T *z, T *t) {
+    T *E = (T *)L->E;
+    launch_op_elastic_box<T>(L->d, el_m1<T>(L), el_coef<T>(L), (T)L->mu, (T)L->lam, z, E, L->ex());
+    launch_gather_components<T>(L->d, 3, E, t, L->ex(), r);
 }
 
-void el_relax(vsr_elasticity *L, const double *r, double *z) {
+// out_c = alpha S_c in_c + beta out_c for the three components (with out64: also written in
+// FP64): component c's scalar FDM vertex-star relaxation in its working precision T.  The
+// three are independent and run concurrently, one stream each.
+template <typename T, typename Tin>
+void el_relax(vsr_elasticity *L, const Tin *in, T *out, T alpha, T beta, double *out64) {
     L->per_component([&](int c, hipStream_t s) {
         vsr_problem *P = L->comp[c];
         const hipStream_t keep = P->stream;
@@ -1054,8 +1074,7 @@ void el_relax(vsr_elasticity *L, const double *r, double *z) {
         P->stream = s;
         P->gate = L->gate;
         try {
-            if (P->fp32) el_relax_component<float>(P, r + c * L->n, z + c * L->n);
-            else el_relax_component<double>(P, r + c * L->n, z + c * L->n);
+            relax_apply<T, Tin>(P, in + c * L->n, out + c * L->n, alpha, beta, out64 ? out64 + c * L->n : nullptr);
         } catch (...) {
             P->stream = keep;
             P->gate = keep_gate;
@@ -1066,39 +1085,43 @@ void el_relax(vsr_elasticity *L, const double *r, double *z) {
     });
 }
 
-// z = P A0^{-1} P^T r with Q1 in every component
-void el_coarse(vsr_elasticity *L, const double *r, double *z) {
+// out = alpha P A0^{-1} P^T in + beta out with Q1 in every component (with out64: also in
+// FP64); the three restrictions and the three prolongations are one launch each
+template <typename T, typename Tin>
+void el_coarse(vsr_elasticity *L, const Tin *in, T *out, T alpha, T beta, double *out64) {
     if (L->nc == 0) {
-        launch_fill<double>(3 * L->n, z, 0.0, L->ex());
+        if (beta == T(0)) launch_fill<T>(3 * L->n, out, T(0), L->ex());
+        if (out64) launch_axpby_to_double<T>(3 * L->n, 1.0, out, 0.0, out64, L->ex());
         return;
     }
     vsr_problem *P = L->comp[0];
     const int Ld[3] = {L->d.Lx, L->d.Ly, L->d.Lz}, NC[3] = {L->d.nx, L->d.ny, L->d.nz};
-    // the three components' restrictions in one launch, the coupled solve, the three prolongations
-    launch_transfer<double, double>(XFER_COARSE_RESTRICT, L->d.p, NC, Ld, P->cdim, P->xm64[XFER_COARSE_RESTRICT], r,
-                                    L->c0, 1.0, 0.0, L->ex(), nullptr, nullptr, nullptr, 0, 3);
-    launch_dense_gemv<double>(3 * L->nc, L->A0inv, L->c0, L->c1, 1.0, 0.0, L->ex());
-    launch_transfer<double, double>(XFER_COARSE_PROLONG, L->d.p, NC, P->cdim, Ld, P->xm64[XFER_COARSE_PROLONG], L->c1,
-                                    z, 1.0, 0.0, L->ex(), nullptr, nullptr, nullptr, 0, 3);
+    T *c0 = (T *)L->cc0, *c1 = (T *)L->cc1;
+    launch_transfer<Tin, T>(XFER_COARSE_RESTRICT, L->d.p, NC, Ld, P->cdim, xm<T>(P, XFER_COARSE_RESTRICT), in, c0, T(1),
+                            T(0), L->ex(), nullptr, nullptr, nullptr, 0, 3);
+    launch_dense_gemv<T>(3 * L->nc, el_a0<T>(L), c0, c1, T(1), T(0), L->ex());
+    launch_transfer<T, T>(XFER_COARSE_PROLONG, L->d.p, NC, P->cdim, Ld, xm<T>(P, XFER_COARSE_PROLONG), c1, out, alpha,
+                          beta, L->ex(), out64, nullptr, nullptr, 0, 3);
 }
 
-// mode 0: the hybrid V(1,1) z1 = w S r, z2 = z1 + C (r - A z1), z = z2 + w S (r - A z2);
-// mode 1: S r; mode 2: C r.  r and z must not alias the work vectors vt, vu.
+// z = M r in the cycle's precision T.  mode 0: the hybrid V(1,1) z1 = w S r,
+// z2 = z1 + C (r - A z1), z = z2 + w S (r - A z2); mode 1: S r; mode 2: C r.
+template <typename T>
+void el_precond_t(vsr_elasticity *L, const double *r, double *z, int mode) {
+    T *z1 = (T *)L->cz, *t = (T *)L->ct;
+    const T w = (T)L->omega;
+    if (mode == 1) return el_relax<T, double>(L, r, z1, T(1), T(0), z);
+    if (mode == 2) return el_coarse<T, double>(L, r, z1, T(1), T(0), z);
+    el_relax<T, double>(L, r, z1, w, T(0), nullptr);        // z1 = w S r
+    el_residual<T>(L, r, z1, t);                            // t = r - A z1
+    el_coarse<T, T>(L, t, z1, T(1), T(1), nullptr);         // z2 = z1 + C t
+    el_residual<T>(L, r, z1, t);                            // t = r - A z2
+    el_relax<T, T>(L, t, z1, w, T(1), z);                   // z = z2 + w S t
+}
+
 void el_precond(vsr_elasticity *L, const double *r, double *z, int mode) {
-    const int64_t N = 3 * L->n;
-    if (mode == 1) return el_relax(L, r, z);
-    if (mode == 2) return el_coarse(L, r, z);
-    double *t = L->vt, *u = L->vu;
-    el_relax(L, r, z);                                                        // z = S r
-    launch_axpby_to_double<double>(N, 0.0, z, L->omega, z, L->ex());          // z1 = w S r
-    el_op(L, z, t);
-    launch_axpby_to_double<double>(N, 1.0, r, -1.0, t, L->ex());              // t = r - A z1
-    el_coarse(L, t, u);
-    launch_axpby_to_double<double>(N, 1.0, u, 1.0, z, L->ex());               // z2
-    el_op(L, z, t);
-    launch_axpby_to_double<double>(N, 1.0, r, -1.0, t, L->ex());              // t = r - A z2
-    el_relax(L, t, u);
-    launch_axpby_to_double<double>(N, L->omega, u, 1.0, z, L->ex());          // z = z2 + w S t
+    if (L->fp32) el_precond_t<float>(L, r, z, mode);
+    else el_precond_t<double>(L, r, z, mode);
 }
 
 // CG-Lanczos on S A from the splitmix64 start vector (the scalar estimate's recipe, 3 n entries)
@@ -1107,7 +1130,7 @@ void el_damping(vsr_elasticity *L, int steps, uint64_t seed) {
     std::vector<double> h(N);
     for (int64_t i = 0; i < N; ++i) h[i] = (double)(splitmix64_at(seed, (uint64_t)i) >> 11) * 0x1.0p-53 * 2.0 - 1.0;
     VSR_HIP(hipMemcpy(L->vr, h.data(), N * sizeof(double), hipMemcpyHostToDevice));
-    el_relax(L, L->vr, L->vz);
+    el_precond(L, L->vr, L->vz, 1);
     double rz = el_dot(L, L->vr, L->vz);
     const double rz0 = rz;
     launch_axpby_to_double<double>(N, 1.0, L->vz, 0.0, L->vp, L->ex());
@@ -1117,7 +1140,7 @@ void el_damping(vsr_elasticity *L, int steps, uint64_t seed) {
         const double alpha = rz / el_dot(L, L->vp, L->vq);
         if (!(alpha > 0) || !std::isfinite(alpha)) throw Error(VSR_ENOCONV, "Lanczos breakdown");
         launch_axpby_to_double<double>(N, -alpha, L->vq, 1.0, L->vr, L->ex());
-        el_relax(L, L->vr, L->vz);
+        el_precond(L, L->vr, L->vz, 1);
         const double rzn = el_dot(L, L->vr, L->vz);
         alphas.push_back(alpha);
         betas.push_back(rzn / rz);
@@ -1683,7 +1706,21 @@ vsr_status vsr_elasticity_setup(const vsr_mesh *mesh, int32_t p, double mu, doub
         L->vp = L->dalloc<double>(N);
         L->vq = L->dalloc<double>(N);
         L->vt = L->dalloc<double>(N);
-        L->vu = L->dalloc<double>(N);
+        // the V-cycle's precision follows the component relaxations'
+        L->fp32 = o.relax_fp32 != 0;
+        const size_t tsz = L->fp32 ? sizeof(float) : sizeof(double);
+        auto upload_f = [&](const std::vector<double> &v) {
+            std::vector<float> f(v.begin(), v.end());
+            float *d = L->dalloc<float>(f.size());
+            VSR_HIP(hipMemcpy(d, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
+            return d;
+        };
+        if (L->fp32) {
+            L->M1f = upload_f(M1);
+            L->coeff = upload_f(coef);
+        }
+        L->cz = L->dalloc<char>(N * tsz);
+        L->ct = L->dalloc<char>(N * tsz);
         // vector Q1 coarse space, exact solve
         L->nc = (nx - 1) * (ny - 1) * (nz - 1);
         if (L->nc > 0) {
@@ -1692,8 +1729,9 @@ vsr_status vsr_elasticity_setup(const vsr_mesh *mesh, int32_t p, double mu, doub
             std::vector<double> A0i = spd_inverse(3 * L->nc, A0);
             L->A0inv = L->dalloc<double>(A0i.size());
             VSR_HIP(hipMemcpy(L->A0inv, A0i.data(), A0i.size() * sizeof(double), hipMemcpyHostToDevice));
-            L->c0 = L->dalloc<double>(3 * L->nc);
-            L->c1 = L->dalloc<double>(3 * L->nc);
+            if (L->fp32) L->A0f = upload_f(A0i);
+            L->cc0 = L->dalloc<char>(3 * L->nc * tsz);
+            L->cc1 = L->dalloc<char>(3 * L->nc * tsz);
         }
         if (o.omega > 0) L->omega = o.omega;
         else el_damping(L.get(), o.lanczos_steps > 0 ? o.lanczos_steps : 20, o.seed);

@@ -1,4 +1,4 @@
-// Primal linear elasticity operator on axis-aligned cells (Sec. 3.1), FP64.
+// Primal linear elasticity operator on axis-aligned cells (Sec. 3.1), FP64 or FP32.
 //
 // a(v, u) = int 2 mu eps(v) : eps(u) + lam div v div u.  On a box cell every block A_cd of
 // the component blocks is a sum of Kronecker products of the 1-D reference matrices
@@ -47,13 +47,13 @@ constexpr int term_mat(int axis, int C, int D, int s) {
 constexpr bool has_term(int C, int D, int s) { return C == D || s < 2; }
 
 // Planes k0 <= k < k0 + KH (below N1) of X = (I x I x Mx) xs, for column (j, i)
-template <int N1, int KH>
-__device__ __forceinline__ void x_half(const double *Mx, const double *xs, double *X, int j, int i, int k0) {
+template <typename T, int N1, int KH>
+__device__ __forceinline__ void x_half(const T *Mx, const T *xs, T *X, int j, int i, int k0) {
 #pragma unroll
     for (int kk = 0; kk < KH; ++kk) {
         const int k = k0 + kk;
         if (k < N1) {
-            double s = 0;
+            T s = 0;
 #pragma unroll
             for (int ii = 0; ii < N1; ++ii) s += Mx[i * N1 + ii] * xs[(k * N1 + j) * N1 + ii];
             X[(k * N1 + j) * N1 + i] = s;
@@ -62,13 +62,13 @@ __device__ __forceinline__ void x_half(const double *Mx, const double *xs, doubl
 }
 
 // The same planes of Yv = (I x My x I) X
-template <int N1, int KH>
-__device__ __forceinline__ void y_half(const double *My, const double *X, double *Yv, int j, int i, int k0) {
+template <typename T, int N1, int KH>
+__device__ __forceinline__ void y_half(const T *My, const T *X, T *Yv, int j, int i, int k0) {
 #pragma unroll
     for (int kk = 0; kk < KH; ++kk) {
         const int k = k0 + kk;
         if (k < N1) {
-            double s = 0;
+            T s = 0;
 #pragma unroll
             for (int jj = 0; jj < N1; ++jj) s += My[j * N1 + jj] * X[(k * N1 + jj) * N1 + i];
             Yv[(k * N1 + j) * N1 + i] = s;
@@ -77,17 +77,16 @@ __device__ __forceinline__ void y_half(const double *My, const double *X, double
 }
 
 // y[kk] += w ((Mz x I x I) Yv)[k0 + kk] for column (j, i)
-template <int N1, int KH>
-__device__ __forceinline__ void z_half(const double *Mz, const double *Yv, int j, int i, int k0, double w,
-                                       double (&y)[KH]) {
-    double Yc[N1];
+template <typename T, int N1, int KH>
+__device__ __forceinline__ void z_half(const T *Mz, const T *Yv, int j, int i, int k0, T w, T (&y)[KH]) {
+    T Yc[N1];
 #pragma unroll
     for (int kk = 0; kk < N1; ++kk) Yc[kk] = Yv[(kk * N1 + j) * N1 + i];
 #pragma unroll
     for (int kk = 0; kk < KH; ++kk) {
         const int k = k0 + kk;
         if (k < N1) {
-            double s = 0;
+            T s = 0;
 #pragma unroll
             for (int m = 0; m < N1; ++m) s += Mz[k * N1 + m] * Yc[m];
             y[kk] += w * s;
@@ -96,11 +95,11 @@ __device__ __forceinline__ void z_half(const double *Mz, const double *Yv, int j
 }
 
 // X = (I x I x Mx) xs for the group's columns
-template <int N1>
-__device__ __forceinline__ void x_pass(const double *Mx, const double *xs, double *X, int j, int i) {
+template <typename T, int N1>
+__device__ __forceinline__ void x_pass(const T *Mx, const T *xs, T *X, int j, int i) {
 #pragma unroll
     for (int k = 0; k < N1; ++k) {
-        double s = 0;
+        T s = 0;
 #pragma unroll
         for (int ii = 0; ii < N1; ++ii) s += Mx[i * N1 + ii] * xs[(k * N1 + j) * N1 + ii];
         X[(k * N1 + j) * N1 + i] = s;
@@ -108,52 +107,51 @@ __device__ __forceinline__ void x_pass(const double *Mx, const double *xs, doubl
 }
 
 // y += w (Mz x My x I) X for thread (j, i)'s z-column, in registers
-template <int N1>
-__device__ __forceinline__ void yz_pass(const double *My, const double *Mz, const double *X, int j, int i, double w,
-                                        double (&y)[N1]) {
-    double Y[N1];
+template <typename T, int N1>
+__device__ __forceinline__ void yz_pass(const T *My, const T *Mz, const T *X, int j, int i, T w, T (&y)[N1]) {
+    T Y[N1];
 #pragma unroll
     for (int k = 0; k < N1; ++k) {
-        double s = 0;
+        T s = 0;
 #pragma unroll
         for (int jj = 0; jj < N1; ++jj) s += My[j * N1 + jj] * X[(k * N1 + jj) * N1 + i];
         Y[k] = s;
     }
 #pragma unroll
     for (int k = 0; k < N1; ++k) {
-        double s = 0;
+        T s = 0;
 #pragma unroll
         for (int kk = 0; kk < N1; ++kk) s += Mz[k * N1 + kk] * Y[kk];
         y[k] += w * s;
     }
 }
 
-template <int P>
+template <typename T, int P>
 __global__ void __launch_bounds__(3 * el_group(P))
-    k_op_elastic_box(const double *__restrict__ gate, Dims d, const double *__restrict__ M1, const double *__restrict__ coef,
-                     double mu, double lam, const double *__restrict__ x, double *__restrict__ E) {
+    k_op_elastic_box(const double *__restrict__ gate, Dims d, const T *__restrict__ M1, const T *__restrict__ coef, T mu,
+                     T lam, const T *__restrict__ x, T *__restrict__ E) {
     if (gated(gate)) return;
     constexpr int N1 = P + 1, N2 = N1 * N1, N3 = N2 * N1, NG = el_group(P), H = el_halves(P);
     constexpr int KH = (N1 + H - 1) / H;   // z planes per thread
     // A, B, C, C^T: [m][row = test][col = trial], in LDS (at p = 15 with the cell blocks 139 KB)
-    __shared__ double sM[4 * N2];
-    __shared__ double xs[N3];                   // the input component's cell block [k][j][i]
-    __shared__ double Xs[(H == 2 ? 6 : 3) * N3];   // per group: after the x (and the y) contraction
+    __shared__ T sM[4 * N2];
+    __shared__ T xs[N3];                        // the input component's cell block [k][j][i]
+    __shared__ T Xs[(H == 2 ? 6 : 3) * N3];     // per group: after the x (and the y) contraction
     const int tid = threadIdx.x;
     const int g = tid / NG, lt = tid - g * NG;
     const int64_t e = blockIdx.x;
     const int ex = (int)(e % d.nx), ey = (int)((e / d.nx) % d.ny), ez = (int)(e / ((int64_t)d.nx * d.ny));
     for (int t = tid; t < 4 * N2; t += blockDim.x) sM[t] = M1[t];
-    const double *cf = coef + e * kElasticCoef;
-    double *X = Xs + g * N3;
-    double *Yv = Xs + (3 + g) * N3;   // used only with two threads per column
+    const T *cf = coef + e * kElasticCoef;
+    T *X = Xs + g * N3;
+    T *Yv = Xs + (3 + g) * N3;   // used only with two threads per column
     const bool col = lt < H * N2;
     const int h = lt / N2, c2 = lt - h * N2;   // half, column
     const int j = c2 / N1, i = c2 % N1, k0 = h * KH;
     const int64_t n = (int64_t)d.Lx * d.Ly * d.Lz;
-    double y[KH];
+    T y[KH];
 #pragma unroll
-    for (int k = 0; k < KH; ++k) y[k] = 0.0;
+    for (int k = 0; k < KH; ++k) y[k] = T(0);
     // Input component D: load it, then terms 0 and 1 of every group and term 2 of group D.
     // Barriers: after the load (xs ready), after each contraction pass (its slab ready), and
     // after the last pass of a term (the slabs free again); the last term of a component also
@@ -164,27 +162,27 @@ __global__ void __launch_bounds__(3 * el_group(P))
         for (int t = tid; t < N3; t += blockDim.x) {
             const int kk = t / N2, jj = (t / N1) % N1, ii = t % N1;
             const int K = P * ez + kk, J = P * ey + jj, I = P * ex + ii;
-            xs[t] = is_free(d, K, J, I) ? x[D * n + free_index(d, K, J, I)] : 0.0;
+            xs[t] = is_free(d, K, J, I) ? x[D * n + free_index(d, K, J, I)] : T(0);
         }
         __syncthreads();
 #pragma unroll 1
         for (int S = 0; S < 3; ++S) {
             // group g's term S on component D (g is uniform per wavefront)
             const bool active = col && has_term(g, D, S);
-            const double *Mx = sM + term_mat(0, g, D, S) * N2, *My = sM + term_mat(1, g, D, S) * N2,
-                         *Mz = sM + term_mat(2, g, D, S) * N2;
-            const double w = g == D ? cf[3 * D + S] : (S == 0 ? mu : lam) * cf[9 + g + D - 1];   // s_xy, s_xz, s_yz at 9..11
+            const T *Mx = sM + term_mat(0, g, D, S) * N2, *My = sM + term_mat(1, g, D, S) * N2,
+                    *Mz = sM + term_mat(2, g, D, S) * N2;
+            const T w = g == D ? cf[3 * D + S] : (S == 0 ? mu : lam) * cf[9 + g + D - 1];   // s_xy, s_xz, s_yz at 9..11
             if constexpr (H == 2) {
-                if (active) x_half<N1, KH>(Mx, xs, X, j, i, k0);
+                if (active) x_half<T, N1, KH>(Mx, xs, X, j, i, k0);
                 __syncthreads();
-                if (active) y_half<N1, KH>(My, X, Yv, j, i, k0);
+                if (active) y_half<T, N1, KH>(My, X, Yv, j, i, k0);
                 __syncthreads();
-                if (active) z_half<N1, KH>(Mz, Yv, j, i, k0, w, y);
+                if (active) z_half<T, N1, KH>(Mz, Yv, j, i, k0, w, y);
                 __syncthreads();
             } else {
-                if (active) x_pass<N1>(Mx, xs, X, j, i);
+                if (active) x_pass<T, N1>(Mx, xs, X, j, i);
                 __syncthreads();
-                if (active) yz_pass<N1>(My, Mz, X, j, i, w, y);
+                if (active) yz_pass<T, N1>(My, Mz, X, j, i, w, y);
                 __syncthreads();
             }
         }
@@ -202,14 +200,19 @@ __global__ void __launch_bounds__(3 * el_group(P))
 
 using namespace dev;
 
-void launch_op_elastic_box(const Dims &d, const double *M1, const double *coef, double mu, double lam, const double *x,
-                           double *E, const Exec &e) {
+template <typename T>
+void launch_op_elastic_box(const Dims &d, const T *M1, const T *coef, T mu, T lam, const T *x, T *E, const Exec &e) {
     const int64_t ncell = (int64_t)d.nx * d.ny * d.nz;
 #define CALL(P)                                                                                                   \
-    hipLaunchKernelGGL((k_op_elastic_box<P>), dim3((unsigned)ncell), dim3(3 * el_group(P)), 0, e.s, e.gate, d, M1, coef, \
-                       mu, lam, x, E)
+    hipLaunchKernelGGL((k_op_elastic_box<T, P>), dim3((unsigned)ncell), dim3(3 * el_group(P)), 0, e.s, e.gate, d, M1,  \
+                       coef, mu, lam, x, E)
     VSR_P_SWITCH(d.p, CALL)
 #undef CALL
 }
+
+template void launch_op_elastic_box<double>(const Dims &, const double *, const double *, double, double, const double *,
+                                            double *, const Exec &);
+template void launch_op_elastic_box<float>(const Dims &, const float *, const float *, float, float, const float *,
+                                           float *, const Exec &);
 
 }  // namespace vsr

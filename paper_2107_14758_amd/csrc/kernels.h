@@ -76,9 +76,10 @@ template <typename T>
 void launch_gather(const Dims &d, int slots, const T *E, const double *r, T *out, const Exec &e,
                    const double *dotv = nullptr, double *partials = nullptr);
 // ncomp independent gathers in one launch: out + c n = the sum of the single-slot element
-// vector E + c ncell (p+1)^3 per free node, for c < ncomp (n = free nodes).
+// vector E + c ncell (p+1)^3 per free node (with r: r + c n minus that sum), for c < ncomp
+// (n = free nodes).
 template <typename T>
-void launch_gather_components(const Dims &d, int ncomp, const T *E, T *out, const Exec &e);
+void launch_gather_components(const Dims &d, int ncomp, const T *E, T *out, const Exec &e, const double *r = nullptr);
 int64_t gather_blocks(const Dims &d);
 // Adds nb partial sums in a fixed order and applies them to scal by mode (see launch_dot).
 void launch_finalize(int nb, const double *partials, double *scal, int mode, double *mirror, const Exec &e);
@@ -99,7 +100,7 @@ void launch_load_vector(const Dims &d, const double *IDq, const double *wdet, co
 // star boxes ((2p-1)^3 per mesh vertex) and the prolongation reads their assembled sum (the
 // scatter-add of Sec. 2.5) instead of a lattice vector; 2 = the same with only the interior
 // vertices' stars; 0 = a lattice vector.  ncomp > 1: that many independent vectors one after
-// another in `in` and in `out` (lattice input only, no out64, dotv or partials), one launch.
+// another in `in`, `out` and out64 (lattice input only, no dotv or partials), one launch.
 template <typename Tin, typename T>
 void launch_transfer(int kind, int p, const int ncell[3], const int in_dims[3], const int out_dims[3], const T *M,
                      const Tin *in, T *out, T alpha, T beta, const Exec &e, double *out64 = nullptr,
@@ -129,13 +130,13 @@ void launch_patch_all(const Dims &d, const PatchArgs &a, int n_int, const int *v
 // kFusedScatterMaxP; up to it the prolongation reads the star boxes itself).
 template <typename T>
 void launch_patch_assemble(const Dims &d, const T *U, T *zF, const Exec &e);
-// Primal linear elasticity on axis-aligned cells (Sec. 3.1), FP64: the three components'
+// Primal linear elasticity on axis-aligned cells (Sec. 3.1), FP64 or FP32: the three components'
 // cell results of y = A x into E (three element vectors of ncell (p+1)^3, one per output
 // component; launch_gather_components sums them).  M1: the 1-D matrices A, B, C, C^T ((p+1)^2 each,
 // row = test index; C[a][b] = int phi_a' phi_b); coef: 12 per cell (k[c][a] at 3c + a, then
 // s_xy, s_xz, s_yz); x: 3 n values, component after component.
-void launch_op_elastic_box(const Dims &d, const double *M1, const double *coef, double mu, double lam, const double *x,
-                           double *E, const Exec &e);
+template <typename T>
+void launch_op_elastic_box(const Dims &d, const T *M1, const T *coef, T mu, T lam, const T *x, T *E, const Exec &e);
 
 constexpr int kFusedScatterMaxP = 7;
 // Length of U for launch_patch_all.

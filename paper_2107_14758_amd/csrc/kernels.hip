@@ -467,9 +467,11 @@ __global__ void __launch_bounds__(XB) k_gather(const double *__restrict__ gate, 
                                                 const T *__restrict__ rT) {
     if (gated(gate)) return;
     constexpr int N1 = P + 1, N3 = N1 * N1 * N1;
-    if (gridDim.y > 1) {   // independent components (r, rT, dotv unused): E and out per blockIdx.y
+    if (gridDim.y > 1) {   // independent components (rT, dotv unused): E, r and out per blockIdx.y
+        const int64_t nfree = (int64_t)d.Lx * d.Ly * d.Lz;
         E += (int64_t)blockIdx.y * slots * d.nx * d.ny * d.nz * N3;
-        out += (int64_t)blockIdx.y * d.Lx * d.Ly * d.Lz;
+        out += blockIdx.y * nfree;
+        if (r != nullptr) r += blockIdx.y * nfree;
     }
     const int xblocks = (d.Lx + XB - 1) / XB;
     const int line = (int)(blockIdx.x / xblocks), I0 = (int)(blockIdx.x - (int64_t)line * xblocks) * XB + threadIdx.x + 1;
@@ -830,10 +832,10 @@ void launch_gather(const Dims &d, int slots, const T *E, const double *r, T *out
 }
 
 template <typename T>
-void launch_gather_components(const Dims &d, int ncomp, const T *E, T *out, const Exec &e) {
+void launch_gather_components(const Dims &d, int ncomp, const T *E, T *out, const Exec &e, const double *r) {
 #define CALL(P)                                                                                                   \
-    hipLaunchKernelGGL((k_gather<T, P>), dim3(line_blocks(d), (unsigned)ncomp), dim3(XB), 0, e.s, e.gate, d, 1, E,          \
-                       (const double *)nullptr, out, (const double *)nullptr, (double *)nullptr, (const T *)nullptr)
+    hipLaunchKernelGGL((k_gather<T, P>), dim3(line_blocks(d), (unsigned)ncomp), dim3(XB), 0, e.s, e.gate, d, 1, E, r, \
+                       out, (const double *)nullptr, (double *)nullptr, (const T *)nullptr)
     VSR_P_SWITCH(d.p, CALL)
 #undef CALL
 }
@@ -947,7 +949,7 @@ int launch_axpby_to_double(int64_t n, double a, const T *x, double b, double *y,
     template void launch_gather<T>(const Dims &, int, const T *, const double *, T *, const Exec &, const double *, \
                                    double *);                                                                    \
     template void launch_gather_sub<T>(const Dims &, const T *, const T *, T *, const Exec &);                   \
-    template void launch_gather_components<T>(const Dims &, int, const T *, T *, const Exec &);                  \
+    template void launch_gather_components<T>(const Dims &, int, const T *, T *, const Exec &, const double *);  \
     template void launch_patch_assemble<T>(const Dims &, const T *, T *, const Exec &);                   \
     template void launch_op_kron_restrict<T>(const Dims &, int, const T *, const T *, const T *, T *, const Exec &); \
     template void launch_coarse_gather<T>(const Dims &, const T *, const T *, T *, const Exec &);              \

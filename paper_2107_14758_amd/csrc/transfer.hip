@@ -88,9 +88,10 @@ __global__ void __launch_bounds__(XFER_THREADS)
                T *__restrict__ out, T alpha, T beta, double *__restrict__ out64, const double *__restrict__ dotv,
                double *__restrict__ partials, int box_mode) {
     if (gated(gate)) return;
-    if (gridDim.y > 1) {   // independent components (lattice input, no out64 / dot): blockIdx.y selects one
+    if (gridDim.y > 1) {   // independent components (lattice input, no dot): blockIdx.y selects one
         in += blockIdx.y * (int64_t)ix * iy * iz;
         out += blockIdx.y * (int64_t)ox * oy * oz;
+        if (out64 != nullptr) out64 += blockIdx.y * (int64_t)ox * oy * oz;
     }
     constexpr int KX = K + (CX - 1) * IS, KY = K + (CY - 1) * IS;   // window extents along x and y
     constexpr int AX = CX * OA, AY = CY * OA;                       // outputs along x and y
@@ -237,8 +238,8 @@ template <typename Tin, typename T>
 void launch_transfer(int kind, int p, const int ncell[3], const int in_dims[3], const int out_dims[3], const T *M,
                      const Tin *in, T *out, T alpha, T beta, const Exec &e, double *out64, const double *dotv,
                      double *partials, int box_mode, int ncomp) {
-    if (ncomp < 1 || (ncomp > 1 && (out64 != nullptr || dotv != nullptr || partials != nullptr || box_mode != 0)))
-        throw Error(VSR_EINVAL, "transfer components: lattice input without FP64 copy or dot only");
+    if (ncomp < 1 || (ncomp > 1 && (dotv != nullptr || partials != nullptr || box_mode != 0)))
+        throw Error(VSR_EINVAL, "transfer components: lattice input without a dot only");
     const int nc = ncell[0] * ncell[1] * ncell[2];
     if (nc == 0 || (int64_t)out_dims[0] * out_dims[1] * out_dims[2] == 0) {
         const int nb = transfer_blocks(kind, p, ncell);

@@ -1,7 +1,7 @@
 """GPU parity of primal linear elasticity with the SDC relaxation (Sec. 3.1) against the
 oracle: operator, load vector, the SDC relaxation, the vector Q1 coarse correction, the full
-V(1,1), the damping estimate and PCG (FP64 to 1e-12 / 1e-10, FP32 relaxation to 1e-6), on
-uniform and stretched tensor grids of boxes."""
+V(1,1), the damping estimate and PCG (FP64 to 1e-12 / 1e-10; the FP32 V-cycle to 1e-5 per
+apply and its PCG solution to 1e-6), on uniform and stretched tensor grids of boxes."""
 import numpy as np
 import pytest
 
@@ -84,6 +84,27 @@ def test_operator_load_and_relaxations(vsr, name, shape, p, stretched, mu, lam):
         err = np.abs(host(z) - ref).max() / np.abs(ref).max()
         say(f"  mode {mode}: max-abs {err:.2e}")
         assert close(host(z), ref, 1e-11)
+    g.close()
+
+
+@pytest.mark.parametrize("name,shape,p,stretched,mu,lam", [CASES[1], CASES[3]])
+def test_fp32_cycle_per_apply(vsr, name, shape, p, stretched, mu, lam):
+    """The V-cycle in FP32 (component relaxations, the two inner operator applies and
+    residuals, the coarse restriction, solve and prolongation): each mode within 1e-5 of the
+    oracle's FP64 result, max-abs error over max |ref|."""
+    say("case", name)
+    V = grid(shape, stretched)
+    d = Discretization(V, p)
+    el = OracleElasticity(d, mu, lam)
+    s = SDCSolver(el, setup_1d(p), omega=0.3)
+    g = vsr.Elasticity(V, p, mu, lam, omega=0.3, relax_fp32=True)
+    r = np.random.default_rng(11).uniform(-1, 1, el.n)
+    for mode, ref in ((1, s.relax(r)), (2, s.coarse(r)), (0, s.precondition(r))):
+        z = torch.zeros(el.n, dtype=torch.float64, device="cuda")
+        g.apply_relaxation(dev(r), z, mode)
+        err = np.abs(host(z) - ref).max() / np.abs(ref).max()
+        say(f"  mode {mode}: max-abs {err:.2e}")
+        assert err <= 1e-5
     g.close()
 
 
