@@ -56,7 +56,7 @@ CASES = [("uniform_2x2x2_p2", (2, 2, 2), 2, False, 1.0, 0.0),
          ("stretched_3x2x4_p3", (3, 2, 4), 3, True, 1.3, 2.9),
          ("stretched_2x3x2_p5", (2, 3, 2), 5, True, 0.7, 10.0),
          ("uniform_2x2x3_p7", (2, 2, 3), 7, False, 1.0, 1.0),
-         ("stretched_2x3x2_p15", (2, 3, 2), 15, True, 1.1, 4.0)]   # 1-D matrices read from global memory
+         ("stretched_2x3x2_p15", (2, 3, 2), 15, True, 1.1, 4.0)]   # one thread per column in the operator
 
 
 @pytest.mark.parametrize("name,shape,p,stretched,mu,lam", CASES)
@@ -87,7 +87,7 @@ def test_operator_load_and_relaxations(vsr, name, shape, p, stretched, mu, lam):
     g.close()
 
 
-@pytest.mark.parametrize("name,shape,p,stretched,mu,lam", [CASES[1], CASES[3]])
+@pytest.mark.parametrize("name,shape,p,stretched,mu,lam", [CASES[1], CASES[3], CASES[4]])
 def test_fp32_cycle_per_apply(vsr, name, shape, p, stretched, mu, lam):
     """The V-cycle in FP32 (component relaxations, the two inner operator applies and
     residuals, the coarse restriction, solve and prolongation): each mode within 1e-5 of the
