@@ -168,8 +168,7 @@ vsr_status vsr_elasticity_damping(const vsr_elasticity *el, double *omega, doubl
  * vsr_pcg_solve, without stagnation handling.  Returns VSR_ENOCONV at max_iterations and
  * VSR_EINVAL for a non-finite b.  The iterations run on the library's own stream, forked from
  * and joined back to the options' stream, as replays of one recorded iteration (kept for the
- * next solve into the same x_dev), the three component relaxations on two more streams; calls
- * on one object must not overlap. */
+ * next solve into the same x_dev); calls on one object must not overlap. */
 vsr_status vsr_elasticity_pcg_solve(vsr_elasticity *el, const double *b_dev, double *x_dev, double rtol,
                                     vsr_solve_info *info);
 void vsr_elasticity_destroy(vsr_elasticity *el);

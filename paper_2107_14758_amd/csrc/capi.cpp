@@ -65,6 +65,7 @@ struct vsr_problem {
     float *AB32 = nullptr, *IDq32 = nullptr, *mu32 = nullptr, *geo32 = nullptr;
     // relaxation data in the cycle precision
     void *mu_sur = nullptr, *lam = nullptr, *afc = nullptr, *fint = nullptr, *fbnd = nullptr;
+    int64_t mu_len = 0, fint_len = 0, fbnd_len = 0;   // elements of mu_sur, fint, fbnd
     int n_int = 0, n_bnd = 0;
     int *verts = nullptr, *bdesc = nullptr, *fidx = nullptr;   // fidx: factor of each interior star
     int64_t *boff = nullptr;
@@ -138,6 +139,17 @@ struct vsr_problem {
     T *upload_as(const std::vector<double> &v) {
         std::vector<T> c(v.begin(), v.end());
         return upload(c);
+    }
+    // Move `bytes` of device data from *slot to dst (device memory the caller owns) and free
+    // the old allocation: *slot then points at dst.
+    void move_to(void **slot, void *dst, size_t bytes) {
+        VSR_HIP(hipMemcpy(dst, *slot, bytes, hipMemcpyDeviceToDevice));
+        auto it = std::find(allocs.begin(), allocs.end(), *slot);
+        if (it != allocs.end()) {
+            (void)hipFree(*it);
+            allocs.erase(it);
+        }
+        *slot = dst;
     }
 };
 
@@ -659,6 +671,9 @@ void upload_patch_data(vsr_problem *P, const PatchSet &S, const std::vector<doub
     P->afc = P->upload_as<T>(afc);
     P->fint = P->upload_as<T>(S.interior_factor);
     P->fbnd = P->upload_as<T>(S.boundary_factor);
+    P->mu_len = (int64_t)mu_sur.size();
+    P->fint_len = (int64_t)S.interior_factor.size();
+    P->fbnd_len = (int64_t)S.boundary_factor.size();
 }
 
 }  // namespace
@@ -971,8 +986,7 @@ struct vsr_elasticity {
     double mu = 0, lam = 0;
     double omega = 1, lmin = 0, lmax = 0, setup_seconds = 0;
     hipStream_t stream = nullptr;
-    hipStream_t side[2] = {nullptr, nullptr};   // components 1 and 2 run their relaxations here
-    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t fork = nullptr;                  // joins the solve's own stream to the caller's and back
     hipEvent_t it_ev[2] = {nullptr, nullptr};   // end of the last two iterations
     hipStream_t origin = nullptr;               // the solve's own stream (graph capture needs one)
     hipGraph_t graph = nullptr;                 // one PCG iteration, recorded for the output vector graph_x
@@ -987,6 +1001,7 @@ struct vsr_elasticity {
     // coefficients and coarse inverse in that precision (FP32 copies; the FP64 ones otherwise),
     // the cycle's iterate z1 and residual t (3 n each), the coarse vectors (3 nc each)
     bool fp32 = false;
+    CompStrides cs{};   // the components' patch arrays lie one after another (see the setup)
     float *M1f = nullptr, *coeff = nullptr, *A0f = nullptr;
     void *cz = nullptr, *ct = nullptr, *cc0 = nullptr, *cc1 = nullptr;
     Exec ex() const { return Exec{stream, gate, Tuning{}}; }
@@ -1000,33 +1015,16 @@ struct vsr_elasticity {
     }
     ~vsr_elasticity() {
         if (stream) (void)hipStreamSynchronize(stream);
-        for (hipStream_t s : side)
-            if (s) (void)hipStreamSynchronize(s);
-        for (vsr_problem *c : comp) destroy_problem(c);
-        for (void *p : allocs) (void)hipFree(p);
         if (origin) (void)hipStreamSynchronize(origin);
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
+        for (vsr_problem *c : comp) destroy_problem(c);
+        for (void *p : allocs) (void)hipFree(p);
         if (origin) (void)hipStreamDestroy(origin);
         if (host_done) (void)hipHostFree(host_done);
         for (hipEvent_t e : it_ev)
             if (e) (void)hipEventDestroy(e);
-        for (hipEvent_t e : ev)
-            if (e) (void)hipEventDestroy(e);
-        for (hipStream_t s : side)
-            if (s) (void)hipStreamDestroy(s);
-    }
-    // Run fn(c, stream) for the three components, component 0 on `stream`, 1 and 2 on the side
-    // streams, forked from and joined back to `stream`.
-    template <typename F>
-    void per_component(F &&fn) {
-        VSR_HIP(hipEventRecord(ev[0], stream));
-        for (hipStream_t s : side) VSR_HIP(hipStreamWaitEvent(s, ev[0], 0));
-        for (int c = 0; c < 3; ++c) fn(c, c == 0 ? stream : side[c - 1]);
-        for (int j = 0; j < 2; ++j) {
-            VSR_HIP(hipEventRecord(ev[1 + j], side[j]));
-            VSR_HIP(hipStreamWaitEvent(stream, ev[1 + j], 0));
-        }
+        if (fork) (void)hipEventDestroy(fork);
     }
 };
 
@@ -1064,25 +1062,27 @@ void el_residual(vsr_elasticity *L, const double *r, const T *z, T *t) {
 
 // out_c = alpha S_c in_c + beta out_c for the three components (with out64: also written in
 // FP64): component c's scalar FDM vertex-star relaxation in its working precision T.  The
-// three are independent and run concurrently, one stream each.
+// components' patch data lie one after another, so each phase (the FDM restriction, the patch
+// solves, the scatter-add and prolongation) is one launch over all three.
 template <typename T, typename Tin>
 void el_relax(vsr_elasticity *L, const Tin *in, T *out, T alpha, T beta, double *out64) {
-    L->per_component([&](int c, hipStream_t s) {
-        vsr_problem *P = L->comp[c];
-        const hipStream_t keep = P->stream;
-        const double *keep_gate = P->gate;
-        P->stream = s;
-        P->gate = L->gate;
-        try {
-            relax_apply<T, Tin>(P, in + c * L->n, out + c * L->n, alpha, beta, out64 ? out64 + c * L->n : nullptr);
-        } catch (...) {
-            P->stream = keep;
-            P->gate = keep_gate;
-            throw;
-        }
-        P->stream = keep;
-        P->gate = keep_gate;
-    });
+    vsr_problem *P = L->comp[0];
+    const int Ld[3] = {P->d.Lx, P->d.Ly, P->d.Lz}, NC[3] = {P->d.nx, P->d.ny, P->d.nz};
+    const Exec e{L->stream, L->gate, P->tune};
+    launch_transfer<Tin, T>(XFER_FDM_RESTRICT, P->d.p, NC, Ld, Ld, xm<T>(P, XFER_FDM_RESTRICT), in, (T *)P->rF, T(1),
+                            T(0), e, nullptr, nullptr, nullptr, 0, 3);
+    launch_patch_all<T>(P->d, P->pa, P->n_int, P->verts, P->fidx, (const T *)P->fint, P->n_bnd, P->bdesc, P->boff,
+                        (const T *)P->fbnd, (const T *)P->mu_sur, (const T *)P->lam, (const T *)P->afc, (const T *)P->rF,
+                        (T *)P->U, e, 3, L->cs);
+    if (P->d.p <= kFusedScatterMaxP) {
+        launch_transfer<T, T>(XFER_FDM_PROLONG, P->d.p, NC, Ld, Ld, xm<T>(P, XFER_FDM_PROLONG), (const T *)P->U, out, alpha,
+                              beta, e, out64, nullptr, nullptr, P->opt.interior_patches_only ? 2 : 1, 3);
+    } else {
+        launch_patch_assemble<T>(P->d, (const T *)P->U, (T *)P->zF, e, 3);
+        launch_transfer<T, T>(XFER_FDM_PROLONG, P->d.p, NC, Ld, Ld, xm<T>(P, XFER_FDM_PROLONG), (const T *)P->zF, out, alpha,
+                              beta, e, out64, nullptr, nullptr, 0, 3);
+    }
+    VSR_HIP(hipGetLastError());
 }
 
 // out = alpha P A0^{-1} P^T in + beta out with Q1 in every component (with out64: also in
@@ -1640,8 +1640,7 @@ vsr_status vsr_elasticity_setup(const vsr_mesh *mesh, int32_t p, double mu, doub
         L->mu = mu;
         L->lam = lambda;
         L->stream = (hipStream_t)o.stream;
-        for (hipStream_t &s : L->side) VSR_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
-        for (hipEvent_t &e : L->ev) VSR_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        VSR_HIP(hipEventCreateWithFlags(&L->fork, hipEventDisableTiming));
         for (hipEvent_t &e : L->it_ev) VSR_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         VSR_HIP(hipStreamCreateWithFlags(&L->origin, hipStreamNonBlocking));
         VSR_HIP(hipHostMalloc((void **)&L->host_done, sizeof(double), hipHostMallocMapped | hipHostMallocCoherent));
@@ -1682,6 +1681,28 @@ vsr_status vsr_elasticity_setup(const vsr_mesh *mesh, int32_t p, double mu, doub
         L->d = P0->d;
         L->n = P0->n;
         L->ncell = ncell;
+        // the three components' patch arrays (factors, scalings, FDM residuals, star boxes,
+        // assembled solutions) moved next to each other, so that each phase of the SDC
+        // relaxation runs as one launch over all three
+        {
+            const size_t tb = P0->fp32 ? sizeof(float) : sizeof(double);
+            const int64_t ulen = patch_solution_entries(P0->d);
+            for (int c = 1; c < 3; ++c)
+                if (L->comp[c]->fint_len != P0->fint_len || L->comp[c]->fbnd_len != P0->fbnd_len ||
+                    L->comp[c]->mu_len != P0->mu_len || L->comp[c]->fp32 != P0->fp32)
+                    throw Error(VSR_EINVAL, "elasticity components differ in structure");
+            auto merge = [&](void *vsr_problem::*member, int64_t len) {
+                char *base = L->dalloc<char>(3 * (size_t)len * tb);
+                for (int c = 0; c < 3; ++c) L->comp[c]->move_to(&(L->comp[c]->*member), base + c * (size_t)len * tb, len * tb);
+            };
+            merge(&vsr_problem::fint, P0->fint_len);
+            merge(&vsr_problem::fbnd, P0->fbnd_len);
+            merge(&vsr_problem::mu_sur, P0->mu_len);
+            merge(&vsr_problem::rF, P0->n);
+            merge(&vsr_problem::U, ulen);
+            if (P0->zF) merge(&vsr_problem::zF, P0->n);
+            L->cs = CompStrides{P0->fint_len, P0->fbnd_len, P0->mu_len, P0->n, ulen};
+        }
         const int n1 = p + 1;
         // 1-D matrices A, B, C (C[a][b] = sum_q w_q l_a'(x_q) l_b(x_q)) and C^T
         const OneD &od = P0->od;
@@ -1814,12 +1835,11 @@ vsr_status vsr_elasticity_pcg_solve(vsr_elasticity *L, const double *b, double *
             el_precond(L, L->vr, L->vz, 0);
             launch_dot(N, L->vr, L->vz, P->partials, P->scal, 3, nullptr, L->ex());    // RZ = r.z
             launch_axpby_to_double<double>(N, 1.0, L->vz, 0.0, L->vp, L->ex());
-            // the iterations run on the library's own stream, forked from the caller's, one
-            // recorded graph per iteration (its fork to the component streams and its joins
-            // are edges of the graph); the graph holds x's address and is recorded again for
-            // another x
-            VSR_HIP(hipEventRecord(L->ev[0], user));
-            VSR_HIP(hipStreamWaitEvent(L->origin, L->ev[0], 0));
+            // the iterations run on the library's own stream, forked from the caller's, as
+            // replays of one recorded iteration; the recording holds x's address and is made
+            // again for another x
+            VSR_HIP(hipEventRecord(L->fork, user));
+            VSR_HIP(hipStreamWaitEvent(L->origin, L->fork, 0));
             L->stream = L->origin;
             if (!L->exec || L->graph_x != x) {
                 if (L->exec) VSR_HIP(hipGraphExecDestroy(L->exec));
@@ -1855,8 +1875,8 @@ vsr_status vsr_elasticity_pcg_solve(vsr_elasticity *L, const double *b, double *
             L->gate = nullptr;
             throw;
         }
-        VSR_HIP(hipEventRecord(L->ev[0], L->origin));
-        VSR_HIP(hipStreamWaitEvent(user, L->ev[0], 0));
+        VSR_HIP(hipEventRecord(L->fork, L->origin));
+        VSR_HIP(hipStreamWaitEvent(user, L->fork, 0));
         L->stream = user;
         L->gate = nullptr;
         VSR_HIP(hipStreamSynchronize(L->stream));

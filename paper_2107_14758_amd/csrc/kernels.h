@@ -99,8 +99,9 @@ void launch_load_vector(const Dims &d, const double *IDq, const double *wdet, co
 // box_mode (XFER_FDM_PROLONG up to degree kFusedScatterMaxP): 1 = in holds the patch solves'
 // star boxes ((2p-1)^3 per mesh vertex) and the prolongation reads their assembled sum (the
 // scatter-add of Sec. 2.5) instead of a lattice vector; 2 = the same with only the interior
-// vertices' stars; 0 = a lattice vector.  ncomp > 1: that many independent vectors one after
-// another in `in`, `out` and out64 (lattice input only, no dotv or partials), one launch.
+// vertices' stars; 0 = a lattice vector.  ncomp > 1: that many independent inputs (lattice
+// vectors, or with box_mode the star boxes of that many patch-solve launches) and outputs one
+// after another in `in`, `out` and out64 (no dotv or partials), one launch.
 template <typename Tin, typename T>
 void launch_transfer(int kind, int p, const int ncell[3], const int in_dims[3], const int out_dims[3], const T *M,
                      const Tin *in, T *out, T alpha, T beta, const Exec &e, double *out64 = nullptr,
@@ -121,15 +122,22 @@ struct PatchArgs {
 // nodes each, one per vertex-parity class (vx mod 2) + 2 (vy mod 2) + 4 (vz mod 2), read by
 // launch_patch_assemble.  Either way, entries no star writes must hold zero (the caller
 // zeroes U once; the kernel writes its stars' entries only).
+// Independent problems of one structure (the same mesh, degree and patch layout) in one launch:
+// problem c's arrays start c strides after the first's (elements of T).
+struct CompStrides {
+    int64_t fint = 0, fbnd = 0, mu = 0, rF = 0, U = 0;
+};
+// ncomp > 1: that many such problems, blockIdx.y selecting one.
 template <typename T>
 void launch_patch_all(const Dims &d, const PatchArgs &a, int n_int, const int *verts, const int *fidx, const T *fint, int n_bnd,
                       const int *desc, const int64_t *off, const T *fbnd, const T *mu, const T *lam, const T *afc,
-                      const T *rF, T *U, const Exec &e);
+                      const T *rF, T *U, const Exec &e, int ncomp = 1, CompStrides cs = CompStrides{});
 
 // Additive Schwarz sum z_F = sum_j Rbar_j^T u_j (Sec. 2.5) into a lattice vector (degrees above
 // kFusedScatterMaxP; up to it the prolongation reads the star boxes itself).
+// ncomp > 1: that many (U, zF) pairs one after another, one launch.
 template <typename T>
-void launch_patch_assemble(const Dims &d, const T *U, T *zF, const Exec &e);
+void launch_patch_assemble(const Dims &d, const T *U, T *zF, const Exec &e, int ncomp = 1);
 // Primal linear elasticity on axis-aligned cells (Sec. 3.1), FP64 or FP32: the three components'
 // cell results of y = A x into E (three element vectors of ncell (p+1)^3, one per output
 // component; launch_gather_components sums them).  M1: the 1-D matrices A, B, C, C^T ((p+1)^2 each,

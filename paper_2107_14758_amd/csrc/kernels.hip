@@ -563,6 +563,10 @@ __global__ void __launch_bounds__(XB) k_patch_assemble(const double *__restrict_
     if (gated(gate)) return;
     const int64_t n = (int64_t)d.Lx * d.Ly * d.Lz, i = (int64_t)blockIdx.x * XB + threadIdx.x;
     if (i >= n) return;
+    if (gridDim.y > 1) {   // independent (U, zF) pairs: U holds 8 n values per pair
+        U += blockIdx.y * 8 * n;
+        zF += blockIdx.y * n;
+    }
     zF[i] = star_box_sum<T>(U, n, i);
 }
 
@@ -816,9 +820,10 @@ void launch_load_vector(const Dims &d, const double *IDq, const double *wdet, co
 inline unsigned line_blocks(const Dims &d) { return (unsigned)(((d.Lx + XB - 1) / XB) * (int64_t)d.Ly * d.Lz); }
 
 template <typename T>
-void launch_patch_assemble(const Dims &d, const T *U, T *zF, const Exec &e) {
+void launch_patch_assemble(const Dims &d, const T *U, T *zF, const Exec &e, int ncomp) {
     const int64_t n = (int64_t)d.Lx * d.Ly * d.Lz;
-    hipLaunchKernelGGL((k_patch_assemble<T>), dim3((unsigned)((n + XB - 1) / XB)), dim3(XB), 0, e.s, e.gate, d, U, zF);
+    hipLaunchKernelGGL((k_patch_assemble<T>), dim3((unsigned)((n + XB - 1) / XB), (unsigned)ncomp), dim3(XB), 0, e.s, e.gate,
+                       d, U, zF);
 }
 
 template <typename T>
@@ -950,7 +955,7 @@ int launch_axpby_to_double(int64_t n, double a, const T *x, double b, double *y,
                                    double *);                                                                    \
     template void launch_gather_sub<T>(const Dims &, const T *, const T *, T *, const Exec &);                   \
     template void launch_gather_components<T>(const Dims &, int, const T *, T *, const Exec &, const double *);  \
-    template void launch_patch_assemble<T>(const Dims &, const T *, T *, const Exec &);                   \
+    template void launch_patch_assemble<T>(const Dims &, const T *, T *, const Exec &, int);              \
     template void launch_op_kron_restrict<T>(const Dims &, int, const T *, const T *, const T *, T *, const Exec &); \
     template void launch_coarse_gather<T>(const Dims &, const T *, const T *, T *, const Exec &);              \
     template int launch_axpby_to_double<T>(int64_t, double, const T *, double, double *, const Exec &, const double *, \

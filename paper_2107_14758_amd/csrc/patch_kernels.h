@@ -866,8 +866,16 @@ k_patch_all(const double *__restrict__ gate, Dims d, PatchArgs A, int n_int,
                                                    const int *__restrict__ desc, const int64_t *__restrict__ off,
                                                    const T *__restrict__ fbnd, const T *__restrict__ mu,
                                                    const T *__restrict__ lam, const T *__restrict__ afc,
-                                                   const T *__restrict__ rF, T *__restrict__ U) {
+                                                   const T *__restrict__ rF, T *__restrict__ U, CompStrides cs) {
     if (gated(gate)) return;
+    if (gridDim.y > 1) {   // independent problems of one structure: blockIdx.y selects one
+        const int64_t c = blockIdx.y;
+        fint += c * cs.fint;
+        fbnd += c * cs.fbnd;
+        mu += c * cs.mu;
+        rF += c * cs.rF;
+        U += c * cs.U;
+    }
     if ((int)blockIdx.x < n_int) patch_interior<T, P, UNR, NTH>(blockIdx.x, d, A, verts, fidx, fint, mu, lam, afc, rF, U);
     else patch_boundary<T, P, NTH>(blockIdx.x - n_int, d, desc, off, fbnd, mu, lam, afc, rF, U);
 }
@@ -877,15 +885,16 @@ k_patch_all(const double *__restrict__ gate, Dims d, PatchArgs A, int n_int,
 template <typename T>
 void launch_patch_all(const Dims &d, const PatchArgs &a, int n_int, const int *verts, const int *fidx, const T *fint, int n_bnd,
                       const int *desc, const int64_t *off, const T *fbnd, const T *mu, const T *lam, const T *afc,
-                      const T *rF, T *U, const Exec &e) {
+                      const T *rF, T *U, const Exec &e, int ncomp, CompStrides cs) {
     if (n_int + n_bnd == 0) return;
+    if (ncomp < 1 || ncomp > 65535) throw Error(VSR_EINVAL, "patch launch: bad problem count");
     const int unr = e.t.patch_unroll, nth = e.t.patch_threads;
     if (unr != 4 && unr != 8 && unr != 16) throw Error(VSR_EINVAL, "patch_unroll must be 4, 8 or 16");
     if (nth != 256 && nth != 512 && nth != 1024) throw Error(VSR_EINVAL, "patch_threads must be 256, 512 or 1024");
     if (nth == 1024 && unr == 16) throw Error(VSR_EINVAL, "1024 patch threads take an unroll of 4 or 8");
 #define CALLT(P, UU, NN)                                                                                          \
-    hipLaunchKernelGGL((k_patch_all<T, P, UU, NN>), dim3(n_int + n_bnd), dim3(NN), 0, e.s, e.gate, d, a, n_int, verts, fidx, fint, \
-                       desc, off, fbnd, mu, lam, afc, rF, U)
+    hipLaunchKernelGGL((k_patch_all<T, P, UU, NN>), dim3(n_int + n_bnd, ncomp), dim3(NN), 0, e.s, e.gate, d, a, n_int, verts, \
+                       fidx, fint, desc, off, fbnd, mu, lam, afc, rF, U, cs)
 #define CALLU(P, UU)                                       \
     if (nth == 512) CALLT(P, UU, 512);                      \
     else if (nth == 1024) {                                 \
@@ -908,5 +917,5 @@ void launch_patch_all(const Dims &d, const PatchArgs &a, int n_int, const int *v
     template void launch_patch_all<T>(const Dims &, const PatchArgs &, int, const int *, const int *, const T *, int,   \
                                       const int *,                                                                   \
                                       const int64_t *, const T *, const T *, const T *, const T *, const T *, T *,   \
-                                      const Exec &);                                                                \
+                                      const Exec &, int, CompStrides);                                              \
     }

@@ -86,10 +86,10 @@ __global__ void __launch_bounds__(XFER_THREADS)
     k_transfer(const double *__restrict__ gate, const T *__restrict__ M, int ncx, int ncy, int ncz, int in_off,
                int out_step, int ix, int iy, int iz, int ox, int oy, int oz, const Tin *__restrict__ in,
                T *__restrict__ out, T alpha, T beta, double *__restrict__ out64, const double *__restrict__ dotv,
-               double *__restrict__ partials, int box_mode) {
+               double *__restrict__ partials, int box_mode, int64_t in_cstride) {
     if (gated(gate)) return;
-    if (gridDim.y > 1) {   // independent components (lattice input, no dot): blockIdx.y selects one
-        in += blockIdx.y * (int64_t)ix * iy * iz;
+    if (gridDim.y > 1) {   // independent components (no dot): blockIdx.y selects one
+        in += blockIdx.y * in_cstride;
         out += blockIdx.y * (int64_t)ox * oy * oz;
         if (out64 != nullptr) out64 += blockIdx.y * (int64_t)ox * oy * oz;
     }
@@ -238,9 +238,14 @@ template <typename Tin, typename T>
 void launch_transfer(int kind, int p, const int ncell[3], const int in_dims[3], const int out_dims[3], const T *M,
                      const Tin *in, T *out, T alpha, T beta, const Exec &e, double *out64, const double *dotv,
                      double *partials, int box_mode, int ncomp) {
-    if (ncomp < 1 || (ncomp > 1 && (dotv != nullptr || partials != nullptr || box_mode != 0)))
-        throw Error(VSR_EINVAL, "transfer components: lattice input without a dot only");
+    if (ncomp < 1 || (ncomp > 1 && (dotv != nullptr || partials != nullptr)))
+        throw Error(VSR_EINVAL, "transfer components: no dot");
     const int nc = ncell[0] * ncell[1] * ncell[2];
+    // the input of one component: a lattice vector, or the star boxes of its patch solves
+    // ((nx+1)(ny+1)(nz+1) boxes of (2p-1)^3 values)
+    const int64_t wb = 2 * p - 1;
+    const int64_t in_cstride = box_mode != 0 ? (int64_t)(ncell[0] + 1) * (ncell[1] + 1) * (ncell[2] + 1) * wb * wb * wb
+                                             : (int64_t)in_dims[0] * in_dims[1] * in_dims[2];
     if (nc == 0 || (int64_t)out_dims[0] * out_dims[1] * out_dims[2] == 0) {
         const int nb = transfer_blocks(kind, p, ncell);
         if (partials != nullptr && nb > 0) launch_fill<double>(nb, partials, 0.0, e);
@@ -252,16 +257,17 @@ void launch_transfer(int kind, int p, const int ncell[3], const int in_dims[3], 
         const int nb = ((ncell[0] + CX - 1) / CX) * ((ncell[1] + CY - 1) / CY) * ncell[2];                            \
         if (box_mode != 0) {                                                                                           \
             if constexpr (KIND == XFER_FDM_PROLONG && std::is_same<Tin, T>::value)                                     \
-                hipLaunchKernelGGL((k_transfer<Tin, T, OA, K, IS, CX, CY, true>), dim3(8u * (unsigned)((nb + 7) / 8)), \
-                                   dim3(XFER_THREADS), 0, e.s, e.gate, M, ncell[0], ncell[1], ncell[2], IO, OS,        \
-                                   in_dims[0], in_dims[1], in_dims[2], out_dims[0], out_dims[1], out_dims[2], in, out, \
-                                   alpha, beta, out64, dotv, partials, box_mode);                                      \
+                hipLaunchKernelGGL((k_transfer<Tin, T, OA, K, IS, CX, CY, true>),                                      \
+                                   dim3(8u * (unsigned)((nb + 7) / 8), (unsigned)ncomp), dim3(XFER_THREADS), 0, e.s,   \
+                                   e.gate, M, ncell[0], ncell[1], ncell[2], IO, OS, in_dims[0], in_dims[1], in_dims[2], \
+                                   out_dims[0], out_dims[1], out_dims[2], in, out, alpha, beta, out64, dotv, partials, \
+                                   box_mode, in_cstride);                                                              \
             else throw Error(VSR_EINVAL, "star-box input is for the FDM prolongation only");                           \
         } else {                                                                                                       \
             hipLaunchKernelGGL((k_transfer<Tin, T, OA, K, IS, CX, CY>), dim3(8u * (unsigned)((nb + 7) / 8), (unsigned)ncomp), \
                                dim3(XFER_THREADS), 0, e.s, e.gate, M, ncell[0], ncell[1], ncell[2], IO, OS, in_dims[0], \
                                in_dims[1], in_dims[2], out_dims[0], out_dims[1], out_dims[2], in, out, alpha, beta,   \
-                               out64, dotv, partials, 0);                                                             \
+                               out64, dotv, partials, 0, in_cstride);                                                 \
         }                                                                                                              \
     }
 #define CALL(P)                                                               \

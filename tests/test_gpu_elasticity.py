@@ -148,8 +148,7 @@ def test_damping_and_pcg(vsr, name, shape, p, stretched, mu, lam):
 def test_pcg_zero_rhs_iteration_cap_and_repeat(vsr):
     """The device-driven solve: b = 0 stops before any iteration with x = 0; an iteration cap
     below the needed count reports non-convergence after exactly that many updates; a second
-    solve of the same system repeats the first bit for bit (the three component relaxations run
-    on separate streams, which must not change any result), also when a later solve replays the
+    solve of the same system repeats the first bit for bit, also when a later solve replays the
     iteration recorded by an earlier one."""
     V = grid((3, 2, 3), True, seed=4)
     d = Discretization(V, 3)

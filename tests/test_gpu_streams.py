@@ -1,7 +1,7 @@
 """The library on a caller's stream (options.stream): a solve issued on a non-default torch
 stream gives bit for bit the solve on the default stream (deterministic mode), for the scalar
-problem (graph-replayed iterations over the library's streams) and for elasticity (component
-relaxations forked from and joined back to the caller's stream)."""
+problem (graph-replayed iterations over the library's streams) and for elasticity (its
+iterations on the library's stream, forked from and joined back to the caller's)."""
 import numpy as np
 import pytest
 
