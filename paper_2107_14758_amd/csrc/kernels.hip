@@ -445,8 +445,8 @@ __global__ void __launch_bounds__(opg_threads(P, S)) k_op_general(const double *
 
 // Assembly of an element vector: every free lattice node sums the blocks of the (up to 8)
 // cells that contain it, each with its S slots, in a fixed order.  r == nullptr: out = sum;
-// else out = r - sum (the residual of the cycle, in T).  A workgroup covers XB nodes of one
-// x-line: the line's (y, z) position and cells are uniform across it.
+// else out = r - sum (the residual of the cycle, in T).  A workgroup covers XB consecutive
+// free nodes in lattice order.
 constexpr int XB = 128;
 
 template <int P>
@@ -468,16 +468,17 @@ __global__ void __launch_bounds__(XB) k_gather(const double *__restrict__ gate, 
     if (gated(gate)) return;
     constexpr int N1 = P + 1, N3 = N1 * N1 * N1;
     if (gridDim.y > 1) {   // independent components (rT, dotv unused): E, r and out per blockIdx.y
-        const int64_t nfree = (int64_t)d.Lx * d.Ly * d.Lz;
+        const int64_t nf = (int64_t)d.Lx * d.Ly * d.Lz;
         E += (int64_t)blockIdx.y * slots * d.nx * d.ny * d.nz * N3;
-        out += blockIdx.y * nfree;
-        if (r != nullptr) r += blockIdx.y * nfree;
+        out += blockIdx.y * nf;
+        if (r != nullptr) r += blockIdx.y * nf;
     }
-    const int xblocks = (d.Lx + XB - 1) / XB;
-    const int line = (int)(blockIdx.x / xblocks), I0 = (int)(blockIdx.x - (int64_t)line * xblocks) * XB + threadIdx.x + 1;
-    const bool live = I0 <= d.Lx;
-    const int I = live ? I0 : d.Lx;
-    const int J = line % d.Ly + 1, K = line / d.Ly + 1;
+    // the free nodes in lattice order, XB consecutive ones per workgroup (whole lines and
+    // line ends together, so that short lines leave no thread idle)
+    const int64_t nfree = (int64_t)d.Lx * d.Ly * d.Lz, g0 = (int64_t)blockIdx.x * XB + threadIdx.x;
+    const bool live = g0 < nfree;
+    const int64_t g = live ? g0 : nfree - 1, line = g / d.Lx;
+    const int I = (int)(g - line * d.Lx) + 1, J = (int)(line % d.Ly) + 1, K = (int)(line / d.Ly) + 1;
     int cx[2], lx[2], cy[2], ly[2], cz[2], lz[2];
     const int mx = axis_cells<P>(I, cx, lx), my = axis_cells<P>(J, cy, ly), mz = axis_cells<P>(K, cz, lz);
     const int64_t slot = (int64_t)d.nx * d.ny * d.nz * N3, rowlen = (int64_t)d.nx * N1;
@@ -499,7 +500,7 @@ __global__ void __launch_bounds__(XB) k_gather(const double *__restrict__ gate, 
     for (int s = 0; s < 2; ++s)
 #pragma unroll
         for (int t = 0; t < 4; ++t) sum += v[s][t][0] + v[s][t][1];
-    const int64_t idx = ((int64_t)(K - 1) * d.Ly + (J - 1)) * d.Lx + (I - 1);
+    const int64_t idx = g;
     const T o = rT != nullptr ? rT[idx] - sum : (r == nullptr ? sum : (T)r[idx] - sum);
     if (live) out[idx] = o;
     if (dotv != nullptr) {   // partial sum of dotv . out for this workgroup
@@ -817,7 +818,7 @@ void launch_load_vector(const Dims &d, const double *IDq, const double *wdet, co
 
 
 // one workgroup per XB nodes of an x-line
-inline unsigned line_blocks(const Dims &d) { return (unsigned)(((d.Lx + XB - 1) / XB) * (int64_t)d.Ly * d.Lz); }
+inline unsigned line_blocks(const Dims &d) { return (unsigned)(((int64_t)d.Lx * d.Ly * d.Lz + XB - 1) / XB); }
 
 template <typename T>
 void launch_patch_assemble(const Dims &d, const T *U, T *zF, const Exec &e, int ncomp) {
