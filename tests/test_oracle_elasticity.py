@@ -142,3 +142,20 @@ def test_pcg_matches_direct_solve(lam):
     M = np.stack([s.precondition(e) for e in np.eye(el.n)], axis=1)
     ev = np.sort(np.linalg.eigvals(M @ A).real)
     assert ev[0] - 1e-9 <= lmin and lmax <= ev[-1] + 1e-9
+
+
+def test_sdc_conditioning_degrades_with_lambda():
+    # eq. SDC: the SDC-preconditioned condition number grows like (1 - nu) / (1 - 2 nu), i.e.
+    # without bound as lambda / mu grows (nearly incompressible); the two-level method inherits
+    # it.  Dense spectrum of M A on a small mesh for lambda = 0, 10, 100.
+    d = Discretization(inputs.cube_vertices(3, 2, 2), 2)
+    kappas = []
+    for lam in (0.0, 10.0, 100.0):
+        el = Elasticity(d, 1.0, lam)
+        s = SDCSolver(el, setup_1d(2), seed=0)
+        A = np.stack([el.apply(e) for e in np.eye(el.n)], axis=1)
+        M = np.stack([s.precondition(e) for e in np.eye(el.n)], axis=1)
+        ev = np.sort(np.linalg.eigvals(M @ A).real)
+        assert ev[0] > 0
+        kappas.append(ev[-1] / ev[0])
+    assert kappas[0] < kappas[1] < kappas[2] and kappas[2] > 3 * kappas[0]
