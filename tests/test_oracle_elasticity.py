@@ -2,7 +2,8 @@
 rigid rotations in the kernel of the element operators, the diagonal blocks against the
 scalar operator with the tensor coefficient K_j, the Q1 coarse matrix against the operator
 itself, the SDC scalings' closed form on boxes, the single-patch SDC relaxation against the
-exact block-diagonal solve, and PCG against a direct solve."""
+exact block-diagonal solve, PCG against a direct solve, and the growth of the preconditioned
+condition number with lambda that eq. SDC predicts."""
 import numpy as np
 import pytest
 
